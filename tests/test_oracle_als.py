@@ -1,0 +1,112 @@
+"""Pins of the oracle's full sweep (Algorithm 1, Sec. 3) and of Theorem 5 /
+Corollary 3 (Sec. 4), CPU only.
+
+Anchors: exact recovery of a noise-free TT (the objective (3.1) reaches 0 at
+the generating cores), convergence to the noise floor, the injective-sketch
+sweep equals exact proximal TT-ALS, Eckart-Young for d = 2, and the
+(1 + eps) * OPT guarantee of Theorem 5 at a size where Corollary 3's m is
+attainable.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import als, bound, sketch, solve, tables
+from tests.test_oracle_solve import injective_tables
+
+
+def test_noise_free_tt_is_recovered():
+    n, R, J = [10, 10, 10, 10], [1, 3, 3, 3, 1], 256
+    X, _ = synth.tt_tensor_host(n, R, 0.0, 31)
+    cores = synth.random_cores(n, R, 32)
+    res = []
+    for t in range(10):
+        cores = als.sweep(X, n, cores, J, 1e-3, seed=5, t=t)
+        res.append(als.rel_residual(X, cores))
+    assert res[-1] < 1e-7, res
+    assert res[-1] < res[0] * 1e-4
+
+
+def test_noisy_tt_converges_to_noise_floor():
+    n, R, J, noise = [10, 10, 10, 10], [1, 3, 3, 3, 1], 256, 1e-2
+    X, _ = synth.tt_tensor_host(n, R, noise, 33)
+    floor = noise * np.sqrt(X.size) / np.linalg.norm(X)
+    cores = synth.random_cores(n, R, 34)
+    for t in range(8):
+        cores = als.sweep(X, n, cores, J, 1e-3, seed=6, t=t)
+    r = als.rel_residual(X, cores)
+    assert 0.5 * floor < r < 1.5 * floor, (r, floor)
+
+
+def test_injective_sketch_sweep_is_exact_prox_als():
+    # With S^T S = I every step is the exact proximal TT-ALS step (3.3).
+    n, R, lam = [4, 5, 3], [1, 2, 3, 1], 0.1
+    X = synth.rng(35).standard_normal(60)
+    cores0 = synth.random_cores(n, R, 36)
+    hs, vs, J = injective_tables(n)
+    got = als.sweep(X, n, cores0, J, lam, tabs=(hs, vs))
+    # exact proximal ALS written with dense H_k and A_(k)
+    cores = solve.right_orthogonalize(cores0)
+    for k in range(3):
+        H = sketch.interface_matrix(cores, k)
+        s = H.shape[1]
+        A = np.vstack([H, np.sqrt(lam) * np.eye(s)])
+        B = np.vstack([sketch.unfold(X, n, k).T, np.sqrt(lam) * solve.core_unfold2(cores[k]).T])
+        Z = np.linalg.lstsq(A, B, rcond=None)[0]
+        cores[k] = solve.core_fold2(Z.T, cores[k].shape[0], cores[k].shape[2])
+        if k < 2:
+            cores[k], cores[k + 1] = solve.left_orth_absorb(cores[k], cores[k + 1])
+    for a, b in zip(got, cores):
+        np.testing.assert_allclose(a, b, rtol=1e-8, atol=1e-10)
+
+
+def test_d2_exact_sketch_reaches_eckart_young():
+    g = synth.rng(37)
+    n0, n1, r = 9, 8, 3
+    U, _ = np.linalg.qr(g.standard_normal((n0, n0)))
+    V, _ = np.linalg.qr(g.standard_normal((n1, n1)))
+    sv = np.array([10.0, 8.0, 6.0, 1.0, 0.5, 0.3, 0.2, 0.1])
+    M = U[:, :8] @ np.diag(sv) @ V.T
+    X = M.reshape(-1, order="F")
+    best = np.sqrt((sv[r:] ** 2).sum()) / np.linalg.norm(sv)
+    hs, vs, J = injective_tables([n0, n1])
+    cores = synth.random_cores([n0, n1], [1, r, 1], 38)
+    for t in range(40):
+        cores = als.sweep(X, [n0, n1], cores, J, 1e-12, tabs=(hs, vs))
+    assert abs(als.rel_residual(X, cores) - best) < 1e-8
+
+
+def test_cor3_bound_values():
+    # s = 1, q = 2, eps = 1, delta = 0.5 -> m = max{88/0.5, 88/0.5} = 176
+    assert bound.cor3_sketch_size_int(1, 2, 1.0, 0.5) == 176
+    # the s^2 branch dominates when s > 1/eps
+    assert bound.cor3_sketch_size(10, 3, 0.5, 0.1) == max(8 * 100 * 29 / 0.1, 8 * 10 * 29 / 0.05)
+
+
+def test_theorem5_one_plus_eps_opt():
+    # d = 3, update of the middle core (q = 2 sketched modes), ranks 1 (s = 1):
+    # Cor. 3's m = 176 at eps = 1, delta = 0.5.
+    eps, delta = 1.0, 0.5
+    J = bound.cor3_sketch_size_int(1, 2, eps, delta)
+    n, R, lam, k = [6, 5, 7], [1, 1, 1, 1], 0.5, 1
+    g = synth.rng(39)
+    X = g.standard_normal(210)
+    cores = solve.right_orthogonalize(synth.random_cores(n, R, 40))
+    H = sketch.interface_matrix(cores, k)
+    B = sketch.unfold(X, n, k).T
+    C = solve.core_unfold2(cores[k]).T
+
+    def f(Z):
+        return 0.5 * np.linalg.norm(H @ Z - B) ** 2 + 0.5 * lam * np.linalg.norm(Z - C) ** 2
+
+    A = np.vstack([H, np.sqrt(lam) * np.eye(1)])
+    Zopt = np.linalg.lstsq(A, np.vstack([B, np.sqrt(lam) * C]), rcond=None)[0]
+    opt = f(Zopt)
+    ok, T = 0, 200
+    for t in range(T):
+        hs, vs = tables.sweep_tables(900 + t, 0, n, J)
+        SH = sketch.interface_cyclic(cores, k, hs, vs, J)
+        Y = sketch.data_sketch(X, n, k, hs, vs, J)
+        Z = solve.core_unfold2(solve.prox_update(SH, Y, cores[k], lam)).T
+        ok += f(Z) <= (1 + eps) * opt
+    assert ok / T >= 1 - delta

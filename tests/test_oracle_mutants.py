@@ -1,0 +1,87 @@
+"""Planted mistakes in the oracle must be caught by its pins (CPU only).
+
+Each case patches one plausible error into an oracle function (a wrong shift
+direction, a dropped sign, a dropped proximal term, a transposed operand, a
+missing QR sign normalisation) and checks that the corresponding pin test
+fails.  Nothing here touches the GPU path.
+"""
+import numpy as np
+import pytest
+
+from oracle import sketch, solve
+from tests import test_oracle_als as T_als
+from tests import test_oracle_sketch as T_sk
+from tests import test_oracle_solve as T_so
+
+
+def _fails(fn, *a):
+    with pytest.raises(AssertionError):
+        fn(*a)
+
+
+def test_shift_direction_mutant(monkeypatch):
+    monkeypatch.setattr(sketch, "_shift", lambda P, h: np.roll(P, -int(h), axis=0))
+    _fails(T_sk.test_interface_cyclic_equals_explicit, [3, 4, 2, 3], [1, 2, 3, 2, 1], 7)
+
+
+def test_tensorsketch_sign_mutant(monkeypatch):
+    orig = sketch.tensorsketch_matrix
+
+    def bad(hs, vs, J):          # sign of the first mode only
+        return orig(hs, [vs[0]] + [np.ones_like(v) for v in vs[1:]], J)
+    monkeypatch.setattr(sketch, "tensorsketch_matrix", bad)
+    _fails(T_sk.test_paper_worked_example)
+
+
+def test_tensorsketch_no_mod_mutant(monkeypatch):
+    def bad(hs, vs, J):          # hash sum clipped instead of reduced mod J
+        sizes = [len(h) for h in hs]
+        S = np.zeros((J, int(np.prod(sizes))))
+        for j in range(S.shape[1]):
+            rem, b, sg = j, 0, 1
+            for h, v, ns in zip(hs, vs, sizes):
+                i = rem % ns
+                rem //= ns
+                b += int(h[i])
+                sg *= int(v[i])
+            S[min(b, J - 1), j] += sg
+        return S
+    monkeypatch.setattr(sketch, "tensorsketch_matrix", bad)
+    _fails(T_sk.test_paper_worked_example)
+
+
+def test_data_sketch_dropped_sign_mutant(monkeypatch):
+    orig = sketch.data_sketch
+
+    def bad(X, n, k, hs, vs, J, slab_entries=1 << 24):
+        return orig(X, n, k, hs, [np.ones_like(v) for v in vs], J, slab_entries)
+    monkeypatch.setattr(sketch, "data_sketch", bad)
+    _fails(T_sk.test_data_sketch_equals_explicit, (3, 4, 2), 5)
+
+
+def test_prox_dropped_term_mutant(monkeypatch):
+    def bad(SH, Y, G_old, lam):
+        r0, nk, r1 = G_old.shape
+        M = SH.T @ SH + lam * np.eye(r0 * r1)
+        Z = np.linalg.solve(M, SH.T @ Y)            # lambda * G_old missing
+        return solve.core_fold2(Z.T, r0, r1)
+    monkeypatch.setattr(solve, "prox_update", bad)
+    _fails(T_so.test_prox_update_equals_stacked_lstsq)
+
+
+def test_interface_kron_order_mutant(monkeypatch):
+    def bad(cores, k):           # operands of the Kronecker product swapped
+        return np.kron(sketch.left_product(cores, k), sketch.right_product(cores, k).T)
+    monkeypatch.setattr(sketch, "interface_matrix", bad)
+    _fails(T_sk.test_tt_products_and_interface_matrix)
+
+
+def test_qr_sign_mutant(monkeypatch):
+    monkeypatch.setattr(solve, "qr_pos", lambda A: np.linalg.qr(-np.asarray(A, float), mode="reduced"))
+    _fails(T_so.test_qr_pos_properties)
+
+
+def test_sweep_wrong_gauge_mutant(monkeypatch):
+    # skipping the QR + absorb step leaves H_k without orthonormal columns
+    monkeypatch.setattr(solve, "left_orth_absorb", lambda a, b: (a, b))
+    _fails(T_so.test_sweep_gauge_makes_interface_orthonormal)
