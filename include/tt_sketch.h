@@ -1,0 +1,181 @@
+/*
+ * tt_sketch.h -- C ABI of the MI355X (gfx950) implementation of randomized
+ * proximal TT-ALS with TensorSketch (TT-TS): Chen, Jiang, Yu, Qi,
+ * "Low-rank Tensor Train Decomposition Using TensorSketch", arXiv 2309.08093.
+ *
+ * Problem statement (Algorithm 1, Sec. 3): given a tensor A (here X) with mode
+ * sizes n_0..n_{d-1}, TT ranks R_0..R_d (R_0 = R_d = 1), sketch size J (the
+ * paper's m) and proximal parameter lambda (the paper's sigma), compute TT
+ * cores G_k of shape (R_k, n_k, R_{k+1}) by sweeps of sketched proximal
+ * least-squares updates.
+ *
+ * Conventions shared by every entry point
+ *   - Indices are 0-based.  X is dense, mode 0 varying fastest (the paper's
+ *     linear order, Sec. 2.2), i.e. a row-major torch tensor of shape
+ *     (n_{d-1}, ..., n_0).
+ *   - Core k is FP64, shape (R_k, n_k, R_{k+1}), first index fastest:
+ *     G_k(a, i, b) at a + R_k * (i + n_k * b).  Its left unfolding G^L
+ *     (R_k n_k x R_{k+1}) and right unfolding G^R (R_k x n_k R_{k+1}) (Sec. 1.2)
+ *     are column-major views of the same memory.
+ *   - "Work" arrays (Y, SH) use the plan's work type (FP64 or FP32) and are
+ *     column-major: Y_k is J x n_k at Y[b + J*i], SH_k is J x R_k R_{k+1} at
+ *     SH[b + J*(a + R_k*c)] (column alpha + beta R_k, Theorem 1, Sec. 3).
+ *   - Ownership: the caller owns every device buffer it passes (X, cores, Y,
+ *     SH, workspace) and the stream.  The library never allocates or frees
+ *     device memory; all device scratch lives in the caller's workspace.
+ *   - Asynchrony: every call enqueues work on the plan's stream and returns.
+ *     Only tt_plan_get_tables, tt_plan_sync_status and a non-NULL
+ *     rel_residual synchronise the stream.
+ *   - Errors: argument and shape errors return before any device work, with
+ *     outputs untouched.  A failed launch returns TT_ERR_HIP.  A failed
+ *     Cholesky (not SPD, e.g. lambda = 0 with a rank-deficient SH) is recorded
+ *     on the device and reported by the next synchronising call as
+ *     TT_ERR_NOT_SPD.  Nothing throws across the ABI and nothing prints;
+ *     tt_last_error() returns a thread-local message for the last failure.
+ *   - A plan is not thread-safe; use one plan per stream.
+ */
+#ifndef TT_SKETCH_H
+#define TT_SKETCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TT_MAX_ORDER 16      /* d */
+#define TT_MAX_J 8192        /* sketch size (LDS FFT and bucket accumulators) */
+#define TT_MAX_RANK 16       /* max R_k */
+#define TT_MAX_S 180         /* max R_k R_{k+1} (packed FP64 Cholesky in LDS) */
+#define TT_MAX_N0 4096       /* max n_0 */
+
+typedef struct tt_plan_s* tt_plan;
+
+typedef enum {
+  TT_OK = 0,
+  TT_ERR_ARG = 1,        /* null pointer, bad enum, k out of range, bad J / lambda */
+  TT_ERR_SHAPE = 2,      /* infeasible ranks or sizes beyond the limits above */
+  TT_ERR_WORKSPACE = 3,  /* no workspace bound, or smaller than required */
+  TT_ERR_HIP = 4,        /* a HIP runtime call or kernel launch failed */
+  TT_ERR_NOT_SPD = 5,    /* Cholesky of SH^T SH + lambda I failed */
+  TT_ERR_NONFINITE = 6,  /* NaN/Inf in the residual */
+  TT_ERR_STATE = 7       /* call order violated (e.g. tables never set) */
+} tt_status;
+
+typedef enum { TT_F64 = 0, TT_F32 = 1, TT_BF16 = 2 } tt_dtype;
+
+typedef enum {
+  TT_GRAM_WORK = 0,      /* Gram / RHS contractions in the work type (FP32 or FP64 MFMA) */
+  TT_GRAM_BF16 = 1       /* SH and Y rounded to BF16, MFMA with FP32 accumulation */
+} tt_gram_mode;
+
+typedef struct {
+  int32_t d;             /* tensor order, 2 <= d <= TT_MAX_ORDER */
+  const int64_t* n;      /* d mode sizes (host memory, read during the call only) */
+  const int64_t* r;      /* d+1 TT ranks, r[0] = r[d] = 1, r[k] <= r[k-1] n[k-1], r[k] <= n[k] r[k+1] */
+  int64_t J;             /* sketch size m, 1 <= J <= TT_MAX_J, prime factors in {2,3,5,7} */
+  double lambda;         /* proximal parameter sigma >= 0 */
+  uint64_t seed;         /* seed of the hash/sign tables */
+  tt_dtype x_dtype;      /* storage type of X */
+  tt_dtype work_dtype;   /* TT_F64 or TT_F32: type of Y, SH and the sketch accumulators */
+  int32_t gram_mode;     /* tt_gram_mode */
+  uint32_t flags;        /* reserved, must be 0 */
+} tt_plan_desc;
+
+/* Create a plan (Algorithm 1, REQUIRE line: tensor shape, TT ranks, m, sigma).
+ * Validates the descriptor, computes the workspace size the caller must
+ * provide (*workspace_bytes), and stores the stream (a hipStream_t, may be
+ * NULL for the null stream).  Launches nothing.  The sweep index starts at 0
+ * and the tables are generated when the workspace is bound. */
+tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream,
+                         size_t* workspace_bytes, tt_plan* out);
+
+/* Bind caller-owned device memory of at least *workspace_bytes bytes,
+ * 256-byte aligned.  Enqueues the generation of the sweep-0 tables. */
+tt_status tt_plan_bind_workspace(tt_plan plan, void* dev_workspace, size_t bytes);
+
+tt_status tt_plan_set_stream(tt_plan plan, void* hip_stream);
+tt_status tt_plan_destroy(tt_plan plan);
+
+/* TensorSketch operators S_s for sweep t (Algorithm 1, "Define TensorSketch
+ * operators", once per outer iteration; Sec. 2.2 Definitions of CountSketch
+ * and TensorSketch).  For every mode s, h_s[i] in [0, J) and v_s[i] in {-1,+1}
+ * are drawn from SplitMix64 keyed by seed XOR ((t+1)*2^16 + s): state0 =
+ * mix64(key); output j = mix64(state0 + (j+1)*0x9E3779B97F4A7C15);
+ * h_s[i] = floor(out_i * J / 2^64), v_s[i] = 1 - 2*(out_{n_s+i} >> 63).
+ * Generated on the device; clears any table override. */
+tt_status tt_plan_set_sweep(tt_plan plan, int64_t t);
+tt_status tt_plan_get_sweep(tt_plan plan, int64_t* t);
+
+/* Copy the current tables of mode s to host memory (n_s entries each).
+ * Synchronises the stream. */
+tt_status tt_plan_get_tables(tt_plan plan, int32_t s, int32_t* h, int8_t* v);
+
+/* Override the tables of mode s with host values (h in [0, J), v = +-1).
+ * The override persists until tt_plan_set_sweep; tt_als_sweep keeps it
+ * (used for the paper's worked example and for injective test sketches). */
+tt_status tt_plan_set_tables(tt_plan plan, int32_t s, const int32_t* h, const int8_t* v);
+
+/* Data sketch Y_k = S_{-k} A_(k)^T (sketched subproblem, Sec. 3 eq. (3.4);
+ * TensorSketch over all modes except k, eqs. (2.1)-(2.2)): every entry
+ * X(i_0..i_{d-1}) adds prod_{s!=k} v_s(i_s) X(i) to
+ * Y[(sum_{s!=k} h_s(i_s)) mod J, i_k].  X: device, x_dtype, N entries.
+ * Y: device, work type, J x n_k column-major, fully overwritten. */
+tt_status tt_sketch_tensor(tt_plan plan, const void* X, int32_t k, void* Y);
+
+/* Interface sketch SH_k = S_{-k} (G_{>k}^T (x) G_{<k}) (Theorem 1 and 2,
+ * Sec. 3): per-core CountSketch along mode 2, length-J FFT, slice-wise
+ * products per frequency, face-splitting product, inverse FFT, real part.
+ * cores: host array of d device pointers to FP64 cores (core k unused).
+ * SH: device, work type, J x R_k R_{k+1} column-major, fully overwritten. */
+tt_status tt_sketch_interface(tt_plan plan, const void* const* cores, int32_t k, void* SH);
+
+/* Sketched proximal update of core k (closed form, Sec. 3 eq. (3.5), with
+ * S^T S): G_k(2)^new = (Y^T SH + lambda G_k(2)^old)(SH^T SH + lambda I)^{-1}.
+ * SH, Y: device, work type (as produced above).  G_old, G_new: device FP64
+ * cores of shape (R_k, n_k, R_{k+1}); they may alias.  The Gram and RHS
+ * contractions run on MFMA (work type, or BF16 with FP32 accumulation under
+ * TT_GRAM_BF16); the Cholesky factorisation and the solve run in FP64. */
+tt_status tt_prox_solve(tt_plan plan, int32_t k, const void* SH, const void* Y,
+                        const void* G_old, void* G_new);
+
+/* QR step of Algorithm 1's inner loop for k < d-1: [Q,R] = qr(G_k^L) by FP64
+ * Householder with diag(R) >= 0; G_k <- Q; G_{k+1} <- R G_{k+1}^R.  In place
+ * on the device cores (host array of d device pointers). */
+tt_status tt_left_orth_absorb(tt_plan plan, void* const* cores, int32_t k);
+
+/* Right-to-left orthogonalisation (Algorithm 1, first step of each outer
+ * iteration): for k = d-1..1, LQ of G_k^R via Householder QR of its
+ * transpose, G_k <- Q^T, G_{k-1}^L <- G_{k-1}^L R^T.  In place, FP64. */
+tt_status tt_right_orthogonalize(tt_plan plan, void* const* cores);
+
+/* Relative residual ||X - [[G]]||_F / ||X||_F (objective (3.1), Sec. 3),
+ * reconstructing the TT on the fly and accumulating in FP64.  Synchronises;
+ * *rel_residual receives the value.  Returns TT_ERR_NONFINITE on NaN/Inf. */
+tt_status tt_residual(tt_plan plan, const void* X, const void* const* cores, double* rel_residual);
+
+/* One outer iteration of Algorithm 1 with the plan's current tables:
+ * right-to-left orthogonalisation; then for k = 0..d-1 the interface sketch,
+ * the data sketch, the proximal update and (k < d-1) QR + absorb.  Cores are
+ * updated in place.  Afterwards the sweep index advances by one and, unless
+ * tables were overridden, the next sweep's tables are generated.  If
+ * rel_residual is not NULL the residual is computed and the call
+ * synchronises. */
+tt_status tt_als_sweep(tt_plan plan, const void* X, void* const* cores, double* rel_residual);
+
+/* Synchronise the plan's stream and report device-side failures recorded so
+ * far (TT_ERR_NOT_SPD); clears the recorded status. */
+tt_status tt_plan_sync_status(tt_plan plan);
+
+/* Thread-local message describing the last non-OK status ("" if none). */
+const char* tt_last_error(void);
+
+/* Library version string. */
+const char* tt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TT_SKETCH_H */

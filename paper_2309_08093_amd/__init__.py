@@ -1,0 +1,215 @@
+"""MI355X (gfx950) randomized proximal TT-ALS with TensorSketch.
+
+Thin Python binding over the C ABI of ``libttsketch.so`` (include/tt_sketch.h):
+argument checking and marshalling only.  Every step of the method runs in the
+library's HIP kernels; torch supplies device memory and the stream.  There is
+no fallback: if the library is missing, importing this package raises.
+
+Layouts (see the header): X is a contiguous device tensor whose flat order has
+mode 0 fastest (a row-major torch tensor of shape (n_{d-1}, ..., n_0));
+core k is a contiguous float64 device tensor of R_k * n_k * R_{k+1} entries,
+first index fastest; Y and SH are column-major J x n_k and J x R_k R_{k+1}.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import TTError, check
+
+_lib = _abi.load()
+
+_DT = {"f64": _abi.TT_F64, "f32": _abi.TT_F32, "bf16": _abi.TT_BF16}
+_TORCH = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+_GRAM = {"work": _abi.TT_GRAM_WORK, "bf16": _abi.TT_GRAM_BF16}
+
+
+def version():
+    return _lib.tt_version().decode()
+
+
+def core_to_device(core, device="cuda"):
+    """numpy core (R_k, n_k, R_{k+1}) -> flat float64 device tensor (first index fastest)."""
+    flat = np.ascontiguousarray(np.asarray(core, dtype=np.float64).reshape(-1, order="F"))
+    return torch.from_numpy(flat).to(device)
+
+
+def core_to_host(t, shape):
+    """flat device core -> numpy (R_k, n_k, R_{k+1})."""
+    return t.detach().to("cpu", torch.float64).numpy().reshape(tuple(shape), order="F")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """One TT-TS problem: shape, ranks, sketch size J, proximal lambda, seed,
+    storage type of X and work type; owns a device workspace (a torch
+    tensor) and runs on a HIP stream (torch's current stream by default)."""
+
+    def __init__(self, n, ranks, J, lam, seed=0, x_dtype="f32", work_dtype="f32", gram="work",
+                 device="cuda", stream=None):
+        self.n = [int(x) for x in n]
+        self.ranks = [int(x) for x in ranks]
+        self.d = len(self.n)
+        self.J = int(J)
+        self.lam = float(lam)
+        self.x_dtype, self.work_dtype = x_dtype, work_dtype
+        self.device = torch.device(device)
+        if x_dtype not in _DT or work_dtype not in ("f64", "f32") or gram not in _GRAM:
+            raise ValueError("bad dtype or gram mode")
+        if len(self.ranks) != self.d + 1:
+            raise ValueError("ranks must have d+1 entries")
+        self._n_arr = (ctypes.c_int64 * self.d)(*self.n)
+        self._r_arr = (ctypes.c_int64 * (self.d + 1))(*self.ranks)
+        desc = _abi.PlanDesc(self.d, self._n_arr, self._r_arr, self.J, self.lam, int(seed) & (2 ** 64 - 1),
+                             _DT[x_dtype], _DT[work_dtype], _GRAM[gram], 0)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        ws = ctypes.c_size_t(0)
+        h = ctypes.c_void_p()
+        check(_lib.tt_sketch_plan(ctypes.byref(desc), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(ws),
+                                  ctypes.byref(h)), "tt_sketch_plan")
+        self._h = h
+        self.workspace_bytes = ws.value
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        check(_lib.tt_plan_bind_workspace(self._h, ctypes.c_void_p(aligned), self.workspace_bytes),
+              "tt_plan_bind_workspace")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.tt_plan_destroy(h)
+            self._h = None
+
+    # -- shapes
+    @property
+    def N(self):
+        return int(np.prod(self.n))
+
+    def core_shape(self, k):
+        return (self.ranks[k], self.n[k], self.ranks[k + 1])
+
+    def s(self, k):
+        return self.ranks[k] * self.ranks[k + 1]
+
+    @property
+    def wdtype(self):
+        return _TORCH[self.work_dtype]
+
+    # -- argument checks
+    def _check_X(self, X):
+        if not (isinstance(X, torch.Tensor) and X.device.type == "cuda" and X.is_contiguous()
+                and X.dtype == _TORCH[self.x_dtype] and X.numel() == self.N):
+            raise ValueError("X must be a contiguous %s device tensor with %d entries" % (self.x_dtype, self.N))
+
+    def _check_work(self, T, numel, name):
+        if not (isinstance(T, torch.Tensor) and T.device.type == "cuda" and T.is_contiguous()
+                and T.dtype == self.wdtype and T.numel() == numel):
+            raise ValueError("%s must be a contiguous %s device tensor with %d entries" % (name, self.work_dtype, numel))
+
+    def _check_core(self, G, k):
+        numel = self.ranks[k] * self.n[k] * self.ranks[k + 1]
+        if not (isinstance(G, torch.Tensor) and G.device.type == "cuda" and G.is_contiguous()
+                and G.dtype == torch.float64 and G.numel() == numel):
+            raise ValueError("core %d must be a contiguous float64 device tensor with %d entries" % (k, numel))
+
+    def _cores(self, cores, skip=None):
+        if len(cores) != self.d:
+            raise ValueError("need %d cores" % self.d)
+        ptrs = []
+        for k, G in enumerate(cores):
+            if k == skip and G is None:
+                ptrs.append(None)
+                continue
+            self._check_core(G, k)
+            ptrs.append(G.data_ptr())
+        return _abi.ptr_array(ptrs)
+
+    # -- tables
+    def set_sweep(self, t):
+        check(_lib.tt_plan_set_sweep(self._h, int(t)), "tt_plan_set_sweep")
+
+    def get_sweep(self):
+        t = ctypes.c_int64()
+        check(_lib.tt_plan_get_sweep(self._h, ctypes.byref(t)), "tt_plan_get_sweep")
+        return t.value
+
+    def get_tables(self, s):
+        ns = self.n[s]
+        h = (ctypes.c_int32 * ns)()
+        v = (ctypes.c_int8 * ns)()
+        check(_lib.tt_plan_get_tables(self._h, int(s), h, v), "tt_plan_get_tables")
+        return np.array(h, dtype=np.int64), np.array(v, dtype=np.int8)
+
+    def set_tables(self, s, h, v):
+        ns = self.n[s]
+        h = np.asarray(h, dtype=np.int32)
+        v = np.asarray(v, dtype=np.int8)
+        if h.shape != (ns,) or v.shape != (ns,):
+            raise ValueError("tables of mode %d need %d entries" % (s, ns))
+        check(_lib.tt_plan_set_tables(self._h, int(s), (ctypes.c_int32 * ns)(*h.tolist()),
+                                      (ctypes.c_int8 * ns)(*v.tolist())), "tt_plan_set_tables")
+
+    # -- the hot path
+    def sketch_tensor(self, X, k, Y=None):
+        self._check_X(X)
+        if Y is None:
+            Y = torch.empty(self.J * self.n[k], dtype=self.wdtype, device=self.device)
+        self._check_work(Y, self.J * self.n[k], "Y")
+        check(_lib.tt_sketch_tensor(self._h, _ptr(X), int(k), _ptr(Y)), "tt_sketch_tensor")
+        return Y
+
+    def sketch_interface(self, cores, k, SH=None):
+        arr, keep = self._cores(cores, skip=k)
+        if SH is None:
+            SH = torch.empty(self.J * self.s(k), dtype=self.wdtype, device=self.device)
+        self._check_work(SH, self.J * self.s(k), "SH")
+        check(_lib.tt_sketch_interface(self._h, arr, int(k), _ptr(SH)), "tt_sketch_interface")
+        return SH
+
+    def prox_solve(self, k, SH, Y, G_old, G_new=None):
+        self._check_work(SH, self.J * self.s(k), "SH")
+        self._check_work(Y, self.J * self.n[k], "Y")
+        self._check_core(G_old, k)
+        if G_new is None:
+            G_new = torch.empty_like(G_old)
+        self._check_core(G_new, k)
+        check(_lib.tt_prox_solve(self._h, int(k), _ptr(SH), _ptr(Y), _ptr(G_old), _ptr(G_new)), "tt_prox_solve")
+        return G_new
+
+    def left_orth_absorb(self, cores, k):
+        arr, keep = self._cores(cores)
+        check(_lib.tt_left_orth_absorb(self._h, arr, int(k)), "tt_left_orth_absorb")
+
+    def right_orthogonalize(self, cores):
+        arr, keep = self._cores(cores)
+        check(_lib.tt_right_orthogonalize(self._h, arr), "tt_right_orthogonalize")
+
+    def residual(self, X, cores):
+        self._check_X(X)
+        arr, keep = self._cores(cores)
+        out = ctypes.c_double()
+        check(_lib.tt_residual(self._h, _ptr(X), arr, ctypes.byref(out)), "tt_residual")
+        return out.value
+
+    def als_sweep(self, X, cores, residual=False):
+        self._check_X(X)
+        arr, keep = self._cores(cores)
+        if residual:
+            out = ctypes.c_double()
+            check(_lib.tt_als_sweep(self._h, _ptr(X), arr, ctypes.byref(out)), "tt_als_sweep")
+            return out.value
+        check(_lib.tt_als_sweep(self._h, _ptr(X), arr, None), "tt_als_sweep")
+        return None
+
+    def sync_status(self):
+        check(_lib.tt_plan_sync_status(self._h), "tt_plan_sync_status")
+
+
+__all__ = ["Plan", "TTError", "core_to_device", "core_to_host", "version"]

@@ -1,0 +1,94 @@
+"""ctypes declarations of the C ABI in include/tt_sketch.h (argument marshalling only)."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libttsketch.so")
+
+TT_OK, TT_ERR_ARG, TT_ERR_SHAPE, TT_ERR_WORKSPACE, TT_ERR_HIP, TT_ERR_NOT_SPD, TT_ERR_NONFINITE, TT_ERR_STATE = range(8)
+STATUS_NAMES = {0: "TT_OK", 1: "TT_ERR_ARG", 2: "TT_ERR_SHAPE", 3: "TT_ERR_WORKSPACE", 4: "TT_ERR_HIP",
+                5: "TT_ERR_NOT_SPD", 6: "TT_ERR_NONFINITE", 7: "TT_ERR_STATE"}
+TT_F64, TT_F32, TT_BF16 = 0, 1, 2
+TT_GRAM_WORK, TT_GRAM_BF16 = 0, 1
+
+MAX_ORDER, MAX_J, MAX_RANK, MAX_S, MAX_N0 = 16, 8192, 16, 180, 4096
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32),
+        ("n", ctypes.POINTER(ctypes.c_int64)),
+        ("r", ctypes.POINTER(ctypes.c_int64)),
+        ("J", ctypes.c_int64),
+        ("lambda_", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("x_dtype", ctypes.c_int32),
+        ("work_dtype", ctypes.c_int32),
+        ("gram_mode", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+_vp = ctypes.c_void_p
+_vpp = ctypes.POINTER(ctypes.c_void_p)
+
+# (name, argtypes) of every exported entry point; all return tt_status (int)
+# except the two string getters.
+SIGNATURES = {
+    "tt_sketch_plan": [ctypes.POINTER(PlanDesc), _vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_vp)],
+    "tt_plan_bind_workspace": [_vp, _vp, ctypes.c_size_t],
+    "tt_plan_set_stream": [_vp, _vp],
+    "tt_plan_destroy": [_vp],
+    "tt_plan_set_sweep": [_vp, ctypes.c_int64],
+    "tt_plan_get_sweep": [_vp, ctypes.POINTER(ctypes.c_int64)],
+    "tt_plan_get_tables": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int8)],
+    "tt_plan_set_tables": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int8)],
+    "tt_sketch_tensor": [_vp, _vp, ctypes.c_int32, _vp],
+    "tt_sketch_interface": [_vp, _vpp, ctypes.c_int32, _vp],
+    "tt_prox_solve": [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp],
+    "tt_left_orth_absorb": [_vp, _vpp, ctypes.c_int32],
+    "tt_right_orthogonalize": [_vp, _vpp],
+    "tt_residual": [_vp, _vp, _vpp, ctypes.POINTER(ctypes.c_double)],
+    "tt_als_sweep": [_vp, _vp, _vpp, ctypes.POINTER(ctypes.c_double)],
+    "tt_plan_sync_status": [_vp],
+}
+STRING_FUNCS = ["tt_last_error", "tt_version"]
+
+_lib = None
+
+
+def load():
+    """Load the in-tree HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libttsketch.so not found at %s: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    for name in STRING_FUNCS:
+        f = getattr(lib, name)
+        f.argtypes = []
+        f.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class TTError(RuntimeError):
+    def __init__(self, status, func, msg):
+        super().__init__("%s returned %s: %s" % (func, STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def check(status, func):
+    if status != TT_OK:
+        raise TTError(status, func, load().tt_last_error().decode())
+
+
+def ptr_array(ptrs):
+    arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
+    return ctypes.cast(arr, _vpp), arr

@@ -1,0 +1,410 @@
+// C ABI of the TT-TensorSketch library: plan, workspace layout, validation,
+// and the orchestration of Algorithm 1 (Sec. 3) on one HIP stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "tt_internal.h"
+
+namespace {
+thread_local char g_err[512] = "";
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+CoreDesc make_desc(const tt_plan_s* p, const void* const* cores) {
+  CoreDesc cd{};
+  cd.d = p->d;
+  int64_t off = 0;
+  for (int i = 0; i < p->d; ++i) {
+    cd.G[i] = cores ? static_cast<const double*>(cores[i]) : nullptr;
+    cd.r0[i] = (int32_t)p->r[i];
+    cd.n[i] = (int32_t)p->n[i];
+    cd.r1[i] = (int32_t)p->r[i + 1];
+    cd.tab_off[i] = (int32_t)p->tab_off[i];
+    cd.chat_off[i] = off;
+    off += p->r[i] * p->r[i + 1];
+  }
+  return cd;
+}
+
+tt_status check_plan(tt_plan p) {
+  if (!p) return tt_fail(TT_ERR_ARG, "null plan");
+  if (!p->ws) return tt_fail(TT_ERR_WORKSPACE, "no workspace bound (tt_plan_bind_workspace)");
+  return TT_OK;
+}
+
+tt_status check_cores(tt_plan p, const void* const* cores) {
+  if (!cores) return tt_fail(TT_ERR_ARG, "null core array");
+  for (int i = 0; i < p->d; ++i)
+    if (!cores[i]) return tt_fail(TT_ERR_ARG, "core %d is null", i);
+  return TT_OK;
+}
+
+tt_status gen_tables(tt_plan p) {
+  TT_HIP_TRY(launch_gen_tables(p, p->sweep));
+  p->override_tables = false;
+  return TT_OK;
+}
+
+// QR + absorb of Algorithm 1's inner loop, k < d-1.
+tt_status left_orth(tt_plan p, double* const* G, int k) {
+  const int64_t m = p->r[k] * p->n[k], r = p->r[k + 1];
+  TT_HIP_TRY(launch_qr_core(p, G[k], m, r, 1, m));
+  TT_HIP_TRY(launch_absorb_left(p, G[k + 1], r, p->n[k + 1] * p->r[k + 2]));
+  return TT_OK;
+}
+
+// One step of the right-to-left orthogonalisation, k >= 1.
+tt_status right_orth(tt_plan p, double* const* G, int k) {
+  const int64_t m = p->n[k] * p->r[k + 1], r = p->r[k];
+  TT_HIP_TRY(launch_qr_core(p, G[k], m, r, r, 1));
+  TT_HIP_TRY(launch_absorb_right(p, G[k - 1], p->r[k - 1] * p->n[k - 1], r));
+  return TT_OK;
+}
+
+}  // namespace
+
+void tt_set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+tt_status tt_fail(tt_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+extern "C" {
+
+const char* tt_last_error(void) { return g_err; }
+const char* tt_version(void) { return "tt_sketch 0.1 gfx950"; }
+
+tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* workspace_bytes, tt_plan* out) {
+  if (!desc || !workspace_bytes || !out) return tt_fail(TT_ERR_ARG, "null argument");
+  const int d = desc->d;
+  if (d < 2 || d > TT_MAX_ORDER) return tt_fail(TT_ERR_SHAPE, "order d=%d outside [2, %d]", d, TT_MAX_ORDER);
+  if (!desc->n || !desc->r) return tt_fail(TT_ERR_ARG, "null n or r");
+  if (desc->flags != 0) return tt_fail(TT_ERR_ARG, "flags must be 0");
+  if (desc->x_dtype != TT_F64 && desc->x_dtype != TT_F32 && desc->x_dtype != TT_BF16)
+    return tt_fail(TT_ERR_ARG, "bad x_dtype");
+  if (desc->work_dtype != TT_F64 && desc->work_dtype != TT_F32) return tt_fail(TT_ERR_ARG, "work_dtype must be F64 or F32");
+  if (desc->gram_mode != TT_GRAM_WORK && desc->gram_mode != TT_GRAM_BF16) return tt_fail(TT_ERR_ARG, "bad gram_mode");
+  if (desc->gram_mode == TT_GRAM_BF16 && desc->work_dtype != TT_F32)
+    return tt_fail(TT_ERR_ARG, "TT_GRAM_BF16 needs work_dtype F32");
+  if (!(desc->lambda >= 0.0) || !isfinite(desc->lambda)) return tt_fail(TT_ERR_ARG, "lambda must be finite and >= 0");
+  const int64_t Jmax = desc->work_dtype == TT_F64 ? TT_MAX_J / 2 : TT_MAX_J;
+  if (desc->J < 1 || desc->J > Jmax) return tt_fail(TT_ERR_ARG, "J=%lld outside [1, %lld]", (long long)desc->J, (long long)Jmax);
+  int rad[32], nrad = 0;
+  if (!tt_factor_fft(desc->J, rad, &nrad)) return tt_fail(TT_ERR_ARG, "J=%lld has a prime factor > 7", (long long)desc->J);
+  if (desc->r[0] != 1 || desc->r[d] != 1) return tt_fail(TT_ERR_SHAPE, "boundary ranks must be 1");
+  int64_t N = 1;
+  for (int k = 0; k < d; ++k) {
+    const int64_t nk = desc->n[k];
+    if (nk < 1 || nk > (int64_t)1 << 30) return tt_fail(TT_ERR_SHAPE, "n[%d]=%lld out of range", k, (long long)nk);
+    if (N > ((int64_t)1 << 46) / nk) return tt_fail(TT_ERR_SHAPE, "tensor too large");
+    N *= nk;
+  }
+  if (desc->n[0] > TT_MAX_N0) return tt_fail(TT_ERR_SHAPE, "n[0]=%lld > %d", (long long)desc->n[0], TT_MAX_N0);
+  for (int k = 1; k < d; ++k) {
+    const int64_t rk = desc->r[k];
+    if (rk < 1 || rk > TT_MAX_RANK) return tt_fail(TT_ERR_SHAPE, "r[%d]=%lld outside [1, %d]", k, (long long)rk, TT_MAX_RANK);
+    if (rk > desc->r[k - 1] * desc->n[k - 1] || rk > desc->n[k] * desc->r[k + 1])
+      return tt_fail(TT_ERR_SHAPE, "rank r[%d]=%lld is infeasible", k, (long long)rk);
+  }
+  for (int k = 0; k < d; ++k)
+    if (desc->r[k] * desc->r[k + 1] > TT_MAX_S)
+      return tt_fail(TT_ERR_SHAPE, "r[%d] r[%d] > %d", k, k + 1, TT_MAX_S);
+
+  tt_plan_s* p = new (std::nothrow) tt_plan_s();
+  if (!p) return tt_fail(TT_ERR_ARG, "out of host memory");
+  p->d = d;
+  for (int k = 0; k < d; ++k) p->n[k] = desc->n[k];
+  for (int k = 0; k <= d; ++k) p->r[k] = desc->r[k];
+  p->J = desc->J;
+  p->lambda = desc->lambda;
+  p->seed = desc->seed;
+  p->xdt = desc->x_dtype;
+  p->wdt = desc->work_dtype;
+  p->gram_mode = desc->gram_mode;
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  p->sweep = 0;
+  p->override_tables = false;
+  p->N = N;
+  p->fft_nrad = nrad;
+  for (int i = 0; i < nrad; ++i) p->fft_radix[i] = rad[i];
+
+  p->tab_off[0] = 0;
+  p->max_n = 0;
+  for (int k = 0; k < d; ++k) {
+    p->tab_off[k + 1] = p->tab_off[k] + p->n[k];
+    if (p->n[k] > p->max_n) p->max_n = p->n[k];
+  }
+  p->s_max = 0;
+  p->r_max = 1;
+  p->chat_cols = 0;
+  p->qr_m = 1;
+  for (int k = 0; k < d; ++k) {
+    const int64_t s = p->r[k] * p->r[k + 1];
+    if (s > p->s_max) p->s_max = s;
+    if (p->r[k + 1] > p->r_max) p->r_max = p->r[k + 1];
+    p->chat_cols += s;
+    const int64_t m1 = p->r[k] * p->n[k], m2 = p->n[k] * p->r[k + 1];
+    if (m1 > p->qr_m) p->qr_m = m1;
+    if (m2 > p->qr_m) p->qr_m = m2;
+  }
+  p->O0 = 1;
+  for (int s = 2; s < d; ++s) p->O0 *= p->n[s];
+  if (p->O0 >= ((int64_t)1 << 31)) {
+    delete p;
+    return tt_fail(TT_ERR_SHAPE, "prod n[2..d-1] must be < 2^31");
+  }
+  p->max_M = 1;
+  for (int s = 1; s < d - 1; ++s) p->max_M *= p->n[s];
+  p->max_R = p->O0 > 1 ? p->O0 : 1;
+  p->part_entries = 1;
+  for (int k = 1; k < d; ++k) {
+    const int64_t e = p->n[k] * tt_sketch_chunks(p, k) * p->J;
+    if (e > p->part_entries) p->part_entries = e;
+  }
+  p->gram_chunks = tt_gram_chunks(p->J);
+  int64_t rb = (p->O0 + 3) / 4;
+  if (rb > 2048) rb = 2048;
+  if (rb < 1) rb = 1;
+  p->res_waves = 4 * rb;
+
+  const size_t ws = p->wsize();
+  const size_t gs = (p->wdt == TT_F64) ? 8 : 4;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + (bytes ? bytes : 1));
+    return at;
+  };
+  p->o_tab = take(sizeof(uint32_t) * p->tab_off[d]);
+  p->o_KI = take(sizeof(uint32_t) * p->max_M);
+  p->o_KO = take(sizeof(uint32_t) * p->max_R);
+  p->o_cnt = take(sizeof(uint32_t) * (p->J + 1));
+  p->o_cursor = take(sizeof(uint32_t) * p->J);
+  p->o_sortO = take(sizeof(uint32_t) * p->max_R);
+  p->o_part = take(ws * p->part_entries);
+  p->o_chat = take(2 * ws * p->J * p->chat_cols);
+  p->o_pre = take(2 * ws * p->J * TT_MAX_RANK);
+  p->o_suf = take(2 * ws * p->J * TT_MAX_RANK);
+  p->o_SH = take(ws * p->J * p->s_max);
+  p->o_Y = take(ws * p->J * p->max_n);
+  p->o_gram = take(gs * p->gram_chunks * p->s_max * (p->s_max + p->max_n));
+  p->o_minv = take(sizeof(double) * p->s_max * p->s_max);
+  p->o_W = take(sizeof(double));
+  p->o_qrA = take(sizeof(double) * p->qr_m * p->r_max);
+  p->o_qrQ = take(sizeof(double) * p->qr_m * p->r_max);
+  p->o_qrR = take(sizeof(double) * p->r_max * p->r_max);
+  p->o_status = take(64);
+  p->o_res = take(sizeof(double) * (2 * p->res_waves + 8));
+  p->o_gold = take(sizeof(double));
+  p->ws_need = o;
+  p->ws = nullptr;
+  p->ws_bytes = 0;
+  *workspace_bytes = o;
+  *out = p;
+  g_err[0] = 0;
+  return TT_OK;
+}
+
+tt_status tt_plan_bind_workspace(tt_plan p, void* dev_ws, size_t bytes) {
+  if (!p || !dev_ws) return tt_fail(TT_ERR_ARG, "null argument");
+  if (bytes < p->ws_need) return tt_fail(TT_ERR_WORKSPACE, "workspace %zu bytes < required %zu", bytes, p->ws_need);
+  if (((uintptr_t)dev_ws & 255) != 0) return tt_fail(TT_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  p->ws = static_cast<char*>(dev_ws);
+  p->ws_bytes = bytes;
+  TT_HIP_TRY(hipMemsetAsync(p->ws + p->o_status, 0, 64, p->stream));
+  return gen_tables(p);
+}
+
+tt_status tt_plan_set_stream(tt_plan p, void* s) {
+  if (!p) return tt_fail(TT_ERR_ARG, "null plan");
+  p->stream = static_cast<hipStream_t>(s);
+  return TT_OK;
+}
+
+tt_status tt_plan_destroy(tt_plan p) {
+  delete p;
+  return TT_OK;
+}
+
+tt_status tt_plan_set_sweep(tt_plan p, int64_t t) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (t < 0) return tt_fail(TT_ERR_ARG, "sweep index must be >= 0");
+  p->sweep = t;
+  return gen_tables(p);
+}
+
+tt_status tt_plan_get_sweep(tt_plan p, int64_t* t) {
+  if (!p || !t) return tt_fail(TT_ERR_ARG, "null argument");
+  *t = p->sweep;
+  return TT_OK;
+}
+
+tt_status tt_plan_get_tables(tt_plan p, int32_t s, int32_t* h, int8_t* v) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (s < 0 || s >= p->d || !h || !v) return tt_fail(TT_ERR_ARG, "bad mode or null output");
+  const int64_t ns = p->n[s];
+  std::vector<uint32_t> buf(ns);
+  TT_HIP_TRY(hipMemcpyAsync(buf.data(), p->ws + p->o_tab + sizeof(uint32_t) * p->tab_off[s], sizeof(uint32_t) * ns,
+                            hipMemcpyDeviceToHost, p->stream));
+  TT_HIP_TRY(hipStreamSynchronize(p->stream));
+  for (int64_t i = 0; i < ns; ++i) {
+    h[i] = (int32_t)(buf[i] & TT_KEY_MASK);
+    v[i] = (buf[i] & TT_KEY_SIGN) ? -1 : 1;
+  }
+  return TT_OK;
+}
+
+tt_status tt_plan_set_tables(tt_plan p, int32_t s, const int32_t* h, const int8_t* v) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (s < 0 || s >= p->d || !h || !v) return tt_fail(TT_ERR_ARG, "bad mode or null input");
+  const int64_t ns = p->n[s];
+  std::vector<uint32_t> buf(ns);
+  for (int64_t i = 0; i < ns; ++i) {
+    if (h[i] < 0 || h[i] >= p->J || (v[i] != 1 && v[i] != -1))
+      return tt_fail(TT_ERR_ARG, "table entry %lld of mode %d out of range", (long long)i, s);
+    buf[i] = (uint32_t)h[i] | (v[i] < 0 ? TT_KEY_SIGN : 0u);
+  }
+  TT_HIP_TRY(hipMemcpyAsync(p->ws + p->o_tab + sizeof(uint32_t) * p->tab_off[s], buf.data(), sizeof(uint32_t) * ns,
+                            hipMemcpyHostToDevice, p->stream));
+  TT_HIP_TRY(hipStreamSynchronize(p->stream));
+  p->override_tables = true;
+  return TT_OK;
+}
+
+tt_status tt_sketch_tensor(tt_plan p, const void* X, int32_t k, void* Y) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (!X || !Y) return tt_fail(TT_ERR_ARG, "null X or Y");
+  if (k < 0 || k >= p->d) return tt_fail(TT_ERR_ARG, "k=%d out of range", k);
+  TT_HIP_TRY(launch_sketch_tensor(p, X, k, Y));
+  return TT_OK;
+}
+
+tt_status tt_sketch_interface(tt_plan p, const void* const* cores, int32_t k, void* SH) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (k < 0 || k >= p->d) return tt_fail(TT_ERR_ARG, "k=%d out of range", k);
+  if (!cores || !SH) return tt_fail(TT_ERR_ARG, "null argument");
+  for (int i = 0; i < p->d; ++i)
+    if (i != k && !cores[i]) return tt_fail(TT_ERR_ARG, "core %d is null", i);
+  const CoreDesc cd = make_desc(p, cores);
+  TT_HIP_TRY(launch_core_fft(p, cd, 0, p->d - 1, k));
+  TT_HIP_TRY(launch_interface_from_chat(p, cd, k, SH));
+  return TT_OK;
+}
+
+tt_status tt_prox_solve(tt_plan p, int32_t k, const void* SH, const void* Y, const void* G_old, void* G_new) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (k < 0 || k >= p->d) return tt_fail(TT_ERR_ARG, "k=%d out of range", k);
+  if (!SH || !Y || !G_old || !G_new) return tt_fail(TT_ERR_ARG, "null argument");
+  TT_HIP_TRY(launch_gram(p, k, SH, Y));
+  TT_HIP_TRY(launch_prox_from_gram(p, k, static_cast<const double*>(G_old), static_cast<double*>(G_new)));
+  return TT_OK;
+}
+
+tt_status tt_left_orth_absorb(tt_plan p, void* const* cores, int32_t k) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (k < 0 || k >= p->d - 1) return tt_fail(TT_ERR_ARG, "k=%d out of range [0, d-2]", k);
+  if ((st = check_cores(p, cores))) return st;
+  return left_orth(p, reinterpret_cast<double* const*>(cores), k);
+}
+
+tt_status tt_right_orthogonalize(tt_plan p, void* const* cores) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if ((st = check_cores(p, cores))) return st;
+  double* const* G = reinterpret_cast<double* const*>(cores);
+  for (int k = p->d - 1; k >= 1; --k)
+    if ((st = right_orth(p, G, k))) return st;
+  return TT_OK;
+}
+
+static tt_status residual_impl(tt_plan p, const void* X, const void* const* cores, double* out) {
+  const CoreDesc cd = make_desc(p, cores);
+  TT_HIP_TRY(launch_residual(p, X, cd));
+  double host[3];
+  double* dres = p->at<double>(p->o_res) + 2 * p->res_waves;
+  TT_HIP_TRY(hipMemcpyAsync(host, dres, sizeof host, hipMemcpyDeviceToHost, p->stream));
+  TT_HIP_TRY(hipStreamSynchronize(p->stream));
+  *out = host[0];
+  if (!isfinite(host[0])) return tt_fail(TT_ERR_NONFINITE, "residual is not finite (%g / %g)", host[1], host[2]);
+  return TT_OK;
+}
+
+tt_status tt_residual(tt_plan p, const void* X, const void* const* cores, double* rel_residual) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (!X || !rel_residual) return tt_fail(TT_ERR_ARG, "null argument");
+  if ((st = check_cores(p, cores))) return st;
+  return residual_impl(p, X, cores, rel_residual);
+}
+
+tt_status tt_plan_sync_status(tt_plan p) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  int32_t flags[1] = {0};
+  TT_HIP_TRY(hipMemcpyAsync(flags, p->ws + p->o_status, sizeof flags, hipMemcpyDeviceToHost, p->stream));
+  TT_HIP_TRY(hipStreamSynchronize(p->stream));
+  TT_HIP_TRY(hipMemsetAsync(p->ws + p->o_status, 0, 64, p->stream));
+  if (flags[0] & 1) return tt_fail(TT_ERR_NOT_SPD, "Cholesky of SH^T SH + lambda I failed (not positive definite)");
+  return TT_OK;
+}
+
+tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel_residual) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (!X) return tt_fail(TT_ERR_ARG, "null X");
+  if ((st = check_cores(p, cores))) return st;
+  double* const* G = reinterpret_cast<double* const*>(cores);
+  const int d = p->d;
+  // 1. right-to-left orthogonalisation
+  for (int k = d - 1; k >= 1; --k)
+    if ((st = right_orth(p, G, k))) return st;
+  // 2. tables of this sweep are current (generated at bind / set_sweep / end of
+  //    the previous sweep, or overridden)
+  const CoreDesc cd = make_desc(p, cores);
+  void* SH = p->ws + p->o_SH;
+  void* Y = p->ws + p->o_Y;
+  // transformed CountSketches of all cores (core 0 is not needed for k = 0)
+  TT_HIP_TRY(launch_core_fft(p, cd, 0, d - 1, 0));
+  for (int k = 0; k < d; ++k) {
+    TT_HIP_TRY(launch_interface_from_chat(p, cd, k, SH));
+    TT_HIP_TRY(launch_sketch_tensor(p, X, k, Y));
+    TT_HIP_TRY(launch_gram(p, k, SH, Y));
+    TT_HIP_TRY(launch_prox_from_gram(p, k, G[k], G[k]));
+    if (k < d - 1) {
+      if ((st = left_orth(p, G, k))) return st;
+      // core k changed (now Q); it enters every later prefix
+      TT_HIP_TRY(launch_core_fft(p, cd, k, k, -1));
+    }
+  }
+  p->sweep += 1;
+  if (!p->override_tables)
+    if ((st = gen_tables(p))) return st;
+  if (rel_residual) {
+    if ((st = residual_impl(p, X, cores, rel_residual))) return st;
+    return tt_plan_sync_status(p);
+  }
+  return TT_OK;
+}
+
+}  // extern "C"

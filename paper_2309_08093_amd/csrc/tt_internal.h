@@ -1,0 +1,100 @@
+// Internal declarations of the TT-TensorSketch HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/tt_sketch.h"
+
+// Packed hash key: bits 0..30 bucket in [0, J), bit 31 sign (1 = negative).
+#define TT_KEY_MASK 0x7fffffffu
+#define TT_KEY_SIGN 0x80000000u
+
+struct tt_plan_s {
+  int d;
+  int64_t n[TT_MAX_ORDER];
+  int64_t r[TT_MAX_ORDER + 1];
+  int64_t J;
+  double lambda;
+  uint64_t seed;
+  tt_dtype xdt, wdt;
+  int gram_mode;
+  hipStream_t stream;
+  int64_t sweep;
+  bool override_tables;
+
+  // derived sizes
+  int64_t N;                   // entries of X
+  int64_t tab_off[TT_MAX_ORDER + 1];   // prefix of n (packed table offsets)
+  int64_t max_n, s_max, r_max;
+  int64_t max_M, max_R;        // largest inner / outer fibre-key table
+  int64_t O0;                  // outer combos for k = 0 (modes 2..d-1)
+  int64_t part_entries;        // data-sketch partial accumulators (work type elements)
+  int64_t gram_chunks;         // split-K chunks of the Gram
+  int64_t chat_cols;           // sum_i R_i R_{i+1}
+  int64_t qr_m;                // max rows of a QR operand
+  int fft_radix[32];
+  int fft_nrad;
+  int64_t res_waves;
+
+  // workspace
+  char* ws;
+  size_t ws_bytes;
+  size_t ws_need;
+  size_t o_tab, o_KI, o_KO, o_cnt, o_cursor, o_sortO, o_part, o_chat, o_pre, o_suf, o_SH, o_Y,
+      o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold;
+
+  template <typename T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  size_t wsize() const { return wdt == TT_F64 ? 8 : 4; }
+  size_t xsize() const { return xdt == TT_F64 ? 8 : (xdt == TT_F32 ? 4 : 2); }
+};
+
+// Error plumbing ------------------------------------------------------------
+void tt_set_error(const char* fmt, ...);
+tt_status tt_fail(tt_status st, const char* fmt, ...);
+#define TT_HIP_TRY(expr)                                                         \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return tt_fail(TT_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Per-core launch descriptor (passed by value to kernels).
+struct CoreDesc {
+  const double* G[TT_MAX_ORDER];
+  int32_t r0[TT_MAX_ORDER], n[TT_MAX_ORDER], r1[TT_MAX_ORDER];
+  int32_t tab_off[TT_MAX_ORDER];
+  int64_t chat_off[TT_MAX_ORDER];   // column offset of core i in the transformed-core store
+  int32_t d;
+};
+
+// Launchers (each enqueues on p->stream; returns hipSuccess or the launch error)
+hipError_t launch_gen_tables(const tt_plan_s* p, int64_t sweep);
+hipError_t launch_build_keys(const tt_plan_s* p, uint32_t* out, int64_t count, int first, int last);
+hipError_t launch_outer_sort(const tt_plan_s* p);     // k = 0 bucket lists (modes 2..d-1)
+hipError_t launch_sketch_tensor(const tt_plan_s* p, const void* X, int k, void* Y);
+hipError_t launch_core_fft(const tt_plan_s* p, const CoreDesc& cd, int core_lo, int core_hi, int skip);
+hipError_t launch_interface_from_chat(const tt_plan_s* p, const CoreDesc& cd, int k, void* SH);
+hipError_t launch_gram(const tt_plan_s* p, int k, const void* SH, const void* Y);
+hipError_t launch_prox_from_gram(const tt_plan_s* p, int k, const double* G_old, double* G_new);
+hipError_t launch_qr_core(const tt_plan_s* p, double* G, int64_t m, int64_t rcols, int64_t rs, int64_t cs);
+hipError_t launch_absorb_left(const tt_plan_s* p, double* Gnext, int64_t r, int64_t cols);   // G^R <- R G^R
+hipError_t launch_absorb_right(const tt_plan_s* p, double* Gprev, int64_t rows, int64_t r);  // G^L <- G^L R^T
+hipError_t launch_residual(const tt_plan_s* p, const void* X, const CoreDesc& cd);
+hipError_t launch_copy_f64(const tt_plan_s* p, double* dst, const double* src, int64_t count);
+
+int64_t tt_sketch_chunks(const tt_plan_s* p, int k);   // fibre chunks per column, k >= 1
+int64_t tt_gram_chunks(int64_t J);                      // split-K chunks of the Gram
+
+// Allow a kernel more than 64 KB of dynamic LDS (gfx950 has 160 KB per CU).
+template <typename K>
+inline hipError_t tt_allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+// FFT plan helper: factor J into radices {4,2,3,5,7}; returns false if J has other factors.
+bool tt_factor_fft(int64_t J, int* radix, int* nrad);

@@ -1,0 +1,110 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/tt_sketch.h, and validates descriptors before any device
+work (the error codes documented in the header)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from tests.conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "tt_sketch.h")
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_2309_08093_amd import _abi
+    _abi.load()
+    return _abi
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:tt_status|const char\*)\s+(tt_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("tt_sketch_plan", "tt_sketch_tensor", "tt_sketch_interface", "tt_prox_solve", "tt_als_sweep"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(abi):
+    lib = abi.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(abi.SIGNATURES) | set(abi.STRING_FUNCS)
+
+
+def _desc(abi, n, r, J=16, lam=1e-3, x=None, w=None, gram=0, flags=0):
+    x = abi.TT_F32 if x is None else x
+    w = abi.TT_F32 if w is None else w
+    na = (ctypes.c_int64 * len(n))(*n)
+    ra = (ctypes.c_int64 * len(r))(*r)
+    d = abi.PlanDesc(len(n), na, ra, J, lam, 1, x, w, gram, flags)
+    return d, (na, ra)
+
+
+def _plan(abi, *a, **kw):
+    lib = abi.load()
+    d, keep = _desc(abi, *a, **kw)
+    ws = ctypes.c_size_t(0)
+    h = ctypes.c_void_p()
+    st = lib.tt_sketch_plan(ctypes.byref(d), None, ctypes.byref(ws), ctypes.byref(h))
+    return st, h, ws.value
+
+
+def test_valid_plan_reports_workspace(abi):
+    st, h, ws = _plan(abi, [200, 200, 200, 200], [1, 10, 10, 10, 1], J=4000)
+    assert st == abi.TT_OK and h.value and ws > 0
+    lib = abi.load()
+    # calls before a workspace is bound fail without touching the device
+    Y = ctypes.c_void_p(1 << 20)
+    assert lib.tt_sketch_tensor(h, Y, 0, Y) == abi.TT_ERR_WORKSPACE
+    assert b"workspace" in lib.tt_last_error()
+    assert lib.tt_plan_destroy(h) == abi.TT_OK
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=[5], r=[1, 1]), "TT_ERR_SHAPE"),                                    # d < 2
+    (dict(n=[4, 4, 4], r=[1, 2, 2, 2]), "TT_ERR_SHAPE"),                         # r_d != 1
+    (dict(n=[4, 4, 4], r=[1, 5, 2, 1]), "TT_ERR_SHAPE"),                         # r_1 > r_0 n_0
+    (dict(n=[4, 4, 4], r=[1, 4, 9, 1]), "TT_ERR_SHAPE"),                         # r_2 > n_2 r_3
+    (dict(n=[40, 40, 40], r=[1, 17, 17, 1]), "TT_ERR_SHAPE"),                    # rank > TT_MAX_RANK
+    (dict(n=[4, 4, 4], r=[1, 2, 2, 1], J=11), "TT_ERR_ARG"),                     # J has factor 11
+    (dict(n=[4, 4, 4], r=[1, 2, 2, 1], J=0), "TT_ERR_ARG"),
+    (dict(n=[4, 4, 4], r=[1, 2, 2, 1], J=8192 * 2), "TT_ERR_ARG"),
+    (dict(n=[4, 4, 4], r=[1, 2, 2, 1], lam=-1.0), "TT_ERR_ARG"),
+    (dict(n=[4, 4, 4], r=[1, 2, 2, 1], lam=float("nan")), "TT_ERR_ARG"),
+    (dict(n=[4, 4, 4], r=[1, 2, 2, 1], gram=1, w=0), "TT_ERR_ARG"),              # BF16 Gram needs F32 work
+    (dict(n=[4, 4, 4], r=[1, 2, 2, 1], flags=1), "TT_ERR_ARG"),
+    (dict(n=[5000, 4], r=[1, 4, 1]), "TT_ERR_SHAPE"),                            # n_0 > TT_MAX_N0
+])
+def test_invalid_descriptors(abi, kw, code):
+    st, h, ws = _plan(abi, **kw)
+    assert st == getattr(abi, code), (st, abi.load().tt_last_error())
+    assert abi.load().tt_last_error() != b""
+
+
+def test_null_arguments(abi):
+    lib = abi.load()
+    assert lib.tt_sketch_plan(None, None, None, None) == abi.TT_ERR_ARG
+    assert lib.tt_sketch_tensor(None, None, 0, None) == abi.TT_ERR_ARG
+    assert lib.tt_als_sweep(None, None, None, None) == abi.TT_ERR_ARG
+
+
+def test_f64_work_caps_J(abi):
+    st, h, ws = _plan(abi, [8, 8, 8], [1, 2, 2, 1], J=8192, w=0)
+    assert st == abi.TT_ERR_ARG
+    st, h, ws = _plan(abi, [8, 8, 8], [1, 2, 2, 1], J=4096, w=0)
+    assert st == abi.TT_OK
+    abi.load().tt_plan_destroy(h)
+
+
+def test_package_import_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2309_08093_amd import _abi as A
+    monkeypatch.setattr(A, "_lib", None)
+    monkeypatch.setattr(A, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        A.load()

@@ -1,0 +1,341 @@
+"""GPU parity of every step of the hot path against the FP64 oracle.
+
+All calls go through the C ABI (via the thin binding) on seeded synthetic
+inputs; the oracle receives the same arrays and the same tables.  Tolerances:
+  * hash/sign tables and integer-valued data sketches: bit-exact;
+  * FP64 work type: 1e-10 relative (Frobenius);
+  * FP32 work type: 1e-5 relative for sketches, derived bounds for solves;
+  * full sweeps: relative residual within 1e-4 of the oracle's.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth
+from oracle import als, sketch, solve, tables
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tts():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2309_08093_amd as m
+    return m
+
+
+DEV = "cuda"
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def host_tables(plan):
+    hs, vs = [], []
+    for s in range(plan.d):
+        h, v = plan.get_tables(s)
+        hs.append(h)
+        vs.append(v)
+    return hs, vs
+
+
+def to_dev_x(Xh, dtype):
+    t = synth.to_dtype_host(Xh, dtype)
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(t)
+    return t.to(DEV)
+
+
+# ------------------------------------------------------------------ tables
+@pytest.mark.parametrize("seed,n,J", [(0, [16, 16, 16, 16], 256), (12345, [200, 7, 33], 4000),
+                                      (2 ** 63 + 5, [5, 64, 3, 2, 9], 3000), (7, [3, 4], 1)])
+def test_tables_bit_exact(tts, seed, n, J):
+    say("tables", seed, n, J)
+    R = [1] + [1] * (len(n) - 1) + [1]
+    plan = tts.Plan(n, R, J, 1e-3, seed=seed, x_dtype="f32", work_dtype="f32")
+    for t in (0, 1, 7):
+        plan.set_sweep(t)
+        for s in range(len(n)):
+            h, v = plan.get_tables(s)
+            ho, vo = tables.mode_tables(seed, t, s, n[s], J)
+            assert np.array_equal(h, ho) and np.array_equal(v, vo), (t, s)
+
+
+def test_set_tables_roundtrip(tts):
+    say("set_tables")
+    n, J = [6, 5, 4], 8
+    plan = tts.Plan(n, [1, 2, 2, 1], J, 1e-3)
+    h = np.array([7, 0, 3, 3, 1, 5])
+    v = np.array([1, -1, -1, 1, 1, -1])
+    plan.set_tables(0, h, v)
+    h2, v2 = plan.get_tables(0)
+    assert np.array_equal(h2, h) and np.array_equal(v2, v)
+    with pytest.raises(tts.TTError):
+        plan.set_tables(0, np.full(6, 8), v)       # bucket out of range
+
+
+# ------------------------------------------------------------------ data sketch
+SKETCH_CASES = [
+    # n, J, x dtype, work dtype
+    ([16, 16, 16, 16], 256, "f64", "f64"),
+    ([37, 5, 9, 4], 60, "f32", "f32"),
+    ([200, 3, 2], 4000, "f32", "f32"),
+    ([65, 130], 12, "f32", "f32"),
+    ([7, 300, 5], 1000, "f32", "f32"),
+    ([64, 8, 8, 8, 8], 3000, "bf16", "f32"),
+    ([300, 4, 3], 128, "f32", "f32"),
+    ([1030, 3, 2], 50, "f32", "f32"),          # n_0 > 1024: chunked k = 0 path
+    ([1, 5, 4], 8, "f32", "f32"),
+    ([5, 1, 4], 8, "f64", "f64"),
+]
+
+
+@pytest.mark.parametrize("n,J,xd,wd", SKETCH_CASES)
+def test_data_sketch_integer_exact(tts, n, J, xd, wd):
+    say("sketch int", n, J, xd, wd)
+    N = int(np.prod(n))
+    Xh = synth.rng(1).integers(-4, 5, size=N).astype(np.float64)   # every partial sum exact in FP32
+    plan = tts.Plan(n, [1] * (len(n) + 1), J, 1e-3, seed=3, x_dtype=xd, work_dtype=wd)
+    hs, vs = host_tables(plan)
+    X = to_dev_x(Xh, xd)
+    for k in range(len(n)):
+        Y = plan.sketch_tensor(X, k).cpu().numpy().astype(np.float64).reshape(J, n[k], order="F")
+        Yo = sketch.data_sketch(Xh, n, k, hs, vs, J)
+        assert np.array_equal(Y, Yo), (k, np.abs(Y - Yo).max())
+
+
+@pytest.mark.parametrize("n,J,xd,wd", SKETCH_CASES)
+def test_data_sketch_float(tts, n, J, xd, wd):
+    say("sketch float", n, J, xd, wd)
+    N = int(np.prod(n))
+    Xh = synth.rng(2).standard_normal(N)
+    plan = tts.Plan(n, [1] * (len(n) + 1), J, 1e-3, seed=4, x_dtype=xd, work_dtype=wd)
+    hs, vs = host_tables(plan)
+    X = to_dev_x(Xh, xd)
+    Xo = synth.upcast_host(synth.to_dtype_host(Xh, xd))   # the oracle reads the same stored values
+    tol = 1e-12 if wd == "f64" else 1e-5
+    for k in range(len(n)):
+        Y = plan.sketch_tensor(X, k).cpu().numpy().astype(np.float64).reshape(J, n[k], order="F")
+        assert rel(Y, sketch.data_sketch(Xo, n, k, hs, vs, J)) < tol, k
+
+
+def test_paper_example_via_gpu_sketch(tts):
+    # Sec. 2.2 worked example: m = 2, two modes of size 2; a third mode of
+    # size 1 plays the unsketched index, one-hot inputs read off S's columns.
+    say("paper example")
+    import json, os
+    from tests.conftest import GOLDEN
+    ex = json.load(open(os.path.join(GOLDEN, "paper_example_tensorsketch.json")))
+    n = [2, 2, 1]
+    plan = tts.Plan(n, [1, 1, 1, 1], 2, 1e-3, x_dtype="f32", work_dtype="f32")
+    for s in range(2):
+        plan.set_tables(s, np.array(ex["h_one_based"][s]) - 1, np.array(ex["v"][s]))
+    plan.set_tables(2, np.array([0]), np.array([1]))
+    S = np.zeros((2, 4))
+    for j in range(4):
+        X = torch.zeros(4, dtype=torch.float32, device=DEV)
+        X[j] = 1.0
+        S[:, j] = plan.sketch_tensor(X, 2).cpu().numpy()
+    assert np.array_equal(S, np.array(ex["S"], dtype=float))
+
+
+# ------------------------------------------------------------------ interface sketch
+IFACE_CASES = [
+    ([16, 16, 16, 16], [1, 3, 3, 3, 1], 256, "f64"),
+    ([20, 9, 13, 7], [1, 4, 5, 3, 1], 120, "f32"),
+    ([12, 10, 11], [1, 6, 5, 1], 3000, "f32"),
+    ([9, 8], [1, 7, 1], 4000, "f32"),
+    ([6, 5, 4, 5, 6], [1, 3, 4, 4, 3, 1], 210, "f64"),
+    ([30, 30, 30], [1, 16, 11, 1], 210, "f32"),   # s = 176
+    ([40, 30, 20], [1, 3, 2, 1], 8000, "f32"),     # J = 8000: 128 KB of LDS per FFT
+]
+
+
+@pytest.mark.parametrize("n,R,J,wd", IFACE_CASES)
+def test_interface_sketch(tts, n, R, J, wd):
+    say("interface", n, R, J, wd)
+    cores = synth.random_cores(n, R, 7)
+    plan = tts.Plan(n, R, J, 1e-3, seed=8, x_dtype=wd, work_dtype=wd)
+    hs, vs = host_tables(plan)
+    dc = [tts.core_to_device(c) for c in cores]
+    tol = 1e-10 if wd == "f64" else 1e-5
+    for k in range(len(n)):
+        SH = plan.sketch_interface(dc, k).cpu().numpy().astype(np.float64).reshape(J, -1, order="F")
+        ref = sketch.interface_cyclic(cores, k, hs, vs, J)
+        assert rel(SH, ref) < tol, (k, rel(SH, ref))
+
+
+# ------------------------------------------------------------------ prox solve
+@pytest.mark.parametrize("r0,nk,r1,J,wd,gram", [(3, 16, 3, 256, "f64", "work"), (10, 200, 10, 4000, "f32", "work"),
+                                                (12, 37, 12, 500, "f32", "work"), (1, 50, 8, 64, "f64", "work"),
+                                                (8, 64, 8, 3000, "f32", "bf16"), (13, 9, 13, 300, "f64", "work")])
+def test_prox_solve(tts, r0, nk, r1, J, wd, gram):
+    say("prox", r0, nk, r1, J, wd, gram)
+    g = synth.rng(9)
+    n = [r0, nk, r1]             # a 3-core problem whose middle core has this shape
+    R = [1, r0, r1, 1]
+    lam = 1e-2
+    plan = tts.Plan(n, R, J, lam, x_dtype=wd, work_dtype=wd, gram=gram)
+    s = r0 * r1
+    SH = g.standard_normal((J, s)) / np.sqrt(J)
+    Y = g.standard_normal((J, nk)) / np.sqrt(J)
+    G = g.standard_normal((r0, nk, r1))
+    tdt = torch.float64 if wd == "f64" else torch.float32
+    SHd = torch.from_numpy(SH.reshape(-1, order="F").copy()).to(DEV, tdt)
+    Yd = torch.from_numpy(Y.reshape(-1, order="F").copy()).to(DEV, tdt)
+    SHo = SHd.cpu().double().numpy().reshape(J, s, order="F")
+    Yo = Yd.cpu().double().numpy().reshape(J, nk, order="F")
+    Gd = tts.core_to_device(G)
+    out = tts.core_to_host(plan.prox_solve(1, SHd, Yd, Gd), G.shape)
+    plan.sync_status()
+    if gram == "bf16":
+        # the oracle sees the same BF16-rounded operands; the FP32 accumulation
+        # and the solve are compared at a BF16-scaled bound
+        bf = lambda A: torch.from_numpy(A).float().bfloat16().double().numpy()
+        ref = solve.prox_update(bf(SHo), bf(Yo), G, lam)
+        tol = 1e-4
+    else:
+        ref = solve.prox_update(SHo, Yo, G, lam)
+        tol = 1e-11 if wd == "f64" else 2e-5
+    assert rel(out, ref) < tol, rel(out, ref)
+    # aliasing G_old == G_new is allowed
+    plan.prox_solve(1, SHd, Yd, Gd, Gd)
+    assert rel(tts.core_to_host(Gd, G.shape), out) < 1e-14
+
+
+def test_prox_not_spd_reported(tts):
+    say("not spd")
+    n, R, J = [2, 5, 2], [1, 2, 2, 1], 16
+    plan = tts.Plan(n, R, J, 0.0, x_dtype="f32", work_dtype="f32")
+    SH = torch.zeros(J * 4, dtype=torch.float32, device=DEV)
+    Y = torch.zeros(J * 5, dtype=torch.float32, device=DEV)
+    G = torch.zeros(20, dtype=torch.float64, device=DEV)
+    plan.prox_solve(1, SH, Y, G)
+    with pytest.raises(tts.TTError) as ei:
+        plan.sync_status()
+    assert ei.value.status == 5
+    plan.sync_status()   # cleared
+
+
+# ------------------------------------------------------------------ QR / orthogonalisation
+@pytest.mark.parametrize("n,R", [([16, 16, 16, 16], [1, 3, 3, 3, 1]), ([200, 20, 7], [1, 10, 7, 1]),
+                                 ([5, 4, 6, 3], [1, 5, 12, 3, 1]), ([3, 50, 40], [1, 3, 16, 1])])
+def test_orthogonalisation(tts, n, R):
+    say("orth", n, R)
+    cores = synth.random_cores(n, R, 10)
+    plan = tts.Plan(n, R, 16, 1e-3, x_dtype="f64", work_dtype="f64")
+    dc = [tts.core_to_device(c) for c in cores]
+    plan.right_orthogonalize(dc)
+    ref = solve.right_orthogonalize(cores)
+    for a, b in zip(dc, ref):
+        assert rel(tts.core_to_host(a, b.shape), b) < 1e-12
+    for k in range(len(n) - 1):
+        plan.left_orth_absorb(dc, k)
+        ref[k], ref[k + 1] = solve.left_orth_absorb(ref[k], ref[k + 1])
+        for a, b in zip(dc, ref):
+            assert rel(tts.core_to_host(a, b.shape), b) < 1e-12
+
+
+def test_qr_zero_core_convention(tts):
+    say("qr zeros")
+    n, R = [4, 5, 3], [1, 3, 2, 1]
+    cores = synth.zero_cores(n, R)
+    plan = tts.Plan(n, R, 16, 1e-3, x_dtype="f64", work_dtype="f64")
+    dc = [tts.core_to_device(c) for c in cores]
+    plan.right_orthogonalize(dc)
+    ref = solve.right_orthogonalize(cores)
+    for a, b in zip(dc, ref):
+        assert np.array_equal(tts.core_to_host(a, b.shape), b)
+
+
+# ------------------------------------------------------------------ residual
+@pytest.mark.parametrize("n,R,xd,wd", [([16, 16, 16, 16], [1, 3, 3, 3, 1], "f64", "f64"),
+                                       ([40, 30, 20], [1, 5, 4, 1], "f32", "f32"),
+                                       ([300, 12], [1, 9, 1], "f32", "f32"),
+                                       ([64, 8, 8, 8], [1, 8, 8, 8, 1], "bf16", "f32")])
+def test_residual(tts, n, R, xd, wd):
+    say("residual", n, R, xd)
+    Xh, _ = synth.tt_tensor_host(n, R, 0.05, 11)
+    cores = synth.random_cores(n, R, 12)
+    plan = tts.Plan(n, R, 16, 1e-3, x_dtype=xd, work_dtype=wd)
+    X = to_dev_x(Xh, xd)
+    Xo = synth.upcast_host(synth.to_dtype_host(Xh, xd))
+    got = plan.residual(X, [tts.core_to_device(c) for c in cores])
+    ref = als.rel_residual(Xo, cores)
+    tol = 1e-12 if wd == "f64" else 1e-5
+    assert abs(got - ref) / ref < tol, (got, ref)
+    # exact TT: residual at round-off
+    X2 = to_dev_x(als.tt_full(cores), xd)
+    got2 = plan.residual(X2, [tts.core_to_device(c) for c in cores])
+    assert got2 < (1e-13 if wd == "f64" else (5e-3 if xd == "bf16" else 1e-6))
+
+
+# ------------------------------------------------------------------ full sweeps
+def _run_sweeps(tts, n, R, J, lam, seed, sweeps, xd, wd, noise, init_seed=2):
+    Xh, _ = synth.tt_tensor_host(n, R, noise, 1)
+    init = synth.random_cores(n, R, init_seed)
+    plan = tts.Plan(n, R, J, lam, seed=seed, x_dtype=xd, work_dtype=wd)
+    X = to_dev_x(Xh, xd)
+    Xo = synth.upcast_host(synth.to_dtype_host(Xh, xd))
+    dc = [tts.core_to_device(c) for c in init]
+    ref = [c.copy() for c in init]
+    res, res_o = [], []
+    for t in range(sweeps):
+        res.append(plan.als_sweep(X, dc, residual=True))
+        ref = als.sweep(Xo, n, ref, J, lam, seed=seed, t=t)
+        res_o.append(als.rel_residual(Xo, ref))
+    return plan, dc, ref, res, res_o, Xo
+
+
+def test_sweeps_c1_fp64(tts):
+    # 16^4 FP64, ranks 3, J = 256, lambda = 1e-3, noise 1e-3, 5 sweeps
+    say("sweeps C1")
+    plan, dc, ref, res, res_o, Xo = _run_sweeps(tts, [16] * 4, [1, 3, 3, 3, 1], 256, 1e-3, 17, 5, "f64", "f64", 1e-3)
+    print("gpu", res, "\noracle", res_o)
+    for a, b in zip(res, res_o):
+        assert abs(a - b) < 1e-10
+    got = [tts.core_to_host(c, r.shape) for c, r in zip(dc, ref)]
+    assert rel(als.tt_full(got), als.tt_full(ref)) < 1e-9
+    assert plan.get_sweep() == 5
+
+
+def test_sweeps_fp32(tts):
+    say("sweeps fp32")
+    plan, dc, ref, res, res_o, Xo = _run_sweeps(tts, [30, 20, 25, 10], [1, 4, 5, 3, 1], 500, 1e-3, 5, 4, "f32", "f32", 1e-2)
+    print("gpu", res, "\noracle", res_o)
+    assert abs(res[-1] - res_o[-1]) < 1e-4
+
+
+def test_injective_sweep_is_exact_prox_als(tts):
+    # h_s(i) = i prod_{t<s} n_t, v = +1, J = N: S^T S = I for every k.
+    say("injective sweep")
+    n, R, lam = [4, 5, 3], [1, 2, 3, 1], 0.1
+    J = 60
+    Xh = synth.rng(35).standard_normal(60)
+    init = synth.random_cores(n, R, 36)
+    plan = tts.Plan(n, R, J, lam, x_dtype="f64", work_dtype="f64")
+    stride = 1
+    hs, vs = [], []
+    for s, ns in enumerate(n):
+        hs.append(np.arange(ns) * stride)
+        vs.append(np.ones(ns, dtype=np.int8))
+        plan.set_tables(s, hs[-1], vs[-1])
+        stride *= ns
+    dc = [tts.core_to_device(c) for c in init]
+    plan.als_sweep(torch.from_numpy(Xh).to(DEV), dc)
+    ref = als.sweep(Xh, n, init, J, lam, tabs=(hs, vs))
+    for a, b in zip(dc, ref):
+        assert rel(tts.core_to_host(a, b.shape), b) < 1e-10
