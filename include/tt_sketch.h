@@ -164,6 +164,24 @@ tt_status tt_residual(tt_plan plan, const void* X, const void* const* cores, dou
  * synchronises. */
 tt_status tt_als_sweep(tt_plan plan, const void* X, void* const* cores, double* rel_residual);
 
+/* Measurement: when enabled, every launch of the kernels below is bracketed
+ * by a pair of HIP events recorded on the plan's stream.  Classes: */
+#define TT_PROF_SKETCH0 0    /* data sketch main kernel, k = 0 (bucket gather) */
+#define TT_PROF_SKETCHK 1    /* data sketch main kernel, k >= 1 (LDS buckets) */
+#define TT_PROF_SKETCH_AUX 2 /* data sketch key tables, bucket lists, partial sums */
+#define TT_PROF_INTERFACE 3  /* core CountSketch + FFT, chains, face-split + inverse FFT */
+#define TT_PROF_GRAM 4       /* MFMA Gram / right-hand side */
+#define TT_PROF_SOLVE 5      /* FP64 Cholesky, inverse, apply */
+#define TT_PROF_QR 6         /* FP64 Householder QR and absorb */
+#define TT_PROF_RESIDUAL 7   /* residual pass */
+#define TT_PROF_TABLES 8     /* hash/sign table generation */
+#define TT_PROF_NCLASS 9
+tt_status tt_plan_profile(tt_plan plan, int32_t enable);
+/* Synchronise, then return per class the summed milliseconds and the number
+ * of launches since the last read (arrays of nclass <= TT_PROF_NCLASS
+ * entries, host memory), and reset the counters. */
+tt_status tt_plan_profile_read(tt_plan plan, int32_t nclass, double* ms, int64_t* launches);
+
 /* Synchronise the plan's stream and report device-side failures recorded so
  * far (TT_ERR_NOT_SPD); clears the recorded status. */
 tt_status tt_plan_sync_status(tt_plan plan);

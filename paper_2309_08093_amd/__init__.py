@@ -208,6 +208,17 @@ class Plan:
         check(_lib.tt_als_sweep(self._h, _ptr(X), arr, None), "tt_als_sweep")
         return None
 
+    def profile(self, enable=True):
+        check(_lib.tt_plan_profile(self._h, 1 if enable else 0), "tt_plan_profile")
+
+    def profile_read(self):
+        """{class: (total ms, launches)} since the last read (synchronises)."""
+        nc = len(_abi.PROF_CLASSES)
+        ms = (ctypes.c_double * nc)()
+        cnt = (ctypes.c_int64 * nc)()
+        check(_lib.tt_plan_profile_read(self._h, nc, ms, cnt), "tt_plan_profile_read")
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(_abi.PROF_CLASSES)}
+
     def sync_status(self):
         check(_lib.tt_plan_sync_status(self._h), "tt_plan_sync_status")
 

@@ -51,7 +51,10 @@ SIGNATURES = {
     "tt_residual": [_vp, _vp, _vpp, ctypes.POINTER(ctypes.c_double)],
     "tt_als_sweep": [_vp, _vp, _vpp, ctypes.POINTER(ctypes.c_double)],
     "tt_plan_sync_status": [_vp],
+    "tt_plan_profile": [_vp, ctypes.c_int32],
+    "tt_plan_profile_read": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
 }
+PROF_CLASSES = ["sketch_k0", "sketch_k", "sketch_aux", "interface", "gram", "solve", "qr", "residual", "tables"]
 STRING_FUNCS = ["tt_last_error", "tt_version"]
 
 _lib = None

@@ -45,6 +45,7 @@ tt_status check_cores(tt_plan p, const void* const* cores) {
 }
 
 tt_status gen_tables(tt_plan p) {
+  TTProfScope ps(p, TT_PROF_TABLES);
   TT_HIP_TRY(launch_gen_tables(p, p->sweep));
   p->override_tables = false;
   return TT_OK;
@@ -53,6 +54,7 @@ tt_status gen_tables(tt_plan p) {
 // QR + absorb of Algorithm 1's inner loop, k < d-1.
 tt_status left_orth(tt_plan p, double* const* G, int k) {
   const int64_t m = p->r[k] * p->n[k], r = p->r[k + 1];
+  TTProfScope ps(p, TT_PROF_QR);
   TT_HIP_TRY(launch_qr_core(p, G[k], m, r, 1, m));
   TT_HIP_TRY(launch_absorb_left(p, G[k + 1], r, p->n[k + 1] * p->r[k + 2]));
   return TT_OK;
@@ -61,6 +63,7 @@ tt_status left_orth(tt_plan p, double* const* G, int k) {
 // One step of the right-to-left orthogonalisation, k >= 1.
 tt_status right_orth(tt_plan p, double* const* G, int k) {
   const int64_t m = p->n[k] * p->r[k + 1], r = p->r[k];
+  TTProfScope ps(p, TT_PROF_QR);
   TT_HIP_TRY(launch_qr_core(p, G[k], m, r, r, 1));
   TT_HIP_TRY(launch_absorb_right(p, G[k - 1], p->r[k - 1] * p->n[k - 1], r));
   return TT_OK;
@@ -172,11 +175,14 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->max_R = p->O0 > 1 ? p->O0 : 1;
   p->part_entries = 1;
   for (int k = 1; k < d; ++k) {
-    const int64_t e = p->n[k] * tt_sketch_chunks(p, k) * p->J;
+    // the largest grid a launch can use gives the most partials per column
+    const int64_t W = tt_sketch_workgroups(p, k, TT_SKETCH_MAX_WG);
+    const int64_t e = p->n[k] * tt_sketch_slots(p, k, W) * p->J;
     if (e > p->part_entries) p->part_entries = e;
   }
   p->gram_chunks = tt_gram_chunks(p->J);
-  int64_t rb = (p->O0 + 3) / 4;
+  // residual work units: (outer tuple, block of 64 i_1), four waves per block
+  int64_t rb = (p->O0 * ((p->n[1] + 63) / 64) + 3) / 4;
   if (rb > 2048) rb = 2048;
   if (rb < 1) rb = 1;
   p->res_waves = 4 * rb;
@@ -195,7 +201,7 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_cnt = take(sizeof(uint32_t) * (p->J + 1));
   p->o_cursor = take(sizeof(uint32_t) * p->J);
   p->o_sortO = take(sizeof(uint32_t) * p->max_R);
-  p->o_part = take(ws * p->part_entries);
+  p->o_part = take(sizeof(double) * p->part_entries);
   p->o_chat = take(2 * ws * p->J * p->chat_cols);
   p->o_pre = take(2 * ws * p->J * TT_MAX_RANK);
   p->o_suf = take(2 * ws * p->J * TT_MAX_RANK);
@@ -236,6 +242,7 @@ tt_status tt_plan_set_stream(tt_plan p, void* s) {
 }
 
 tt_status tt_plan_destroy(tt_plan p) {
+  if (p) tt_prof_free(p);
   delete p;
   return TT_OK;
 }
@@ -305,6 +312,7 @@ tt_status tt_sketch_interface(tt_plan p, const void* const* cores, int32_t k, vo
   for (int i = 0; i < p->d; ++i)
     if (i != k && !cores[i]) return tt_fail(TT_ERR_ARG, "core %d is null", i);
   const CoreDesc cd = make_desc(p, cores);
+  TTProfScope ps(p, TT_PROF_INTERFACE);
   TT_HIP_TRY(launch_core_fft(p, cd, 0, p->d - 1, k));
   TT_HIP_TRY(launch_interface_from_chat(p, cd, k, SH));
   return TT_OK;
@@ -315,7 +323,11 @@ tt_status tt_prox_solve(tt_plan p, int32_t k, const void* SH, const void* Y, con
   if (st) return st;
   if (k < 0 || k >= p->d) return tt_fail(TT_ERR_ARG, "k=%d out of range", k);
   if (!SH || !Y || !G_old || !G_new) return tt_fail(TT_ERR_ARG, "null argument");
-  TT_HIP_TRY(launch_gram(p, k, SH, Y));
+  {
+    TTProfScope ps(p, TT_PROF_GRAM);
+    TT_HIP_TRY(launch_gram(p, k, SH, Y));
+  }
+  TTProfScope ps(p, TT_PROF_SOLVE);
   TT_HIP_TRY(launch_prox_from_gram(p, k, static_cast<const double*>(G_old), static_cast<double*>(G_new)));
   return TT_OK;
 }
@@ -340,7 +352,10 @@ tt_status tt_right_orthogonalize(tt_plan p, void* const* cores) {
 
 static tt_status residual_impl(tt_plan p, const void* X, const void* const* cores, double* out) {
   const CoreDesc cd = make_desc(p, cores);
-  TT_HIP_TRY(launch_residual(p, X, cd));
+  {
+    TTProfScope ps(p, TT_PROF_RESIDUAL);
+    TT_HIP_TRY(launch_residual(p, X, cd));
+  }
   double host[3];
   double* dres = p->at<double>(p->o_res) + 2 * p->res_waves;
   TT_HIP_TRY(hipMemcpyAsync(host, dres, sizeof host, hipMemcpyDeviceToHost, p->stream));
@@ -385,15 +400,28 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
   void* SH = p->ws + p->o_SH;
   void* Y = p->ws + p->o_Y;
   // transformed CountSketches of all cores (core 0 is not needed for k = 0)
-  TT_HIP_TRY(launch_core_fft(p, cd, 0, d - 1, 0));
+  {
+    TTProfScope ps(p, TT_PROF_INTERFACE);
+    TT_HIP_TRY(launch_core_fft(p, cd, 0, d - 1, 0));
+  }
   for (int k = 0; k < d; ++k) {
-    TT_HIP_TRY(launch_interface_from_chat(p, cd, k, SH));
+    {
+      TTProfScope ps(p, TT_PROF_INTERFACE);
+      TT_HIP_TRY(launch_interface_from_chat(p, cd, k, SH));
+    }
     TT_HIP_TRY(launch_sketch_tensor(p, X, k, Y));
-    TT_HIP_TRY(launch_gram(p, k, SH, Y));
-    TT_HIP_TRY(launch_prox_from_gram(p, k, G[k], G[k]));
+    {
+      TTProfScope ps(p, TT_PROF_GRAM);
+      TT_HIP_TRY(launch_gram(p, k, SH, Y));
+    }
+    {
+      TTProfScope ps(p, TT_PROF_SOLVE);
+      TT_HIP_TRY(launch_prox_from_gram(p, k, G[k], G[k]));
+    }
     if (k < d - 1) {
       if ((st = left_orth(p, G, k))) return st;
       // core k changed (now Q); it enters every later prefix
+      TTProfScope ps(p, TT_PROF_INTERFACE);
       TT_HIP_TRY(launch_core_fft(p, cd, k, k, -1));
     }
   }

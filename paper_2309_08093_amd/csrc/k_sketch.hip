@@ -3,18 +3,27 @@
 //
 // X is read as a sequence of mode-0 fibres (n_0 contiguous entries).  Within a
 // fibre only i_0 varies, so the hash contribution of every other mode is one
-// wave-uniform packed key per fibre; lane l owns positions i_0 = l + 64 j and
-// keeps their packed table entries in registers.
+// packed key per fibre.  A wave reads fibres with 16-byte vector loads: lane
+// group g (LPF lanes) takes one fibre, lane v of the group the positions
+// i_0 = (v + LPF j) V + e, whose packed mode-0 table entries stay in
+// registers.  Short fibres therefore share a wave (64 / LPF fibres per load).
 //
-//  * k >= 1: one workgroup owns one column i_k of Y and a chunk of that
-//    column's fibres; it accumulates into a J-entry LDS array with LDS
-//    atomics and writes the array to a partial buffer.  A second kernel sums
-//    the partials of each column in FP64 in a fixed order.
+//  * k >= 1: persistent grid sized to the device occupancy.  The fibres of
+//    all columns i_k, column by column, are split into equal contiguous
+//    ranges, one per workgroup.  A workgroup accumulates the part of its range
+//    that lies in one column into a J-entry FP64 LDS array (LDS atomics),
+//    writes the array as one partial of that column, and moves on to the
+//    next column of its range.  A second kernel sums the partials of each
+//    column in FP64 in a fixed order.  The accumulators are FP64 for every
+//    work type: on gfx950 the LDS FP64 atomic add sustains about nine times
+//    the rate of the FP32 one, and it makes the per-bucket sums exact to
+//    FP32 rounding of the inputs.  Fibre keys are fetched 64 at a time (one
+//    vector load per lane) and handed to the lane groups by shuffles.
 //  * k = 0: a fibre has one bucket (its entries differ only in i_0, the
 //    unsketched mode), so one workgroup owns one bucket b and gathers the
-//    fibres hashed to b: for each i_1 it visits the outer tuples (modes 2..d-1)
-//    whose partial hash is (b - h_1(i_1)) mod J, found in a bucket-sorted list.
-//    Accumulation is in registers; no atomics.
+//    fibres hashed to b: for each i_1 it visits the outer tuples (modes
+//    2..d-1) whose partial hash is (b - h_1(i_1)) mod J, found in a
+//    bucket-sorted list.  Accumulation is in registers; no atomics.
 #include "tt_internal.h"
 
 namespace {
@@ -35,211 +44,364 @@ __device__ __forceinline__ WT to_work(uint16_t v) { return (WT)__uint_as_float((
 template <typename WT>
 __device__ __forceinline__ WT apply_sign(WT x, uint32_t key) { return (key & TT_KEY_SIGN) ? -x : x; }
 
-// ---------------------------------------------------------------- k >= 1
-template <typename XT, typename WT, int NJ, int U>
-__global__ __launch_bounds__(256) void k_sketch_modek(
-    const XT* __restrict__ X, const uint32_t* __restrict__ tab0, const uint32_t* __restrict__ KI,
-    const uint32_t* __restrict__ KO, WT* __restrict__ part, int32_t n0, int32_t nk, int64_t M, int64_t F,
-    uint32_t J, int32_t S) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  WT* acc = reinterpret_cast<WT*>(smem_raw);
-  const int col = blockIdx.x;
-  const int chunk = blockIdx.y;
-  for (uint32_t b = threadIdx.x; b < J; b += blockDim.x) acc[b] = (WT)0;
-
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int W = blockDim.x >> 6;
-  uint32_t t0[NJ];
+// V consecutive elements of X as one load (16 bytes when V * sizeof(XT) == 16)
+template <typename XT, int V>
+struct Vec {
+  XT e[V];
+};
+template <typename XT, int V>
+__device__ __forceinline__ Vec<XT, V> load_vec(const XT* p) {
+  if constexpr (V == 1) {
+    return Vec<XT, 1>{{*p}};
+  } else {
+    typedef XT raw_t __attribute__((ext_vector_type(V)));
+    const raw_t r = *reinterpret_cast<const raw_t*>(p);
+    Vec<XT, V> out;
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int i0 = lane + 64 * j;
-    t0[j] = i0 < n0 ? tab0[i0] : 0u;
+    for (int e = 0; e < V; ++e) out.e[e] = r[e];
+    return out;
   }
-  const int64_t q0 = F * chunk / S, q1 = F * (chunk + 1) / S;
-  const int64_t qa = q0 + (q1 - q0) * w / W, qe = q0 + (q1 - q0) * (w + 1) / W;
-  __syncthreads();
-
-  int64_t mu = qa % M, rho = qa / M;
-  for (int64_t q = qa; q < qe; q += U) {
-    const XT* base[U];
-    uint32_t kf[U];
-    bool ok[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      ok[u] = q + u < qe;
-      kf[u] = ok[u] ? key_add(KI[mu], KO[rho], J) : 0u;
-      base[u] = X + (((rho * nk + col) * M + mu) * (int64_t)n0);
-      if (++mu == M) { mu = 0; ++rho; }
-    }
-    XT v[U][NJ];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int i0 = lane + 64 * j;
-        v[u][j] = (ok[u] && i0 < n0) ? base[u][i0] : (XT)0;
-      }
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int i0 = lane + 64 * j;
-        if (ok[u] && i0 < n0) {
-          const uint32_t key = key_add(t0[j], kf[u], J);
-          atomicAdd(&acc[key & TT_KEY_MASK], apply_sign<WT>(to_work<WT>(v[u][j]), key));
-        }
-      }
-  }
-  __syncthreads();
-  WT* out = part + ((int64_t)col * S + chunk) * (int64_t)J;
-  for (uint32_t b = threadIdx.x; b < J; b += blockDim.x) out[b] = acc[b];
 }
 
-// Y[b + J i] = sum_c part[(i S + c) J + b], summed in FP64 in chunk order.
+__device__ __forceinline__ int64_t shfl64(int64_t x, int src) {
+  const int lo = __shfl((int)(uint32_t)(uint64_t)x, src, 64);
+  const int hi = __shfl((int)(uint32_t)((uint64_t)x >> 32), src, 64);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// workgroup that owns global fibre g when Ftot fibres are split into W ranges
+__device__ __forceinline__ int64_t owner(int64_t g, int64_t W, int64_t Ftot) { return ((g + 1) * W - 1) / Ftot; }
+
+// ---------------------------------------------------------------- k >= 1
+template <typename XT, typename WT, int V, int NJ, int U>
+__global__ __launch_bounds__(256) void k_sketch_modek(
+    const XT* __restrict__ X, const uint32_t* __restrict__ tab0, const uint32_t* __restrict__ KI,
+    const uint32_t* __restrict__ KO, double* __restrict__ part, int32_t n0, int32_t nk, int64_t M, int64_t F,
+    uint32_t J, int32_t lpf_log2, int32_t maxslots) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* acc = reinterpret_cast<double*>(smem_raw);
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int NW = blockDim.x >> 6;
+  const int LPF = 1 << lpf_log2;
+  const int G = 64 >> lpf_log2;          // fibres per load instruction
+  const int g = lane >> lpf_log2;
+  const int v = lane & (LPF - 1);
+  uint32_t t0[NJ][V];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const int i0 = (v + LPF * j) * V + e;
+      t0[j][e] = i0 < n0 ? tab0[i0] : 0u;
+    }
+  const int64_t W = gridDim.x;
+  const int64_t w = blockIdx.x;
+  const int64_t Ftot = (int64_t)nk * F;
+  const int64_t gs = w * Ftot / W, ge = (w + 1) * Ftot / W;
+  for (int64_t c = gs / F; gs < ge && c * F < ge; ++c) {
+    const int64_t qa = (gs > c * F ? gs : c * F) - c * F;
+    const int64_t qe = (ge < (c + 1) * F ? ge : (c + 1) * F) - c * F;
+    for (uint32_t b = threadIdx.x; b < J; b += blockDim.x) acc[b] = 0.0;
+    __syncthreads();
+    const int64_t wa = qa + (qe - qa) * wv / NW, we = qa + (qe - qa) * (wv + 1) / NW;
+    for (int64_t qb = wa; qb < we; qb += 64) {
+      // keys and element offsets of the next (up to) 64 fibres, one per lane
+      const int64_t ql = qb + lane;
+      uint32_t keyl = 0;
+      int64_t offl = 0;
+      if (ql < we) {
+        const int64_t rho = ql / M, mu = ql - rho * M;
+        keyl = key_add(KI[mu], KO[rho], J);
+        offl = ((rho * nk + c) * M + mu) * (int64_t)n0;
+      }
+      const int nb = (we - qb) < 64 ? (int)(we - qb) : 64;
+      for (int t = 0; t < nb; t += G * U) {
+        Vec<XT, V> x[U][NJ];
+        uint32_t kf[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int idx = t + u * G + g;
+          ok[u] = idx < nb;
+          kf[u] = __shfl(keyl, idx & 63, 64);
+          const int64_t off = shfl64(offl, idx & 63);
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            const int p = (v + LPF * j) * V;
+            if (ok[u] && p < n0) x[u][j] = load_vec<XT, V>(X + off + p);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            const int p = (v + LPF * j) * V;
+            if (ok[u] && p < n0) {
+#pragma unroll
+              for (int e = 0; e < V; ++e) {
+                const uint32_t key = key_add(t0[j][e], kf[u], J);
+                atomicAdd(&acc[key & TT_KEY_MASK], apply_sign<double>(to_work<double>(x[u][j].e[e]), key));
+              }
+            }
+          }
+      }
+    }
+    __syncthreads();
+    const int64_t slot = w - owner(c * F, W, Ftot);
+    double* out = part + ((int64_t)c * maxslots + slot) * (int64_t)J;
+    for (uint32_t b = threadIdx.x; b < J; b += blockDim.x) out[b] = acc[b];
+    __syncthreads();
+  }
+}
+
+// Y[b + J c] = sum over the partials of column c, in FP64, in slot order.
 template <typename WT>
-__global__ void k_reduce_parts(const WT* __restrict__ part, WT* __restrict__ Y, int64_t J, int64_t nk, int32_t S) {
+__global__ void k_reduce_parts(const double* __restrict__ part, WT* __restrict__ Y, int64_t J, int64_t nk, int64_t F,
+                               int64_t W, int32_t maxslots) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= J * nk) return;
-  const int64_t i = idx / J, b = idx - i * J;
-  const WT* p = part + i * S * J + b;
+  const int64_t c = idx / J, b = idx - c * J;
+  const int64_t Ftot = nk * F;
+  const int64_t cnt = owner((c + 1) * F - 1, W, Ftot) - owner(c * F, W, Ftot) + 1;
+  const double* p = part + c * maxslots * J + b;
   double s = 0.0;
-  for (int c = 0; c < S; ++c) s += (double)p[(int64_t)c * J];
+  for (int64_t q = 0; q < cnt; ++q) s += p[q * J];
   Y[idx] = (WT)s;
 }
 
 // ---------------------------------------------------------------- k = 0
-template <typename XT, typename WT, int NJ, int U>
+template <typename XT, typename WT, int V, int NJ, int U>
 __global__ __launch_bounds__(256) void k_sketch_mode0(
     const XT* __restrict__ X, const uint32_t* __restrict__ tab1, const uint32_t* __restrict__ off,
-    const uint32_t* __restrict__ sorted, WT* __restrict__ Y, int32_t n0, int32_t n1, uint32_t J,
-    int32_t i0_lo, int32_t i0_cnt) {
+    const uint32_t* __restrict__ sorted, WT* __restrict__ Y, int32_t n0, int32_t n1, uint32_t J, int32_t i0_lo,
+    int32_t i0_cnt, int32_t lpf_log2) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  WT* red = reinterpret_cast<WT*>(smem_raw);   // W x (NJ*64)
+  WT* red = reinterpret_cast<WT*>(smem_raw);   // NW x (64 * NJ * V)
   const uint32_t b = blockIdx.x;
   const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int W = blockDim.x >> 6;
-  WT acc[NJ];
+  const int wv = threadIdx.x >> 6;
+  const int NW = blockDim.x >> 6;
+  const int LPF = 1 << lpf_log2;
+  const int G = 64 >> lpf_log2;
+  const int g = lane >> lpf_log2;
+  const int v = lane & (LPF - 1);
+  WT acc[NJ][V];
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) acc[j] = (WT)0;
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int e = 0; e < V; ++e) acc[j][e] = (WT)0;
 
-  for (int i1 = w; i1 < n1; i1 += W) {
+  for (int i1 = wv; i1 < n1; i1 += NW) {
     const uint32_t t1 = tab1[i1];
     const uint32_t h1 = t1 & TT_KEY_MASK;
     const uint32_t c = b >= h1 ? b - h1 : b + J - h1;
     const uint32_t beg = off[c], end = off[c + 1];
-    for (uint32_t e = beg; e < end; e += U) {
-      uint32_t item[U];
-      XT v[U][NJ];
+    for (uint32_t e0 = beg; e0 < end; e0 += G * U) {
+      Vec<XT, V> x[U][NJ];
+      uint32_t sg[U];
+      bool ok[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const bool ok = e + u < end;
-        item[u] = ok ? sorted[e + u] : 0u;
-        const XT* base = X + ((int64_t)(item[u] & TT_KEY_MASK) * n1 + i1) * (int64_t)n0 + i0_lo;
+        const uint32_t e = e0 + u * G + g;
+        ok[u] = e < end;
+        const uint32_t item = ok[u] ? sorted[e] : 0u;
+        sg[u] = (item ^ t1) & TT_KEY_SIGN;
+        const XT* base = X + ((int64_t)(item & TT_KEY_MASK) * n1 + i1) * (int64_t)n0 + i0_lo;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-          const int i0 = lane + 64 * j;
-          v[u][j] = (ok && i0 < i0_cnt) ? base[i0] : (XT)0;
+          const int p = (v + LPF * j) * V;
+          if (ok[u] && p < i0_cnt) x[u][j] = load_vec<XT, V>(base + p);
         }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) acc[j] += apply_sign<WT>(to_work<WT>(v[u][j]), item[u] ^ t1);
+        for (int j = 0; j < NJ; ++j) {
+          const int p = (v + LPF * j) * V;
+          if (ok[u] && p < i0_cnt)
+#pragma unroll
+            for (int e = 0; e < V; ++e) acc[j][e] += apply_sign<WT>(to_work<WT>(x[u][j].e[e]), sg[u]);
+        }
     }
   }
+  // lane groups hold partial sums of the same positions: fold them
+  for (int m = LPF; m < 64; m <<= 1)
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) red[w * (NJ * 64) + j * 64 + lane] = acc[j];
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int e = 0; e < V; ++e) acc[j][e] += __shfl_xor(acc[j][e], m, 64);
+  constexpr int PW = 64 * NJ * V;   // positions per wave slot
+  if (g == 0)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int e = 0; e < V; ++e) red[wv * PW + (v + LPF * j) * V + e] = acc[j][e];
   __syncthreads();
   for (int i = threadIdx.x; i < i0_cnt; i += blockDim.x) {
     WT s = (WT)0;
-    for (int ww = 0; ww < W; ++ww) s += red[ww * (NJ * 64) + i];
+    for (int ww = 0; ww < NW; ++ww) s += red[ww * PW + i];
     Y[(int64_t)b + (int64_t)J * (i0_lo + i)] = s;
   }
 }
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-template <typename XT, typename WT, int NJ>
-hipError_t run_modek(const tt_plan_s* p, const XT* X, int k, WT* Y) {
+int ilog2_ceil(int64_t x) {
+  int l = 0;
+  while (((int64_t)1 << l) < x) ++l;
+  return l;
+}
+
+int g_num_cus = 0;
+int num_cus() {
+  if (g_num_cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      g_num_cus = n;
+    else
+      g_num_cus = 256;
+  }
+  return g_num_cus;
+}
+
+template <typename XT, typename WT, int V, int NJ>
+hipError_t run_modek(const tt_plan_s* p, const XT* X, int k, WT* Y, int lpf_log2) {
   constexpr int U = NJ >= 8 ? 1 : 8 / NJ;
   const int64_t n0 = p->n[0], nk = p->n[k];
   int64_t M = 1, Rk = 1;
   for (int s = 1; s < k; ++s) M *= p->n[s];
   for (int s = k + 1; s < p->d; ++s) Rk *= p->n[s];
   const int64_t F = M * Rk;
-  const int64_t S = tt_sketch_chunks(p, k);
   uint32_t* KI = p->at<uint32_t>(p->o_KI);
   uint32_t* KO = p->at<uint32_t>(p->o_KO);
   hipError_t e;
-  // an empty mode range yields the single key 0 (bucket 0, sign +)
-  if ((e = launch_build_keys(p, KI, M, 1, k - 1)) != hipSuccess) return e;
-  if ((e = launch_build_keys(p, KO, Rk, k + 1, p->d - 1)) != hipSuccess) return e;
-  WT* part = p->at<WT>(p->o_part);
+  {
+    TTProfScope ps(p, TT_PROF_SKETCH_AUX);
+    // an empty mode range yields the single key 0 (bucket 0, sign +)
+    if ((e = launch_build_keys(p, KI, M, 1, k - 1)) != hipSuccess) return e;
+    if ((e = launch_build_keys(p, KO, Rk, k + 1, p->d - 1)) != hipSuccess) return e;
+  }
+  const size_t lds = (size_t)p->J * sizeof(double);
+  auto kern = k_sketch_modek<XT, WT, V, NJ, U>;
+  int per_cu = 0;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds)) != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  const int64_t W = tt_sketch_workgroups(p, k, (int64_t)per_cu * num_cus());
+  const int64_t maxslots = tt_sketch_slots(p, k, W);
+  if (nk * maxslots * p->J > p->part_entries) return hipErrorInvalidValue;   // sized at plan time
+  double* part = p->at<double>(p->o_part);
   const uint32_t* tab0 = p->at<uint32_t>(p->o_tab) + p->tab_off[0];
-  const size_t lds = (size_t)p->J * sizeof(WT);
-  hipLaunchKernelGGL((k_sketch_modek<XT, WT, NJ, U>), dim3((unsigned)nk, (unsigned)S), dim3(256), lds, p->stream,
-                     X, tab0, KI, KO, part, (int32_t)n0, (int32_t)nk, M, F, (uint32_t)p->J, (int32_t)S);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_reduce_parts<WT>), dim3(nblk(p->J * nk, 256)), dim3(256), 0, p->stream, part, Y, p->J, nk,
-                     (int32_t)S);
+  {
+    TTProfScope ps(p, TT_PROF_SKETCHK);
+    hipLaunchKernelGGL(kern, dim3((unsigned)W), dim3(256), lds, p->stream, X, tab0, KI, KO, part, (int32_t)n0,
+                       (int32_t)nk, M, F, (uint32_t)p->J, lpf_log2, (int32_t)maxslots);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  TTProfScope ps(p, TT_PROF_SKETCH_AUX);
+  hipLaunchKernelGGL((k_reduce_parts<WT>), dim3(nblk(p->J * nk, 256)), dim3(256), 0, p->stream, part, Y, p->J, nk, F,
+                     W, (int32_t)maxslots);
   return hipGetLastError();
 }
 
-template <typename XT, typename WT, int NJ>
-hipError_t run_mode0(const tt_plan_s* p, const XT* X, WT* Y) {
+template <typename XT, typename WT, int V, int NJ>
+hipError_t run_mode0(const tt_plan_s* p, const XT* X, WT* Y, int lpf_log2, int64_t chunk) {
   constexpr int U = NJ >= 8 ? 1 : 8 / NJ;
-  hipError_t e = launch_outer_sort(p);
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  {
+    TTProfScope ps(p, TT_PROF_SKETCH_AUX);
+    if ((e = launch_outer_sort(p)) != hipSuccess) return e;
+  }
   const int64_t n0 = p->n[0], n1 = p->n[1];
   const uint32_t* tab1 = p->at<uint32_t>(p->o_tab) + p->tab_off[1];
   const uint32_t* off = p->at<uint32_t>(p->o_cnt);
   const uint32_t* sorted = p->at<uint32_t>(p->o_sortO);
-  constexpr int CH = NJ * 64;
-  const size_t lds = (size_t)4 * CH * sizeof(WT);
-  for (int64_t lo = 0; lo < n0; lo += CH) {
-    const int64_t cnt = (n0 - lo) < CH ? (n0 - lo) : CH;
-    hipLaunchKernelGGL((k_sketch_mode0<XT, WT, NJ, U>), dim3((unsigned)p->J), dim3(256), lds, p->stream, X, tab1, off,
-                       sorted, Y, (int32_t)n0, (int32_t)n1, (uint32_t)p->J, (int32_t)lo, (int32_t)cnt);
+  const size_t lds = (size_t)4 * 64 * NJ * V * sizeof(WT);
+  TTProfScope ps(p, TT_PROF_SKETCH0);
+  for (int64_t lo = 0; lo < n0; lo += chunk) {
+    const int64_t cnt = (n0 - lo) < chunk ? (n0 - lo) : chunk;
+    hipLaunchKernelGGL((k_sketch_mode0<XT, WT, V, NJ, U>), dim3((unsigned)p->J), dim3(256), lds, p->stream, X, tab1,
+                       off, sorted, Y, (int32_t)n0, (int32_t)n1, (uint32_t)p->J, (int32_t)lo, (int32_t)cnt, lpf_log2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// Lanes per fibre (power of two <= 64) and vector loads per lane for n0.
+void lane_shape(int64_t n0, int V, int* lpf_log2, int* nj) {
+  const int64_t vecs = (n0 + V - 1) / V;
+  if (vecs <= 64) {
+    *lpf_log2 = ilog2_ceil(vecs);
+    *nj = 1;
+  } else {
+    *lpf_log2 = 6;
+    *nj = 1 << ilog2_ceil((vecs + 63) / 64);
+  }
+}
+
+template <typename XT, typename WT, int V>
+hipError_t dispatch_v(const tt_plan_s* p, const XT* X, int k, WT* Y) {
+  const int64_t n0 = p->n[0];
+  int lpf, nj;
+  if (k == 0) {
+    // the k = 0 gather covers at most 64 * 16 * V positions of i_0 per launch
+    const int64_t chunk = 64 * 16 * V;
+    lane_shape(n0 < chunk ? n0 : chunk, V, &lpf, &nj);
+    switch (nj) {
+      case 1: return run_mode0<XT, WT, V, 1>(p, X, Y, lpf, chunk);
+      case 2: return run_mode0<XT, WT, V, 2>(p, X, Y, lpf, chunk);
+      case 4: return run_mode0<XT, WT, V, 4>(p, X, Y, lpf, chunk);
+      case 8: return run_mode0<XT, WT, V, 8>(p, X, Y, lpf, chunk);
+      default: return run_mode0<XT, WT, V, 16>(p, X, Y, lpf, chunk);
+    }
+  }
+  lane_shape(n0, V, &lpf, &nj);
+  switch (nj) {
+    case 1: return run_modek<XT, WT, V, 1>(p, X, k, Y, lpf);
+    case 2: return run_modek<XT, WT, V, 2>(p, X, k, Y, lpf);
+    case 4: return run_modek<XT, WT, V, 4>(p, X, k, Y, lpf);
+    case 8: return run_modek<XT, WT, V, 8>(p, X, k, Y, lpf);
+    case 16: return run_modek<XT, WT, V, 16>(p, X, k, Y, lpf);
+    case 32: return run_modek<XT, WT, V, 32>(p, X, k, Y, lpf);
+    default: return run_modek<XT, WT, V, 64>(p, X, k, Y, lpf);
+  }
 }
 
 template <typename XT, typename WT>
 hipError_t dispatch(const tt_plan_s* p, const void* Xv, int k, void* Yv) {
   const XT* X = static_cast<const XT*>(Xv);
   WT* Y = static_cast<WT*>(Yv);
-  const int64_t n0 = p->n[0];
-  if (k == 0) {
-    // chunks of at most 1024 positions of i_0 per launch
-    if (n0 <= 64) return run_mode0<XT, WT, 1>(p, X, Y);
-    if (n0 <= 128) return run_mode0<XT, WT, 2>(p, X, Y);
-    if (n0 <= 256) return run_mode0<XT, WT, 4>(p, X, Y);
-    if (n0 <= 512) return run_mode0<XT, WT, 8>(p, X, Y);
-    return run_mode0<XT, WT, 16>(p, X, Y);
-  }
-  if (n0 <= 64) return run_modek<XT, WT, 1>(p, X, k, Y);
-  if (n0 <= 128) return run_modek<XT, WT, 2>(p, X, k, Y);
-  if (n0 <= 256) return run_modek<XT, WT, 4>(p, X, k, Y);
-  if (n0 <= 512) return run_modek<XT, WT, 8>(p, X, k, Y);
-  if (n0 <= 1024) return run_modek<XT, WT, 16>(p, X, k, Y);
-  if (n0 <= 2048) return run_modek<XT, WT, 32>(p, X, k, Y);
-  return run_modek<XT, WT, 64>(p, X, k, Y);
+  constexpr int VV = 16 / (int)sizeof(XT);
+  // 16-byte loads when every fibre starts on a 16-byte boundary
+  const bool vec = (p->n[0] % VV) == 0 && ((uintptr_t)Xv % 16) == 0;
+  return vec ? dispatch_v<XT, WT, VV>(p, X, k, Y) : dispatch_v<XT, WT, 1>(p, X, k, Y);
 }
 
 }  // namespace
 
-// Number of fibre chunks per column for k >= 1 (also sizes the partials).
-int64_t tt_sketch_chunks(const tt_plan_s* p, int k) {
-  int64_t M = 1, Rk = 1;
-  for (int s = 1; s < k; ++s) M *= p->n[s];
-  for (int s = k + 1; s < p->d; ++s) Rk *= p->n[s];
-  const int64_t F = M * Rk;
-  int64_t S = (2048 + p->n[k] - 1) / p->n[k];
-  if (S > F) S = F;
-  return S < 1 ? 1 : S;
+// Workgroups of the k >= 1 sketch: the occupancy-limited resident count,
+// capped so that each workgroup streams at least 8 J entries of X per J-entry
+// partial it writes, by the number of fibres (every range non-empty) and by
+// TT_SKETCH_MAX_WG.
+int64_t tt_sketch_workgroups(const tt_plan_s* p, int k, int64_t resident) {
+  const int64_t Ftot = p->N / p->n[0];
+  int64_t W = resident;
+  const int64_t cap = p->N / (8 * p->J);
+  if (W > cap) W = cap;
+  if (W > Ftot) W = Ftot;
+  if (W > TT_SKETCH_MAX_WG) W = TT_SKETCH_MAX_WG;
+  (void)k;
+  return W < 1 ? 1 : W;
+}
+
+// Upper bound on the workgroups whose ranges meet one column: ranges hold at
+// least m = floor(Ftot / W) >= 1 fibres, a column F consecutive fibres.
+int64_t tt_sketch_slots(const tt_plan_s* p, int k, int64_t W) {
+  const int64_t Ftot = p->N / p->n[0];
+  const int64_t F = Ftot / p->n[k];
+  const int64_t m = Ftot / W;
+  return (F - 1) / m + 2;
 }
 
 hipError_t launch_sketch_tensor(const tt_plan_s* p, const void* X, int k, void* Y) {

@@ -42,6 +42,8 @@ struct tt_plan_s {
   char* ws;
   size_t ws_bytes;
   size_t ws_need;
+  void* prof;                  // ProfState* when measurement is enabled, else null
+
   size_t o_tab, o_KI, o_KO, o_cnt, o_cursor, o_sortO, o_part, o_chat, o_pre, o_suf, o_SH, o_Y,
       o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold;
 
@@ -60,6 +62,17 @@ tt_status tt_fail(tt_status st, const char* fmt, ...);
     if (e_ != hipSuccess)                                                        \
       return tt_fail(TT_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
+
+// Measurement scopes (no-ops unless tt_plan_profile enabled them)
+void tt_prof_begin(const tt_plan_s* p, int cls);
+void tt_prof_end(const tt_plan_s* p, int cls);
+void tt_prof_free(tt_plan_s* p);
+struct TTProfScope {
+  const tt_plan_s* p;
+  int cls;
+  TTProfScope(const tt_plan_s* p_, int c) : p(p_), cls(c) { tt_prof_begin(p, cls); }
+  ~TTProfScope() { tt_prof_end(p, cls); }
+};
 
 // Per-core launch descriptor (passed by value to kernels).
 struct CoreDesc {
@@ -85,7 +98,9 @@ hipError_t launch_absorb_right(const tt_plan_s* p, double* Gprev, int64_t rows, 
 hipError_t launch_residual(const tt_plan_s* p, const void* X, const CoreDesc& cd);
 hipError_t launch_copy_f64(const tt_plan_s* p, double* dst, const double* src, int64_t count);
 
-int64_t tt_sketch_chunks(const tt_plan_s* p, int k);   // fibre chunks per column, k >= 1
+#define TT_SKETCH_MAX_WG 4096
+int64_t tt_sketch_workgroups(const tt_plan_s* p, int k, int64_t resident);   // k >= 1 sketch grid
+int64_t tt_sketch_slots(const tt_plan_s* p, int k, int64_t W);              // partials per column
 int64_t tt_gram_chunks(int64_t J);                      // split-K chunks of the Gram
 
 // Allow a kernel more than 64 KB of dynamic LDS (gfx950 has 160 KB per CU).
