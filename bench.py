@@ -76,7 +76,9 @@ def main():
     ap.add_argument("--seed", type=int, default=2023)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-target", action="store_true")
-    ap.add_argument("--cpu-entries", type=int, default=32_000_000)
+    ap.add_argument("--cpu-entries", type=int, default=128_000_000)
+    ap.add_argument("--serial", action="store_true",
+                    help="keep the data sketches on the plan's stream (no overlap with the solve chain)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -99,7 +101,7 @@ def main():
     X, _ = synth.tt_tensor_device(n, R, cfg["noise"], args.seed, dtype=cfg["xd"], device=dev)
     init = synth.random_cores(n, R, args.seed + 1)
     plan = tts.Plan(n, R, J, lam, seed=args.seed, x_dtype=cfg["xd"], work_dtype=cfg["wd"], gram=cfg["gram"],
-                    device=dev)
+                    device=dev, serial=args.serial)
     cores = [tts.core_to_device(c, dev) for c in init]
     torch.cuda.synchronize()
 
@@ -159,7 +161,8 @@ def main():
         "dtype": cfg["xd"],
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "n": n, "ranks": R, "J": J, "lambda": lam,
-                   "step": "one sweep of Algorithm 1 (%d data-sketch passes over X)" % d},
+                   "step": "one sweep of Algorithm 1 (%d data-sketch passes over X)" % d,
+                   "schedule": "serial" if args.serial else "data sketches overlapped on a second stream"},
         "hbm_gbps_sweep": d * N * xbytes / (ms_per_step * 1e-3) / 1e9,
         "wall_s_timed": wall,
         "roofline": rf,

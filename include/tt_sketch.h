@@ -80,8 +80,15 @@ typedef struct {
   tt_dtype x_dtype;      /* storage type of X */
   tt_dtype work_dtype;   /* TT_F64 or TT_F32: type of Y, SH and the sketch accumulators */
   int32_t gram_mode;     /* tt_gram_mode */
-  uint32_t flags;        /* reserved, must be 0 */
+  uint32_t flags;        /* TT_FLAG_* bits, 0 for the defaults */
 } tt_plan_desc;
+
+/* tt_als_sweep runs the d data sketches of a sweep (which need only X and the
+ * sweep's tables) on a second, plan-owned stream of default priority,
+ * overlapped with the latency-bound interface / solve / QR chain on the
+ * plan's stream, joined by events.  This flag keeps every kernel on the
+ * plan's stream instead. */
+#define TT_FLAG_SERIAL 1u
 
 /* Create a plan (Algorithm 1, REQUIRE line: tensor shape, TT ranks, m, sigma).
  * Validates the descriptor, computes the workspace size the caller must

@@ -50,7 +50,7 @@ class Plan:
     tensor) and runs on a HIP stream (torch's current stream by default)."""
 
     def __init__(self, n, ranks, J, lam, seed=0, x_dtype="f32", work_dtype="f32", gram="work",
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, serial=False):
         self.n = [int(x) for x in n]
         self.ranks = [int(x) for x in ranks]
         self.d = len(self.n)
@@ -65,7 +65,7 @@ class Plan:
         self._n_arr = (ctypes.c_int64 * self.d)(*self.n)
         self._r_arr = (ctypes.c_int64 * (self.d + 1))(*self.ranks)
         desc = _abi.PlanDesc(self.d, self._n_arr, self._r_arr, self.J, self.lam, int(seed) & (2 ** 64 - 1),
-                             _DT[x_dtype], _DT[work_dtype], _GRAM[gram], 0)
+                             _DT[x_dtype], _DT[work_dtype], _GRAM[gram], _abi.TT_FLAG_SERIAL if serial else 0)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream

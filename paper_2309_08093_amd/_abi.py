@@ -10,6 +10,7 @@ STATUS_NAMES = {0: "TT_OK", 1: "TT_ERR_ARG", 2: "TT_ERR_SHAPE", 3: "TT_ERR_WORKS
                 5: "TT_ERR_NOT_SPD", 6: "TT_ERR_NONFINITE", 7: "TT_ERR_STATE"}
 TT_F64, TT_F32, TT_BF16 = 0, 1, 2
 TT_GRAM_WORK, TT_GRAM_BF16 = 0, 1
+TT_FLAG_SERIAL = 1
 
 MAX_ORDER, MAX_J, MAX_RANK, MAX_S, MAX_N0 = 16, 8192, 16, 180, 4096
 

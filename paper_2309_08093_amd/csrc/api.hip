@@ -96,7 +96,7 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   const int d = desc->d;
   if (d < 2 || d > TT_MAX_ORDER) return tt_fail(TT_ERR_SHAPE, "order d=%d outside [2, %d]", d, TT_MAX_ORDER);
   if (!desc->n || !desc->r) return tt_fail(TT_ERR_ARG, "null n or r");
-  if (desc->flags != 0) return tt_fail(TT_ERR_ARG, "flags must be 0");
+  if (desc->flags & ~TT_FLAG_SERIAL) return tt_fail(TT_ERR_ARG, "unknown flags");
   if (desc->x_dtype != TT_F64 && desc->x_dtype != TT_F32 && desc->x_dtype != TT_BF16)
     return tt_fail(TT_ERR_ARG, "bad x_dtype");
   if (desc->work_dtype != TT_F64 && desc->work_dtype != TT_F32) return tt_fail(TT_ERR_ARG, "work_dtype must be F64 or F32");
@@ -139,6 +139,9 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->wdt = desc->work_dtype;
   p->gram_mode = desc->gram_mode;
   p->stream = static_cast<hipStream_t>(hip_stream);
+  p->user_stream = p->stream;
+  p->side = nullptr;
+  p->flags = desc->flags;
   p->sweep = 0;
   p->override_tables = false;
   p->N = N;
@@ -216,6 +219,12 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_status = take(64);
   p->o_res = take(sizeof(double) * (2 * p->res_waves + 8));
   p->o_gold = take(sizeof(double));
+  p->o_Yall = take(ws * p->J * p->tab_off[d]);   // Y_k of every mode for one sweep
+  p->max_F = 1;
+  for (int k = 1; k < d; ++k)
+    if (N / (p->n[0] * p->n[k]) > p->max_F) p->max_F = N / (p->n[0] * p->n[k]);
+  p->o_fkeys = take(sizeof(uint32_t) * p->max_F);
+  p->o_fsort = take(8 * p->max_F);
   p->ws_need = o;
   p->ws = nullptr;
   p->ws_bytes = 0;
@@ -238,11 +247,21 @@ tt_status tt_plan_bind_workspace(tt_plan p, void* dev_ws, size_t bytes) {
 tt_status tt_plan_set_stream(tt_plan p, void* s) {
   if (!p) return tt_fail(TT_ERR_ARG, "null plan");
   p->stream = static_cast<hipStream_t>(s);
+  p->user_stream = p->stream;
   return TT_OK;
 }
 
 tt_status tt_plan_destroy(tt_plan p) {
-  if (p) tt_prof_free(p);
+  if (p) {
+    tt_prof_free(p);
+    if (p->side) {
+      hipStreamSynchronize(p->side);
+      hipStreamDestroy(p->side);
+      hipEventDestroy(p->ev_fork);
+      hipEventDestroy(p->ev_join);
+      for (int k = 0; k < TT_MAX_ORDER; ++k) hipEventDestroy(p->ev_y[k]);
+    }
+  }
   delete p;
   return TT_OK;
 }
@@ -399,6 +418,31 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
   const CoreDesc cd = make_desc(p, cores);
   void* SH = p->ws + p->o_SH;
   void* Y = p->ws + p->o_Y;
+  // data sketches: only X and this sweep's tables, so they can run ahead on
+  // the side stream while the chain below proceeds
+  const bool overlap = !(p->flags & TT_FLAG_SERIAL);
+  char* Yall = p->ws + p->o_Yall;
+  if (overlap) {
+    if (!p->side) {
+      TT_HIP_TRY(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+      TT_HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+      TT_HIP_TRY(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+      for (int k = 0; k < TT_MAX_ORDER; ++k) TT_HIP_TRY(hipEventCreateWithFlags(&p->ev_y[k], hipEventDisableTiming));
+    }
+    TT_HIP_TRY(hipEventRecord(p->ev_fork, p->user_stream));
+    TT_HIP_TRY(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+    p->stream = p->side;
+    for (int k = 0; k < d; ++k) {
+      const hipError_t e = launch_sketch_tensor(p, X, k, Yall + p->wsize() * p->J * p->tab_off[k]);
+      if (e == hipSuccess) TT_HIP_TRY(hipEventRecord(p->ev_y[k], p->side));
+      if (e != hipSuccess) {
+        p->stream = p->user_stream;
+        return tt_fail(TT_ERR_HIP, "data sketch launch failed: %s", hipGetErrorString(e));
+      }
+    }
+    TT_HIP_TRY(hipEventRecord(p->ev_join, p->side));
+    p->stream = p->user_stream;
+  }
   // transformed CountSketches of all cores (core 0 is not needed for k = 0)
   {
     TTProfScope ps(p, TT_PROF_INTERFACE);
@@ -409,7 +453,12 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
       TTProfScope ps(p, TT_PROF_INTERFACE);
       TT_HIP_TRY(launch_interface_from_chat(p, cd, k, SH));
     }
-    TT_HIP_TRY(launch_sketch_tensor(p, X, k, Y));
+    if (overlap) {
+      Y = Yall + p->wsize() * p->J * p->tab_off[k];
+      TT_HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_y[k], 0));
+    } else {
+      TT_HIP_TRY(launch_sketch_tensor(p, X, k, Y));
+    }
     {
       TTProfScope ps(p, TT_PROF_GRAM);
       TT_HIP_TRY(launch_gram(p, k, SH, Y));
@@ -425,6 +474,7 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
       TT_HIP_TRY(launch_core_fft(p, cd, k, k, -1));
     }
   }
+  if (overlap) TT_HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_join, 0));
   p->sweep += 1;
   if (!p->override_tables)
     if ((st = gen_tables(p))) return st;

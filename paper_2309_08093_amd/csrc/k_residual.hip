@@ -27,10 +27,10 @@ struct Vec {
 template <typename XT, int V>
 __device__ __forceinline__ Vec<XT, V> load_vec(const XT* p) {
   if constexpr (V == 1) {
-    return Vec<XT, 1>{{*p}};
+    return Vec<XT, 1>{{__builtin_nontemporal_load(p)}};
   } else {
     typedef XT raw_t __attribute__((ext_vector_type(V)));
-    const raw_t r = *reinterpret_cast<const raw_t*>(p);
+    const raw_t r = __builtin_nontemporal_load(reinterpret_cast<const raw_t*>(p));
     Vec<XT, V> out;
 #pragma unroll
     for (int e = 0; e < V; ++e) out.e[e] = r[e];

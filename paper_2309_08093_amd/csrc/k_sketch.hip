@@ -19,12 +19,31 @@
 //    the rate of the FP32 one, and it makes the per-bucket sums exact to
 //    FP32 rounding of the inputs.  Fibre keys are fetched 64 at a time (one
 //    vector load per lane) and handed to the lane groups by shuffles.
+//  * k >= 1 when a column holds at least two fibres per key (the usual case
+//    for large tensors): the fibres of one column, listed once per sweep and
+//    mode in order of their key c over the modes other than 0 and k (a
+//    counting sort that does not depend on the column), are summed in
+//    registers while the key stays the same, and only the sums are scattered
+//    into the LDS buckets (h_0(i_0) + c) mod J.  This divides the LDS atomics
+//    by the number of fibres per key (about N / (n_0 n_k J)).  A workgroup owns
+//    one column and an equal share of the sorted list; a key split between
+//    shares is completed when the partials are summed.
 //  * k = 0: a fibre has one bucket (its entries differ only in i_0, the
 //    unsketched mode), so one workgroup owns one bucket b and gathers the
 //    fibres hashed to b: for each i_1 it visits the outer tuples (modes
 //    2..d-1) whose partial hash is (b - h_1(i_1)) mod J, found in a
 //    bucket-sorted list.  Accumulation is in registers; no atomics.
 #include "tt_internal.h"
+
+// threads per workgroup of the k >= 1 sketch kernels
+#ifndef TT_SKETCH_THREADS
+#define TT_SKETCH_THREADS 256
+#endif
+// a k >= 1 sketch takes the key-grouped path when a column holds at least
+// this many fibres per key
+#ifndef TT_SKETCH_GS_MIN
+#define TT_SKETCH_GS_MIN 2
+#endif
 
 namespace {
 
@@ -44,18 +63,34 @@ __device__ __forceinline__ WT to_work(uint16_t v) { return (WT)__uint_as_float((
 template <typename WT>
 __device__ __forceinline__ WT apply_sign(WT x, uint32_t key) { return (key & TT_KEY_SIGN) ? -x : x; }
 
+// (+-x) as FP64 with the sign applied as a bit flip: s is 0 or 0x80000000.
+__device__ __forceinline__ double signed_f64(float x, uint32_t s) { return (double)__uint_as_float(__float_as_uint(x) ^ s); }
+__device__ __forceinline__ double signed_f64(uint16_t x, uint32_t s) { return (double)__uint_as_float(((uint32_t)x << 16) ^ s); }
+__device__ __forceinline__ double signed_f64(double x, uint32_t s) {
+  return __longlong_as_double(__double_as_longlong(x) ^ ((long long)s << 32));
+}
+
+// Bucket offsets are kept pre-scaled to LDS byte offsets (8 b): the sum of two
+// offsets below 8 J wraps with one subtraction and an unsigned min.
+__device__ __forceinline__ uint32_t wrap8(uint32_t b8, uint32_t J8) {
+  const uint32_t t = b8 - J8;
+  return t < b8 ? t : b8;
+}
+
 // V consecutive elements of X as one load (16 bytes when V * sizeof(XT) == 16)
 template <typename XT, int V>
 struct Vec {
   XT e[V];
 };
+// X is streamed once per pass: nontemporal loads keep it from displacing the
+// small tables and partials in the caches.
 template <typename XT, int V>
 __device__ __forceinline__ Vec<XT, V> load_vec(const XT* p) {
   if constexpr (V == 1) {
-    return Vec<XT, 1>{{*p}};
+    return Vec<XT, 1>{{__builtin_nontemporal_load(p)}};
   } else {
     typedef XT raw_t __attribute__((ext_vector_type(V)));
-    const raw_t r = *reinterpret_cast<const raw_t*>(p);
+    const raw_t r = __builtin_nontemporal_load(reinterpret_cast<const raw_t*>(p));
     Vec<XT, V> out;
 #pragma unroll
     for (int e = 0; e < V; ++e) out.e[e] = r[e];
@@ -74,7 +109,7 @@ __device__ __forceinline__ int64_t owner(int64_t g, int64_t W, int64_t Ftot) { r
 
 // ---------------------------------------------------------------- k >= 1
 template <typename XT, typename WT, int V, int NJ, int U>
-__global__ __launch_bounds__(256) void k_sketch_modek(
+__global__ __launch_bounds__(TT_SKETCH_THREADS) void k_sketch_modek(
     const XT* __restrict__ X, const uint32_t* __restrict__ tab0, const uint32_t* __restrict__ KI,
     const uint32_t* __restrict__ KO, double* __restrict__ part, int32_t n0, int32_t nk, int64_t M, int64_t F,
     uint32_t J, int32_t lpf_log2, int32_t maxslots) {
@@ -87,14 +122,20 @@ __global__ __launch_bounds__(256) void k_sketch_modek(
   const int G = 64 >> lpf_log2;          // fibres per load instruction
   const int g = lane >> lpf_log2;
   const int v = lane & (LPF - 1);
-  uint32_t t0[NJ][V];
+  // mode-0 part of the key for this lane's positions: LDS byte offset 8 h_0
+  // and sign mask
+  uint32_t tb[NJ][V], ts[NJ][V];
 #pragma unroll
   for (int j = 0; j < NJ; ++j)
 #pragma unroll
     for (int e = 0; e < V; ++e) {
       const int i0 = (v + LPF * j) * V + e;
-      t0[j][e] = i0 < n0 ? tab0[i0] : 0u;
+      const uint32_t t = i0 < n0 ? tab0[i0] : 0u;
+      tb[j][e] = (t & TT_KEY_MASK) << 3;
+      ts[j][e] = t & TT_KEY_SIGN;
     }
+  const uint32_t J8 = J << 3;
+  char* accb = reinterpret_cast<char*>(acc);
   const int64_t W = gridDim.x;
   const int64_t w = blockIdx.x;
   const int64_t Ftot = (int64_t)nk * F;
@@ -115,16 +156,18 @@ __global__ __launch_bounds__(256) void k_sketch_modek(
         keyl = key_add(KI[mu], KO[rho], J);
         offl = ((rho * nk + c) * M + mu) * (int64_t)n0;
       }
+      const uint32_t kbl = (keyl & TT_KEY_MASK) << 3, ksl = keyl & TT_KEY_SIGN;
       const int nb = (we - qb) < 64 ? (int)(we - qb) : 64;
       for (int t = 0; t < nb; t += G * U) {
         Vec<XT, V> x[U][NJ];
-        uint32_t kf[U];
+        uint32_t kb[U], ks[U];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int idx = t + u * G + g;
           ok[u] = idx < nb;
-          kf[u] = __shfl(keyl, idx & 63, 64);
+          kb[u] = __shfl(kbl, idx & 63, 64);
+          ks[u] = __shfl(ksl, idx & 63, 64);
           const int64_t off = shfl64(offl, idx & 63);
 #pragma unroll
           for (int j = 0; j < NJ; ++j) {
@@ -140,8 +183,8 @@ __global__ __launch_bounds__(256) void k_sketch_modek(
             if (ok[u] && p < n0) {
 #pragma unroll
               for (int e = 0; e < V; ++e) {
-                const uint32_t key = key_add(t0[j][e], kf[u], J);
-                atomicAdd(&acc[key & TT_KEY_MASK], apply_sign<double>(to_work<double>(x[u][j].e[e]), key));
+                const uint32_t b8 = wrap8(tb[j][e] + kb[u], J8);
+                atomicAdd(reinterpret_cast<double*>(accb + b8), signed_f64(x[u][j].e[e], ts[j][e] ^ ks[u]));
               }
             }
           }
@@ -168,6 +211,109 @@ __global__ void k_reduce_parts(const double* __restrict__ part, WT* __restrict__
   double s = 0.0;
   for (int64_t q = 0; q < cnt; ++q) s += p[q * J];
   Y[idx] = (WT)s;
+}
+
+// ---------------------------------------------------------------- k >= 1, key-grouped
+template <typename XT, typename WT, int V, int NJ, int U>
+__global__ __launch_bounds__(TT_SKETCH_THREADS) void k_sketch_gs(
+    const XT* __restrict__ X, const uint32_t* __restrict__ tab0, const uint2* __restrict__ list,
+    double* __restrict__ part, int32_t n0, int32_t nk, int64_t M, int64_t F, uint32_t J, int32_t lpf_log2,
+    int32_t maxslots) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* acc = reinterpret_cast<double*>(smem_raw);
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int NW = blockDim.x >> 6;
+  const int LPF = 1 << lpf_log2;
+  const int G = 64 >> lpf_log2;
+  const int g = lane >> lpf_log2;
+  const int v = lane & (LPF - 1);
+  uint32_t tb[NJ][V], ts[NJ][V];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j)
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const int i0 = (v + LPF * j) * V + e;
+      const uint32_t t = i0 < n0 ? tab0[i0] : 0u;
+      tb[j][e] = (t & TT_KEY_MASK) << 3;
+      ts[j][e] = t & TT_KEY_SIGN;
+    }
+  const uint32_t J8 = J << 3;
+  char* accb = reinterpret_cast<char*>(acc);
+  // this workgroup's share of the (column, list entry) sequence
+  const int64_t W = gridDim.x;
+  const int64_t w = blockIdx.x;
+  const int64_t Ftot = (int64_t)nk * F;
+  const int64_t gs = w * Ftot / W, ge = (w + 1) * Ftot / W;
+  for (int64_t c = gs / F; gs < ge && c * F < ge; ++c) {
+    const int64_t qa = (gs > c * F ? gs : c * F) - c * F;
+    const int64_t qe = (ge < (c + 1) * F ? ge : (c + 1) * F) - c * F;
+    for (uint32_t b = threadIdx.x; b < J; b += blockDim.x) acc[b] = 0.0;
+    __syncthreads();
+    const int64_t wa = qa + (qe - qa) * wv / NW, we = qa + (qe - qa) * (wv + 1) / NW;
+    const XT* Xc = X + c * M * (int64_t)n0;
+    double sacc[NJ][V];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int e = 0; e < V; ++e) sacc[j][e] = 0.0;
+    uint32_t cur = 0xffffffffu;   // key of the running sums (none yet)
+    auto flush = [&]() {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int p = (v + LPF * j) * V;
+        if (p < n0)
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            const uint32_t b8 = wrap8(tb[j][e] + (cur << 3), J8);
+            atomicAdd(reinterpret_cast<double*>(accb + b8), signed_f64(sacc[j][e], ts[j][e]));
+            sacc[j][e] = 0.0;
+          }
+      }
+    };
+    for (int64_t eb = wa; eb < we; eb += G * U) {
+      uint2 it[U];
+      bool ok[U];
+      Vec<XT, V> x[U][NJ];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t e = eb + u * G + g;
+        ok[u] = e < we;
+        it[u] = ok[u] ? list[e] : make_uint2(0u, 0u);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const XT* base = Xc + (int64_t)(it[u].x & TT_KEY_MASK) * n0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const int p = (v + LPF * j) * V;
+          if (ok[u] && p < n0) x[u][j] = load_vec<XT, V>(base + p);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (ok[u]) {
+          if (it[u].y != cur) {
+            if (cur != 0xffffffffu) flush();
+            cur = it[u].y;
+          }
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            const int p = (v + LPF * j) * V;
+            if (p < n0)
+#pragma unroll
+              for (int e = 0; e < V; ++e) sacc[j][e] += signed_f64(x[u][j].e[e], it[u].x & TT_KEY_SIGN);
+          }
+        }
+      }
+    }
+    if (cur != 0xffffffffu) flush();
+    __syncthreads();
+    const int64_t slot = w - owner(c * F, W, Ftot);
+    double* out = part + ((int64_t)c * maxslots + slot) * (int64_t)J;
+    for (uint32_t b = threadIdx.x; b < J; b += blockDim.x) out[b] = acc[b];
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------- k = 0
@@ -286,7 +432,7 @@ hipError_t run_modek(const tt_plan_s* p, const XT* X, int k, WT* Y, int lpf_log2
   const size_t lds = (size_t)p->J * sizeof(double);
   auto kern = k_sketch_modek<XT, WT, V, NJ, U>;
   int per_cu = 0;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds)) != hipSuccess) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TT_SKETCH_THREADS, lds)) != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   const int64_t W = tt_sketch_workgroups(p, k, (int64_t)per_cu * num_cus());
   const int64_t maxslots = tt_sketch_slots(p, k, W);
@@ -295,8 +441,44 @@ hipError_t run_modek(const tt_plan_s* p, const XT* X, int k, WT* Y, int lpf_log2
   const uint32_t* tab0 = p->at<uint32_t>(p->o_tab) + p->tab_off[0];
   {
     TTProfScope ps(p, TT_PROF_SKETCHK);
-    hipLaunchKernelGGL(kern, dim3((unsigned)W), dim3(256), lds, p->stream, X, tab0, KI, KO, part, (int32_t)n0,
+    hipLaunchKernelGGL(kern, dim3((unsigned)W), dim3(TT_SKETCH_THREADS), lds, p->stream, X, tab0, KI, KO, part, (int32_t)n0,
                        (int32_t)nk, M, F, (uint32_t)p->J, lpf_log2, (int32_t)maxslots);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  TTProfScope ps(p, TT_PROF_SKETCH_AUX);
+  hipLaunchKernelGGL((k_reduce_parts<WT>), dim3(nblk(p->J * nk, 256)), dim3(256), 0, p->stream, part, Y, p->J, nk, F,
+                     W, (int32_t)maxslots);
+  return hipGetLastError();
+}
+
+template <typename XT, typename WT, int V, int NJ>
+hipError_t run_gs(const tt_plan_s* p, const XT* X, int k, WT* Y, int lpf_log2) {
+  constexpr int U = NJ >= 8 ? 1 : 8 / NJ;
+  const int64_t n0 = p->n[0], nk = p->n[k];
+  int64_t M = 1, Rk = 1;
+  for (int s = 1; s < k; ++s) M *= p->n[s];
+  for (int s = k + 1; s < p->d; ++s) Rk *= p->n[s];
+  const int64_t F = M * Rk;
+  hipError_t e;
+  {
+    TTProfScope ps(p, TT_PROF_SKETCH_AUX);
+    if ((e = launch_fibre_sort(p, k)) != hipSuccess) return e;
+  }
+  const size_t lds = (size_t)p->J * sizeof(double);
+  auto kern = k_sketch_gs<XT, WT, V, NJ, U>;
+  int per_cu = 0;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TT_SKETCH_THREADS, lds)) != hipSuccess) return e;
+  if (per_cu < 1) per_cu = 1;
+  const int64_t W = tt_sketch_workgroups(p, k, (int64_t)per_cu * num_cus());
+  const int64_t maxslots = tt_sketch_slots(p, k, W);
+  if (nk * maxslots * p->J > p->part_entries) return hipErrorInvalidValue;   // sized at plan time
+  double* part = p->at<double>(p->o_part);
+  const uint32_t* tab0 = p->at<uint32_t>(p->o_tab) + p->tab_off[0];
+  {
+    TTProfScope ps(p, TT_PROF_SKETCHK);
+    hipLaunchKernelGGL(kern, dim3((unsigned)W), dim3(TT_SKETCH_THREADS), lds, p->stream, X, tab0,
+                       p->at<uint2>(p->o_fsort), part, (int32_t)n0, (int32_t)nk, M, F, (uint32_t)p->J, lpf_log2,
+                       (int32_t)maxslots);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   TTProfScope ps(p, TT_PROF_SKETCH_AUX);
@@ -357,6 +539,17 @@ hipError_t dispatch_v(const tt_plan_s* p, const XT* X, int k, WT* Y) {
     }
   }
   lane_shape(n0, V, &lpf, &nj);
+  if (tt_sketch_use_gs(p, k)) {
+    switch (nj) {
+      case 1: return run_gs<XT, WT, V, 1>(p, X, k, Y, lpf);
+      case 2: return run_gs<XT, WT, V, 2>(p, X, k, Y, lpf);
+      case 4: return run_gs<XT, WT, V, 4>(p, X, k, Y, lpf);
+      case 8: return run_gs<XT, WT, V, 8>(p, X, k, Y, lpf);
+      case 16: return run_gs<XT, WT, V, 16>(p, X, k, Y, lpf);
+      case 32: return run_gs<XT, WT, V, 32>(p, X, k, Y, lpf);
+      default: return run_gs<XT, WT, V, 64>(p, X, k, Y, lpf);
+    }
+  }
   switch (nj) {
     case 1: return run_modek<XT, WT, V, 1>(p, X, k, Y, lpf);
     case 2: return run_modek<XT, WT, V, 2>(p, X, k, Y, lpf);
@@ -402,6 +595,14 @@ int64_t tt_sketch_slots(const tt_plan_s* p, int k, int64_t W) {
   const int64_t F = Ftot / p->n[k];
   const int64_t m = Ftot / W;
   return (F - 1) / m + 2;
+}
+
+// Key-grouped path for k >= 1 when a column has at least two fibres per key
+// on average and fibre offsets fit the 31-bit list entries.
+bool tt_sketch_use_gs(const tt_plan_s* p, int k) {
+  if (k < 1) return false;
+  const int64_t F = p->N / (p->n[0] * p->n[k]);
+  return F >= (int64_t)TT_SKETCH_GS_MIN * p->J && p->N / p->n[0] < ((int64_t)1 << 31);
 }
 
 hipError_t launch_sketch_tensor(const tt_plan_s* p, const void* X, int k, void* Y) {

@@ -44,7 +44,8 @@ struct KeyArgs {
   const uint32_t* tab;
   int32_t tab_off[TT_MAX_ORDER];
   int32_t n[TT_MAX_ORDER];
-  int32_t first, last;   // modes first..last (inclusive), first varies fastest
+  int32_t modes[TT_MAX_ORDER];   // modes of the tuple, first varies fastest
+  int32_t nm;
   uint32_t J;
 };
 
@@ -54,13 +55,14 @@ __device__ __forceinline__ uint32_t key_add(uint32_t a, uint32_t b, uint32_t J) 
   return s | ((a ^ b) & TT_KEY_SIGN);
 }
 
-// out[q] = combined key of the mode tuple q over modes first..last.
+// out[q] = combined key (sum of hashes mod J, product of signs) of tuple q.
 __global__ void k_build_keys(uint32_t* out, int64_t count, KeyArgs a) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= count) return;
   int64_t rem = q;
   uint32_t key = 0;
-  for (int s = a.first; s <= a.last; ++s) {
+  for (int t = 0; t < a.nm; ++t) {
+    const int s = a.modes[t];
     const int64_t i = rem % a.n[s];
     rem /= a.n[s];
     key = key_add(key, a.tab[a.tab_off[s] + i], a.J);
@@ -129,19 +131,41 @@ hipError_t launch_gen_tables(const tt_plan_s* p, int64_t sweep) {
   return hipGetLastError();
 }
 
-hipError_t launch_build_keys(const tt_plan_s* p, uint32_t* out, int64_t count, int first, int last) {
+hipError_t launch_build_keys_modes(const tt_plan_s* p, uint32_t* out, int64_t count, const int* modes, int nm) {
   KeyArgs a{};
   a.tab = p->at<uint32_t>(p->o_tab);
   for (int s = 0; s < p->d; ++s) {
     a.tab_off[s] = (int32_t)p->tab_off[s];
     a.n[s] = (int32_t)p->n[s];
   }
-  a.first = first;
-  a.last = last;
+  for (int t = 0; t < nm; ++t) a.modes[t] = modes[t];
+  a.nm = nm;
   a.J = (uint32_t)p->J;
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_build_keys, dim3(nblk(count, 256)), dim3(256), 0, p->stream, out, count, a);
   return hipGetLastError();
+}
+
+hipError_t launch_build_keys(const tt_plan_s* p, uint32_t* out, int64_t count, int first, int last) {
+  int modes[TT_MAX_ORDER];
+  int nm = 0;
+  for (int s = first; s <= last; ++s) modes[nm++] = s;
+  return launch_build_keys_modes(p, out, count, modes, nm);
+}
+
+// Fibre list of the k >= 1 sketch: fibre t = mu + M rho of a column (modes
+// 1..k-1 give mu, modes k+1..d-1 give rho) goes to its key's bucket as
+// {column-independent fibre offset rho n_k M + mu, with the key's sign bit;
+//  the key's bucket}.
+__global__ void k_scatter_fibres(const uint32_t* __restrict__ keys, int64_t F, int64_t M, int64_t nkM,
+                                 uint32_t* __restrict__ cursor, uint2* __restrict__ sorted) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= F) return;
+  const uint32_t key = keys[t];
+  const uint32_t c = key & TT_KEY_MASK;
+  const uint32_t pos = atomicAdd(&cursor[c], 1u);
+  const int64_t rho = t / M, mu = t - rho * M;
+  sorted[pos] = make_uint2((uint32_t)(rho * nkM + mu) | (key & TT_KEY_SIGN), c);
 }
 
 // Bucket lists of the k = 0 data sketch: the outer mode tuples (modes
@@ -166,5 +190,33 @@ hipError_t launch_outer_sort(const tt_plan_s* p) {
   hipLaunchKernelGGL(k_count, dim3(nblk(O, 256)), dim3(256), 0, p->stream, keys, O, cursor);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, cursor, cnt, cursor, (int32_t)p->J);
   hipLaunchKernelGGL(k_scatter, dim3(nblk(O, 256)), dim3(256), 0, p->stream, keys, O, cursor, sorted);
+  return hipGetLastError();
+}
+
+// Sort the fibres of a mode-k column (k >= 1) by their key over modes != 0, k.
+// Offsets of the J buckets go to o_cnt (J+1 entries), the list to o_fsort.
+hipError_t launch_fibre_sort(const tt_plan_s* p, int k) {
+  int64_t M = 1, Rk = 1;
+  for (int s = 1; s < k; ++s) M *= p->n[s];
+  for (int s = k + 1; s < p->d; ++s) Rk *= p->n[s];
+  const int64_t F = M * Rk;
+  int modes[TT_MAX_ORDER];
+  int nm = 0;
+  for (int s = 1; s < p->d; ++s)
+    if (s != k) modes[nm++] = s;
+  uint32_t* keys = p->at<uint32_t>(p->o_fkeys);
+  uint32_t* off = p->at<uint32_t>(p->o_cnt);
+  uint32_t* cursor = p->at<uint32_t>(p->o_cursor);
+  hipError_t e;
+  if (nm > 0) {
+    if ((e = launch_build_keys_modes(p, keys, F, modes, nm)) != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, p->stream, keys, (int64_t)1, 0u);
+  }
+  hipLaunchKernelGGL(k_fill_u32, dim3(nblk(p->J, 256)), dim3(256), 0, p->stream, cursor, p->J, 0u);
+  hipLaunchKernelGGL(k_count, dim3(nblk(F, 256)), dim3(256), 0, p->stream, keys, F, cursor);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, cursor, off, cursor, (int32_t)p->J);
+  hipLaunchKernelGGL(k_scatter_fibres, dim3(nblk(F, 256)), dim3(256), 0, p->stream, keys, F, M, p->n[k] * M, cursor,
+                     p->at<uint2>(p->o_fsort));
   return hipGetLastError();
 }

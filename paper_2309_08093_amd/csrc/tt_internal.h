@@ -20,7 +20,11 @@ struct tt_plan_s {
   uint64_t seed;
   tt_dtype xdt, wdt;
   int gram_mode;
-  hipStream_t stream;
+  hipStream_t stream;          // stream the launchers enqueue on (the user's, or the side stream)
+  hipStream_t user_stream;     // the plan's stream (tt_sketch_plan / tt_plan_set_stream)
+  hipStream_t side;            // plan-owned stream for the overlapped data sketches (lazy)
+  hipEvent_t ev_fork, ev_join, ev_y[TT_MAX_ORDER];
+  uint32_t flags;
   int64_t sweep;
   bool override_tables;
 
@@ -45,7 +49,8 @@ struct tt_plan_s {
   void* prof;                  // ProfState* when measurement is enabled, else null
 
   size_t o_tab, o_KI, o_KO, o_cnt, o_cursor, o_sortO, o_part, o_chat, o_pre, o_suf, o_SH, o_Y,
-      o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold;
+      o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_fkeys, o_fsort;
+  int64_t max_F;               // largest fibre count of one column over k >= 1
 
   template <typename T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -86,7 +91,9 @@ struct CoreDesc {
 // Launchers (each enqueues on p->stream; returns hipSuccess or the launch error)
 hipError_t launch_gen_tables(const tt_plan_s* p, int64_t sweep);
 hipError_t launch_build_keys(const tt_plan_s* p, uint32_t* out, int64_t count, int first, int last);
+hipError_t launch_build_keys_modes(const tt_plan_s* p, uint32_t* out, int64_t count, const int* modes, int nm);
 hipError_t launch_outer_sort(const tt_plan_s* p);     // k = 0 bucket lists (modes 2..d-1)
+hipError_t launch_fibre_sort(const tt_plan_s* p, int k);   // k >= 1 fibre lists by key
 hipError_t launch_sketch_tensor(const tt_plan_s* p, const void* X, int k, void* Y);
 hipError_t launch_core_fft(const tt_plan_s* p, const CoreDesc& cd, int core_lo, int core_hi, int skip);
 hipError_t launch_interface_from_chat(const tt_plan_s* p, const CoreDesc& cd, int k, void* SH);
@@ -101,6 +108,7 @@ hipError_t launch_copy_f64(const tt_plan_s* p, double* dst, const double* src, i
 #define TT_SKETCH_MAX_WG 4096
 int64_t tt_sketch_workgroups(const tt_plan_s* p, int k, int64_t resident);   // k >= 1 sketch grid
 int64_t tt_sketch_slots(const tt_plan_s* p, int k, int64_t W);              // partials per column
+bool tt_sketch_use_gs(const tt_plan_s* p, int k);                           // key-grouped k >= 1 path
 int64_t tt_gram_chunks(int64_t J);                      // split-K chunks of the Gram
 
 // Allow a kernel more than 64 KB of dynamic LDS (gfx950 has 160 KB per CU).

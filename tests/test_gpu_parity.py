@@ -100,6 +100,12 @@ SKETCH_CASES = [
     ([1030, 3, 2], 50, "f32", "f32"),          # n_0 > 1024: chunked k = 0 path
     ([1, 5, 4], 8, "f32", "f32"),
     ([5, 1, 4], 8, "f64", "f64"),
+    # at least two fibres per key for every k >= 1: key-grouped path
+    ([20, 30, 40, 10], 60, "f32", "f32"),
+    ([64, 16, 16, 16], 64, "bf16", "f32"),
+    ([16, 16, 16, 16], 32, "f64", "f64"),
+    ([37, 12, 11, 13], 40, "f32", "f32"),      # n_0 not a multiple of 4: scalar loads
+    ([8, 40, 50], 24, "f64", "f64"),           # lane groups of 4 fibres
 ]
 
 
@@ -319,6 +325,15 @@ def test_sweeps_fp32(tts):
     assert abs(res[-1] - res_o[-1]) < 1e-4
 
 
+def test_sweeps_fp32_key_grouped(tts):
+    # 60 x 50 x 40 x 30 with J = 120: every k >= 1 sketch uses the key-grouped path
+    say("sweeps fp32 key-grouped")
+    plan, dc, ref, res, res_o, Xo = _run_sweeps(tts, [60, 50, 40, 30], [1, 4, 5, 3, 1], 120, 1e-3, 6, 3, "f32", "f32",
+                                                1e-2)
+    print("gpu", res, "\noracle", res_o)
+    assert abs(res[-1] - res_o[-1]) < 1e-4
+
+
 def test_injective_sweep_is_exact_prox_als(tts):
     # h_s(i) = i prod_{t<s} n_t, v = +1, J = N: S^T S = I for every k.
     say("injective sweep")
@@ -339,3 +354,25 @@ def test_injective_sweep_is_exact_prox_als(tts):
     ref = als.sweep(Xh, n, init, J, lam, tabs=(hs, vs))
     for a, b in zip(dc, ref):
         assert rel(tts.core_to_host(a, b.shape), b) < 1e-10
+
+
+def test_overlapped_sweep_matches_serial(tts):
+    # the data sketches on the side stream give the same sweep as the serial schedule
+    say("overlap vs serial")
+    n, R, J = [40, 30, 20, 12], [1, 5, 6, 4, 1], 600
+    Xh, _ = synth.tt_tensor_host(n, R, 1e-2, 3)
+    init = synth.random_cores(n, R, 4)
+    X = to_dev_x(Xh, "f32")
+    out = []
+    for serial in (False, True):
+        plan = tts.Plan(n, R, J, 1e-3, seed=9, x_dtype="f32", work_dtype="f32", serial=serial)
+        dc = [tts.core_to_device(c) for c in init]
+        for _ in range(3):
+            plan.als_sweep(X, dc)
+        res = plan.residual(X, dc)
+        out.append(([tts.core_to_host(c, c0.shape) for c, c0 in zip(dc, init)], res))
+    (a, ra), (b, rb) = out
+    # equal up to FP32 rounding: LDS atomics sum in a run-dependent order and
+    # three sweeps amplify last-bit differences of Y
+    assert abs(ra - rb) < 1e-5 * ra
+    assert rel(als.tt_full(a), als.tt_full(b)) < 1e-4
