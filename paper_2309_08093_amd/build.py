@@ -31,11 +31,22 @@ def _compile(src):
     return obj, r.stderr
 
 
-def build(verbose=False, jobs=8):
+def _fresh(src, headers_mtime):
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    return os.path.exists(obj) and os.path.getmtime(obj) > max(os.path.getmtime(src), headers_mtime)
+
+
+def build(verbose=False, jobs=8, incremental=False):
+    """Compile every source (or, with incremental=True, only those newer than
+    their object or than any header) and link the library."""
     os.makedirs(OBJ, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    hdr = max(os.path.getmtime(h) for h in glob.glob(os.path.join(CSRC, "*.h")) +
+              [os.path.join(os.path.dirname(HERE), "include", "tt_sketch.h")])
+    todo = [s for s in srcs if not (incremental and _fresh(s, hdr))]
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        results = list(ex.map(_compile, srcs))
+        done = dict(zip(todo, ex.map(_compile, todo)))
+    results = [done.get(s, (os.path.join(OBJ, os.path.basename(s) + ".o"), "")) for s in srcs]
     if verbose:
         for obj, err in results:
             if err.strip():
@@ -50,4 +61,4 @@ def build(verbose=False, jobs=8):
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

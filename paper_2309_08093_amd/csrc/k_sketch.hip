@@ -271,38 +271,44 @@ __global__ __launch_bounds__(TT_SKETCH_THREADS) void k_sketch_gs(
           }
       }
     };
-    for (int64_t eb = wa; eb < we; eb += G * U) {
-      uint2 it[U];
-      bool ok[U];
-      Vec<XT, V> x[U][NJ];
+    // list entries are fetched 64 at a time, one per lane, one batch ahead,
+    // so that the loads of X never wait on a list load issued just before
+    uint2 nxt = (wa + lane < we) ? list[wa + lane] : make_uint2(0u, 0u);
+    for (int64_t eb = wa; eb < we; eb += 64) {
+      const uint2 itl = nxt;
+      if (eb + 64 + lane < we) nxt = list[eb + 64 + lane];
+      const int nb = (we - eb) < 64 ? (int)(we - eb) : 64;
+      for (int t = 0; t < nb; t += G * U) {
+        uint32_t ix[U], iy[U];
+        bool ok[U];
+        Vec<XT, V> x[U][NJ];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t e = eb + u * G + g;
-        ok[u] = e < we;
-        it[u] = ok[u] ? list[e] : make_uint2(0u, 0u);
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const XT* base = Xc + (int64_t)(it[u].x & TT_KEY_MASK) * n0;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          const int p = (v + LPF * j) * V;
-          if (ok[u] && p < n0) x[u][j] = load_vec<XT, V>(base + p);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (ok[u]) {
-          if (it[u].y != cur) {
-            if (cur != 0xffffffffu) flush();
-            cur = it[u].y;
-          }
+        for (int u = 0; u < U; ++u) {
+          const int idx = t + u * G + g;
+          ok[u] = idx < nb;
+          ix[u] = (uint32_t)__shfl((int)itl.x, idx & 63, 64);
+          iy[u] = (uint32_t)__shfl((int)itl.y, idx & 63, 64);
+          const XT* base = Xc + (int64_t)(ix[u] & TT_KEY_MASK) * n0;
 #pragma unroll
           for (int j = 0; j < NJ; ++j) {
             const int p = (v + LPF * j) * V;
-            if (p < n0)
+            if (ok[u] && p < n0) x[u][j] = load_vec<XT, V>(base + p);
+          }
+        }
 #pragma unroll
-              for (int e = 0; e < V; ++e) sacc[j][e] += signed_f64(x[u][j].e[e], it[u].x & TT_KEY_SIGN);
+        for (int u = 0; u < U; ++u) {
+          if (ok[u]) {
+            if (iy[u] != cur) {
+              if (cur != 0xffffffffu) flush();
+              cur = iy[u];
+            }
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+              const int p = (v + LPF * j) * V;
+              if (p < n0)
+#pragma unroll
+                for (int e = 0; e < V; ++e) sacc[j][e] += signed_f64(x[u][j].e[e], ix[u] & TT_KEY_SIGN);
+            }
           }
         }
       }
@@ -338,37 +344,68 @@ __global__ __launch_bounds__(256) void k_sketch_mode0(
 #pragma unroll
     for (int e = 0; e < V; ++e) acc[j][e] = (WT)0;
 
-  for (int i1 = wv; i1 < n1; i1 += NW) {
-    const uint32_t t1 = tab1[i1];
-    const uint32_t h1 = t1 & TT_KEY_MASK;
-    const uint32_t c = b >= h1 ? b - h1 : b + J - h1;
-    const uint32_t beg = off[c], end = off[c + 1];
-    for (uint32_t e0 = beg; e0 < end; e0 += G * U) {
-      Vec<XT, V> x[U][NJ];
-      uint32_t sg[U];
-      bool ok[U];
+  // the i_1 of this wave (i_1 = wv + NW q) are taken 64 at a time: lane q
+  // fetches the table entry and list segment of one of them, and the first
+  // 64 list entries of the next segment are loaded before the fibres of the
+  // current one, so the loads of X never wait on a list load issued just
+  // before them
+  for (int i1b = wv; i1b < n1; i1b += NW * 64) {
+    const int i1l = i1b + NW * lane;
+    uint32_t t1l = 0, begl = 0, endl = 0;
+    if (i1l < n1) {
+      t1l = tab1[i1l];
+      const uint32_t h1 = t1l & TT_KEY_MASK;
+      const uint32_t c = b >= h1 ? b - h1 : b + J - h1;
+      begl = off[c];
+      endl = off[c + 1];
+    }
+    const int nq0 = (n1 - i1b + NW - 1) / NW;
+    const int nq = nq0 < 64 ? nq0 : 64;
+    uint32_t nxt;
+    {
+      const uint32_t nb0 = (uint32_t)__shfl((int)begl, 0, 64), ne0 = (uint32_t)__shfl((int)endl, 0, 64);
+      nxt = (nb0 + lane < ne0) ? sorted[nb0 + lane] : 0u;
+    }
+    for (int q = 0; q < nq; ++q) {
+      const uint32_t t1 = (uint32_t)__shfl((int)t1l, q, 64);
+      const uint32_t beg = (uint32_t)__shfl((int)begl, q, 64), end = (uint32_t)__shfl((int)endl, q, 64);
+      const int i1 = i1b + NW * q;
+      const uint32_t first = nxt;
+      if (q + 1 < nq) {
+        const uint32_t nb1 = (uint32_t)__shfl((int)begl, q + 1, 64), ne1 = (uint32_t)__shfl((int)endl, q + 1, 64);
+        nxt = (nb1 + lane < ne1) ? sorted[nb1 + lane] : 0u;
+      }
+      for (uint32_t e0 = beg; e0 < end; e0 += 64) {
+        const uint32_t itl = e0 == beg ? first : ((e0 + lane < end) ? sorted[e0 + lane] : 0u);
+        const int nb = (end - e0) < 64u ? (int)(end - e0) : 64;
+        for (int t = 0; t < nb; t += G * U) {
+          Vec<XT, V> x[U][NJ];
+          uint32_t sg[U];
+          bool ok[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t e = e0 + u * G + g;
-        ok[u] = e < end;
-        const uint32_t item = ok[u] ? sorted[e] : 0u;
-        sg[u] = (item ^ t1) & TT_KEY_SIGN;
-        const XT* base = X + ((int64_t)(item & TT_KEY_MASK) * n1 + i1) * (int64_t)n0 + i0_lo;
+          for (int u = 0; u < U; ++u) {
+            const int idx = t + u * G + g;
+            ok[u] = idx < nb;
+            const uint32_t item = (uint32_t)__shfl((int)itl, idx & 63, 64);
+            sg[u] = (item ^ t1) & TT_KEY_SIGN;
+            const XT* base = X + ((int64_t)(item & TT_KEY_MASK) * n1 + i1) * (int64_t)n0 + i0_lo;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          const int p = (v + LPF * j) * V;
-          if (ok[u] && p < i0_cnt) x[u][j] = load_vec<XT, V>(base + p);
+            for (int j = 0; j < NJ; ++j) {
+              const int p = (v + LPF * j) * V;
+              if (ok[u] && p < i0_cnt) x[u][j] = load_vec<XT, V>(base + p);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+              const int p = (v + LPF * j) * V;
+              if (ok[u] && p < i0_cnt)
+#pragma unroll
+                for (int e = 0; e < V; ++e) acc[j][e] += apply_sign<WT>(to_work<WT>(x[u][j].e[e]), sg[u]);
+            }
         }
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          const int p = (v + LPF * j) * V;
-          if (ok[u] && p < i0_cnt)
-#pragma unroll
-            for (int e = 0; e < V; ++e) acc[j][e] += apply_sign<WT>(to_work<WT>(x[u][j].e[e]), sg[u]);
-        }
     }
   }
   // lane groups hold partial sums of the same positions: fold them
