@@ -67,6 +67,52 @@ def cpu_baseline(X, cfg, plan, budget_entries):
                       % (len(n), len(n) - 1, ns, Xs.size, dt)}
 
 
+def source_digest():
+    """sha256 of the data-sketch kernel source: a stored counter reading is
+    used only while the kernel it was taken from is unchanged."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2309_08093_amd", "csrc", "k_sketch.hip")
+    try:
+        return hashlib.sha256(open(path, "rb").read()).hexdigest()
+    except OSError:
+        return None
+
+
+def stored_traffic(kernel, config):
+    """HBM bytes per launch of `kernel` on `config` from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a device copy of known size),
+    or None if there is none for the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s_%s.txt" % (kernel, config))
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        if ln.startswith("JSON: "):
+            rec = json.loads(ln[6:])
+            if rec.get("source_sha256") == source_digest():
+                return rec["traffic_bytes_per_launch"]
+    return None
+
+
+def probe_traffic(plan, X, d, J, n, dev):
+    """One launch of every data sketch and one device-to-device copy of X,
+    bracketed by prints: the workload of the FETCH_SIZE / WRITE_SIZE runs."""
+    import torch
+    Ys = [torch.empty(J * n[k], dtype=plan.wdtype, device=dev) for k in range(d)]
+    for k in range(d):                      # warm (fibre lists, caches of tables)
+        plan.sketch_tensor(X, k, Ys[k])
+    torch.cuda.synchronize()
+    for k in range(d):
+        plan.sketch_tensor(X, k, Ys[k])
+        torch.cuda.synchronize()
+        print("[probe] sketch k=%d kernel=%s" % (k, plan.sketch_kernel(k)), flush=True)
+    dst = torch.empty_like(X)
+    dst.copy_(X)
+    torch.cuda.synchronize()
+    print("[probe] copy bytes=%d" % (X.numel() * X.element_size()), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +125,10 @@ def main():
     ap.add_argument("--cpu-entries", type=int, default=128_000_000)
     ap.add_argument("--serial", action="store_true",
                     help="keep the data sketches on the plan's stream (no overlap with the solve chain)")
+    ap.add_argument("--reserve-cus", type=int, default=None,
+                    help="CUs kept free of the overlapped data sketches (library default if omitted)")
+    ap.add_argument("--probe-traffic", action="store_true",
+                    help="run each data sketch once and one device copy of X, then exit (for HBM counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -102,8 +152,13 @@ def main():
     init = synth.random_cores(n, R, args.seed + 1)
     plan = tts.Plan(n, R, J, lam, seed=args.seed, x_dtype=cfg["xd"], work_dtype=cfg["wd"], gram=cfg["gram"],
                     device=dev, serial=args.serial)
+    if args.reserve_cus is not None:
+        plan.set_overlap(args.reserve_cus)
     cores = [tts.core_to_device(c, dev) for c in init]
     torch.cuda.synchronize()
+    if args.probe_traffic:
+        probe_traffic(plan, X, d, J, n, dev)
+        return
 
     print("[bench] warmup %d sweeps" % args.warmup, file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -131,20 +186,22 @@ def main():
     entries_per_s = d * N / (ms_per_step * 1e-3)
     xbytes = XBYTES[cfg["xd"]]
 
-    # dominant kernel: the k >= 1 data sketch (d - 1 launches per sweep)
-    def roof(cls):
+    # the data sketches dominate: k >= 1 (d - 1 launches per sweep) and k = 0
+    def roof(cls, kernel):
         ms, cnt = prof[cls]
         if cnt == 0:
             return None
         avg_s = ms / cnt * 1e-3
         gbps = N * xbytes / avg_s / 1e9
         return {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": None, "kernel": "k_sketch_modek" if cls == "sketch_k"
-                else "k_sketch_mode0", "avg_launch_ms": round(ms / cnt, 4), "launches": cnt,
+                "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": stored_traffic(kernel, args.config),
+                "kernel": kernel, "avg_launch_ms": round(ms / cnt, 4), "launches": cnt,
                 "bytes_per_launch": N * xbytes}
 
-    rf = roof("sketch_k")
-    rf0 = roof("sketch_k0")
+    kern_k = sorted(set(plan.sketch_kernel(k) for k in range(1, d)))
+    rfk = roof("sketch_k", "+".join(kern_k))
+    rf0 = roof("sketch_k0", plan.sketch_kernel(0))
+    rf, rf_other = (rfk, rf0) if prof["sketch_k"][0] >= prof["sketch_k0"][0] else (rf0, rfk)
     kernels = {k: round(v[0] / args.steps, 4) for k, v in prof.items()}
 
     out = {
@@ -162,13 +219,33 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "n": n, "ranks": R, "J": J, "lambda": lam,
                    "step": "one sweep of Algorithm 1 (%d data-sketch passes over X)" % d,
-                   "schedule": "serial" if args.serial else "data sketches overlapped on a second stream"},
+                   "schedule": "serial" if args.serial else "data sketches overlapped on a second stream",
+                   "reserved_cus": None if args.serial else args.reserve_cus},
         "hbm_gbps_sweep": d * N * xbytes / (ms_per_step * 1e-3) / 1e9,
         "wall_s_timed": wall,
         "roofline": rf,
-        "roofline_k0": rf0,
+        "roofline_other_sketch": rf_other,
         "kernels_ms_per_step": kernels,
     }
+
+    # each data sketch alone on the plan's stream (no concurrent core updates)
+    iso = {}
+    Ytmp = [torch.empty(J * n[k], dtype=plan.wdtype, device=dev) for k in range(d)]
+    for k in range(d):
+        plan.sketch_tensor(X, k, Ytmp[k])
+        torch.cuda.synchronize()
+        plan.profile(True)
+        plan.profile_read()
+        for _ in range(5):
+            plan.sketch_tensor(X, k, Ytmp[k])
+        pr = plan.profile_read()
+        plan.profile(False)
+        ms, cnt = pr["sketch_k0" if k == 0 else "sketch_k"]
+        gbps = N * xbytes / (ms / cnt * 1e-3) / 1e9
+        iso[k] = {"kernel": plan.sketch_kernel(k), "avg_launch_ms": round(ms / cnt, 4), "GB/s": round(gbps, 1),
+                  "frac": round(gbps / HBM_PEAK_GBPS, 4)}
+    out["sketch_isolated"] = iso
+    del Ytmp
 
     if not args.no_time_to_target:
         print("[bench] time to relative residual 1e-2", file=sys.stderr, flush=True)

@@ -171,6 +171,17 @@ tt_status tt_residual(tt_plan plan, const void* X, const void* const* cores, dou
  * synchronises. */
 tt_status tt_als_sweep(tt_plan plan, const void* X, void* const* cores, double* rel_residual);
 
+/* Schedule of an overlapped sweep (flags without TT_FLAG_SERIAL).  The d data
+ * sketches of a sweep depend only on X and the sweep's tables, so they run on
+ * a plan-owned side stream while the core updates run on a second plan-owned
+ * stream; both fork from and join back into the plan's stream, so the call
+ * stays asynchronous and ordered with respect to it.  reserved_cus CUs are
+ * left out of the side stream's CU mask (hipExtStreamCreateWithCUMask) for
+ * the short kernels of the core updates; 0 (the default) gives the side
+ * stream every CU.  TT_ERR_ARG if reserved_cus is negative or not below the
+ * device's CU count.  Synchronises and recreates the plan's streams. */
+tt_status tt_plan_set_overlap(tt_plan plan, int32_t reserved_cus);
+
 /* Measurement: when enabled, every launch of the kernels below is bracketed
  * by a pair of HIP events recorded on the plan's stream.  Classes: */
 #define TT_PROF_SKETCH0 0    /* data sketch main kernel, k = 0 (bucket gather) */
@@ -188,6 +199,18 @@ tt_status tt_plan_profile(tt_plan plan, int32_t enable);
  * of launches since the last read (arrays of nclass <= TT_PROF_NCLASS
  * entries, host memory), and reset the counters. */
 tt_status tt_plan_profile_read(tt_plan plan, int32_t nclass, double* ms, int64_t* launches);
+
+/* Which data-sketch kernel tt_sketch_tensor runs for mode k of this plan
+ * (host query, no device work): TT_SKETCH_PATH_BUCKET for k = 0 (one
+ * workgroup per bucket gathers the fibres hashed to it), TT_SKETCH_PATH_STREAM
+ * (fibres streamed in memory order into LDS bucket arrays) or
+ * TT_SKETCH_PATH_GROUPED (fibres of a column visited in order of their key and
+ * summed per key before the LDS scatter) for k >= 1.  TT_ERR_ARG for a bad k
+ * or null output. */
+#define TT_SKETCH_PATH_BUCKET 0
+#define TT_SKETCH_PATH_STREAM 1
+#define TT_SKETCH_PATH_GROUPED 2
+tt_status tt_plan_sketch_path(tt_plan plan, int32_t k, int32_t* path);
 
 /* Synchronise the plan's stream and report device-side failures recorded so
  * far (TT_ERR_NOT_SPD); clears the recorded status. */

@@ -219,6 +219,16 @@ class Plan:
         check(_lib.tt_plan_profile_read(self._h, nc, ms, cnt), "tt_plan_profile_read")
         return {name: (ms[i], cnt[i]) for i, name in enumerate(_abi.PROF_CLASSES)}
 
+    def set_overlap(self, reserved_cus):
+        """CUs kept free of the overlapped data sketches (see tt_plan_set_overlap)."""
+        check(_lib.tt_plan_set_overlap(self._h, int(reserved_cus)), "tt_plan_set_overlap")
+
+    def sketch_kernel(self, k):
+        """Name of the data-sketch kernel tt_sketch_tensor runs for mode k."""
+        path = ctypes.c_int32()
+        check(_lib.tt_plan_sketch_path(self._h, int(k), ctypes.byref(path)), "tt_plan_sketch_path")
+        return _abi.SKETCH_PATHS[path.value]
+
     def sync_status(self):
         check(_lib.tt_plan_sync_status(self._h), "tt_plan_sync_status")
 

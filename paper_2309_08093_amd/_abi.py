@@ -54,7 +54,10 @@ SIGNATURES = {
     "tt_plan_sync_status": [_vp],
     "tt_plan_profile": [_vp, ctypes.c_int32],
     "tt_plan_profile_read": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+    "tt_plan_sketch_path": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "tt_plan_set_overlap": [_vp, ctypes.c_int32],
 }
+SKETCH_PATHS = {0: "k_sketch_mode0", 1: "k_sketch_modek", 2: "k_sketch_gs"}
 PROF_CLASSES = ["sketch_k0", "sketch_k", "sketch_aux", "interface", "gram", "solve", "qr", "residual", "tables"]
 STRING_FUNCS = ["tt_last_error", "tt_version"]
 

@@ -141,6 +141,9 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->stream = static_cast<hipStream_t>(hip_stream);
   p->user_stream = p->stream;
   p->side = nullptr;
+  p->chain = nullptr;
+  p->reserved_cus = TT_DEFAULT_RESERVED_CUS;
+  p->sketch_cus = 0;
   p->flags = desc->flags;
   p->sweep = 0;
   p->override_tables = false;
@@ -251,16 +254,75 @@ tt_status tt_plan_set_stream(tt_plan p, void* s) {
   return TT_OK;
 }
 
+namespace {
+
+void free_streams(tt_plan p) {
+  if (!p->side) return;
+  (void)hipStreamSynchronize(p->side);
+  (void)hipStreamSynchronize(p->chain);
+  (void)hipStreamDestroy(p->side);
+  (void)hipStreamDestroy(p->chain);
+  (void)hipEventDestroy(p->ev_fork);
+  (void)hipEventDestroy(p->ev_join);
+  (void)hipEventDestroy(p->ev_done);
+  for (int k = 0; k < TT_MAX_ORDER; ++k) (void)hipEventDestroy(p->ev_y[k]);
+  p->side = p->chain = nullptr;
+}
+
+int device_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return n;
+}
+
+// The side stream carries the data sketches; its CU mask leaves the first
+// reserved_cus CUs (in the runtime's CU numbering) to the chain stream, so
+// the short latency-bound kernels of the core updates are not queued behind
+// the persistent sketch grids.
+tt_status make_streams(tt_plan p) {
+  if (p->side) return TT_OK;
+  const int ncu = device_cus();
+  if (p->reserved_cus > 0 && ncu > p->reserved_cus) {
+    std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+    for (int i = p->reserved_cus; i < ncu; ++i) mask[i / 32] |= 1u << (i % 32);
+    TT_HIP_TRY(hipExtStreamCreateWithCUMask(&p->side, (uint32_t)mask.size(), mask.data()));
+  } else {
+    TT_HIP_TRY(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+  }
+  TT_HIP_TRY(hipStreamCreateWithFlags(&p->chain, hipStreamNonBlocking));
+  TT_HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+  TT_HIP_TRY(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+  TT_HIP_TRY(hipEventCreateWithFlags(&p->ev_done, hipEventDisableTiming));
+  for (int k = 0; k < TT_MAX_ORDER; ++k) TT_HIP_TRY(hipEventCreateWithFlags(&p->ev_y[k], hipEventDisableTiming));
+  return TT_OK;
+}
+
+// restores the plan's launch stream when an overlapped sweep returns
+struct StreamRestore {
+  tt_plan p;
+  ~StreamRestore() {
+    p->stream = p->user_stream;
+    p->sketch_cus = 0;
+  }
+};
+
+}  // namespace
+
+tt_status tt_plan_set_overlap(tt_plan p, int32_t reserved_cus) {
+  if (!p) return tt_fail(TT_ERR_ARG, "null plan");
+  const int ncu = device_cus();
+  if (reserved_cus < 0 || (ncu > 0 && reserved_cus >= ncu))
+    return tt_fail(TT_ERR_ARG, "reserved_cus=%d outside [0, %d)", reserved_cus, ncu);
+  free_streams(p);
+  p->reserved_cus = reserved_cus;
+  return TT_OK;
+}
+
 tt_status tt_plan_destroy(tt_plan p) {
   if (p) {
     tt_prof_free(p);
-    if (p->side) {
-      hipStreamSynchronize(p->side);
-      hipStreamDestroy(p->side);
-      hipEventDestroy(p->ev_fork);
-      hipEventDestroy(p->ev_join);
-      for (int k = 0; k < TT_MAX_ORDER; ++k) hipEventDestroy(p->ev_y[k]);
-    }
+    free_streams(p);
   }
   delete p;
   return TT_OK;
@@ -311,6 +373,13 @@ tt_status tt_plan_set_tables(tt_plan p, int32_t s, const int32_t* h, const int8_
                             hipMemcpyHostToDevice, p->stream));
   TT_HIP_TRY(hipStreamSynchronize(p->stream));
   p->override_tables = true;
+  return TT_OK;
+}
+
+tt_status tt_plan_sketch_path(tt_plan p, int32_t k, int32_t* path) {
+  if (!p || !path) return tt_fail(TT_ERR_ARG, "null argument");
+  if (k < 0 || k >= p->d) return tt_fail(TT_ERR_ARG, "k=%d out of range", k);
+  *path = k == 0 ? TT_SKETCH_PATH_BUCKET : (tt_sketch_use_gs(p, k) ? TT_SKETCH_PATH_GROUPED : TT_SKETCH_PATH_STREAM);
   return TT_OK;
 }
 
@@ -410,39 +479,36 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
   if ((st = check_cores(p, cores))) return st;
   double* const* G = reinterpret_cast<double* const*>(cores);
   const int d = p->d;
-  // 1. right-to-left orthogonalisation
-  for (int k = d - 1; k >= 1; --k)
-    if ((st = right_orth(p, G, k))) return st;
-  // 2. tables of this sweep are current (generated at bind / set_sweep / end of
-  //    the previous sweep, or overridden)
   const CoreDesc cd = make_desc(p, cores);
   void* SH = p->ws + p->o_SH;
   void* Y = p->ws + p->o_Y;
-  // data sketches: only X and this sweep's tables, so they can run ahead on
-  // the side stream while the chain below proceeds
+  // The data sketches need only X and this sweep's tables (generated at bind,
+  // set_sweep or the end of the previous sweep, or overridden), so they run
+  // ahead on the side stream while the chain of core updates proceeds on the
+  // chain stream; both fork from and join back into the plan's stream.
   const bool overlap = !(p->flags & TT_FLAG_SERIAL);
   char* Yall = p->ws + p->o_Yall;
+  StreamRestore restore{p};
   if (overlap) {
-    if (!p->side) {
-      TT_HIP_TRY(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
-      TT_HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
-      TT_HIP_TRY(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
-      for (int k = 0; k < TT_MAX_ORDER; ++k) TT_HIP_TRY(hipEventCreateWithFlags(&p->ev_y[k], hipEventDisableTiming));
-    }
+    if ((st = make_streams(p))) return st;
     TT_HIP_TRY(hipEventRecord(p->ev_fork, p->user_stream));
     TT_HIP_TRY(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+    TT_HIP_TRY(hipStreamWaitEvent(p->chain, p->ev_fork, 0));
     p->stream = p->side;
+    const int ncu = device_cus();
+    p->sketch_cus = (p->reserved_cus > 0 && ncu > p->reserved_cus) ? ncu - p->reserved_cus : 0;
     for (int k = 0; k < d; ++k) {
       const hipError_t e = launch_sketch_tensor(p, X, k, Yall + p->wsize() * p->J * p->tab_off[k]);
-      if (e == hipSuccess) TT_HIP_TRY(hipEventRecord(p->ev_y[k], p->side));
-      if (e != hipSuccess) {
-        p->stream = p->user_stream;
-        return tt_fail(TT_ERR_HIP, "data sketch launch failed: %s", hipGetErrorString(e));
-      }
+      if (e != hipSuccess) return tt_fail(TT_ERR_HIP, "data sketch launch failed: %s", hipGetErrorString(e));
+      TT_HIP_TRY(hipEventRecord(p->ev_y[k], p->side));
     }
     TT_HIP_TRY(hipEventRecord(p->ev_join, p->side));
-    p->stream = p->user_stream;
+    p->stream = p->chain;
+    p->sketch_cus = 0;
   }
+  // 1. right-to-left orthogonalisation
+  for (int k = d - 1; k >= 1; --k)
+    if ((st = right_orth(p, G, k))) return st;
   // transformed CountSketches of all cores (core 0 is not needed for k = 0)
   {
     TTProfScope ps(p, TT_PROF_INTERFACE);
@@ -474,7 +540,12 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
       TT_HIP_TRY(launch_core_fft(p, cd, k, k, -1));
     }
   }
-  if (overlap) TT_HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_join, 0));
+  if (overlap) {
+    TT_HIP_TRY(hipStreamWaitEvent(p->chain, p->ev_join, 0));
+    TT_HIP_TRY(hipEventRecord(p->ev_done, p->chain));
+    TT_HIP_TRY(hipStreamWaitEvent(p->user_stream, p->ev_done, 0));
+    p->stream = p->user_stream;
+  }
   p->sweep += 1;
   if (!p->override_tables)
     if ((st = gen_tables(p))) return st;

@@ -471,7 +471,7 @@ hipError_t run_modek(const tt_plan_s* p, const XT* X, int k, WT* Y, int lpf_log2
   int per_cu = 0;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TT_SKETCH_THREADS, lds)) != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
-  const int64_t W = tt_sketch_workgroups(p, k, (int64_t)per_cu * num_cus());
+  const int64_t W = tt_sketch_workgroups(p, k, (int64_t)per_cu * (p->sketch_cus > 0 ? p->sketch_cus : num_cus()));
   const int64_t maxslots = tt_sketch_slots(p, k, W);
   if (nk * maxslots * p->J > p->part_entries) return hipErrorInvalidValue;   // sized at plan time
   double* part = p->at<double>(p->o_part);
@@ -506,7 +506,7 @@ hipError_t run_gs(const tt_plan_s* p, const XT* X, int k, WT* Y, int lpf_log2) {
   int per_cu = 0;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TT_SKETCH_THREADS, lds)) != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
-  const int64_t W = tt_sketch_workgroups(p, k, (int64_t)per_cu * num_cus());
+  const int64_t W = tt_sketch_workgroups(p, k, (int64_t)per_cu * (p->sketch_cus > 0 ? p->sketch_cus : num_cus()));
   const int64_t maxslots = tt_sketch_slots(p, k, W);
   if (nk * maxslots * p->J > p->part_entries) return hipErrorInvalidValue;   // sized at plan time
   double* part = p->at<double>(p->o_part);

@@ -23,7 +23,10 @@ struct tt_plan_s {
   hipStream_t stream;          // stream the launchers enqueue on (the user's, or the side stream)
   hipStream_t user_stream;     // the plan's stream (tt_sketch_plan / tt_plan_set_stream)
   hipStream_t side;            // plan-owned stream for the overlapped data sketches (lazy)
-  hipEvent_t ev_fork, ev_join, ev_y[TT_MAX_ORDER];
+  hipStream_t chain;           // plan-owned stream for the rest of an overlapped sweep (lazy)
+  hipEvent_t ev_fork, ev_join, ev_done, ev_y[TT_MAX_ORDER];
+  int32_t reserved_cus;        // CUs withheld from the side stream (its CU mask)
+  int32_t sketch_cus;          // CUs a persistent sketch grid may fill on p->stream (0: all)
   uint32_t flags;
   int64_t sweep;
   bool override_tables;
@@ -106,6 +109,10 @@ hipError_t launch_residual(const tt_plan_s* p, const void* X, const CoreDesc& cd
 hipError_t launch_copy_f64(const tt_plan_s* p, double* dst, const double* src, int64_t count);
 
 #define TT_SKETCH_MAX_WG 4096
+// CUs an overlapped sweep keeps free of the data sketches by default
+#ifndef TT_DEFAULT_RESERVED_CUS
+#define TT_DEFAULT_RESERVED_CUS 0
+#endif
 int64_t tt_sketch_workgroups(const tt_plan_s* p, int k, int64_t resident);   // k >= 1 sketch grid
 int64_t tt_sketch_slots(const tt_plan_s* p, int k, int64_t W);              // partials per column
 bool tt_sketch_use_gs(const tt_plan_s* p, int k);                           // key-grouped k >= 1 path
