@@ -115,6 +115,15 @@ tt_status tt_plan_destroy(tt_plan plan);
 tt_status tt_plan_set_sweep(tt_plan plan, int64_t t);
 tt_status tt_plan_get_sweep(tt_plan plan, int64_t* t);
 
+/* Change the sketch size and proximal parameter used from now on (Alg. 1
+ * takes m and sigma as inputs; a sketch-size policy may change them between
+ * sweeps).  1 <= J <= the descriptor's J (the workspace is sized for it) and
+ * J a product of 2, 3, 5 and 7; lambda finite and >= 0.  Regenerates the
+ * tables of the current sweep for the new J and drops any table override.
+ * TT_ERR_ARG otherwise, with the plan unchanged. */
+tt_status tt_plan_set_sketch(tt_plan plan, int64_t J, double lambda);
+tt_status tt_plan_get_sketch(tt_plan plan, int64_t* J, double* lambda);
+
 /* Copy the current tables of mode s to host memory (n_s entries each).
  * Synchronises the stream. */
 tt_status tt_plan_get_tables(tt_plan plan, int32_t s, int32_t* h, int8_t* v);
@@ -221,6 +230,88 @@ const char* tt_last_error(void);
 
 /* Library version string. */
 const char* tt_version(void);
+
+/* ------------------------------------------------------------------------
+ * Learned sketch-size policy.
+ *
+ * The paper fixes the sketch size only through the bound of Corollary 3
+ * (Sec. 4) and notes in Sec. 5 that the bound is conservative.  This
+ * extension predicts (log J, log lambda) for each core update from cheap
+ * features with a small multilayer perceptron, and falls back to the
+ * Corollary 3 bound (capped at the plan's J) when a residual check fails.
+ *
+ * Network: F = 8 inputs -> 64 -> 64 -> 64 -> 2 outputs, ReLU after each
+ * hidden layer, FP32.  Parameters are one device array of
+ * TT_JPOLICY_PARAMS floats: for each layer, W (fan_out x fan_in, row-major)
+ * then the bias.  Features and targets are row-major B x F and B x 2 device
+ * arrays.  Loss: mean over the B x 2 outputs of (y - target)^2.
+ * Outputs: y0 = ln J - 7, y1 = log10 lambda + 3.
+ * Features of core k at sweep t (tt_jpolicy_features):
+ *   ln n_k / 4, ln R_k / 2, ln R_{k+1} / 2, ln(N / n_k) / 16, d / 5, k / d,
+ *   t / 10, and the last residual drop log10(res_{t-1} / res_t) (res_{-1} = 1,
+ *   0 at t = 0), clipped to [-1, 4].
+ * ---------------------------------------------------------------------- */
+#define TT_JPOLICY_FEATURES 8
+#define TT_JPOLICY_HIDDEN 64
+#define TT_JPOLICY_OUTPUTS 2
+#define TT_JPOLICY_PARAMS 9026
+#define TT_JPOLICY_MAX_BATCH (1 << 20)
+
+/* y = net(feats) for B samples (1 <= B <= TT_JPOLICY_MAX_BATCH); device
+ * pointers; asynchronous on `stream`. */
+tt_status tt_jpolicy_forward(const float* params, const float* feats, int32_t B, float* out, void* stream);
+
+/* Gradient of the loss w.r.t. the parameters (TT_JPOLICY_PARAMS floats,
+ * overwritten) and the loss itself (one float), for B samples
+ * (1 <= B <= 4096), by backpropagation in one workgroup with a fixed
+ * summation order (deterministic).  Device pointers; asynchronous. */
+tt_status tt_jpolicy_loss_grad(const float* params, const float* feats, const float* targets, int32_t B, float* grad,
+                               float* loss, void* stream);
+
+/* One Adam step (Kingma and Ba) on `count` parameters in place, step >= 1
+ * (bias corrections 1 - beta^step).  m, v: device moment arrays of the same
+ * length, updated in place.  Asynchronous. */
+tt_status tt_jpolicy_adam(float* params, float* m, float* v, const float* grad, int64_t count, int64_t step, float lr,
+                          float beta1, float beta2, float eps, void* stream);
+
+/* Features of every core update of the plan at sweep t (host output, d x F
+ * floats, row k = core k).  No device work. */
+tt_status tt_jpolicy_features(tt_plan plan, int64_t t, double last_drop, float* feats);
+
+/* Apply the network to the plan's d feature rows (in the plan's workspace, on
+ * its stream; synchronises) and return the sweep's sketch size and lambda:
+ * J = the largest of the d predictions, rounded to the nearest product of
+ * 2, 3, 5, 7 in [J_min, plan J]; lambda = the prediction of that core. */
+tt_status tt_jpolicy_choose(tt_plan plan, const float* params, int64_t t, double last_drop, int64_t J_min, int64_t* J,
+                            double* lambda);
+
+/* Corollary 3 (Sec. 4): m = max{8 s^2 (2 + 3^q) / delta, 8 s (2 + 3^q) /
+ * (eps delta)} for s unknowns per column and q sketched modes.
+ * TT_ERR_ARG unless s >= 1, q >= 1, 0 < eps, 0 < delta < 1. */
+tt_status tt_sketch_size_bound(int64_t s, int32_t q, double eps, double delta, double* m);
+
+/* Fallback sketch size of the plan: the largest Corollary 3 bound over its
+ * core updates (s = R_k R_{k+1}, q = d - 1), capped at the plan's J and
+ * rounded down to a product of 2, 3, 5, 7. */
+tt_status tt_plan_fallback_J(tt_plan plan, double eps, double delta, int64_t* J);
+
+/* Run sweeps until the exact relative residual is <= target or max_sweeps
+ * sweeps are done.  With params == NULL every sweep uses the plan's current
+ * J and lambda.  Otherwise the policy chooses (J, lambda) before each sweep
+ * from the features above; when a sweep does not lower the residual, the next
+ * sweep uses tt_plan_fallback_J (eps = 0.5, delta = 0.1) and the
+ * descriptor's lambda.  The residual of every sweep is computed exactly and
+ * read back (synchronising).  residuals, Js, lambdas: host arrays of
+ * max_sweeps entries or NULL. */
+typedef struct {
+  int32_t sweeps;      /* sweeps performed */
+  int32_t reached;     /* 1 if the last residual <= target */
+  int32_t fallbacks;   /* sweeps run at the fallback size */
+  double residual;     /* last exact relative residual */
+} tt_run_stats;
+tt_status tt_als_run(tt_plan plan, const void* X, void* const* cores, const float* params, int32_t max_sweeps,
+                     double target, int64_t J_min, double* residuals, int64_t* Js, double* lambdas,
+                     tt_run_stats* stats);
 
 #ifdef __cplusplus
 }

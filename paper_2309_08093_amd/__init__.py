@@ -219,6 +219,55 @@ class Plan:
         check(_lib.tt_plan_profile_read(self._h, nc, ms, cnt), "tt_plan_profile_read")
         return {name: (ms[i], cnt[i]) for i, name in enumerate(_abi.PROF_CLASSES)}
 
+    def set_sketch(self, J, lam):
+        """Sketch size and proximal parameter from now on (J <= the plan's J)."""
+        check(_lib.tt_plan_set_sketch(self._h, int(J), float(lam)), "tt_plan_set_sketch")
+
+    def get_sketch(self):
+        J = ctypes.c_int64()
+        lam = ctypes.c_double()
+        check(_lib.tt_plan_get_sketch(self._h, ctypes.byref(J), ctypes.byref(lam)), "tt_plan_get_sketch")
+        return J.value, lam.value
+
+    def fallback_J(self, eps=0.5, delta=0.1):
+        """Corollary 3 sketch size of this plan, capped at its J."""
+        J = ctypes.c_int64()
+        check(_lib.tt_plan_fallback_J(self._h, float(eps), float(delta), ctypes.byref(J)), "tt_plan_fallback_J")
+        return J.value
+
+    def features(self, t, last_drop):
+        """Policy features of the d core updates at sweep t (numpy d x F)."""
+        out = (ctypes.c_float * (self.d * _abi.JPOLICY_FEATURES))()
+        check(_lib.tt_jpolicy_features(self._h, int(t), float(last_drop), out), "tt_jpolicy_features")
+        return np.frombuffer(out, dtype=np.float32).reshape(self.d, _abi.JPOLICY_FEATURES).copy()
+
+    def choose(self, params, t, last_drop, J_min=64):
+        """(J, lambda) the policy network picks for sweep t."""
+        J = ctypes.c_int64()
+        lam = ctypes.c_double()
+        check(_lib.tt_jpolicy_choose(self._h, _ptr(params), int(t), float(last_drop), int(J_min), ctypes.byref(J),
+                                     ctypes.byref(lam)), "tt_jpolicy_choose")
+        return J.value, lam.value
+
+    def run(self, X, cores, max_sweeps, target, params=None, J_min=64):
+        """Sweeps until the exact residual <= target (tt_als_run).  Returns a
+        dict with the per-sweep residuals, J and lambda and the run stats."""
+        self._check_X(X)
+        arr, keep = self._cores(cores)
+        if params is not None and not (isinstance(params, torch.Tensor) and params.dtype == torch.float32
+                                       and params.is_contiguous() and params.numel() == _abi.JPOLICY_PARAMS
+                                       and params.device.type == "cuda"):
+            raise ValueError("params must be a contiguous float32 device tensor of %d entries" % _abi.JPOLICY_PARAMS)
+        res = (ctypes.c_double * max_sweeps)()
+        Js = (ctypes.c_int64 * max_sweeps)()
+        lams = (ctypes.c_double * max_sweeps)()
+        st = _abi.RunStats()
+        check(_lib.tt_als_run(self._h, _ptr(X), arr, None if params is None else _ptr(params), int(max_sweeps),
+                              float(target), int(J_min), res, Js, lams, ctypes.byref(st)), "tt_als_run")
+        n = st.sweeps
+        return {"sweeps": n, "reached": bool(st.reached), "fallbacks": st.fallbacks, "residual": st.residual,
+                "residuals": list(res[:n]), "J": list(Js[:n]), "lambda": list(lams[:n])}
+
     def set_overlap(self, reserved_cus):
         """CUs kept free of the overlapped data sketches (see tt_plan_set_overlap)."""
         check(_lib.tt_plan_set_overlap(self._h, int(reserved_cus)), "tt_plan_set_overlap")
@@ -233,4 +282,11 @@ class Plan:
         check(_lib.tt_plan_sync_status(self._h), "tt_plan_sync_status")
 
 
-__all__ = ["Plan", "TTError", "core_to_device", "core_to_host", "version"]
+def sketch_size_bound(s, q, eps=0.5, delta=0.1):
+    """Corollary 3 sketch size m for s unknowns per column and q sketched modes."""
+    m = ctypes.c_double()
+    check(_lib.tt_sketch_size_bound(int(s), int(q), float(eps), float(delta), ctypes.byref(m)), "tt_sketch_size_bound")
+    return m.value
+
+
+__all__ = ["Plan", "TTError", "core_to_device", "core_to_host", "version", "sketch_size_bound"]

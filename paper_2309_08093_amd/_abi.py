@@ -56,7 +56,32 @@ SIGNATURES = {
     "tt_plan_profile_read": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
     "tt_plan_sketch_path": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "tt_plan_set_overlap": [_vp, ctypes.c_int32],
+    "tt_plan_set_sketch": [_vp, ctypes.c_int64, ctypes.c_double],
+    "tt_plan_get_sketch": [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
+    "tt_jpolicy_forward": [_vp, _vp, ctypes.c_int32, _vp, _vp],
+    "tt_jpolicy_loss_grad": [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp],
+    "tt_jpolicy_adam": [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_float, ctypes.c_float,
+                        ctypes.c_float, ctypes.c_float, _vp],
+    "tt_jpolicy_features": [_vp, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(ctypes.c_float)],
+    "tt_jpolicy_choose": [_vp, _vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                          ctypes.POINTER(ctypes.c_double)],
+    "tt_sketch_size_bound": [ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                             ctypes.POINTER(ctypes.c_double)],
+    "tt_plan_fallback_J": [_vp, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)],
+    "tt_als_run": [_vp, _vp, _vpp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                   ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
 }
+JPOLICY_FEATURES = 8
+JPOLICY_HIDDEN = 64
+JPOLICY_OUTPUTS = 2
+JPOLICY_PARAMS = 9026
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("reached", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
+                ("residual", ctypes.c_double)]
+
+
 SKETCH_PATHS = {0: "k_sketch_mode0", 1: "k_sketch_modek", 2: "k_sketch_gs"}
 PROF_CLASSES = ["sketch_k0", "sketch_k", "sketch_aux", "interface", "gram", "solve", "qr", "residual", "tables"]
 STRING_FUNCS = ["tt_last_error", "tt_version"]

@@ -133,7 +133,9 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   for (int k = 0; k < d; ++k) p->n[k] = desc->n[k];
   for (int k = 0; k <= d; ++k) p->r[k] = desc->r[k];
   p->J = desc->J;
+  p->J_cap = desc->J;
   p->lambda = desc->lambda;
+  p->lambda0 = desc->lambda;
   p->seed = desc->seed;
   p->xdt = desc->x_dtype;
   p->wdt = desc->work_dtype;
@@ -182,7 +184,9 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->part_entries = 1;
   for (int k = 1; k < d; ++k) {
     // the largest grid a launch can use gives the most partials per column
-    const int64_t W = tt_sketch_workgroups(p, k, TT_SKETCH_MAX_WG);
+    // (for every J up to J_cap, see tt_plan_set_sketch)
+    const int64_t Ftot = N / p->n[0];
+    const int64_t W = Ftot < TT_SKETCH_MAX_WG ? Ftot : TT_SKETCH_MAX_WG;
     const int64_t e = p->n[k] * tt_sketch_slots(p, k, W) * p->J;
     if (e > p->part_entries) p->part_entries = e;
   }
@@ -228,6 +232,7 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
     if (N / (p->n[0] * p->n[k]) > p->max_F) p->max_F = N / (p->n[0] * p->n[k]);
   p->o_fkeys = take(sizeof(uint32_t) * p->max_F);
   p->o_fsort = take(8 * p->max_F);
+  p->o_pol = take(sizeof(float) * TT_MAX_ORDER * (TT_JPOLICY_FEATURES + TT_JPOLICY_OUTPUTS));
   p->ws_need = o;
   p->ws = nullptr;
   p->ws_bytes = 0;
@@ -334,6 +339,28 @@ tt_status tt_plan_set_sweep(tt_plan p, int64_t t) {
   if (t < 0) return tt_fail(TT_ERR_ARG, "sweep index must be >= 0");
   p->sweep = t;
   return gen_tables(p);
+}
+
+tt_status tt_plan_set_sketch(tt_plan p, int64_t J, double lambda) {
+  if (!p) return tt_fail(TT_ERR_ARG, "null plan");
+  if (J < 1 || J > p->J_cap) return tt_fail(TT_ERR_ARG, "J=%lld outside [1, %lld]", (long long)J, (long long)p->J_cap);
+  int rad[32], nrad = 0;
+  if (!tt_factor_fft(J, rad, &nrad)) return tt_fail(TT_ERR_ARG, "J=%lld has a prime factor > 7", (long long)J);
+  if (!(lambda >= 0.0) || !isfinite(lambda)) return tt_fail(TT_ERR_ARG, "lambda must be finite and >= 0");
+  p->J = J;
+  p->lambda = lambda;
+  p->fft_nrad = nrad;
+  for (int i = 0; i < nrad; ++i) p->fft_radix[i] = rad[i];
+  p->override_tables = false;
+  if (p->ws) return gen_tables(p);
+  return TT_OK;
+}
+
+tt_status tt_plan_get_sketch(tt_plan p, int64_t* J, double* lambda) {
+  if (!p || !J || !lambda) return tt_fail(TT_ERR_ARG, "null argument");
+  *J = p->J;
+  *lambda = p->lambda;
+  return TT_OK;
 }
 
 tt_status tt_plan_get_sweep(tt_plan p, int64_t* t) {
@@ -552,6 +579,119 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
   if (rel_residual) {
     if ((st = residual_impl(p, X, cores, rel_residual))) return st;
     return tt_plan_sync_status(p);
+  }
+  return TT_OK;
+}
+
+// ---------------------------------------------------------------- sketch-size policy
+
+tt_status tt_jpolicy_features(tt_plan p, int64_t t, double last_drop, float* feats) {
+  if (!p || !feats) return tt_fail(TT_ERR_ARG, "null argument");
+  if (t < 0) return tt_fail(TT_ERR_ARG, "sweep index must be >= 0");
+  double drop = last_drop == last_drop ? last_drop : 0.0;
+  drop = drop < -1.0 ? -1.0 : (drop > 4.0 ? 4.0 : drop);
+  const int d = p->d;
+  for (int k = 0; k < d; ++k) {
+    float* f = feats + (size_t)k * TT_JPOLICY_FEATURES;
+    f[0] = (float)(log((double)p->n[k]) / 4.0);
+    f[1] = (float)(log((double)p->r[k]) / 2.0);
+    f[2] = (float)(log((double)p->r[k + 1]) / 2.0);
+    f[3] = (float)(log((double)p->N / (double)p->n[k]) / 16.0);
+    f[4] = (float)(d / 5.0);
+    f[5] = (float)((double)k / d);
+    f[6] = (float)((double)t / 10.0);
+    f[7] = (float)drop;
+  }
+  return TT_OK;
+}
+
+tt_status tt_jpolicy_choose(tt_plan p, const float* params, int64_t t, double last_drop, int64_t J_min, int64_t* J,
+                            double* lambda) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (!params || !J || !lambda) return tt_fail(TT_ERR_ARG, "null argument");
+  if (J_min < 1 || J_min > p->J_cap) return tt_fail(TT_ERR_ARG, "J_min=%lld outside [1, %lld]", (long long)J_min,
+                                                    (long long)p->J_cap);
+  const int d = p->d;
+  float host[TT_MAX_ORDER * (TT_JPOLICY_FEATURES + TT_JPOLICY_OUTPUTS)];
+  if ((st = tt_jpolicy_features(p, t, last_drop, host))) return st;
+  float* dfeat = p->at<float>(p->o_pol);
+  float* dout = dfeat + TT_MAX_ORDER * TT_JPOLICY_FEATURES;
+  TT_HIP_TRY(hipMemcpyAsync(dfeat, host, sizeof(float) * d * TT_JPOLICY_FEATURES, hipMemcpyHostToDevice, p->stream));
+  TT_HIP_TRY(launch_mlp_forward(params, dfeat, d, dout, p->stream));
+  float out[TT_MAX_ORDER * TT_JPOLICY_OUTPUTS];
+  TT_HIP_TRY(hipMemcpyAsync(out, dout, sizeof(float) * d * TT_JPOLICY_OUTPUTS, hipMemcpyDeviceToHost, p->stream));
+  TT_HIP_TRY(hipStreamSynchronize(p->stream));
+  int best = 0;
+  for (int k = 1; k < d; ++k)
+    if (out[k * TT_JPOLICY_OUTPUTS] > out[best * TT_JPOLICY_OUTPUTS]) best = k;
+  const double lnJ = (double)out[best * TT_JPOLICY_OUTPUTS] + 7.0;
+  const double l10 = (double)out[best * TT_JPOLICY_OUTPUTS + 1] - 3.0;
+  if (!isfinite(lnJ) || !isfinite(l10)) return tt_fail(TT_ERR_NONFINITE, "policy output is not finite");
+  const int64_t lo = tt_floor_smooth(J_min) < J_min ? tt_round_smooth((double)J_min, J_min, p->J_cap) : J_min;
+  *J = tt_round_smooth(exp(lnJ > 30.0 ? 30.0 : lnJ), lo, tt_floor_smooth(p->J_cap));
+  const double lam = pow(10.0, l10 < -12.0 ? -12.0 : (l10 > 2.0 ? 2.0 : l10));
+  *lambda = lam;
+  return TT_OK;
+}
+
+tt_status tt_plan_fallback_J(tt_plan p, double eps, double delta, int64_t* J) {
+  if (!p || !J) return tt_fail(TT_ERR_ARG, "null argument");
+  double m = 0.0;
+  for (int k = 0; k < p->d; ++k) {
+    double mk = 0.0;
+    tt_status st = tt_sketch_size_bound(p->r[k] * p->r[k + 1], p->d - 1, eps, delta, &mk);
+    if (st) return st;
+    if (mk > m) m = mk;
+  }
+  const double cap = (double)p->J_cap;
+  *J = tt_floor_smooth(m < cap ? (int64_t)ceil(m) : p->J_cap);
+  return TT_OK;
+}
+
+tt_status tt_als_run(tt_plan p, const void* X, void* const* cores, const float* params, int32_t max_sweeps, double target,
+                     int64_t J_min, double* residuals, int64_t* Js, double* lambdas, tt_run_stats* stats) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (!X || !stats) return tt_fail(TT_ERR_ARG, "null argument");
+  if (max_sweeps < 1) return tt_fail(TT_ERR_ARG, "max_sweeps must be >= 1");
+  if ((st = check_cores(p, cores))) return st;
+  stats->sweeps = 0;
+  stats->reached = 0;
+  stats->fallbacks = 0;
+  stats->residual = 1.0;
+  double prev = 1.0, drop = 0.0;
+  bool fallback = false;
+  for (int32_t t = 0; t < max_sweeps; ++t) {
+    if (params) {
+      int64_t J = p->J;
+      double lam = p->lambda;
+      if (fallback) {
+        if ((st = tt_plan_fallback_J(p, 0.5, 0.1, &J))) return st;
+        lam = p->lambda0;
+        stats->fallbacks += 1;
+      } else if ((st = tt_jpolicy_choose(p, params, t, t == 0 ? 0.0 : drop, J_min, &J, &lam))) {
+        return st;
+      }
+      if (J != p->J || lam != p->lambda)
+        if ((st = tt_plan_set_sketch(p, J, lam))) return st;
+    }
+    if (Js) Js[t] = p->J;
+    if (lambdas) lambdas[t] = p->lambda;
+    double res = 0.0;
+    if ((st = tt_als_sweep(p, X, cores, &res))) return st;
+    if (residuals) residuals[t] = res;
+    stats->sweeps = t + 1;
+    stats->residual = res;
+    drop = log10(prev / res);
+    // the residual check: a sweep that does not lower the residual sends the
+    // next one to the fallback size
+    fallback = params && !(res < prev);
+    prev = res;
+    if (res <= target) {
+      stats->reached = 1;
+      break;
+    }
   }
   return TT_OK;
 }

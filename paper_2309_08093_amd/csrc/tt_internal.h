@@ -25,6 +25,8 @@ struct tt_plan_s {
   hipStream_t side;            // plan-owned stream for the overlapped data sketches (lazy)
   hipStream_t chain;           // plan-owned stream for the rest of an overlapped sweep (lazy)
   hipEvent_t ev_fork, ev_join, ev_done, ev_y[TT_MAX_ORDER];
+  int64_t J_cap;               // J of the plan descriptor: workspace sized for it
+  double lambda0;              // lambda of the plan descriptor
   int32_t reserved_cus;        // CUs withheld from the side stream (its CU mask)
   int32_t sketch_cus;          // CUs a persistent sketch grid may fill on p->stream (0: all)
   uint32_t flags;
@@ -52,7 +54,7 @@ struct tt_plan_s {
   void* prof;                  // ProfState* when measurement is enabled, else null
 
   size_t o_tab, o_KI, o_KO, o_cnt, o_cursor, o_sortO, o_part, o_chat, o_pre, o_suf, o_SH, o_Y,
-      o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_fkeys, o_fsort;
+      o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_fkeys, o_fsort, o_pol;
   int64_t max_F;               // largest fibre count of one column over k >= 1
 
   template <typename T>
@@ -128,3 +130,8 @@ inline hipError_t tt_allow_lds(K kernel, size_t bytes) {
 
 // FFT plan helper: factor J into radices {4,2,3,5,7}; returns false if J has other factors.
 bool tt_factor_fft(int64_t J, int* radix, int* nrad);
+
+// sketch-size policy (k_mlp.hip)
+hipError_t launch_mlp_forward(const float* params, const float* feats, int32_t B, float* out, hipStream_t stream);
+int64_t tt_round_smooth(double x, int64_t lo, int64_t hi);   // nearest 2^a 3^b 5^c 7^e in [lo, hi]
+int64_t tt_floor_smooth(int64_t x);                          // largest 2^a 3^b 5^c 7^e <= x

@@ -1,0 +1,252 @@
+"""Sketch-size policy: training data from the method's own runs, training on
+the GPU with the library's forward / backward / Adam kernels, and use.
+
+The network and its kernels are in the C ABI (tt_jpolicy_*, tt_als_run);
+this module marshals arrays and runs the label-collection loop, in which
+every sweep, residual and feature vector is computed by the library.
+
+Labels (one per sweep state of a run): starting from the same cores and the
+same sweep index, one sweep is run for every J of a geometric grid; the label
+J* is the smallest J whose residual drop log10(res_before / res_after) is at
+least (1 - tol) times the drop at the largest J.  At J* one sweep per lambda
+of a grid gives the label lambda* (largest drop), and the run continues from
+that sweep's cores.  The d feature rows of the state (one per core update)
+all carry the label (ln J* - 7, log10 lambda* + 3).
+"""
+import json
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import check
+
+_lib = _abi.load()
+
+F, H, O, P = _abi.JPOLICY_FEATURES, _abi.JPOLICY_HIDDEN, _abi.JPOLICY_OUTPUTS, _abi.JPOLICY_PARAMS
+
+
+def _ptr(t):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    import ctypes
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def init_params(seed):
+    """He-uniform weights, zero biases, in the C ABI's parameter layout."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for a, b in [(F, H), (H, H), (H, H), (H, O)]:
+        lim = math.sqrt(6.0 / a)
+        out.append(g.uniform(-lim, lim, size=(b, a)).reshape(-1))
+        out.append(np.zeros(b))
+    theta = np.concatenate(out).astype(np.float32)
+    assert theta.size == P
+    return theta
+
+
+def encode_targets(J, lam):
+    return np.array([math.log(J) - 7.0, math.log10(lam) + 3.0], dtype=np.float32)
+
+
+class Policy:
+    """Parameters on the device plus Adam moments."""
+
+    def __init__(self, params=None, device="cuda", seed=0):
+        self.device = torch.device(device)
+        theta = init_params(seed) if params is None else np.asarray(params, dtype=np.float32).reshape(-1)
+        if theta.size != P:
+            raise ValueError("policy needs %d parameters" % P)
+        self.params = torch.from_numpy(theta.copy()).to(self.device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        return cls(np.load(path, allow_pickle=False), device=device)
+
+    def save(self, path):
+        np.save(path, self.params.detach().cpu().numpy())
+
+    def _rows(self, A, width):
+        A = torch.as_tensor(A, dtype=torch.float32)
+        A = A.to(self.device).contiguous()
+        if A.dim() != 2 or A.shape[1] != width:
+            raise ValueError("expected B x %d rows" % width)
+        return A
+
+    def forward(self, feats):
+        X = self._rows(feats, F)
+        Y = torch.empty((X.shape[0], O), dtype=torch.float32, device=self.device)
+        check(_lib.tt_jpolicy_forward(_ptr(self.params), _ptr(X), X.shape[0], _ptr(Y), _stream(self.device)),
+              "tt_jpolicy_forward")
+        return Y
+
+    def loss_grad(self, feats, targets):
+        X = self._rows(feats, F)
+        T = self._rows(targets, O)
+        g = torch.empty_like(self.params)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        check(_lib.tt_jpolicy_loss_grad(_ptr(self.params), _ptr(X), _ptr(T), X.shape[0], _ptr(g), _ptr(loss),
+                                        _stream(self.device)), "tt_jpolicy_loss_grad")
+        return loss, g
+
+    def adam(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step += 1
+        check(_lib.tt_jpolicy_adam(_ptr(self.params), _ptr(self.m), _ptr(self.v), _ptr(grad), P, self.step, lr, beta1,
+                                   beta2, eps, _stream(self.device)), "tt_jpolicy_adam")
+
+    def fit(self, feats, targets, steps=3000, lr=1e-3, batch=256, seed=0, log_every=500, log=None):
+        """Minibatch Adam on the device.  Returns the loss every log_every steps."""
+        X = self._rows(feats, F)
+        T = self._rows(targets, O)
+        n = X.shape[0]
+        g = np.random.Generator(np.random.PCG64(seed))
+        hist = []
+        order = g.permutation(n)
+        pos = 0
+        for it in range(steps):
+            if pos + batch > n:
+                order = g.permutation(n)
+                pos = 0
+            idx = torch.from_numpy(order[pos:pos + batch].copy()).to(self.device)
+            pos += batch
+            loss, grad = self.loss_grad(X.index_select(0, idx), T.index_select(0, idx))
+            self.adam(grad, lr=lr)
+            if (it + 1) % log_every == 0 or it == 0:
+                hist.append((it + 1, float(loss.item())))
+                if log:
+                    log("[policy] step %d loss %.5f" % hist[-1])
+        return hist
+
+    def mse(self, feats, targets):
+        """Full-batch loss with the current parameters (chunks of 4096)."""
+        X = self._rows(feats, F)
+        T = self._rows(targets, O)
+        tot = 0.0
+        for a in range(0, X.shape[0], 4096):
+            loss, _ = self.loss_grad(X[a:a + 4096], T[a:a + 4096])
+            tot += float(loss.item()) * min(4096, X.shape[0] - a)
+        return tot / X.shape[0]
+
+
+def random_problem(g):
+    """Shape, ranks and relative noise of one training run: order 4-5, modes
+    in [30, 40], ranks U[2, 12] clipped to feasibility, noise log-uniform in
+    [1e-4, 1e-1] relative to the entry scale."""
+    import synth
+    d = int(g.integers(4, 6))
+    n = [int(x) for x in g.integers(30, 41, size=d)]
+    R = [1] + [int(x) for x in g.integers(2, 13, size=d - 1)] + [1]
+    R = synth.clip_ranks(n, R)
+    nu = float(10 ** g.uniform(-4, -1))
+    return n, R, nu
+
+
+def collect(n_tensors, seed, device="cuda", J_grid=(250, 500, 1000, 2000, 4000, 8000),
+            lam_grid=(1e-4, 1e-3, 1e-2, 1e-1), tol=0.1, sweeps=5, log=None):
+    """Labelled (features, targets) from n_tensors runs; see the module doc."""
+    import synth
+    from . import Plan, core_to_device
+    dev = torch.device(device)
+    g = np.random.Generator(np.random.PCG64(seed))
+    feats, targs, meta = [], [], []
+    Jmax = max(J_grid)
+    t0 = time.time()
+    for i in range(n_tensors):
+        n, R, nu = random_problem(g)
+        s_i = int(g.integers(1, 2 ** 31))
+        scale = math.sqrt(float(np.prod(R[1:-1])))
+        X, _ = synth.tt_tensor_device(n, R, nu * scale, s_i, dtype="f32", device=dev)
+        plan = Plan(n, R, Jmax, 1e-3, seed=s_i, x_dtype="f32", work_dtype="f32", device=dev)
+        cores = [core_to_device(c, dev) for c in synth.random_cores(n, R, s_i + 1)]
+        prev, last_drop = 1.0, 0.0
+        for t in range(sweeps):
+            state = [c.clone() for c in cores]
+
+            def trial(J, lam):
+                for c, s0 in zip(cores, state):
+                    c.copy_(s0)
+                plan.set_sweep(t)
+                plan.set_sketch(J, lam)
+                res = plan.als_sweep(X, cores, residual=True)
+                return math.log10(prev / res), res
+
+            drops = {J: trial(J, 1e-3)[0] for J in J_grid}
+            top = drops[Jmax]
+            Jstar = Jmax
+            if top > 0:
+                for J in sorted(J_grid):
+                    if drops[J] >= (1.0 - tol) * top:
+                        Jstar = J
+                        break
+            best = None
+            for lam in lam_grid:
+                dr, res = trial(Jstar, lam)
+                if best is None or dr > best[0]:
+                    best = (dr, res, lam, [c.clone() for c in cores])
+            dr, res, lam, cbest = best
+            F_rows = plan.features(t, last_drop)
+            feats.append(F_rows)
+            targs.append(np.repeat(encode_targets(Jstar, lam)[None, :], len(n), axis=0))
+            meta.append({"n": n, "R": R, "noise": nu, "t": t, "J": Jstar, "lambda": lam, "drops": drops,
+                         "res": res})
+            for c, cb in zip(cores, cbest):
+                c.copy_(cb)
+            last_drop, prev = dr, res
+        del X, plan, cores
+        if log and (i + 1) % 20 == 0:
+            log("[collect] %d/%d tensors, %d rows, %.0f s" % (i + 1, n_tensors, sum(len(f) for f in feats),
+                                                          time.time() - t0))
+    return np.concatenate(feats).astype(np.float32), np.concatenate(targs).astype(np.float32), meta
+
+
+def main():
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser(description="collect labels from method runs and train the sketch-size policy")
+    ap.add_argument("--tensors", type=int, default=400)
+    ap.add_argument("--sweeps", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=11)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--out", required=True, help="prefix of the weights (.npy) and summary (.json) files")
+    args = ap.parse_args()
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    X, T, meta = collect(args.tensors, args.seed, dev, sweeps=args.sweeps, log=log)
+    np.savez(args.out + "_data.npz", X=X, T=T)
+    g = np.random.Generator(np.random.PCG64(args.seed + 1))
+    perm = g.permutation(len(meta))
+    nval = max(1, len(meta) // 10)
+    d_of = [len(m["n"]) for m in meta]
+    starts = np.cumsum([0] + d_of)
+    rows = lambda ids: np.concatenate([np.arange(starts[i], starts[i + 1]) for i in ids])
+    val, tr = rows(perm[:nval]), rows(perm[nval:])
+    pol = Policy(seed=args.seed + 2, device=dev)
+    base = float(np.mean((T[val] - T[tr].mean(axis=0)) ** 2))
+    hist = pol.fit(X[tr], T[tr], steps=args.steps, lr=args.lr, seed=args.seed + 3, log=log)
+    summary = {"tensors": args.tensors, "rows": int(len(X)), "train_rows": int(len(tr)), "val_rows": int(len(val)),
+               "steps": args.steps, "lr": args.lr, "train_loss": hist, "val_mse": pol.mse(X[val], T[val]),
+               "val_mse_of_mean_predictor": base,
+               "label_J_counts": {str(J): int(sum(1 for m in meta if m["J"] == J)) for J in sorted({m["J"] for m in meta})},
+               "label_lambda_counts": {str(l): int(sum(1 for m in meta if m["lambda"] == l))
+                                       for l in sorted({m["lambda"] for m in meta})}}
+    pol.save(args.out + ".npy")
+    with open(args.out + ".json", "w") as f:
+        json.dump(summary, f, indent=1)
+    log(json.dumps({k: v for k, v in summary.items() if k != "train_loss"}))
+
+
+if __name__ == "__main__":
+    main()

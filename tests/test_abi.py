@@ -108,3 +108,57 @@ def test_package_import_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(A, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         A.load()
+
+
+def test_sketch_size_bound_matches_corollary3(abi):
+    from oracle import bound
+    lib = abi.load()
+    for s, q in [(1, 1), (9, 3), (100, 3), (144, 3), (64, 4)]:
+        m = ctypes.c_double()
+        assert lib.tt_sketch_size_bound(s, q, 0.5, 0.1, ctypes.byref(m)) == abi.TT_OK
+        assert m.value == pytest.approx(bound.cor3_sketch_size(s, q, 0.5, 0.1), rel=1e-12)
+    m = ctypes.c_double()
+    assert lib.tt_sketch_size_bound(0, 3, 0.5, 0.1, ctypes.byref(m)) == abi.TT_ERR_ARG
+    assert lib.tt_sketch_size_bound(4, 3, 0.5, 1.0, ctypes.byref(m)) == abi.TT_ERR_ARG
+
+
+def test_fallback_J_is_capped_bound(abi):
+    lib = abi.load()
+    J = ctypes.c_int64()
+    # 200^4 ranks 10: the bound (2.3e7) exceeds the plan's J, which caps it
+    st, h, _ = _plan(abi, [200] * 4, [1, 10, 10, 10, 1], J=4000)
+    assert lib.tt_plan_fallback_J(h, 0.5, 0.1, ctypes.byref(J)) == abi.TT_OK and J.value == 4000
+    lib.tt_plan_destroy(h)
+    # d = 2, ranks 1: s = 1, q = 1 -> max(8*5/0.1, 8*5/0.05) = 800 < J
+    st, h, _ = _plan(abi, [30, 40], [1, 1, 1], J=4096)
+    assert lib.tt_plan_fallback_J(h, 0.5, 0.1, ctypes.byref(J)) == abi.TT_OK and J.value == 800
+    lib.tt_plan_destroy(h)
+
+
+def test_policy_features_follow_the_header(abi):
+    import math
+    lib = abi.load()
+    n, r = [30, 35, 40, 33], [1, 4, 6, 5, 1]
+    st, h, _ = _plan(abi, n, r, J=2000)
+    out = (ctypes.c_float * (4 * 8))()
+    assert lib.tt_jpolicy_features(h, 3, 0.25, out) == abi.TT_OK
+    N = 30 * 35 * 40 * 33
+    for k in range(4):
+        want = [math.log(n[k]) / 4, math.log(r[k]) / 2, math.log(r[k + 1]) / 2, math.log(N / n[k]) / 16, 4 / 5,
+                k / 4, 0.3, 0.25]
+        assert list(out[8 * k:8 * k + 8]) == pytest.approx(want, rel=1e-6)
+    assert lib.tt_jpolicy_features(h, 0, 9.0, out) == abi.TT_OK and out[7] == 4.0     # clipped
+    lib.tt_plan_destroy(h)
+
+
+def test_set_sketch_validates(abi):
+    lib = abi.load()
+    st, h, _ = _plan(abi, [8, 8, 8], [1, 2, 2, 1], J=1000)
+    assert lib.tt_plan_set_sketch(h, 2000, 1e-3) == abi.TT_ERR_ARG       # above the plan's J
+    assert lib.tt_plan_set_sketch(h, 11 * 8, 1e-3) == abi.TT_ERR_ARG     # factor 11
+    assert lib.tt_plan_set_sketch(h, 500, -1.0) == abi.TT_ERR_ARG
+    assert lib.tt_plan_set_sketch(h, 500, 1e-2) == abi.TT_OK
+    J, lam = ctypes.c_int64(), ctypes.c_double()
+    assert lib.tt_plan_get_sketch(h, ctypes.byref(J), ctypes.byref(lam)) == abi.TT_OK
+    assert (J.value, lam.value) == (500, 1e-2)
+    lib.tt_plan_destroy(h)

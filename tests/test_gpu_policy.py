@@ -1,0 +1,165 @@
+"""GPU parity of the sketch-size policy kernels (forward, backpropagation,
+Adam) against the FP64 oracle, and of the policy-driven run loop."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+F, H, O = 8, 64, 2
+
+
+def say(msg):
+    print("[case] " + msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2309_08093_amd as tts
+    from paper_2309_08093_amd import jpolicy
+    return torch, tts, jpolicy
+
+
+def rand_inputs(seed, B, scale=1.0):
+    g = np.random.default_rng(seed)
+    return (g.standard_normal((B, F)) * scale).astype(np.float32), g.standard_normal((B, O)).astype(np.float32)
+
+
+@pytest.mark.parametrize("B", [1, 63, 64, 200, 1000])
+def test_forward_matches_oracle(env, B):
+    torch, tts, jpolicy = env
+    say("forward B=%d" % B)
+    pol = jpolicy.Policy(seed=B)
+    X, _ = rand_inputs(B + 1, B)
+    Y = pol.forward(X).cpu().numpy()
+    theta = pol.params.cpu().numpy().astype(np.float64)
+    Yo, _ = mlp.forward(theta, X.astype(np.float64), F, H, O)
+    assert np.linalg.norm(Y - Yo) <= 1e-5 * np.linalg.norm(Yo)
+
+
+@pytest.mark.parametrize("B", [1, 64, 130, 4096])
+def test_gradient_matches_oracle(env, B):
+    torch, tts, jpolicy = env
+    say("loss_grad B=%d" % B)
+    pol = jpolicy.Policy(seed=3 * B)
+    X, T = rand_inputs(B + 7, B)
+    loss, g = pol.loss_grad(X, T)
+    theta = pol.params.cpu().numpy().astype(np.float64)
+    Lo, go = mlp.loss_grad(theta, X.astype(np.float64), T.astype(np.float64), F, H, O)
+    g = g.cpu().numpy()
+    assert float(loss.item()) == pytest.approx(Lo, rel=1e-5)
+    assert np.linalg.norm(g - go) <= 1e-5 * np.linalg.norm(go)
+    # every layer, not only the norm-dominant ones
+    off = 0
+    for a, b in mlp.layer_sizes(F, H, O):
+        sl = slice(off, off + a * b + b)
+        assert np.linalg.norm(g[sl] - go[sl]) <= 2e-5 * np.linalg.norm(go[sl]) + 1e-12
+        off += a * b + b
+
+
+def test_adam_matches_oracle(env):
+    torch, tts, jpolicy = env
+    say("adam 3 steps")
+    pol = jpolicy.Policy(seed=5)
+    theta = pol.params.cpu().numpy().astype(np.float64)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    g = np.random.default_rng(6)
+    for step in range(1, 4):
+        gr = (g.standard_normal(theta.size) * 10 ** g.uniform(-4, 0, theta.size)).astype(np.float32)
+        pol.adam(torch.from_numpy(gr).cuda(), lr=1e-2)
+        theta, m, v = mlp.adam_step(theta, m, v, gr.astype(np.float64), step, 1e-2)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(pol.params.cpu().numpy(), theta, rtol=1e-5, atol=1e-6)
+    # m is a short FP32 recurrence over gradients of both signs: near zero its
+    # error is absolute, of the order of the FP32 rounding of |g| <= ~4
+    np.testing.assert_allclose(pol.m.cpu().numpy(), m, rtol=1e-5, atol=4e-7)
+
+
+def test_training_on_gpu_reduces_loss(env):
+    torch, tts, jpolicy = env
+    say("fit affine target")
+    g = np.random.default_rng(9)
+    X = g.standard_normal((2048, F)).astype(np.float32)
+    A = g.standard_normal((O, F))
+    T = (X @ A.T + 0.3).astype(np.float32)
+    pol = jpolicy.Policy(seed=10)
+    L0 = pol.mse(X, T)
+    pol.fit(X, T, steps=600, lr=3e-3, batch=256, seed=1)
+    assert pol.mse(X, T) < 0.02 * L0
+
+
+def test_choose_decodes_outputs(env):
+    """All weights zero: the output is the last bias, so J = exp(b0 + 7)
+    rounded to a 2-3-5-7 number and lambda = 10^(b1 - 3)."""
+    torch, tts, jpolicy = env
+    say("choose")
+    theta = np.zeros(jpolicy.P, dtype=np.float32)
+    theta[-2] = math.log(1990.0) - 7.0
+    theta[-1] = math.log10(2e-2) + 3.0
+    pol = jpolicy.Policy(theta)
+    plan = tts.Plan([12, 10, 9, 11], [1, 3, 4, 3, 1], 4000, 1e-3, seed=1)
+    J, lam = plan.choose(pol.params, 2, 0.5, J_min=64)
+    assert J == 2000 and lam == pytest.approx(2e-2, rel=1e-5)
+    theta[-2] = math.log(20.0) - 7.0
+    J, _ = plan.choose(jpolicy.Policy(theta).params, 0, 0.0, J_min=100)
+    assert J == 100
+    theta[-2] = 20.0
+    J, _ = plan.choose(jpolicy.Policy(theta).params, 0, 0.0, J_min=64)
+    assert J == 4000
+
+
+def _problem(torch, tts, n, R, noise, seed, J, lam=1e-3):
+    import synth
+    dev = torch.device("cuda:0")
+    X, _ = synth.tt_tensor_device(n, R, noise, seed, dtype="f32", device=dev)
+    plan = tts.Plan(n, R, J, lam, seed=seed, x_dtype="f32", work_dtype="f32", device=dev)
+    cores = [tts.core_to_device(c, dev) for c in synth.random_cores(n, R, seed + 1)]
+    return X, plan, cores
+
+
+def test_run_without_policy_equals_sweeps(env):
+    torch, tts, jpolicy = env
+    say("run fixed J vs sweeps")
+    n, R = [20, 22, 18, 21], [1, 4, 5, 4, 1]
+    X, plan, cores = _problem(torch, tts, n, R, 1e-3, 21, 500)
+    out = plan.run(X, cores, 4, 0.0)
+    X2, plan2, cores2 = _problem(torch, tts, n, R, 1e-3, 21, 500)
+    res = [plan2.als_sweep(X2, cores2, residual=True) for _ in range(4)]
+    assert out["sweeps"] == 4 and not out["reached"] and out["fallbacks"] == 0
+    # the same arithmetic, up to the order of LDS atomic adds (FP32 rounding)
+    np.testing.assert_allclose(out["residuals"], res, rtol=1e-5)
+    assert out["J"] == [500] * 4
+
+
+def test_run_with_policy_follows_its_rules(env):
+    """Each sweep's J is a 2-3-5-7 number in [J_min, plan J]; a sweep that
+    did not lower the residual is followed by the Corollary 3 fallback size
+    (capped) with the descriptor's lambda; the run stops at the target."""
+    torch, tts, jpolicy = env
+    say("run with policy")
+    n, R = [24, 20, 22, 18], [1, 5, 6, 5, 1]
+    X, plan, cores = _problem(torch, tts, n, R, 1e-3, 31, 4000)
+    pol = jpolicy.Policy(seed=4)
+    out = plan.run(X, cores, 8, 1e-2, params=pol.params, J_min=64)
+    fb = plan.fallback_J()
+    res = out["residuals"]
+    nfb = 0
+    for t in range(out["sweeps"]):
+        J = out["J"][t]
+        x = J
+        for q in (2, 3, 5, 7):
+            while x % q == 0:
+                x //= q
+        assert x == 1 and 64 <= J <= 4000
+        if t > 0 and not (res[t - 1] < (res[t - 2] if t >= 2 else 1.0)):
+            assert J == fb and out["lambda"][t] == 1e-3
+            nfb += 1
+    assert nfb == out["fallbacks"]
+    assert out["reached"] == (out["residuals"][-1] <= 1e-2)
+    if out["reached"]:
+        assert all(r > 1e-2 for r in out["residuals"][:-1])
