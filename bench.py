@@ -67,6 +67,104 @@ def cpu_baseline(X, cfg, plan, budget_entries):
                       % (len(n), len(n) - 1, ns, Xs.size, dt)}
 
 
+POLICY_WEIGHTS = os.path.join(ROOT, "paper_2309_08093_amd", "jpolicy_weights.npy")
+
+
+def timed_plain(plan, X, cores, target, max_sweeps):
+    """Fixed J and lambda: sweeps timed with events on the plan's stream, the
+    exact residual checked after each sweep outside the timed region."""
+    import torch
+    stream = plan.stream
+    t_ms, hist = 0.0, []
+    for _ in range(max_sweeps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.als_sweep(X, cores)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_ms += e0.elapsed_time(e1)
+        hist.append(plan.residual(X, cores))
+        if hist[-1] <= target:
+            break
+    return {"seconds": t_ms * 1e-3, "sweeps": len(hist), "residuals": hist, "reached": bool(hist[-1] <= target)}
+
+
+def timed_learned(plan, X, cores, params, target, max_sweeps, ref_plan=None, X_ref=None, J_min=256):
+    """Policy-driven run (tt_als_run): the residual check after each sweep is
+    a policy input, so the whole call, checks included, is timed."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = plan.run(X, cores, max_sweeps, target, params=params, J_min=J_min)
+    torch.cuda.synchronize()
+    out["seconds"] = time.perf_counter() - t0
+    if ref_plan is not None:
+        out["residual_vs_fp32_data"] = ref_plan.residual(X_ref, cores)
+    return out
+
+
+def compare_forms(seed, dev, log):
+    """Time to a target relative residual: plain FP32 at fixed J vs mixed
+    precision (BF16 X, BF16 MFMA Gram) with the learned sketch-size policy."""
+    import numpy as np
+    import torch
+    import paper_2309_08093_amd as tts
+    from paper_2309_08093_amd import jpolicy
+    import synth
+    if not os.path.exists(POLICY_WEIGHTS):
+        return {"error": "no trained policy weights at %s" % POLICY_WEIGHTS}
+    pol = jpolicy.Policy.load(POLICY_WEIGHTS, device=dev)
+    out = {}
+    # 64^5 random TT, ranks 8, noise 1e-3: FP32 twin vs BF16 storage
+    n, R = [64] * 5, [1, 8, 8, 8, 8, 1]
+    log("[bench] compare on 64^5: plain FP32 J=3000 vs mixed + learned J")
+    X32, _ = synth.tt_tensor_device(n, R, 1e-3, seed, dtype="f32", device=dev)
+    X16 = X32.to(torch.bfloat16)
+    init = synth.random_cores(n, R, seed + 1)
+    p32 = tts.Plan(n, R, 3000, 1e-3, seed=seed, x_dtype="f32", work_dtype="f32", device=dev)
+    c = [tts.core_to_device(x, dev) for x in init]
+    plain = timed_plain(p32, X32, c, 1e-2, 30)
+    p16 = tts.Plan(n, R, 8000, 1e-3, seed=seed, x_dtype="bf16", work_dtype="f32", gram="bf16", device=dev)
+    c = [tts.core_to_device(x, dev) for x in init]
+    p32.set_sweep(0)
+    mixed = timed_learned(p16, X16, c, pol.params, 1e-2, 30, ref_plan=p32, X_ref=X32)
+    out["tt_64x5_r8"] = {"target": 1e-2, "plain_fp32_J3000": plain, "mixed_bf16_learned": mixed,
+                         "speedup": plain["seconds"] / mixed["seconds"] if mixed.get("reached") else None}
+    del X32, X16, p32, p16
+    torch.cuda.empty_cache()
+    # video-shaped smooth tensor 240x320x3x100, ranks 12: the 1e-2 noise is a
+    # relative floor of 0.032 and rank-12 truncation leaves 0.085 (TT-SVD), so
+    # the target is 0.1
+    n, R = [240, 320, 3, 100], [1, 12, 12, 12, 1]
+    tgt = 0.1
+    log("[bench] compare on 240x320x3x100: plain FP32 fixed J grid vs mixed + learned J")
+    Xh = synth.sinusoid_tensor_host(n, 20, 1e-2, seed)
+    X32 = torch.from_numpy(Xh).to(dev, torch.float32)
+    X16 = torch.from_numpy(Xh).to(dev).to(torch.bfloat16)
+    del Xh
+    init = synth.random_cores(n, R, seed + 3)
+    grid = {}
+    for J in (500, 1000, 2000, 3000, 4000, 8000):
+        p = tts.Plan(n, R, J, 1e-3, seed=seed, x_dtype="f32", work_dtype="f32", device=dev)
+        c = [tts.core_to_device(x, dev) for x in init]
+        grid[J] = timed_plain(p, X32, c, tgt, 30)
+        del p
+    reached = {J: r["seconds"] for J, r in grid.items() if r["reached"]}
+    bestJ = min(reached, key=reached.get) if reached else None
+    p16 = tts.Plan(n, R, 8000, 1e-3, seed=seed, x_dtype="bf16", work_dtype="f32", gram="bf16", device=dev)
+    pref = tts.Plan(n, R, 3000, 1e-3, seed=seed, x_dtype="f32", work_dtype="f32", device=dev)
+    c = [tts.core_to_device(x, dev) for x in init]
+    mixed = timed_learned(p16, X16, c, pol.params, tgt, 30, ref_plan=pref, X_ref=X32)
+    out["video_240x320x3x100_r12"] = {
+        "target": tgt, "plain_fp32": {str(J): r for J, r in grid.items()}, "plain_best_J": bestJ,
+        "mixed_bf16_learned": mixed,
+        "speedup_vs_J3000": grid[3000]["seconds"] / mixed["seconds"] if grid[3000]["reached"] and mixed["reached"]
+        else None,
+        "speedup_vs_best_fixed_J": reached[bestJ] / mixed["seconds"] if bestJ and mixed["reached"] else None}
+    return out
+
+
 def source_digest():
     """sha256 of the data-sketch kernel source: a stored counter reading is
     used only while the kernel it was taken from is unchanged."""
@@ -122,6 +220,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2023)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-time-to-target", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the mixed + learned-J vs plain FP32 time-to-target comparison")
     ap.add_argument("--cpu-entries", type=int, default=128_000_000)
     ap.add_argument("--serial", action="store_true",
                     help="keep the data sketches on the plan's stream (no overlap with the solve chain)")
@@ -267,6 +367,10 @@ def main():
         out["time_to_rel_residual_1e-2"] = {"form": "plain " + cfg["xd"], "seconds": t_ms * 1e-3,
                                             "sweeps": len(hist), "residuals": hist,
                                             "reached": bool(hist and hist[-1] <= 1e-2)}
+
+    if not args.no_compare:
+        out["mixed_learned_vs_plain"] = compare_forms(args.seed, dev,
+                                                      lambda m: print(m, file=sys.stderr, flush=True))
 
     if not args.no_cpu_baseline:
         print("[bench] CPU baseline (oracle)", file=sys.stderr, flush=True)

@@ -313,6 +313,50 @@ tt_status tt_als_run(tt_plan plan, const void* X, void* const* cores, const floa
                      double target, int64_t J_min, double* residuals, int64_t* Js, double* lambdas,
                      tt_run_stats* stats);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent problems of uneven shapes and ranks advance
+ * together.  Each problem is described by its own tt_plan_desc (FP32 X, FP32
+ * work, TT_GRAM_WORK; n_0 <= 256; any order, ranks, J, lambda, seed).  A
+ * sweep runs step k = 0, 1, ... for all problems of order > k: per-problem
+ * interface sketches and core updates, and ONE persistent data-sketch launch
+ * covering every participating problem.  The whole sweep can be captured into
+ * a hipGraph (tt_batch_set_graph) and replayed; tables then follow a device
+ * sweep counter.  The batch owns one plan per problem; all device memory is
+ * one caller workspace.
+ * ---------------------------------------------------------------------- */
+#define TT_BATCH_MAX 4096
+typedef struct tt_batch_s* tt_batch;
+
+/* descs: count descriptors (host).  Reports the workspace size. */
+tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stream, size_t* workspace_bytes,
+                        tt_batch* out);
+tt_status tt_batch_bind_workspace(tt_batch batch, void* dev_workspace, size_t bytes);
+tt_status tt_batch_destroy(tt_batch batch);
+
+/* The plan of problem i, owned by the batch (for queries such as
+ * tt_plan_get_tables; do not destroy it, rebind it or change its sweep). */
+tt_status tt_batch_get_plan(tt_batch batch, int32_t i, tt_plan* plan);
+
+/* Capture sweeps into a hipGraph (enable = 1) or enqueue them directly (0).
+ * A graph is re-captured when the X or core pointers change. */
+tt_status tt_batch_set_graph(tt_batch batch, int32_t enable);
+
+/* The batched data sketch of step k alone: Y[i] (J_i x n_k, column-major,
+ * FP32, device) for every problem of order > k; Y[i] of the others is not
+ * touched.  X: count device pointers. */
+tt_status tt_batch_sketch_tensor(tt_batch batch, const void* const* X, int32_t k, void* const* Y);
+
+/* One sweep of every problem.  X: count device pointers; cores: count host
+ * arrays of d_i device core pointers.  residuals: NULL, or count host doubles
+ * receiving each problem's exact relative residual (synchronises). */
+tt_status tt_batch_sweep(tt_batch batch, const void* const* X, void* const* const* cores, double* residuals);
+
+/* Autotuner: time the k >= 1 data-sketch launch of every step with workgroup
+ * counts of 1/2, 1, 2 and 4 times the device occupancy (reps launches each)
+ * and keep the fastest.  chosen: NULL or host int64 array of max order
+ * entries receiving the choice per step (0 for k = 0). */
+tt_status tt_batch_autotune(tt_batch batch, const void* const* X, int32_t reps, int64_t* chosen);
+
 #ifdef __cplusplus
 }
 #endif

@@ -282,6 +282,119 @@ class Plan:
         check(_lib.tt_plan_sync_status(self._h), "tt_plan_sync_status")
 
 
+class Batch:
+    """Many independent problems advanced together (tt_batch_*).  problems:
+    list of dicts with keys n, ranks, J, lam, seed; FP32 X and work."""
+
+    def __init__(self, problems, device="cuda", stream=None):
+        self.device = torch.device(device)
+        self.problems = [dict(p) for p in problems]
+        self.count = len(problems)
+        self._keep = []
+        descs = (_abi.PlanDesc * self.count)()
+        for i, pr in enumerate(self.problems):
+            n = (ctypes.c_int64 * len(pr["n"]))(*pr["n"])
+            r = (ctypes.c_int64 * len(pr["ranks"]))(*pr["ranks"])
+            self._keep += [n, r]
+            descs[i] = _abi.PlanDesc(len(pr["n"]), n, r, int(pr["J"]), float(pr.get("lam", 1e-3)),
+                                     int(pr.get("seed", i)) & (2 ** 64 - 1), _abi.TT_F32, _abi.TT_F32,
+                                     _abi.TT_GRAM_WORK, 0)
+        self._descs = descs
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        ws = ctypes.c_size_t(0)
+        h = ctypes.c_void_p()
+        check(_lib.tt_batch_plan(self.count, ctypes.cast(descs, ctypes.c_void_p), ctypes.c_void_p(stream.cuda_stream),
+                                 ctypes.byref(ws), ctypes.byref(h)), "tt_batch_plan")
+        self._h = h
+        self.workspace_bytes = ws.value
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.workspace.data_ptr() + 255) & ~255
+        check(_lib.tt_batch_bind_workspace(self._h, ctypes.c_void_p(aligned), self.workspace_bytes),
+              "tt_batch_bind_workspace")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.tt_batch_destroy(h)
+            self._h = None
+
+    def _xs(self, Xs):
+        if len(Xs) != self.count:
+            raise ValueError("need %d tensors" % self.count)
+        for X, pr in zip(Xs, self.problems):
+            if not (isinstance(X, torch.Tensor) and X.device.type == "cuda" and X.is_contiguous()
+                    and X.dtype == torch.float32 and X.numel() == int(np.prod(pr["n"]))):
+                raise ValueError("each X must be a contiguous float32 device tensor of its problem's size")
+        return _abi.ptr_array([X.data_ptr() for X in Xs])
+
+    def _cores(self, cores):
+        if len(cores) != self.count:
+            raise ValueError("need %d core lists" % self.count)
+        inner, keep = [], []
+        for cs, pr in zip(cores, self.problems):
+            n, R = pr["n"], pr["ranks"]
+            if len(cs) != len(n):
+                raise ValueError("core list of the wrong length")
+            for k, G in enumerate(cs):
+                if not (isinstance(G, torch.Tensor) and G.dtype == torch.float64 and G.is_contiguous()
+                        and G.numel() == R[k] * n[k] * R[k + 1] and G.device.type == "cuda"):
+                    raise ValueError("core %d must be a contiguous float64 device tensor" % k)
+            arr, a = _abi.ptr_array([G.data_ptr() for G in cs])
+            inner.append(arr)
+            keep.append(a)
+        outer = (ctypes.POINTER(ctypes.c_void_p) * self.count)(*inner)
+        return ctypes.cast(outer, ctypes.c_void_p), (outer, keep)
+
+    def plan_tables(self, i, s):
+        """(h, v) of problem i, mode s (host copies)."""
+        ph = ctypes.c_void_p()
+        check(_lib.tt_batch_get_plan(self._h, int(i), ctypes.byref(ph)), "tt_batch_get_plan")
+        ns = self.problems[i]["n"][s]
+        h = (ctypes.c_int32 * ns)()
+        v = (ctypes.c_int8 * ns)()
+        check(_lib.tt_plan_get_tables(ph, int(s), h, v), "tt_plan_get_tables")
+        return np.array(h, dtype=np.int64), np.array(v, dtype=np.int8)
+
+    def set_graph(self, enable=True):
+        check(_lib.tt_batch_set_graph(self._h, 1 if enable else 0), "tt_batch_set_graph")
+
+    def sketch_tensor(self, Xs, k):
+        """Batched data sketch of step k: list of J x n_k (flat, column-major)
+        FP32 tensors, None for problems of order <= k."""
+        xs, keep = self._xs(Xs)
+        Ys, ptrs = [], []
+        for pr in self.problems:
+            if len(pr["n"]) > k:
+                Y = torch.empty(int(pr["J"]) * pr["n"][k], dtype=torch.float32, device=self.device)
+                Ys.append(Y)
+                ptrs.append(Y.data_ptr())
+            else:
+                Ys.append(None)
+                ptrs.append(None)
+        ya, ykeep = _abi.ptr_array(ptrs)
+        check(_lib.tt_batch_sketch_tensor(self._h, xs, int(k), ya), "tt_batch_sketch_tensor")
+        return Ys
+
+    def sweep(self, Xs, cores, residuals=False):
+        xs, keep = self._xs(Xs)
+        cs, ckeep = self._cores(cores)
+        if residuals:
+            out = (ctypes.c_double * self.count)()
+            check(_lib.tt_batch_sweep(self._h, xs, cs, out), "tt_batch_sweep")
+            return list(out)
+        check(_lib.tt_batch_sweep(self._h, xs, cs, None), "tt_batch_sweep")
+        return None
+
+    def autotune(self, Xs, reps=3):
+        xs, keep = self._xs(Xs)
+        dmax = max(len(p["n"]) for p in self.problems)
+        out = (ctypes.c_int64 * dmax)()
+        check(_lib.tt_batch_autotune(self._h, xs, int(reps), out), "tt_batch_autotune")
+        return list(out)
+
+
 def sketch_size_bound(s, q, eps=0.5, delta=0.1):
     """Corollary 3 sketch size m for s unknowns per column and q sketched modes."""
     m = ctypes.c_double()
@@ -289,4 +402,4 @@ def sketch_size_bound(s, q, eps=0.5, delta=0.1):
     return m.value
 
 
-__all__ = ["Plan", "TTError", "core_to_device", "core_to_host", "version", "sketch_size_bound"]
+__all__ = ["Plan", "Batch", "TTError", "core_to_device", "core_to_host", "version", "sketch_size_bound"]

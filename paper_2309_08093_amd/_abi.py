@@ -68,6 +68,14 @@ SIGNATURES = {
     "tt_sketch_size_bound": [ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                              ctypes.POINTER(ctypes.c_double)],
     "tt_plan_fallback_J": [_vp, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)],
+    "tt_batch_plan": [ctypes.c_int32, _vp, _vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_vp)],
+    "tt_batch_bind_workspace": [_vp, _vp, ctypes.c_size_t],
+    "tt_batch_destroy": [_vp],
+    "tt_batch_get_plan": [_vp, ctypes.c_int32, ctypes.POINTER(_vp)],
+    "tt_batch_set_graph": [_vp, ctypes.c_int32],
+    "tt_batch_sketch_tensor": [_vp, _vpp, ctypes.c_int32, _vpp],
+    "tt_batch_sweep": [_vp, _vpp, _vp, ctypes.POINTER(ctypes.c_double)],
+    "tt_batch_autotune": [_vp, _vpp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)],
     "tt_als_run": [_vp, _vp, _vpp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
 }

@@ -86,6 +86,60 @@ tt_status tt_fail(tt_status st, const char* fmt, ...) {
   return st;
 }
 
+// ---------------------------------------------------------------- pieces of one sweep
+
+CoreDesc tt_make_desc(const tt_plan_s* p, const void* const* cores) { return make_desc(p, cores); }
+tt_status tt_plan_check(tt_plan p) { return check_plan(p); }
+
+// Right-to-left orthogonalisation of every core (Alg. 1 keeps the cores
+// right-orthogonal before each left-to-right pass), then the transformed
+// CountSketches of cores 1..d-1 (core 0 enters no interface sketch of k = 0
+// and is transformed after its own update).
+tt_status tt_sweep_begin(tt_plan p, double* const* G, const CoreDesc& cd) {
+  tt_status st;
+  for (int k = p->d - 1; k >= 1; --k)
+    if ((st = right_orth(p, G, k))) return st;
+  TTProfScope ps(p, TT_PROF_INTERFACE);
+  TT_HIP_TRY(launch_core_fft(p, cd, 0, p->d - 1, 0));
+  return TT_OK;
+}
+
+// Interface sketch SH_k (Theorems 1-2) into the plan's SH buffer.
+tt_status tt_sweep_interface(tt_plan p, const CoreDesc& cd, int k) {
+  TTProfScope ps(p, TT_PROF_INTERFACE);
+  TT_HIP_TRY(launch_interface_from_chat(p, cd, k, p->ws + p->o_SH));
+  return TT_OK;
+}
+
+// Core update k from SH_k and the data sketch Y: Gram / right-hand side, the
+// proximal solve in place, and for k < d-1 QR + absorb and the new transform
+// of core k.
+tt_status tt_sweep_update(tt_plan p, double* const* G, const CoreDesc& cd, int k, const void* Y) {
+  {
+    TTProfScope ps(p, TT_PROF_GRAM);
+    TT_HIP_TRY(launch_gram(p, k, p->ws + p->o_SH, Y));
+  }
+  {
+    TTProfScope ps(p, TT_PROF_SOLVE);
+    TT_HIP_TRY(launch_prox_from_gram(p, k, G[k], G[k]));
+  }
+  if (k < p->d - 1) {
+    tt_status st;
+    if ((st = left_orth(p, G, k))) return st;
+    TTProfScope ps(p, TT_PROF_INTERFACE);
+    TT_HIP_TRY(launch_core_fft(p, cd, k, k, -1));
+  }
+  return TT_OK;
+}
+
+// Advance the sweep index and draw the next sweep's tables (unless they are
+// overridden).
+tt_status tt_sweep_end(tt_plan p) {
+  p->sweep += 1;
+  if (!p->override_tables) return gen_tables(p);
+  return TT_OK;
+}
+
 extern "C" {
 
 const char* tt_last_error(void) { return g_err; }
@@ -134,6 +188,7 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   for (int k = 0; k <= d; ++k) p->r[k] = desc->r[k];
   p->J = desc->J;
   p->J_cap = desc->J;
+  p->dsweep = nullptr;
   p->lambda = desc->lambda;
   p->lambda0 = desc->lambda;
   p->seed = desc->seed;
@@ -507,7 +562,6 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
   double* const* G = reinterpret_cast<double* const*>(cores);
   const int d = p->d;
   const CoreDesc cd = make_desc(p, cores);
-  void* SH = p->ws + p->o_SH;
   void* Y = p->ws + p->o_Y;
   // The data sketches need only X and this sweep's tables (generated at bind,
   // set_sweep or the end of the previous sweep, or overridden), so they run
@@ -533,39 +587,16 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
     p->stream = p->chain;
     p->sketch_cus = 0;
   }
-  // 1. right-to-left orthogonalisation
-  for (int k = d - 1; k >= 1; --k)
-    if ((st = right_orth(p, G, k))) return st;
-  // transformed CountSketches of all cores (core 0 is not needed for k = 0)
-  {
-    TTProfScope ps(p, TT_PROF_INTERFACE);
-    TT_HIP_TRY(launch_core_fft(p, cd, 0, d - 1, 0));
-  }
+  if ((st = tt_sweep_begin(p, G, cd))) return st;
   for (int k = 0; k < d; ++k) {
-    {
-      TTProfScope ps(p, TT_PROF_INTERFACE);
-      TT_HIP_TRY(launch_interface_from_chat(p, cd, k, SH));
-    }
+    if ((st = tt_sweep_interface(p, cd, k))) return st;
     if (overlap) {
       Y = Yall + p->wsize() * p->J * p->tab_off[k];
       TT_HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_y[k], 0));
     } else {
       TT_HIP_TRY(launch_sketch_tensor(p, X, k, Y));
     }
-    {
-      TTProfScope ps(p, TT_PROF_GRAM);
-      TT_HIP_TRY(launch_gram(p, k, SH, Y));
-    }
-    {
-      TTProfScope ps(p, TT_PROF_SOLVE);
-      TT_HIP_TRY(launch_prox_from_gram(p, k, G[k], G[k]));
-    }
-    if (k < d - 1) {
-      if ((st = left_orth(p, G, k))) return st;
-      // core k changed (now Q); it enters every later prefix
-      TTProfScope ps(p, TT_PROF_INTERFACE);
-      TT_HIP_TRY(launch_core_fft(p, cd, k, k, -1));
-    }
+    if ((st = tt_sweep_update(p, G, cd, k, Y))) return st;
   }
   if (overlap) {
     TT_HIP_TRY(hipStreamWaitEvent(p->chain, p->ev_join, 0));
@@ -573,9 +604,7 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
     TT_HIP_TRY(hipStreamWaitEvent(p->user_stream, p->ev_done, 0));
     p->stream = p->user_stream;
   }
-  p->sweep += 1;
-  if (!p->override_tables)
-    if ((st = gen_tables(p))) return st;
+  if ((st = tt_sweep_end(p))) return st;
   if (rel_residual) {
     if ((st = residual_impl(p, X, cores, rel_residual))) return st;
     return tt_plan_sync_status(p);

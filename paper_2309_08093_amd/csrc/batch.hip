@@ -1,0 +1,695 @@
+// Batched form: many independent TT-TS problems of uneven shapes and ranks
+// advance together, one sweep step at a time.
+//
+// Each problem keeps its own plan (tables, cores, interface and solve
+// buffers) in a slice of one batch workspace.  Per step k of a sweep:
+//  * the interface sketches and core updates of all problems with order > k
+//    are enqueued per problem (short, latency-bound kernels);
+//  * the data sketches of all those problems are ONE persistent launch:
+//    - k >= 1: the fibres of every participating problem, problem by problem
+//      and column by column, form one sequence that is split into equal
+//      contiguous ranges, one per workgroup.  A workgroup accumulates the part
+//      of a column it holds in a J-entry FP64 LDS array (keys computed on the
+//      fly from the tables) and writes it as one partial of that column; a
+//      second launch adds the partials of each column in a fixed order;
+//    - k = 0: one workgroup per (problem, bucket) gathers the fibres hashed to
+//      the bucket from the problem's bucket-sorted list of outer tuples.
+// A whole sweep can be captured once into a hipGraph and replayed; the table
+// generator then reads the sweep index from a device counter that the graph
+// advances.  The workgroup count of each k >= 1 launch is chosen by
+// tt_batch_autotune from timed candidates.
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "tt_internal.h"
+
+namespace {
+
+struct BTensor {
+  const float* X;
+  float* Y;                  // the plan's Y buffer (J x n_k, column-major)
+  const uint32_t* tab;       // packed tables of all modes
+  const uint32_t* off;       // k = 0: bucket offsets of the outer tuples (J + 1)
+  const uint32_t* sorted;    // k = 0: outer tuples sorted by bucket
+  int32_t n[TT_MAX_ORDER];
+  int32_t toff[TT_MAX_ORDER];
+  int32_t d;
+  uint32_t J;
+};
+
+__device__ __forceinline__ uint32_t key_add(uint32_t a, uint32_t b, uint32_t J) {
+  uint32_t s = (a & TT_KEY_MASK) + (b & TT_KEY_MASK);
+  s = s >= J ? s - J : s;
+  return s | ((a ^ b) & TT_KEY_SIGN);
+}
+
+__device__ __forceinline__ double signed_f64(float x, uint32_t s) {
+  return (double)__uint_as_float(__float_as_uint(x) ^ s);
+}
+
+__device__ __forceinline__ int64_t owner(int64_t g, int64_t W, int64_t Ftot) { return ((g + 1) * W - 1) / Ftot; }
+
+// index of the segment of a non-decreasing prefix array (n + 1 entries) that holds g
+__device__ __forceinline__ int seg_of(const int64_t* pre, int n, int64_t g) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int lpf_log2_of(int n0) {
+  int l = 0;
+  while ((1 << l) < n0 && l < 6) ++l;
+  return l;
+}
+
+// ---------------------------------------------------------------- k >= 1
+template <int NJ>
+__global__ __launch_bounds__(256) void k_bsketch_k(const BTensor* __restrict__ T, const int32_t* __restrict__ tids,
+                                                   const int64_t* __restrict__ fpre, const int64_t* __restrict__ cpre,
+                                                   const int64_t* __restrict__ spre, int32_t nt, int32_t k,
+                                                   double* __restrict__ part, int32_t Jmax) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* acc = reinterpret_cast<double*>(smem_raw);
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int NW = blockDim.x >> 6;
+  const int64_t W = gridDim.x, w = blockIdx.x;
+  const int64_t Ttot = fpre[nt];
+  const int64_t gs = w * Ttot / W, ge = (w + 1) * Ttot / W;
+  if (gs >= ge) return;
+  int j = seg_of(fpre, nt, gs);
+  int64_t g = gs;
+  while (g < ge) {
+    while (fpre[j + 1] <= g) ++j;
+    const BTensor& t = T[tids[j]];
+    const int d = t.d, n0 = t.n[0], nk = t.n[k];
+    const uint32_t J = t.J;
+    int64_t M = 1, R = 1;
+    for (int s = 1; s < k; ++s) M *= t.n[s];
+    for (int s = k + 1; s < d; ++s) R *= t.n[s];
+    const int64_t F = M * R;
+    const int lpf_log2 = lpf_log2_of(n0);
+    const int LPF = 1 << lpf_log2, G = 64 >> lpf_log2;
+    const int gi = lane >> lpf_log2, v = lane & (LPF - 1);
+    uint32_t tb[NJ], ts[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+      const int i0 = v + LPF * q;
+      const uint32_t e = i0 < n0 ? t.tab[t.toff[0] + i0] : 0u;
+      tb[q] = e & TT_KEY_MASK;
+      ts[q] = e & TT_KEY_SIGN;
+    }
+    const int64_t q0 = g - fpre[j];
+    const int64_t c = q0 / F;
+    const int64_t qa = q0 - c * F;
+    const int64_t lim = ge - fpre[j] - c * F;
+    const int64_t qe = lim < F ? lim : F;
+    for (uint32_t b = threadIdx.x; b < J; b += blockDim.x) acc[b] = 0.0;
+    __syncthreads();
+    const int64_t wa = qa + (qe - qa) * wv / NW, we = qa + (qe - qa) * (wv + 1) / NW;
+    for (int64_t fb = wa; fb < we; fb += 64) {
+      // key and element offset of the next (up to) 64 fibres, one per lane
+      const int64_t fl = fb + lane;
+      uint32_t keyl = 0;
+      int64_t offl = 0;
+      if (fl < we) {
+        int64_t rho = fl / M, mu = fl - rho * M;
+        offl = ((rho * nk + c) * M + mu) * (int64_t)n0;
+        for (int s = 1; s < k; ++s) {
+          const int64_t i = mu % t.n[s];
+          mu /= t.n[s];
+          keyl = key_add(keyl, t.tab[t.toff[s] + i], J);
+        }
+        for (int s = k + 1; s < d; ++s) {
+          const int64_t i = rho % t.n[s];
+          rho /= t.n[s];
+          keyl = key_add(keyl, t.tab[t.toff[s] + i], J);
+        }
+      }
+      const int nb = (we - fb) < 64 ? (int)(we - fb) : 64;
+      for (int u0 = 0; u0 < nb; u0 += 4 * G) {
+        float x[4][NJ];
+        uint32_t kb[4], ks[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int idx = u0 + u * G + gi;
+          ok[u] = idx < nb;
+          const uint32_t key = (uint32_t)__shfl((int)keyl, idx & 63, 64);
+          kb[u] = key & TT_KEY_MASK;
+          ks[u] = key & TT_KEY_SIGN;
+          const int lo = __shfl((int)(uint32_t)(uint64_t)offl, idx & 63, 64);
+          const int hi = __shfl((int)(uint32_t)((uint64_t)offl >> 32), idx & 63, 64);
+          const int64_t off = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+#pragma unroll
+          for (int q = 0; q < NJ; ++q) {
+            const int i0 = v + LPF * q;
+            x[u][q] = (ok[u] && i0 < n0) ? __builtin_nontemporal_load(t.X + off + i0) : 0.0f;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int q = 0; q < NJ; ++q) {
+            const int i0 = v + LPF * q;
+            if (ok[u] && i0 < n0) {
+              uint32_t bk = tb[q] + kb[u];
+              bk = bk >= J ? bk - J : bk;
+              atomicAdd(&acc[bk], signed_f64(x[u][q], ts[q] ^ ks[u]));
+            }
+          }
+      }
+    }
+    __syncthreads();
+    const int64_t gc = cpre[j] + c;
+    const int64_t slot = w - owner(fpre[j] + c * F, W, Ttot);
+    double* out = part + (spre[gc] + slot) * (int64_t)Jmax;
+    for (uint32_t b = threadIdx.x; b < J; b += blockDim.x) out[b] = acc[b];
+    __syncthreads();
+    g = fpre[j] + c * F + qe;
+  }
+}
+
+// Y_j[b + J c] = sum over the partials of column (j, c), in slot order.
+__global__ void k_breduce(const BTensor* __restrict__ T, const int32_t* __restrict__ tids,
+                          const int64_t* __restrict__ fpre, const int64_t* __restrict__ cpre,
+                          const int64_t* __restrict__ spre, int32_t nt, int32_t k, const double* __restrict__ part,
+                          int32_t Jmax, int64_t W) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ncol = cpre[nt];
+  if (idx >= ncol * Jmax) return;
+  const int64_t gc = idx / Jmax;
+  const uint32_t b = (uint32_t)(idx - gc * Jmax);
+  const int j = seg_of(cpre, nt, gc);
+  const BTensor& t = T[tids[j]];
+  if (b >= t.J) return;
+  const int64_t c = gc - cpre[j];
+  int64_t F = 1;
+  for (int s = 1; s < t.d; ++s)
+    if (s != k) F *= t.n[s];
+  const int64_t Ttot = fpre[nt];
+  const int64_t first = fpre[j] + c * F;
+  const int64_t cnt = owner(first + F - 1, W, Ttot) - owner(first, W, Ttot) + 1;
+  const double* p = part + spre[gc] * (int64_t)Jmax + b;
+  double s = 0.0;
+  for (int64_t q = 0; q < cnt; ++q) s += p[q * Jmax];
+  t.Y[b + (int64_t)t.J * c] = (float)s;
+}
+
+// ---------------------------------------------------------------- k = 0
+template <int NJ>
+__global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T, const int32_t* __restrict__ tids,
+                                                   int32_t Jmax) {
+  __shared__ float red[4][64 * NJ];
+  const int j = blockIdx.x / Jmax;
+  const uint32_t b = blockIdx.x - (uint32_t)j * Jmax;
+  const BTensor& t = T[tids[j]];
+  if (b >= t.J) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, NW = blockDim.x >> 6;
+  const int n0 = t.n[0], n1 = t.n[1];
+  const uint32_t J = t.J;
+  const int lpf_log2 = lpf_log2_of(n0);
+  const int LPF = 1 << lpf_log2, G = 64 >> lpf_log2;
+  const int gi = lane >> lpf_log2, v = lane & (LPF - 1);
+  const uint32_t* tab1 = t.tab + t.toff[1];
+  float acc[NJ];
+#pragma unroll
+  for (int q = 0; q < NJ; ++q) acc[q] = 0.0f;
+  for (int i1 = wv; i1 < n1; i1 += NW) {
+    const uint32_t t1 = tab1[i1];
+    const uint32_t h1 = t1 & TT_KEY_MASK;
+    const uint32_t c = b >= h1 ? b - h1 : b + J - h1;
+    const uint32_t beg = t.off[c], end = t.off[c + 1];
+    for (uint32_t e0 = beg; e0 < end; e0 += 64) {
+      const uint32_t itl = (e0 + lane < end) ? t.sorted[e0 + lane] : 0u;
+      const int nb = (end - e0) < 64u ? (int)(end - e0) : 64;
+      for (int u0 = 0; u0 < nb; u0 += G) {
+        const int idx = u0 + gi;
+        const uint32_t item = (uint32_t)__shfl((int)itl, idx & 63, 64);
+        if (idx < nb) {
+          const uint32_t sg = (item ^ t1) & TT_KEY_SIGN;
+          const float* base = t.X + ((int64_t)(item & TT_KEY_MASK) * n1 + i1) * (int64_t)n0;
+#pragma unroll
+          for (int q = 0; q < NJ; ++q) {
+            const int i0 = v + LPF * q;
+            if (i0 < n0) acc[q] += __uint_as_float(__float_as_uint(__builtin_nontemporal_load(base + i0)) ^ sg);
+          }
+        }
+      }
+    }
+  }
+  for (int m = LPF; m < 64; m <<= 1)
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) acc[q] += __shfl_xor(acc[q], m, 64);
+  if (gi == 0)
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) red[wv][v + LPF * q] = acc[q];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n0; i += blockDim.x) {
+    float s = 0.0f;
+    for (int ww = 0; ww < NW; ++ww) s += red[ww][i];
+    t.Y[b + (int64_t)J * i] = s;
+  }
+}
+
+__global__ void k_set_i64(int64_t* p, int64_t v) {
+  if (threadIdx.x == 0) p[0] = v;
+}
+__global__ void k_inc_i64(int64_t* p) {
+  if (threadIdx.x == 0) p[0] += 1;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct tt_batch_s {
+  int32_t count = 0;
+  std::vector<tt_plan> plans;
+  std::vector<size_t> plan_off;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_need = 0;
+  int max_d = 0;
+  int32_t Jmax = 0;
+  int nj = 1;
+  // per step k
+  std::vector<std::vector<int32_t>> tids;
+  std::vector<std::vector<int64_t>> fpre, cpre, spre;
+  size_t o_desc = 0, o_part = 0, o_counter = 0;
+  size_t o_tids[TT_MAX_ORDER], o_fpre[TT_MAX_ORDER], o_cpre[TT_MAX_ORDER], o_spre[TT_MAX_ORDER];
+  int64_t Wmax = 8192;
+  int64_t W[TT_MAX_ORDER];   // workgroups of the k >= 1 launch (0: device occupancy)
+  // descriptors as last uploaded
+  std::vector<BTensor> host_desc;
+  bool desc_valid = false;
+  // graph
+  bool use_graph = false;
+  hipStream_t cap = nullptr;   // private stream the sweep is captured on
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> cap_ptrs;
+  int64_t replays = 0;
+};
+
+namespace {
+
+int occupancy_grid(int nj, int32_t Jmax) {
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    ncu = 256;
+  const size_t lds = sizeof(double) * Jmax;
+  hipError_t e = hipErrorInvalidValue;
+  if (nj == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_k<1>, 256, lds);
+  else if (nj == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_k<2>, 256, lds);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_k<4>, 256, lds);
+  if (e != hipSuccess || per < 1) per = 1;
+  return per * ncu;
+}
+
+std::vector<const void*> pointer_key(tt_batch b, const void* const* X, void* const* const* cores) {
+  std::vector<const void*> key;
+  for (int i = 0; i < b->count; ++i) {
+    key.push_back(X[i]);
+    for (int s = 0; s < b->plans[i]->d; ++s) key.push_back(cores[i][s]);
+  }
+  return key;
+}
+
+tt_status check_inputs(tt_batch b, const void* const* X, void* const* const* cores) {
+  if (!X || !cores) return tt_fail(TT_ERR_ARG, "null X or core arrays");
+  for (int i = 0; i < b->count; ++i) {
+    if (!X[i] || !cores[i]) return tt_fail(TT_ERR_ARG, "problem %d: null X or cores", i);
+    for (int s = 0; s < b->plans[i]->d; ++s)
+      if (!cores[i][s]) return tt_fail(TT_ERR_ARG, "problem %d: core %d is null", i, s);
+  }
+  return TT_OK;
+}
+
+// upload the per-problem descriptors (X pointers may change between calls)
+tt_status upload_desc(tt_batch b, const void* const* X) {
+  bool same = b->desc_valid;
+  for (int i = 0; i < b->count && same; ++i) same = b->host_desc[i].X == X[i];
+  if (same) return TT_OK;
+  for (int i = 0; i < b->count; ++i) {
+    tt_plan p = b->plans[i];
+    BTensor& t = b->host_desc[i];
+    t.X = static_cast<const float*>(X[i]);
+    t.Y = p->at<float>(p->o_Y);
+    t.tab = p->at<uint32_t>(p->o_tab);
+    t.off = p->at<uint32_t>(p->o_cnt);
+    t.sorted = p->at<uint32_t>(p->o_sortO);
+    for (int s = 0; s < TT_MAX_ORDER; ++s) {
+      t.n[s] = s < p->d ? (int32_t)p->n[s] : 1;
+      t.toff[s] = s < p->d ? (int32_t)p->tab_off[s] : 0;
+    }
+    t.d = p->d;
+    t.J = (uint32_t)p->J;
+  }
+  TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_desc, b->host_desc.data(), sizeof(BTensor) * b->count, hipMemcpyHostToDevice,
+                            b->stream));
+  TT_HIP_TRY(hipStreamSynchronize(b->stream));
+  b->desc_valid = true;
+  return TT_OK;
+}
+
+hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
+  const BTensor* T = reinterpret_cast<const BTensor*>(b->ws + b->o_desc);
+  const int32_t* tids = reinterpret_cast<const int32_t*>(b->ws + b->o_tids[k]);
+  const int32_t nt = (int32_t)b->tids[k].size();
+  if (nt == 0) return hipSuccess;
+  hipError_t e;
+  if (k == 0) {
+    for (int32_t j = 0; j < nt; ++j)
+      if ((e = launch_outer_sort(b->plans[b->tids[0][j]])) != hipSuccess) return e;
+    const dim3 grid((unsigned)(nt * b->Jmax));
+    if (b->nj == 1) hipLaunchKernelGGL(k_bsketch_0<1>, grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
+    else if (b->nj == 2) hipLaunchKernelGGL(k_bsketch_0<2>, grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
+    else hipLaunchKernelGGL(k_bsketch_0<4>, grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
+    return hipGetLastError();
+  }
+  const int64_t* fpre = reinterpret_cast<const int64_t*>(b->ws + b->o_fpre[k]);
+  const int64_t* cpre = reinterpret_cast<const int64_t*>(b->ws + b->o_cpre[k]);
+  const int64_t* spre = reinterpret_cast<const int64_t*>(b->ws + b->o_spre[k]);
+  double* part = reinterpret_cast<double*>(b->ws + b->o_part);
+  const int64_t Ttot = b->fpre[k].back();
+  int64_t W = Wk > 0 ? Wk : occupancy_grid(b->nj, b->Jmax);
+  if (W > b->Wmax) W = b->Wmax;
+  if (W > Ttot) W = Ttot;
+  if (W < 1) W = 1;
+  const size_t lds = sizeof(double) * b->Jmax;
+  if (b->nj == 1)
+    hipLaunchKernelGGL(k_bsketch_k<1>, dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre, cpre, spre, nt, k,
+                       part, b->Jmax);
+  else if (b->nj == 2)
+    hipLaunchKernelGGL(k_bsketch_k<2>, dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre, cpre, spre, nt, k,
+                       part, b->Jmax);
+  else
+    hipLaunchKernelGGL(k_bsketch_k<4>, dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre, cpre, spre, nt, k,
+                       part, b->Jmax);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int64_t total = b->cpre[k].back() * b->Jmax;
+  hipLaunchKernelGGL(k_breduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, b->stream, T, tids, fpre, cpre,
+                     spre, nt, k, part, b->Jmax, W);
+  return hipGetLastError();
+}
+
+// Enqueue one sweep of every problem on the batch stream.
+tt_status enqueue_sweep(tt_batch b, void* const* const* cores) {
+  std::vector<CoreDesc> cd(b->count);
+  tt_status st;
+  for (int i = 0; i < b->count; ++i) {
+    cd[i] = tt_make_desc(b->plans[i], cores[i]);
+    if ((st = tt_sweep_begin(b->plans[i], reinterpret_cast<double* const*>(cores[i]), cd[i]))) return st;
+  }
+  for (int k = 0; k < b->max_d; ++k) {
+    for (int32_t i : b->tids[k])
+      if ((st = tt_sweep_interface(b->plans[i], cd[i], k))) return st;
+    TT_HIP_TRY(launch_step_sketch(b, k, b->W[k]));
+    for (int32_t i : b->tids[k]) {
+      tt_plan p = b->plans[i];
+      if ((st = tt_sweep_update(p, reinterpret_cast<double* const*>(cores[i]), cd[i], k, p->ws + p->o_Y))) return st;
+    }
+  }
+  hipLaunchKernelGGL(k_inc_i64, dim3(1), dim3(64), 0, b->stream, reinterpret_cast<int64_t*>(b->ws + b->o_counter));
+  TT_HIP_TRY(hipGetLastError());
+  for (int i = 0; i < b->count; ++i)
+    if ((st = tt_sweep_end(b->plans[i]))) return st;
+  return TT_OK;
+}
+
+void drop_graph(tt_batch b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  b->cap_ptrs.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stream, size_t* workspace_bytes,
+                        tt_batch* out) {
+  if (!descs || !workspace_bytes || !out) return tt_fail(TT_ERR_ARG, "null argument");
+  if (count < 1 || count > TT_BATCH_MAX) return tt_fail(TT_ERR_ARG, "count=%d outside [1, %d]", count, TT_BATCH_MAX);
+  tt_batch b = new (std::nothrow) tt_batch_s();
+  if (!b) return tt_fail(TT_ERR_ARG, "out of host memory");
+  b->count = count;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  size_t o = 0;
+  int max_n0 = 1;
+  for (int i = 0; i < count; ++i) {
+    const tt_plan_desc& ds = descs[i];
+    if (ds.x_dtype != TT_F32 || ds.work_dtype != TT_F32 || ds.gram_mode != TT_GRAM_WORK) {
+      tt_batch_destroy(b);
+      return tt_fail(TT_ERR_ARG, "problem %d: the batched form takes FP32 X and FP32 work", i);
+    }
+    if (ds.d < 2 || !ds.n || ds.n[0] > 256) {
+      tt_batch_destroy(b);
+      return tt_fail(TT_ERR_SHAPE, "problem %d: the batched form needs d >= 2 and n_0 <= 256", i);
+    }
+    tt_plan_desc sd = ds;
+    sd.flags |= TT_FLAG_SERIAL;
+    size_t ws = 0;
+    tt_plan p = nullptr;
+    const tt_status st = tt_sketch_plan(&sd, hip_stream, &ws, &p);
+    if (st) {
+      tt_batch_destroy(b);
+      return st;
+    }
+    b->plans.push_back(p);
+    b->plan_off.push_back(o);
+    o = align256(o + ws);
+    if (p->d > b->max_d) b->max_d = p->d;
+    if (p->J > b->Jmax) b->Jmax = (int32_t)p->J;
+    if (p->n[0] > max_n0) max_n0 = (int)p->n[0];
+  }
+  b->nj = max_n0 <= 64 ? 1 : (max_n0 <= 128 ? 2 : 4);
+  // per-step work lists: problems of order > k, their fibre and column prefixes,
+  // and partial slots per column for the largest grid
+  b->tids.resize(b->max_d);
+  b->fpre.resize(b->max_d);
+  b->cpre.resize(b->max_d);
+  b->spre.resize(b->max_d);
+  size_t part_max = 1;
+  for (int k = 0; k < b->max_d; ++k) {
+    b->W[k] = 0;
+    b->fpre[k].push_back(0);
+    b->cpre[k].push_back(0);
+    for (int i = 0; i < count; ++i) {
+      tt_plan p = b->plans[i];
+      if (p->d <= k) continue;
+      b->tids[k].push_back(i);
+      b->fpre[k].push_back(b->fpre[k].back() + p->N / p->n[0]);
+      b->cpre[k].push_back(b->cpre[k].back() + p->n[k]);
+    }
+    const int64_t Ttot = b->fpre[k].back();
+    b->spre[k].push_back(0);
+    for (size_t j = 0; j < b->tids[k].size(); ++j) {
+      tt_plan p = b->plans[b->tids[k][j]];
+      const int64_t F = (p->N / p->n[0]) / (k == 0 ? 1 : p->n[k]);
+      // a column of F consecutive fibres meets at most floor((F - 1) W / T) + 2 ranges
+      const int64_t slots = (int64_t)(((__int128)(F - 1) * b->Wmax) / (Ttot > 0 ? Ttot : 1)) + 2;
+      for (int64_t c = 0; c < p->n[k]; ++c) b->spre[k].push_back(b->spre[k].back() + slots);
+    }
+    if (k >= 1 && (size_t)b->spre[k].back() > part_max) part_max = (size_t)b->spre[k].back();
+  }
+  b->o_desc = o;
+  o = align256(o + sizeof(BTensor) * count);
+  for (int k = 0; k < b->max_d; ++k) {
+    b->o_tids[k] = o;
+    o = align256(o + sizeof(int32_t) * (b->tids[k].size() + 1));
+    b->o_fpre[k] = o;
+    o = align256(o + sizeof(int64_t) * b->fpre[k].size());
+    b->o_cpre[k] = o;
+    o = align256(o + sizeof(int64_t) * b->cpre[k].size());
+    b->o_spre[k] = o;
+    o = align256(o + sizeof(int64_t) * b->spre[k].size());
+  }
+  b->o_part = o;
+  o = align256(o + sizeof(double) * part_max * b->Jmax);
+  b->o_counter = o;
+  o = align256(o + sizeof(int64_t));
+  b->ws_need = o;
+  b->host_desc.resize(count);
+  *workspace_bytes = o;
+  *out = b;
+  return TT_OK;
+}
+
+tt_status tt_batch_bind_workspace(tt_batch b, void* dev_ws, size_t bytes) {
+  if (!b || !dev_ws) return tt_fail(TT_ERR_ARG, "null argument");
+  if (bytes < b->ws_need) return tt_fail(TT_ERR_WORKSPACE, "workspace %zu bytes < required %zu", bytes, b->ws_need);
+  if (((uintptr_t)dev_ws & 255) != 0) return tt_fail(TT_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  b->ws = static_cast<char*>(dev_ws);
+  int64_t* counter = reinterpret_cast<int64_t*>(b->ws + b->o_counter);
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, b->stream, counter, (int64_t)0);
+  TT_HIP_TRY(hipGetLastError());
+  for (int i = 0; i < b->count; ++i) {
+    tt_plan p = b->plans[i];
+    p->dsweep = counter;
+    const tt_status st = tt_plan_bind_workspace(p, b->ws + b->plan_off[i], p->ws_need);
+    if (st) return st;
+  }
+  for (int k = 0; k < b->max_d; ++k) {
+    TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_tids[k], b->tids[k].data(), sizeof(int32_t) * b->tids[k].size(),
+                              hipMemcpyHostToDevice, b->stream));
+    TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_fpre[k], b->fpre[k].data(), sizeof(int64_t) * b->fpre[k].size(),
+                              hipMemcpyHostToDevice, b->stream));
+    TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_cpre[k], b->cpre[k].data(), sizeof(int64_t) * b->cpre[k].size(),
+                              hipMemcpyHostToDevice, b->stream));
+    TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_spre[k], b->spre[k].data(), sizeof(int64_t) * b->spre[k].size(),
+                              hipMemcpyHostToDevice, b->stream));
+  }
+  TT_HIP_TRY(hipStreamSynchronize(b->stream));
+  b->desc_valid = false;
+  drop_graph(b);
+  return TT_OK;
+}
+
+tt_status tt_batch_get_plan(tt_batch b, int32_t i, tt_plan* plan) {
+  if (!b || !plan) return tt_fail(TT_ERR_ARG, "null argument");
+  if (i < 0 || i >= b->count) return tt_fail(TT_ERR_ARG, "problem %d out of range", i);
+  *plan = b->plans[i];
+  return TT_OK;
+}
+
+tt_status tt_batch_set_graph(tt_batch b, int32_t enable) {
+  if (!b) return tt_fail(TT_ERR_ARG, "null batch");
+  drop_graph(b);
+  b->use_graph = enable != 0;
+  return TT_OK;
+}
+
+tt_status tt_batch_sketch_tensor(tt_batch b, const void* const* X, int32_t k, void* const* Y) {
+  if (!b || !X || !Y) return tt_fail(TT_ERR_ARG, "null argument");
+  if (!b->ws) return tt_fail(TT_ERR_WORKSPACE, "no workspace bound");
+  if (k < 0 || k >= b->max_d) return tt_fail(TT_ERR_ARG, "k=%d out of range", k);
+  for (int i = 0; i < b->count; ++i)
+    if (!X[i]) return tt_fail(TT_ERR_ARG, "problem %d: null X", i);
+  tt_status st;
+  if ((st = upload_desc(b, X))) return st;
+  TT_HIP_TRY(launch_step_sketch(b, k, b->W[k]));
+  for (int32_t i : b->tids[k]) {
+    tt_plan p = b->plans[i];
+    if (!Y[i]) return tt_fail(TT_ERR_ARG, "problem %d: null Y", i);
+    TT_HIP_TRY(hipMemcpyAsync(Y[i], p->ws + p->o_Y, sizeof(float) * p->J * p->n[k], hipMemcpyDeviceToDevice, b->stream));
+  }
+  return TT_OK;
+}
+
+tt_status tt_batch_sweep(tt_batch b, const void* const* X, void* const* const* cores, double* residuals) {
+  if (!b) return tt_fail(TT_ERR_ARG, "null batch");
+  if (!b->ws) return tt_fail(TT_ERR_WORKSPACE, "no workspace bound");
+  tt_status st;
+  if ((st = check_inputs(b, X, cores))) return st;
+  if ((st = upload_desc(b, X))) return st;
+  if (!b->use_graph) {
+    if ((st = enqueue_sweep(b, cores))) return st;
+  } else {
+    const std::vector<const void*> key = pointer_key(b, X, cores);
+    if (!b->exec || key != b->cap_ptrs) {
+      drop_graph(b);
+      // the caller's stream may be the legacy default stream, which cannot be
+      // captured: capture on a private stream, replay on the caller's
+      if (!b->cap) TT_HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+      // the capture must not start before work already queued for these buffers
+      TT_HIP_TRY(hipStreamSynchronize(b->stream));
+      const hipStream_t user = b->stream;
+      b->stream = b->cap;
+      for (tt_plan p : b->plans) p->stream = p->user_stream = b->cap;
+      hipGraph_t graph = nullptr;
+      hipError_t ce = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+      if (ce == hipSuccess) {
+        st = enqueue_sweep(b, cores);
+        ce = hipStreamEndCapture(b->cap, &graph);
+      }
+      b->stream = user;
+      for (tt_plan p : b->plans) p->stream = p->user_stream = user;
+      if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      if (ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return tt_fail(TT_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+      }
+      // capture enqueued nothing: the host sweep indices advanced once too many
+      for (int i = 0; i < b->count; ++i) b->plans[i]->sweep -= 1;
+      const hipError_t ie = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        b->exec = nullptr;
+        return tt_fail(TT_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+      }
+      b->cap_ptrs = key;
+    }
+    TT_HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    for (int i = 0; i < b->count; ++i) b->plans[i]->sweep += 1;
+    b->replays += 1;
+  }
+  if (residuals) {
+    for (int i = 0; i < b->count; ++i) {
+      if ((st = tt_residual(b->plans[i], X[i], cores[i], &residuals[i]))) return st;
+      if ((st = tt_plan_sync_status(b->plans[i]))) return st;
+    }
+  }
+  return TT_OK;
+}
+
+tt_status tt_batch_autotune(tt_batch b, const void* const* X, int32_t reps, int64_t* chosen) {
+  if (!b || !X) return tt_fail(TT_ERR_ARG, "null argument");
+  if (!b->ws) return tt_fail(TT_ERR_WORKSPACE, "no workspace bound");
+  if (reps < 1) reps = 1;
+  tt_status st;
+  if ((st = upload_desc(b, X))) return st;
+  const int64_t res = occupancy_grid(b->nj, b->Jmax);
+  const int64_t cand[4] = {res / 2, res, 2 * res, 4 * res};
+  hipEvent_t e0, e1;
+  TT_HIP_TRY(hipEventCreate(&e0));
+  TT_HIP_TRY(hipEventCreate(&e1));
+  for (int k = 1; k < b->max_d; ++k) {
+    if (b->tids[k].empty()) continue;
+    float best = 1e30f;
+    int64_t bestW = res;
+    for (int64_t W : cand) {
+      if (W < 1 || W > b->Wmax) continue;
+      TT_HIP_TRY(launch_step_sketch(b, k, W));   // warm
+      TT_HIP_TRY(hipEventRecord(e0, b->stream));
+      for (int r = 0; r < reps; ++r) TT_HIP_TRY(launch_step_sketch(b, k, W));
+      TT_HIP_TRY(hipEventRecord(e1, b->stream));
+      TT_HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      TT_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        bestW = W;
+      }
+    }
+    b->W[k] = bestW;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (chosen)
+    for (int k = 0; k < b->max_d; ++k) chosen[k] = b->W[k];
+  drop_graph(b);
+  return TT_OK;
+}
+
+tt_status tt_batch_destroy(tt_batch b) {
+  if (!b) return TT_OK;
+  drop_graph(b);
+  if (b->cap) {
+    (void)hipStreamSynchronize(b->cap);
+    (void)hipStreamDestroy(b->cap);
+  }
+  for (tt_plan p : b->plans) tt_plan_destroy(p);
+  delete b;
+  return TT_OK;
+}
+
+}  // extern "C"

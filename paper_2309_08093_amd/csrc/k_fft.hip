@@ -149,16 +149,21 @@ __global__ __launch_bounds__(256) void k_core_fft(CoreDesc cd, const uint32_t* _
   }
   const int r0 = cd.r0[i], ni = cd.n[i];
   const int aa = (int)(q % r0), cc = (int)(q / r0);
-  for (int s = threadIdx.x; s < J; s += blockDim.x) a[s] = cplx<T>{(T)0, (T)0};
+  // CountSketch of the column into J FP64 buckets (the FFT scratch buffer holds
+  // J doubles), so the result hardly depends on the order of the atomic adds
+  double* acc = reinterpret_cast<double*>(b);
+  for (int s = threadIdx.x; s < J; s += blockDim.x) acc[s] = 0.0;
   __syncthreads();
   const double* G = cd.G[i];
   const uint32_t* t = tab + cd.tab_off[i];
   for (int j = threadIdx.x; j < ni; j += blockDim.x) {
     const uint32_t key = t[j];
-    T val = (T)G[aa + (int64_t)r0 * (j + (int64_t)ni * cc)];
+    double val = G[aa + (int64_t)r0 * (j + (int64_t)ni * cc)];
     if (key & TT_KEY_SIGN) val = -val;
-    atomicAdd(&a[key & TT_KEY_MASK].x, val);
+    atomicAdd(&acc[key & TT_KEY_MASK], val);
   }
+  __syncthreads();
+  for (int s = threadIdx.x; s < J; s += blockDim.x) a[s] = cplx<T>{(T)acc[s], (T)0};
   __syncthreads();
   cplx<T>* res = fft_lds<T>(a, b, J, fp, (T)-1);
   cplx<T>* out = chat + (cd.chat_off[i] + q) * (int64_t)J;

@@ -26,6 +26,7 @@ struct tt_plan_s {
   hipStream_t chain;           // plan-owned stream for the rest of an overlapped sweep (lazy)
   hipEvent_t ev_fork, ev_join, ev_done, ev_y[TT_MAX_ORDER];
   int64_t J_cap;               // J of the plan descriptor: workspace sized for it
+  const int64_t* dsweep;       // device sweep counter read by the table generator (batched graphs), or null
   double lambda0;              // lambda of the plan descriptor
   int32_t reserved_cus;        // CUs withheld from the side stream (its CU mask)
   int32_t sketch_cus;          // CUs a persistent sketch grid may fill on p->stream (0: all)
@@ -130,6 +131,14 @@ inline hipError_t tt_allow_lds(K kernel, size_t bytes) {
 
 // FFT plan helper: factor J into radices {4,2,3,5,7}; returns false if J has other factors.
 bool tt_factor_fft(int64_t J, int* radix, int* nrad);
+
+// pieces of one sweep (api.hip), shared by tt_als_sweep and the batched driver
+CoreDesc tt_make_desc(const tt_plan_s* p, const void* const* cores);
+tt_status tt_sweep_begin(tt_plan p, double* const* G, const CoreDesc& cd);
+tt_status tt_sweep_interface(tt_plan p, const CoreDesc& cd, int k);
+tt_status tt_sweep_update(tt_plan p, double* const* G, const CoreDesc& cd, int k, const void* Y);
+tt_status tt_sweep_end(tt_plan p);
+tt_status tt_plan_check(tt_plan p);
 
 // sketch-size policy (k_mlp.hip)
 hipError_t launch_mlp_forward(const float* params, const float* feats, int32_t B, float* out, hipStream_t stream);
