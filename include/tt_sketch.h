@@ -256,6 +256,9 @@ const char* tt_version(void);
 #define TT_JPOLICY_OUTPUTS 2
 #define TT_JPOLICY_PARAMS 9026
 #define TT_JPOLICY_MAX_BATCH (1 << 20)
+/* tt_jpolicy_choose clamps log10 lambda to the range of the training labels */
+#define TT_JPOLICY_LOG10_LAMBDA_MIN (-4.0)
+#define TT_JPOLICY_LOG10_LAMBDA_MAX (-1.0)
 
 /* y = net(feats) for B samples (1 <= B <= TT_JPOLICY_MAX_BATCH); device
  * pointers; asynchronous on `stream`. */
@@ -281,7 +284,8 @@ tt_status tt_jpolicy_features(tt_plan plan, int64_t t, double last_drop, float* 
 /* Apply the network to the plan's d feature rows (in the plan's workspace, on
  * its stream; synchronises) and return the sweep's sketch size and lambda:
  * J = the largest of the d predictions, rounded to the nearest product of
- * 2, 3, 5, 7 in [J_min, plan J]; lambda = the prediction of that core. */
+ * 2, 3, 5, 7 in [J_min, plan J]; lambda = the prediction of that core,
+ * clamped to [10^TT_JPOLICY_LOG10_LAMBDA_MIN, 10^TT_JPOLICY_LOG10_LAMBDA_MAX]. */
 tt_status tt_jpolicy_choose(tt_plan plan, const float* params, int64_t t, double last_drop, int64_t J_min, int64_t* J,
                             double* lambda);
 
@@ -343,7 +347,8 @@ tt_status tt_batch_set_graph(tt_batch batch, int32_t enable);
 
 /* The batched data sketch of step k alone: Y[i] (J_i x n_k, column-major,
  * FP32, device) for every problem of order > k; Y[i] of the others is not
- * touched.  X: count device pointers. */
+ * touched.  X: count device pointers.  Y == NULL runs the launch only (the
+ * results stay in the problems' plans), e.g. to time it. */
 tt_status tt_batch_sketch_tensor(tt_batch batch, const void* const* X, int32_t k, void* const* Y);
 
 /* One sweep of every problem.  X: count device pointers; cores: count host

@@ -377,6 +377,11 @@ class Batch:
         check(_lib.tt_batch_sketch_tensor(self._h, xs, int(k), ya), "tt_batch_sketch_tensor")
         return Ys
 
+    def sketch_launch(self, Xs, k):
+        """The batched data-sketch launch of step k without copying results out."""
+        xs, keep = self._xs(Xs)
+        check(_lib.tt_batch_sketch_tensor(self._h, xs, int(k), None), "tt_batch_sketch_tensor")
+
     def sweep(self, Xs, cores, residuals=False):
         xs, keep = self._xs(Xs)
         cs, ckeep = self._cores(cores)

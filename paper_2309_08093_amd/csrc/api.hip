@@ -659,7 +659,9 @@ tt_status tt_jpolicy_choose(tt_plan p, const float* params, int64_t t, double la
   if (!isfinite(lnJ) || !isfinite(l10)) return tt_fail(TT_ERR_NONFINITE, "policy output is not finite");
   const int64_t lo = tt_floor_smooth(J_min) < J_min ? tt_round_smooth((double)J_min, J_min, p->J_cap) : J_min;
   *J = tt_round_smooth(exp(lnJ > 30.0 ? 30.0 : lnJ), lo, tt_floor_smooth(p->J_cap));
-  const double lam = pow(10.0, l10 < -12.0 ? -12.0 : (l10 > 2.0 ? 2.0 : l10));
+  // lambda stays within the range of the training labels
+  const double lam = pow(10.0, l10 < TT_JPOLICY_LOG10_LAMBDA_MIN ? TT_JPOLICY_LOG10_LAMBDA_MIN
+                                   : (l10 > TT_JPOLICY_LOG10_LAMBDA_MAX ? TT_JPOLICY_LOG10_LAMBDA_MAX : l10));
   *lambda = lam;
   return TT_OK;
 }

@@ -205,7 +205,7 @@ __global__ void k_breduce(const BTensor* __restrict__ T, const int32_t* __restri
 template <int NJ>
 __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T, const int32_t* __restrict__ tids,
                                                    int32_t Jmax) {
-  __shared__ float red[4][64 * NJ];
+  __shared__ double red[4][64 * NJ];
   const int j = blockIdx.x / Jmax;
   const uint32_t b = blockIdx.x - (uint32_t)j * Jmax;
   const BTensor& t = T[tids[j]];
@@ -217,9 +217,9 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
   const int LPF = 1 << lpf_log2, G = 64 >> lpf_log2;
   const int gi = lane >> lpf_log2, v = lane & (LPF - 1);
   const uint32_t* tab1 = t.tab + t.toff[1];
-  float acc[NJ];
+  double acc[NJ];   // FP64: the result does not depend on the order of the list
 #pragma unroll
-  for (int q = 0; q < NJ; ++q) acc[q] = 0.0f;
+  for (int q = 0; q < NJ; ++q) acc[q] = 0.0;
   for (int i1 = wv; i1 < n1; i1 += NW) {
     const uint32_t t1 = tab1[i1];
     const uint32_t h1 = t1 & TT_KEY_MASK;
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
 #pragma unroll
           for (int q = 0; q < NJ; ++q) {
             const int i0 = v + LPF * q;
-            if (i0 < n0) acc[q] += __uint_as_float(__float_as_uint(__builtin_nontemporal_load(base + i0)) ^ sg);
+            if (i0 < n0) acc[q] += signed_f64(__builtin_nontemporal_load(base + i0), sg);
           }
         }
       }
@@ -251,9 +251,9 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
     for (int q = 0; q < NJ; ++q) red[wv][v + LPF * q] = acc[q];
   __syncthreads();
   for (int i = threadIdx.x; i < n0; i += blockDim.x) {
-    float s = 0.0f;
+    double s = 0.0;
     for (int ww = 0; ww < NW; ++ww) s += red[ww][i];
-    t.Y[b + (int64_t)J * i] = s;
+    t.Y[b + (int64_t)J * i] = (float)s;
   }
 }
 
@@ -566,7 +566,7 @@ tt_status tt_batch_set_graph(tt_batch b, int32_t enable) {
 }
 
 tt_status tt_batch_sketch_tensor(tt_batch b, const void* const* X, int32_t k, void* const* Y) {
-  if (!b || !X || !Y) return tt_fail(TT_ERR_ARG, "null argument");
+  if (!b || !X) return tt_fail(TT_ERR_ARG, "null argument");
   if (!b->ws) return tt_fail(TT_ERR_WORKSPACE, "no workspace bound");
   if (k < 0 || k >= b->max_d) return tt_fail(TT_ERR_ARG, "k=%d out of range", k);
   for (int i = 0; i < b->count; ++i)
@@ -574,6 +574,7 @@ tt_status tt_batch_sketch_tensor(tt_batch b, const void* const* X, int32_t k, vo
   tt_status st;
   if ((st = upload_desc(b, X))) return st;
   TT_HIP_TRY(launch_step_sketch(b, k, b->W[k]));
+  if (!Y) return TT_OK;
   for (int32_t i : b->tids[k]) {
     tt_plan p = b->plans[i];
     if (!Y[i]) return tt_fail(TT_ERR_ARG, "problem %d: null Y", i);

@@ -329,7 +329,7 @@ __global__ __launch_bounds__(256) void k_sketch_mode0(
     const uint32_t* __restrict__ sorted, WT* __restrict__ Y, int32_t n0, int32_t n1, uint32_t J, int32_t i0_lo,
     int32_t i0_cnt, int32_t lpf_log2) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  WT* red = reinterpret_cast<WT*>(smem_raw);   // NW x (64 * NJ * V)
+  double* red = reinterpret_cast<double*>(smem_raw);   // NW x (64 * NJ * V)
   const uint32_t b = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -338,11 +338,13 @@ __global__ __launch_bounds__(256) void k_sketch_mode0(
   const int G = 64 >> lpf_log2;
   const int g = lane >> lpf_log2;
   const int v = lane & (LPF - 1);
-  WT acc[NJ][V];
+  // FP64 sums: exact enough that the order in which fibres arrive does not
+  // show in the FP32 result
+  double acc[NJ][V];
 #pragma unroll
   for (int j = 0; j < NJ; ++j)
 #pragma unroll
-    for (int e = 0; e < V; ++e) acc[j][e] = (WT)0;
+    for (int e = 0; e < V; ++e) acc[j][e] = 0.0;
 
   // the i_1 of this wave (i_1 = wv + NW q) are taken 64 at a time: lane q
   // fetches the table entry and list segment of one of them, and the first
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(256) void k_sketch_mode0(
               const int p = (v + LPF * j) * V;
               if (ok[u] && p < i0_cnt)
 #pragma unroll
-                for (int e = 0; e < V; ++e) acc[j][e] += apply_sign<WT>(to_work<WT>(x[u][j].e[e]), sg[u]);
+                for (int e = 0; e < V; ++e) acc[j][e] += signed_f64(x[u][j].e[e], sg[u]);
             }
         }
       }
@@ -422,9 +424,9 @@ __global__ __launch_bounds__(256) void k_sketch_mode0(
       for (int e = 0; e < V; ++e) red[wv * PW + (v + LPF * j) * V + e] = acc[j][e];
   __syncthreads();
   for (int i = threadIdx.x; i < i0_cnt; i += blockDim.x) {
-    WT s = (WT)0;
+    double s = 0.0;
     for (int ww = 0; ww < NW; ++ww) s += red[ww * PW + i];
-    Y[(int64_t)b + (int64_t)J * (i0_lo + i)] = s;
+    Y[(int64_t)b + (int64_t)J * (i0_lo + i)] = (WT)s;
   }
 }
 
@@ -536,7 +538,7 @@ hipError_t run_mode0(const tt_plan_s* p, const XT* X, WT* Y, int lpf_log2, int64
   const uint32_t* tab1 = p->at<uint32_t>(p->o_tab) + p->tab_off[1];
   const uint32_t* off = p->at<uint32_t>(p->o_cnt);
   const uint32_t* sorted = p->at<uint32_t>(p->o_sortO);
-  const size_t lds = (size_t)4 * 64 * NJ * V * sizeof(WT);
+  const size_t lds = (size_t)4 * 64 * NJ * V * sizeof(double);
   TTProfScope ps(p, TT_PROF_SKETCH0);
   for (int64_t lo = 0; lo < n0; lo += chunk) {
     const int64_t cnt = (n0 - lo) < chunk ? (n0 - lo) : chunk;
@@ -564,15 +566,13 @@ hipError_t dispatch_v(const tt_plan_s* p, const XT* X, int k, WT* Y) {
   const int64_t n0 = p->n[0];
   int lpf, nj;
   if (k == 0) {
-    // the k = 0 gather covers at most 64 * 16 * V positions of i_0 per launch
-    const int64_t chunk = 64 * 16 * V;
+    // the k = 0 gather covers at most 64 * 4 * V positions of i_0 per launch
+    const int64_t chunk = 64 * 4 * V;
     lane_shape(n0 < chunk ? n0 : chunk, V, &lpf, &nj);
     switch (nj) {
       case 1: return run_mode0<XT, WT, V, 1>(p, X, Y, lpf, chunk);
       case 2: return run_mode0<XT, WT, V, 2>(p, X, Y, lpf, chunk);
-      case 4: return run_mode0<XT, WT, V, 4>(p, X, Y, lpf, chunk);
-      case 8: return run_mode0<XT, WT, V, 8>(p, X, Y, lpf, chunk);
-      default: return run_mode0<XT, WT, V, 16>(p, X, Y, lpf, chunk);
+      default: return run_mode0<XT, WT, V, 4>(p, X, Y, lpf, chunk);
     }
   }
   lane_shape(n0, V, &lpf, &nj);

@@ -116,35 +116,6 @@ __global__ void k_scatter(const uint32_t* keys, int64_t count, uint32_t* cursor,
   sorted[pos] = (uint32_t)q | (key & TT_KEY_SIGN);
 }
 
-// The scatters above place the entries of a bucket in the order their atomic
-// increments happened to run.  Sorting every bucket's segment by index (one
-// thread per bucket, Shell sort with Ciura's gaps) makes the lists, and so the
-// order in which the gathers add their fibres, independent of scheduling.
-__device__ __forceinline__ uint32_t sort_key(uint32_t v) { return v & TT_KEY_MASK; }
-__device__ __forceinline__ uint32_t sort_key(uint2 v) { return v.x & TT_KEY_MASK; }
-
-template <typename E>
-__global__ void k_sort_segments(E* __restrict__ v, const uint32_t* __restrict__ off, int32_t nseg) {
-  const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nseg) return;
-  E* a = v + off[b];
-  const int m = (int)(off[b + 1] - off[b]);
-  const int gaps[8] = {701, 301, 132, 57, 23, 10, 4, 1};
-  for (int gi = 0; gi < 8; ++gi) {
-    const int gap = gaps[gi];
-    for (int i = gap; i < m; ++i) {
-      const E x = a[i];
-      const uint32_t kx = sort_key(x);
-      int j = i;
-      while (j >= gap && sort_key(a[j - gap]) > kx) {
-        a[j] = a[j - gap];
-        j -= gap;
-      }
-      a[j] = x;
-    }
-  }
-}
-
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -222,8 +193,6 @@ hipError_t launch_outer_sort(const tt_plan_s* p) {
   hipLaunchKernelGGL(k_count, dim3(nblk(O, 256)), dim3(256), 0, p->stream, keys, O, cursor);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, cursor, cnt, cursor, (int32_t)p->J);
   hipLaunchKernelGGL(k_scatter, dim3(nblk(O, 256)), dim3(256), 0, p->stream, keys, O, cursor, sorted);
-  hipLaunchKernelGGL(k_sort_segments<uint32_t>, dim3(nblk(p->J, 256)), dim3(256), 0, p->stream, sorted, cnt,
-                     (int32_t)p->J);
   return hipGetLastError();
 }
 
@@ -252,7 +221,5 @@ hipError_t launch_fibre_sort(const tt_plan_s* p, int k) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, cursor, off, cursor, (int32_t)p->J);
   hipLaunchKernelGGL(k_scatter_fibres, dim3(nblk(F, 256)), dim3(256), 0, p->stream, keys, F, M, p->n[k] * M, cursor,
                      p->at<uint2>(p->o_fsort));
-  hipLaunchKernelGGL(k_sort_segments<uint2>, dim3(nblk(p->J, 256)), dim3(256), 0, p->stream, p->at<uint2>(p->o_fsort),
-                     off, (int32_t)p->J);
   return hipGetLastError();
 }

@@ -131,9 +131,10 @@ def test_run_without_policy_equals_sweeps(env):
     X2, plan2, cores2 = _problem(torch, tts, n, R, 1e-3, 21, 500)
     res = [plan2.als_sweep(X2, cores2, residual=True) for _ in range(4)]
     assert out["sweeps"] == 4 and not out["reached"] and out["fallbacks"] == 0
-    # the same arithmetic; atomic adds go to FP64 accumulators and the bucket
-    # lists are sorted, so repeated runs agree to FP64 rounding
-    np.testing.assert_allclose(out["residuals"], res, rtol=1e-9)
+    # the same arithmetic; the atomic adds and list-order dependent sums go to
+    # FP64 accumulators, so repeated runs differ only where an FP64 rounding
+    # difference moves an FP32 result by one unit
+    np.testing.assert_allclose(out["residuals"], res, rtol=1e-6)
     assert out["J"] == [500] * 4
 
 
