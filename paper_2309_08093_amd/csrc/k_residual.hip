@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_residual(const XT* __restrict__ X, Core
   const double* G0 = cd.G[0];
   const double* G1 = cd.G[1];
   // G_0 rows of this lane's positions (registers when few, else cached loads)
-  constexpr bool kReg = NJ * V <= 4;
+  constexpr bool kReg = NJ * V * sizeof(WT) <= 32;
   constexpr int NR = kReg ? NJ : 1;
   WT g0[NR][V][TT_MAX_RANK];
 #pragma unroll

@@ -1,28 +1,36 @@
 // FP64 proximal solve (Sec. 3, eq. (3.5)).
 //
-// Solve: M = SH^T SH + lambda I is summed from the Gram partials in FP64 and
-// factored M = L L^T (right-looking Cholesky, packed lower triangle in LDS,
-// one workgroup); a second kernel forms B = SH^T Y + lambda G_(2)^T for a
-// block of columns and solves L L^T Z = B by forward and back substitution in
-// LDS, one workgroup per block of columns.
+// Solve: the split-K Gram partials of [SH^T SH | SH^T Y] are summed in FP64;
+// M = SH^T SH + lambda I is factored M = L L^T (blocked right-looking
+// Cholesky, packed lower triangle in LDS, one workgroup); a second kernel
+// forms B = SH^T Y + lambda G_(2)^T for a block of columns and solves
+// L L^T Z = B by blocked forward and back substitution in LDS, one workgroup
+// per block of columns.
 // lambda > 0 makes M positive definite (Sec. 3, remark after eq. (3.5)); a
 // non-positive pivot records TT_ERR_NOT_SPD in the status word.
 #include "tt_internal.h"
 
 namespace {
 
-constexpr int kSolveThreads = 1024;
-
 // Column-major packed lower triangle: column c holds rows c..s-1.
 __device__ __forceinline__ int coff(int c, int s) { return c * s - (c * (c - 1)) / 2; }
 __device__ __forceinline__ int lidx(int i, int c, int s) { return coff(c, s) + (i - c); }   // i >= c
 
-// M = sum of the Gram partials + lambda I (lower triangle), factored
-// M = L L^T in LDS; L is written (packed) to Lout.  One workgroup.
+// Blocked right-looking Cholesky, blocks of 16 columns: the first wave
+// factors the 16 x 16 diagonal block (LDS, wave-ordered), one thread per row
+// solves the panel below it with the row's 16 values in registers, and all
+// threads apply the trailing update in 4 x 4 register tiles: three barriers
+// per block of 16 pivots.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename AT>
-__global__ __launch_bounds__(kSolveThreads) void k_chol(const AT* __restrict__ gpart, int32_t chunks, int32_t s,
-                                                       int32_t ldg, double lambda, double* __restrict__ Lout,
-                                                       int32_t* __restrict__ status) {
+__global__ __launch_bounds__(256) void k_chol_blk(const AT* __restrict__ gpart, int32_t chunks, int32_t s, int32_t ldg,
+                                                 double lambda, double* __restrict__ Lout,
+                                                 int32_t* __restrict__ status) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* L = reinterpret_cast<double*>(smem_raw);
   __shared__ int bad;
@@ -37,26 +45,89 @@ __global__ __launch_bounds__(kSolveThreads) void k_chol(const AT* __restrict__ g
       L[lidx(i, c, s)] = acc + (i == c ? lambda : 0.0);
     }
   __syncthreads();
-  for (int j = 0; j < s; ++j) {
-    const double djj = L[lidx(j, j, s)];
-    if (!(djj > 0.0) || !isfinite(djj)) {
-      if (tid == 0) bad = 1;
-      break;   // uniform: every thread read the same pivot
+  constexpr int B = 16;
+  const int nb = (s + B - 1) / B;
+  for (int ib = 0; ib < nb; ++ib) {
+    const int j0 = ib * B, j1 = min(s, j0 + B);
+    // (a) diagonal block, unblocked, by wave 0
+    if (wv == 0) {
+      int fail = 0;
+      for (int j = j0; j < j1; ++j) {
+        const double djj = L[lidx(j, j, s)];
+        if (!(djj > 0.0) || !isfinite(djj)) {
+          fail = 1;
+          break;
+        }
+        const double dj = sqrt(djj), inv = 1.0 / dj;
+        wave_sync();
+        const int oj = coff(j, s) - j;
+        if (lane == 0) L[oj + j] = dj;
+        if (j + 1 + lane < j1) L[oj + j + 1 + lane] *= inv;
+        wave_sync();
+        // trailing part of the block: pairs (i, c), j < c <= i < j1
+        const int m = j1 - j - 1;
+        for (int e = lane; e < m * m; e += 64) {
+          const int c = j + 1 + e / m, i = j + 1 + e % m;
+          if (i >= c) L[lidx(i, c, s)] -= L[oj + i] * L[oj + c];
+        }
+        wave_sync();
+      }
+      if (lane == 0 && fail) bad = 1;
     }
-    const double dj = sqrt(djj);
-    const double inv = 1.0 / dj;
-    __syncthreads();   // all threads have read the pivot before it is overwritten
-    for (int i = j + 1 + tid; i < s; i += T) L[lidx(i, j, s)] *= inv;
-    if (tid == 0) L[lidx(j, j, s)] = dj;
     __syncthreads();
-    for (int c = j + 1 + wv; c < s; c += NW) {
-      const double lcj = L[lidx(c, j, s)];
-      const int oc = coff(c, s) - c, oj = coff(j, s) - j;
-      for (int i = c + lane; i < s; i += 64) L[oc + i] -= L[oj + i] * lcj;
+    if (bad) break;
+    // (b) panel rows i >= j1: L[i][j0:j1] <- M[i][j0:j1] L_blk^-T
+    for (int i = j1 + tid; i < s; i += T) {
+      double x[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) x[u] = (j0 + u < j1) ? L[lidx(i, j0 + u, s)] : 0.0;
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        if (j0 + u < j1) {
+          double t = x[u];
+#pragma unroll
+          for (int v = 0; v < u; ++v) t -= L[lidx(j0 + u, j0 + v, s)] * x[v];
+          x[u] = t / L[lidx(j0 + u, j0 + u, s)];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+        if (j0 + u < j1) L[lidx(i, j0 + u, s)] = x[u];
+    }
+    __syncthreads();
+    // (c) trailing update of the lower triangle beyond j1 in 4 x 4 tiles
+    const int R = s - j1;
+    if (R > 0) {
+      const int nt = (R + 3) / 4;
+      for (int t = tid; t < nt * nt; t += T) {
+        const int ti = t / nt, tc = t % nt;
+        if (ti < tc) continue;
+        const int i0 = j1 + 4 * ti, c0 = j1 + 4 * tc;
+        double acc[4][4] = {};
+        for (int u = j0; u < j1; ++u) {
+          const int ou = coff(u, s) - u;
+          double li[4], lc[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            li[a] = (i0 + a < s) ? L[ou + i0 + a] : 0.0;
+            lc[a] = (c0 + a < s) ? L[ou + c0 + a] : 0.0;
+          }
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += li[a] * lc[b];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int i = i0 + a, c = c0 + b;
+            if (i < s && c < s && i >= c) L[lidx(i, c, s)] -= acc[a][b];
+          }
+      }
     }
     __syncthreads();
   }
-  __syncthreads();
   if (bad) {
     for (int e = tid; e < np; e += T) Lout[e] = __longlong_as_double(0x7ff8000000000000ll);
     if (tid == 0) atomicOr(status, 1);
@@ -65,14 +136,18 @@ __global__ __launch_bounds__(kSolveThreads) void k_chol(const AT* __restrict__ g
   for (int e = tid; e < np; e += T) Lout[e] = L[e];
 }
 
-// For a block of CB right-hand-side columns: B = SH^T Y + lambda G_(2)^T (from
-// the Gram partials), then L y = B and L^T z = y by column-oriented
-// substitution in LDS (one barrier per pivot; row normalisation deferred),
-// and z is stored as the new core columns.
+// Blocked variant of the substitution: rows in blocks of 16.  Per block, one
+// thread per right-hand-side column solves the 16 x 16 diagonal triangle with
+// the column's 16 values in registers, then all threads update the rows the
+// block feeds in 4 x 4 register tiles: two barriers per block instead of one
+// per pivot.
+constexpr int kTB = 16;
+
 template <typename AT>
-__global__ __launch_bounds__(256) void k_prox_trsm(const AT* __restrict__ gpart, int32_t chunks, int32_t s, int32_t ldg,
-                                                  double lambda, const double* __restrict__ Lg, const double* G_old,
-                                                  double* G_new, int32_t rk, int32_t nk, int32_t CB) {
+__global__ __launch_bounds__(256) void k_prox_trsm_blk(const AT* __restrict__ gpart, int32_t chunks, int32_t s,
+                                                      int32_t ldg, double lambda, const double* __restrict__ Lg,
+                                                      const double* G_old, double* G_new, int32_t rk, int32_t nk,
+                                                      int32_t CB) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int np = s * (s + 1) / 2;
   double* L = reinterpret_cast<double*>(smem_raw);
@@ -95,27 +170,100 @@ __global__ __launch_bounds__(256) void k_prox_trsm(const AT* __restrict__ gpart,
   __syncthreads();   // every read of G_old for these columns precedes the writes below
   for (int j = tid; j < s; j += T) invd[j] = 1.0 / L[lidx(j, j, s)];
   __syncthreads();
-  // forward: rows i > j take row j (final, not yet scaled) times L(i,j)/L(j,j)
-  for (int j = 0; j < s - 1; ++j) {
-    const double dj = invd[j];
-    const int oj = coff(j, s) - j;
-    const int n = (s - 1 - j) * CB;
-    for (int e = tid; e < n; e += T) {
-      const int ii = e / CB, cl = e - ii * CB;
-      const int i = j + 1 + ii;
-      Bs[i * CB + cl] -= L[oj + i] * dj * Bs[j * CB + cl];
+  const int nb = (s + kTB - 1) / kTB;
+  const int ctiles = (CB + 3) / 4;
+  // forward: L y = B
+  for (int ib = 0; ib < nb; ++ib) {
+    const int j0 = ib * kTB, j1 = min(s, j0 + kTB);
+    if (tid < CB) {
+      double x[kTB];
+#pragma unroll
+      for (int u = 0; u < kTB; ++u) x[u] = (j0 + u < j1) ? Bs[(j0 + u) * CB + tid] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kTB; ++u) {
+        if (j0 + u < j1) {
+          x[u] *= invd[j0 + u];
+          const int oj = coff(j0 + u, s) - (j0 + u);
+#pragma unroll
+          for (int v = u + 1; v < kTB; ++v)
+            if (j0 + v < j1) x[v] -= L[oj + j0 + v] * x[u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kTB; ++u)
+        if (j0 + u < j1) Bs[(j0 + u) * CB + tid] = x[u];
+    }
+    __syncthreads();
+    const int rows = s - j1;
+    if (rows > 0) {
+      const int rtiles = (rows + 3) / 4;
+      for (int t = tid; t < rtiles * ctiles; t += T) {
+        const int i0 = j1 + (t / ctiles) * 4, cc = (t % ctiles) * 4;
+        double acc[4][4] = {};
+        for (int j = j0; j < j1; ++j) {
+          const int oj = coff(j, s) - j;
+          double lv[4], yv[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) lv[a] = (i0 + a < s) ? L[oj + i0 + a] : 0.0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) yv[b] = (cc + b < CB) ? Bs[j * CB + cc + b] : 0.0;
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += lv[a] * yv[b];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if (i0 + a < s && cc + b < CB) Bs[(i0 + a) * CB + cc + b] -= acc[a][b];
+      }
     }
     __syncthreads();
   }
-  for (int e = tid; e < s * CB; e += T) Bs[e] *= invd[e / CB];
-  __syncthreads();
-  // backward: L^T z = y, rows i < j take z_j = row j / L(j,j) times L(j,i)
-  for (int j = s - 1; j > 0; --j) {
-    const double dj = invd[j];
-    const int n = j * CB;
-    for (int e = tid; e < n; e += T) {
-      const int i = e / CB, cl = e - i * CB;
-      Bs[i * CB + cl] -= L[lidx(j, i, s)] * dj * Bs[j * CB + cl];
+  // backward: L^T z = y
+  for (int ib = nb - 1; ib >= 0; --ib) {
+    const int j0 = ib * kTB, j1 = min(s, j0 + kTB);
+    if (tid < CB) {
+      double x[kTB];
+#pragma unroll
+      for (int u = 0; u < kTB; ++u) x[u] = (j0 + u < j1) ? Bs[(j0 + u) * CB + tid] : 0.0;
+#pragma unroll
+      for (int u = kTB - 1; u >= 0; --u) {
+        if (j0 + u < j1) {
+          x[u] *= invd[j0 + u];
+#pragma unroll
+          for (int v = 0; v < u; ++v) x[v] -= L[lidx(j0 + u, j0 + v, s)] * x[u];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kTB; ++u)
+        if (j0 + u < j1) Bs[(j0 + u) * CB + tid] = x[u];
+    }
+    __syncthreads();
+    const int rows = j0;
+    if (rows > 0) {
+      const int rtiles = (rows + 3) / 4;
+      for (int t = tid; t < rtiles * ctiles; t += T) {
+        const int i0 = (t / ctiles) * 4, cc = (t % ctiles) * 4;
+        double acc[4][4] = {};
+        for (int j = j0; j < j1; ++j) {
+          double lv[4], zv[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) lv[a] = (i0 + a < rows) ? L[lidx(j, i0 + a, s)] : 0.0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) zv[b] = (cc + b < CB) ? Bs[j * CB + cc + b] : 0.0;
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += lv[a] * zv[b];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if (i0 + a < rows && cc + b < CB) Bs[(i0 + a) * CB + cc + b] -= acc[a][b];
+      }
     }
     __syncthreads();
   }
@@ -124,9 +272,20 @@ __global__ __launch_bounds__(256) void k_prox_trsm(const AT* __restrict__ gpart,
     const int col = c0 + cl;
     if (col < nk) {
       const int a = q % rk, b = q / rk;
-      G_new[a + (int64_t)rk * (col + (int64_t)nk * b)] = Bs[e] * invd[q];
+      G_new[a + (int64_t)rk * (col + (int64_t)nk * b)] = Bs[e];
     }
   }
+}
+
+// out[e] = sum over the split-K chunks of the Gram / right-hand-side partials
+// (chunk q at q * count), in FP64 and in chunk order; one thread per entry.
+template <typename AT>
+__global__ void k_gram_sum(const AT* __restrict__ gpart, int32_t chunks, int64_t count, double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  double acc = 0.0;
+  for (int q = 0; q < chunks; ++q) acc += (double)gpart[(int64_t)q * count + e];
+  out[e] = acc;
 }
 
 __global__ void k_copy_f64(double* dst, const double* src, int64_t count) {
@@ -142,23 +301,30 @@ hipError_t prox_t(const tt_plan_s* p, int k, const double* G_old, double* G_new)
   const int nk = (int)p->n[k];
   const int ldg = s + nk;
   const int chunks = (int)tt_gram_chunks(p->J);
-  const AT* gpart = p->at<AT>(p->o_gram);
   double* Lg = p->at<double>(p->o_minv);
   int32_t* status = p->at<int32_t>(p->o_status);
+  // the split-K partials summed once, every entry in parallel; the solve
+  // kernels then read one FP64 copy
+  double* gsum = p->at<double>(p->o_gsum);
+  const int64_t count = (int64_t)s * ldg;
+  hipLaunchKernelGGL(k_gram_sum<AT>, dim3(nblk(count, 256)), dim3(256), 0, p->stream, p->at<AT>(p->o_gram), chunks,
+                     count, gsum);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   const size_t np = (size_t)s * (s + 1) / 2;
   const size_t lds1 = np * sizeof(double);
-  hipError_t e = tt_allow_lds(k_chol<AT>, lds1);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chol<AT>, dim3(1), dim3(kSolveThreads), lds1, p->stream, gpart, chunks, s, ldg, p->lambda, Lg,
+  if ((e = tt_allow_lds(k_chol_blk<double>, lds1)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chol_blk<double>, dim3(1), dim3(256), lds1, p->stream, gsum, 1, s, ldg, p->lambda, Lg,
                      status);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // right-hand-side block: as wide as fits next to L in 150 KB of LDS
+  // right-hand-side block: as wide as fits next to L in 150 KB of LDS, at
+  // most 64 columns (one thread per column solves the diagonal blocks)
   int CB = 64;
   while (CB > 1 && (np + (size_t)s * CB + s) * sizeof(double) > 150 * 1024) CB >>= 1;
   const size_t lds2 = (np + (size_t)s * CB + s) * sizeof(double);
-  if ((e = tt_allow_lds(k_prox_trsm<AT>, lds2)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_prox_trsm<AT>, dim3(nblk(nk, CB)), dim3(256), lds2, p->stream, gpart, chunks, s, ldg, p->lambda,
-                     Lg, G_old, G_new, (int32_t)p->r[k], nk, CB);
+  if ((e = tt_allow_lds(k_prox_trsm_blk<double>, lds2)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prox_trsm_blk<double>, dim3(nblk(nk, CB)), dim3(256), lds2, p->stream, gsum, 1, s, ldg,
+                     p->lambda, Lg, G_old, G_new, (int32_t)p->r[k], nk, CB);
   return hipGetLastError();
 }
 
