@@ -281,6 +281,7 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_qrR = take(sizeof(double) * p->r_max * p->r_max);
   p->o_status = take(64);
   p->o_res = take(sizeof(double) * (2 * p->res_waves + 8));
+  p->o_resU = take(ws * p->O0 * p->r[2]);   // u(o) of the residual, O0 x R_2
   p->o_gold = take(sizeof(double));
   p->o_Yall = take(ws * p->J * p->tab_off[d]);   // Y_k of every mode for one sweep
   p->max_F = 1;

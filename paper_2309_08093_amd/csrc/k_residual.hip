@@ -1,14 +1,17 @@
-// Relative residual ||X - [[G]]||_F / ||X||_F (objective (3.1), Sec. 3).
+// Relative residual ||X - [[G]]||_F / ||X||_F (objective (lrtt), Sec. 3).
 //
-// X is streamed once as mode-0 fibres.  Work units are (outer tuple o =
-// (i_2..i_{d-1}), block of 64 consecutive i_1); a wave takes units in turn.
-// For a unit it forms u = G_2(:,i_2,:) ... G_{d-1}(:,i_{d-1},0) (length R_2,
-// entry b in lane b), then lane l computes w(i_1) = G_1(:,i_1,:) u for
-// i_1 = block start + l (R_1 values in registers).  Fibres are read with
-// 16-byte loads by lane groups as in the data sketch; each group fetches its
-// fibre's w by shuffles and reconstructs T(i_0) = G_0(0,i_0,:) w with G_0 rows
-// held in registers.  Squares are summed per fibre in the work type and
-// accumulated in FP64; per-wave partials are summed in a fixed order.
+// Write an entry as X(i_0, i_1, o) with o = (i_2, ..., i_{d-1}).  Its TT value
+// is sum_b H(i_0, i_1, b) u_b(o), where H = G_0 x G_1 contracted over their
+// shared rank (n_0 n_1 x R_2) and u(o) = G_2(:, i_2, :) ... G_{d-1}(:, i_{d-1}, 0).
+//  * k_res_u: one thread per outer tuple o computes u(o) (length R_2).
+//  * k_res_slab: X is a sequence of slabs of S = n_0 n_1 contiguous entries,
+//    one per o.  A wave task is (tile of 64 V consecutive slab positions, run
+//    of consecutive o).  Lane l keeps H(p, :) for its V positions p in
+//    registers and, for each o of the run, reads its V entries of slab o with
+//    one vector load, forms T = H(p, :) u(o) (u is the same for the whole wave)
+//    and accumulates (X - T)^2 and X^2.  Squares are summed per o in the work
+//    type and accumulated in FP64; per-wave partials are summed in a fixed
+//    order.  This avoids the cancellation of ||X||^2 - 2<X, T> + ||T||^2.
 #include "tt_internal.h"
 
 namespace {
@@ -38,113 +41,105 @@ __device__ __forceinline__ Vec<XT, V> load_vec(const XT* p) {
   }
 }
 
-template <typename XT, typename WT, int V, int NJ, int U>
-__global__ __launch_bounds__(256) void k_residual(const XT* __restrict__ X, CoreDesc cd, double* __restrict__ part,
-                                                  int64_t O, int32_t lpf_log2) {
-  const int lane = threadIdx.x & 63;
-  const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int TW = gridDim.x * (blockDim.x >> 6);
-  const int LPF = 1 << lpf_log2;
-  const int G = 64 >> lpf_log2;
-  const int g = lane >> lpf_log2;
-  const int v = lane & (LPF - 1);
+// U[o * R2 + b] = u_b(o): the product of the core slices of modes 2..d-1,
+// taken right to left (mode 2 varies fastest in o).
+template <typename WT>
+__global__ void k_res_u(CoreDesc cd, WT* __restrict__ U, int64_t O) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= O) return;
   const int d = cd.d;
+  int idx[TT_MAX_ORDER];
+  int64_t rem = o;
+  for (int s = 2; s < d; ++s) {
+    idx[s] = (int)(rem % cd.n[s]);
+    rem /= cd.n[s];
+  }
+  double v[TT_MAX_RANK];
+#pragma unroll
+  for (int a = 0; a < TT_MAX_RANK; ++a) v[a] = a == 0 ? 1.0 : 0.0;
+  int rv = 1;   // length of v
+  for (int s = d - 1; s >= 2; --s) {
+    const int r0 = cd.r0[s], ns = cd.n[s];
+    const double* Gs = cd.G[s];
+    double nv[TT_MAX_RANK];
+#pragma unroll
+    for (int a = 0; a < TT_MAX_RANK; ++a) {
+      double acc = 0.0;
+      if (a < r0)
+#pragma unroll
+        for (int b = 0; b < TT_MAX_RANK; ++b)
+          if (b < rv) acc += Gs[a + (int64_t)r0 * (idx[s] + (int64_t)ns * b)] * v[b];
+      nv[a] = acc;
+    }
+#pragma unroll
+    for (int a = 0; a < TT_MAX_RANK; ++a) v[a] = nv[a];
+    rv = r0;
+  }
+#pragma unroll
+  for (int b = 0; b < TT_MAX_RANK; ++b)
+    if (b < rv) U[o * rv + b] = (WT)v[b];
+}
+
+// RB: bound on R_2 (registers per position)
+template <typename XT, typename WT, int V, int RB>
+__global__ __launch_bounds__(256) void k_res_slab(const XT* __restrict__ X, CoreDesc cd, const WT* __restrict__ U,
+                                                  double* __restrict__ part, int64_t O, int32_t orun) {
+  const int lane = threadIdx.x & 63;
+  // wave-uniform, so that task, o and the u(o) loads stay scalar
+  const int gw = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int TW = gridDim.x * (blockDim.x >> 6);
   const int n0 = cd.n[0], n1 = cd.n[1];
   const int R1 = cd.r1[0], R2 = cd.r1[1];
+  const int64_t S = (int64_t)n0 * n1;
   const double* G0 = cd.G[0];
   const double* G1 = cd.G[1];
-  // G_0 rows of this lane's positions (registers when few, else cached loads)
-  constexpr bool kReg = NJ * V * sizeof(WT) <= 32;
-  constexpr int NR = kReg ? NJ : 1;
-  WT g0[NR][V][TT_MAX_RANK];
-#pragma unroll
-  for (int j = 0; j < NR; ++j)
+  const int64_t tiles = (S + 64 * V - 1) / (64 * V);
+  const int64_t runs = (O + orun - 1) / orun;
+  const int64_t tasks = tiles * runs;
+  double sd = 0.0, sx = 0.0;
+  for (int64_t task = gw; task < tasks; task += TW) {
+    const int64_t tile = task % tiles, run = task / tiles;
+    const int64_t p0 = (tile * 64 + lane) * V;
+    // H(p, :) for the lane's positions
+    WT h[V][RB];
 #pragma unroll
     for (int e = 0; e < V; ++e) {
-      const int i0 = (v + LPF * j) * V + e;
+      const int64_t p = p0 + e;
+      const int i0 = (int)(p % n0), i1 = (int)(p / n0);
 #pragma unroll
-      for (int a = 0; a < TT_MAX_RANK; ++a)
-        g0[j][e][a] = (kReg && i0 < n0 && a < R1) ? (WT)G0[i0 + (int64_t)n0 * a] : (WT)0;
-    }
-  const int nblk1 = (n1 + 63) / 64;
-  const int64_t units = O * nblk1;
-  double sd = 0.0, sx = 0.0;
-  for (int64_t unit = gw; unit < units; unit += TW) {
-    const int64_t o = unit / nblk1;
-    const int i1lo = (int)(unit - o * nblk1) * 64;
-    // u over modes d-1 .. 2 (lane b holds u_b)
-    double u = lane == 0 ? 1.0 : 0.0;
-    int ru = 1;
-    {
-      int64_t idx[TT_MAX_ORDER];
-      int64_t rem = o;
-      for (int s = 2; s < d; ++s) {
-        idx[s] = rem % cd.n[s];
-        rem /= cd.n[s];
-      }
-      for (int s = d - 1; s >= 2; --s) {
-        const int r0 = cd.r0[s], ns = cd.n[s];
-        const double* Gs = cd.G[s];
-        double nu = 0.0;
-        for (int b = 0; b < ru; ++b) {
-          const double ub = __shfl(u, b, 64);
-          if (lane < r0) nu += Gs[lane + (int64_t)r0 * (idx[s] + (int64_t)ns * b)] * ub;
-        }
-        u = lane < r0 ? nu : 0.0;
-        ru = r0;
-      }
-    }
-    double ub[TT_MAX_RANK];
-#pragma unroll
-    for (int b = 0; b < TT_MAX_RANK; ++b) ub[b] = __shfl(u, b, 64);
-    // w(i_1) for i_1 = i1lo + lane
-    WT wl[TT_MAX_RANK];
-    {
-      const int i1 = i1lo + lane;
-#pragma unroll
-      for (int a = 0; a < TT_MAX_RANK; ++a) {
+      for (int b = 0; b < RB; ++b) {
         double acc = 0.0;
-        if (a < R1 && i1 < n1)
-#pragma unroll
-          for (int b = 0; b < TT_MAX_RANK; ++b)
-            if (b < R2) acc += G1[a + (int64_t)R1 * (i1 + (int64_t)n1 * b)] * ub[b];
-        wl[a] = (WT)acc;
+        if (p < S && b < R2)
+          for (int a = 0; a < R1; ++a) acc += G0[i0 + (int64_t)n0 * a] * G1[a + (int64_t)R1 * (i1 + (int64_t)n1 * b)];
+        h[e][b] = (WT)acc;
       }
     }
-    const int nb = (n1 - i1lo) < 64 ? (n1 - i1lo) : 64;
-    const XT* Xo = X + ((int64_t)o * n1 + i1lo) * (int64_t)n0;
-    for (int t = 0; t < nb; t += G * U) {
-      Vec<XT, V> x[U][NJ];
-      bool ok[U];
-      int fi[U];
+    const bool ok = p0 < S;
+    const int64_t oa = run * orun, oe = (oa + orun) < O ? oa + orun : O;
+    // four slabs in flight per wave
+    constexpr int UO = 4;
+    for (int64_t ob = oa; ob < oe; ob += UO) {
+      Vec<XT, V> x[UO];
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        fi[q] = t + q * G + g;
-        ok[q] = fi[q] < nb;
+      for (int q = 0; q < UO; ++q)
+        if (ok && ob + q < oe) x[q] = load_vec<XT, V>(X + (ob + q) * S + p0);
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          const int p = (v + LPF * j) * V;
-          if (ok[q] && p < n0) x[q][j] = load_vec<XT, V>(Xo + (int64_t)fi[q] * n0 + p);
-        }
-      }
+      for (int q = 0; q < UO; ++q) {
+        if (ob + q >= oe) break;
+        const int64_t o = ob + q;
+        WT u[RB];
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        WT wv[TT_MAX_RANK];
-#pragma unroll
-        for (int a = 0; a < TT_MAX_RANK; ++a) wv[a] = a < R1 ? (WT)__shfl(wl[a], fi[q] & 63, 64) : (WT)0;
+        for (int b = 0; b < RB; ++b) u[b] = b < R2 ? U[o * R2 + b] : (WT)0;
         WT sdf = (WT)0, sxf = (WT)0;
+        if (ok) {
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          const int p = (v + LPF * j) * V;
-          if (ok[q] && p < n0) {
+          for (int e = 0; e < V; ++e) {
+            if (p0 + e < S) {
+              WT t = (WT)0;
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-              WT tt = (WT)0;
-#pragma unroll
-              for (int a = 0; a < TT_MAX_RANK; ++a)
-                if (a < R1) tt += (kReg ? g0[kReg ? j : 0][e][a] : (WT)G0[p + e + (int64_t)n0 * a]) * wv[a];
-              const WT xv = to_work<WT>(x[q][j].e[e]);
-              const WT df = xv - tt;
+              for (int b = 0; b < RB; ++b) t += h[e][b] * u[b];
+              const WT xv = to_work<WT>(x[q].e[e]);
+              const WT df = xv - t;
               sdf += df * df;
               sxf += xv * xv;
             }
@@ -190,19 +185,19 @@ __global__ void k_residual_final(const double* __restrict__ part, int32_t nw, do
   }
 }
 
-int ilog2_ceil(int64_t x) {
-  int l = 0;
-  while (((int64_t)1 << l) < x) ++l;
-  return l;
-}
-
-template <typename XT, typename WT, int V, int NJ>
-hipError_t run(const tt_plan_s* p, const XT* X, const CoreDesc& cd, int lpf) {
-  constexpr int U = NJ >= 4 ? 1 : 4 / NJ;
+template <typename XT, typename WT, int V, int RB>
+hipError_t run(const tt_plan_s* p, const XT* X, const CoreDesc& cd, const WT* U) {
   const int nw = (int)p->res_waves;
   double* part = p->at<double>(p->o_res);
-  hipLaunchKernelGGL((k_residual<XT, WT, V, NJ, U>), dim3((unsigned)(nw / 4)), dim3(256), 0, p->stream, X, cd, part,
-                     p->O0, lpf);
+  const int64_t S = p->n[0] * p->n[1];
+  const int64_t tiles = (S + 64 * V - 1) / (64 * V);
+  // runs of outer tuples: enough tasks for every wave, long enough to
+  // amortise forming H
+  int64_t orun = (tiles * p->O0) / (2 * (int64_t)nw);
+  if (orun < 4) orun = 4;
+  if (orun > 512) orun = 512;
+  hipLaunchKernelGGL((k_res_slab<XT, WT, V, RB>), dim3((unsigned)(nw / 4)), dim3(256), 0, p->stream, X, cd, U, part,
+                     p->O0, (int32_t)orun);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, p->stream, part, nw, part + 2 * nw);
@@ -210,28 +205,23 @@ hipError_t run(const tt_plan_s* p, const XT* X, const CoreDesc& cd, int lpf) {
 }
 
 template <typename XT, typename WT, int V>
-hipError_t dispatch_v(const tt_plan_s* p, const XT* X, const CoreDesc& cd) {
-  const int64_t vecs = (p->n[0] + V - 1) / V;
-  int lpf = 6, nj = 1;
-  if (vecs <= 64) lpf = ilog2_ceil(vecs);
-  else nj = 1 << ilog2_ceil((vecs + 63) / 64);
-  switch (nj) {
-    case 1: return run<XT, WT, V, 1>(p, X, cd, lpf);
-    case 2: return run<XT, WT, V, 2>(p, X, cd, lpf);
-    case 4: return run<XT, WT, V, 4>(p, X, cd, lpf);
-    case 8: return run<XT, WT, V, 8>(p, X, cd, lpf);
-    case 16: return run<XT, WT, V, 16>(p, X, cd, lpf);
-    case 32: return run<XT, WT, V, 32>(p, X, cd, lpf);
-    default: return run<XT, WT, V, 64>(p, X, cd, lpf);
-  }
+hipError_t dispatch_r(const tt_plan_s* p, const XT* X, const CoreDesc& cd, const WT* U) {
+  const int64_t R2 = p->r[2];
+  if (R2 <= 4) return run<XT, WT, V, 4>(p, X, cd, U);
+  if (R2 <= 8) return run<XT, WT, V, 8>(p, X, cd, U);
+  return run<XT, WT, V, 16>(p, X, cd, U);
 }
 
 template <typename XT, typename WT>
 hipError_t dispatch(const tt_plan_s* p, const void* Xv, const CoreDesc& cd) {
   const XT* X = static_cast<const XT*>(Xv);
+  WT* U = p->at<WT>(p->o_resU);
+  hipLaunchKernelGGL(k_res_u<WT>, dim3((unsigned)((p->O0 + 255) / 256)), dim3(256), 0, p->stream, cd, U, p->O0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   constexpr int VV = 16 / (int)sizeof(XT);
-  const bool vec = (p->n[0] % VV) == 0 && ((uintptr_t)Xv % 16) == 0;
-  return vec ? dispatch_v<XT, WT, VV>(p, X, cd) : dispatch_v<XT, WT, 1>(p, X, cd);
+  const bool vec = ((p->n[0] * p->n[1]) % VV) == 0 && ((uintptr_t)Xv % 16) == 0;
+  return vec ? dispatch_r<XT, WT, VV>(p, X, cd, U) : dispatch_r<XT, WT, 1>(p, X, cd, U);
 }
 
 }  // namespace
