@@ -28,7 +28,7 @@ namespace {
 
 struct BTensor {
   const float* X;
-  float* Y;                  // the plan's Y buffer (J x n_k, column-major)
+  float* Y;                  // the plan's all-mode Y buffer: Y_k (J x n_k, column-major) at J * toff[k]
   const uint32_t* tab;       // packed tables of all modes
   const uint32_t* off;       // k = 0: bucket offsets of the outer tuples (J + 1)
   const uint32_t* sorted;    // k = 0: outer tuples sorted by bucket
@@ -198,7 +198,7 @@ __global__ void k_breduce(const BTensor* __restrict__ T, const int32_t* __restri
   const double* p = part + spre[gc] * (int64_t)Jmax + b;
   double s = 0.0;
   for (int64_t q = 0; q < cnt; ++q) s += p[q * Jmax];
-  t.Y[b + (int64_t)t.J * c] = (float)s;
+  t.Y[(int64_t)t.J * t.toff[k] + b + (int64_t)t.J * c] = (float)s;
 }
 
 // ---------------------------------------------------------------- k = 0
@@ -291,6 +291,9 @@ struct tt_batch_s {
   // graph
   bool use_graph = false;
   hipStream_t cap = nullptr;   // private stream the sweep is captured on
+  hipStream_t side = nullptr;  // batched data sketches of a sweep
+  hipStream_t lane[8] = {};    // per-problem core updates
+  hipEvent_t ev_fork = nullptr, ev_done = nullptr, ev_lane[8] = {}, ev_step[TT_MAX_ORDER] = {};
   hipGraphExec_t exec = nullptr;
   std::vector<const void*> cap_ptrs;
   int64_t replays = 0;
@@ -339,7 +342,7 @@ tt_status upload_desc(tt_batch b, const void* const* X) {
     tt_plan p = b->plans[i];
     BTensor& t = b->host_desc[i];
     t.X = static_cast<const float*>(X[i]);
-    t.Y = p->at<float>(p->o_Y);
+    t.Y = p->at<float>(p->o_Yall);
     t.tab = p->at<uint32_t>(p->o_tab);
     t.off = p->at<uint32_t>(p->o_cnt);
     t.sorted = p->at<uint32_t>(p->o_sortO);
@@ -364,8 +367,14 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
   if (nt == 0) return hipSuccess;
   hipError_t e;
   if (k == 0) {
-    for (int32_t j = 0; j < nt; ++j)
-      if ((e = launch_outer_sort(b->plans[b->tids[0][j]])) != hipSuccess) return e;
+    for (int32_t j = 0; j < nt; ++j) {
+      tt_plan p = b->plans[b->tids[0][j]];
+      const hipStream_t keep = p->stream;
+      p->stream = b->stream;
+      e = launch_outer_sort(p);
+      p->stream = keep;
+      if (e != hipSuccess) return e;
+    }
     const dim3 grid((unsigned)(nt * b->Jmax));
     if (b->nj == 1) hipLaunchKernelGGL(k_bsketch_0<1>, grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
     else if (b->nj == 2) hipLaunchKernelGGL(k_bsketch_0<2>, grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
@@ -398,27 +407,78 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
   return hipGetLastError();
 }
 
-// Enqueue one sweep of every problem on the batch stream.
+constexpr int kLanes = 8;   // streams the per-problem core updates are spread over
+
+tt_status make_lanes(tt_batch b) {
+  if (b->side) return TT_OK;
+  TT_HIP_TRY(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+  for (int l = 0; l < kLanes; ++l) {
+    TT_HIP_TRY(hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking));
+    TT_HIP_TRY(hipEventCreateWithFlags(&b->ev_lane[l], hipEventDisableTiming));
+  }
+  TT_HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+  TT_HIP_TRY(hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
+  for (int k = 0; k < TT_MAX_ORDER; ++k) TT_HIP_TRY(hipEventCreateWithFlags(&b->ev_step[k], hipEventDisableTiming));
+  return TT_OK;
+}
+
+// Enqueue one sweep of every problem.  The batched data sketches of all steps
+// need only X and the sweep's tables, so they go first, on the side stream,
+// one launch per step; the core updates of problem i run on lane i mod
+// kLanes and wait for the sketch of their step.  The next sweep's tables are
+// drawn once every sketch has read the current ones.  Everything forks from
+// and joins back into the batch stream.
 tt_status enqueue_sweep(tt_batch b, void* const* const* cores) {
-  std::vector<CoreDesc> cd(b->count);
   tt_status st;
-  for (int i = 0; i < b->count; ++i) {
-    cd[i] = tt_make_desc(b->plans[i], cores[i]);
-    if ((st = tt_sweep_begin(b->plans[i], reinterpret_cast<double* const*>(cores[i]), cd[i]))) return st;
-  }
+  if ((st = make_lanes(b))) return st;
+  const hipStream_t main = b->stream;
+  TT_HIP_TRY(hipEventRecord(b->ev_fork, main));
+  TT_HIP_TRY(hipStreamWaitEvent(b->side, b->ev_fork, 0));
+  for (int l = 0; l < kLanes; ++l) TT_HIP_TRY(hipStreamWaitEvent(b->lane[l], b->ev_fork, 0));
+  // data sketches
+  b->stream = b->side;
   for (int k = 0; k < b->max_d; ++k) {
-    for (int32_t i : b->tids[k])
-      if ((st = tt_sweep_interface(b->plans[i], cd[i], k))) return st;
-    TT_HIP_TRY(launch_step_sketch(b, k, b->W[k]));
-    for (int32_t i : b->tids[k]) {
-      tt_plan p = b->plans[i];
-      if ((st = tt_sweep_update(p, reinterpret_cast<double* const*>(cores[i]), cd[i], k, p->ws + p->o_Y))) return st;
+    const hipError_t e = launch_step_sketch(b, k, b->W[k]);
+    if (e != hipSuccess) {
+      b->stream = main;
+      return tt_fail(TT_ERR_HIP, "batched sketch launch failed: %s", hipGetErrorString(e));
     }
+    TT_HIP_TRY(hipEventRecord(b->ev_step[k], b->side));
   }
-  hipLaunchKernelGGL(k_inc_i64, dim3(1), dim3(64), 0, b->stream, reinterpret_cast<int64_t*>(b->ws + b->o_counter));
+  hipLaunchKernelGGL(k_inc_i64, dim3(1), dim3(64), 0, b->side, reinterpret_cast<int64_t*>(b->ws + b->o_counter));
   TT_HIP_TRY(hipGetLastError());
-  for (int i = 0; i < b->count; ++i)
-    if ((st = tt_sweep_end(b->plans[i]))) return st;
+  TT_HIP_TRY(hipEventRecord(b->ev_done, b->side));
+  b->stream = main;
+  // core updates
+  for (int i = 0; i < b->count; ++i) {
+    tt_plan p = b->plans[i];
+    const hipStream_t lane = b->lane[i % kLanes];
+    const hipStream_t keep = p->stream;
+    p->stream = lane;
+    const CoreDesc cd = tt_make_desc(p, cores[i]);
+    double* const* G = reinterpret_cast<double* const*>(cores[i]);
+    st = tt_sweep_begin(p, G, cd);
+    for (int k = 0; k < p->d && !st; ++k) {
+      if ((st = tt_sweep_interface(p, cd, k))) break;
+      const hipError_t e = hipStreamWaitEvent(lane, b->ev_step[k], 0);
+      if (e != hipSuccess) {
+        st = tt_fail(TT_ERR_HIP, "hipStreamWaitEvent failed: %s", hipGetErrorString(e));
+        break;
+      }
+      st = tt_sweep_update(p, G, cd, k, p->at<float>(p->o_Yall) + p->J * p->tab_off[k]);
+    }
+    if (!st) {
+      const hipError_t e = hipStreamWaitEvent(lane, b->ev_done, 0);
+      st = e == hipSuccess ? tt_sweep_end(p) : tt_fail(TT_ERR_HIP, "hipStreamWaitEvent failed");
+    }
+    p->stream = keep;
+    if (st) return st;
+  }
+  for (int l = 0; l < kLanes; ++l) {
+    TT_HIP_TRY(hipEventRecord(b->ev_lane[l], b->lane[l]));
+    TT_HIP_TRY(hipStreamWaitEvent(main, b->ev_lane[l], 0));
+  }
+  TT_HIP_TRY(hipStreamWaitEvent(main, b->ev_done, 0));
   return TT_OK;
 }
 
@@ -578,7 +638,8 @@ tt_status tt_batch_sketch_tensor(tt_batch b, const void* const* X, int32_t k, vo
   for (int32_t i : b->tids[k]) {
     tt_plan p = b->plans[i];
     if (!Y[i]) return tt_fail(TT_ERR_ARG, "problem %d: null Y", i);
-    TT_HIP_TRY(hipMemcpyAsync(Y[i], p->ws + p->o_Y, sizeof(float) * p->J * p->n[k], hipMemcpyDeviceToDevice, b->stream));
+    TT_HIP_TRY(hipMemcpyAsync(Y[i], p->at<float>(p->o_Yall) + p->J * p->tab_off[k], sizeof(float) * p->J * p->n[k],
+                              hipMemcpyDeviceToDevice, b->stream));
   }
   return TT_OK;
 }
@@ -589,6 +650,7 @@ tt_status tt_batch_sweep(tt_batch b, const void* const* X, void* const* const* c
   tt_status st;
   if ((st = check_inputs(b, X, cores))) return st;
   if ((st = upload_desc(b, X))) return st;
+  if ((st = make_lanes(b))) return st;   // streams and events exist before any capture
   if (!b->use_graph) {
     if ((st = enqueue_sweep(b, cores))) return st;
   } else {
@@ -684,6 +746,18 @@ tt_status tt_batch_autotune(tt_batch b, const void* const* X, int32_t reps, int6
 tt_status tt_batch_destroy(tt_batch b) {
   if (!b) return TT_OK;
   drop_graph(b);
+  if (b->side) {
+    (void)hipStreamSynchronize(b->side);
+    (void)hipStreamDestroy(b->side);
+    for (int l = 0; l < kLanes; ++l) {
+      (void)hipStreamSynchronize(b->lane[l]);
+      (void)hipStreamDestroy(b->lane[l]);
+      (void)hipEventDestroy(b->ev_lane[l]);
+    }
+    (void)hipEventDestroy(b->ev_fork);
+    (void)hipEventDestroy(b->ev_done);
+    for (int k = 0; k < TT_MAX_ORDER; ++k) (void)hipEventDestroy(b->ev_step[k]);
+  }
   if (b->cap) {
     (void)hipStreamSynchronize(b->cap);
     (void)hipStreamDestroy(b->cap);
