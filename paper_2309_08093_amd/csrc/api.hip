@@ -282,6 +282,9 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_status = take(64);
   p->o_res = take(sizeof(double) * (2 * p->res_waves + 8));
   p->o_resU = take(ws * p->O0 * p->r[2]);   // u(o) of the residual, O0 x R_2
+  // G_0 x G_1 of the residual (n_0 n_1 x R_2), when it is at most 2^26 entries
+  const int64_t nH = p->n[0] * p->n[1] * p->r[2];
+  p->o_resH = nH <= ((int64_t)1 << 26) ? take(ws * nH) : 0;
   p->o_gold = take(sizeof(double));
   p->o_Yall = take(ws * p->J * p->tab_off[d]);   // Y_k of every mode for one sweep
   p->max_F = 1;

@@ -80,10 +80,30 @@ __global__ void k_res_u(CoreDesc cd, WT* __restrict__ U, int64_t O) {
     if (b < rv) U[o * rv + b] = (WT)v[b];
 }
 
-// RB: bound on R_2 (registers per position)
+// H[p * R2 + b] = sum_a G_0(0, i_0, a) G_1(a, i_1, b) for slab position
+// p = i_0 + n_0 i_1.
+template <typename WT>
+__global__ void k_res_h(CoreDesc cd, WT* __restrict__ H) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n0 = cd.n[0], n1 = cd.n[1];
+  if (p >= (int64_t)n0 * n1) return;
+  const int R1 = cd.r1[0], R2 = cd.r1[1];
+  const int i0 = (int)(p % n0), i1 = (int)(p / n0);
+  const double* G0 = cd.G[0];
+  const double* G1 = cd.G[1];
+  for (int b = 0; b < R2; ++b) {
+    double acc = 0.0;
+    for (int a = 0; a < R1; ++a) acc += G0[i0 + (int64_t)n0 * a] * G1[a + (int64_t)R1 * (i1 + (int64_t)n1 * b)];
+    H[p * R2 + b] = (WT)acc;
+  }
+}
+
+// RB: bound on R_2 (registers per position).  Hb: H precomputed (k_res_h) or
+// null, then each task forms its rows itself.
 template <typename XT, typename WT, int V, int RB>
 __global__ __launch_bounds__(256) void k_res_slab(const XT* __restrict__ X, CoreDesc cd, const WT* __restrict__ U,
-                                                  double* __restrict__ part, int64_t O, int32_t orun) {
+                                                  const WT* __restrict__ Hb, double* __restrict__ part, int64_t O,
+                                                  int32_t orun) {
   const int lane = threadIdx.x & 63;
   // wave-uniform, so that task, o and the u(o) loads stay scalar
   const int gw = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
@@ -102,16 +122,24 @@ __global__ __launch_bounds__(256) void k_res_slab(const XT* __restrict__ X, Core
     const int64_t p0 = (tile * 64 + lane) * V;
     // H(p, :) for the lane's positions
     WT h[V][RB];
+    if (Hb) {
 #pragma unroll
-    for (int e = 0; e < V; ++e) {
-      const int64_t p = p0 + e;
-      const int i0 = (int)(p % n0), i1 = (int)(p / n0);
+      for (int e = 0; e < V; ++e)
 #pragma unroll
-      for (int b = 0; b < RB; ++b) {
-        double acc = 0.0;
-        if (p < S && b < R2)
-          for (int a = 0; a < R1; ++a) acc += G0[i0 + (int64_t)n0 * a] * G1[a + (int64_t)R1 * (i1 + (int64_t)n1 * b)];
-        h[e][b] = (WT)acc;
+        for (int b = 0; b < RB; ++b) h[e][b] = (p0 + e < S && b < R2) ? Hb[(p0 + e) * R2 + b] : (WT)0;
+    } else {
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        const int64_t p = p0 + e;
+        const int i0 = (int)(p % n0), i1 = (int)(p / n0);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+          double acc = 0.0;
+          if (p < S && b < R2)
+            for (int a = 0; a < R1; ++a)
+              acc += G0[i0 + (int64_t)n0 * a] * G1[a + (int64_t)R1 * (i1 + (int64_t)n1 * b)];
+          h[e][b] = (WT)acc;
+        }
       }
     }
     const bool ok = p0 < S;
@@ -186,7 +214,7 @@ __global__ void k_residual_final(const double* __restrict__ part, int32_t nw, do
 }
 
 template <typename XT, typename WT, int V, int RB>
-hipError_t run(const tt_plan_s* p, const XT* X, const CoreDesc& cd, const WT* U) {
+hipError_t run(const tt_plan_s* p, const XT* X, const CoreDesc& cd, const WT* U, const WT* H) {
   const int nw = (int)p->res_waves;
   double* part = p->at<double>(p->o_res);
   const int64_t S = p->n[0] * p->n[1];
@@ -196,8 +224,8 @@ hipError_t run(const tt_plan_s* p, const XT* X, const CoreDesc& cd, const WT* U)
   int64_t orun = (tiles * p->O0) / (2 * (int64_t)nw);
   if (orun < 4) orun = 4;
   if (orun > 512) orun = 512;
-  hipLaunchKernelGGL((k_res_slab<XT, WT, V, RB>), dim3((unsigned)(nw / 4)), dim3(256), 0, p->stream, X, cd, U, part,
-                     p->O0, (int32_t)orun);
+  hipLaunchKernelGGL((k_res_slab<XT, WT, V, RB>), dim3((unsigned)(nw / 4)), dim3(256), 0, p->stream, X, cd, U, H,
+                     part, p->O0, (int32_t)orun);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, p->stream, part, nw, part + 2 * nw);
@@ -205,11 +233,11 @@ hipError_t run(const tt_plan_s* p, const XT* X, const CoreDesc& cd, const WT* U)
 }
 
 template <typename XT, typename WT, int V>
-hipError_t dispatch_r(const tt_plan_s* p, const XT* X, const CoreDesc& cd, const WT* U) {
+hipError_t dispatch_r(const tt_plan_s* p, const XT* X, const CoreDesc& cd, const WT* U, const WT* H) {
   const int64_t R2 = p->r[2];
-  if (R2 <= 4) return run<XT, WT, V, 4>(p, X, cd, U);
-  if (R2 <= 8) return run<XT, WT, V, 8>(p, X, cd, U);
-  return run<XT, WT, V, 16>(p, X, cd, U);
+  if (R2 <= 4) return run<XT, WT, V, 4>(p, X, cd, U, H);
+  if (R2 <= 8) return run<XT, WT, V, 8>(p, X, cd, U, H);
+  return run<XT, WT, V, 16>(p, X, cd, U, H);
 }
 
 template <typename XT, typename WT>
@@ -219,9 +247,17 @@ hipError_t dispatch(const tt_plan_s* p, const void* Xv, const CoreDesc& cd) {
   hipLaunchKernelGGL(k_res_u<WT>, dim3((unsigned)((p->O0 + 255) / 256)), dim3(256), 0, p->stream, cd, U, p->O0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // H = G_0 x G_1 once, when the plan's buffer holds it
+  const int64_t S = p->n[0] * p->n[1];
+  WT* H = nullptr;
+  if (p->o_resH) {
+    H = p->at<WT>(p->o_resH);
+    hipLaunchKernelGGL(k_res_h<WT>, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, p->stream, cd, H);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   constexpr int VV = 16 / (int)sizeof(XT);
-  const bool vec = ((p->n[0] * p->n[1]) % VV) == 0 && ((uintptr_t)Xv % 16) == 0;
-  return vec ? dispatch_r<XT, WT, VV>(p, X, cd, U) : dispatch_r<XT, WT, 1>(p, X, cd, U);
+  const bool vec = (S % VV) == 0 && ((uintptr_t)Xv % 16) == 0;
+  return vec ? dispatch_r<XT, WT, VV>(p, X, cd, U, H) : dispatch_r<XT, WT, 1>(p, X, cd, U, H);
 }
 
 }  // namespace

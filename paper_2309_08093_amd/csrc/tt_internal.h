@@ -55,7 +55,7 @@ struct tt_plan_s {
   void* prof;                  // ProfState* when measurement is enabled, else null
 
   size_t o_tab, o_KI, o_KO, o_cnt, o_cursor, o_sortO, o_part, o_chat, o_pre, o_suf, o_SH, o_Y,
-      o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_fkeys, o_fsort, o_pol, o_gsum, o_resU;
+      o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_fkeys, o_fsort, o_pol, o_gsum, o_resU, o_resH;
   int64_t max_F;               // largest fibre count of one column over k >= 1
 
   template <typename T>

@@ -6,12 +6,14 @@ this module marshals arrays and runs the label-collection loop, in which
 every sweep, residual and feature vector is computed by the library.
 
 Labels (one per sweep state of a run): starting from the same cores and the
-same sweep index, one sweep is run for every J of a geometric grid; the label
-J* is the smallest J whose residual drop log10(res_before / res_after) is at
-least (1 - tol) times the drop at the largest J.  At J* one sweep per lambda
-of a grid gives the label lambda* (largest drop), and the run continues from
-that sweep's cores.  The d feature rows of the state (one per core update)
-all carry the label (ln J* - 7, log10 lambda* + 3).
+same sweep index, one sweep is run and timed for every J of a geometric grid
+(the plan's serial schedule, as tt_als_run uses); the label J* maximises the
+residual drop per second, log10(res_before / res_after) / time, which is what
+the time to a target residual depends on.  At J* one sweep per lambda of a
+grid gives the label lambda* (largest drop), and the run continues from that
+sweep's cores.  The d feature rows of the state (one per core update) all
+carry the label (ln J* - 7, log10 lambda* + 3); their residual drop is that
+of the previous sweep, as in tt_als_run.
 """
 import json
 import math
@@ -140,10 +142,16 @@ class Policy:
 def random_problem(g):
     """Shape, ranks and relative noise of one training run: order 4-5, modes
     in [30, 40], ranks U[2, 12] clipped to feasibility, noise log-uniform in
-    [1e-4, 1e-1] relative to the entry scale."""
+    [1e-4, 1e-1] relative to the entry scale; one run in six is a large order-5
+    tensor with modes in [50, 64] (up to 1.07e9 entries), so that the
+    features of large tensors are inside the training range."""
     import synth
-    d = int(g.integers(4, 6))
-    n = [int(x) for x in g.integers(30, 41, size=d)]
+    if g.uniform() < 1.0 / 6.0:
+        d = 5
+        n = [int(x) for x in g.integers(50, 65, size=d)]
+    else:
+        d = int(g.integers(4, 6))
+        n = [int(x) for x in g.integers(30, 41, size=d)]
     R = [1] + [int(x) for x in g.integers(2, 13, size=d - 1)] + [1]
     R = synth.clip_ranks(n, R)
     nu = float(10 ** g.uniform(-4, -1))
@@ -151,7 +159,7 @@ def random_problem(g):
 
 
 def collect(n_tensors, seed, device="cuda", J_grid=(250, 500, 1000, 2000, 4000, 8000),
-            lam_grid=(1e-4, 1e-3, 1e-2, 1e-1), tol=0.1, sweeps=5, log=None):
+            lam_grid=(1e-4, 1e-3, 1e-2, 1e-1), sweeps=5, log=None):
     """Labelled (features, targets) from n_tensors runs; see the module doc."""
     import synth
     from . import Plan, core_to_device
@@ -160,14 +168,15 @@ def collect(n_tensors, seed, device="cuda", J_grid=(250, 500, 1000, 2000, 4000, 
     feats, targs, meta = [], [], []
     Jmax = max(J_grid)
     t0 = time.time()
+    stream = torch.cuda.current_stream(dev)
     for i in range(n_tensors):
         n, R, nu = random_problem(g)
         s_i = int(g.integers(1, 2 ** 31))
         scale = math.sqrt(float(np.prod(R[1:-1])))
         X, _ = synth.tt_tensor_device(n, R, nu * scale, s_i, dtype="f32", device=dev)
-        plan = Plan(n, R, Jmax, 1e-3, seed=s_i, x_dtype="f32", work_dtype="f32", device=dev)
+        plan = Plan(n, R, Jmax, 1e-3, seed=s_i, x_dtype="f32", work_dtype="f32", device=dev, serial=True)
         cores = [core_to_device(c, dev) for c in synth.random_cores(n, R, s_i + 1)]
-        prev, last_drop = 1.0, 0.0
+        hist = [1.0]        # hist[s + 1]: residual after sweep s; 1 before the first (tt_als_run's convention)
         for t in range(sweeps):
             state = [c.clone() for c in cores]
 
@@ -176,31 +185,33 @@ def collect(n_tensors, seed, device="cuda", J_grid=(250, 500, 1000, 2000, 4000, 
                     c.copy_(s0)
                 plan.set_sweep(t)
                 plan.set_sketch(J, lam)
-                res = plan.als_sweep(X, cores, residual=True)
-                return math.log10(prev / res), res
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                plan.als_sweep(X, cores)
+                e1.record(stream)
+                res = plan.residual(X, cores)
+                return math.log10(hist[-1] / res), res, e0.elapsed_time(e1)
 
-            drops = {J: trial(J, 1e-3)[0] for J in J_grid}
-            top = drops[Jmax]
-            Jstar = Jmax
-            if top > 0:
-                for J in sorted(J_grid):
-                    if drops[J] >= (1.0 - tol) * top:
-                        Jstar = J
-                        break
+            runs = {J: trial(J, 1e-3) for J in J_grid}
+            rate = {J: r[0] / r[2] for J, r in runs.items()}
+            Jstar = max(J_grid, key=lambda J: (rate[J], -J)) if max(rate.values()) > 0 else Jmax
             best = None
             for lam in lam_grid:
-                dr, res = trial(Jstar, lam)
+                dr, res, _ = trial(Jstar, lam)
                 if best is None or dr > best[0]:
                     best = (dr, res, lam, [c.clone() for c in cores])
             dr, res, lam, cbest = best
-            F_rows = plan.features(t, last_drop)
+            drop = math.log10(hist[t - 1] / hist[t]) if t >= 1 else 0.0
+            F_rows = plan.features(t, drop)
             feats.append(F_rows)
             targs.append(np.repeat(encode_targets(Jstar, lam)[None, :], len(n), axis=0))
-            meta.append({"n": n, "R": R, "noise": nu, "t": t, "J": Jstar, "lambda": lam, "drops": drops,
+            meta.append({"n": n, "R": R, "noise": nu, "t": t, "J": Jstar, "lambda": lam,
+                         "drops": {J: r[0] for J, r in runs.items()}, "ms": {J: r[2] for J, r in runs.items()},
                          "res": res})
             for c, cb in zip(cores, cbest):
                 c.copy_(cb)
-            last_drop, prev = dr, res
+            hist.append(res)
         del X, plan, cores
         if log and (i + 1) % 20 == 0:
             log("[collect] %d/%d tensors, %d rows, %.0f s" % (i + 1, n_tensors, sum(len(f) for f in feats),

@@ -123,6 +123,8 @@ def _problem(torch, tts, n, R, noise, seed, J, lam=1e-3):
 
 
 def test_run_without_policy_equals_sweeps(env):
+    """tt_als_run without a policy makes the same sweeps (serial schedule) as
+    tt_als_sweep."""
     torch, tts, jpolicy = env
     say("run fixed J vs sweeps")
     n, R = [20, 22, 18, 21], [1, 4, 5, 4, 1]
@@ -131,11 +133,24 @@ def test_run_without_policy_equals_sweeps(env):
     X2, plan2, cores2 = _problem(torch, tts, n, R, 1e-3, 21, 500)
     res = [plan2.als_sweep(X2, cores2, residual=True) for _ in range(4)]
     assert out["sweeps"] == 4 and not out["reached"] and out["fallbacks"] == 0
-    # the same arithmetic; the atomic adds and list-order dependent sums go to
-    # FP64 accumulators, so repeated runs differ only where an FP64 rounding
-    # difference moves an FP32 result by one unit
     np.testing.assert_allclose(out["residuals"], res, rtol=1e-6)
     assert out["J"] == [500] * 4
+
+
+def test_run_stops_at_the_target(env):
+    """A run whose target is met after sweep t stops there: t + 1 sweeps, and
+    the cores are those after sweep t."""
+    torch, tts, jpolicy = env
+    say("run stops at target")
+    n, R = [20, 22, 18, 21], [1, 4, 5, 4, 1]
+    X2, plan2, cores2 = _problem(torch, tts, n, R, 1e-3, 21, 500)
+    res = [plan2.als_sweep(X2, cores2, residual=True) for _ in range(4)]
+    t_hit = next(i for i, r in enumerate(res) if r <= 5e-2)
+    X, plan, cores = _problem(torch, tts, n, R, 1e-3, 21, 500)
+    out = plan.run(X, cores, 8, 5e-2)
+    assert out["reached"] and out["sweeps"] == t_hit + 1
+    assert out["residual"] == pytest.approx(res[t_hit], rel=1e-4)
+    assert plan.residual(X, cores) == pytest.approx(res[t_hit], rel=1e-4)
 
 
 def test_run_with_policy_follows_its_rules(env):
@@ -158,10 +173,12 @@ def test_run_with_policy_follows_its_rules(env):
             while x % q == 0:
                 x //= q
         assert x == 1 and 64 <= J <= 4000
+        # a sweep that did not lower the residual (1 before the first) sends
+        # the next to the fallback size with the descriptor's lambda
         if t > 0 and not (res[t - 1] < (res[t - 2] if t >= 2 else 1.0)):
             assert J == fb and out["lambda"][t] == 1e-3
             nfb += 1
     assert nfb == out["fallbacks"]
-    assert out["reached"] == (out["residuals"][-1] <= 1e-2)
+    assert out["reached"] == (out["residual"] <= 1e-2)
     if out["reached"]:
         assert all(r > 1e-2 for r in out["residuals"][:-1])
