@@ -47,6 +47,10 @@ tt_status check_cores(tt_plan p, const void* const* cores) {
 tt_status gen_tables(tt_plan p) {
   TTProfScope ps(p, TT_PROF_TABLES);
   TT_HIP_TRY(launch_gen_tables(p, p->sweep));
+  if (p->tw_J != p->J) {   // roots of unity of the FFTs, once per J
+    TT_HIP_TRY(launch_fill_twiddles(p));
+    p->tw_J = p->J;
+  }
   p->override_tables = false;
   return TT_OK;
 }
@@ -270,6 +274,8 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_chat = take(2 * ws * p->J * p->chat_cols);
   p->o_pre = take(2 * ws * p->J * TT_MAX_RANK);
   p->o_suf = take(2 * ws * p->J * TT_MAX_RANK);
+  p->o_tw = take(2 * ws * p->J);
+  p->tw_J = 0;
   p->o_SH = take(ws * p->J * p->s_max);
   p->o_Y = take(ws * p->J * p->max_n);
   p->o_gram = take(gs * p->gram_chunks * p->s_max * (p->s_max + p->max_n));
@@ -308,6 +314,7 @@ tt_status tt_plan_bind_workspace(tt_plan p, void* dev_ws, size_t bytes) {
   if (((uintptr_t)dev_ws & 255) != 0) return tt_fail(TT_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   p->ws = static_cast<char*>(dev_ws);
   p->ws_bytes = bytes;
+  p->tw_J = 0;
   TT_HIP_TRY(hipMemsetAsync(p->ws + p->o_status, 0, 64, p->stream));
   return gen_tables(p);
 }

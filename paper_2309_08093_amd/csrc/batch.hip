@@ -282,6 +282,18 @@ struct tt_batch_s {
   std::vector<std::vector<int32_t>> tids;
   std::vector<std::vector<int64_t>> fpre, cpre, spre;
   size_t o_desc = 0, o_part = 0, o_counter = 0;
+  // batched core updates per step k: descriptors, QR classes, launch bounds
+  struct QrClass {
+    int32_t rmax, rpt, off, cnt;
+  };
+  std::vector<std::vector<BUpd>> upd;
+  std::vector<std::vector<QrClass>> qcls;
+  std::vector<std::vector<int32_t>> qidx, qfall;   // QR class members (index into upd[k]); per-problem QRs
+  size_t o_upd[TT_MAX_ORDER] = {}, o_qidx[TT_MAX_ORDER] = {};
+  int32_t g_gx[TT_MAX_ORDER] = {}, g_count[TT_MAX_ORDER] = {}, g_cbb[TT_MAX_ORDER] = {}, g_cols[TT_MAX_ORDER] = {};
+  size_t g_lchol[TT_MAX_ORDER] = {}, g_ltrsm[TT_MAX_ORDER] = {};
+  std::vector<const void*> upd_key;
+  hipEvent_t ev_main = nullptr;
   size_t o_tids[TT_MAX_ORDER], o_fpre[TT_MAX_ORDER], o_cpre[TT_MAX_ORDER], o_spre[TT_MAX_ORDER];
   int64_t Wmax = 8192;
   int64_t W[TT_MAX_ORDER];   // workgroups of the k >= 1 launch (0: device occupancy)
@@ -418,16 +430,54 @@ tt_status make_lanes(tt_batch b) {
   }
   TT_HIP_TRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
   TT_HIP_TRY(hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming));
+  TT_HIP_TRY(hipEventCreateWithFlags(&b->ev_main, hipEventDisableTiming));
   for (int k = 0; k < TT_MAX_ORDER; ++k) TT_HIP_TRY(hipEventCreateWithFlags(&b->ev_step[k], hipEventDisableTiming));
+  return TT_OK;
+}
+
+// Fill and upload the core-update descriptors (core pointers may change
+// between calls; the descriptors live in device memory, so a captured graph
+// stays valid when only their contents change).
+tt_status upload_upd(tt_batch b, void* const* const* cores) {
+  std::vector<const void*> key;
+  for (int i = 0; i < b->count; ++i)
+    for (int s2 = 0; s2 < b->plans[i]->d; ++s2) key.push_back(cores[i][s2]);
+  if (key == b->upd_key) return TT_OK;
+  for (int k = 0; k < b->max_d; ++k) {
+    for (size_t j = 0; j < b->upd[k].size(); ++j) {
+      const int i = b->tids[k][j];
+      tt_plan p = b->plans[i];
+      BUpd& u = b->upd[k][j];
+      u.SH = p->at<float>(p->o_SH);
+      u.Y = p->at<float>(p->o_Yall) + p->J * p->tab_off[k];
+      u.gpart = p->at<float>(p->o_gram);
+      u.gsum = p->at<double>(p->o_gsum);
+      u.Lg = p->at<double>(p->o_minv);
+      u.status = p->at<int32_t>(p->o_status);
+      u.G = static_cast<double*>(cores[i][k]);
+      const bool fall = std::find(b->qfall[k].begin(), b->qfall[k].end(), i) != b->qfall[k].end();
+      u.Gnext = (k + 1 < p->d && !fall) ? static_cast<double*>(cores[i][k + 1]) : nullptr;
+      u.R = p->at<double>(p->o_qrR);
+    }
+    if (!b->upd[k].empty())
+      TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_upd[k], b->upd[k].data(), sizeof(BUpd) * b->upd[k].size(),
+                                hipMemcpyHostToDevice, b->stream));
+  }
+  TT_HIP_TRY(hipStreamSynchronize(b->stream));
+  b->upd_key = key;
   return TT_OK;
 }
 
 // Enqueue one sweep of every problem.  The batched data sketches of all steps
 // need only X and the sweep's tables, so they go first, on the side stream,
-// one launch per step; the core updates of problem i run on lane i mod
-// kLanes and wait for the sketch of their step.  The next sweep's tables are
-// drawn once every sketch has read the current ones.  Everything forks from
-// and joins back into the batch stream.
+// one launch per step.  Per step k: the interface sketches (and the new
+// transform of core k - 1) run per problem on lanes (problem i on lane
+// i mod kLanes); then, on the batch stream, one launch each covers the Gram,
+// the solve (summed partials, Cholesky, substitution) and the QR + absorb of
+// every problem of order > k (QR grouped by register shape; QRs too tall for
+// registers run per problem).  The next sweep's tables are drawn once every
+// sketch has read the current ones.  Everything forks from and joins back
+// into the batch stream.
 tt_status enqueue_sweep(tt_batch b, void* const* const* cores) {
   tt_status st;
   if ((st = make_lanes(b))) return st;
@@ -449,31 +499,72 @@ tt_status enqueue_sweep(tt_batch b, void* const* const* cores) {
   TT_HIP_TRY(hipGetLastError());
   TT_HIP_TRY(hipEventRecord(b->ev_done, b->side));
   b->stream = main;
-  // core updates
+  std::vector<CoreDesc> cd(b->count);
+  std::vector<hipStream_t> keep(b->count);
+  for (int i = 0; i < b->count; ++i) {
+    keep[i] = b->plans[i]->stream;
+    cd[i] = tt_make_desc(b->plans[i], cores[i]);
+  }
+  auto lane_of = [&](int i) { return b->lane[i % kLanes]; };
+  auto restore = [&]() {
+    for (int i = 0; i < b->count; ++i) b->plans[i]->stream = keep[i];
+  };
+  // right-to-left orthogonalisation and core transforms, per problem
+  for (int i = 0; i < b->count; ++i) {
+    b->plans[i]->stream = lane_of(i);
+    if ((st = tt_sweep_begin(b->plans[i], reinterpret_cast<double* const*>(cores[i]), cd[i]))) {
+      restore();
+      return st;
+    }
+  }
+  for (int k = 0; k < b->max_d; ++k) {
+    for (int32_t i : b->tids[k]) {
+      tt_plan p = b->plans[i];
+      p->stream = lane_of(i);
+      hipError_t e = hipSuccess;
+      if (k >= 1) e = launch_core_fft(p, cd[i], k - 1, k - 1, -1);   // core k - 1 changed in step k - 1
+      if (e != hipSuccess || (st = tt_sweep_interface(p, cd[i], k))) {
+        restore();
+        return e != hipSuccess ? tt_fail(TT_ERR_HIP, "core transform launch failed: %s", hipGetErrorString(e)) : st;
+      }
+    }
+    for (int l = 0; l < kLanes; ++l) {
+      TT_HIP_TRY(hipEventRecord(b->ev_lane[l], b->lane[l]));
+      TT_HIP_TRY(hipStreamWaitEvent(main, b->ev_lane[l], 0));
+    }
+    TT_HIP_TRY(hipStreamWaitEvent(main, b->ev_step[k], 0));
+    const BUpd* du = reinterpret_cast<const BUpd*>(b->ws + b->o_upd[k]);
+    const int32_t nt = (int32_t)b->tids[k].size();
+    TT_HIP_TRY(launch_gram_batched(du, nt, b->g_gx[k], main));
+    TT_HIP_TRY(launch_solve_batched(du, nt, 0, b->g_count[k], b->g_cbb[k], b->g_lchol[k], b->g_ltrsm[k], main));
+    const int32_t* dq = reinterpret_cast<const int32_t*>(b->ws + b->o_qidx[k]);
+    for (const auto& c : b->qcls[k]) TT_HIP_TRY(launch_qr_batched(du, dq + c.off, c.cnt, c.rmax, c.rpt, main));
+    for (int32_t i : b->qfall[k]) {
+      tt_plan p = b->plans[i];
+      p->stream = main;
+      double* const* G = reinterpret_cast<double* const*>(cores[i]);
+      const int64_t m = p->r[k] * p->n[k], r = p->r[k + 1];
+      TT_HIP_TRY(launch_qr_core(p, G[k], m, r, 1, m));
+      TT_HIP_TRY(launch_absorb_left(p, G[k + 1], r, p->n[k + 1] * p->r[k + 2]));
+      p->stream = keep[i];
+    }
+    // R of the batched QRs into core k + 1 (the per-problem QRs above absorbed
+    // theirs; their descriptors carry no next core)
+    TT_HIP_TRY(launch_absorb_left_batched(du, nt, b->g_cols[k], main));
+    TT_HIP_TRY(hipEventRecord(b->ev_main, main));
+    for (int l = 0; l < kLanes; ++l) TT_HIP_TRY(hipStreamWaitEvent(b->lane[l], b->ev_main, 0));
+  }
+  // next sweep's tables, once the sketches are done
   for (int i = 0; i < b->count; ++i) {
     tt_plan p = b->plans[i];
-    const hipStream_t lane = b->lane[i % kLanes];
-    const hipStream_t keep = p->stream;
-    p->stream = lane;
-    const CoreDesc cd = tt_make_desc(p, cores[i]);
-    double* const* G = reinterpret_cast<double* const*>(cores[i]);
-    st = tt_sweep_begin(p, G, cd);
-    for (int k = 0; k < p->d && !st; ++k) {
-      if ((st = tt_sweep_interface(p, cd, k))) break;
-      const hipError_t e = hipStreamWaitEvent(lane, b->ev_step[k], 0);
-      if (e != hipSuccess) {
-        st = tt_fail(TT_ERR_HIP, "hipStreamWaitEvent failed: %s", hipGetErrorString(e));
-        break;
-      }
-      st = tt_sweep_update(p, G, cd, k, p->at<float>(p->o_Yall) + p->J * p->tab_off[k]);
+    p->stream = lane_of(i);
+    const hipError_t e = hipStreamWaitEvent(p->stream, b->ev_done, 0);
+    if (e != hipSuccess || (st = tt_sweep_end(p))) {
+      restore();
+      return e != hipSuccess ? tt_fail(TT_ERR_HIP, "hipStreamWaitEvent failed") : st;
     }
-    if (!st) {
-      const hipError_t e = hipStreamWaitEvent(lane, b->ev_done, 0);
-      st = e == hipSuccess ? tt_sweep_end(p) : tt_fail(TT_ERR_HIP, "hipStreamWaitEvent failed");
-    }
-    p->stream = keep;
-    if (st) return st;
   }
+  restore();
   for (int l = 0; l < kLanes; ++l) {
     TT_HIP_TRY(hipEventRecord(b->ev_lane[l], b->lane[l]));
     TT_HIP_TRY(hipStreamWaitEvent(main, b->ev_lane[l], 0));
@@ -560,6 +651,75 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
   }
   b->o_desc = o;
   o = align256(o + sizeof(BTensor) * count);
+  // batched core updates: shapes known now, pointers filled per call
+  b->upd.resize(b->max_d);
+  b->qcls.resize(b->max_d);
+  b->qidx.resize(b->max_d);
+  b->qfall.resize(b->max_d);
+  for (int k = 0; k < b->max_d; ++k) {
+    const int nt = (int)b->tids[k].size();
+    b->upd[k].resize(nt);
+    for (int j = 0; j < nt; ++j) {
+      tt_plan p = b->plans[b->tids[k][j]];
+      BUpd& u = b->upd[k][j];
+      u = BUpd{};
+      u.J = (int32_t)p->J;
+      u.s = (int32_t)(p->r[k] * p->r[k + 1]);
+      u.nk = (int32_t)p->n[k];
+      u.rk = (int32_t)p->r[k];
+      u.rk1 = (int32_t)p->r[k + 1];
+      u.chunks = (int32_t)tt_gram_chunks(p->J);
+      u.lambda = p->lambda;
+      const size_t np = (size_t)u.s * (u.s + 1) / 2;
+      int CB = 64;
+      while (CB > 1 && (np + (size_t)u.s * CB + u.s) * sizeof(double) > 150 * 1024) CB >>= 1;
+      u.CB = CB;
+      u.ncols_next = k + 1 < p->d ? (int32_t)(p->n[k + 1] * p->r[k + 2]) : 0;
+      const int tiles = ((u.s + 15) / 16) * ((u.s + u.nk + 15) / 16);
+      b->g_gx[k] = std::max(b->g_gx[k], ((tiles + 3) / 4) * u.chunks);
+      b->g_count[k] = std::max(b->g_count[k], u.s * (u.s + u.nk));
+      b->g_cbb[k] = std::max(b->g_cbb[k], (u.nk + CB - 1) / CB);
+      b->g_cols[k] = std::max(b->g_cols[k], u.ncols_next);
+      b->g_lchol[k] = std::max(b->g_lchol[k], np * sizeof(double));
+      b->g_ltrsm[k] = std::max(b->g_ltrsm[k], (np + (size_t)u.s * CB + u.s) * sizeof(double));
+      if (k + 1 < p->d) {
+        const int64_t m = (int64_t)u.rk * u.nk;
+        if (m > 4 * 512 || u.rk1 > 16) {
+          b->qfall[k].push_back(b->tids[k][j]);
+        } else {
+          const int32_t rmax = u.rk1 <= 4 ? 4 : (u.rk1 <= 8 ? 8 : (u.rk1 <= 12 ? 12 : 16));
+          const int32_t rpt = m <= 512 ? 1 : (m <= 1024 ? 2 : 4);
+          size_t c = 0;
+          while (c < b->qcls[k].size() && !(b->qcls[k][c].rmax == rmax && b->qcls[k][c].rpt == rpt)) ++c;
+          if (c == b->qcls[k].size()) b->qcls[k].push_back({rmax, rpt, 0, 0});
+          b->qcls[k][c].cnt += 1;
+        }
+      }
+    }
+    // class member lists, contiguous per class
+    int32_t off = 0;
+    for (auto& c : b->qcls[k]) {
+      c.off = off;
+      off += c.cnt;
+      c.cnt = 0;
+    }
+    b->qidx[k].assign(off, 0);
+    for (int j = 0; j < nt; ++j) {
+      tt_plan p = b->plans[b->tids[k][j]];
+      const BUpd& u = b->upd[k][j];
+      if (k + 1 >= p->d) continue;
+      const int64_t m = (int64_t)u.rk * u.nk;
+      if (m > 4 * 512 || u.rk1 > 16) continue;
+      const int32_t rmax = u.rk1 <= 4 ? 4 : (u.rk1 <= 8 ? 8 : (u.rk1 <= 12 ? 12 : 16));
+      const int32_t rpt = m <= 512 ? 1 : (m <= 1024 ? 2 : 4);
+      for (auto& c : b->qcls[k])
+        if (c.rmax == rmax && c.rpt == rpt) b->qidx[k][c.off + c.cnt++] = j;
+    }
+    b->o_upd[k] = o;
+    o = align256(o + sizeof(BUpd) * (nt + 1));
+    b->o_qidx[k] = o;
+    o = align256(o + sizeof(int32_t) * (b->qidx[k].size() + 1));
+  }
   for (int k = 0; k < b->max_d; ++k) {
     b->o_tids[k] = o;
     o = align256(o + sizeof(int32_t) * (b->tids[k].size() + 1));
@@ -605,8 +765,13 @@ tt_status tt_batch_bind_workspace(tt_batch b, void* dev_ws, size_t bytes) {
     TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_spre[k], b->spre[k].data(), sizeof(int64_t) * b->spre[k].size(),
                               hipMemcpyHostToDevice, b->stream));
   }
+  for (int k = 0; k < b->max_d; ++k)
+    if (!b->qidx[k].empty())
+      TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_qidx[k], b->qidx[k].data(), sizeof(int32_t) * b->qidx[k].size(),
+                                hipMemcpyHostToDevice, b->stream));
   TT_HIP_TRY(hipStreamSynchronize(b->stream));
   b->desc_valid = false;
+  b->upd_key.clear();
   drop_graph(b);
   return TT_OK;
 }
@@ -651,6 +816,7 @@ tt_status tt_batch_sweep(tt_batch b, const void* const* X, void* const* const* c
   if ((st = check_inputs(b, X, cores))) return st;
   if ((st = upload_desc(b, X))) return st;
   if ((st = make_lanes(b))) return st;   // streams and events exist before any capture
+  if ((st = upload_upd(b, cores))) return st;
   if (!b->use_graph) {
     if ((st = enqueue_sweep(b, cores))) return st;
   } else {
@@ -756,6 +922,7 @@ tt_status tt_batch_destroy(tt_batch b) {
     }
     (void)hipEventDestroy(b->ev_fork);
     (void)hipEventDestroy(b->ev_done);
+    (void)hipEventDestroy(b->ev_main);
     for (int k = 0; k < TT_MAX_ORDER; ++k) (void)hipEventDestroy(b->ev_step[k]);
   }
   if (b->cap) {

@@ -32,14 +32,15 @@ __device__ __forceinline__ short to_bf16(float x) {
   return (short)(u >> 16);
 }
 
+// One wave: output tile (blk * 4 + wave) of [SH^T SH | SH^T Y], K chunk `chunk`.
 template <typename T, typename AT>
-__global__ __launch_bounds__(256) void k_gram(const T* __restrict__ SH, const T* __restrict__ Y, AT* __restrict__ gpart,
-                                             int32_t J, int32_t s, int32_t nk, int32_t tiles_c, int32_t ntiles) {
+__device__ __forceinline__ void gram_body(const T* __restrict__ SH, const T* __restrict__ Y, AT* __restrict__ gpart,
+                                          int32_t J, int32_t s, int32_t nk, int32_t tiles_c, int32_t ntiles, int blk,
+                                          int chunk) {
   const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int tile = blk * 4 + (threadIdx.x >> 6);
   if (tile >= ntiles) return;
   const int tr = tile / tiles_c, tc = tile - tr * tiles_c;
-  const int chunk = blockIdx.y;
   const int k0 = chunk * kChunk;
   const int k1 = min(J, k0 + kChunk);
   const int ncol = s + nk;
@@ -74,6 +75,23 @@ __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ SH, const T*
       if (row < s && b_ok) gpart[((int64_t)chunk * s + row) * ncol + bcol] = acc[r];
     }
   }
+}
+
+template <typename T, typename AT>
+__global__ __launch_bounds__(256) void k_gram(const T* __restrict__ SH, const T* __restrict__ Y, AT* __restrict__ gpart,
+                                             int32_t J, int32_t s, int32_t nk, int32_t tiles_c, int32_t ntiles) {
+  gram_body<T, AT>(SH, Y, gpart, J, s, nk, tiles_c, ntiles, blockIdx.x, blockIdx.y);
+}
+
+// Batched: problem blockIdx.y; blockIdx.x runs over (tile block, chunk).
+__global__ __launch_bounds__(256) void kb_gram(const BUpd* __restrict__ d) {
+  const BUpd u = d[blockIdx.y];
+  const int tiles_r = (u.s + 15) / 16, tiles_c = (u.s + u.nk + 15) / 16;
+  const int ntiles = tiles_r * tiles_c;
+  const int tb = (ntiles + 3) / 4;
+  const int chunk = blockIdx.x / tb;
+  if (chunk >= u.chunks) return;
+  gram_body<float, float>(u.SH, u.Y, u.gpart, u.J, u.s, u.nk, tiles_c, ntiles, blockIdx.x - chunk * tb, chunk);
 }
 
 // BF16 operands, FP32 accumulation; K step 16 (4 per lane).
@@ -130,5 +148,11 @@ hipError_t launch_gram(const tt_plan_s* p, int k, const void* SH, const void* Y)
     hipLaunchKernelGGL((k_gram<float, float>), grid, dim3(256), 0, p->stream, static_cast<const float*>(SH),
                        static_cast<const float*>(Y), p->at<float>(p->o_gram), (int32_t)p->J, s, nk, tiles_c, ntiles);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_batched(const BUpd* d, int32_t nprob, int32_t gx, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_gram, dim3((unsigned)gx, (unsigned)nprob), dim3(256), 0, st, d);
   return hipGetLastError();
 }

@@ -28,18 +28,16 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 template <typename AT>
-__global__ __launch_bounds__(256) void k_chol_blk(const AT* __restrict__ gpart, int32_t chunks, int32_t s, int32_t ldg,
-                                                 double lambda, double* __restrict__ Lout,
-                                                 int32_t* __restrict__ status) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* L = reinterpret_cast<double*>(smem_raw);
-  __shared__ int bad;
+__device__ __forceinline__ void chol_blk_body(const AT* __restrict__ gpart, int32_t chunks, int32_t s, int32_t ldg, double lambda,
+                              double* __restrict__ Lout, int32_t* __restrict__ status, double* L, int& bad) {
   const int tid = threadIdx.x, T = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6, NW = T >> 6;
   const int np = s * (s + 1) / 2;
+  __shared__ double rdiag[16];   // reciprocal pivots of the current diagonal block
   if (tid == 0) bad = 0;
-  for (int c = wv; c < s; c += NW)
-    for (int i = c + lane; i < s; i += 64) {
+  // row i of M is contiguous in c: a wave per row, lanes along it
+  for (int i = wv; i < s; i += NW)
+    for (int c = lane; c <= i; c += 64) {
       double acc = 0.0;
       for (int q = 0; q < chunks; ++q) acc += (double)gpart[((int64_t)q * s + i) * ldg + c];
       L[lidx(i, c, s)] = acc + (i == c ? lambda : 0.0);
@@ -61,14 +59,24 @@ __global__ __launch_bounds__(256) void k_chol_blk(const AT* __restrict__ gpart, 
         const double dj = sqrt(djj), inv = 1.0 / dj;
         wave_sync();
         const int oj = coff(j, s) - j;
-        if (lane == 0) L[oj + j] = dj;
+        if (lane == 0) {
+          L[oj + j] = dj;
+          rdiag[j - j0] = inv;
+        }
         if (j + 1 + lane < j1) L[oj + j + 1 + lane] *= inv;
         wave_sync();
-        // trailing part of the block: pairs (i, c), j < c <= i < j1
-        const int m = j1 - j - 1;
-        for (int e = lane; e < m * m; e += 64) {
-          const int c = j + 1 + e / m, i = j + 1 + e % m;
-          if (i >= c) L[lidx(i, c, s)] -= L[oj + i] * L[oj + c];
+        // trailing part of the block, j < c <= i < j1: lane -> row
+        // i = j + 1 + (lane & 15), columns c = j + 1 + (lane >> 4) + 4 k
+        {
+          const int i = j + 1 + (lane & 15);
+          if (i < j1) {
+            const double li = L[oj + i];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int c = j + 1 + (lane >> 4) + 4 * k;
+              if (c <= i) L[lidx(i, c, s)] -= li * L[oj + c];
+            }
+          }
         }
         wave_sync();
       }
@@ -87,7 +95,7 @@ __global__ __launch_bounds__(256) void k_chol_blk(const AT* __restrict__ gpart, 
           double t = x[u];
 #pragma unroll
           for (int v = 0; v < u; ++v) t -= L[lidx(j0 + u, j0 + v, s)] * x[v];
-          x[u] = t / L[lidx(j0 + u, j0 + u, s)];
+          x[u] = t * rdiag[u];
         }
       }
 #pragma unroll
@@ -136,6 +144,15 @@ __global__ __launch_bounds__(256) void k_chol_blk(const AT* __restrict__ gpart, 
   for (int e = tid; e < np; e += T) Lout[e] = L[e];
 }
 
+template <typename AT>
+__global__ __launch_bounds__(256) void k_chol_blk(const AT* __restrict__ gpart, int32_t chunks, int32_t s, int32_t ldg,
+                                                 double lambda, double* __restrict__ Lout,
+                                                 int32_t* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int bad;
+  chol_blk_body<AT>(gpart, chunks, s, ldg, lambda, Lout, status, reinterpret_cast<double*>(smem_raw), bad);
+}
+
 // Blocked variant of the substitution: rows in blocks of 16.  Per block, one
 // thread per right-hand-side column solves the 16 x 16 diagonal triangle with
 // the column's 16 values in registers, then all threads update the rows the
@@ -144,16 +161,13 @@ __global__ __launch_bounds__(256) void k_chol_blk(const AT* __restrict__ gpart, 
 constexpr int kTB = 16;
 
 template <typename AT>
-__global__ __launch_bounds__(256) void k_prox_trsm_blk(const AT* __restrict__ gpart, int32_t chunks, int32_t s,
-                                                      int32_t ldg, double lambda, const double* __restrict__ Lg,
-                                                      const double* G_old, double* G_new, int32_t rk, int32_t nk,
-                                                      int32_t CB) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ void trsm_blk_body(const AT* __restrict__ gpart, int32_t chunks, int32_t s, int32_t ldg, double lambda,
+                              const double* __restrict__ Lg, const double* G_old, double* G_new, int32_t rk, int32_t nk,
+                              int32_t CB, int bx, double* L) {
   const int np = s * (s + 1) / 2;
-  double* L = reinterpret_cast<double*>(smem_raw);
   double* Bs = L + np;                 // s x CB, column block index fastest
   double* invd = Bs + (size_t)s * CB;  // s
-  const int c0 = blockIdx.x * CB;
+  const int c0 = bx * CB;
   const int tid = threadIdx.x, T = blockDim.x;
   for (int e = tid; e < np; e += T) L[e] = Lg[e];
   for (int e = tid; e < s * CB; e += T) {
@@ -277,6 +291,43 @@ __global__ __launch_bounds__(256) void k_prox_trsm_blk(const AT* __restrict__ gp
   }
 }
 
+template <typename AT>
+__global__ __launch_bounds__(256) void k_prox_trsm_blk(const AT* __restrict__ gpart, int32_t chunks, int32_t s,
+                                                      int32_t ldg, double lambda, const double* __restrict__ Lg,
+                                                      const double* G_old, double* G_new, int32_t rk, int32_t nk,
+                                                      int32_t CB) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  trsm_blk_body<AT>(gpart, chunks, s, ldg, lambda, Lg, G_old, G_new, rk, nk, CB, blockIdx.x,
+                    reinterpret_cast<double*>(smem_raw));
+}
+
+// Batched forms (problem blockIdx.y, or blockIdx.x for the one-workgroup
+// factorisation): the same bodies with each problem's sizes and buffers.
+__global__ void kb_gram_sum(const BUpd* __restrict__ d) {
+  const BUpd u = d[blockIdx.y];
+  const int64_t count = (int64_t)u.s * (u.s + u.nk);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  double acc = 0.0;
+  for (int q = 0; q < u.chunks; ++q) acc += (double)u.gpart[(int64_t)q * count + e];
+  u.gsum[e] = acc;
+}
+
+__global__ __launch_bounds__(256) void kb_chol(const BUpd* __restrict__ d) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int bad;
+  const BUpd u = d[blockIdx.x];
+  chol_blk_body<double>(u.gsum, 1, u.s, u.s + u.nk, u.lambda, u.Lg, u.status, reinterpret_cast<double*>(smem_raw), bad);
+}
+
+__global__ __launch_bounds__(256) void kb_trsm(const BUpd* __restrict__ d) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const BUpd u = d[blockIdx.y];
+  if ((int)blockIdx.x * u.CB >= u.nk) return;
+  trsm_blk_body<double>(u.gsum, 1, u.s, u.s + u.nk, u.lambda, u.Lg, u.G, u.G, u.rk, u.nk, u.CB, blockIdx.x,
+                        reinterpret_cast<double*>(smem_raw));
+}
+
 // out[e] = sum over the split-K chunks of the Gram / right-hand-side partials
 // (chunk q at q * count), in FP64 and in chunk order; one thread per entry.
 template <typename AT>
@@ -337,5 +388,20 @@ hipError_t launch_prox_from_gram(const tt_plan_s* p, int k, const double* G_old,
 hipError_t launch_copy_f64(const tt_plan_s* p, double* dst, const double* src, int64_t count) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_copy_f64, dim3(nblk(count, 256)), dim3(256), 0, p->stream, dst, src, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_batched(const BUpd* d, int32_t nprob, int32_t max_s, int32_t max_count, int32_t max_cb_blocks,
+                                size_t lds_chol, size_t lds_trsm, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  (void)max_s;
+  hipLaunchKernelGGL(kb_gram_sum, dim3(nblk(max_count, 256), (unsigned)nprob), dim3(256), 0, st, d);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = tt_allow_lds(kb_chol, lds_chol)) != hipSuccess) return e;
+  hipLaunchKernelGGL(kb_chol, dim3((unsigned)nprob), dim3(256), lds_chol, st, d);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = tt_allow_lds(kb_trsm, lds_trsm)) != hipSuccess) return e;
+  hipLaunchKernelGGL(kb_trsm, dim3((unsigned)max_cb_blocks, (unsigned)nprob), dim3(256), lds_trsm, st, d);
   return hipGetLastError();
 }

@@ -55,7 +55,9 @@ struct tt_plan_s {
   void* prof;                  // ProfState* when measurement is enabled, else null
 
   size_t o_tab, o_KI, o_KO, o_cnt, o_cursor, o_sortO, o_part, o_chat, o_pre, o_suf, o_SH, o_Y,
-      o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_fkeys, o_fsort, o_pol, o_gsum, o_resU, o_resH;
+      o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_fkeys, o_fsort, o_pol, o_gsum, o_resU, o_resH,
+      o_tw;
+  int64_t tw_J;                // J whose roots of unity the o_tw table holds (0: none)
   int64_t max_F;               // largest fibre count of one column over k >= 1
 
   template <typename T>
@@ -96,6 +98,7 @@ struct CoreDesc {
 
 // Launchers (each enqueues on p->stream; returns hipSuccess or the launch error)
 hipError_t launch_gen_tables(const tt_plan_s* p, int64_t sweep);
+hipError_t launch_fill_twiddles(const tt_plan_s* p);   // o_tw <- exp(-2 pi i e / J), e < J
 hipError_t launch_build_keys(const tt_plan_s* p, uint32_t* out, int64_t count, int first, int last);
 hipError_t launch_build_keys_modes(const tt_plan_s* p, uint32_t* out, int64_t count, const int* modes, int nm);
 hipError_t launch_outer_sort(const tt_plan_s* p);     // k = 0 bucket lists (modes 2..d-1)
@@ -131,6 +134,28 @@ inline hipError_t tt_allow_lds(K kernel, size_t bytes) {
 
 // FFT plan helper: factor J into radices {4,2,3,5,7}; returns false if J has other factors.
 bool tt_factor_fft(int64_t J, int* radix, int* nrad);
+
+// One problem's core update k within a batched step (FP32 work): the device
+// array of these drives the batched Gram, solve, QR and absorb launches
+// (batch.hip), one workgroup (or block set) per problem.
+struct BUpd {
+  const float* SH;      // J x s
+  const float* Y;       // J x n_k
+  float* gpart;         // Gram partials
+  double* gsum;         // summed Gram
+  double* Lg;           // Cholesky factor
+  int32_t* status;      // plan status words
+  double* G;            // core k (updated in place)
+  double* Gnext;        // core k + 1 (R absorbed), or null for k = d - 1
+  double* R;            // QR factor R
+  double lambda;
+  int32_t J, s, nk, rk, rk1, chunks, CB, ncols_next;   // ncols_next = n_{k+1} R_{k+2}
+};
+hipError_t launch_gram_batched(const BUpd* d, int32_t nprob, int32_t gx, hipStream_t st);
+hipError_t launch_solve_batched(const BUpd* d, int32_t nprob, int32_t max_s, int32_t max_count, int32_t max_cb_blocks,
+                                size_t lds_chol, size_t lds_trsm, hipStream_t st);
+hipError_t launch_qr_batched(const BUpd* d, const int32_t* idx, int32_t nidx, int32_t rmax, int32_t rpt, hipStream_t st);
+hipError_t launch_absorb_left_batched(const BUpd* d, int32_t nprob, int32_t max_cols, hipStream_t st);
 
 // pieces of one sweep (api.hip), shared by tt_als_sweep and the batched driver
 CoreDesc tt_make_desc(const tt_plan_s* p, const void* const* cores);
