@@ -680,7 +680,7 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
       b->g_count[k] = std::max(b->g_count[k], u.s * (u.s + u.nk));
       b->g_cbb[k] = std::max(b->g_cbb[k], (u.nk + CB - 1) / CB);
       b->g_cols[k] = std::max(b->g_cols[k], u.ncols_next);
-      b->g_lchol[k] = std::max(b->g_lchol[k], np * sizeof(double));
+      b->g_lchol[k] = std::max(b->g_lchol[k], tt_chol_lds_bytes(u.s));
       b->g_ltrsm[k] = std::max(b->g_ltrsm[k], (np + (size_t)u.s * CB + u.s) * sizeof(double));
       if (k + 1 < p->d) {
         const int64_t m = (int64_t)u.rk * u.nk;

@@ -1,138 +1,181 @@
 // FP64 proximal solve (Sec. 3, eq. (3.5)).
 //
-// Solve: the split-K Gram partials of [SH^T SH | SH^T Y] are summed in FP64;
-// M = SH^T SH + lambda I is factored M = L L^T (blocked right-looking
-// Cholesky, packed lower triangle in LDS, one workgroup); a second kernel
-// forms B = SH^T Y + lambda G_(2)^T for a block of columns and solves
-// L L^T Z = B by blocked forward and back substitution in LDS, one workgroup
-// per block of columns.
+// Solve: the split-K Gram partials of [SH^T SH | SH^T Y] are summed in FP64
+// (k_gram_sum); M = SH^T SH + lambda I is factored M = L L^T by a blocked
+// right-looking Cholesky (packed lower triangle in LDS, one workgroup); a
+// second kernel forms B = SH^T Y + lambda G_(2)^T for a block of columns and
+// solves L L^T Z = B by blocked forward and back substitution in LDS, one
+// workgroup per block of columns.
 // lambda > 0 makes M positive definite (Sec. 3, remark after eq. (3.5)); a
 // non-positive pivot records TT_ERR_NOT_SPD in the status word.
+//
+// Blocks of 16 pivots.  The critical path is the chain of pivots, so it is
+// kept short:
+//  * the 16 x 16 diagonal block is factored in the registers of one wave
+//    (lane (i, q) holds row i, columns q, q+4, q+8, q+12), pivots taken with
+//    readlane and column values broadcast with shuffles, and 1/sqrt(d) is the
+//    hardware estimate refined by two Newton steps (sqrt(d) = d / sqrt(d));
+//  * the panel below it is solved one row per thread against a dense
+//    transposed copy of the block and its reciprocal pivots;
+//  * the trailing updates (the Cholesky's lower triangle, the substitutions'
+//    remaining rows) are 16 x 16 tiles of FP64 MFMA (v_mfma_f64_16x16x4f64)
+//    over the block's 16 columns, operands read straight from LDS.
 #include "tt_internal.h"
 
 namespace {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBS = 16;                         // pivots per block
+constexpr int kLbLd = kBS + 1;                  // leading dimension of the dense block copy
+constexpr int kCholExtra = kBS * kLbLd + kBS;   // doubles after the packed triangle
 
 // Column-major packed lower triangle: column c holds rows c..s-1.
 __device__ __forceinline__ int coff(int c, int s) { return c * s - (c * (c - 1)) / 2; }
 __device__ __forceinline__ int lidx(int i, int c, int s) { return coff(c, s) + (i - c); }   // i >= c
 
-// Blocked right-looking Cholesky, blocks of 16 columns: the first wave
-// factors the 16 x 16 diagonal block (LDS, wave-ordered), one thread per row
-// solves the panel below it with the row's 16 values in registers, and all
-// threads apply the trailing update in 4 x 4 register tiles: three barriers
-// per block of 16 pivots.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// x of lane l (l the same in every lane)
+__device__ __forceinline__ double lane_value(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
 }
 
-template <typename AT>
-__device__ __forceinline__ void chol_blk_body(const AT* __restrict__ gpart, int32_t chunks, int32_t s, int32_t ldg, double lambda,
-                              double* __restrict__ Lout, int32_t* __restrict__ status, double* L, int& bad) {
+// 1/sqrt(d) for finite d > 0: the hardware estimate and two Newton steps
+// y <- y (3 - d y^2) / 2 (each step roughly doubles the correct bits).
+__device__ __forceinline__ double rsqrt_newton(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double hd = 0.5 * d;
+  y = y * (1.5 - hd * y * y);
+  y = y * (1.5 - hd * y * y);
+  return y;
+}
+
+__device__ __forceinline__ doublex4 mfma16(double a, double b, doublex4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// M (row i at M + i ldg, the lower triangle read) + lambda I = L L^T; L
+// packed to Lout.  LDS: the packed triangle, then the dense copy of the
+// current diagonal block (LbT[c kLbLd + i] = L[j0 + i][j0 + c]) and its
+// reciprocal pivots.
+__device__ __forceinline__ void chol_blk_body(const double* __restrict__ M, int32_t s, int32_t ldg, double lambda,
+                                              double* __restrict__ Lout, int32_t* __restrict__ status, double* L,
+                                              int& bad) {
   const int tid = threadIdx.x, T = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6, NW = T >> 6;
   const int np = s * (s + 1) / 2;
-  __shared__ double rdiag[16];   // reciprocal pivots of the current diagonal block
+  double* LbT = L + np;
+  double* rinv = LbT + kBS * kLbLd;
   if (tid == 0) bad = 0;
-  // row i of M is contiguous in c: a wave per row, lanes along it
-  for (int i = wv; i < s; i += NW)
-    for (int c = lane; c <= i; c += 64) {
-      double acc = 0.0;
-      for (int q = 0; q < chunks; ++q) acc += (double)gpart[((int64_t)q * s + i) * ldg + c];
-      L[lidx(i, c, s)] = acc + (i == c ? lambda : 0.0);
-    }
-  __syncthreads();
-  constexpr int B = 16;
-  const int nb = (s + B - 1) / B;
-  for (int ib = 0; ib < nb; ++ib) {
-    const int j0 = ib * B, j1 = min(s, j0 + B);
-    // (a) diagonal block, unblocked, by wave 0
-    if (wv == 0) {
-      int fail = 0;
-      for (int j = j0; j < j1; ++j) {
-        const double djj = L[lidx(j, j, s)];
-        if (!(djj > 0.0) || !isfinite(djj)) {
-          fail = 1;
-          break;
-        }
-        const double dj = sqrt(djj), inv = 1.0 / dj;
-        wave_sync();
-        const int oj = coff(j, s) - j;
-        if (lane == 0) {
-          L[oj + j] = dj;
-          rdiag[j - j0] = inv;
-        }
-        if (j + 1 + lane < j1) L[oj + j + 1 + lane] *= inv;
-        wave_sync();
-        // trailing part of the block, j < c <= i < j1: lane -> row
-        // i = j + 1 + (lane & 15), columns c = j + 1 + (lane >> 4) + 4 k
-        {
-          const int i = j + 1 + (lane & 15);
-          if (i < j1) {
-            const double li = L[oj + i];
+  // a wave per row (contiguous in c), four rows in flight
+  for (int i0 = wv; i0 < s; i0 += 4 * NW) {
+    double v[4][3];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const int c = j + 1 + (lane >> 4) + 4 * k;
-              if (c <= i) L[lidx(i, c, s)] -= li * L[oj + c];
-            }
-          }
-        }
-        wave_sync();
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+        const int i = i0 + q * NW, c = lane + 64 * h;
+        v[q][h] = (i < s && c <= i) ? M[(int64_t)i * ldg + c] : 0.0;
       }
-      if (lane == 0 && fail) bad = 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+        const int i = i0 + q * NW, c = lane + 64 * h;
+        if (i < s && c <= i) L[lidx(i, c, s)] = v[q][h] + (i == c ? lambda : 0.0);
+      }
+  }
+  __syncthreads();
+  for (int j0 = 0; j0 < s; j0 += kBS) {
+    const int bs = min(kBS, s - j0), j1 = j0 + bs;
+    // (a) diagonal block in the registers of wave 0; rows and columns beyond
+    // the matrix are padded with the identity
+    if (wv == 0) {
+      const int i = lane & 15, q = lane >> 4;
+      double a[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int c = q + 4 * k;
+        a[k] = (i < bs && c <= i) ? L[lidx(j0 + i, j0 + c, s)] : (i == c ? 1.0 : 0.0);
+      }
+      bool ok = true;
+#pragma unroll
+      for (int p = 0; p < kBS; ++p) {
+        const int src = p + 16 * (p & 3);   // lane holding A[p][p], slot p / 4
+        const double d = lane_value(a[p >> 2], src);
+        const bool good = d > 0.0 && isfinite(d);
+        ok = ok && good;
+        const double y = good ? rsqrt_newton(d) : 0.0;
+        if (q == (p & 3)) {
+          if (i == p) a[p >> 2] = d * y;
+          else if (i > p) a[p >> 2] *= y;
+        }
+        if (lane == 0) rinv[p] = y;
+        const double li = __shfl(a[p >> 2], i + 16 * (p & 3), 64);   // L[i][p]
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int c = q + 4 * k;
+          const double lc = __shfl(a[p >> 2], c + 16 * (p & 3), 64);   // L[c][p]
+          if (c > p && c <= i) a[k] -= li * lc;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int c = q + 4 * k;
+        if (i < bs && c <= i) L[lidx(j0 + i, j0 + c, s)] = a[k];
+        if (c < i) LbT[c * kLbLd + i] = a[k];   // zero in the padding rows
+      }
+      if (lane == 0 && !ok) bad = 1;
     }
     __syncthreads();
     if (bad) break;
     // (b) panel rows i >= j1: L[i][j0:j1] <- M[i][j0:j1] L_blk^-T
+    // (padding columns stay zero: rinv = 1 and zero couplings there, so the
+    // loops need no bounds and every load can be issued early)
     for (int i = j1 + tid; i < s; i += T) {
-      double x[B];
+      double x[kBS];
 #pragma unroll
-      for (int u = 0; u < B; ++u) x[u] = (j0 + u < j1) ? L[lidx(i, j0 + u, s)] : 0.0;
-#pragma unroll
-      for (int u = 0; u < B; ++u) {
-        if (j0 + u < j1) {
-          double t = x[u];
-#pragma unroll
-          for (int v = 0; v < u; ++v) t -= L[lidx(j0 + u, j0 + v, s)] * x[v];
-          x[u] = t * rdiag[u];
-        }
+      for (int u = 0; u < kBS; ++u) {
+        const double t = L[lidx(i, j0 + min(u, bs - 1), s)];
+        x[u] = u < bs ? t : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < B; ++u)
-        if (j0 + u < j1) L[lidx(i, j0 + u, s)] = x[u];
+      for (int u = 0; u < kBS; ++u) {
+        x[u] *= rinv[u];
+#pragma unroll
+        for (int v = u + 1; v < kBS; ++v) x[v] -= LbT[u * kLbLd + v] * x[u];
+      }
+#pragma unroll
+      for (int u = 0; u < kBS; ++u)
+        if (u < bs) L[lidx(i, j0 + u, s)] = x[u];
     }
     __syncthreads();
-    // (c) trailing update of the lower triangle beyond j1 in 4 x 4 tiles
+    // (c) trailing update A22 -= L21 L21^T, lower 16 x 16 tiles, a wave per tile
     const int R = s - j1;
     if (R > 0) {
-      const int nt = (R + 3) / 4;
-      for (int t = tid; t < nt * nt; t += T) {
-        const int ti = t / nt, tc = t % nt;
-        if (ti < tc) continue;
-        const int i0 = j1 + 4 * ti, c0 = j1 + 4 * tc;
-        double acc[4][4] = {};
-        for (int u = j0; u < j1; ++u) {
-          const int ou = coff(u, s) - u;
-          double li[4], lc[4];
+      const int nt = (R + 15) / 16;
+      const int rl = lane & 15, kq = lane >> 4;
+      int e = 0;
+      for (int ti = 0; ti < nt; ++ti)
+        for (int tc = 0; tc <= ti; ++tc, ++e) {
+          if (e % NW != wv) continue;
+          const int i0 = j1 + 16 * ti, c0 = j1 + 16 * tc;
+          doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            li[a] = (i0 + a < s) ? L[ou + i0 + a] : 0.0;
-            lc[a] = (c0 + a < s) ? L[ou + c0 + a] : 0.0;
+          for (int kk = 0; kk < kBS; kk += 4) {
+            const int u = kk + kq, uc = j0 + min(u, bs - 1);
+            const int ia = i0 + rl, ic = c0 + rl;
+            const double ta = L[lidx(min(ia, s - 1), uc, s)], tb = L[lidx(min(ic, s - 1), uc, s)];
+            const double av = (u < bs && ia < s) ? ta : 0.0;
+            const double bv = (u < bs && ic < s) ? tb : 0.0;
+            acc = mfma16(av, bv, acc);
           }
 #pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] += li[a] * lc[b];
+          for (int r = 0; r < 4; ++r) {   // D[row 4 r + kq][col rl]
+            const int row = i0 + 4 * r + kq, col = c0 + rl;
+            if (row < s && col <= row) L[lidx(row, col, s)] -= acc[r];
+          }
         }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int i = i0 + a, c = c0 + b;
-            if (i < s && c < s && i >= c) L[lidx(i, c, s)] -= acc[a][b];
-          }
-      }
     }
     __syncthreads();
   }
@@ -144,139 +187,129 @@ __device__ __forceinline__ void chol_blk_body(const AT* __restrict__ gpart, int3
   for (int e = tid; e < np; e += T) Lout[e] = L[e];
 }
 
-template <typename AT>
-__global__ __launch_bounds__(256) void k_chol_blk(const AT* __restrict__ gpart, int32_t chunks, int32_t s, int32_t ldg,
-                                                 double lambda, double* __restrict__ Lout,
-                                                 int32_t* __restrict__ status) {
+__global__ __launch_bounds__(256) void k_chol_blk(const double* __restrict__ M, int32_t s, int32_t ldg, double lambda,
+                                                 double* __restrict__ Lout, int32_t* __restrict__ status) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int bad;
-  chol_blk_body<AT>(gpart, chunks, s, ldg, lambda, Lout, status, reinterpret_cast<double*>(smem_raw), bad);
+  chol_blk_body(M, s, ldg, lambda, Lout, status, reinterpret_cast<double*>(smem_raw), bad);
 }
 
-// Blocked variant of the substitution: rows in blocks of 16.  Per block, one
-// thread per right-hand-side column solves the 16 x 16 diagonal triangle with
-// the column's 16 values in registers, then all threads update the rows the
-// block feeds in 4 x 4 register tiles: two barriers per block instead of one
-// per pivot.
-constexpr int kTB = 16;
-
-template <typename AT>
-__device__ __forceinline__ void trsm_blk_body(const AT* __restrict__ gpart, int32_t chunks, int32_t s, int32_t ldg, double lambda,
-                              const double* __restrict__ Lg, const double* G_old, double* G_new, int32_t rk, int32_t nk,
-                              int32_t CB, int bx, double* L) {
+// Columns c0 .. c0 + CB - 1 of B = (SH^T Y)(:, cols) + lambda G_(2)^T, the
+// right-hand side (row j of M + j ldg, columns s..), solved in place by
+// L y = B (forward) and L^T z = y (backward), 16 rows at a time: one wave
+// (a thread per column) solves the block's triangle, then all waves update
+// the rows the block feeds with 16 x 16 MFMA tiles.  LDS: L (packed), B
+// (s x CB, row-major), 1 / L[j][j].
+__device__ __forceinline__ void trsm_blk_body(const double* __restrict__ M, int32_t s, int32_t ldg, double lambda,
+                                              const double* __restrict__ Lg, const double* G_old, double* G_new,
+                                              int32_t rk, int32_t nk, int32_t CB, int bx, double* L) {
   const int np = s * (s + 1) / 2;
-  double* Bs = L + np;                 // s x CB, column block index fastest
-  double* invd = Bs + (size_t)s * CB;  // s
+  double* Bs = L + np;
+  double* invd = Bs + (size_t)s * CB;
   const int c0 = bx * CB;
   const int tid = threadIdx.x, T = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6, NW = T >> 6;
+  const int rl = lane & 15, kq = lane >> 4;
   for (int e = tid; e < np; e += T) L[e] = Lg[e];
   for (int e = tid; e < s * CB; e += T) {
     const int j = e / CB, cl = e - j * CB;
     const int col = c0 + cl;
     double acc = 0.0;
     if (col < nk) {
-      for (int q = 0; q < chunks; ++q) acc += (double)gpart[((int64_t)q * s + j) * ldg + s + col];
       const int a = j % rk, b = j / rk;
-      acc += lambda * G_old[a + (int64_t)rk * (col + (int64_t)nk * b)];
+      acc = M[(int64_t)j * ldg + s + col] + lambda * G_old[a + (int64_t)rk * (col + (int64_t)nk * b)];
     }
     Bs[e] = acc;
   }
   __syncthreads();   // every read of G_old for these columns precedes the writes below
   for (int j = tid; j < s; j += T) invd[j] = 1.0 / L[lidx(j, j, s)];
   __syncthreads();
-  const int nb = (s + kTB - 1) / kTB;
-  const int ctiles = (CB + 3) / 4;
+  const int ctiles = (CB + 15) / 16;
   // forward: L y = B
-  for (int ib = 0; ib < nb; ++ib) {
-    const int j0 = ib * kTB, j1 = min(s, j0 + kTB);
+  for (int j0 = 0; j0 < s; j0 += kBS) {
+    const int bs = min(kBS, s - j0), j1 = j0 + bs;
     if (tid < CB) {
-      double x[kTB];
+      // rows beyond the matrix: x = 0, so clamped (in-range) loads suffice
+      double x[kBS];
 #pragma unroll
-      for (int u = 0; u < kTB; ++u) x[u] = (j0 + u < j1) ? Bs[(j0 + u) * CB + tid] : 0.0;
-#pragma unroll
-      for (int u = 0; u < kTB; ++u) {
-        if (j0 + u < j1) {
-          x[u] *= invd[j0 + u];
-          const int oj = coff(j0 + u, s) - (j0 + u);
-#pragma unroll
-          for (int v = u + 1; v < kTB; ++v)
-            if (j0 + v < j1) x[v] -= L[oj + j0 + v] * x[u];
-        }
+      for (int u = 0; u < kBS; ++u) {
+        const double t = Bs[(j0 + min(u, bs - 1)) * CB + tid];
+        x[u] = u < bs ? t : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < kTB; ++u)
-        if (j0 + u < j1) Bs[(j0 + u) * CB + tid] = x[u];
+      for (int u = 0; u < kBS; ++u) {
+        const int ju = min(j0 + u, s - 1);
+        x[u] *= invd[ju];
+#pragma unroll
+        for (int v = u + 1; v < kBS; ++v) x[v] -= L[lidx(min(j0 + v, s - 1), ju, s)] * x[u];
+      }
+#pragma unroll
+      for (int u = 0; u < kBS; ++u)
+        if (u < bs) Bs[(j0 + u) * CB + tid] = x[u];
     }
     __syncthreads();
-    const int rows = s - j1;
-    if (rows > 0) {
-      const int rtiles = (rows + 3) / 4;
-      for (int t = tid; t < rtiles * ctiles; t += T) {
-        const int i0 = j1 + (t / ctiles) * 4, cc = (t % ctiles) * 4;
-        double acc[4][4] = {};
-        for (int j = j0; j < j1; ++j) {
-          const int oj = coff(j, s) - j;
-          double lv[4], yv[4];
+    // rows i >= j1: B[i][:] -= L[i][j0:j1] y[j0:j1][:]
+    const int rtiles = (s - j1 + 15) / 16;
+    for (int t = wv; t < rtiles * ctiles; t += NW) {
+      const int i0 = j1 + 16 * (t / ctiles), cc = 16 * (t % ctiles);
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int a = 0; a < 4; ++a) lv[a] = (i0 + a < s) ? L[oj + i0 + a] : 0.0;
+      for (int kk = 0; kk < kBS; kk += 4) {
+        const int u = kk + kq, uc = j0 + min(u, bs - 1);
+        const int ia = i0 + rl, cb = cc + rl;
+        const double ta = L[lidx(min(ia, s - 1), uc, s)], tb = Bs[uc * CB + min(cb, CB - 1)];
+        const double av = (u < bs && ia < s) ? ta : 0.0;
+        const double bv = (u < bs && cb < CB) ? tb : 0.0;
+        acc = mfma16(av, bv, acc);
+      }
 #pragma unroll
-          for (int b = 0; b < 4; ++b) yv[b] = (cc + b < CB) ? Bs[j * CB + cc + b] : 0.0;
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] += lv[a] * yv[b];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-            if (i0 + a < s && cc + b < CB) Bs[(i0 + a) * CB + cc + b] -= acc[a][b];
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + 4 * r + kq, col = cc + rl;
+        if (row < s && col < CB) Bs[row * CB + col] -= acc[r];
       }
     }
     __syncthreads();
   }
   // backward: L^T z = y
-  for (int ib = nb - 1; ib >= 0; --ib) {
-    const int j0 = ib * kTB, j1 = min(s, j0 + kTB);
+  for (int j0 = ((s - 1) / kBS) * kBS; j0 >= 0; j0 -= kBS) {
+    const int bs = min(kBS, s - j0);
     if (tid < CB) {
-      double x[kTB];
+      double x[kBS];
 #pragma unroll
-      for (int u = 0; u < kTB; ++u) x[u] = (j0 + u < j1) ? Bs[(j0 + u) * CB + tid] : 0.0;
-#pragma unroll
-      for (int u = kTB - 1; u >= 0; --u) {
-        if (j0 + u < j1) {
-          x[u] *= invd[j0 + u];
-#pragma unroll
-          for (int v = 0; v < u; ++v) x[v] -= L[lidx(j0 + u, j0 + v, s)] * x[u];
-        }
+      for (int u = 0; u < kBS; ++u) {
+        const double t = Bs[(j0 + min(u, bs - 1)) * CB + tid];
+        x[u] = u < bs ? t : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < kTB; ++u)
-        if (j0 + u < j1) Bs[(j0 + u) * CB + tid] = x[u];
+      for (int u = kBS - 1; u >= 0; --u) {
+        const int ju = min(j0 + u, s - 1);
+        x[u] *= invd[ju];
+#pragma unroll
+        for (int v = 0; v < u; ++v) x[v] -= L[lidx(ju, j0 + v, s)] * x[u];
+      }
+#pragma unroll
+      for (int u = 0; u < kBS; ++u)
+        if (u < bs) Bs[(j0 + u) * CB + tid] = x[u];
     }
     __syncthreads();
-    const int rows = j0;
-    if (rows > 0) {
-      const int rtiles = (rows + 3) / 4;
-      for (int t = tid; t < rtiles * ctiles; t += T) {
-        const int i0 = (t / ctiles) * 4, cc = (t % ctiles) * 4;
-        double acc[4][4] = {};
-        for (int j = j0; j < j1; ++j) {
-          double lv[4], zv[4];
+    // rows i < j0: B[i][:] -= sum_u L[j0 + u][i] z[j0 + u][:]
+    const int rtiles = j0 / 16;
+    for (int t = wv; t < rtiles * ctiles; t += NW) {
+      const int i0 = 16 * (t / ctiles), cc = 16 * (t % ctiles);
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int a = 0; a < 4; ++a) lv[a] = (i0 + a < rows) ? L[lidx(j, i0 + a, s)] : 0.0;
+      for (int kk = 0; kk < kBS; kk += 4) {
+        const int u = kk + kq, uc = j0 + min(u, bs - 1);
+        const int cb = cc + rl;
+        const double ta = L[lidx(uc, i0 + rl, s)], tb = Bs[uc * CB + min(cb, CB - 1)];
+        const double av = u < bs ? ta : 0.0;
+        const double bv = (u < bs && cb < CB) ? tb : 0.0;
+        acc = mfma16(av, bv, acc);
+      }
 #pragma unroll
-          for (int b = 0; b < 4; ++b) zv[b] = (cc + b < CB) ? Bs[j * CB + cc + b] : 0.0;
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] += lv[a] * zv[b];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-            if (i0 + a < rows && cc + b < CB) Bs[(i0 + a) * CB + cc + b] -= acc[a][b];
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + 4 * r + kq, col = cc + rl;
+        if (col < CB) Bs[row * CB + col] -= acc[r];
       }
     }
     __syncthreads();
@@ -291,14 +324,12 @@ __device__ __forceinline__ void trsm_blk_body(const AT* __restrict__ gpart, int3
   }
 }
 
-template <typename AT>
-__global__ __launch_bounds__(256) void k_prox_trsm_blk(const AT* __restrict__ gpart, int32_t chunks, int32_t s,
-                                                      int32_t ldg, double lambda, const double* __restrict__ Lg,
+__global__ __launch_bounds__(256) void k_prox_trsm_blk(const double* __restrict__ M, int32_t s, int32_t ldg,
+                                                      double lambda, const double* __restrict__ Lg,
                                                       const double* G_old, double* G_new, int32_t rk, int32_t nk,
                                                       int32_t CB) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  trsm_blk_body<AT>(gpart, chunks, s, ldg, lambda, Lg, G_old, G_new, rk, nk, CB, blockIdx.x,
-                    reinterpret_cast<double*>(smem_raw));
+  trsm_blk_body(M, s, ldg, lambda, Lg, G_old, G_new, rk, nk, CB, blockIdx.x, reinterpret_cast<double*>(smem_raw));
 }
 
 // Batched forms (problem blockIdx.y, or blockIdx.x for the one-workgroup
@@ -317,15 +348,15 @@ __global__ __launch_bounds__(256) void kb_chol(const BUpd* __restrict__ d) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int bad;
   const BUpd u = d[blockIdx.x];
-  chol_blk_body<double>(u.gsum, 1, u.s, u.s + u.nk, u.lambda, u.Lg, u.status, reinterpret_cast<double*>(smem_raw), bad);
+  chol_blk_body(u.gsum, u.s, u.s + u.nk, u.lambda, u.Lg, u.status, reinterpret_cast<double*>(smem_raw), bad);
 }
 
 __global__ __launch_bounds__(256) void kb_trsm(const BUpd* __restrict__ d) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const BUpd u = d[blockIdx.y];
   if ((int)blockIdx.x * u.CB >= u.nk) return;
-  trsm_blk_body<double>(u.gsum, 1, u.s, u.s + u.nk, u.lambda, u.Lg, u.G, u.G, u.rk, u.nk, u.CB, blockIdx.x,
-                        reinterpret_cast<double*>(smem_raw));
+  trsm_blk_body(u.gsum, u.s, u.s + u.nk, u.lambda, u.Lg, u.G, u.G, u.rk, u.nk, u.CB, blockIdx.x,
+                reinterpret_cast<double*>(smem_raw));
 }
 
 // out[e] = sum over the split-K chunks of the Gram / right-hand-side partials
@@ -363,23 +394,24 @@ hipError_t prox_t(const tt_plan_s* p, int k, const double* G_old, double* G_new)
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t np = (size_t)s * (s + 1) / 2;
-  const size_t lds1 = np * sizeof(double);
-  if ((e = tt_allow_lds(k_chol_blk<double>, lds1)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chol_blk<double>, dim3(1), dim3(256), lds1, p->stream, gsum, 1, s, ldg, p->lambda, Lg,
-                     status);
+  const size_t lds1 = tt_chol_lds_bytes(s);
+  if ((e = tt_allow_lds(k_chol_blk, lds1)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chol_blk, dim3(1), dim3(256), lds1, p->stream, gsum, s, ldg, p->lambda, Lg, status);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // right-hand-side block: as wide as fits next to L in 150 KB of LDS, at
   // most 64 columns (one thread per column solves the diagonal blocks)
   int CB = 64;
   while (CB > 1 && (np + (size_t)s * CB + s) * sizeof(double) > 150 * 1024) CB >>= 1;
   const size_t lds2 = (np + (size_t)s * CB + s) * sizeof(double);
-  if ((e = tt_allow_lds(k_prox_trsm_blk<double>, lds2)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_prox_trsm_blk<double>, dim3(nblk(nk, CB)), dim3(256), lds2, p->stream, gsum, 1, s, ldg,
+  if ((e = tt_allow_lds(k_prox_trsm_blk, lds2)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_prox_trsm_blk, dim3(nblk(nk, CB)), dim3(256), lds2, p->stream, gsum, s, ldg,
                      p->lambda, Lg, G_old, G_new, (int32_t)p->r[k], nk, CB);
   return hipGetLastError();
 }
 
 }  // namespace
+
+size_t tt_chol_lds_bytes(int64_t s) { return (size_t)(s * (s + 1) / 2 + kCholExtra) * sizeof(double); }
 
 hipError_t launch_prox_from_gram(const tt_plan_s* p, int k, const double* G_old, double* G_new) {
   return p->wdt == TT_F64 ? prox_t<double>(p, k, G_old, G_new) : prox_t<float>(p, k, G_old, G_new);

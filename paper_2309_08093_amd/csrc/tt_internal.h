@@ -152,6 +152,7 @@ struct BUpd {
   int32_t J, s, nk, rk, rk1, chunks, CB, ncols_next;   // ncols_next = n_{k+1} R_{k+2}
 };
 hipError_t launch_gram_batched(const BUpd* d, int32_t nprob, int32_t gx, hipStream_t st);
+size_t tt_chol_lds_bytes(int64_t s);   // dynamic LDS of the Cholesky kernel for an s x s system
 hipError_t launch_solve_batched(const BUpd* d, int32_t nprob, int32_t max_s, int32_t max_count, int32_t max_cb_blocks,
                                 size_t lds_chol, size_t lds_trsm, hipStream_t st);
 hipError_t launch_qr_batched(const BUpd* d, const int32_t* idx, int32_t nidx, int32_t rmax, int32_t rpt, hipStream_t st);
