@@ -332,13 +332,16 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the mixed + learned-J vs plain FP32 time-to-target comparison")
     ap.add_argument("--cpu-entries", type=int, default=128_000_000)
-    ap.add_argument("--serial", action="store_true",
-                    help="keep the data sketches on the plan's stream (no overlap with the solve chain)")
+    ap.add_argument("--overlap", action="store_true",
+                    help="time the overlapped schedule (data sketches on a second stream beside the core "
+                         "updates) instead of the serial one")
+    ap.add_argument("--serial", action="store_true", help="the serial schedule (the default)")
     ap.add_argument("--reserve-cus", type=int, default=None,
                     help="CUs kept free of the overlapped data sketches (library default if omitted)")
     ap.add_argument("--probe-traffic", action="store_true",
                     help="run each data sketch once and one device copy of X, then exit (for HBM counter runs)")
     args = ap.parse_args()
+    args.serial = not args.overlap
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the data sketch would shard by slabs of the last mode plus one all-reduce of J x n_k "
@@ -438,6 +441,25 @@ def main():
         "roofline_other_sketch": rf_other,
         "kernels_ms_per_step": kernels,
     }
+
+    # the other schedule, for comparison: the overlapped one runs the data
+    # sketches beside the core updates, so its sweep is a little shorter but
+    # every kernel's launch time includes the sharing of the GPU
+    if args.serial and not args.no_isolated:
+        plan2 = tts.Plan(n, R, J, lam, seed=args.seed, x_dtype=cfg["xd"], work_dtype=cfg["wd"], gram=cfg["gram"],
+                         device=dev, serial=False)
+        cores3 = [tts.core_to_device(c, dev) for c in init]
+        for _ in range(args.warmup):
+            plan2.als_sweep(X, cores3)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            plan2.als_sweep(X, cores3)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms2 = ev0.elapsed_time(ev1) / args.steps
+        out["overlapped_schedule"] = {"ms_per_step": ms2, "value": d * N / (ms2 * 1e-3), "unit": "entries/s"}
+        del plan2, cores3
 
     # each data sketch alone on the plan's stream (no concurrent core updates)
     iso = {}

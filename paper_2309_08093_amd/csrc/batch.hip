@@ -68,6 +68,9 @@ __device__ __forceinline__ int lpf_log2_of(int n0) {
 }
 
 // ---------------------------------------------------------------- k >= 1
+constexpr int kBFib = 16;   // k >= 1: fibres per lane group per load batch
+constexpr int kB0Fib = 8;   // k = 0: fibres per lane group per load batch
+
 template <int NJ>
 __global__ __launch_bounds__(256) void k_bsketch_k(const BTensor* __restrict__ T, const int32_t* __restrict__ tids,
                                                    const int64_t* __restrict__ fpre, const int64_t* __restrict__ cpre,
@@ -118,26 +121,32 @@ __global__ __launch_bounds__(256) void k_bsketch_k(const BTensor* __restrict__ T
       uint32_t keyl = 0;
       int64_t offl = 0;
       if (fl < we) {
-        int64_t rho = fl / M, mu = fl - rho * M;
-        offl = ((rho * nk + c) * M + mu) * (int64_t)n0;
+        // a problem's fibre indices fit in 32 bits (its size is checked at plan time)
+        const uint32_t M32 = (uint32_t)M;
+        uint32_t rho = (uint32_t)fl / M32, mu = (uint32_t)fl - rho * M32;
+        offl = (((int64_t)rho * nk + c) * M + mu) * (int64_t)n0;
         for (int s = 1; s < k; ++s) {
-          const int64_t i = mu % t.n[s];
-          mu /= t.n[s];
-          keyl = key_add(keyl, t.tab[t.toff[s] + i], J);
+          const uint32_t ns = (uint32_t)t.n[s];
+          const uint32_t q = mu / ns;
+          keyl = key_add(keyl, t.tab[t.toff[s] + (mu - q * ns)], J);
+          mu = q;
         }
         for (int s = k + 1; s < d; ++s) {
-          const int64_t i = rho % t.n[s];
-          rho /= t.n[s];
-          keyl = key_add(keyl, t.tab[t.toff[s] + i], J);
+          const uint32_t ns = (uint32_t)t.n[s];
+          const uint32_t q = rho / ns;
+          keyl = key_add(keyl, t.tab[t.toff[s] + (rho - q * ns)], J);
+          rho = q;
         }
       }
       const int nb = (we - fb) < 64 ? (int)(we - fb) : 64;
-      for (int u0 = 0; u0 < nb; u0 += 4 * G) {
-        float x[4][NJ];
-        uint32_t kb[4], ks[4];
-        bool ok[4];
+      // kBFib fibres per lane group in flight: short fibres need many loads
+      // outstanding per wave to cover the memory latency
+      for (int u0 = 0; u0 < nb; u0 += kBFib * G) {
+        float x[kBFib][NJ];
+        uint32_t kb[kBFib], ks[kBFib];
+        bool ok[kBFib];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kBFib; ++u) {
           const int idx = u0 + u * G + gi;
           ok[u] = idx < nb;
           const uint32_t key = (uint32_t)__shfl((int)keyl, idx & 63, 64);
@@ -153,7 +162,7 @@ __global__ __launch_bounds__(256) void k_bsketch_k(const BTensor* __restrict__ T
           }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < kBFib; ++u)
 #pragma unroll
           for (int q = 0; q < NJ; ++q) {
             const int i0 = v + LPF * q;
@@ -228,18 +237,25 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
     for (uint32_t e0 = beg; e0 < end; e0 += 64) {
       const uint32_t itl = (e0 + lane < end) ? t.sorted[e0 + lane] : 0u;
       const int nb = (end - e0) < 64u ? (int)(end - e0) : 64;
-      for (int u0 = 0; u0 < nb; u0 += G) {
-        const int idx = u0 + gi;
-        const uint32_t item = (uint32_t)__shfl((int)itl, idx & 63, 64);
-        if (idx < nb) {
-          const uint32_t sg = (item ^ t1) & TT_KEY_SIGN;
+      for (int u0 = 0; u0 < nb; u0 += kB0Fib * G) {
+        float x[kB0Fib][NJ];
+        uint32_t sg[kB0Fib];
+#pragma unroll
+        for (int u = 0; u < kB0Fib; ++u) {   // all loads first, then the sums
+          const int idx = u0 + u * G + gi;
+          const uint32_t item = (uint32_t)__shfl((int)itl, idx & 63, 64);
+          sg[u] = (item ^ t1) & TT_KEY_SIGN;
           const float* base = t.X + ((int64_t)(item & TT_KEY_MASK) * n1 + i1) * (int64_t)n0;
 #pragma unroll
           for (int q = 0; q < NJ; ++q) {
             const int i0 = v + LPF * q;
-            if (i0 < n0) acc[q] += signed_f64(__builtin_nontemporal_load(base + i0), sg);
+            x[u][q] = (idx < nb && i0 < n0) ? __builtin_nontemporal_load(base + i0) : 0.0f;
           }
         }
+#pragma unroll
+        for (int u = 0; u < kB0Fib; ++u)   // in list order, as before
+#pragma unroll
+          for (int q = 0; q < NJ; ++q) acc[q] += signed_f64(x[u][q], sg[u]);
       }
     }
   }
@@ -613,6 +629,10 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
       return st;
     }
     b->plans.push_back(p);
+    if (p->N / p->n[0] > (int64_t)UINT32_MAX) {   // fibre indices are 32-bit in the batched sketch
+      tt_batch_destroy(b);
+      return tt_fail(TT_ERR_SHAPE, "problem %d: more than 2^32 mode-0 fibres for the batched form", i);
+    }
     b->plan_off.push_back(o);
     o = align256(o + ws);
     if (p->d > b->max_d) b->max_d = p->d;

@@ -187,7 +187,9 @@ def test_interface_sketch(tts, n, R, J, wd):
 # ------------------------------------------------------------------ prox solve
 @pytest.mark.parametrize("r0,nk,r1,J,wd,gram", [(3, 16, 3, 256, "f64", "work"), (10, 200, 10, 4000, "f32", "work"),
                                                 (12, 37, 12, 500, "f32", "work"), (1, 50, 8, 64, "f64", "work"),
-                                                (8, 64, 8, 3000, "f32", "bf16"), (13, 9, 13, 300, "f64", "work")])
+                                                (8, 64, 8, 3000, "f32", "bf16"), (13, 9, 13, 300, "f64", "work"),
+                                                # s = 180, the largest system: 8 right-hand sides per block
+                                                (12, 20, 15, 500, "f64", "work")])
 def test_prox_solve(tts, r0, nk, r1, J, wd, gram):
     say("prox", r0, nk, r1, J, wd, gram)
     g = synth.rng(9)
@@ -238,7 +240,11 @@ def test_prox_not_spd_reported(tts):
 
 # ------------------------------------------------------------------ QR / orthogonalisation
 @pytest.mark.parametrize("n,R", [([16, 16, 16, 16], [1, 3, 3, 3, 1]), ([200, 20, 7], [1, 10, 7, 1]),
-                                 ([5, 4, 6, 3], [1, 5, 12, 3, 1]), ([3, 50, 40], [1, 3, 16, 1])])
+                                 ([5, 4, 6, 3], [1, 5, 12, 3, 1]), ([3, 50, 40], [1, 3, 16, 1]),
+                                 # register QR with 4 and 8 rows per thread (1600 and 2400 rows)
+                                 ([4, 400, 6], [1, 4, 6, 1]),
+                                 # 16 columns with 4 rows per thread; 4800 rows (global-memory QR)
+                                 ([11, 120, 16], [1, 11, 16, 1]), ([2, 300, 16], [1, 2, 16, 1])])
 def test_orthogonalisation(tts, n, R):
     say("orth", n, R)
     cores = synth.random_cores(n, R, 10)
