@@ -279,7 +279,7 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_SH = take(ws * p->J * p->s_max);
   p->o_Y = take(ws * p->J * p->max_n);
   p->o_gram = take(gs * p->gram_chunks * p->s_max * (p->s_max + p->max_n));
-  p->o_minv = take(sizeof(double) * p->s_max * p->s_max);
+  p->o_minv = take(sizeof(double) * tt_chol_out_doubles(p->s_max));   // L and its diagonal-block inverses
   p->o_gsum = take(sizeof(double) * p->s_max * (p->s_max + p->max_n));
   p->o_W = take(sizeof(double));
   p->o_qrA = take(sizeof(double) * p->qr_m * p->r_max);

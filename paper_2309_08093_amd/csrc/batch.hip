@@ -692,7 +692,7 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
       u.lambda = p->lambda;
       const size_t np = (size_t)u.s * (u.s + 1) / 2;
       int CB = 64;
-      while (CB > 1 && (np + (size_t)u.s * CB + u.s) * sizeof(double) > 150 * 1024) CB >>= 1;
+      while (CB > 1 && (np + (size_t)u.s * CB) * sizeof(double) > 150 * 1024) CB >>= 1;
       u.CB = CB;
       u.ncols_next = k + 1 < p->d ? (int32_t)(p->n[k + 1] * p->r[k + 2]) : 0;
       const int tiles = ((u.s + 15) / 16) * ((u.s + u.nk + 15) / 16);
@@ -701,7 +701,7 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
       b->g_cbb[k] = std::max(b->g_cbb[k], (u.nk + CB - 1) / CB);
       b->g_cols[k] = std::max(b->g_cols[k], u.ncols_next);
       b->g_lchol[k] = std::max(b->g_lchol[k], tt_chol_lds_bytes(u.s));
-      b->g_ltrsm[k] = std::max(b->g_ltrsm[k], (np + (size_t)u.s * CB + u.s) * sizeof(double));
+      b->g_ltrsm[k] = std::max(b->g_ltrsm[k], (np + (size_t)u.s * CB) * sizeof(double));
       if (k + 1 < p->d) {
         const int64_t m = (int64_t)u.rk * u.nk;
         if (m > 4 * 512 || u.rk1 > 16) {

@@ -16,7 +16,9 @@
 //    readlane and column values broadcast with shuffles, and 1/sqrt(d) is the
 //    hardware estimate refined by two Newton steps (sqrt(d) = d / sqrt(d));
 //  * the panel below it is solved one row per thread against a dense
-//    transposed copy of the block and its reciprocal pivots;
+//    transposed copy of the block and its reciprocal pivots, and 16 more
+//    threads invert the block the same way (W_b = L_b^-1, stored after the
+//    packed triangle), so the substitution's diagonal steps are products;
 //  * the trailing updates (the Cholesky's lower triangle, the substitutions'
 //    remaining rows) are 16 x 16 tiles of FP64 MFMA (v_mfma_f64_16x16x4f64)
 //    over the block's 16 columns, operands read straight from LDS.
@@ -55,7 +57,8 @@ __device__ __forceinline__ doublex4 mfma16(double a, double b, doublex4 c) {
 }
 
 // M (row i at M + i ldg, the lower triangle read) + lambda I = L L^T; L
-// packed to Lout.  LDS: the packed triangle, then the dense copy of the
+// packed to Lout, followed by W_b = L_b^-1 of each 16 x 16 diagonal block
+// (column-major, 256 doubles per block).  LDS: the packed triangle, then the dense copy of the
 // current diagonal block (LbT[c kLbLd + i] = L[j0 + i][j0 + c]) and its
 // reciprocal pivots.
 __device__ __forceinline__ void chol_blk_body(const double* __restrict__ M, int32_t s, int32_t ldg, double lambda,
@@ -129,9 +132,12 @@ __device__ __forceinline__ void chol_blk_body(const double* __restrict__ M, int3
     }
     __syncthreads();
     if (bad) break;
-    // (b) panel rows i >= j1: L[i][j0:j1] <- M[i][j0:j1] L_blk^-T
-    // (padding columns stay zero: rinv = 1 and zero couplings there, so the
-    // loops need no bounds and every load can be issued early)
+    // (b) panel rows i >= j1: L[i][j0:j1] <- M[i][j0:j1] L_blk^-T (a forward
+    // substitution per row).  Meanwhile the last 16 threads run the same
+    // substitution on unit vectors: W_b = L_blk^-1, stored column-major
+    // after the packed triangle for the substitution kernel.  Padding
+    // columns stay zero (rinv = 1, zero couplings), so the loops need no
+    // bounds and every load can be issued early.
     for (int i = j1 + tid; i < s; i += T) {
       double x[kBS];
 #pragma unroll
@@ -148,6 +154,21 @@ __device__ __forceinline__ void chol_blk_body(const double* __restrict__ M, int3
 #pragma unroll
       for (int u = 0; u < kBS; ++u)
         if (u < bs) L[lidx(i, j0 + u, s)] = x[u];
+    }
+    if (tid >= T - kBS) {   // s <= TT_MAX_S keeps these threads out of the panel
+      const int c = tid - (T - kBS);
+      double x[kBS];
+#pragma unroll
+      for (int u = 0; u < kBS; ++u) x[u] = u == c ? 1.0 : 0.0;
+#pragma unroll
+      for (int u = 0; u < kBS; ++u) {
+        x[u] *= rinv[u];
+#pragma unroll
+        for (int v = u + 1; v < kBS; ++v) x[v] -= LbT[u * kLbLd + v] * x[u];
+      }
+      double* W = Lout + np + (size_t)(j0 / kBS) * kBS * kBS;
+#pragma unroll
+      for (int u = 0; u < kBS; ++u) W[u + kBS * c] = x[u];   // W[u][c]
     }
     __syncthreads();
     // (c) trailing update A22 -= L21 L21^T, lower 16 x 16 tiles, a wave per tile
@@ -194,58 +215,71 @@ __global__ __launch_bounds__(256) void k_chol_blk(const double* __restrict__ M, 
   chol_blk_body(M, s, ldg, lambda, Lout, status, reinterpret_cast<double*>(smem_raw), bad);
 }
 
-// Columns c0 .. c0 + CB - 1 of B = (SH^T Y)(:, cols) + lambda G_(2)^T, the
-// right-hand side (row j of M + j ldg, columns s..), solved in place by
-// L y = B (forward) and L^T z = y (backward), 16 rows at a time: one wave
-// (a thread per column) solves the block's triangle, then all waves update
-// the rows the block feeds with 16 x 16 MFMA tiles.  LDS: L (packed), B
-// (s x CB, row-major), 1 / L[j][j].
+// Columns c0 .. c0 + CB - 1 (CB a power of two) of
+// B = (SH^T Y)(:, cols) + lambda G_(2)^T, the right-hand side (row j of M + j
+// ldg, columns s..), solved in place by L y = B (forward) and L^T z = y
+// (backward), 16 rows at a time.  The diagonal step of a block is a product
+// with the block's inverse W_b (written by the Cholesky kernel after the
+// packed triangle): y_b = W_b B_b forward, z_b = W_b^T y_b backward; then all
+// waves update the rows the block feeds.  Both are 16 x 16 MFMA tiles.  LDS:
+// L (packed) and B (s x CB, row-major); W_b is read from L2.
 __device__ __forceinline__ void trsm_blk_body(const double* __restrict__ M, int32_t s, int32_t ldg, double lambda,
                                               const double* __restrict__ Lg, const double* G_old, double* G_new,
                                               int32_t rk, int32_t nk, int32_t CB, int bx, double* L) {
   const int np = s * (s + 1) / 2;
   double* Bs = L + np;
-  double* invd = Bs + (size_t)s * CB;
+  const double* Wg = Lg + np;
   const int c0 = bx * CB;
+  const int lcb = __builtin_ctz((unsigned)CB);
   const int tid = threadIdx.x, T = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6, NW = T >> 6;
   const int rl = lane & 15, kq = lane >> 4;
-  for (int e = tid; e < np; e += T) L[e] = Lg[e];
-  for (int e = tid; e < s * CB; e += T) {
-    const int j = e / CB, cl = e - j * CB;
-    const int col = c0 + cl;
-    double acc = 0.0;
-    if (col < nk) {
-      const int a = j % rk, b = j / rk;
-      acc = M[(int64_t)j * ldg + s + col] + lambda * G_old[a + (int64_t)rk * (col + (int64_t)nk * b)];
+  // loads four per thread in flight
+  for (int e0 = tid; e0 < np; e0 += 4 * T) {
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = e0 + q * T < np ? Lg[e0 + q * T] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (e0 + q * T < np) L[e0 + q * T] = v[q];
+  }
+  for (int e0 = tid; e0 < s * CB; e0 += 4 * T) {
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = e0 + q * T;
+      const int j = e >> lcb, col = c0 + (e & (CB - 1));
+      v[q] = 0.0;
+      if (e < s * CB && col < nk) {
+        const int a = j % rk, b = j / rk;
+        v[q] = M[(int64_t)j * ldg + s + col] + lambda * G_old[a + (int64_t)rk * (col + (int64_t)nk * b)];
+      }
     }
-    Bs[e] = acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (e0 + q * T < s * CB) Bs[e0 + q * T] = v[q];
   }
   __syncthreads();   // every read of G_old for these columns precedes the writes below
-  for (int j = tid; j < s; j += T) invd[j] = 1.0 / L[lidx(j, j, s)];
-  __syncthreads();
   const int ctiles = (CB + 15) / 16;
   // forward: L y = B
   for (int j0 = 0; j0 < s; j0 += kBS) {
     const int bs = min(kBS, s - j0), j1 = j0 + bs;
-    if (tid < CB) {
-      // rows beyond the matrix: x = 0, so clamped (in-range) loads suffice
-      double x[kBS];
+    const double* Wb = Wg + (size_t)(j0 / kBS) * kBS * kBS;
+    for (int t = wv; t < ctiles; t += NW) {   // y_b = W_b B_b, a wave per column tile
+      const int cc = 16 * t;
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int u = 0; u < kBS; ++u) {
-        const double t = Bs[(j0 + min(u, bs - 1)) * CB + tid];
-        x[u] = u < bs ? t : 0.0;
+      for (int kk = 0; kk < kBS; kk += 4) {
+        const int u = kk + kq, cb = cc + rl;
+        const double av = Wb[rl + kBS * u];   // W[rl][u]
+        const double tb = Bs[min(j0 + u, s - 1) * CB + min(cb, CB - 1)];
+        acc = mfma16(av, (u < bs && cb < CB) ? tb : 0.0, acc);
       }
 #pragma unroll
-      for (int u = 0; u < kBS; ++u) {
-        const int ju = min(j0 + u, s - 1);
-        x[u] *= invd[ju];
-#pragma unroll
-        for (int v = u + 1; v < kBS; ++v) x[v] -= L[lidx(min(j0 + v, s - 1), ju, s)] * x[u];
+      for (int r = 0; r < 4; ++r) {
+        const int row = j0 + 4 * r + kq, col = cc + rl;
+        if (row < s && col < CB) Bs[row * CB + col] = acc[r];
       }
-#pragma unroll
-      for (int u = 0; u < kBS; ++u)
-        if (u < bs) Bs[(j0 + u) * CB + tid] = x[u];
     }
     __syncthreads();
     // rows i >= j1: B[i][:] -= L[i][j0:j1] y[j0:j1][:]
@@ -273,23 +307,22 @@ __device__ __forceinline__ void trsm_blk_body(const double* __restrict__ M, int3
   // backward: L^T z = y
   for (int j0 = ((s - 1) / kBS) * kBS; j0 >= 0; j0 -= kBS) {
     const int bs = min(kBS, s - j0);
-    if (tid < CB) {
-      double x[kBS];
+    const double* Wb = Wg + (size_t)(j0 / kBS) * kBS * kBS;
+    for (int t = wv; t < ctiles; t += NW) {   // z_b = W_b^T y_b
+      const int cc = 16 * t;
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int u = 0; u < kBS; ++u) {
-        const double t = Bs[(j0 + min(u, bs - 1)) * CB + tid];
-        x[u] = u < bs ? t : 0.0;
+      for (int kk = 0; kk < kBS; kk += 4) {
+        const int u = kk + kq, cb = cc + rl;
+        const double av = Wb[u + kBS * rl];   // W[u][rl]
+        const double tb = Bs[min(j0 + u, s - 1) * CB + min(cb, CB - 1)];
+        acc = mfma16(av, (u < bs && cb < CB) ? tb : 0.0, acc);
       }
 #pragma unroll
-      for (int u = kBS - 1; u >= 0; --u) {
-        const int ju = min(j0 + u, s - 1);
-        x[u] *= invd[ju];
-#pragma unroll
-        for (int v = 0; v < u; ++v) x[v] -= L[lidx(ju, j0 + v, s)] * x[u];
+      for (int r = 0; r < 4; ++r) {
+        const int row = j0 + 4 * r + kq, col = cc + rl;
+        if (row < s && col < CB) Bs[row * CB + col] = acc[r];
       }
-#pragma unroll
-      for (int u = 0; u < kBS; ++u)
-        if (u < bs) Bs[(j0 + u) * CB + tid] = x[u];
     }
     __syncthreads();
     // rows i < j0: B[i][:] -= sum_u L[j0 + u][i] z[j0 + u][:]
@@ -315,8 +348,7 @@ __device__ __forceinline__ void trsm_blk_body(const double* __restrict__ M, int3
     __syncthreads();
   }
   for (int e = tid; e < s * CB; e += T) {
-    const int q = e / CB, cl = e - q * CB;
-    const int col = c0 + cl;
+    const int q = e >> lcb, col = c0 + (e & (CB - 1));
     if (col < nk) {
       const int a = q % rk, b = q / rk;
       G_new[a + (int64_t)rk * (col + (int64_t)nk * b)] = Bs[e];
@@ -401,8 +433,8 @@ hipError_t prox_t(const tt_plan_s* p, int k, const double* G_old, double* G_new)
   // right-hand-side block: as wide as fits next to L in 150 KB of LDS, at
   // most 64 columns (one thread per column solves the diagonal blocks)
   int CB = 64;
-  while (CB > 1 && (np + (size_t)s * CB + s) * sizeof(double) > 150 * 1024) CB >>= 1;
-  const size_t lds2 = (np + (size_t)s * CB + s) * sizeof(double);
+  while (CB > 1 && (np + (size_t)s * CB) * sizeof(double) > 150 * 1024) CB >>= 1;
+  const size_t lds2 = (np + (size_t)s * CB) * sizeof(double);
   if ((e = tt_allow_lds(k_prox_trsm_blk, lds2)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_prox_trsm_blk, dim3(nblk(nk, CB)), dim3(256), lds2, p->stream, gsum, s, ldg,
                      p->lambda, Lg, G_old, G_new, (int32_t)p->r[k], nk, CB);
@@ -412,6 +444,7 @@ hipError_t prox_t(const tt_plan_s* p, int k, const double* G_old, double* G_new)
 }  // namespace
 
 size_t tt_chol_lds_bytes(int64_t s) { return (size_t)(s * (s + 1) / 2 + kCholExtra) * sizeof(double); }
+int64_t tt_chol_out_doubles(int64_t s) { return s * (s + 1) / 2 + ((s + kBS - 1) / kBS) * kBS * kBS; }
 
 hipError_t launch_prox_from_gram(const tt_plan_s* p, int k, const double* G_old, double* G_new) {
   return p->wdt == TT_F64 ? prox_t<double>(p, k, G_old, G_new) : prox_t<float>(p, k, G_old, G_new);

@@ -153,6 +153,7 @@ struct BUpd {
 };
 hipError_t launch_gram_batched(const BUpd* d, int32_t nprob, int32_t gx, hipStream_t st);
 size_t tt_chol_lds_bytes(int64_t s);   // dynamic LDS of the Cholesky kernel for an s x s system
+int64_t tt_chol_out_doubles(int64_t s);  // packed L plus the inverses of its 16 x 16 diagonal blocks
 hipError_t launch_solve_batched(const BUpd* d, int32_t nprob, int32_t max_s, int32_t max_count, int32_t max_cb_blocks,
                                 size_t lds_chol, size_t lds_trsm, hipStream_t st);
 hipError_t launch_qr_batched(const BUpd* d, const int32_t* idx, int32_t nidx, int32_t rmax, int32_t rpt, hipStream_t st);
