@@ -50,6 +50,12 @@ __device__ __forceinline__ double signed_f64(float x, uint32_t s) {
 
 __device__ __forceinline__ int64_t owner(int64_t g, int64_t W, int64_t Ftot) { return ((g + 1) * W - 1) / Ftot; }
 
+// Descriptor pointers are plain (generic) pointers; reading X through the
+// global address space keeps its loads off the LDS wait counter, so the
+// shuffles and LDS atomics between them do not wait for the loads.
+typedef const float __attribute__((address_space(1)))* gfloat;
+typedef const uint32_t __attribute__((address_space(1)))* guint;
+
 // index of the segment of a non-decreasing prefix array (n + 1 entries) that holds g
 __device__ __forceinline__ int seg_of(const int64_t* pre, int n, int64_t g) {
   int lo = 0, hi = n - 1;
@@ -99,11 +105,13 @@ __global__ __launch_bounds__(256) void k_bsketch_k(const BTensor* __restrict__ T
     const int lpf_log2 = lpf_log2_of(n0);
     const int LPF = 1 << lpf_log2, G = 64 >> lpf_log2;
     const int gi = lane >> lpf_log2, v = lane & (LPF - 1);
+    const gfloat Xg = (gfloat)t.X;
+    const guint tabg = (guint)t.tab;
     uint32_t tb[NJ], ts[NJ];
 #pragma unroll
     for (int q = 0; q < NJ; ++q) {
       const int i0 = v + LPF * q;
-      const uint32_t e = i0 < n0 ? t.tab[t.toff[0] + i0] : 0u;
+      const uint32_t e = i0 < n0 ? tabg[t.toff[0] + i0] : 0u;
       tb[q] = e & TT_KEY_MASK;
       ts[q] = e & TT_KEY_SIGN;
     }
@@ -128,13 +136,13 @@ __global__ __launch_bounds__(256) void k_bsketch_k(const BTensor* __restrict__ T
         for (int s = 1; s < k; ++s) {
           const uint32_t ns = (uint32_t)t.n[s];
           const uint32_t q = mu / ns;
-          keyl = key_add(keyl, t.tab[t.toff[s] + (mu - q * ns)], J);
+          keyl = key_add(keyl, tabg[t.toff[s] + (mu - q * ns)], J);
           mu = q;
         }
         for (int s = k + 1; s < d; ++s) {
           const uint32_t ns = (uint32_t)t.n[s];
           const uint32_t q = rho / ns;
-          keyl = key_add(keyl, t.tab[t.toff[s] + (rho - q * ns)], J);
+          keyl = key_add(keyl, tabg[t.toff[s] + (rho - q * ns)], J);
           rho = q;
         }
       }
@@ -156,9 +164,9 @@ __global__ __launch_bounds__(256) void k_bsketch_k(const BTensor* __restrict__ T
           const int hi = __shfl((int)(uint32_t)((uint64_t)offl >> 32), idx & 63, 64);
           const int64_t off = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 #pragma unroll
-          for (int q = 0; q < NJ; ++q) {
+          for (int q = 0; q < NJ; ++q) {   // lanes past the fibre stay masked off (no load issued)
             const int i0 = v + LPF * q;
-            x[u][q] = (ok[u] && i0 < n0) ? __builtin_nontemporal_load(t.X + off + i0) : 0.0f;
+            x[u][q] = (ok[u] && i0 < n0) ? __builtin_nontemporal_load(Xg + off + i0) : 0.0f;
           }
         }
 #pragma unroll
@@ -226,6 +234,8 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
   const int LPF = 1 << lpf_log2, G = 64 >> lpf_log2;
   const int gi = lane >> lpf_log2, v = lane & (LPF - 1);
   const uint32_t* tab1 = t.tab + t.toff[1];
+  const gfloat Xg = (gfloat)t.X;
+  const guint offg = (guint)t.off, sortg = (guint)t.sorted;
   double acc[NJ];   // FP64: the result does not depend on the order of the list
 #pragma unroll
   for (int q = 0; q < NJ; ++q) acc[q] = 0.0;
@@ -233,9 +243,9 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
     const uint32_t t1 = tab1[i1];
     const uint32_t h1 = t1 & TT_KEY_MASK;
     const uint32_t c = b >= h1 ? b - h1 : b + J - h1;
-    const uint32_t beg = t.off[c], end = t.off[c + 1];
+    const uint32_t beg = offg[c], end = offg[c + 1];
     for (uint32_t e0 = beg; e0 < end; e0 += 64) {
-      const uint32_t itl = (e0 + lane < end) ? t.sorted[e0 + lane] : 0u;
+      const uint32_t itl = (e0 + lane < end) ? sortg[e0 + lane] : 0u;
       const int nb = (end - e0) < 64u ? (int)(end - e0) : 64;
       for (int u0 = 0; u0 < nb; u0 += kB0Fib * G) {
         float x[kB0Fib][NJ];
@@ -245,7 +255,7 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
           const int idx = u0 + u * G + gi;
           const uint32_t item = (uint32_t)__shfl((int)itl, idx & 63, 64);
           sg[u] = (item ^ t1) & TT_KEY_SIGN;
-          const float* base = t.X + ((int64_t)(item & TT_KEY_MASK) * n1 + i1) * (int64_t)n0;
+          const gfloat base = Xg + ((int64_t)(item & TT_KEY_MASK) * n1 + i1) * (int64_t)n0;
 #pragma unroll
           for (int q = 0; q < NJ; ++q) {
             const int i0 = v + LPF * q;
