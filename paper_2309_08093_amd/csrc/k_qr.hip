@@ -216,7 +216,7 @@ __device__ __forceinline__ void block_sums(double (&v)[NV], double* part, double
 // thread that holds it.  LDS buffers alternate between reductions, so one
 // reduction's readers never race the next one's writers.
 template <int RMAX, int RPT>
-__device__ __forceinline__ void qr_reg_body(double* G, int64_t m, int32_t r, int64_t rs, int64_t cs, double* __restrict__ Rout) {
+__device__ __forceinline__ void qr_reg_body(gdbl G, int64_t m, int32_t r, int64_t rs, int64_t cs, gdbl __restrict__ Rout) {
   constexpr int NV = RMAX <= 4 ? 4 : (RMAX <= 8 ? 8 : 16);
   static_assert(RMAX <= 16, "register QR holds at most 16 columns");
   __shared__ double part[2][NV * kQrRegWaves];
@@ -349,7 +349,7 @@ __device__ __forceinline__ void qr_reg_body(double* G, int64_t m, int32_t r, int
 template <int RMAX, int RPT>
 __global__ __launch_bounds__(kQrRegThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_qr_reg(double* G, int64_t m, int32_t r, int64_t rs, int64_t cs,
                                                          double* __restrict__ Rout) {
-  qr_reg_body<RMAX, RPT>(G, m, r, rs, cs, Rout);
+  qr_reg_body<RMAX, RPT>((gdbl)G, m, r, rs, cs, (gdbl)Rout);
 }
 
 // Batched: QR of G_k^L (R_k n_k x R_{k+1}) of problem idx[blockIdx.x].
@@ -357,7 +357,7 @@ template <int RMAX, int RPT>
 __global__ __launch_bounds__(kQrRegThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void kb_qr(const BUpd* __restrict__ d, const int32_t* __restrict__ idx) {
   const BUpd u = d[idx[blockIdx.x]];
   const int64_t m = (int64_t)u.rk * u.nk;
-  qr_reg_body<RMAX, RPT>(u.G, m, u.rk1, 1, m, u.R);
+  qr_reg_body<RMAX, RPT>((gdbl)u.G, m, u.rk1, 1, m, (gdbl)u.R);
 }
 
 template <int RMAX>
@@ -396,20 +396,22 @@ __global__ void k_absorb_left(double* G, const double* __restrict__ R, int32_t r
 __global__ void kb_absorb_left(const BUpd* __restrict__ d) {
   const BUpd u = d[blockIdx.y];
   if (!u.Gnext) return;
+  const gdbl Gn = (gdbl)u.Gnext;
+  const cgdbl Rg = (cgdbl)u.R;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= u.ncols_next) return;
   const int r = u.rk1;
   double x[TT_MAX_RANK];
 #pragma unroll
-  for (int q = 0; q < TT_MAX_RANK; ++q) x[q] = q < r ? u.Gnext[p * r + q] : 0.0;
+  for (int q = 0; q < TT_MAX_RANK; ++q) x[q] = q < r ? Gn[p * r + q] : 0.0;
 #pragma unroll
   for (int a = 0; a < TT_MAX_RANK; ++a) {
     if (a < r) {
       double acc = 0.0;
 #pragma unroll
       for (int q = 0; q < TT_MAX_RANK; ++q)
-        if (q < r) acc += u.R[a * r + q] * x[q];
-      u.Gnext[p * r + a] = acc;
+        if (q < r) acc += Rg[a * r + q] * x[q];
+      Gn[p * r + a] = acc;
     }
   }
 }

@@ -61,8 +61,8 @@ __device__ __forceinline__ doublex4 mfma16(double a, double b, doublex4 c) {
 // (column-major, 256 doubles per block).  LDS: the packed triangle, then the dense copy of the
 // current diagonal block (LbT[c kLbLd + i] = L[j0 + i][j0 + c]) and its
 // reciprocal pivots.
-__device__ __forceinline__ void chol_blk_body(const double* __restrict__ M, int32_t s, int32_t ldg, double lambda,
-                                              double* __restrict__ Lout, int32_t* __restrict__ status, double* L,
+__device__ __forceinline__ void chol_blk_body(cgdbl __restrict__ M, int32_t s, int32_t ldg, double lambda,
+                                              gdbl __restrict__ Lout, int32_t* __restrict__ status, double* L,
                                               int& bad) {
   const int tid = threadIdx.x, T = blockDim.x;
   const int lane = tid & 63, wv = tid >> 6, NW = T >> 6;
@@ -166,7 +166,7 @@ __device__ __forceinline__ void chol_blk_body(const double* __restrict__ M, int3
 #pragma unroll
         for (int v = u + 1; v < kBS; ++v) x[v] -= LbT[u * kLbLd + v] * x[u];
       }
-      double* W = Lout + np + (size_t)(j0 / kBS) * kBS * kBS;
+      const gdbl W = Lout + np + (size_t)(j0 / kBS) * kBS * kBS;
 #pragma unroll
       for (int u = 0; u < kBS; ++u) W[u + kBS * c] = x[u];   // W[u][c]
     }
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256) void k_chol_blk(const double* __restrict__ M, 
                                                  double* __restrict__ Lout, int32_t* __restrict__ status) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int bad;
-  chol_blk_body(M, s, ldg, lambda, Lout, status, reinterpret_cast<double*>(smem_raw), bad);
+  chol_blk_body((cgdbl)M, s, ldg, lambda, (gdbl)Lout, status, reinterpret_cast<double*>(smem_raw), bad);
 }
 
 // Columns c0 .. c0 + CB - 1 (CB a power of two) of
@@ -223,12 +223,12 @@ __global__ __launch_bounds__(256) void k_chol_blk(const double* __restrict__ M, 
 // packed triangle): y_b = W_b B_b forward, z_b = W_b^T y_b backward; then all
 // waves update the rows the block feeds.  Both are 16 x 16 MFMA tiles.  LDS:
 // L (packed) and B (s x CB, row-major); W_b is read from L2.
-__device__ __forceinline__ void trsm_blk_body(const double* __restrict__ M, int32_t s, int32_t ldg, double lambda,
-                                              const double* __restrict__ Lg, const double* G_old, double* G_new,
-                                              int32_t rk, int32_t nk, int32_t CB, int bx, double* L) {
+__device__ __forceinline__ void trsm_blk_body(cgdbl __restrict__ M, int32_t s, int32_t ldg, double lambda,
+                                              cgdbl __restrict__ Lg, cgdbl G_old, gdbl G_new, int32_t rk, int32_t nk,
+                                              int32_t CB, int bx, double* L) {
   const int np = s * (s + 1) / 2;
   double* Bs = L + np;
-  const double* Wg = Lg + np;
+  const cgdbl Wg = Lg + np;
   const int c0 = bx * CB;
   const int lcb = __builtin_ctz((unsigned)CB);
   const int tid = threadIdx.x, T = blockDim.x;
@@ -264,7 +264,7 @@ __device__ __forceinline__ void trsm_blk_body(const double* __restrict__ M, int3
   // forward: L y = B
   for (int j0 = 0; j0 < s; j0 += kBS) {
     const int bs = min(kBS, s - j0), j1 = j0 + bs;
-    const double* Wb = Wg + (size_t)(j0 / kBS) * kBS * kBS;
+    const cgdbl Wb = Wg + (size_t)(j0 / kBS) * kBS * kBS;
     for (int t = wv; t < ctiles; t += NW) {   // y_b = W_b B_b, a wave per column tile
       const int cc = 16 * t;
       doublex4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -307,7 +307,7 @@ __device__ __forceinline__ void trsm_blk_body(const double* __restrict__ M, int3
   // backward: L^T z = y
   for (int j0 = ((s - 1) / kBS) * kBS; j0 >= 0; j0 -= kBS) {
     const int bs = min(kBS, s - j0);
-    const double* Wb = Wg + (size_t)(j0 / kBS) * kBS * kBS;
+    const cgdbl Wb = Wg + (size_t)(j0 / kBS) * kBS * kBS;
     for (int t = wv; t < ctiles; t += NW) {   // z_b = W_b^T y_b
       const int cc = 16 * t;
       doublex4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -361,7 +361,8 @@ __global__ __launch_bounds__(256) void k_prox_trsm_blk(const double* __restrict_
                                                       const double* G_old, double* G_new, int32_t rk, int32_t nk,
                                                       int32_t CB) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  trsm_blk_body(M, s, ldg, lambda, Lg, G_old, G_new, rk, nk, CB, blockIdx.x, reinterpret_cast<double*>(smem_raw));
+  trsm_blk_body((cgdbl)M, s, ldg, lambda, (cgdbl)Lg, (cgdbl)G_old, (gdbl)G_new, rk, nk, CB, blockIdx.x,
+                reinterpret_cast<double*>(smem_raw));
 }
 
 // Batched forms (problem blockIdx.y, or blockIdx.x for the one-workgroup
@@ -380,14 +381,15 @@ __global__ __launch_bounds__(256) void kb_chol(const BUpd* __restrict__ d) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ int bad;
   const BUpd u = d[blockIdx.x];
-  chol_blk_body(u.gsum, u.s, u.s + u.nk, u.lambda, u.Lg, u.status, reinterpret_cast<double*>(smem_raw), bad);
+  chol_blk_body((cgdbl)u.gsum, u.s, u.s + u.nk, u.lambda, (gdbl)u.Lg, u.status, reinterpret_cast<double*>(smem_raw),
+                bad);
 }
 
 __global__ __launch_bounds__(256) void kb_trsm(const BUpd* __restrict__ d) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const BUpd u = d[blockIdx.y];
   if ((int)blockIdx.x * u.CB >= u.nk) return;
-  trsm_blk_body(u.gsum, u.s, u.s + u.nk, u.lambda, u.Lg, u.G, u.G, u.rk, u.nk, u.CB, blockIdx.x,
+  trsm_blk_body((cgdbl)u.gsum, u.s, u.s + u.nk, u.lambda, (cgdbl)u.Lg, (cgdbl)u.G, (gdbl)u.G, u.rk, u.nk, u.CB, blockIdx.x,
                 reinterpret_cast<double*>(smem_raw));
 }
 

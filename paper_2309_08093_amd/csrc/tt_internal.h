@@ -138,6 +138,13 @@ bool tt_factor_fft(int64_t J, int* radix, int* nrad);
 // One problem's core update k within a batched step (FP32 work): the device
 // array of these drives the batched Gram, solve, QR and absorb launches
 // (batch.hip), one workgroup (or block set) per problem.
+// Global-address-space pointers: kernels that take their buffers from a
+// descriptor in memory see generic pointers, which compile to flat accesses
+// sharing the LDS wait counter; casting to these keeps them global.
+typedef double __attribute__((address_space(1)))* gdbl;
+typedef const double __attribute__((address_space(1)))* cgdbl;
+typedef int32_t __attribute__((address_space(1)))* gi32;
+
 struct BUpd {
   const float* SH;      // J x s
   const float* Y;       // J x n_k
