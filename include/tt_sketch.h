@@ -198,7 +198,7 @@ tt_status tt_plan_set_overlap(tt_plan plan, int32_t reserved_cus);
 #define TT_PROF_SKETCH_AUX 2 /* data sketch key tables, bucket lists, partial sums */
 #define TT_PROF_INTERFACE 3  /* core CountSketch + FFT, chains, face-split + inverse FFT */
 #define TT_PROF_GRAM 4       /* MFMA Gram / right-hand side */
-#define TT_PROF_SOLVE 5      /* FP64 Cholesky, inverse, apply */
+#define TT_PROF_SOLVE 5      /* FP64 partial sums, Cholesky, substitution */
 #define TT_PROF_QR 6         /* FP64 Householder QR and absorb */
 #define TT_PROF_RESIDUAL 7   /* residual pass */
 #define TT_PROF_TABLES 8     /* hash/sign table generation */

@@ -3,8 +3,14 @@
 //
 // Each problem keeps its own plan (tables, cores, interface and solve
 // buffers) in a slice of one batch workspace.  Per step k of a sweep:
-//  * the interface sketches and core updates of all problems with order > k
-//    are enqueued per problem (short, latency-bound kernels);
+//  * the interface sketches (and the new transform of core k - 1) of all
+//    problems with order > k are enqueued per problem on 8 streams (short,
+//    latency-bound kernels);
+//  * the core updates of all those problems are one launch per kernel: the
+//    Gram contraction, the summed partials, the Cholesky factorisation, the
+//    substitution, QR (one launch per register shape; blocks too tall for
+//    registers per problem) and the absorb of R, each with one workgroup (or
+//    block set) per problem, driven by per-step descriptors in device memory;
 //  * the data sketches of all those problems are ONE persistent launch:
 //    - k >= 1: the fibres of every participating problem, problem by problem
 //      and column by column, form one sequence that is split into equal
@@ -14,7 +20,10 @@
 //      second launch adds the partials of each column in a fixed order;
 //    - k = 0: one workgroup per (problem, bucket) gathers the fibres hashed to
 //      the bucket from the problem's bucket-sorted list of outer tuples.
-// A whole sweep can be captured once into a hipGraph and replayed; the table
+// The data sketches of every step need only X and the sweep's tables, so they
+// all run first, on a side stream, and step k's core updates wait for step
+// k's sketch.  A whole sweep can be captured once into a hipGraph and
+// replayed; the table
 // generator then reads the sweep index from a device counter that the graph
 // advances.  The workgroup count of each k >= 1 launch is chosen by
 // tt_batch_autotune from timed candidates.
