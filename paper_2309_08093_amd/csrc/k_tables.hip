@@ -84,21 +84,34 @@ __global__ void k_count(const uint32_t* keys, int64_t count, uint32_t* cnt) {
 
 // Exclusive scan of cnt[0..J) into off[0..J]; cursor[c] = off[c].  One block.
 __global__ void k_scan(const uint32_t* cnt, uint32_t* off, uint32_t* cursor, int32_t J) {
-  __shared__ uint32_t part[1024];
-  const int t = threadIdx.x, T = blockDim.x;
+  // exclusive prefix sum of cnt[0..J) into off (and cursor), off[J] = total;
+  // per-thread runs, then an inclusive scan by shuffles within each wave and
+  // over the wave totals
+  __shared__ uint32_t wsum[16];
+  const int t = threadIdx.x, T = blockDim.x, lane = t & 63, w = t >> 6, NW = T >> 6;
   const int per = (J + T - 1) / T;
   const int lo = min(J, t * per), hi = min(J, lo + per);
   uint32_t s = 0;
   for (int c = lo; c < hi; ++c) s += cnt[c];
-  part[t] = s;
+  uint32_t x = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
   __syncthreads();
-  if (t == 0) {
-    uint32_t acc = 0;
-    for (int i = 0; i < T; ++i) { uint32_t v = part[i]; part[i] = acc; acc += v; }
-    off[J] = acc;
+  if (w == 0) {
+    uint32_t v = lane < NW ? wsum[lane] : 0u;
+    const uint32_t own = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)v, o, 64);
+      if (lane >= o) v += y;
+    }
+    if (lane < NW) wsum[lane] = v - own;   // exclusive over the waves
   }
   __syncthreads();
-  uint32_t acc = part[t];
+  uint32_t acc = wsum[w] + x - s;          // exclusive prefix of this thread's run
+  if (t == T - 1) off[J] = acc + s;
   for (int c = lo; c < hi; ++c) {   // cnt may alias cursor: read before writing
     const uint32_t v = cnt[c];
     off[c] = acc;
