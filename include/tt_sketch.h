@@ -302,9 +302,9 @@ tt_status tt_plan_fallback_J(tt_plan plan, double eps, double delta, int64_t* J)
 /* Run sweeps until the exact relative residual is <= target or max_sweeps
  * sweeps are done.  With params == NULL every sweep uses the plan's current
  * J and lambda.  Otherwise the policy chooses (J, lambda) before each sweep
- * from the features above; when a sweep does not lower the residual, the next
- * sweep uses tt_plan_fallback_J (eps = 0.5, delta = 0.1) and the
- * descriptor's lambda.  The residual of every sweep is computed exactly and
+ * from the features above; when a sweep (from the second on) does not lower
+ * the previous sweep's residual, the next sweep uses tt_plan_fallback_J
+ * (eps = 0.5, delta = 0.1) and the descriptor's lambda.  The residual of every sweep is computed exactly and
  * read back (synchronising).  residuals, Js, lambdas: host arrays of
  * max_sweeps entries or NULL. */
 typedef struct {

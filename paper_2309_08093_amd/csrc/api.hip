@@ -727,9 +727,11 @@ tt_status tt_als_run(tt_plan p, const void* X, void* const* cores, const float* 
     stats->sweeps = t + 1;
     stats->residual = res;
     drop = log10(prev / res);
-    // the residual check: a sweep that does not lower the residual sends the
-    // next one to the fallback size
-    fallback = params && !(res < prev);
+    // the residual check: a sweep that does not lower the previous sweep's
+    // residual sends the next one to the fallback size.  The first sweep has
+    // no measured predecessor (the 1.0 above only seeds the drop feature; a
+    // random start can lie above 1), so the check begins with the second.
+    fallback = params && t > 0 && !(res < prev);
     prev = res;
     if (res <= target) {
       stats->reached = 1;

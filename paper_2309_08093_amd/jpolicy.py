@@ -5,15 +5,20 @@ The network and its kernels are in the C ABI (tt_jpolicy_*, tt_als_run);
 this module marshals arrays and runs the label-collection loop, in which
 every sweep, residual and feature vector is computed by the library.
 
-Labels (one per sweep state of a run): starting from the same cores and the
-same sweep index, one sweep is run and timed for every J of a geometric grid
-(the plan's serial schedule, as tt_als_run uses); the label J* maximises the
-residual drop per second, log10(res_before / res_after) / time, which is what
-the time to a target residual depends on.  At J* one sweep per lambda of a
-grid gives the label lambda* (largest drop), and the run continues from that
-sweep's cores.  The d feature rows of the state (one per core update) all
-carry the label (ln J* - 7, log10 lambda* + 3); their residual drop is that
-of the previous sweep, as in tt_als_run.
+Two label designs (one label per sweep state; the d feature rows of a state,
+one per core update, all carry it as (ln J* - 7, log10 lambda* + 3), and
+their residual drop is that of the previous sweep, as in tt_als_run):
+
+* "runs" (default): from the problem's start, one run per J of a geometric
+  grid at lambda = 1e-3, each up to a fixed number of sweeps, timed with its
+  residual check after every sweep (as tt_als_run runs).  The target is
+  max(1e-2, 1.5 x the best residual any run reached); J* is the J whose run
+  reaches it first, and the states of that run up to the target are labelled
+  J*.  This is the quantity a run is judged by, the time to a target.
+* "sweep": starting from the same cores and sweep index, one sweep per J;
+  J* maximises that sweep's residual drop per second, lambda* is the best of
+  a grid at J*, and the run continues from that sweep.  Greedy: a larger
+  first drop need not remove a sweep before a target is reached.
 """
 import json
 import math
@@ -219,6 +224,68 @@ def collect(n_tensors, seed, device="cuda", J_grid=(250, 500, 1000, 2000, 4000, 
     return np.concatenate(feats).astype(np.float32), np.concatenate(targs).astype(np.float32), meta
 
 
+def collect_runs(n_tensors, seed, device="cuda", J_grid=(250, 500, 1000, 2000, 4000, 8000), lam=1e-3,
+                 max_sweeps=8, log=None):
+    """Labelled (features, targets) from whole runs to a target; see the
+    module doc.  Returns the same layout as collect()."""
+    import synth
+    from . import Plan, core_to_device
+    dev = torch.device(device)
+    g = np.random.Generator(np.random.PCG64(seed))
+    feats, targs, meta = [], [], []
+    Jmax = max(J_grid)
+    t0 = time.time()
+    for i in range(n_tensors):
+        n, R, nu = random_problem(g)
+        s_i = int(g.integers(1, 2 ** 31))
+        scale = math.sqrt(float(np.prod(R[1:-1])))
+        X, _ = synth.tt_tensor_device(n, R, nu * scale, s_i, dtype="f32", device=dev)
+        plan = Plan(n, R, Jmax, lam, seed=s_i, x_dtype="f32", work_dtype="f32", device=dev, serial=True)
+        init = synth.random_cores(n, R, s_i + 1)
+        scratch = [core_to_device(c, dev) for c in init]   # first-use costs out of the timings
+        plan.als_sweep(X, scratch)
+        plan.residual(X, scratch)
+        runs = {}
+        for J in J_grid:
+            cores = [core_to_device(c, dev) for c in init]
+            plan.set_sketch(J, lam)
+            plan.set_sweep(0)
+            torch.cuda.synchronize()
+            t_acc, times, res = 0.0, [], []
+            for _ in range(max_sweeps):
+                ta = time.perf_counter()
+                plan.als_sweep(X, cores)
+                r = plan.residual(X, cores)   # synchronises
+                t_acc += time.perf_counter() - ta
+                times.append(t_acc)
+                res.append(r)
+            runs[J] = (times, res)
+        best = min(min(r) for _, r in runs.values())
+        tau = max(1e-2, 1.5 * best)
+
+        def reach(J):
+            times, res = runs[J]
+            for s, r in enumerate(res):
+                if r <= tau:
+                    return times[s], s + 1
+            return math.inf, None
+
+        Jstar = min(J_grid, key=lambda J: (reach(J)[0], J))
+        T_star = reach(Jstar)[1]
+        h = [1.0] + runs[Jstar][1]   # h[s + 1]: residual after sweep s
+        for t in range(T_star):
+            drop = math.log10(h[t - 1] / h[t]) if t >= 1 else 0.0
+            feats.append(plan.features(t, drop))
+            targs.append(np.repeat(encode_targets(Jstar, lam)[None, :], len(n), axis=0))
+            meta.append({"n": n, "R": R, "noise": nu, "t": t, "J": Jstar, "lambda": lam, "target": tau,
+                         "ms_to_target": {J: reach(J)[0] * 1e3 for J in J_grid}})
+        del X, plan, scratch
+        if log and (i + 1) % 20 == 0:
+            log("[collect] %d/%d tensors, %d rows, %.0f s" % (i + 1, n_tensors, sum(len(f) for f in feats),
+                                                          time.time() - t0))
+    return np.concatenate(feats).astype(np.float32), np.concatenate(targs).astype(np.float32), meta
+
+
 def main():
     import argparse
     import sys
@@ -228,6 +295,8 @@ def main():
     ap.add_argument("--seed", type=int, default=11)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--labels", choices=("runs", "sweep"), default="runs")
+    ap.add_argument("--max-sweeps", type=int, default=8, help="sweeps per run of the 'runs' labels")
     ap.add_argument("--out", required=True, help="prefix of the weights (.npy) and summary (.json) files")
     args = ap.parse_args()
 
@@ -235,7 +304,10 @@ def main():
         print(msg, file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
-    X, T, meta = collect(args.tensors, args.seed, dev, sweeps=args.sweeps, log=log)
+    if args.labels == "runs":
+        X, T, meta = collect_runs(args.tensors, args.seed, dev, max_sweeps=args.max_sweeps, log=log)
+    else:
+        X, T, meta = collect(args.tensors, args.seed, dev, sweeps=args.sweeps, log=log)
     np.savez(args.out + "_data.npz", X=X, T=T)
     g = np.random.Generator(np.random.PCG64(args.seed + 1))
     perm = g.permutation(len(meta))

@@ -173,12 +173,33 @@ def test_run_with_policy_follows_its_rules(env):
             while x % q == 0:
                 x //= q
         assert x == 1 and 64 <= J <= 4000
-        # a sweep that did not lower the residual (1 before the first) sends
-        # the next to the fallback size with the descriptor's lambda
-        if t > 0 and not (res[t - 1] < (res[t - 2] if t >= 2 else 1.0)):
+        # a sweep (from the second on) that did not lower the previous
+        # residual sends the next to the fallback size with the descriptor's
+        # lambda
+        if t >= 2 and not (res[t - 1] < res[t - 2]):
             assert J == fb and out["lambda"][t] == 1e-3
             nfb += 1
     assert nfb == out["fallbacks"]
     assert out["reached"] == (out["residual"] <= 1e-2)
     if out["reached"]:
         assert all(r > 1e-2 for r in out["residuals"][:-1])
+
+
+def test_whole_run_labels(env):
+    """The whole-run labels name the J whose run reaches the target first, and
+    label every state of that run up to the target."""
+    torch, tts, jpolicy = env
+    say("whole-run labels")
+    # seed 2 draws a small order-4 problem (33 x 34 x 38 x 34)
+    X, T, meta = jpolicy.collect_runs(1, 2, "cuda", J_grid=(250, 1000), max_sweeps=3)
+    assert meta
+    ms = meta[0]["ms_to_target"]
+    finite = {J: v for J, v in ms.items() if v != math.inf}
+    assert finite, ms   # the run with the best residual always reaches max(1e-2, 1.5 x best)
+    Jstar = min(finite, key=lambda J: (finite[J], J))
+    assert all(m["J"] == Jstar for m in meta)
+    assert [m["t"] for m in meta] == list(range(len(meta)))
+    d = len(meta[0]["n"])
+    assert X.shape == (d * len(meta), F) and T.shape == (d * len(meta), O)
+    assert np.allclose(T[:, 0], math.log(Jstar) - 7.0) and np.allclose(T[:, 1], 0.0)   # lambda = 1e-3
+    assert np.allclose(X[:d, 7], 0.0)   # no residual drop before the first sweep
