@@ -67,6 +67,37 @@ def test_batched_sketch_matches_oracle(env, integer):
                 assert np.linalg.norm(got - want) <= 1e-5 * np.linalg.norm(want)
 
 
+# batches whose longest mode-0 fibre takes 2 and 4 entries per lane
+WIDE = {
+    "n0<=128": [dict(n=[100, 6, 7], ranks=[1, 4, 5, 1], J=90, seed=111),
+                dict(n=[40, 5, 4, 3], ranks=[1, 3, 3, 2, 1], J=64, seed=112)],
+    "n0<=256": [dict(n=[200, 5, 4, 3], ranks=[1, 4, 3, 2, 1], J=150, seed=113),
+                dict(n=[129, 7, 6], ranks=[1, 3, 4, 1], J=128, seed=114),
+                dict(n=[9, 10, 11], ranks=[1, 3, 3, 1], J=72, seed=115)],
+}
+
+
+@pytest.mark.parametrize("which", sorted(WIDE))
+def test_batched_sketch_wide_fibres(env, which):
+    torch, tts = env
+    say("batched sketch, wide fibres %s" % which)
+    probs = WIDE[which]
+    b = tts.Batch(probs)
+    Xs, Xh = make_inputs(torch, probs, integer=True)
+    for k in range(4):
+        Ys = b.sketch_tensor(Xs, k)
+        torch.cuda.synchronize()
+        for i, p in enumerate(probs):
+            d = len(p["n"])
+            if d <= k:
+                assert Ys[i] is None
+                continue
+            hs, vs = zip(*[b.plan_tables(i, s) for s in range(d)])
+            want = sketch.data_sketch(Xh[i], p["n"], k, hs, vs, p["J"])
+            got = Ys[i].cpu().numpy().astype(np.float64).reshape(want.shape, order="F")
+            np.testing.assert_array_equal(got, want)
+
+
 def test_tables_are_the_plans_tables(env):
     torch, tts = env
     say("batch tables")
