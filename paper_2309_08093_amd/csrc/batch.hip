@@ -76,9 +76,12 @@ __device__ __forceinline__ int seg_of(const int64_t* pre, int n, int64_t g) {
   return lo;
 }
 
+// lanes per fibre (log2): the smallest power of two whose NJ entries per lane
+// cover the fibre, at most 64
+template <int NJ>
 __device__ __forceinline__ int lpf_log2_of(int n0) {
   int l = 0;
-  while ((1 << l) < n0 && l < 6) ++l;
+  while ((NJ << l) < n0 && l < 6) ++l;
   return l;
 }
 
@@ -111,7 +114,7 @@ __global__ __launch_bounds__(256) void k_bsketch_k(const BTensor* __restrict__ T
     for (int s = 1; s < k; ++s) M *= t.n[s];
     for (int s = k + 1; s < d; ++s) R *= t.n[s];
     const int64_t F = M * R;
-    const int lpf_log2 = lpf_log2_of(n0);
+    const int lpf_log2 = lpf_log2_of<NJ>(n0);
     const int LPF = 1 << lpf_log2, G = 64 >> lpf_log2;
     const int gi = lane >> lpf_log2, v = lane & (LPF - 1);
     const gfloat Xg = (gfloat)t.X;
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, NW = blockDim.x >> 6;
   const int n0 = t.n[0], n1 = t.n[1];
   const uint32_t J = t.J;
-  const int lpf_log2 = lpf_log2_of(n0);
+  const int lpf_log2 = lpf_log2_of<NJ>(n0);
   const int LPF = 1 << lpf_log2, G = 64 >> lpf_log2;
   const int gi = lane >> lpf_log2, v = lane & (LPF - 1);
   const uint32_t* tab1 = t.tab + t.toff[1];
@@ -354,8 +357,7 @@ int occupancy_grid(int nj, int32_t Jmax) {
     ncu = 256;
   const size_t lds = sizeof(double) * Jmax;
   hipError_t e = hipErrorInvalidValue;
-  if (nj == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_k<1>, 256, lds);
-  else if (nj == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_k<2>, 256, lds);
+  if (nj == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_k<2>, 256, lds);
   else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_k<4>, 256, lds);
   if (e != hipSuccess || per < 1) per = 1;
   return per * ncu;
@@ -423,8 +425,7 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
       if (e != hipSuccess) return e;
     }
     const dim3 grid((unsigned)(nt * b->Jmax));
-    if (b->nj == 1) hipLaunchKernelGGL(k_bsketch_0<1>, grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
-    else if (b->nj == 2) hipLaunchKernelGGL(k_bsketch_0<2>, grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
+    if (b->nj == 2) hipLaunchKernelGGL(k_bsketch_0<2>, grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
     else hipLaunchKernelGGL(k_bsketch_0<4>, grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
     return hipGetLastError();
   }
@@ -438,10 +439,7 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
   if (W > Ttot) W = Ttot;
   if (W < 1) W = 1;
   const size_t lds = sizeof(double) * b->Jmax;
-  if (b->nj == 1)
-    hipLaunchKernelGGL(k_bsketch_k<1>, dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre, cpre, spre, nt, k,
-                       part, b->Jmax);
-  else if (b->nj == 2)
+  if (b->nj == 2)
     hipLaunchKernelGGL(k_bsketch_k<2>, dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre, cpre, spre, nt, k,
                        part, b->Jmax);
   else
@@ -658,7 +656,12 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
     if (p->J > b->Jmax) b->Jmax = (int32_t)p->J;
     if (p->n[0] > max_n0) max_n0 = (int)p->n[0];
   }
-  b->nj = max_n0 <= 64 ? 1 : (max_n0 <= 128 ? 2 : 4);
+  // entries of a fibre per lane: at least 2, so that a lane group serves
+  // two or more short fibres per load round and the per-fibre work (key and
+  // offset shuffles, bucket arithmetic) is shared by more entries (measured
+  // on 256 uneven TTs with n_0 in [20, 60]: 1 / 2 / 4 entries per lane gave
+  // 81.7 / 73.0 / 81.1 ms per sweep)
+  b->nj = max_n0 <= 128 ? 2 : 4;
   // per-step work lists: problems of order > k, their fibre and column prefixes,
   // and partial slots per column for the largest grid
   b->tids.resize(b->max_d);
