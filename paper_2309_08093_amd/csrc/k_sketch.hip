@@ -214,7 +214,11 @@ __global__ void k_reduce_parts(const double* __restrict__ part, WT* __restrict__
 }
 
 // ---------------------------------------------------------------- k >= 1, key-grouped
-template <typename XT, typename WT, int V, int NJ, int U>
+// DB (double-buffered): the loads of the next batch of fibres are issued
+// before the current batch is summed, so a wave always has loads in flight.
+// It pays when one fibre fills the wave (one fibre per load, long fibres);
+// for short fibres the second buffer costs more occupancy than it gains.
+template <typename XT, typename WT, int V, int NJ, int U, bool DB>
 __global__ __launch_bounds__(TT_SKETCH_THREADS) void k_sketch_gs(
     const XT* __restrict__ X, const uint32_t* __restrict__ tab0, const uint2* __restrict__ list,
     double* __restrict__ part, int32_t n0, int32_t nk, int64_t M, int64_t F, uint32_t J, int32_t lpf_log2,
@@ -271,45 +275,85 @@ __global__ __launch_bounds__(TT_SKETCH_THREADS) void k_sketch_gs(
           }
       }
     };
-    // list entries are fetched 64 at a time, one per lane, one batch ahead,
-    // so that the loads of X never wait on a list load issued just before
-    uint2 nxt = (wa + lane < we) ? list[wa + lane] : make_uint2(0u, 0u);
-    for (int64_t eb = wa; eb < we; eb += 64) {
-      const uint2 itl = nxt;
-      if (eb + 64 + lane < we) nxt = list[eb + 64 + lane];
-      const int nb = (we - eb) < 64 ? (int)(we - eb) : 64;
-      for (int t = 0; t < nb; t += G * U) {
-        uint32_t ix[U], iy[U];
-        bool ok[U];
-        Vec<XT, V> x[U][NJ];
+    // a batch: the fibres off + u G + g of the current chunk of 64 list
+    // entries, fibre u G + g to lane group g; off + u G + g stays below 64
+    auto issue = [&](const uint2& itl, int off, int64_t left, uint32_t (&ix)[U], uint32_t (&iy)[U], bool (&ok)[U],
+                     Vec<XT, V> (&x)[U][NJ]) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int idx = t + u * G + g;
-          ok[u] = idx < nb;
-          ix[u] = (uint32_t)__shfl((int)itl.x, idx & 63, 64);
-          iy[u] = (uint32_t)__shfl((int)itl.y, idx & 63, 64);
-          const XT* base = Xc + (int64_t)(ix[u] & TT_KEY_MASK) * n0;
+      for (int u = 0; u < U; ++u) {
+        const int idx = off + u * G + g;
+        ok[u] = u * G < 64 && u * G + g < left;
+        ix[u] = (uint32_t)__shfl((int)itl.x, idx & 63, 64);
+        iy[u] = (uint32_t)__shfl((int)itl.y, idx & 63, 64);
+        const XT* base = Xc + (int64_t)(ix[u] & TT_KEY_MASK) * n0;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const int p = (v + LPF * j) * V;
+          if (ok[u] && p < n0) x[u][j] = load_vec<XT, V>(base + p);
+        }
+      }
+    };
+    auto consume = [&](const uint32_t (&ix)[U], const uint32_t (&iy)[U], const bool (&ok)[U],
+                       const Vec<XT, V> (&x)[U][NJ]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (ok[u]) {
+          if (iy[u] != cur) {
+            if (cur != 0xffffffffu) flush();
+            cur = iy[u];
+          }
 #pragma unroll
           for (int j = 0; j < NJ; ++j) {
             const int p = (v + LPF * j) * V;
-            if (ok[u] && p < n0) x[u][j] = load_vec<XT, V>(base + p);
+            if (p < n0)
+#pragma unroll
+              for (int e = 0; e < V; ++e) sacc[j][e] += signed_f64(x[u][j].e[e], ix[u] & TT_KEY_SIGN);
           }
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (ok[u]) {
-            if (iy[u] != cur) {
-              if (cur != 0xffffffffu) flush();
-              cur = iy[u];
-            }
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-              const int p = (v + LPF * j) * V;
-              if (p < n0)
-#pragma unroll
-                for (int e = 0; e < V; ++e) sacc[j][e] += signed_f64(x[u][j].e[e], ix[u] & TT_KEY_SIGN);
-            }
-          }
+      }
+    };
+    const int64_t n = we - wa;
+    uint32_t ixa[U], iya[U];
+    bool oka[U];
+    Vec<XT, V> xa[U][NJ];
+    // list entries are fetched 64 at a time, one per lane, one chunk ahead,
+    // so that the loads of X never wait on a list load issued just before
+    if constexpr (DB) {
+      const int B = G * U < 64 ? G * U : 64;
+      uint2 lc = lane < n ? list[wa + lane] : make_uint2(0u, 0u);
+      uint2 ln = 64 + lane < n ? list[wa + 64 + lane] : make_uint2(0u, 0u);
+      uint32_t ixb[U], iyb[U];
+      bool okb[U];
+      Vec<XT, V> xb[U][NJ];
+      auto next = [&](int64_t e0) {   // the chunk of entries [e0, e0 + 64) becomes current
+        if ((e0 & 63) == 0) {
+          lc = ln;
+          ln = e0 + 64 + lane < n ? list[wa + e0 + 64 + lane] : make_uint2(0u, 0u);
+        }
+      };
+      if (n > 0) issue(lc, 0, n, ixa, iya, oka, xa);
+      for (int64_t e0 = 0; e0 < n; e0 += 2 * B) {
+        if (e0 + B < n) {
+          next(e0 + B);
+          issue(lc, (int)((e0 + B) & 63), n - e0 - B, ixb, iyb, okb, xb);
+        }
+        consume(ixa, iya, oka, xa);
+        if (e0 + B >= n) break;
+        if (e0 + 2 * B < n) {
+          next(e0 + 2 * B);
+          issue(lc, (int)((e0 + 2 * B) & 63), n - e0 - 2 * B, ixa, iya, oka, xa);
+        }
+        consume(ixb, iyb, okb, xb);
+      }
+    } else {
+      uint2 nxt = lane < n ? list[wa + lane] : make_uint2(0u, 0u);
+      for (int64_t eb = 0; eb < n; eb += 64) {
+        const uint2 itl = nxt;
+        if (eb + 64 + lane < n) nxt = list[wa + eb + 64 + lane];
+        const int nb = (n - eb) < 64 ? (int)(n - eb) : 64;
+        for (int t = 0; t < nb; t += G * U) {
+          issue(itl, t, nb - t, ixa, iya, oka, xa);
+          consume(ixa, iya, oka, xa);
         }
       }
     }
@@ -492,7 +536,7 @@ hipError_t run_modek(const tt_plan_s* p, const XT* X, int k, WT* Y, int lpf_log2
 
 template <typename XT, typename WT, int V, int NJ>
 hipError_t run_gs(const tt_plan_s* p, const XT* X, int k, WT* Y, int lpf_log2) {
-  constexpr int U = NJ >= 8 ? 1 : 8 / NJ;
+  constexpr int U = NJ >= 4 ? 1 : 4 / NJ;
   const int64_t n0 = p->n[0], nk = p->n[k];
   int64_t M = 1, Rk = 1;
   for (int s = 1; s < k; ++s) M *= p->n[s];
@@ -504,7 +548,7 @@ hipError_t run_gs(const tt_plan_s* p, const XT* X, int k, WT* Y, int lpf_log2) {
     if ((e = launch_fibre_sort(p, k)) != hipSuccess) return e;
   }
   const size_t lds = (size_t)p->J * sizeof(double);
-  auto kern = k_sketch_gs<XT, WT, V, NJ, U>;
+  auto kern = lpf_log2 == 6 ? k_sketch_gs<XT, WT, V, NJ, U, true> : k_sketch_gs<XT, WT, V, NJ, U, false>;
   int per_cu = 0;
   if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TT_SKETCH_THREADS, lds)) != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
@@ -528,7 +572,7 @@ hipError_t run_gs(const tt_plan_s* p, const XT* X, int k, WT* Y, int lpf_log2) {
 
 template <typename XT, typename WT, int V, int NJ>
 hipError_t run_mode0(const tt_plan_s* p, const XT* X, WT* Y, int lpf_log2, int64_t chunk) {
-  constexpr int U = NJ >= 8 ? 1 : 8 / NJ;
+  constexpr int U = NJ >= 4 ? 1 : 4 / NJ;
   hipError_t e;
   {
     TTProfScope ps(p, TT_PROF_SKETCH_AUX);
