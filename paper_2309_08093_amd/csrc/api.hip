@@ -268,7 +268,6 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_KI = take(sizeof(uint32_t) * p->max_M);
   p->o_KO = take(sizeof(uint32_t) * p->max_R);
   p->o_cnt = take(sizeof(uint32_t) * (p->J + 1));
-  p->o_cursor = take(sizeof(uint32_t) * p->J);
   p->o_sortO = take(sizeof(uint32_t) * p->max_R);
   p->o_part = take(sizeof(double) * p->part_entries);
   p->o_chat = take(2 * ws * p->J * p->chat_cols);
@@ -297,6 +296,8 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   for (int k = 1; k < d; ++k)
     if (N / (p->n[0] * p->n[k]) > p->max_F) p->max_F = N / (p->n[0] * p->n[k]);
   p->o_fkeys = take(sizeof(uint32_t) * p->max_F);
+  // per-chunk bucket counts of the key sorts
+  p->o_hist = take(sizeof(uint32_t) * p->J * tt_sort_chunks(p->max_F > p->O0 ? p->max_F : p->O0));
   p->o_fsort = take(8 * p->max_F);
   p->o_pol = take(sizeof(float) * TT_MAX_ORDER * (TT_JPOLICY_FEATURES + TT_JPOLICY_OUTPUTS));
   p->ws_need = o;

@@ -57,42 +57,95 @@ __device__ __forceinline__ uint32_t key_add(uint32_t a, uint32_t b, uint32_t J) 
   return s | ((a ^ b) & TT_KEY_SIGN);
 }
 
-// out[q] = combined key (sum of hashes mod J, product of signs) of tuple q.
+// combined key (sum of hashes mod J, product of signs) of tuple q
+__device__ __forceinline__ uint32_t tuple_key(uint32_t q, const KeyArgs& a) {
+  uint32_t rem = q, key = 0;
+  for (int t = 0; t < a.nm; ++t) {
+    const int s = a.modes[t];
+    const uint32_t nxt = rem / (uint32_t)a.n[s];
+    key = key_add(key, a.tab[a.tab_off[s] + (rem - nxt * (uint32_t)a.n[s])], a.J);
+    rem = nxt;
+  }
+  return key;
+}
+
+// out[q] = key of tuple q (q < 2^31)
 __global__ void k_build_keys(uint32_t* out, int64_t count, KeyArgs a) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= count) return;
-  int64_t rem = q;
-  uint32_t key = 0;
-  for (int t = 0; t < a.nm; ++t) {
-    const int s = a.modes[t];
-    const int64_t i = rem % a.n[s];
-    rem /= a.n[s];
-    key = key_add(key, a.tab[a.tab_off[s] + i], a.J);
+  out[q] = tuple_key((uint32_t)q, a);
+}
+
+// Counting sort of tuple keys by bucket, in three launches and without
+// global atomics.  The tuples are cut into nb contiguous chunks.
+//  1. k_sort_count: workgroup w computes the keys of chunk w, stores them,
+//     counts them per bucket in LDS and writes the counts to hist[w][.].
+//  2. k_sort_scan (one workgroup): per bucket b, hist[w][b] becomes the
+//     number of earlier-chunk tuples in b; the bucket totals are scanned into
+//     off[0..J] (off[J] = number of tuples).
+//  3. k_sort_place: chunk w's tuples of bucket b go to positions
+//     off[b] + hist[w][b] onward, ranked inside the chunk by LDS atomics.
+// The order inside a bucket follows those atomics and is not fixed; the data
+// sketches that read the lists sum in FP64, so their output does not show it.
+constexpr int kSortThreads = 1024;
+constexpr int kSortPerThread = 8;       // tuples per thread and round, loaded before they are used
+constexpr int64_t kSortMaxChunks = 64;
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_count(uint32_t* __restrict__ keys, int64_t count, int64_t chunk,
+                                                             KeyArgs a, uint32_t* __restrict__ hist) {
+  extern __shared__ uint32_t h[];   // J
+  for (uint32_t b = threadIdx.x; b < a.J; b += blockDim.x) h[b] = 0u;
+  __syncthreads();
+  const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < count ? lo + chunk : count;
+  for (int64_t q0 = lo + threadIdx.x; q0 < hi; q0 += (int64_t)kSortPerThread * blockDim.x) {
+    uint32_t key[kSortPerThread];
+#pragma unroll
+    for (int u = 0; u < kSortPerThread; ++u) {
+      const int64_t q = q0 + (int64_t)u * blockDim.x;
+      key[u] = q < hi ? tuple_key((uint32_t)q, a) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kSortPerThread; ++u) {
+      const int64_t q = q0 + (int64_t)u * blockDim.x;
+      if (q < hi) {
+        keys[q] = key[u];
+        atomicAdd(&h[key[u] & TT_KEY_MASK], 1u);
+      }
+    }
   }
-  out[q] = key;
+  __syncthreads();
+  uint32_t* out = hist + (int64_t)blockIdx.x * a.J;
+  for (uint32_t b = threadIdx.x; b < a.J; b += blockDim.x) out[b] = h[b];
 }
 
-__global__ void k_fill_u32(uint32_t* p, int64_t count, uint32_t v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = v;
-}
-
-__global__ void k_count(const uint32_t* keys, int64_t count, uint32_t* cnt) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) atomicAdd(&cnt[keys[i] & TT_KEY_MASK], 1u);
-}
-
-// Exclusive scan of cnt[0..J) into off[0..J]; cursor[c] = off[c].  One block.
-__global__ void k_scan(const uint32_t* cnt, uint32_t* off, uint32_t* cursor, int32_t J) {
-  // exclusive prefix sum of cnt[0..J) into off (and cursor), off[J] = total;
-  // per-thread runs, then an inclusive scan by shuffles within each wave and
-  // over the wave totals
-  __shared__ uint32_t wsum[16];
+__global__ __launch_bounds__(kSortThreads) void k_sort_scan(uint32_t* __restrict__ hist, int32_t nb, int32_t J,
+                                                            uint32_t* __restrict__ off) {
+  extern __shared__ uint32_t tot[];   // J
+  __shared__ uint32_t wsum[kSortThreads / 64];
   const int t = threadIdx.x, T = blockDim.x, lane = t & 63, w = t >> 6, NW = T >> 6;
+  constexpr int CB = 16;   // chunk counts loaded together
+  for (int b = t; b < J; b += T) {
+    uint32_t run = 0;
+    for (int c0 = 0; c0 < nb; c0 += CB) {
+      uint32_t v[CB];
+#pragma unroll
+      for (int u = 0; u < CB; ++u) v[u] = c0 + u < nb ? hist[(int64_t)(c0 + u) * J + b] : 0u;
+#pragma unroll
+      for (int u = 0; u < CB; ++u)
+        if (c0 + u < nb) {
+          hist[(int64_t)(c0 + u) * J + b] = run;
+          run += v[u];
+        }
+    }
+    tot[b] = run;
+  }
+  __syncthreads();
+  // exclusive scan of tot: per-thread runs, shuffles within each wave, then
+  // over the wave totals
   const int per = (J + T - 1) / T;
   const int lo = min(J, t * per), hi = min(J, lo + per);
   uint32_t s = 0;
-  for (int c = lo; c < hi; ++c) s += cnt[c];
+  for (int c = lo; c < hi; ++c) s += tot[c];
   uint32_t x = s;
   for (int o = 1; o < 64; o <<= 1) {
     const uint32_t y = (uint32_t)__shfl_up((int)x, o, 64);
@@ -112,21 +165,49 @@ __global__ void k_scan(const uint32_t* cnt, uint32_t* off, uint32_t* cursor, int
   __syncthreads();
   uint32_t acc = wsum[w] + x - s;          // exclusive prefix of this thread's run
   if (t == T - 1) off[J] = acc + s;
-  for (int c = lo; c < hi; ++c) {   // cnt may alias cursor: read before writing
-    const uint32_t v = cnt[c];
+  for (int c = lo; c < hi; ++c) {
     off[c] = acc;
-    cursor[c] = acc;
-    acc += v;
+    acc += tot[c];
   }
 }
 
-// sorted[pos] = q | sign(q) << 31 grouped by bucket.
-__global__ void k_scatter(const uint32_t* keys, int64_t count, uint32_t* cursor, uint32_t* sorted) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= count) return;
-  const uint32_t key = keys[q];
-  const uint32_t pos = atomicAdd(&cursor[key & TT_KEY_MASK], 1u);
-  sorted[pos] = (uint32_t)q | (key & TT_KEY_SIGN);
+// FIBRE: the list of the k >= 1 sketch, tuple t = mu + M rho of a column
+// (modes 1..k-1 give mu, modes k+1..d-1 give rho) stored as {column-
+// independent fibre offset rho n_k M + mu with the key's sign bit; bucket}.
+// Otherwise the k = 0 bucket lists: {t with the key's sign bit}.
+template <bool FIBRE>
+__global__ __launch_bounds__(kSortThreads) void k_sort_place(const uint32_t* __restrict__ keys, int64_t count,
+                                                             int64_t chunk, const uint32_t* __restrict__ hist,
+                                                             const uint32_t* __restrict__ off, int32_t J,
+                                                             uint32_t* __restrict__ sorted, uint2* __restrict__ fsorted,
+                                                             uint32_t M, uint32_t nkM) {
+  extern __shared__ uint32_t h[];   // J
+  const uint32_t* hw = hist + (int64_t)blockIdx.x * J;
+  for (int b = threadIdx.x; b < J; b += blockDim.x) h[b] = off[b] + hw[b];
+  __syncthreads();
+  const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < count ? lo + chunk : count;
+  for (int64_t q0 = lo + threadIdx.x; q0 < hi; q0 += (int64_t)kSortPerThread * blockDim.x) {
+    uint32_t key[kSortPerThread];
+#pragma unroll
+    for (int u = 0; u < kSortPerThread; ++u) {
+      const int64_t q = q0 + (int64_t)u * blockDim.x;
+      key[u] = q < hi ? keys[q] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kSortPerThread; ++u) {
+      const int64_t q = q0 + (int64_t)u * blockDim.x;
+      if (q < hi) {
+        const uint32_t c = key[u] & TT_KEY_MASK;
+        const uint32_t pos = atomicAdd(&h[c], 1u);
+        if constexpr (FIBRE) {
+          const uint32_t rho = (uint32_t)q / M, mu = (uint32_t)q - rho * M;
+          fsorted[pos] = make_uint2((rho * nkM + mu) | (key[u] & TT_KEY_SIGN), c);
+        } else {
+          sorted[pos] = (uint32_t)q | (key[u] & TT_KEY_SIGN);
+        }
+      }
+    }
+  }
 }
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -147,7 +228,15 @@ hipError_t launch_gen_tables(const tt_plan_s* p, int64_t sweep) {
   return hipGetLastError();
 }
 
-hipError_t launch_build_keys_modes(const tt_plan_s* p, uint32_t* out, int64_t count, const int* modes, int nm) {
+int64_t tt_sort_chunks(int64_t count) {
+  const int64_t per = (int64_t)kSortPerThread * kSortThreads;   // one round of tuples per workgroup
+  int64_t nb = (count + per - 1) / per;
+  return nb < 1 ? 1 : (nb > kSortMaxChunks ? kSortMaxChunks : nb);
+}
+
+namespace {
+
+KeyArgs key_args(const tt_plan_s* p, const int* modes, int nm) {
   KeyArgs a{};
   a.tab = p->at<uint32_t>(p->o_tab);
   for (int s = 0; s < p->d; ++s) {
@@ -157,8 +246,30 @@ hipError_t launch_build_keys_modes(const tt_plan_s* p, uint32_t* out, int64_t co
   for (int t = 0; t < nm; ++t) a.modes[t] = modes[t];
   a.nm = nm;
   a.J = (uint32_t)p->J;
+  return a;
+}
+
+// keys (count entries) and the J+1 offsets of the sort of `count` tuples
+hipError_t sort_keys(const tt_plan_s* p, const int* modes, int nm, int64_t count, uint32_t* keys, uint32_t* off,
+                     int64_t* nb_out, int64_t* chunk_out) {
+  if (count < 1 || count >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  const int64_t nb = tt_sort_chunks(count), chunk = (count + nb - 1) / nb;
+  uint32_t* hist = p->at<uint32_t>(p->o_hist);
+  const size_t lds = sizeof(uint32_t) * p->J;
+  hipLaunchKernelGGL(k_sort_count, dim3((unsigned)nb), dim3(kSortThreads), lds, p->stream, keys, count, chunk,
+                     key_args(p, modes, nm), hist);
+  hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kSortThreads), lds, p->stream, hist, (int32_t)nb, (int32_t)p->J, off);
+  *nb_out = nb;
+  *chunk_out = chunk;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_build_keys_modes(const tt_plan_s* p, uint32_t* out, int64_t count, const int* modes, int nm) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_build_keys, dim3(nblk(count, 256)), dim3(256), 0, p->stream, out, count, a);
+  if (count >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_build_keys, dim3(nblk(count, 256)), dim3(256), 0, p->stream, out, count, key_args(p, modes, nm));
   return hipGetLastError();
 }
 
@@ -169,43 +280,21 @@ hipError_t launch_build_keys(const tt_plan_s* p, uint32_t* out, int64_t count, i
   return launch_build_keys_modes(p, out, count, modes, nm);
 }
 
-// Fibre list of the k >= 1 sketch: fibre t = mu + M rho of a column (modes
-// 1..k-1 give mu, modes k+1..d-1 give rho) goes to its key's bucket as
-// {column-independent fibre offset rho n_k M + mu, with the key's sign bit;
-//  the key's bucket}.
-__global__ void k_scatter_fibres(const uint32_t* __restrict__ keys, int64_t F, int64_t M, int64_t nkM,
-                                 uint32_t* __restrict__ cursor, uint2* __restrict__ sorted) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= F) return;
-  const uint32_t key = keys[t];
-  const uint32_t c = key & TT_KEY_MASK;
-  const uint32_t pos = atomicAdd(&cursor[c], 1u);
-  const int64_t rho = t / M, mu = t - rho * M;
-  sorted[pos] = make_uint2((uint32_t)(rho * nkM + mu) | (key & TT_KEY_SIGN), c);
-}
-
 // Bucket lists of the k = 0 data sketch: the outer mode tuples (modes
 // 2..d-1) grouped by their partial hash.  Uses o_KO as key scratch.
 hipError_t launch_outer_sort(const tt_plan_s* p) {
   const int64_t O = p->O0;
+  int modes[TT_MAX_ORDER];
+  int nm = 0;
+  for (int s = 2; s < p->d; ++s) modes[nm++] = s;
   uint32_t* keys = p->at<uint32_t>(p->o_KO);
-  uint32_t* cnt = p->at<uint32_t>(p->o_cnt);          // J+1
-  uint32_t* cursor = p->at<uint32_t>(p->o_cursor);    // J
-  uint32_t* sorted = p->at<uint32_t>(p->o_sortO);     // O
-  hipError_t e;
-  if (p->d >= 3) {
-    e = launch_build_keys(p, keys, O, 2, p->d - 1);
-  } else {
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, p->stream, keys, (int64_t)1, 0u);
-    e = hipGetLastError();
-  }
+  uint32_t* off = p->at<uint32_t>(p->o_cnt);          // J+1
+  int64_t nb = 0, chunk = 0;
+  hipError_t e = sort_keys(p, modes, nm, O, keys, off, &nb, &chunk);
   if (e != hipSuccess) return e;
-  // counts accumulate in cursor; the scan turns them into the J+1 offsets in
-  // cnt and resets cursor to the offsets for the scatter.
-  hipLaunchKernelGGL(k_fill_u32, dim3(nblk(p->J, 256)), dim3(256), 0, p->stream, cursor, p->J, 0u);
-  hipLaunchKernelGGL(k_count, dim3(nblk(O, 256)), dim3(256), 0, p->stream, keys, O, cursor);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, cursor, cnt, cursor, (int32_t)p->J);
-  hipLaunchKernelGGL(k_scatter, dim3(nblk(O, 256)), dim3(256), 0, p->stream, keys, O, cursor, sorted);
+  hipLaunchKernelGGL(k_sort_place<false>, dim3((unsigned)nb), dim3(kSortThreads), sizeof(uint32_t) * p->J, p->stream,
+                     keys, O, chunk, p->at<uint32_t>(p->o_hist), off, (int32_t)p->J, p->at<uint32_t>(p->o_sortO),
+                     (uint2*)nullptr, 1u, 1u);
   return hipGetLastError();
 }
 
@@ -216,23 +305,18 @@ hipError_t launch_fibre_sort(const tt_plan_s* p, int k) {
   for (int s = 1; s < k; ++s) M *= p->n[s];
   for (int s = k + 1; s < p->d; ++s) Rk *= p->n[s];
   const int64_t F = M * Rk;
+  if (p->n[k] * F >= ((int64_t)1 << 31)) return hipErrorInvalidValue;   // fibre offsets carry a sign bit
   int modes[TT_MAX_ORDER];
   int nm = 0;
   for (int s = 1; s < p->d; ++s)
     if (s != k) modes[nm++] = s;
   uint32_t* keys = p->at<uint32_t>(p->o_fkeys);
   uint32_t* off = p->at<uint32_t>(p->o_cnt);
-  uint32_t* cursor = p->at<uint32_t>(p->o_cursor);
-  hipError_t e;
-  if (nm > 0) {
-    if ((e = launch_build_keys_modes(p, keys, F, modes, nm)) != hipSuccess) return e;
-  } else {
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, p->stream, keys, (int64_t)1, 0u);
-  }
-  hipLaunchKernelGGL(k_fill_u32, dim3(nblk(p->J, 256)), dim3(256), 0, p->stream, cursor, p->J, 0u);
-  hipLaunchKernelGGL(k_count, dim3(nblk(F, 256)), dim3(256), 0, p->stream, keys, F, cursor);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, p->stream, cursor, off, cursor, (int32_t)p->J);
-  hipLaunchKernelGGL(k_scatter_fibres, dim3(nblk(F, 256)), dim3(256), 0, p->stream, keys, F, M, p->n[k] * M, cursor,
-                     p->at<uint2>(p->o_fsort));
+  int64_t nb = 0, chunk = 0;
+  hipError_t e = sort_keys(p, modes, nm, F, keys, off, &nb, &chunk);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sort_place<true>, dim3((unsigned)nb), dim3(kSortThreads), sizeof(uint32_t) * p->J, p->stream,
+                     keys, F, chunk, p->at<uint32_t>(p->o_hist), off, (int32_t)p->J, (uint32_t*)nullptr,
+                     p->at<uint2>(p->o_fsort), (uint32_t)M, (uint32_t)(p->n[k] * M));
   return hipGetLastError();
 }

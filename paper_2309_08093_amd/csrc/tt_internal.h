@@ -54,7 +54,7 @@ struct tt_plan_s {
   size_t ws_need;
   void* prof;                  // ProfState* when measurement is enabled, else null
 
-  size_t o_tab, o_KI, o_KO, o_cnt, o_cursor, o_sortO, o_part, o_chat, o_pre, o_suf, o_SH, o_Y,
+  size_t o_tab, o_KI, o_KO, o_cnt, o_hist, o_sortO, o_part, o_chat, o_pre, o_suf, o_SH, o_Y,
       o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_fkeys, o_fsort, o_pol, o_gsum, o_resU, o_resH,
       o_tw;
   int64_t tw_J;                // J whose roots of unity the o_tw table holds (0: none)
@@ -103,6 +103,7 @@ hipError_t launch_build_keys(const tt_plan_s* p, uint32_t* out, int64_t count, i
 hipError_t launch_build_keys_modes(const tt_plan_s* p, uint32_t* out, int64_t count, const int* modes, int nm);
 hipError_t launch_outer_sort(const tt_plan_s* p);     // k = 0 bucket lists (modes 2..d-1)
 hipError_t launch_fibre_sort(const tt_plan_s* p, int k);   // k >= 1 fibre lists by key
+int64_t tt_sort_chunks(int64_t count);                     // workgroups of a key sort of count tuples
 hipError_t launch_sketch_tensor(const tt_plan_s* p, const void* X, int k, void* Y);
 hipError_t launch_core_fft(const tt_plan_s* p, const CoreDesc& cd, int core_lo, int core_hi, int skip);
 hipError_t launch_interface_from_chat(const tt_plan_s* p, const CoreDesc& cd, int k, void* SH);
