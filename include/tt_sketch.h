@@ -191,8 +191,10 @@ tt_status tt_als_sweep(tt_plan plan, const void* X, void* const* cores, double* 
  * device's CU count.  Synchronises and recreates the plan's streams. */
 tt_status tt_plan_set_overlap(tt_plan plan, int32_t reserved_cus);
 
-/* Measurement: when enabled, every launch of the kernels below is bracketed
- * by a pair of HIP events recorded on the plan's stream.  Classes: */
+/* Measurement: every launch of the kernels of a timed class below is
+ * bracketed by a pair of HIP events recorded on the plan's stream.  Each
+ * record leaves a short gap on the GPU (a few microseconds), so time only the
+ * classes you need.  Classes: */
 #define TT_PROF_SKETCH0 0    /* data sketch main kernel, k = 0 (bucket gather) */
 #define TT_PROF_SKETCHK 1    /* data sketch main kernel, k >= 1 (LDS buckets) */
 #define TT_PROF_SKETCH_AUX 2 /* data sketch key tables, bucket lists, partial sums */
@@ -203,6 +205,11 @@ tt_status tt_plan_set_overlap(tt_plan plan, int32_t reserved_cus);
 #define TT_PROF_RESIDUAL 7   /* residual pass */
 #define TT_PROF_TABLES 8     /* hash/sign table generation */
 #define TT_PROF_NCLASS 9
+#define TT_PROF_ALL 0x1ff    /* every class */
+/* enable: bit mask of the classes to time (bit c for class c, TT_PROF_ALL for
+ * all of them); 0 stops measurement and releases its events (after
+ * synchronising the plan's stream).  Counts already taken are kept until the
+ * next read while the mask changes. */
 tt_status tt_plan_profile(tt_plan plan, int32_t enable);
 /* Synchronise, then return per class the summed milliseconds and the number
  * of launches since the last read (arrays of nclass <= TT_PROF_NCLASS

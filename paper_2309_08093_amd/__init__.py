@@ -208,8 +208,15 @@ class Plan:
         check(_lib.tt_als_sweep(self._h, _ptr(X), arr, None), "tt_als_sweep")
         return None
 
-    def profile(self, enable=True):
-        check(_lib.tt_plan_profile(self._h, 1 if enable else 0), "tt_plan_profile")
+    def profile(self, enable=True, classes=None):
+        """Time the launches of `classes` (names from _abi.PROF_CLASSES; all
+        if None) with HIP events; enable=False stops measurement."""
+        mask = 0
+        if enable:
+            names = _abi.PROF_CLASSES if classes is None else classes
+            for c in names:
+                mask |= 1 << _abi.PROF_CLASSES.index(c)
+        check(_lib.tt_plan_profile(self._h, mask), "tt_plan_profile")
 
     def profile_read(self):
         """{class: (total ms, launches)} since the last read (synchronises)."""

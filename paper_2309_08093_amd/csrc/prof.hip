@@ -6,26 +6,42 @@
 
 namespace {
 struct ProfState {
+  uint32_t mask = 0;   // classes timed (bit c for class c)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> done[TT_PROF_NCLASS];
   hipEvent_t open[TT_PROF_NCLASS] = {};
+  std::vector<hipEvent_t> pool;   // events of earlier reads, recorded again
+
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+  }
 };
+
+bool timed(const tt_plan_s* p, int cls) {
+  return p->prof && ((static_cast<ProfState*>(p->prof)->mask >> cls) & 1u);
+}
 }  // namespace
 
 void tt_prof_begin(const tt_plan_s* p, int cls) {
-  if (!p->prof) return;
+  if (!timed(p, cls)) return;
   ProfState* st = static_cast<ProfState*>(p->prof);
-  hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return;
+  hipEvent_t e = st->take();
+  if (!e) return;
   hipEventRecord(e, p->stream);
   st->open[cls] = e;
 }
 
 void tt_prof_end(const tt_plan_s* p, int cls) {
-  if (!p->prof) return;
+  if (!timed(p, cls)) return;
   ProfState* st = static_cast<ProfState*>(p->prof);
   if (!st->open[cls]) return;
-  hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return;
+  hipEvent_t e = st->take();
+  if (!e) return;
   hipEventRecord(e, p->stream);
   st->done[cls].emplace_back(st->open[cls], e);
   st->open[cls] = nullptr;
@@ -34,11 +50,15 @@ void tt_prof_end(const tt_plan_s* p, int cls) {
 void tt_prof_free(tt_plan_s* p) {
   if (!p->prof) return;
   ProfState* st = static_cast<ProfState*>(p->prof);
+  (void)hipStreamSynchronize(p->stream);
   for (auto& v : st->done)
     for (auto& pr : v) {
       hipEventDestroy(pr.first);
       hipEventDestroy(pr.second);
     }
+  for (hipEvent_t e : st->open)
+    if (e) hipEventDestroy(e);
+  for (hipEvent_t e : st->pool) hipEventDestroy(e);
   delete st;
   p->prof = nullptr;
 }
@@ -47,8 +67,12 @@ extern "C" {
 
 tt_status tt_plan_profile(tt_plan p, int32_t enable) {
   if (!p) return tt_fail(TT_ERR_ARG, "null plan");
-  if (enable && !p->prof) p->prof = new ProfState();
-  if (!enable) tt_prof_free(p);
+  if (!enable) {
+    tt_prof_free(p);
+    return TT_OK;
+  }
+  if (!p->prof) p->prof = new ProfState();
+  static_cast<ProfState*>(p->prof)->mask = (uint32_t)enable;
   return TT_OK;
 }
 
@@ -68,8 +92,8 @@ tt_status tt_plan_profile_read(tt_plan p, int32_t nclass, double* ms, int64_t* l
         ms[c] += t;
         launches[c] += 1;
       }
-      hipEventDestroy(pr.first);
-      hipEventDestroy(pr.second);
+      st->pool.push_back(pr.first);
+      st->pool.push_back(pr.second);
     }
     st->done[c].clear();
   }
