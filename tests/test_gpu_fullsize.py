@@ -1,0 +1,97 @@
+"""GPU parity at the full sizes of the two dense workloads, in the launch
+configuration bench.py times (same shapes, J, seed and sketch kernels):
+
+  * 200^4 FP32 tensor from a random TT with ranks 10 plus noise 1e-2, J=4000;
+  * 64^5 tensor stored BF16 from a random TT with ranks 8 plus noise 1e-3,
+    J=3000.
+
+The oracle cannot sketch 1.6e9 entries in seconds, so the data sketches are
+compared on sampled columns: column c of Y_k is the data sketch of the
+sub-tensor with i_k = c, which the oracle computes as a tensor whose mode k
+has the single index c (the mode-k table is not used for Y_k).  Tolerance as
+for the small cases: 1e-5 relative per column (FP32 work type).
+
+The residual pass is checked at full size by a property that holds at any
+size: for the noise-free tensor and the cores that generated it, the exact
+relative residual is the rounding of X to its storage type (unit roundoff
+2^-8 for BF16) plus the FP32 rounding of the TT values, so it stays below
+2^-8 + 1e-5 (BF16) or 1e-5 (FP32); a wrong slab or rank index gives O(1).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import synth
+from oracle import sketch
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: n, ranks, J, noise, stored dtype, gram mode, (k = 0 kernel, k >= 1 kernel)
+    "200^4 f32": ([200] * 4, [1, 10, 10, 10, 1], 4000, 1e-2, "f32", "work", ("k_sketch_mode0", "k_sketch_gs")),
+    "64^5 bf16": ([64] * 5, [1, 8, 8, 8, 8, 1], 3000, 1e-3, "bf16", "bf16", ("k_sketch_mode0", "k_sketch_gs")),
+}
+SEED = 2023   # bench.py's default seed
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tts():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2309_08093_amd as m
+    return m
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_full_size_sketch_sampled_columns(tts, name):
+    n, R, J, noise, xd, gram, kernels = CASES[name]
+    d = len(n)
+    say("full-size sketch columns", name)
+    X, _ = synth.tt_tensor_device(n, R, noise, SEED, dtype=xd, device="cuda")
+    plan = tts.Plan(n, R, J, 1e-3, seed=SEED, x_dtype=xd, work_dtype="f32", gram=gram, device="cuda")
+    hs, vs = [], []
+    for s in range(d):
+        h, v = plan.get_tables(s)
+        hs.append(h)
+        vs.append(v)
+    Xv = X.view(*n[::-1])   # torch dims (i_{d-1}, ..., i_0): i_0 fastest
+    for k in range(d):
+        assert plan.sketch_kernel(k) == (kernels[0] if k == 0 else kernels[1]), k
+        say("mode", k, plan.sketch_kernel(k))
+        Y = plan.sketch_tensor(X, k).cpu().numpy().astype(np.float64).reshape(J, n[k], order="F")
+        for c in (n[k] // 2 + 1, n[k] - 1):
+            sub = Xv.select(d - 1 - k, c).contiguous().float().cpu().numpy().astype(np.float64).reshape(-1)
+            nsub = list(n)
+            nsub[k] = 1
+            Yo = sketch.data_sketch(sub, nsub, k, hs, vs, J)[:, 0]
+            assert rel(Y[:, c], Yo) < 1e-5, (k, c, rel(Y[:, c], Yo))
+    del X, Xv, plan
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_full_size_residual_of_generating_cores(tts, name):
+    n, R, J, _, xd, gram, _ = CASES[name]
+    say("full-size residual", name)
+    X, cores = synth.tt_tensor_device(n, R, 0.0, SEED, dtype=xd, device="cuda")
+    plan = tts.Plan(n, R, J, 1e-3, seed=SEED, x_dtype=xd, work_dtype="f32", gram=gram, device="cuda")
+    dev_cores = [tts.core_to_device(c, "cuda") for c in cores]
+    r = plan.residual(X, dev_cores)
+    bound = (2.0 ** -8 if xd == "bf16" else 0.0) + 1e-5
+    assert 0.0 <= r < bound, r
+    del X, plan, dev_cores
+    torch.cuda.empty_cache()
