@@ -106,6 +106,11 @@ SKETCH_CASES = [
     ([16, 16, 16, 16], 32, "f64", "f64"),
     ([37, 12, 11, 13], 40, "f32", "f32"),      # n_0 not a multiple of 4: scalar loads
     ([8, 40, 50], 24, "f64", "f64"),           # lane groups of 4 fibres
+    # one fibre fills the wave (double-buffered loads), with a ragged batch tail
+    ([256, 20, 20, 10], 64, "f32", "f32"),
+    ([300, 12, 10, 7], 30, "f32", "f32"),      # two vectors per lane
+    # the largest sketch size and the largest n_0
+    ([4096, 3, 2], 8192, "f32", "f32"),
 ]
 
 
