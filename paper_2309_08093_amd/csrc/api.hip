@@ -292,13 +292,24 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_resH = nH <= ((int64_t)1 << 26) ? take(ws * nH) : 0;
   p->o_gold = take(sizeof(double));
   p->o_Yall = take(ws * p->J * p->tab_off[d]);   // Y_k of every mode for one sweep
-  p->max_F = 1;
-  for (int k = 1; k < d; ++k)
-    if (N / (p->n[0] * p->n[k]) > p->max_F) p->max_F = N / (p->n[0] * p->n[k]);
-  p->o_fkeys = take(sizeof(uint32_t) * p->max_F);
-  // per-chunk bucket counts of the key sorts
-  p->o_hist = take(sizeof(uint32_t) * p->J * tt_sort_chunks(p->max_F > p->O0 ? p->max_F : p->O0));
-  p->o_fsort = take(8 * p->max_F);
+  // key sorts: slot 0 = the outer tuples (O0), slot k = the fibres of one
+  // column of mode k (N / (n_0 n_k))
+  {
+    int64_t nkeys = 0, nlist = 0, nhist = 0;
+    for (int s = 0; s < d; ++s) {
+      const int64_t cnt = s == 0 ? p->O0 : N / (p->n[0] * p->n[s]);
+      p->skeys_off[s] = nkeys;
+      p->hist_off[s] = nhist;
+      nkeys += cnt;
+      nhist += p->J * tt_sort_chunks(cnt);
+      p->flist_off[s] = nlist;
+      if (s > 0) nlist += cnt;
+    }
+    p->o_skeys = take(sizeof(uint32_t) * nkeys);
+    p->o_hist = take(sizeof(uint32_t) * nhist);
+    p->o_flist = take(8 * (nlist > 0 ? nlist : 1));
+    p->o_foff = take(sizeof(uint32_t) * d * (p->J + 1));
+  }
   p->o_pol = take(sizeof(float) * TT_MAX_ORDER * (TT_JPOLICY_FEATURES + TT_JPOLICY_OUTPUTS));
   p->ws_need = o;
   p->ws = nullptr;
@@ -583,6 +594,19 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
   const bool overlap = !(p->flags & TT_FLAG_SERIAL);
   char* Yall = p->ws + p->o_Yall;
   StreamRestore restore{p};
+  // the bucket and fibre lists of every data sketch of the sweep are built
+  // in one launch set ahead of the sketches, which then skip their own sorts
+  struct ListsReady {
+    tt_plan p;
+    ~ListsReady() { p->lists_ready = false; }
+  } lists_guard{p};
+  auto sort_lists = [&]() -> tt_status {
+    TTProfScope ps(p, TT_PROF_SKETCH_AUX);
+    const hipError_t e = launch_sweep_sorts(p);
+    if (e != hipSuccess) return tt_fail(TT_ERR_HIP, "key sort launch failed: %s", hipGetErrorString(e));
+    p->lists_ready = true;
+    return TT_OK;
+  };
   if (overlap) {
     if ((st = make_streams(p))) return st;
     TT_HIP_TRY(hipEventRecord(p->ev_fork, p->user_stream));
@@ -591,14 +615,18 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
     p->stream = p->side;
     const int ncu = device_cus();
     p->sketch_cus = (p->reserved_cus > 0 && ncu > p->reserved_cus) ? ncu - p->reserved_cus : 0;
+    if ((st = sort_lists())) return st;
     for (int k = 0; k < d; ++k) {
       const hipError_t e = launch_sketch_tensor(p, X, k, Yall + p->wsize() * p->J * p->tab_off[k]);
       if (e != hipSuccess) return tt_fail(TT_ERR_HIP, "data sketch launch failed: %s", hipGetErrorString(e));
       TT_HIP_TRY(hipEventRecord(p->ev_y[k], p->side));
     }
     TT_HIP_TRY(hipEventRecord(p->ev_join, p->side));
+    p->lists_ready = false;
     p->stream = p->chain;
     p->sketch_cus = 0;
+  } else if ((st = sort_lists())) {
+    return st;
   }
   if ((st = tt_sweep_begin(p, G, cd))) return st;
   for (int k = 0; k < d; ++k) {
@@ -611,6 +639,7 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
     }
     if ((st = tt_sweep_update(p, G, cd, k, Y))) return st;
   }
+  p->lists_ready = false;
   if (overlap) {
     TT_HIP_TRY(hipStreamWaitEvent(p->chain, p->ev_join, 0));
     TT_HIP_TRY(hipEventRecord(p->ev_done, p->chain));

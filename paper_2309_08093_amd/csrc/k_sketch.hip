@@ -545,7 +545,7 @@ hipError_t run_gs(const tt_plan_s* p, const XT* X, int k, WT* Y, int lpf_log2) {
   hipError_t e;
   {
     TTProfScope ps(p, TT_PROF_SKETCH_AUX);
-    if ((e = launch_fibre_sort(p, k)) != hipSuccess) return e;
+    if (!p->lists_ready && (e = launch_fibre_sort(p, k)) != hipSuccess) return e;
   }
   const size_t lds = (size_t)p->J * sizeof(double);
   auto kern = lpf_log2 == 6 ? k_sketch_gs<XT, WT, V, NJ, U, true> : k_sketch_gs<XT, WT, V, NJ, U, false>;
@@ -560,7 +560,7 @@ hipError_t run_gs(const tt_plan_s* p, const XT* X, int k, WT* Y, int lpf_log2) {
   {
     TTProfScope ps(p, TT_PROF_SKETCHK);
     hipLaunchKernelGGL(kern, dim3((unsigned)W), dim3(TT_SKETCH_THREADS), lds, p->stream, X, tab0,
-                       p->at<uint2>(p->o_fsort), part, (int32_t)n0, (int32_t)nk, M, F, (uint32_t)p->J, lpf_log2,
+                       tt_fibre_list(p, k), part, (int32_t)n0, (int32_t)nk, M, F, (uint32_t)p->J, lpf_log2,
                        (int32_t)maxslots);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -576,7 +576,7 @@ hipError_t run_mode0(const tt_plan_s* p, const XT* X, WT* Y, int lpf_log2, int64
   hipError_t e;
   {
     TTProfScope ps(p, TT_PROF_SKETCH_AUX);
-    if ((e = launch_outer_sort(p)) != hipSuccess) return e;
+    if (!p->lists_ready && (e = launch_outer_sort(p)) != hipSuccess) return e;
   }
   const int64_t n0 = p->n[0], n1 = p->n[1];
   const uint32_t* tab1 = p->at<uint32_t>(p->o_tab) + p->tab_off[1];

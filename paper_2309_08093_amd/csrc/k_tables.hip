@@ -77,12 +77,16 @@ __global__ void k_build_keys(uint32_t* out, int64_t count, KeyArgs a) {
 }
 
 // Counting sort of tuple keys by bucket, in three launches and without
-// global atomics.  The tuples are cut into nb contiguous chunks.
-//  1. k_sort_count: workgroup w computes the keys of chunk w, stores them,
-//     counts them per bucket in LDS and writes the counts to hist[w][.].
-//  2. k_sort_scan (one workgroup): per bucket b, hist[w][b] becomes the
-//     number of earlier-chunk tuples in b; the bucket totals are scanned into
-//     off[0..J] (off[J] = number of tuples).
+// global atomics.  One launch set sorts several tuple sets at once (the
+// outer tuples of the k = 0 sketch and the fibres of every key-grouped
+// k >= 1 sketch of a sweep): each is a job, and the tuples of a job are cut
+// into nb contiguous chunks.
+//  1. k_sort_count: one workgroup per (job, chunk w) computes the keys of the
+//     chunk, stores them, counts them per bucket in LDS and writes the
+//     counts to hist[w][.] of its job.
+//  2. k_sort_scan (one workgroup per job): per bucket b, hist[w][b] becomes
+//     the number of earlier-chunk tuples in b; the bucket totals are scanned
+//     into off[0..J] (off[J] = number of tuples).
 //  3. k_sort_place: chunk w's tuples of bucket b go to positions
 //     off[b] + hist[w][b] onward, ranked inside the chunk by LDS atomics.
 // The order inside a bucket follows those atomics and is not fixed; the data
@@ -91,18 +95,61 @@ constexpr int kSortThreads = 1024;
 constexpr int kSortPerThread = 8;       // tuples per thread and round, loaded before they are used
 constexpr int64_t kSortMaxChunks = 64;
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_count(uint32_t* __restrict__ keys, int64_t count, int64_t chunk,
-                                                             KeyArgs a, uint32_t* __restrict__ hist) {
+struct SortJob {
+  int64_t count, chunk;   // tuples, tuples per chunk
+  int32_t nb, blk0;       // chunks, first workgroup of the count and place launches
+  int32_t lo, ex;         // the tuple's modes: lo..d-1 except ex, the first varying fastest
+  int32_t fibre;          // list entry layout: fibre (uint2) or outer tuple (uint32)
+  uint32_t M, nkM;        // fibre t = mu + M rho -> offset rho nkM + mu
+  uint32_t* keys;
+  uint32_t* hist;         // nb x J
+  uint32_t* off;          // J + 1
+  void* list;
+};
+
+struct SortArgs {
+  const uint32_t* tab;
+  int32_t tab_off[TT_MAX_ORDER];
+  int32_t n[TT_MAX_ORDER];
+  int32_t d, njobs;
+  uint32_t J;
+  SortJob job[TT_MAX_ORDER];
+};
+
+// the job of workgroup b of a count / place launch (uniform across the workgroup)
+__device__ __forceinline__ int job_of(const SortArgs& a, int b) {
+  int j = 0;
+  while (j + 1 < a.njobs && b >= a.job[j + 1].blk0) ++j;
+  return j;
+}
+
+__device__ __forceinline__ uint32_t job_key(uint32_t q, const SortArgs& a, int lo, int ex) {
+  uint32_t rem = q, key = 0;
+  for (int s = lo; s < a.d; ++s) {
+    if (s == ex) continue;
+    const uint32_t ns = (uint32_t)a.n[s], nxt = rem / ns;
+    key = key_add(key, a.tab[a.tab_off[s] + (rem - nxt * ns)], a.J);
+    rem = nxt;
+  }
+  return key;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_count(SortArgs a) {
   extern __shared__ uint32_t h[];   // J
+  const int j = job_of(a, blockIdx.x);
+  const int64_t count = a.job[j].count, chunk = a.job[j].chunk;
+  const int lo_mode = a.job[j].lo, ex = a.job[j].ex;
+  uint32_t* __restrict__ keys = a.job[j].keys;
+  const int w = blockIdx.x - a.job[j].blk0;
   for (uint32_t b = threadIdx.x; b < a.J; b += blockDim.x) h[b] = 0u;
   __syncthreads();
-  const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < count ? lo + chunk : count;
+  const int64_t lo = w * chunk, hi = lo + chunk < count ? lo + chunk : count;
   for (int64_t q0 = lo + threadIdx.x; q0 < hi; q0 += (int64_t)kSortPerThread * blockDim.x) {
     uint32_t key[kSortPerThread];
 #pragma unroll
     for (int u = 0; u < kSortPerThread; ++u) {
       const int64_t q = q0 + (int64_t)u * blockDim.x;
-      key[u] = q < hi ? tuple_key((uint32_t)q, a) : 0u;
+      key[u] = q < hi ? job_key((uint32_t)q, a, lo_mode, ex) : 0u;
     }
 #pragma unroll
     for (int u = 0; u < kSortPerThread; ++u) {
@@ -114,14 +161,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(uint32_t* __restric
     }
   }
   __syncthreads();
-  uint32_t* out = hist + (int64_t)blockIdx.x * a.J;
+  uint32_t* out = a.job[j].hist + (int64_t)w * a.J;
   for (uint32_t b = threadIdx.x; b < a.J; b += blockDim.x) out[b] = h[b];
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_scan(uint32_t* __restrict__ hist, int32_t nb, int32_t J,
-                                                            uint32_t* __restrict__ off) {
+__global__ __launch_bounds__(kSortThreads) void k_sort_scan(SortArgs a) {
   extern __shared__ uint32_t tot[];   // J
   __shared__ uint32_t wsum[kSortThreads / 64];
+  const int J = (int)a.J, nb = a.job[blockIdx.x].nb;
+  uint32_t* __restrict__ hist = a.job[blockIdx.x].hist;
+  uint32_t* __restrict__ off = a.job[blockIdx.x].off;
   const int t = threadIdx.x, T = blockDim.x, lane = t & 63, w = t >> 6, NW = T >> 6;
   constexpr int CB = 16;   // chunk counts loaded together
   for (int b = t; b < J; b += T) {
@@ -171,21 +220,26 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scan(uint32_t* __restrict
   }
 }
 
-// FIBRE: the list of the k >= 1 sketch, tuple t = mu + M rho of a column
-// (modes 1..k-1 give mu, modes k+1..d-1 give rho) stored as {column-
-// independent fibre offset rho n_k M + mu with the key's sign bit; bucket}.
-// Otherwise the k = 0 bucket lists: {t with the key's sign bit}.
-template <bool FIBRE>
-__global__ __launch_bounds__(kSortThreads) void k_sort_place(const uint32_t* __restrict__ keys, int64_t count,
-                                                             int64_t chunk, const uint32_t* __restrict__ hist,
-                                                             const uint32_t* __restrict__ off, int32_t J,
-                                                             uint32_t* __restrict__ sorted, uint2* __restrict__ fsorted,
-                                                             uint32_t M, uint32_t nkM) {
+// Fibre lists (the k >= 1 sketch): tuple t = mu + M rho of a column (modes
+// 1..k-1 give mu, modes k+1..d-1 give rho) stored as {column-independent
+// fibre offset rho n_k M + mu with the key's sign bit; bucket}.  Outer lists
+// (the k = 0 sketch): {t with the key's sign bit}.
+__global__ __launch_bounds__(kSortThreads) void k_sort_place(SortArgs a) {
   extern __shared__ uint32_t h[];   // J
-  const uint32_t* hw = hist + (int64_t)blockIdx.x * J;
+  const int j = job_of(a, blockIdx.x);
+  const int J = (int)a.J;
+  const int64_t count = a.job[j].count, chunk = a.job[j].chunk;
+  const int w = blockIdx.x - a.job[j].blk0;
+  const uint32_t* __restrict__ keys = a.job[j].keys;
+  const uint32_t* hw = a.job[j].hist + (int64_t)w * J;
+  const uint32_t* off = a.job[j].off;
+  const bool fibre = a.job[j].fibre != 0;
+  const uint32_t M = a.job[j].M, nkM = a.job[j].nkM;
+  uint32_t* __restrict__ sorted = static_cast<uint32_t*>(a.job[j].list);
+  uint2* __restrict__ fsorted = static_cast<uint2*>(a.job[j].list);
   for (int b = threadIdx.x; b < J; b += blockDim.x) h[b] = off[b] + hw[b];
   __syncthreads();
-  const int64_t lo = blockIdx.x * chunk, hi = lo + chunk < count ? lo + chunk : count;
+  const int64_t lo = w * chunk, hi = lo + chunk < count ? lo + chunk : count;
   for (int64_t q0 = lo + threadIdx.x; q0 < hi; q0 += (int64_t)kSortPerThread * blockDim.x) {
     uint32_t key[kSortPerThread];
 #pragma unroll
@@ -199,7 +253,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_place(const uint32_t* __r
       if (q < hi) {
         const uint32_t c = key[u] & TT_KEY_MASK;
         const uint32_t pos = atomicAdd(&h[c], 1u);
-        if constexpr (FIBRE) {
+        if (fibre) {
           const uint32_t rho = (uint32_t)q / M, mu = (uint32_t)q - rho * M;
           fsorted[pos] = make_uint2((rho * nkM + mu) | (key[u] & TT_KEY_SIGN), c);
         } else {
@@ -249,18 +303,63 @@ KeyArgs key_args(const tt_plan_s* p, const int* modes, int nm) {
   return a;
 }
 
-// keys (count entries) and the J+1 offsets of the sort of `count` tuples
-hipError_t sort_keys(const tt_plan_s* p, const int* modes, int nm, int64_t count, uint32_t* keys, uint32_t* off,
-                     int64_t* nb_out, int64_t* chunk_out) {
+// Job of sort slot `slot`: 0 = the outer tuples of the k = 0 sketch (modes
+// 2..d-1), k >= 1 = the fibres of mode k (modes 1..d-1 except k).
+hipError_t add_job(const tt_plan_s* p, int slot, SortArgs& a, int32_t& blocks) {
+  SortJob& jb = a.job[a.njobs];
+  int64_t count = 1;
+  if (slot == 0) {
+    count = p->O0;
+    jb.lo = 2;
+    jb.ex = -1;
+    jb.fibre = 0;
+    jb.M = jb.nkM = 1;
+    jb.list = p->at<uint32_t>(p->o_sortO);
+    jb.off = p->at<uint32_t>(p->o_cnt);
+  } else {
+    int64_t M = 1, Rk = 1;
+    for (int s = 1; s < slot; ++s) M *= p->n[s];
+    for (int s = slot + 1; s < p->d; ++s) Rk *= p->n[s];
+    count = M * Rk;
+    if (p->n[slot] * count >= ((int64_t)1 << 31)) return hipErrorInvalidValue;   // offsets carry a sign bit
+    jb.lo = 1;
+    jb.ex = slot;
+    jb.fibre = 1;
+    jb.M = (uint32_t)M;
+    jb.nkM = (uint32_t)(p->n[slot] * M);
+    jb.list = p->at<uint2>(p->o_flist) + p->flist_off[slot];
+    jb.off = p->at<uint32_t>(p->o_foff) + (int64_t)slot * (p->J_cap + 1);
+  }
   if (count < 1 || count >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
-  const int64_t nb = tt_sort_chunks(count), chunk = (count + nb - 1) / nb;
-  uint32_t* hist = p->at<uint32_t>(p->o_hist);
+  jb.count = count;
+  jb.nb = (int32_t)tt_sort_chunks(count);
+  jb.chunk = (count + jb.nb - 1) / jb.nb;
+  jb.blk0 = blocks;
+  jb.keys = p->at<uint32_t>(p->o_skeys) + p->skeys_off[slot];
+  jb.hist = p->at<uint32_t>(p->o_hist) + p->hist_off[slot];
+  blocks += jb.nb;
+  a.njobs += 1;
+  return hipSuccess;
+}
+
+hipError_t run_sorts(const tt_plan_s* p, const int* slots, int nslots) {
+  if (nslots <= 0) return hipSuccess;
+  SortArgs a{};
+  a.tab = p->at<uint32_t>(p->o_tab);
+  for (int s = 0; s < p->d; ++s) {
+    a.tab_off[s] = (int32_t)p->tab_off[s];
+    a.n[s] = (int32_t)p->n[s];
+  }
+  a.d = p->d;
+  a.J = (uint32_t)p->J;
+  int32_t blocks = 0;
+  hipError_t e;
+  for (int i = 0; i < nslots; ++i)
+    if ((e = add_job(p, slots[i], a, blocks)) != hipSuccess) return e;
   const size_t lds = sizeof(uint32_t) * p->J;
-  hipLaunchKernelGGL(k_sort_count, dim3((unsigned)nb), dim3(kSortThreads), lds, p->stream, keys, count, chunk,
-                     key_args(p, modes, nm), hist);
-  hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(kSortThreads), lds, p->stream, hist, (int32_t)nb, (int32_t)p->J, off);
-  *nb_out = nb;
-  *chunk_out = chunk;
+  hipLaunchKernelGGL(k_sort_count, dim3((unsigned)blocks), dim3(kSortThreads), lds, p->stream, a);
+  hipLaunchKernelGGL(k_sort_scan, dim3((unsigned)a.njobs), dim3(kSortThreads), lds, p->stream, a);
+  hipLaunchKernelGGL(k_sort_place, dim3((unsigned)blocks), dim3(kSortThreads), lds, p->stream, a);
   return hipGetLastError();
 }
 
@@ -281,42 +380,28 @@ hipError_t launch_build_keys(const tt_plan_s* p, uint32_t* out, int64_t count, i
 }
 
 // Bucket lists of the k = 0 data sketch: the outer mode tuples (modes
-// 2..d-1) grouped by their partial hash.  Uses o_KO as key scratch.
+// 2..d-1) grouped by their partial hash (o_sortO, offsets in o_cnt).
 hipError_t launch_outer_sort(const tt_plan_s* p) {
-  const int64_t O = p->O0;
-  int modes[TT_MAX_ORDER];
-  int nm = 0;
-  for (int s = 2; s < p->d; ++s) modes[nm++] = s;
-  uint32_t* keys = p->at<uint32_t>(p->o_KO);
-  uint32_t* off = p->at<uint32_t>(p->o_cnt);          // J+1
-  int64_t nb = 0, chunk = 0;
-  hipError_t e = sort_keys(p, modes, nm, O, keys, off, &nb, &chunk);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sort_place<false>, dim3((unsigned)nb), dim3(kSortThreads), sizeof(uint32_t) * p->J, p->stream,
-                     keys, O, chunk, p->at<uint32_t>(p->o_hist), off, (int32_t)p->J, p->at<uint32_t>(p->o_sortO),
-                     (uint2*)nullptr, 1u, 1u);
-  return hipGetLastError();
+  const int slot = 0;
+  return run_sorts(p, &slot, 1);
 }
 
-// Sort the fibres of a mode-k column (k >= 1) by their key over modes != 0, k.
-// Offsets of the J buckets go to o_cnt (J+1 entries), the list to o_fsort.
+// Sort the fibres of a mode-k column (k >= 1) by their key over modes != 0, k
+// (list at tt_fibre_list(p, k)).
 hipError_t launch_fibre_sort(const tt_plan_s* p, int k) {
-  int64_t M = 1, Rk = 1;
-  for (int s = 1; s < k; ++s) M *= p->n[s];
-  for (int s = k + 1; s < p->d; ++s) Rk *= p->n[s];
-  const int64_t F = M * Rk;
-  if (p->n[k] * F >= ((int64_t)1 << 31)) return hipErrorInvalidValue;   // fibre offsets carry a sign bit
-  int modes[TT_MAX_ORDER];
-  int nm = 0;
-  for (int s = 1; s < p->d; ++s)
-    if (s != k) modes[nm++] = s;
-  uint32_t* keys = p->at<uint32_t>(p->o_fkeys);
-  uint32_t* off = p->at<uint32_t>(p->o_cnt);
-  int64_t nb = 0, chunk = 0;
-  hipError_t e = sort_keys(p, modes, nm, F, keys, off, &nb, &chunk);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sort_place<true>, dim3((unsigned)nb), dim3(kSortThreads), sizeof(uint32_t) * p->J, p->stream,
-                     keys, F, chunk, p->at<uint32_t>(p->o_hist), off, (int32_t)p->J, (uint32_t*)nullptr,
-                     p->at<uint2>(p->o_fsort), (uint32_t)M, (uint32_t)(p->n[k] * M));
-  return hipGetLastError();
+  if (k < 1 || k >= p->d) return hipErrorInvalidValue;
+  return run_sorts(p, &k, 1);
 }
+
+// Every list one sweep's data sketches read, in one launch set: the outer
+// tuples and the fibres of each key-grouped mode.
+hipError_t launch_sweep_sorts(const tt_plan_s* p) {
+  int slots[TT_MAX_ORDER];
+  int ns = 0;
+  slots[ns++] = 0;
+  for (int k = 1; k < p->d; ++k)
+    if (tt_sketch_use_gs(p, k)) slots[ns++] = k;
+  return run_sorts(p, slots, ns);
+}
+
+const uint2* tt_fibre_list(const tt_plan_s* p, int k) { return p->at<uint2>(p->o_flist) + p->flist_off[k]; }

@@ -55,10 +55,15 @@ struct tt_plan_s {
   void* prof;                  // ProfState* when measurement is enabled, else null
 
   size_t o_tab, o_KI, o_KO, o_cnt, o_hist, o_sortO, o_part, o_chat, o_pre, o_suf, o_SH, o_Y,
-      o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_fkeys, o_fsort, o_pol, o_gsum, o_resU, o_resH,
+      o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_pol, o_gsum, o_resU, o_resH,
       o_tw;
   int64_t tw_J;                // J whose roots of unity the o_tw table holds (0: none)
-  int64_t max_F;               // largest fibre count of one column over k >= 1
+  // key sorts, slot 0 = outer tuples of the k = 0 sketch, slot k >= 1 =
+  // fibres of mode k: keys (o_skeys), per-chunk counts (o_hist), fibre lists
+  // (o_flist, uint2) and their offsets (o_foff, J_cap + 1 per slot)
+  size_t o_skeys, o_flist, o_foff;
+  int64_t skeys_off[TT_MAX_ORDER], flist_off[TT_MAX_ORDER], hist_off[TT_MAX_ORDER];
+  bool lists_ready;            // this sweep's lists are built (the sketches skip their sorts)
 
   template <typename T>
   T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -104,6 +109,8 @@ hipError_t launch_build_keys_modes(const tt_plan_s* p, uint32_t* out, int64_t co
 hipError_t launch_outer_sort(const tt_plan_s* p);     // k = 0 bucket lists (modes 2..d-1)
 hipError_t launch_fibre_sort(const tt_plan_s* p, int k);   // k >= 1 fibre lists by key
 int64_t tt_sort_chunks(int64_t count);                     // workgroups of a key sort of count tuples
+hipError_t launch_sweep_sorts(const tt_plan_s* p);         // every list of one sweep's data sketches
+const uint2* tt_fibre_list(const tt_plan_s* p, int k);     // the k >= 1 fibre list of mode k
 hipError_t launch_sketch_tensor(const tt_plan_s* p, const void* X, int k, void* Y);
 hipError_t launch_core_fft(const tt_plan_s* p, const CoreDesc& cd, int core_lo, int core_hi, int skip);
 hipError_t launch_interface_from_chat(const tt_plan_s* p, const CoreDesc& cd, int k, void* SH);
