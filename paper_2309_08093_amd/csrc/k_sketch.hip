@@ -412,6 +412,38 @@ __global__ __launch_bounds__(256) void k_sketch_mode0(
       const uint32_t nb0 = (uint32_t)__shfl((int)begl, 0, 64), ne0 = (uint32_t)__shfl((int)endl, 0, 64);
       nxt = (nb0 + lane < ne0) ? sorted[nb0 + lane] : 0u;
     }
+    // a batch: fibres t + u G + g of the list chunk starting at e0 of the
+    // segment of i_1
+    auto issue = [&](uint32_t itl, int t, int nb, uint32_t t1, int i1, Vec<XT, V> (&x)[U][NJ], uint32_t (&sg)[U],
+                     bool (&ok)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = t + u * G + g;
+        ok[u] = idx < nb;
+        const uint32_t item = (uint32_t)__shfl((int)itl, idx & 63, 64);
+        sg[u] = (item ^ t1) & TT_KEY_SIGN;
+        const XT* base = X + ((int64_t)(item & TT_KEY_MASK) * n1 + i1) * (int64_t)n0 + i0_lo;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const int p = (v + LPF * j) * V;
+          if (ok[u] && p < i0_cnt) x[u][j] = load_vec<XT, V>(base + p);
+        }
+      }
+    };
+    auto consume = [&](const Vec<XT, V> (&x)[U][NJ], const uint32_t (&sg)[U], const bool (&ok)[U]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const int p = (v + LPF * j) * V;
+          if (ok[u] && p < i0_cnt)
+#pragma unroll
+            for (int e = 0; e < V; ++e) acc[j][e] += signed_f64(x[u][j].e[e], sg[u]);
+        }
+    };
+    Vec<XT, V> xa[U][NJ];
+    uint32_t sga[U];
+    bool oka[U];
     for (int q = 0; q < nq; ++q) {
       const uint32_t t1 = (uint32_t)__shfl((int)t1l, q, 64);
       const uint32_t beg = (uint32_t)__shfl((int)begl, q, 64), end = (uint32_t)__shfl((int)endl, q, 64);
@@ -425,31 +457,8 @@ __global__ __launch_bounds__(256) void k_sketch_mode0(
         const uint32_t itl = e0 == beg ? first : ((e0 + lane < end) ? sorted[e0 + lane] : 0u);
         const int nb = (end - e0) < 64u ? (int)(end - e0) : 64;
         for (int t = 0; t < nb; t += G * U) {
-          Vec<XT, V> x[U][NJ];
-          uint32_t sg[U];
-          bool ok[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int idx = t + u * G + g;
-            ok[u] = idx < nb;
-            const uint32_t item = (uint32_t)__shfl((int)itl, idx & 63, 64);
-            sg[u] = (item ^ t1) & TT_KEY_SIGN;
-            const XT* base = X + ((int64_t)(item & TT_KEY_MASK) * n1 + i1) * (int64_t)n0 + i0_lo;
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-              const int p = (v + LPF * j) * V;
-              if (ok[u] && p < i0_cnt) x[u][j] = load_vec<XT, V>(base + p);
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-              const int p = (v + LPF * j) * V;
-              if (ok[u] && p < i0_cnt)
-#pragma unroll
-                for (int e = 0; e < V; ++e) acc[j][e] += signed_f64(x[u][j].e[e], sg[u]);
-            }
+          issue(itl, t, nb, t1, i1, xa, sga, oka);
+          consume(xa, sga, oka);
         }
       }
     }
