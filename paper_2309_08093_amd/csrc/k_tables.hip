@@ -1,4 +1,6 @@
-// Seeded TensorSketch tables and the derived per-fibre key tables.
+// Seeded TensorSketch tables, the derived per-fibre key tables, and the
+// counting sorts of fibres and outer tuples by key that the data sketches
+// read.
 //
 // Tables (Sec. 2.2, Definitions of CountSketch and TensorSketch; Algorithm 1
 // draws new operators once per outer iteration): every entry of h_s and v_s
