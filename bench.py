@@ -65,9 +65,19 @@ def cpu_baseline(X, cfg, plan, budget_entries):
         sketch.data_sketch(Xs, nsl, k, hs, vs, plan.J)
     dt = time.perf_counter() - t0
     entries = len(n) * Xs.size
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": entries / dt, "unit": "entries/s", "cores": 1, "kind": "oracle",
             "sample": "numpy FP64 data sketch of all %d modes over the slab i_%d < %d (%d entries, %.1f s)"
-                      % (len(n), len(n) - 1, ns, Xs.size, dt)}
+                      % (len(n), len(n) - 1, ns, Xs.size, dt),
+            "host": {"cpu_model": model, "cpus_visible": len(os.sched_getaffinity(0))}}
 
 
 POLICY_WEIGHTS = os.path.join(ROOT, "paper_2309_08093_amd", "jpolicy_weights.npy")
