@@ -320,6 +320,10 @@ struct tt_batch_s {
   std::vector<std::vector<int32_t>> tids;
   std::vector<std::vector<int64_t>> fpre, cpre, spre;
   size_t o_desc = 0, o_part = 0, o_counter = 0;
+  // the outer-tuple sorts of the k = 0 step, one launch set for all problems:
+  // argument sets and (set, chunk) per workgroup
+  size_t o_sargs = 0, o_ssrc = 0;
+  int32_t sort_sets = 0, sort_blocks = 0;
   // batched core updates per step k: descriptors, QR classes, launch bounds
   struct QrClass {
     int32_t rmax, rpt, off, cnt;
@@ -416,14 +420,9 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
   if (nt == 0) return hipSuccess;
   hipError_t e;
   if (k == 0) {
-    for (int32_t j = 0; j < nt; ++j) {
-      tt_plan p = b->plans[b->tids[0][j]];
-      const hipStream_t keep = p->stream;
-      p->stream = b->stream;
-      e = launch_outer_sort(p);
-      p->stream = keep;
-      if (e != hipSuccess) return e;
-    }
+    if ((e = launch_outer_sorts_batched(b->ws + b->o_sargs, b->ws + b->o_ssrc, b->sort_sets, b->sort_blocks, b->Jmax,
+                                        b->stream)) != hipSuccess)
+      return e;
     const dim3 grid((unsigned)(nt * b->Jmax));
     if (b->nj == 2) hipLaunchKernelGGL(k_bsketch_0<2>, grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
     else hipLaunchKernelGGL(k_bsketch_0<4>, grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
@@ -772,6 +771,13 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
     b->o_spre[k] = o;
     o = align256(o + sizeof(int64_t) * b->spre[k].size());
   }
+  b->sort_sets = (int32_t)b->tids[0].size();
+  b->sort_blocks = 0;
+  for (int32_t j : b->tids[0]) b->sort_blocks += (int32_t)tt_sort_chunks(b->plans[j]->O0);
+  b->o_sargs = o;
+  o = align256(o + tt_sort_args_bytes() * (b->sort_sets + 1));
+  b->o_ssrc = o;
+  o = align256(o + sizeof(int2) * (b->sort_blocks + 1));
   b->o_part = o;
   o = align256(o + sizeof(double) * part_max * b->Jmax);
   b->o_counter = o;
@@ -811,6 +817,22 @@ tt_status tt_batch_bind_workspace(tt_batch b, void* dev_ws, size_t bytes) {
     if (!b->qidx[k].empty())
       TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_qidx[k], b->qidx[k].data(), sizeof(int32_t) * b->qidx[k].size(),
                                 hipMemcpyHostToDevice, b->stream));
+  // argument sets of the outer sorts (pointers into the plans' workspaces)
+  std::vector<char> sargs(tt_sort_args_bytes() * (b->sort_sets + 1));
+  std::vector<int2> ssrc;
+  for (int32_t i = 0; i < b->sort_sets; ++i) {
+    int32_t nb = 0;
+    const hipError_t e = tt_sort_args_outer(b->plans[b->tids[0][i]], sargs.data() + tt_sort_args_bytes() * i, &nb);
+    if (e != hipSuccess) return tt_fail(TT_ERR_SHAPE, "problem %d: outer tuples do not fit the sort", b->tids[0][i]);
+    for (int32_t w = 0; w < nb; ++w) ssrc.push_back(make_int2(i, w));
+  }
+  if ((int32_t)ssrc.size() != b->sort_blocks) return tt_fail(TT_ERR_STATE, "outer sort chunks changed");
+  if (b->sort_sets > 0) {
+    TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_sargs, sargs.data(), tt_sort_args_bytes() * b->sort_sets,
+                              hipMemcpyHostToDevice, b->stream));
+    TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_ssrc, ssrc.data(), sizeof(int2) * ssrc.size(), hipMemcpyHostToDevice,
+                              b->stream));
+  }
   TT_HIP_TRY(hipStreamSynchronize(b->stream));
   b->desc_valid = false;
   b->upd_key.clear();

@@ -6,6 +6,8 @@
 // draws new operators once per outer iteration): every entry of h_s and v_s
 // is an independent SplitMix64 output (Steele, Lea, Flood 2014), generated
 // directly on the device, one thread per entry.
+#include <cstring>
+
 #include "tt_internal.h"
 
 namespace {
@@ -136,13 +138,11 @@ __device__ __forceinline__ uint32_t job_key(uint32_t q, const SortArgs& a, int l
   return key;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_count(SortArgs a) {
+__device__ __forceinline__ void sort_count_body(const SortArgs& a, int j, int w) {
   extern __shared__ uint32_t h[];   // J
-  const int j = job_of(a, blockIdx.x);
   const int64_t count = a.job[j].count, chunk = a.job[j].chunk;
   const int lo_mode = a.job[j].lo, ex = a.job[j].ex;
   uint32_t* __restrict__ keys = a.job[j].keys;
-  const int w = blockIdx.x - a.job[j].blk0;
   for (uint32_t b = threadIdx.x; b < a.J; b += blockDim.x) h[b] = 0u;
   __syncthreads();
   const int64_t lo = w * chunk, hi = lo + chunk < count ? lo + chunk : count;
@@ -167,12 +167,25 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(SortArgs a) {
   for (uint32_t b = threadIdx.x; b < a.J; b += blockDim.x) out[b] = h[b];
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_scan(SortArgs a) {
+__global__ __launch_bounds__(kSortThreads) void k_sort_count(SortArgs a) {
+  const int j = job_of(a, blockIdx.x);
+  sort_count_body(a, j, blockIdx.x - a.job[j].blk0);
+}
+
+// Batched: the argument sets of several plans in device memory, src[b] =
+// (argument set, chunk) of workgroup b (job 0 of each set).
+__global__ __launch_bounds__(kSortThreads) void kb_sort_count(const SortArgs* __restrict__ A,
+                                                              const int2* __restrict__ src) {
+  const int2 t = src[blockIdx.x];
+  sort_count_body(A[t.x], 0, t.y);
+}
+
+__device__ __forceinline__ void sort_scan_body(const SortArgs& a, int j) {
   extern __shared__ uint32_t tot[];   // J
   __shared__ uint32_t wsum[kSortThreads / 64];
-  const int J = (int)a.J, nb = a.job[blockIdx.x].nb;
-  uint32_t* __restrict__ hist = a.job[blockIdx.x].hist;
-  uint32_t* __restrict__ off = a.job[blockIdx.x].off;
+  const int J = (int)a.J, nb = a.job[j].nb;
+  uint32_t* __restrict__ hist = a.job[j].hist;
+  uint32_t* __restrict__ off = a.job[j].off;
   const int t = threadIdx.x, T = blockDim.x, lane = t & 63, w = t >> 6, NW = T >> 6;
   constexpr int CB = 16;   // chunk counts loaded together
   for (int b = t; b < J; b += T) {
@@ -222,16 +235,20 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scan(SortArgs a) {
   }
 }
 
+__global__ __launch_bounds__(kSortThreads) void k_sort_scan(SortArgs a) { sort_scan_body(a, blockIdx.x); }
+
+__global__ __launch_bounds__(kSortThreads) void kb_sort_scan(const SortArgs* __restrict__ A) {
+  sort_scan_body(A[blockIdx.x], 0);
+}
+
 // Fibre lists (the k >= 1 sketch): tuple t = mu + M rho of a column (modes
 // 1..k-1 give mu, modes k+1..d-1 give rho) stored as {column-independent
 // fibre offset rho n_k M + mu with the key's sign bit; bucket}.  Outer lists
 // (the k = 0 sketch): {t with the key's sign bit}.
-__global__ __launch_bounds__(kSortThreads) void k_sort_place(SortArgs a) {
+__device__ __forceinline__ void sort_place_body(const SortArgs& a, int j, int w) {
   extern __shared__ uint32_t h[];   // J
-  const int j = job_of(a, blockIdx.x);
   const int J = (int)a.J;
   const int64_t count = a.job[j].count, chunk = a.job[j].chunk;
-  const int w = blockIdx.x - a.job[j].blk0;
   const uint32_t* __restrict__ keys = a.job[j].keys;
   const uint32_t* hw = a.job[j].hist + (int64_t)w * J;
   const uint32_t* off = a.job[j].off;
@@ -264,6 +281,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_place(SortArgs a) {
       }
     }
   }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_place(SortArgs a) {
+  const int j = job_of(a, blockIdx.x);
+  sort_place_body(a, j, blockIdx.x - a.job[j].blk0);
+}
+
+__global__ __launch_bounds__(kSortThreads) void kb_sort_place(const SortArgs* __restrict__ A,
+                                                              const int2* __restrict__ src) {
+  const int2 t = src[blockIdx.x];
+  sort_place_body(A[t.x], 0, t.y);
 }
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -393,6 +421,41 @@ hipError_t launch_outer_sort(const tt_plan_s* p) {
 hipError_t launch_fibre_sort(const tt_plan_s* p, int k) {
   if (k < 1 || k >= p->d) return hipErrorInvalidValue;
   return run_sorts(p, &k, 1);
+}
+
+size_t tt_sort_args_bytes() { return sizeof(SortArgs); }
+
+// The argument set of plan p's outer sort (one job, its chunks first), in
+// host memory, for the batched launches; *nb = its chunks.
+hipError_t tt_sort_args_outer(const tt_plan_s* p, void* out, int32_t* nb) {
+  SortArgs a{};
+  a.tab = p->at<uint32_t>(p->o_tab);
+  for (int s = 0; s < p->d; ++s) {
+    a.tab_off[s] = (int32_t)p->tab_off[s];
+    a.n[s] = (int32_t)p->n[s];
+  }
+  a.d = p->d;
+  a.J = (uint32_t)p->J;
+  int32_t blocks = 0;
+  const hipError_t e = add_job(p, 0, a, blocks);
+  if (e != hipSuccess) return e;
+  std::memcpy(out, &a, sizeof a);
+  *nb = blocks;
+  return hipSuccess;
+}
+
+// The outer sorts of several plans in one launch set: args = nsets argument
+// sets (device memory), src = (set, chunk) per workgroup, nblocks workgroups.
+hipError_t launch_outer_sorts_batched(const void* args, const void* src, int32_t nsets, int32_t nblocks, int32_t J,
+                                      hipStream_t st) {
+  if (nsets <= 0) return hipSuccess;
+  const SortArgs* A = static_cast<const SortArgs*>(args);
+  const int2* S = static_cast<const int2*>(src);
+  const size_t lds = sizeof(uint32_t) * J;
+  hipLaunchKernelGGL(kb_sort_count, dim3((unsigned)nblocks), dim3(kSortThreads), lds, st, A, S);
+  hipLaunchKernelGGL(kb_sort_scan, dim3((unsigned)nsets), dim3(kSortThreads), lds, st, A);
+  hipLaunchKernelGGL(kb_sort_place, dim3((unsigned)nblocks), dim3(kSortThreads), lds, st, A, S);
+  return hipGetLastError();
 }
 
 // Every list one sweep's data sketches read, in one launch set: the outer

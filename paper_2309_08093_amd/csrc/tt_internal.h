@@ -111,6 +111,10 @@ hipError_t launch_fibre_sort(const tt_plan_s* p, int k);   // k >= 1 fibre lists
 int64_t tt_sort_chunks(int64_t count);                     // workgroups of a key sort of count tuples
 hipError_t launch_sweep_sorts(const tt_plan_s* p);         // every list of one sweep's data sketches
 const uint2* tt_fibre_list(const tt_plan_s* p, int k);     // the k >= 1 fibre list of mode k
+size_t tt_sort_args_bytes();                               // one argument set of the key sorts
+hipError_t tt_sort_args_outer(const tt_plan_s* p, void* out, int32_t* nb);   // plan p's outer sort, host memory
+hipError_t launch_outer_sorts_batched(const void* args, const void* src, int32_t nsets, int32_t nblocks, int32_t J,
+                                      hipStream_t st);
 hipError_t launch_sketch_tensor(const tt_plan_s* p, const void* X, int k, void* Y);
 hipError_t launch_core_fft(const tt_plan_s* p, const CoreDesc& cd, int core_lo, int core_hi, int skip);
 hipError_t launch_interface_from_chat(const tt_plan_s* p, const CoreDesc& cd, int k, void* SH);
