@@ -144,13 +144,15 @@ __global__ __launch_bounds__(256) void k_res_slab(const XT* __restrict__ X, Core
     }
     const bool ok = p0 < S;
     const int64_t oa = run * orun, oe = (oa + orun) < O ? oa + orun : O;
-    // four slabs in flight per wave
+    // UO slabs per batch; the loads of the next batch are issued before the
+    // current one is used, so a wave always has loads in flight
     constexpr int UO = 4;
-    for (int64_t ob = oa; ob < oe; ob += UO) {
-      Vec<XT, V> x[UO];
+    auto issue = [&](Vec<XT, V> (&x)[UO], int64_t ob) {
 #pragma unroll
       for (int q = 0; q < UO; ++q)
         if (ok && ob + q < oe) x[q] = load_vec<XT, V>(X + (ob + q) * S + p0);
+    };
+    auto consume = [&](const Vec<XT, V> (&x)[UO], int64_t ob) {
 #pragma unroll
       for (int q = 0; q < UO; ++q) {
         if (ob + q >= oe) break;
@@ -176,6 +178,15 @@ __global__ __launch_bounds__(256) void k_res_slab(const XT* __restrict__ X, Core
         sd += (double)sdf;
         sx += (double)sxf;
       }
+    };
+    Vec<XT, V> xa[UO], xb[UO];
+    if (oa < oe) issue(xa, oa);
+    for (int64_t ob = oa; ob < oe; ob += 2 * UO) {
+      if (ob + UO < oe) issue(xb, ob + UO);
+      consume(xa, ob);
+      if (ob + UO >= oe) break;
+      if (ob + 2 * UO < oe) issue(xa, ob + 2 * UO);
+      consume(xb, ob + UO);
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
@@ -228,7 +239,7 @@ hipError_t run(const tt_plan_s* p, const XT* X, const CoreDesc& cd, const WT* U,
                      part, p->O0, (int32_t)orun);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, p->stream, part, nw, part + 2 * nw);
+  hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, p->stream, part, nw, part + 2 * p->res_waves);
   return hipGetLastError();
 }
 
@@ -237,6 +248,7 @@ hipError_t dispatch_r(const tt_plan_s* p, const XT* X, const CoreDesc& cd, const
   const int64_t R2 = p->r[2];
   if (R2 <= 4) return run<XT, WT, V, 4>(p, X, cd, U, H);
   if (R2 <= 8) return run<XT, WT, V, 8>(p, X, cd, U, H);
+  if (R2 <= 12) return run<XT, WT, V, 12>(p, X, cd, U, H);
   return run<XT, WT, V, 16>(p, X, cd, U, H);
 }
 
@@ -255,7 +267,9 @@ hipError_t dispatch(const tt_plan_s* p, const void* Xv, const CoreDesc& cd) {
     hipLaunchKernelGGL(k_res_h<WT>, dim3((unsigned)((S + 255) / 256)), dim3(256), 0, p->stream, cd, H);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  constexpr int VV = 16 / (int)sizeof(XT);
+  // 16-byte loads, 8-byte for BF16 (eight BF16 positions per lane would
+  // hold 64 H values in registers and cost two waves of occupancy)
+  constexpr int VV = sizeof(XT) == 2 ? 4 : 16 / (int)sizeof(XT);
   const bool vec = (S % VV) == 0 && ((uintptr_t)Xv % 16) == 0;
   return vec ? dispatch_r<XT, WT, VV>(p, X, cd, U, H) : dispatch_r<XT, WT, 1>(p, X, cd, U, H);
 }
