@@ -120,3 +120,40 @@ def test_full_size_sweeps_reach_the_noise_floor(tts, name):
     assert 0.95 * floor <= res[-1] <= 1.25 * floor, (floor, res)
     del X, plan, dc
     torch.cuda.empty_cache()
+
+
+def test_full_size_batched_form_matches_single_plans(tts):
+    # The batched workload at full size (256 uneven TTs, 36.6 GB), autotuned
+    # and graph-captured as bench.py runs it: after three sweeps, sampled
+    # problems (the largest, the smallest and six more) agree with single
+    # plans run on the same tensors, tables and starting cores.  The k = 0
+    # kernels of the two forms add bucket contributions in different orders
+    # in FP32, which three sweeps carry into the cores, so the tolerance is
+    # that of the small batched test: 1e-4 relative on the residual.
+    say("full-size batched form")
+    shapes = synth.batched_shapes(256, SEED)
+    probs = [dict(n=n, ranks=R, J=1024, lam=1e-3, seed=SEED + 17 * i) for i, (n, R) in enumerate(shapes)]
+    Xs = [synth.tt_tensor_device(p["n"], p["ranks"], 1e-3, SEED + 31 * i, dtype="f32", device="cuda")[0]
+          for i, p in enumerate(probs)]
+    init = [synth.random_cores(p["n"], p["ranks"], SEED + 7 * i + 1) for i, p in enumerate(probs)]
+    batch = tts.Batch(probs, device="cuda")
+    batch.autotune(Xs, reps=1)
+    batch.set_graph(True)
+    cores = [[tts.core_to_device(c, "cuda") for c in init[i]] for i in range(len(probs))]
+    for _ in range(2):
+        batch.sweep(Xs, cores)
+    res_b = batch.sweep(Xs, cores, residuals=True)
+    sizes = [int(np.prod(p["n"])) for p in probs]
+    rng = synth.rng(5)
+    sample = {int(np.argmax(sizes)), int(np.argmin(sizes))} | set(int(i) for i in rng.choice(len(probs), 6, replace=False))
+    for i in sorted(sample):
+        p = probs[i]
+        say("problem", i, p["n"], p["ranks"])
+        plan = tts.Plan(p["n"], p["ranks"], p["J"], p["lam"], seed=p["seed"], serial=True, device="cuda")
+        cs = [tts.core_to_device(c, "cuda") for c in init[i]]
+        for _ in range(2):
+            plan.als_sweep(Xs[i], cs)
+        r = plan.als_sweep(Xs[i], cs, residual=True)
+        assert abs(res_b[i] - r) <= 1e-4 * r + 1e-9, (i, res_b[i], r)
+    del Xs, batch, cores
+    torch.cuda.empty_cache()
