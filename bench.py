@@ -37,6 +37,8 @@ CONFIGS = {
                   desc="dense 64^5 FP32 tensor from a random TT with ranks 8 plus noise 1e-3; J=3000, lambda=1e-3"),
 }
 XBYTES = {"f64": 8, "f32": 4, "bf16": 2}
+# workload names of the committed profile summaries
+PROFILE_TAG = {"c1": "16x4_f64", "c2": "200x4_f32", "c3": "64x5_bf16", "c3f32": "64x5_f32", "c4": "256_uneven_tt_f32"}
 # batched workload: 256 independent problems, order U{3,4,5}, n_i U[20,60],
 # inner ranks U[2,8] (clipped to feasibility), FP32, noise 1e-3, J=1024, lambda=1e-3
 BATCH = dict(count=256, J=1024, lam=1e-3, noise=1e-3)
@@ -308,7 +310,8 @@ def stored_traffic(kernel, config):
     """HBM bytes per launch of `kernel` on `config` from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE scaled by a device copy of known size),
     or None if there is none for the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s_%s.txt" % (kernel, config))
+    tag = PROFILE_TAG.get(config, config)
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s_%s.txt" % (kernel, tag))
     try:
         lines = open(path).read().splitlines()
     except OSError:
