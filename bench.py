@@ -367,7 +367,7 @@ def main():
     args = ap.parse_args()
     args.serial = not args.overlap
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the data sketch would shard by slabs of the last mode plus one all-reduce of J x n_k "
               "per core update); run with --gpus 1", file=sys.stderr)
         sys.exit(2)

@@ -6,8 +6,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The policy maps F features of one core update to two outputs (log J, log
 lambda).  The paper fixes J only through the bound of Corollary 3 (Sec. 4)
-and calls that bound conservative (Sec. 5); the network is this build's
-addition, so the oracle follows the textbook definitions, not the paper.
+and calls that bound conservative (Sec. 5); the network is an addition to
+the method, so the oracle follows the textbook definitions, not the paper.
 
 Parameter vector layout (shared with the C ABI, float32 there):
     for each layer l = 1..L with fan-in a and fan-out b:
