@@ -432,9 +432,12 @@ hipError_t prox_t(const tt_plan_s* p, int k, const double* G_old, double* G_new)
   if ((e = tt_allow_lds(k_chol_blk, lds1)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_chol_blk, dim3(1), dim3(256), lds1, p->stream, gsum, s, ldg, p->lambda, Lg, status);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // right-hand-side block: as wide as fits next to L in 150 KB of LDS, at
-  // most 64 columns (one thread per column solves the diagonal blocks)
-  int CB = 64;
+  // right-hand-side block of 8 columns (a 16-wide MFMA tile half used): each
+  // workgroup's time is the latency of its 2 ceil(s / 16) block steps, not
+  // their MFMA work, so narrow blocks and more workgroups finish first
+  // (s = 100, n = 200: 56 / 38 / 28 / 27 us at 64 / 32 / 16 / 8 columns);
+  // narrower still if L and the block do not fit in 150 KB of LDS
+  int CB = 8;
   while (CB > 1 && (np + (size_t)s * CB) * sizeof(double) > 150 * 1024) CB >>= 1;
   const size_t lds2 = (np + (size_t)s * CB) * sizeof(double);
   if ((e = tt_allow_lds(k_prox_trsm_blk, lds2)) != hipSuccess) return e;
