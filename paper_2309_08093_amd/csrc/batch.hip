@@ -4,8 +4,10 @@
 // Each problem keeps its own plan (tables, cores, interface and solve
 // buffers) in a slice of one batch workspace.  Per step k of a sweep:
 //  * the interface sketches (and the new transform of core k - 1) of all
-//    problems with order > k are enqueued per problem on 8 streams (short,
-//    latency-bound kernels);
+//    problems with order > k are one launch per kernel (core FFTs, chain
+//    products, face-splitting inverse FFTs), one workgroup per (problem,
+//    column), each problem with its own J and FFT plan from a per-step
+//    descriptor;
 //  * the core updates of all those problems are one launch per kernel: the
 //    Gram contraction, the summed partials, the Cholesky factorisation, the
 //    substitution, QR (one launch per register shape; blocks too tall for
@@ -332,6 +334,12 @@ struct tt_batch_s {
   std::vector<std::vector<QrClass>> qcls;
   std::vector<std::vector<int32_t>> qidx, qfall;   // QR class members (index into upd[k]); per-problem QRs
   size_t o_upd[TT_MAX_ORDER] = {}, o_qidx[TT_MAX_ORDER] = {};
+  // batched interface of each step: descriptors, largest core-transform and
+  // output column counts, waves of a chain workgroup
+  std::vector<std::vector<BIface>> bif;
+  size_t o_bif[TT_MAX_ORDER] = {};
+  int32_t if_cols[TT_MAX_ORDER] = {}, if_s[TT_MAX_ORDER] = {};
+  int32_t if_cw = 1;
   int32_t g_gx[TT_MAX_ORDER] = {}, g_count[TT_MAX_ORDER] = {}, g_cbb[TT_MAX_ORDER] = {}, g_cols[TT_MAX_ORDER] = {};
   size_t g_lchol[TT_MAX_ORDER] = {}, g_ltrsm[TT_MAX_ORDER] = {};
   std::vector<const void*> upd_key;
@@ -346,7 +354,7 @@ struct tt_batch_s {
   bool use_graph = false;
   hipStream_t cap = nullptr;   // private stream the sweep is captured on
   hipStream_t side = nullptr;  // batched data sketches of a sweep
-  hipStream_t lane[8] = {};    // per-problem core updates
+  hipStream_t lane[8] = {};    // per-problem orthogonalisation and tables
   hipEvent_t ev_fork = nullptr, ev_done = nullptr, ev_lane[8] = {}, ev_step[TT_MAX_ORDER] = {};
   hipGraphExec_t exec = nullptr;
   std::vector<const void*> cap_ptrs;
@@ -494,6 +502,30 @@ tt_status upload_upd(tt_batch b, void* const* const* cores) {
     if (!b->upd[k].empty())
       TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_upd[k], b->upd[k].data(), sizeof(BUpd) * b->upd[k].size(),
                                 hipMemcpyHostToDevice, b->stream));
+    // the interface descriptors of step k
+    b->bif[k].resize(b->tids[k].size());
+    for (size_t j = 0; j < b->tids[k].size(); ++j) {
+      const int i = b->tids[k][j];
+      tt_plan p = b->plans[i];
+      BIface& f = b->bif[k][j];
+      f.cd = tt_make_desc(p, cores[i]);
+      f.tab = p->at<uint32_t>(p->o_tab);
+      f.chat = p->ws + p->o_chat;
+      f.pre = p->ws + p->o_pre;
+      f.suf = p->ws + p->o_suf;
+      f.SH = p->ws + p->o_SH;
+      f.tw = p->ws + p->o_tw;
+      f.fft_code = 0;
+      for (int r = 0; r < p->fft_nrad; ++r) f.fft_code |= (uint64_t)p->fft_radix[r] << (4 * r);
+      f.fft_nrad = p->fft_nrad;
+      f.J = (int32_t)p->J;
+      f.k = k;
+      f.cols = k >= 1 ? (int32_t)(p->r[k - 1] * p->r[k]) : 0;
+      f.s = (int32_t)(p->r[k] * p->r[k + 1]);
+    }
+    if (!b->bif[k].empty())
+      TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_bif[k], b->bif[k].data(), sizeof(BIface) * b->bif[k].size(),
+                                hipMemcpyHostToDevice, b->stream));
   }
   TT_HIP_TRY(hipStreamSynchronize(b->stream));
   b->upd_key = key;
@@ -502,9 +534,11 @@ tt_status upload_upd(tt_batch b, void* const* const* cores) {
 
 // Enqueue one sweep of every problem.  The batched data sketches of all steps
 // need only X and the sweep's tables, so they go first, on the side stream,
-// one launch per step.  Per step k: the interface sketches (and the new
-// transform of core k - 1) run per problem on lanes (problem i on lane
-// i mod kLanes); then, on the batch stream, one launch each covers the Gram,
+// one launch per step.  The right-to-left orthogonalisation of each problem
+// runs per problem on lanes (problem i on lane i mod kLanes), and the batch
+// stream joins the lanes before step 0.  Per step k, on the batch stream: one launch per
+// kernel computes the interface sketches (and the new transform of core
+// k - 1) of every problem of order > k; then one launch each covers the Gram,
 // the solve (summed partials, Cholesky, substitution) and the QR + absorb of
 // every problem of order > k (QR grouped by register shape; QRs too tall for
 // registers run per problem).  The next sweep's tables are drawn once every
@@ -549,24 +583,24 @@ tt_status enqueue_sweep(tt_batch b, void* const* const* cores) {
       return st;
     }
   }
+  for (int l = 0; l < kLanes; ++l) {
+    TT_HIP_TRY(hipEventRecord(b->ev_lane[l], b->lane[l]));
+    TT_HIP_TRY(hipStreamWaitEvent(main, b->ev_lane[l], 0));
+  }
   for (int k = 0; k < b->max_d; ++k) {
-    for (int32_t i : b->tids[k]) {
-      tt_plan p = b->plans[i];
-      p->stream = lane_of(i);
-      hipError_t e = hipSuccess;
-      if (k >= 1) e = launch_core_fft(p, cd[i], k - 1, k - 1, -1);   // core k - 1 changed in step k - 1
-      if (e != hipSuccess || (st = tt_sweep_interface(p, cd[i], k))) {
+    const int32_t nt = (int32_t)b->tids[k].size();
+    // the transform of core k - 1 (changed in step k - 1) and the interface
+    // sketches of step k, one launch each for all problems of order > k
+    {
+      const hipError_t e = launch_interface_batched(b->ws + b->o_bif[k], nt, k, b->Jmax, b->if_cols[k], b->if_s[k],
+                                                    b->if_cw, main);
+      if (e != hipSuccess) {
         restore();
-        return e != hipSuccess ? tt_fail(TT_ERR_HIP, "core transform launch failed: %s", hipGetErrorString(e)) : st;
+        return tt_fail(TT_ERR_HIP, "interface launch failed: %s", hipGetErrorString(e));
       }
-    }
-    for (int l = 0; l < kLanes; ++l) {
-      TT_HIP_TRY(hipEventRecord(b->ev_lane[l], b->lane[l]));
-      TT_HIP_TRY(hipStreamWaitEvent(main, b->ev_lane[l], 0));
     }
     TT_HIP_TRY(hipStreamWaitEvent(main, b->ev_step[k], 0));
     const BUpd* du = reinterpret_cast<const BUpd*>(b->ws + b->o_upd[k]);
-    const int32_t nt = (int32_t)b->tids[k].size();
     TT_HIP_TRY(launch_gram_batched(du, nt, b->g_gx[k], main));
     TT_HIP_TRY(launch_solve_batched(du, nt, 0, b->g_count[k], b->g_cbb[k], b->g_lchol[k], b->g_ltrsm[k], main));
     const int32_t* dq = reinterpret_cast<const int32_t*>(b->ws + b->o_qidx[k]);
@@ -583,10 +617,11 @@ tt_status enqueue_sweep(tt_batch b, void* const* const* cores) {
     // R of the batched QRs into core k + 1 (the per-problem QRs above absorbed
     // theirs; their descriptors carry no next core)
     TT_HIP_TRY(launch_absorb_left_batched(du, nt, b->g_cols[k], main));
-    TT_HIP_TRY(hipEventRecord(b->ev_main, main));
-    for (int l = 0; l < kLanes; ++l) TT_HIP_TRY(hipStreamWaitEvent(b->lane[l], b->ev_main, 0));
   }
-  // next sweep's tables, once the sketches are done
+  // next sweep's tables, once the sketches (side stream) and the interface
+  // sketches (batch stream) have read the current ones
+  TT_HIP_TRY(hipEventRecord(b->ev_main, main));
+  for (int l = 0; l < kLanes; ++l) TT_HIP_TRY(hipStreamWaitEvent(b->lane[l], b->ev_main, 0));
   for (int i = 0; i < b->count; ++i) {
     tt_plan p = b->plans[i];
     p->stream = lane_of(i);
@@ -694,6 +729,7 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
   o = align256(o + sizeof(BTensor) * count);
   // batched core updates: shapes known now, pointers filled per call
   b->upd.resize(b->max_d);
+  b->bif.resize(b->max_d);
   b->qcls.resize(b->max_d);
   b->qidx.resize(b->max_d);
   b->qfall.resize(b->max_d);
@@ -758,6 +794,16 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
     }
     b->o_upd[k] = o;
     o = align256(o + sizeof(BUpd) * (nt + 1));
+    b->o_bif[k] = o;
+    o = align256(o + sizeof(BIface) * (nt + 1));
+    for (int j = 0; j < nt; ++j) {
+      tt_plan p = b->plans[b->tids[k][j]];
+      const int32_t cols = k >= 1 ? (int32_t)(p->r[k - 1] * p->r[k]) : 0;
+      b->if_cols[k] = std::max(b->if_cols[k], cols);
+      b->if_s[k] = std::max(b->if_s[k], (int32_t)(p->r[k] * p->r[k + 1]));
+      for (int i = 0; i <= p->d; ++i)
+        while (b->if_cw < p->r[i]) b->if_cw <<= 1;
+    }
     b->o_qidx[k] = o;
     o = align256(o + sizeof(int32_t) * (b->qidx[k].size() + 1));
   }

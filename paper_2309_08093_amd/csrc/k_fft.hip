@@ -168,14 +168,13 @@ constexpr int kFftThreads = 512;
 // One workgroup per (core i, column a + R_i c): CountSketch of the column
 // over mode 2 into LDS, forward FFT, store to chat.
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_core_fft(CoreDesc cd, const uint32_t* __restrict__ tab, cplx<T>* chat,
-                                                          int32_t J, FftPlan fp, const cplx<T>* __restrict__ tw,
-                                                          int32_t lo, int32_t hi, int32_t skip, int64_t col_base) {
+__device__ __forceinline__ void core_fft_body(const CoreDesc& cd, const uint32_t* __restrict__ tab, cplx<T>* chat,
+                                              int32_t J, FftPlan fp, const cplx<T>* __restrict__ tw, int32_t lo,
+                                              int32_t hi, int32_t skip, int64_t q) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* a = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* b = a + J;
   // locate core i and its column q
-  int64_t q = blockIdx.x + col_base;
   int i = lo;
   for (; i <= hi; ++i) {
     if (i == skip) continue;
@@ -206,15 +205,22 @@ __global__ __launch_bounds__(kFftThreads) void k_core_fft(CoreDesc cd, const uin
   for (int s = threadIdx.x; s < J; s += blockDim.x) out[s] = res[s];
 }
 
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_core_fft(CoreDesc cd, const uint32_t* __restrict__ tab, cplx<T>* chat,
+                                                          int32_t J, FftPlan fp, const cplx<T>* __restrict__ tw,
+                                                          int32_t lo, int32_t hi, int32_t skip, int64_t col_base) {
+  core_fft_body<T>(cd, tab, chat, J, fp, tw, lo, hi, skip, blockIdx.x + col_base);
+}
+
 // Per frequency s: prefix P_<(s) (1 x R_k) and suffix P_>(s) (R_{k+1} x 1),
 // the slice-wise products.  Workgroup: 64 consecutive frequencies (lane sl)
 // x up to 16 output indices (wave c); after each core the running vector
 // goes through LDS.  Entry c of the new vector sums over the old one in index
 // order, as a plain matrix-vector product would.
 template <typename T>
-__global__ __launch_bounds__(64 * TT_MAX_RANK) void k_chain(CoreDesc cd, const cplx<T>* __restrict__ chat,
-                                                           cplx<T>* __restrict__ pre, cplx<T>* __restrict__ suf,
-                                                           int32_t J, int32_t k) {
+__device__ __forceinline__ void chain_body(const CoreDesc& cd, const cplx<T>* __restrict__ chat,
+                                           cplx<T>* __restrict__ pre, cplx<T>* __restrict__ suf, int32_t J,
+                                           int32_t k) {
   __shared__ cplx<T> vb[2][TT_MAX_RANK][64];
   const int sl = threadIdx.x & 63, c = threadIdx.x >> 6;
   const int s = blockIdx.x * 64 + sl;
@@ -250,17 +256,22 @@ __global__ __launch_bounds__(64 * TT_MAX_RANK) void k_chain(CoreDesc cd, const c
   if (ok && c < cd.r1[k]) suf[(int64_t)c * J + s] = v;
 }
 
+template <typename T>
+__global__ __launch_bounds__(64 * TT_MAX_RANK) void k_chain(CoreDesc cd, const cplx<T>* __restrict__ chat,
+                                                           cplx<T>* __restrict__ pre, cplx<T>* __restrict__ suf,
+                                                           int32_t J, int32_t k) {
+  chain_body<T>(cd, chat, pre, suf, J, k);
+}
+
 // One workgroup per output column q = a + R_k b: face-split product, inverse
 // FFT, real part / J.
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_facesplit_ifft(const cplx<T>* __restrict__ pre,
-                                                                const cplx<T>* __restrict__ suf, T* __restrict__ SH,
-                                                                int32_t J, int32_t rk, FftPlan fp,
-                                                                const cplx<T>* __restrict__ tw) {
+__device__ __forceinline__ void facesplit_body(const cplx<T>* __restrict__ pre, const cplx<T>* __restrict__ suf,
+                                               T* __restrict__ SH, int32_t J, int32_t rk, FftPlan fp,
+                                               const cplx<T>* __restrict__ tw, int q) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* a = reinterpret_cast<cplx<T>*>(smem_raw);
   cplx<T>* b = a + J;
-  const int q = blockIdx.x;
   const int al = q % rk, be = q / rk;
   const cplx<T>* P = pre + (int64_t)al * J;
   const cplx<T>* Q = suf + (int64_t)be * J;
@@ -270,6 +281,39 @@ __global__ __launch_bounds__(kFftThreads) void k_facesplit_ifft(const cplx<T>* _
   const T inv = (T)1 / (T)J;
   T* out = SH + (int64_t)q * J;
   for (int s = threadIdx.x; s < J; s += blockDim.x) out[s] = res[s].x * inv;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_facesplit_ifft(const cplx<T>* __restrict__ pre,
+                                                                const cplx<T>* __restrict__ suf, T* __restrict__ SH,
+                                                                int32_t J, int32_t rk, FftPlan fp,
+                                                                const cplx<T>* __restrict__ tw) {
+  facesplit_body<T>(pre, suf, SH, J, rk, fp, tw, blockIdx.x);
+}
+
+// Batched (FP32): descriptor blockIdx.y; workgroups past a problem's count
+// return at once.
+__global__ __launch_bounds__(kFftThreads) void kb_core_fft(const BIface* __restrict__ d) {
+  const BIface& u = d[blockIdx.y];
+  if ((int32_t)blockIdx.x >= u.cols) return;
+  core_fft_body<float>(u.cd, u.tab, static_cast<cplx<float>*>(u.chat), u.J, FftPlan{u.fft_code, u.fft_nrad},
+                       static_cast<const cplx<float>*>(u.tw), u.k - 1, u.k - 1, -1, blockIdx.x);
+}
+
+// grid.x covers the largest J; frequencies past a problem's J only take part
+// in the workgroup's barriers
+__global__ __launch_bounds__(64 * TT_MAX_RANK) void kb_chain(const BIface* __restrict__ d) {
+  const BIface& u = d[blockIdx.y];
+  chain_body<float>(u.cd, static_cast<const cplx<float>*>(u.chat), static_cast<cplx<float>*>(u.pre),
+                    static_cast<cplx<float>*>(u.suf), u.J, u.k);
+}
+
+__global__ __launch_bounds__(kFftThreads) void kb_facesplit_ifft(const BIface* __restrict__ d) {
+  const BIface& u = d[blockIdx.y];
+  if ((int32_t)blockIdx.x >= u.s) return;
+  facesplit_body<float>(static_cast<const cplx<float>*>(u.pre), static_cast<const cplx<float>*>(u.suf),
+                        static_cast<float*>(u.SH), u.J, u.cd.r0[u.k], FftPlan{u.fft_code, u.fft_nrad},
+                        static_cast<const cplx<float>*>(u.tw), blockIdx.x);
 }
 
 FftPlan make_fft_plan(const tt_plan_s* p) {
@@ -338,6 +382,28 @@ hipError_t launch_core_fft(const tt_plan_s* p, const CoreDesc& cd, int lo, int h
 
 hipError_t launch_interface_from_chat(const tt_plan_s* p, const CoreDesc& cd, int k, void* SH) {
   return p->wdt == TT_F64 ? interface_t<double>(p, cd, k, SH) : interface_t<float>(p, cd, k, SH);
+}
+
+// Batched interface of step k for nprob problems (FP32), each with its own J
+// and FFT radices: for k >= 1 the transform of core k - 1 (max_cols
+// workgroups per problem), then the chains and the face-split inverse FFTs
+// (max_s per problem).  Jmax: the largest J; cw: waves of a chain workgroup.
+hipError_t launch_interface_batched(const void* desc, int32_t nprob, int32_t k, int32_t Jmax, int32_t max_cols,
+                                    int32_t max_s, int32_t cw, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  const BIface* d = static_cast<const BIface*>(desc);
+  const size_t lds = 2 * (size_t)Jmax * sizeof(cplx<float>);
+  hipError_t e;
+  if (k >= 1 && max_cols > 0) {
+    if ((e = tt_allow_lds(kb_core_fft, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(kb_core_fft, dim3((unsigned)max_cols, (unsigned)nprob), dim3(kFftThreads), lds, st, d);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kb_chain, dim3((unsigned)((Jmax + 63) / 64), (unsigned)nprob), dim3(64 * cw), 0, st, d);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = tt_allow_lds(kb_facesplit_ifft, lds)) != hipSuccess) return e;
+  hipLaunchKernelGGL(kb_facesplit_ifft, dim3((unsigned)max_s, (unsigned)nprob), dim3(kFftThreads), lds, st, d);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_twiddles(const tt_plan_s* p) {

@@ -101,6 +101,25 @@ struct CoreDesc {
   int32_t d;
 };
 
+// One problem's interface step in the batched form (FP32): core descriptor
+// and plan buffers; k = the step (the transform of core k - 1 precedes it
+// for k >= 1, over cols columns), s = R_k R_{k+1} output columns.
+struct BIface {
+  CoreDesc cd;
+  const uint32_t* tab;
+  void* chat;
+  void* pre;
+  void* suf;
+  void* SH;
+  const void* tw;
+  uint64_t fft_code;   // the problem's FFT radices, 4 bits each
+  int32_t fft_nrad, J;
+  int32_t k, cols, s;
+};
+// Jmax: the largest J of the batch (LDS and chain grid)
+hipError_t launch_interface_batched(const void* desc, int32_t nprob, int32_t k, int32_t Jmax, int32_t max_cols,
+                                    int32_t max_s, int32_t cw, hipStream_t st);
+
 // Launchers (each enqueues on p->stream; returns hipSuccess or the launch error)
 hipError_t launch_gen_tables(const tt_plan_s* p, int64_t sweep);
 hipError_t launch_fill_twiddles(const tt_plan_s* p);   // o_tw <- exp(-2 pi i e / J), e < J
