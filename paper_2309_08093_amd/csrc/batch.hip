@@ -14,7 +14,8 @@
 //    registers per problem) and the absorb of R, each with one workgroup (or
 //    block set) per problem, driven by per-step descriptors in device memory;
 //  * the data sketches of all those problems are ONE persistent launch:
-//    - k >= 1: the fibres of every participating problem, problem by problem
+//    - k >= 1: the units (mode-0 fibres; for k >= 2 the contiguous
+//      n_0 x n_1 slabs) of every participating problem, problem by problem
 //      and column by column, form one sequence that is split into equal
 //      contiguous ranges, one per workgroup.  A workgroup accumulates the part
 //      of a column it holds in a J-entry FP64 LDS array (keys computed on the
@@ -206,11 +207,136 @@ __global__ __launch_bounds__(256) void k_bsketch_k(const BTensor* __restrict__ T
   }
 }
 
-// Y_j[b + J c] = sum over the partials of column (j, c), in slot order.
+// ---------------------------------------------------------------- k >= 2, slabs
+// For k >= 2 the n_0 x n_1 entries with fixed (i_2, ..., i_{d-1}) (a slab) are
+// contiguous in X, and entry e = i_0 + n_0 i_1 of a slab lands in bucket
+// P[e] + K, with P[e] = h_0(i_0) + h_1(i_1) (a per-problem LDS table) and K
+// the sum of the tables of the other modes but k (one value per slab).  The
+// unit of work is the slab instead of the fibre: the lanes of a wave stream
+// through the entries of its slab range 64 at a time, so every load is a full
+// coalesced row and no per-fibre key or offset is exchanged between lanes.
+// A lane recomputes K (from the mode tables, copied to LDS) only when it
+// steps into another slab.
+constexpr int kSlabU = 8;           // 64-entry rows per lane in flight
+constexpr size_t kSlabLds = 48 << 10;   // bytes for the slab table and the mode tables
+
+__global__ __launch_bounds__(256) void k_bsketch_slab(const BTensor* __restrict__ T, const int32_t* __restrict__ tids,
+                                                      const int64_t* __restrict__ fpre, const int64_t* __restrict__ cpre,
+                                                      const int64_t* __restrict__ spre, int32_t nt, int32_t k,
+                                                      double* __restrict__ part, int32_t Jmax, int32_t Smax) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* acc = reinterpret_cast<double*>(smem_raw);
+  uint32_t* P = reinterpret_cast<uint32_t*>(acc + Jmax);   // Smax entries
+  uint32_t* tl = P + Smax;                                  // the problem's packed tables
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int NW = blockDim.x >> 6;
+  const int64_t W = gridDim.x, w = blockIdx.x;
+  const int64_t Ttot = fpre[nt];
+  const int64_t gs = w * Ttot / W, ge = (w + 1) * Ttot / W;
+  if (gs >= ge) return;
+  int j = seg_of(fpre, nt, gs), jp = -1;
+  int64_t g = gs;
+  while (g < ge) {
+    while (fpre[j + 1] <= g) ++j;
+    const BTensor& t = T[tids[j]];
+    const int d = t.d;
+    const uint32_t n0 = (uint32_t)t.n[0], n1 = (uint32_t)t.n[1], nk = (uint32_t)t.n[k];
+    const uint32_t S = n0 * n1;
+    const uint32_t J = t.J;
+    int64_t Mp = 1, R = 1;
+    for (int s = 2; s < k; ++s) Mp *= t.n[s];
+    for (int s = k + 1; s < d; ++s) R *= t.n[s];
+    const int64_t F = Mp * R;   // slabs per column
+    const int64_t q0 = g - fpre[j];
+    const int64_t c = q0 / F;
+    const int64_t qa = q0 - c * F;
+    const int64_t lim = ge - fpre[j] - c * F;
+    const int64_t qe = lim < F ? lim : F;
+    for (uint32_t b = threadIdx.x; b < J; b += blockDim.x) acc[b] = 0.0;
+    if (j != jp) {   // P and the tables of a new problem (no wave reads them here)
+      const int ntab = t.toff[d - 1] + t.n[d - 1];
+      for (int i = threadIdx.x; i < ntab; i += blockDim.x) tl[i] = t.tab[i];
+      __syncthreads();
+      for (uint32_t e = threadIdx.x; e < S; e += blockDim.x) {
+        const uint32_t i1 = e / n0;
+        P[e] = key_add(tl[t.toff[0] + (e - i1 * n0)], tl[t.toff[1] + i1], J);
+      }
+      jp = j;
+    }
+    __syncthreads();
+    const int64_t wa = qa + (qe - qa) * wv / NW, we = qa + (qe - qa) * (wv + 1) / NW;
+    const int64_t tot = (we - wa) * (int64_t)S;
+    const gfloat Xg = (gfloat)t.X;
+    const uint32_t Mp32 = (uint32_t)Mp;
+    // offset and key of slab sl of column c (sl < F; slab indices of a
+    // problem fit in 32 bits)
+    auto locate = [&](int64_t sl, int64_t& base, uint32_t& K) {
+      uint32_t rho = (uint32_t)sl / Mp32, mu = (uint32_t)sl - rho * Mp32;
+      base = (((int64_t)rho * nk + c) * Mp + mu) * (int64_t)S;
+      K = 0;
+      for (int s = 2; s < k; ++s) {
+        const uint32_t ns = (uint32_t)t.n[s], q = mu / ns;
+        K = key_add(K, tl[t.toff[s] + (mu - q * ns)], J);
+        mu = q;
+      }
+      for (int s = k + 1; s < d; ++s) {
+        const uint32_t ns = (uint32_t)t.n[s], q = rho / ns;
+        K = key_add(K, tl[t.toff[s] + (rho - q * ns)], J);
+        rho = q;
+      }
+    };
+    int64_t sl = wa, base = 0;
+    uint32_t e = (uint32_t)lane, K = 0;
+    while (e >= S) {
+      e -= S;
+      ++sl;
+    }
+    if (sl < we) locate(sl, base, K);
+    for (int64_t m0 = 0; m0 < tot; m0 += 64 * kSlabU) {
+      float x[kSlabU];
+      uint32_t pe[kSlabU], kk[kSlabU];
+      bool ok[kSlabU];
+#pragma unroll
+      for (int u = 0; u < kSlabU; ++u) {
+        ok[u] = sl < we;
+        x[u] = ok[u] ? __builtin_nontemporal_load(Xg + base + e) : 0.0f;
+        pe[u] = e;
+        kk[u] = K;
+        e += 64;
+        if (e >= S) {   // into the next slab (several when S < 64)
+          do {
+            e -= S;
+            ++sl;
+          } while (e >= S);
+          if (sl < we) locate(sl, base, K);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kSlabU; ++u)
+        if (ok[u]) {
+          const uint32_t pk = P[pe[u]];
+          uint32_t bk = (pk & TT_KEY_MASK) + (kk[u] & TT_KEY_MASK);
+          bk = bk >= J ? bk - J : bk;
+          atomicAdd(&acc[bk], signed_f64(x[u], (pk ^ kk[u]) & TT_KEY_SIGN));
+        }
+    }
+    __syncthreads();
+    const int64_t gc = cpre[j] + c;
+    const int64_t slot = w - owner(fpre[j] + c * F, W, Ttot);
+    double* out = part + (spre[gc] + slot) * (int64_t)Jmax;
+    for (uint32_t b = threadIdx.x; b < J; b += blockDim.x) out[b] = acc[b];
+    __syncthreads();
+    g = fpre[j] + c * F + qe;
+  }
+}
+
+// Y_j[b + J c] = sum over the partials of column (j, c), in slot order
+// (units: slabs for the slab launch, else fibres).
 __global__ void k_breduce(const BTensor* __restrict__ T, const int32_t* __restrict__ tids,
                           const int64_t* __restrict__ fpre, const int64_t* __restrict__ cpre,
                           const int64_t* __restrict__ spre, int32_t nt, int32_t k, const double* __restrict__ part,
-                          int32_t Jmax, int64_t W) {
+                          int32_t Jmax, int64_t W, int32_t slab) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t ncol = cpre[nt];
   if (idx >= ncol * Jmax) return;
@@ -221,7 +347,7 @@ __global__ void k_breduce(const BTensor* __restrict__ T, const int32_t* __restri
   if (b >= t.J) return;
   const int64_t c = gc - cpre[j];
   int64_t F = 1;
-  for (int s = 1; s < t.d; ++s)
+  for (int s = slab ? 2 : 1; s < t.d; ++s)   // units of the launch: slabs or fibres
     if (s != k) F *= t.n[s];
   const int64_t Ttot = fpre[nt];
   const int64_t first = fpre[j] + c * F;
@@ -347,6 +473,9 @@ struct tt_batch_s {
   size_t o_tids[TT_MAX_ORDER], o_fpre[TT_MAX_ORDER], o_cpre[TT_MAX_ORDER], o_spre[TT_MAX_ORDER];
   int64_t Wmax = 8192;
   int64_t W[TT_MAX_ORDER];   // workgroups of the k >= 1 launch (0: device occupancy)
+  // k >= 2 steps run in slab units when every slab and table set fits in LDS
+  bool slab[TT_MAX_ORDER] = {};
+  int32_t slab_S[TT_MAX_ORDER] = {}, slab_tab[TT_MAX_ORDER] = {};
   // descriptors as last uploaded
   std::vector<BTensor> host_desc;
   bool desc_valid = false;
@@ -363,13 +492,19 @@ struct tt_batch_s {
 
 namespace {
 
-int occupancy_grid(int nj, int32_t Jmax) {
+size_t step_lds(tt_batch b, int k) {
+  return sizeof(double) * b->Jmax + (b->slab[k] ? sizeof(uint32_t) * (size_t)(b->slab_S[k] + b->slab_tab[k]) : 0);
+}
+
+// resident workgroups of the step-k launch on the whole device
+int occupancy_grid(tt_batch b, int k) {
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     ncu = 256;
-  const size_t lds = sizeof(double) * Jmax;
+  const size_t lds = step_lds(b, k);
   hipError_t e = hipErrorInvalidValue;
-  if (nj == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_k<2>, 256, lds);
+  if (b->slab[k]) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_slab, 256, lds);
+  else if (b->nj == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_k<2>, 256, lds);
   else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_k<4>, 256, lds);
   if (e != hipSuccess || per < 1) per = 1;
   return per * ncu;
@@ -441,12 +576,15 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
   const int64_t* spre = reinterpret_cast<const int64_t*>(b->ws + b->o_spre[k]);
   double* part = reinterpret_cast<double*>(b->ws + b->o_part);
   const int64_t Ttot = b->fpre[k].back();
-  int64_t W = Wk > 0 ? Wk : occupancy_grid(b->nj, b->Jmax);
+  int64_t W = Wk > 0 ? Wk : occupancy_grid(b, k);
   if (W > b->Wmax) W = b->Wmax;
   if (W > Ttot) W = Ttot;
   if (W < 1) W = 1;
-  const size_t lds = sizeof(double) * b->Jmax;
-  if (b->nj == 2)
+  const size_t lds = step_lds(b, k);
+  if (b->slab[k])
+    hipLaunchKernelGGL(k_bsketch_slab, dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre, cpre, spre, nt, k,
+                       part, b->Jmax, b->slab_S[k]);
+  else if (b->nj == 2)
     hipLaunchKernelGGL(k_bsketch_k<2>, dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre, cpre, spre, nt, k,
                        part, b->Jmax);
   else
@@ -455,7 +593,7 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t total = b->cpre[k].back() * b->Jmax;
   hipLaunchKernelGGL(k_breduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, b->stream, T, tids, fpre, cpre,
-                     spre, nt, k, part, b->Jmax, W);
+                     spre, nt, k, part, b->Jmax, W, b->slab[k] ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -707,18 +845,28 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
     b->W[k] = 0;
     b->fpre[k].push_back(0);
     b->cpre[k].push_back(0);
+    // slab units for k >= 2 when the largest slab table and table set fit in
+    // kSlabLds bytes of LDS beside the accumulator
+    b->slab[k] = k >= 2;
+    for (int i = 0; i < count; ++i) {
+      tt_plan p = b->plans[i];
+      if (p->d <= k) continue;
+      b->slab_S[k] = std::max(b->slab_S[k], (int32_t)(p->n[0] * p->n[1]));
+      b->slab_tab[k] = std::max(b->slab_tab[k], (int32_t)p->tab_off[p->d]);
+    }
+    if (sizeof(uint32_t) * ((size_t)b->slab_S[k] + b->slab_tab[k]) > kSlabLds) b->slab[k] = false;
     for (int i = 0; i < count; ++i) {
       tt_plan p = b->plans[i];
       if (p->d <= k) continue;
       b->tids[k].push_back(i);
-      b->fpre[k].push_back(b->fpre[k].back() + p->N / p->n[0]);
+      b->fpre[k].push_back(b->fpre[k].back() + p->N / p->n[0] / (b->slab[k] ? p->n[1] : 1));
       b->cpre[k].push_back(b->cpre[k].back() + p->n[k]);
     }
     const int64_t Ttot = b->fpre[k].back();
     b->spre[k].push_back(0);
     for (size_t j = 0; j < b->tids[k].size(); ++j) {
       tt_plan p = b->plans[b->tids[k][j]];
-      const int64_t F = (p->N / p->n[0]) / (k == 0 ? 1 : p->n[k]);
+      const int64_t F = (p->N / p->n[0] / (b->slab[k] ? p->n[1] : 1)) / (k == 0 ? 1 : p->n[k]);
       // a column of F consecutive fibres meets at most floor((F - 1) W / T) + 2 ranges
       const int64_t slots = (int64_t)(((__int128)(F - 1) * b->Wmax) / (Ttot > 0 ? Ttot : 1)) + 2;
       for (int64_t c = 0; c < p->n[k]; ++c) b->spre[k].push_back(b->spre[k].back() + slots);
@@ -986,13 +1134,13 @@ tt_status tt_batch_autotune(tt_batch b, const void* const* X, int32_t reps, int6
   if (reps < 1) reps = 1;
   tt_status st;
   if ((st = upload_desc(b, X))) return st;
-  const int64_t res = occupancy_grid(b->nj, b->Jmax);
-  const int64_t cand[4] = {res / 2, res, 2 * res, 4 * res};
   hipEvent_t e0, e1;
   TT_HIP_TRY(hipEventCreate(&e0));
   TT_HIP_TRY(hipEventCreate(&e1));
   for (int k = 1; k < b->max_d; ++k) {
     if (b->tids[k].empty()) continue;
+    const int64_t res = occupancy_grid(b, k);
+    const int64_t cand[4] = {res / 2, res, 2 * res, 4 * res};
     float best = 1e30f;
     int64_t bestW = res;
     for (int64_t W : cand) {

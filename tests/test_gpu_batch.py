@@ -67,8 +67,16 @@ def test_batched_sketch_matches_oracle(env, integer):
                 assert np.linalg.norm(got - want) <= 1e-5 * np.linalg.norm(want)
 
 
-# batches whose longest mode-0 fibre takes 2 and 4 entries per lane
+# batches whose longest mode-0 fibre takes 2 and 4 entries per lane; batches
+# whose k >= 2 steps run on slabs shorter than a wave (a lane steps over
+# several slabs per row), and whose largest slab table does not fit in LDS
+# (those steps run on fibres)
 WIDE = {
+    "tiny slabs": [dict(n=[3, 2, 5, 4], ranks=[1, 2, 2, 2, 1], J=40, seed=116),
+                   dict(n=[2, 2, 3, 5, 3], ranks=[1, 2, 2, 2, 2, 1], J=50, seed=117),
+                   dict(n=[7, 9, 4], ranks=[1, 3, 2, 1], J=32, seed=118)],
+    "large slabs": [dict(n=[130, 100, 3], ranks=[1, 3, 2, 1], J=64, seed=119),
+                    dict(n=[10, 10, 4, 3], ranks=[1, 2, 3, 2, 1], J=48, seed=120)],
     "n0<=128": [dict(n=[100, 6, 7], ranks=[1, 4, 5, 1], J=90, seed=111),
                 dict(n=[40, 5, 4, 3], ranks=[1, 3, 3, 2, 1], J=64, seed=112)],
     "n0<=256": [dict(n=[200, 5, 4, 3], ranks=[1, 4, 3, 2, 1], J=150, seed=113),
@@ -84,7 +92,7 @@ def test_batched_sketch_wide_fibres(env, which):
     probs = WIDE[which]
     b = tts.Batch(probs)
     Xs, Xh = make_inputs(torch, probs, integer=True)
-    for k in range(4):
+    for k in range(max(len(p["n"]) for p in probs)):
         Ys = b.sketch_tensor(Xs, k)
         torch.cuda.synchronize()
         for i, p in enumerate(probs):
