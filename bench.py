@@ -271,12 +271,13 @@ def run_batched(args):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 5
-        steps[k] = {"kernel": "k_bsketch_0" if k == 0 else "k_bsketch_k+k_breduce", "avg_launch_ms": round(ms, 4),
+        kern = batch.sketch_kernel(k)
+        steps[k] = {"kernel": kern if k == 0 else kern + "+k_breduce", "avg_launch_ms": round(ms, 4),
                     "bytes": nbytes, "GB/s": round(nbytes / ms / 1e6, 1),
                     "frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBPS, 4)}
     dom = max((k for k in steps if k >= 1), key=lambda k: steps[k]["avg_launch_ms"] * 1.0)
     rf = {"bound": "hbm", "achieved": steps[dom]["GB/s"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-          "frac": steps[dom]["frac"], "traffic": None, "kernel": "k_bsketch_k (step %d)" % dom,
+          "frac": steps[dom]["frac"], "traffic": None, "kernel": "%s (step %d)" % (batch.sketch_kernel(dom), dom),
           "avg_launch_ms": steps[dom]["avg_launch_ms"], "bytes_per_launch": steps[dom]["bytes"]}
     res = batch.sweep(Xs, cores, residuals=True)
     out = {

@@ -328,9 +328,9 @@ tt_status tt_als_run(tt_plan plan, const void* X, void* const* cores, const floa
  * Batched form: many independent problems of uneven shapes and ranks advance
  * together.  Each problem is described by its own tt_plan_desc (FP32 X, FP32
  * work, TT_GRAM_WORK; n_0 <= 256; any order, ranks, J, lambda, seed).  A
- * sweep runs step k = 0, 1, ... for all problems of order > k: per-problem
- * interface sketches and core updates, and ONE persistent data-sketch launch
- * covering every participating problem.  The whole sweep can be captured into
+ * sweep runs step k = 0, 1, ... for all problems of order > k: the interface
+ * sketches and core updates of all of them (one launch per kernel), and ONE
+ * persistent data-sketch launch covering every participating problem.  The whole sweep can be captured into
  * a hipGraph (tt_batch_set_graph) and replayed; tables then follow a device
  * sweep counter.  The batch owns one plan per problem; all device memory is
  * one caller workspace.
@@ -357,6 +357,18 @@ tt_status tt_batch_set_graph(tt_batch batch, int32_t enable);
  * touched.  X: count device pointers.  Y == NULL runs the launch only (the
  * results stay in the problems' plans), e.g. to time it. */
 tt_status tt_batch_sketch_tensor(tt_batch batch, const void* const* X, int32_t k, void* const* Y);
+
+/* Which data-sketch kernel the batched launch of step k runs (host query, no
+ * device work): TT_BSKETCH_PATH_BUCKET for k = 0 (one workgroup per (problem,
+ * bucket) gathers the fibres hashed to it), TT_BSKETCH_PATH_FIBRES (mode-0
+ * fibres streamed into LDS bucket arrays; k = 1, and k >= 2 when slabs do not
+ * fit in LDS) or TT_BSKETCH_PATH_SLABS (for k >= 2, the contiguous n_0 x n_1
+ * slabs streamed 64 entries at a time with a per-problem LDS key table).
+ * TT_ERR_ARG for k outside [0, max order) or null output. */
+#define TT_BSKETCH_PATH_BUCKET 0
+#define TT_BSKETCH_PATH_FIBRES 1
+#define TT_BSKETCH_PATH_SLABS 2
+tt_status tt_batch_sketch_path(tt_batch batch, int32_t k, int32_t* path);
 
 /* One sweep of every problem.  X: count device pointers; cores: count host
  * arrays of d_i device core pointers.  residuals: NULL, or count host doubles

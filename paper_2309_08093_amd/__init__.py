@@ -384,6 +384,12 @@ class Batch:
         check(_lib.tt_batch_sketch_tensor(self._h, xs, int(k), ya), "tt_batch_sketch_tensor")
         return Ys
 
+    def sketch_kernel(self, k):
+        """Name of the data-sketch kernel the batched launch of step k runs."""
+        path = ctypes.c_int32()
+        check(_lib.tt_batch_sketch_path(self._h, int(k), ctypes.byref(path)), "tt_batch_sketch_path")
+        return _abi.BSKETCH_PATHS[path.value]
+
     def sketch_launch(self, Xs, k):
         """The batched data-sketch launch of step k without copying results out."""
         xs, keep = self._xs(Xs)

@@ -76,6 +76,7 @@ SIGNATURES = {
     "tt_batch_sketch_tensor": [_vp, _vpp, ctypes.c_int32, _vpp],
     "tt_batch_sweep": [_vp, _vpp, _vp, ctypes.POINTER(ctypes.c_double)],
     "tt_batch_autotune": [_vp, _vpp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)],
+    "tt_batch_sketch_path": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "tt_als_run": [_vp, _vp, _vpp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
 }
@@ -91,6 +92,7 @@ class RunStats(ctypes.Structure):
 
 
 SKETCH_PATHS = {0: "k_sketch_mode0", 1: "k_sketch_modek", 2: "k_sketch_gs"}
+BSKETCH_PATHS = {0: "k_bsketch_0", 1: "k_bsketch_k", 2: "k_bsketch_slab"}
 PROF_CLASSES = ["sketch_k0", "sketch_k", "sketch_aux", "interface", "gram", "solve", "qr", "residual", "tables"]
 STRING_FUNCS = ["tt_last_error", "tt_version"]
 

@@ -1128,6 +1128,13 @@ tt_status tt_batch_sweep(tt_batch b, const void* const* X, void* const* const* c
   return TT_OK;
 }
 
+tt_status tt_batch_sketch_path(tt_batch b, int32_t k, int32_t* path) {
+  if (!b || !path) return tt_fail(TT_ERR_ARG, "null argument");
+  if (k < 0 || k >= b->max_d) return tt_fail(TT_ERR_ARG, "step %d outside [0, %d)", k, b->max_d);
+  *path = k == 0 ? TT_BSKETCH_PATH_BUCKET : b->slab[k] ? TT_BSKETCH_PATH_SLABS : TT_BSKETCH_PATH_FIBRES;
+  return TT_OK;
+}
+
 tt_status tt_batch_autotune(tt_batch b, const void* const* X, int32_t reps, int64_t* chosen) {
   if (!b || !X) return tt_fail(TT_ERR_ARG, "null argument");
   if (!b->ws) return tt_fail(TT_ERR_WORKSPACE, "no workspace bound");

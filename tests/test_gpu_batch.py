@@ -93,6 +93,11 @@ def test_batched_sketch_wide_fibres(env, which):
     b = tts.Batch(probs)
     Xs, Xh = make_inputs(torch, probs, integer=True)
     for k in range(max(len(p["n"]) for p in probs)):
+        # slabs for k >= 2 unless a participating problem's slab table does
+        # not fit in LDS (n = [130, 100, 3] at k = 2)
+        want_kernel = "k_bsketch_0" if k == 0 else \
+            "k_bsketch_slab" if k >= 2 and (which, k) != ("large slabs", 2) else "k_bsketch_k"
+        assert b.sketch_kernel(k) == want_kernel, (k, b.sketch_kernel(k))
         Ys = b.sketch_tensor(Xs, k)
         torch.cuda.synchronize()
         for i, p in enumerate(probs):
