@@ -376,7 +376,7 @@ tt_status tt_batch_sketch_path(tt_batch batch, int32_t k, int32_t* path);
 tt_status tt_batch_sweep(tt_batch batch, const void* const* X, void* const* const* cores, double* residuals);
 
 /* Autotuner: time the k >= 1 data-sketch launch of every step with workgroup
- * counts of 1/2, 1, 2 and 4 times the device occupancy (reps launches each)
+ * counts of 1/2, 1, 2, 4 and 8 times the device occupancy (at most 16384) (reps launches each)
  * and keep the fastest.  chosen: NULL or host int64 array of max order
  * entries receiving the choice per step (0 for k = 0). */
 tt_status tt_batch_autotune(tt_batch batch, const void* const* X, int32_t reps, int64_t* chosen);

@@ -471,7 +471,7 @@ struct tt_batch_s {
   std::vector<const void*> upd_key;
   hipEvent_t ev_main = nullptr;
   size_t o_tids[TT_MAX_ORDER], o_fpre[TT_MAX_ORDER], o_cpre[TT_MAX_ORDER], o_spre[TT_MAX_ORDER];
-  int64_t Wmax = 8192;
+  int64_t Wmax = 16384;
   int64_t W[TT_MAX_ORDER];   // workgroups of the k >= 1 launch (0: device occupancy)
   // k >= 2 steps run in slab units when every slab and table set fits in LDS
   bool slab[TT_MAX_ORDER] = {};
@@ -1147,7 +1147,7 @@ tt_status tt_batch_autotune(tt_batch b, const void* const* X, int32_t reps, int6
   for (int k = 1; k < b->max_d; ++k) {
     if (b->tids[k].empty()) continue;
     const int64_t res = occupancy_grid(b, k);
-    const int64_t cand[4] = {res / 2, res, 2 * res, 4 * res};
+    const int64_t cand[5] = {res / 2, res, 2 * res, 4 * res, 8 * res};
     float best = 1e30f;
     int64_t bestW = res;
     for (int64_t W : cand) {
