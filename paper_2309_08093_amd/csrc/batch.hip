@@ -851,8 +851,11 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
     for (int i = 0; i < count; ++i) {
       tt_plan p = b->plans[i];
       if (p->d <= k) continue;
-      b->slab_S[k] = std::max(b->slab_S[k], (int32_t)(p->n[0] * p->n[1]));
-      b->slab_tab[k] = std::max(b->slab_tab[k], (int32_t)p->tab_off[p->d]);
+      // (clamped: any value past the LDS limit only turns the slab path off)
+      const int64_t S = std::min<int64_t>((int64_t)p->n[0] * p->n[1], INT32_MAX);
+      const int64_t tab = std::min<int64_t>((int64_t)p->tab_off[p->d], INT32_MAX);
+      b->slab_S[k] = std::max(b->slab_S[k], (int32_t)S);
+      b->slab_tab[k] = std::max(b->slab_tab[k], (int32_t)tab);
     }
     if (sizeof(uint32_t) * ((size_t)b->slab_S[k] + b->slab_tab[k]) > kSlabLds) b->slab[k] = false;
     for (int i = 0; i < count; ++i) {
