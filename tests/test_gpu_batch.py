@@ -111,6 +111,16 @@ def test_batched_sketch_wide_fibres(env, which):
             np.testing.assert_array_equal(got, want)
 
 
+def test_sketch_path_rejects_steps_outside_the_batch(env):
+    torch, tts = env
+    say("batch sketch path arguments")
+    b = tts.Batch(PROBLEMS)
+    assert [b.sketch_kernel(k) for k in range(5)][:2] == ["k_bsketch_0", "k_bsketch_k"]
+    for k in (-1, 5):
+        with pytest.raises(tts.TTError):
+            b.sketch_kernel(k)
+
+
 def test_tables_are_the_plans_tables(env):
     torch, tts = env
     say("batch tables")
