@@ -277,7 +277,8 @@ def run_batched(args):
                     "frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBPS, 4)}
     dom = max((k for k in steps if k >= 1), key=lambda k: steps[k]["avg_launch_ms"] * 1.0)
     rf = {"bound": "hbm", "achieved": steps[dom]["GB/s"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-          "frac": steps[dom]["frac"], "traffic": None, "kernel": "%s (step %d)" % (batch.sketch_kernel(dom), dom),
+          "frac": steps[dom]["frac"], "traffic": stored_traffic("k_bsketch", "c4", "batch.hip", step=dom),
+          "kernel": "%s (step %d)" % (batch.sketch_kernel(dom), dom),
           "avg_launch_ms": steps[dom]["avg_launch_ms"], "bytes_per_launch": steps[dom]["bytes"]}
     res = batch.sweep(Xs, cores, residuals=True)
     out = {
@@ -296,18 +297,18 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def source_digest():
-    """sha256 of the data-sketch kernel source: a stored counter reading is
+def source_digest(source="k_sketch.hip"):
+    """sha256 of a data-sketch kernel source: a stored counter reading is
     used only while the kernel it was taken from is unchanged."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2309_08093_amd", "csrc", "k_sketch.hip")
+    path = os.path.join(ROOT, "paper_2309_08093_amd", "csrc", source)
     try:
         return hashlib.sha256(open(path, "rb").read()).hexdigest()
     except OSError:
         return None
 
 
-def stored_traffic(kernel, config):
+def stored_traffic(kernel, config, source="k_sketch.hip", step=None):
     """HBM bytes per launch of `kernel` on `config` from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE scaled by a device copy of known size),
     or None if there is none for the current kernel source."""
@@ -320,7 +321,7 @@ def stored_traffic(kernel, config):
     for ln in lines:
         if ln.startswith("JSON: "):
             rec = json.loads(ln[6:])
-            if rec.get("source_sha256") == source_digest():
+            if rec.get("source_sha256") == source_digest(source) and rec.get("step") == step:
                 return rec["traffic_bytes_per_launch"]
     return None
 
