@@ -133,8 +133,8 @@ tt_status tt_plan_get_tables(tt_plan plan, int32_t s, int32_t* h, int8_t* v);
  * (used for the paper's worked example and for injective test sketches). */
 tt_status tt_plan_set_tables(tt_plan plan, int32_t s, const int32_t* h, const int8_t* v);
 
-/* Data sketch Y_k = S_{-k} A_(k)^T (sketched subproblem, Sec. 3 eq. (3.4);
- * TensorSketch over all modes except k, eqs. (2.1)-(2.2)): every entry
+/* Data sketch Y_k = S_{-k} A_(k)^T (sketched subproblem, Sec. 3 (lrtt_sub4);
+ * TensorSketch over all modes except k, (eqn_h)-(eqn_v)): every entry
  * X(i_0..i_{d-1}) adds prod_{s!=k} v_s(i_s) X(i) to
  * Y[(sum_{s!=k} h_s(i_s)) mod J, i_k].  X: device, x_dtype, N entries.
  * Y: device, work type, J x n_k column-major, fully overwritten. */
@@ -147,7 +147,7 @@ tt_status tt_sketch_tensor(tt_plan plan, const void* X, int32_t k, void* Y);
  * SH: device, work type, J x R_k R_{k+1} column-major, fully overwritten. */
 tt_status tt_sketch_interface(tt_plan plan, const void* const* cores, int32_t k, void* SH);
 
-/* Sketched proximal update of core k (closed form, Sec. 3 eq. (3.5), with
+/* Sketched proximal update of core k (closed form, Sec. 3 (ite), with
  * S^T S): G_k(2)^new = (Y^T SH + lambda G_k(2)^old)(SH^T SH + lambda I)^{-1}.
  * SH, Y: device, work type (as produced above).  G_old, G_new: device FP64
  * cores of shape (R_k, n_k, R_{k+1}); they may alias.  The Gram and RHS
@@ -166,7 +166,7 @@ tt_status tt_left_orth_absorb(tt_plan plan, void* const* cores, int32_t k);
  * transpose, G_k <- Q^T, G_{k-1}^L <- G_{k-1}^L R^T.  In place, FP64. */
 tt_status tt_right_orthogonalize(tt_plan plan, void* const* cores);
 
-/* Relative residual ||X - [[G]]||_F / ||X||_F (objective (3.1), Sec. 3),
+/* Relative residual ||X - [[G]]||_F / ||X||_F (objective (lrtt), Sec. 3),
  * reconstructing the TT on the fly and accumulating in FP64.  Synchronises;
  * *rel_residual receives the value.  Returns TT_ERR_NONFINITE on NaN/Inf. */
 tt_status tt_residual(tt_plan plan, const void* X, const void* const* cores, double* rel_residual);

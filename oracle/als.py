@@ -14,7 +14,7 @@ def tt_full(cores):
 
 
 def rel_residual(X, cores):
-    """|| [[G]] - A ||_F / || A ||_F, the objective of Sec. 3 eq. (3.1) made
+    """|| [[G]] - A ||_F / || A ||_F, the objective of Sec. 3 (lrtt) made
     relative; accumulated in FP64."""
     X = np.asarray(X, dtype=np.float64).reshape(-1, order="F")
     return float(np.linalg.norm(tt_full(cores) - X) / np.linalg.norm(X))
@@ -31,7 +31,7 @@ def sweep(X, n, cores, J, lam, seed=0, t=0, tabs=None, interface="cyclic", recor
 
     1. right-to-left orthogonalisation of all cores;
     2. TensorSketch tables S_s for this pass (``tabs`` = (hs, vs) overrides);
-    3. for k = 0..d-1: SH_k = S H_k; Y_k = S A_(k)^T; proximal update (3.5)
+    3. for k = 0..d-1: SH_k = S H_k; Y_k = S A_(k)^T; proximal update (ite)
        with G_k^{(t)} = the core's value just before its update; if k < d-1,
        QR of G_k^L, G_k <- Q, G_{k+1} <- R G_{k+1}^R.
 

@@ -4,13 +4,13 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
 Everything here is the plain definition written out:
   * ``tensorsketch_matrix`` builds S = Omega D of Sec. 2.2 (Definition of
-    TensorSketch, eqs. (2.1) combined hash and (2.2) combined sign) entry by
+    TensorSketch, (eqn_h) combined hash and (eqn_v) combined sign) entry by
     entry.
   * ``data_sketch`` computes S A_(k)^T of the sketched subproblem (Sec. 3,
-    eq. (3.4)) by visiting every tensor entry once and adding its signed value
+    (lrtt_sub4)) by visiting every tensor entry once and adding its signed value
     to its bucket: each column of S holds exactly one +-1.
-  * ``interface_explicit`` forms H_k = G_{>k}^T (x) G_{<k} (Sec. 3, under eq.
-    (3.2)) and multiplies by the explicit S.
+  * ``interface_explicit`` forms H_k = G_{>k}^T (x) G_{<k} (Sec. 3, its
+    definition under (lrtt_sub4)) and multiplies by the explicit S.
   * ``interface_cyclic`` computes the same S H_k without FFTs: a CountSketch
     adds the mode hashes mod J, i.e. each core contributes a cyclic shift of
     the bucket axis (the identity behind Lemma 1 / Theorem 1 of Sec. 3,
@@ -23,7 +23,7 @@ def tensorsketch_matrix(hs, vs, J):
     """Explicit TensorSketch matrix over the listed modes (first mode fastest).
 
     Column j <-> (i_0, ..., i_{q-1}) with j = sum_s i_s prod_{t<s} n_t; row
-    (sum_s h_s(i_s)) mod J holds prod_s v_s(i_s) (Sec. 2.2, eqs. (2.1)-(2.2)).
+    (sum_s h_s(i_s)) mod J holds prod_s v_s(i_s) (Sec. 2.2, (eqn_h)-(eqn_v)).
     """
     sizes = [len(h) for h in hs]
     ncols = int(np.prod(sizes)) if sizes else 1
@@ -92,7 +92,7 @@ def data_sketch(X, n, k, hs, vs, J, slab_entries=1 << 24):
 
 
 def left_product(cores, k):
-    """G_{<k} (prod_{i<k} n_i x R[k]); G_{<0} = [[1]] (Sec. 3, under eq. (3.2))."""
+    """G_{<k} (prod_{i<k} n_i x R[k]); G_{<0} = [[1]] (Sec. 3, definition of H_k under (lrtt_sub4))."""
     T = np.ones((1, 1))
     for i in range(k):
         G = np.asarray(cores[i], dtype=np.float64)
@@ -113,7 +113,7 @@ def right_product(cores, k):
 
 
 def interface_matrix(cores, k):
-    """H_k = G_{>k}^T (x) G_{<k}; column alpha + beta*R[k] (Sec. 3, eq. (3.2))."""
+    """H_k = G_{>k}^T (x) G_{<k}; column alpha + beta*R[k] (Sec. 3, definition of H_k under (lrtt_sub4))."""
     return np.kron(right_product(cores, k).T, left_product(cores, k))
 
 

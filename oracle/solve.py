@@ -20,7 +20,7 @@ def core_fold2(G2, r0, r1):
 
 def prox_update(SH, Y, G_old, lam):
     """Closed-form minimiser of the sketched proximal subproblem (Sec. 3,
-    eqs. (3.4)-(3.5), reading the printed 'S S^T' as S^T S, the only
+    (lrtt_sub4)-(ite), reading the printed 'S S^T' as S^T S, the only
     dimensionally consistent product):
 
         G_(2)^{new} = (Y^T SH + lam G_(2)^{old}) (SH^T SH + lam I)^{-1}

@@ -1,5 +1,5 @@
 // Gram and right-hand-side contractions of the closed-form update (Sec. 3,
-// eq. (3.5)): [SH^T SH | SH^T Y] = SH^T [SH | Y], an s x (s + n_k) product
+// (ite)): [SH^T SH | SH^T Y] = SH^T [SH | Y], an s x (s + n_k) product
 // over the J sketch rows.  Split-K: each 16 x 16 output tile and each K chunk
 // of 256 rows is one wave running 16x16 MFMAs; partial tiles go to a buffer
 // that the FP64 solve sums in chunk order.

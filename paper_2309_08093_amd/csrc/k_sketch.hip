@@ -1,4 +1,4 @@
-// Data sketch Y_k = S_{-k} A_(k)^T (Sec. 3, eq. (3.4); TensorSketch of
+// Data sketch Y_k = S_{-k} A_(k)^T (Sec. 3, (lrtt_sub4); TensorSketch of
 // Sec. 2.2): a sign-weighted scatter-add of every entry of X into J buckets.
 //
 // X is read as a sequence of mode-0 fibres (n_0 contiguous entries).  Within a

@@ -1,4 +1,4 @@
-// FP64 proximal solve (Sec. 3, eq. (3.5)).
+// FP64 proximal solve (Sec. 3, (ite)).
 //
 // Solve: the split-K Gram partials of [SH^T SH | SH^T Y] are summed in FP64
 // (k_gram_sum); M = SH^T SH + lambda I is factored M = L L^T by a blocked
@@ -6,7 +6,7 @@
 // second kernel forms B = SH^T Y + lambda G_(2)^T for a block of columns and
 // solves L L^T Z = B by blocked forward and back substitution in LDS, one
 // workgroup per block of columns.
-// lambda > 0 makes M positive definite (Sec. 3, remark after eq. (3.5)); a
+// lambda > 0 makes M positive definite (Sec. 3, remark after (ite)); a
 // non-positive pivot records TT_ERR_NOT_SPD in the status word.
 //
 // Blocks of 16 pivots.  The critical path is the chain of pivots, so it is

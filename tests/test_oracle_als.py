@@ -1,7 +1,7 @@
 """Pins of the oracle's full sweep (Algorithm 1, Sec. 3) and of Theorem 5 /
 Corollary 3 (Sec. 4), CPU only.
 
-Anchors: exact recovery of a noise-free TT (the objective (3.1) reaches 0 at
+Anchors: exact recovery of a noise-free TT (the objective (lrtt) reaches 0 at
 the generating cores), convergence to the noise floor, the injective-sketch
 sweep equals exact proximal TT-ALS, Eckart-Young for d = 2, and the
 (1 + eps) * OPT guarantee of Theorem 5 at a size where Corollary 3's m is
@@ -39,7 +39,7 @@ def test_noisy_tt_converges_to_noise_floor():
 
 
 def test_injective_sketch_sweep_is_exact_prox_als():
-    # With S^T S = I every step is the exact proximal TT-ALS step (3.3).
+    # With S^T S = I every step is the exact proximal TT-ALS step (lrtt_sub_prox).
     n, R, lam = [4, 5, 3], [1, 2, 3, 1], 0.1
     X = synth.rng(35).standard_normal(60)
     cores0 = synth.random_cores(n, R, 36)

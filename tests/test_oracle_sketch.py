@@ -146,7 +146,7 @@ def _brute_tt_entry(cores, idx):
 
 def test_tt_products_and_interface_matrix():
     # [[G]] entry by entry (Sec. 2.1) vs left/right products, and
-    # A_(k)^T = H_k G_k(2)^T with H_k = G_{>k}^T (x) G_{<k} (Sec. 3, eq. (3.2))
+    # A_(k)^T = H_k G_k(2)^T with H_k = G_{>k}^T (x) G_{<k} (Sec. 3, definition of H_k under (lrtt_sub4))
     from oracle import solve
     n, R = [3, 4, 2, 3], [1, 2, 3, 2, 1]
     cores = synth.random_cores(n, R, 12)

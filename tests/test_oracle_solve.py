@@ -1,7 +1,7 @@
 """Pins of the oracle's proximal update, QR and orthogonalisation (CPU only).
 
 Anchors: the stacked least-squares form of Theorem 5's proof (Sec. 4) solved
-by numpy.linalg.lstsq, the exact proximal subproblem (Sec. 3, eq. (3.3)) under
+by numpy.linalg.lstsq, the exact proximal subproblem (Sec. 3, (lrtt_sub_prox)) under
 an injective unit-sign sketch (S^T S = I), limiting cases of lambda, and QR /
 TT invariants.
 """
@@ -65,7 +65,7 @@ def test_injective_sketch_gives_exact_prox_update():
         SH = sketch.interface_cyclic(cores, k, hs, vs, J)
         Y = sketch.data_sketch(X, n, k, hs, vs, J)
         got = solve.prox_update(SH, Y, cores[k], lam)
-        # exact subproblem (3.3): min ||H Z - A_(k)^T||^2 + lam ||Z - G_(2)^T||^2 by dense lstsq
+        # exact subproblem (lrtt_sub_prox): min ||H Z - A_(k)^T||^2 + lam ||Z - G_(2)^T||^2 by dense lstsq
         H = sketch.interface_matrix(cores, k)
         s = H.shape[1]
         A = np.vstack([H, np.sqrt(lam) * np.eye(s)])
