@@ -26,7 +26,7 @@ def core_change(old, new):
     return max(float(np.linalg.norm(b - a) / np.linalg.norm(b)) for a, b in zip(old, new))
 
 
-def sweep(X, n, cores, J, lam, seed=0, t=0, tabs=None, interface="cyclic", record=None):
+def sweep(X, n, cores, J, lam, seed=0, t=0, tabs=None, interface="cyclic", record=None, gram="fp64"):
     """One while-pass of Algorithm 1.
 
     1. right-to-left orthogonalisation of all cores;
@@ -36,7 +36,10 @@ def sweep(X, n, cores, J, lam, seed=0, t=0, tabs=None, interface="cyclic", recor
        QR of G_k^L, G_k <- Q, G_{k+1} <- R G_{k+1}^R.
 
     ``record`` (a list) receives per-k dicts with the step inputs/outputs so
-    that a GPU step can be compared on identical inputs.
+    that a GPU step can be compared on identical inputs.  ``gram="bf16"``
+    models the mixed-precision form (not from the paper): the normal
+    equations are formed from the BF16 roundings of SH and Y
+    (``solve.round_bf16``); everything else stays FP64.
     """
     d = len(n)
     cores = solve.right_orthogonalize(cores)
@@ -51,7 +54,10 @@ def sweep(X, n, cores, J, lam, seed=0, t=0, tabs=None, interface="cyclic", recor
             SH = sketch.interface_cyclic(cores, k, hs, vs, J)
         Y = sketch.data_sketch(X, n, k, hs, vs, J)
         G_old = cores[k]
-        G_new = solve.prox_update(SH, Y, G_old, lam)
+        if gram == "bf16":
+            G_new = solve.prox_update(solve.round_bf16(SH), solve.round_bf16(Y), G_old, lam)
+        else:
+            G_new = solve.prox_update(SH, Y, G_old, lam)
         if record is not None:
             record.append(dict(k=k, cores_in=[c.copy() for c in cores], SH=SH, Y=Y,
                                G_old=G_old.copy(), G_new=G_new.copy()))

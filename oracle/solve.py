@@ -40,6 +40,20 @@ def prox_update(SH, Y, G_old, lam):
     return core_fold2(Z.T, r0, r1)
 
 
+def round_bf16(A):
+    """Round to BF16 the way the precision form feeds its Gram: first to the
+    FP32 work type, then to BF16 (the upper 16 bits of an IEEE binary32,
+    round to nearest, ties to even), returned as FP64 values.
+
+    BF16 is not from the paper; the mixed-precision form computes M and B
+    from BF16 copies of SH and Y.  Finite inputs only."""
+    x = np.ascontiguousarray(np.asarray(A, dtype=np.float64).astype(np.float32))
+    bits = x.view(np.uint32).astype(np.uint64)
+    lsb = (bits >> np.uint64(16)) & np.uint64(1)
+    rounded = ((bits + np.uint64(0x7FFF) + lsb) >> np.uint64(16)) << np.uint64(16)
+    return rounded.astype(np.uint32).view(np.float32).astype(np.float64).reshape(np.shape(A))
+
+
 def prox_update_stacked(SH, Y, G_old, lam):
     """Same minimiser via the stacked least-squares form used in the proof of
     Theorem 5 (Sec. 4): min || [SH; sqrt(lam) I] Z - [Y; sqrt(lam) G_(2)^T] ||_F,

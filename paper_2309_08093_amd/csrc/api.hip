@@ -257,7 +257,7 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->res_waves = 4 * rb;
 
   const size_t ws = p->wsize();
-  const size_t gs = (p->wdt == TT_F64) ? 8 : 4;
+  const size_t gs = (p->gram_mode == TT_GRAM_BF16) ? 4 : 8;   // Gram partials: FP64 unless BF16 MFMA
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;

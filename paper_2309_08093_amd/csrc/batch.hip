@@ -628,7 +628,7 @@ tt_status upload_upd(tt_batch b, void* const* const* cores) {
       BUpd& u = b->upd[k][j];
       u.SH = p->at<float>(p->o_SH);
       u.Y = p->at<float>(p->o_Yall) + p->J * p->tab_off[k];
-      u.gpart = p->at<float>(p->o_gram);
+      u.gpart = p->at<double>(p->o_gram);
       u.gsum = p->at<double>(p->o_gsum);
       u.Lg = p->at<double>(p->o_minv);
       u.status = p->at<int32_t>(p->o_status);

@@ -452,7 +452,8 @@ size_t tt_chol_lds_bytes(int64_t s) { return (size_t)(s * (s + 1) / 2 + kCholExt
 int64_t tt_chol_out_doubles(int64_t s) { return s * (s + 1) / 2 + ((s + kBS - 1) / kBS) * kBS * kBS; }
 
 hipError_t launch_prox_from_gram(const tt_plan_s* p, int k, const double* G_old, double* G_new) {
-  return p->wdt == TT_F64 ? prox_t<double>(p, k, G_old, G_new) : prox_t<float>(p, k, G_old, G_new);
+  // FP32 partials only under TT_GRAM_BF16 (FP32 MFMA accumulation)
+  return p->gram_mode == TT_GRAM_BF16 ? prox_t<float>(p, k, G_old, G_new) : prox_t<double>(p, k, G_old, G_new);
 }
 
 hipError_t launch_copy_f64(const tt_plan_s* p, double* dst, const double* src, int64_t count) {

@@ -179,7 +179,7 @@ typedef int32_t __attribute__((address_space(1)))* gi32;
 struct BUpd {
   const float* SH;      // J x s
   const float* Y;       // J x n_k
-  float* gpart;         // Gram partials
+  double* gpart;        // Gram partials (FP64 MFMA accumulators)
   double* gsum;         // summed Gram
   double* Lg;           // Cholesky factor
   int32_t* status;      // plan status words

@@ -168,6 +168,41 @@ def test_batched_sweep_matches_single_plans(env):
             c, (p["ranks"][k], p["n"][k], p["ranks"][k + 1])) for k, c in enumerate(cb[i])]), rel=1e-4)
 
 
+# the problems above plus an order-5 problem of rank 2 and one whose k = 1 QR
+# (8 x 300 = 2400 rows) takes the per-problem QR launch instead of a batched
+# register-QR class
+ORACLE_PROBLEMS = PROBLEMS + [
+    dict(n=[6, 5, 4, 5, 6], ranks=[1, 2, 2, 2, 2, 1], J=96, seed=107),
+    dict(n=[10, 300, 6], ranks=[1, 8, 6, 1], J=128, seed=108),
+]
+
+
+def test_batched_sweeps_match_oracle(env):
+    """Three batched sweeps (interface FFTs, chains, Gram, Cholesky,
+    substitution, QR and absorb of every problem in shared launches) against
+    the FP64 oracle's Algorithm 1 passes from the same starting cores, with
+    the tables the oracle derives from each problem's seed and sweep index."""
+    import synth
+    torch, tts = env
+    say("batched sweeps vs oracle")
+    probs = ORACLE_PROBLEMS
+    Xs, Xh = make_inputs(torch, probs)
+    b = tts.Batch(probs)
+    init = [synth.random_cores(p["n"], p["ranks"], 90 + i) for i, p in enumerate(probs)]
+    cb = [[tts.core_to_device(c, "cuda") for c in cs] for cs in init]
+    ref = [[c.copy() for c in cs] for cs in init]
+    for t in range(3):
+        res_b = b.sweep(Xs, cb, residuals=True)
+        for i, p in enumerate(probs):
+            ref[i] = als.sweep(Xh[i], p["n"], ref[i], p["J"], 1e-3, seed=p["seed"], t=t)
+            r_o = als.rel_residual(Xh[i], ref[i])
+            Tb, To = _tt(tts, cb[i], p), als.tt_full(ref[i])
+            d_tt = np.linalg.norm(Tb - To) / np.linalg.norm(To)
+            print("sweep %d problem %d: residual %.6e oracle %.6e, TT rel diff %.2e" % (t, i, res_b[i], r_o, d_tt))
+            assert abs(res_b[i] - r_o) < 1e-4, (t, i, res_b[i], r_o)
+            assert d_tt < 1e-4, (t, i, d_tt)
+
+
 def test_graph_replays_match_eager_sweeps(env):
     """Every replay of the captured sweep is checked against the eager sweep of
     the same index, with eager work and synchronisations in between; the

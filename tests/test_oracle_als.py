@@ -110,3 +110,53 @@ def test_theorem5_one_plus_eps_opt():
         Z = solve.core_unfold2(solve.prox_update(SH, Y, cores[k], lam)).T
         ok += f(Z) <= (1 + eps) * opt
     assert ok / T >= 1 - delta
+
+
+def test_core_change_hand_cases():
+    # The accuracy measure of Sec. 5 (first paragraph): the largest, over the
+    # cores, of ||G_k^(t+1) - G_k^(t)||_F / ||G_k^(t+1)||_F.
+    g = synth.rng(41)
+    old = [g.standard_normal((1, 4, 2)), g.standard_normal((2, 5, 3)), g.standard_normal((3, 4, 1))]
+    assert als.core_change(old, [c.copy() for c in old]) == 0.0
+    # one core doubled: ||2G - G|| / ||2G|| = 1/2 (denominator is the NEW core)
+    new = [c.copy() for c in old]
+    new[1] = 2.0 * old[1]
+    assert abs(als.core_change(old, new) - 0.5) < 1e-15
+    # one core halved: ||G/2 - G|| / ||G/2|| = 1 (with the old core as the
+    # denominator this would read 1/2)
+    new = [c.copy() for c in old]
+    new[2] = 0.5 * old[2]
+    assert abs(als.core_change(old, new) - 1.0) < 1e-15
+    # two cores changed: the measure is their maximum, not their sum
+    new = [c.copy() for c in old]
+    new[0] = 2.0 * old[0]           # 0.5
+    new[2] = -old[2]                # ||-2G|| / ||G|| = 2
+    assert abs(als.core_change(old, new) - 2.0) < 1e-15
+    # a change of one entry by e in a core of unit norm gives e / ||new||
+    unit = [np.zeros((1, 3, 1)), np.zeros((1, 3, 1))]
+    unit[0][0, 0, 0] = 1.0
+    unit[1][0, 1, 0] = 1.0
+    moved = [c.copy() for c in unit]
+    moved[1][0, 2, 0] = 0.75        # ||(0,0,.75)|| / ||(0,1,.75)|| = 0.75 / 1.25
+    assert abs(als.core_change(unit, moved) - 0.6) < 1e-15
+
+
+def test_run_histories_match_single_sweeps():
+    # als.run = repeated Algorithm 1 passes with the tables of pass t, logging
+    # after each pass the exact residual and the core change of that pass.
+    n, R, J, lam, seed, T = [6, 5, 4, 5], [1, 2, 3, 2, 1], 64, 1e-3, 17, 3
+    X, _ = synth.tt_tensor_host(n, R, 1e-2, 42)
+    init = synth.random_cores(n, R, 43)
+    cores, res, chg = als.run(X, n, init, J, lam, seed, T)
+    assert len(res) == T and len(chg) == T
+    cur = [c.copy() for c in init]
+    for t in range(T):
+        nxt = als.sweep(X, n, cur, J, lam, seed=seed, t=t)
+        assert res[t] == als.rel_residual(X, nxt)
+        assert chg[t] == als.core_change(cur, nxt)
+        cur = nxt
+    for a, b in zip(cores, cur):
+        assert np.array_equal(a, b)
+    # the first pass starts from unorthogonalised random cores, so every core
+    # moves; the residual history is that of a converging run
+    assert chg[0] > 0.1 and res[-1] < res[0]

@@ -85,3 +85,52 @@ def test_sweep_wrong_gauge_mutant(monkeypatch):
     # skipping the QR + absorb step leaves H_k without orthonormal columns
     monkeypatch.setattr(solve, "left_orth_absorb", lambda a, b: (a, b))
     _fails(T_so.test_sweep_gauge_makes_interface_orthonormal)
+
+
+def test_core_change_old_denominator_mutant(monkeypatch):
+    from oracle import als
+
+    def bad(old, new):           # divides by the OLD core's norm
+        return max(float(np.linalg.norm(b - a) / np.linalg.norm(a)) for a, b in zip(old, new))
+    monkeypatch.setattr(als, "core_change", bad)
+    _fails(T_als.test_core_change_hand_cases)
+
+
+def test_core_change_sum_mutant(monkeypatch):
+    from oracle import als
+
+    def bad(old, new):           # sums the per-core changes
+        return sum(float(np.linalg.norm(b - a) / np.linalg.norm(b)) for a, b in zip(old, new))
+    monkeypatch.setattr(als, "core_change", bad)
+    _fails(T_als.test_core_change_hand_cases)
+
+
+def test_run_skips_table_redraw_mutant(monkeypatch):
+    from oracle import als
+    orig = als.sweep
+
+    def bad(X, n, cores, J, lam, seed=0, t=0, **kw):   # the tables of pass 0 every pass
+        return orig(X, n, cores, J, lam, seed=seed, t=0, **kw)
+    monkeypatch.setattr(als, "sweep", bad)
+    import oracle.als as mod
+
+    def run_bad(X, n, cores, J, lam, seed, sweeps, interface="cyclic"):
+        res, chg = [], []
+        for t in range(sweeps):
+            new = bad(X, n, cores, J, lam, seed=seed, t=t, interface=interface)
+            chg.append(mod.core_change(cores, new))
+            cores = new
+            res.append(mod.rel_residual(X, cores))
+        return cores, res, chg
+    monkeypatch.setattr(als, "run", run_bad)
+    monkeypatch.setattr(als, "sweep", orig)
+    _fails(T_als.test_run_histories_match_single_sweeps)
+
+
+def test_round_bf16_truncation_mutant(monkeypatch):
+    def bad(A):                  # truncates instead of rounding to nearest even
+        x = np.ascontiguousarray(np.asarray(A, dtype=np.float64).astype(np.float32))
+        b = (x.view(np.uint32) >> np.uint32(16)) << np.uint32(16)
+        return b.view(np.float32).astype(np.float64).reshape(np.shape(A))
+    monkeypatch.setattr(solve, "round_bf16", bad)
+    _fails(T_so.test_round_bf16_pins)

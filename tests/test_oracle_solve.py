@@ -120,3 +120,21 @@ def test_sweep_gauge_makes_interface_orthonormal():
     for r in rec:
         H = sketch.interface_matrix(r["cores_in"], r["k"])
         np.testing.assert_allclose(H.T @ H, np.eye(H.shape[1]), atol=1e-11)
+
+
+def test_round_bf16_pins():
+    from oracle import solve
+    # exact BF16 values are kept; 1 + 2^-8 is a tie between 1 and 1 + 2^-7
+    # and goes to the even mantissa (1); 1 + 3 * 2^-8 ties up to 1 + 2^-6
+    x = np.array([1.0, -2.5, 0.0, 1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -8 + 2.0 ** -20, 3.0e38])
+    want = np.array([1.0, -2.5, 0.0, 1.0, 1 + 2.0 ** -6, 1 + 2.0 ** -7, 2.9980e38])
+    got = solve.round_bf16(x)
+    np.testing.assert_array_equal(got[:6], want[:6])
+    assert abs(got[6] - 3.0e38) <= 2.0 ** -8 * 3.0e38
+    # against torch's float32 -> bfloat16 conversion (round to nearest even)
+    import torch
+    g = np.random.default_rng(5).standard_normal(4000) * 10.0 ** np.random.default_rng(6).integers(-20, 20, 4000)
+    ref = torch.from_numpy(g.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(solve.round_bf16(g), ref)
+    # relative error at most 2^-9 of the FP32 value
+    assert np.all(np.abs(solve.round_bf16(g) - g.astype(np.float32)) <= 2.0 ** -8 * np.abs(g.astype(np.float32)))
