@@ -381,6 +381,34 @@ tt_status tt_batch_sweep(tt_batch batch, const void* const* X, void* const* cons
  * entries receiving the choice per step (0 for k = 0). */
 tt_status tt_batch_autotune(tt_batch batch, const void* const* X, int32_t reps, int64_t* chosen);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under stream capture,
+ * serving loops and harnesses that forbid hipMalloc): tt_residual without a
+ * plan or a workspace.
+ *
+ * Computes ||X - [[G]]||_F / ||X||_F exactly as tt_residual does (same
+ * kernels, same launch shape, so the same value) for the tensor described by
+ * d, n (d mode sizes) and r (d + 1 ranks, r[0] = r[d] = 1, each <= TT_MAX_RANK)
+ * with X in x_dtype and the sums in work_dtype (TT_F64 or TT_F32).  X and the
+ * d FP64 cores (host array of device pointers, core k of shape
+ * (r[k], n[k], r[k+1]), first index fastest) are device memory owned by the
+ * caller; n, r and cores are read during the call only.  Work is enqueued on
+ * hip_stream (a hipStream_t of the current device, NULL for the null stream)
+ * and the call synchronises it to read the result.
+ *
+ * Scratch: the per-wave partials, u(o) (prod n[2..d-1] x r[2] work-type
+ * values) and, when room is left, G_0 x G_1 (n[0] n[1] x r[2]) sit in one
+ * static device array of TT_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends.  The call allocates nothing: no hipMalloc, hipFree or
+ * allocating library call.  Every call on a GPU uses that GPU's array, so
+ * calls that overlap on one GPU (other streams, other host threads) race:
+ * serialise them.  Errors: TT_ERR_ARG / TT_ERR_SHAPE (including a scratch
+ * need above TT_NOALLOC_SCRATCH_BYTES) before any device work; TT_ERR_HIP;
+ * TT_ERR_NONFINITE for a NaN or Inf residual. */
+#define TT_NOALLOC_SCRATCH_BYTES (32 << 20)
+tt_status tt_residual_noalloc(int32_t d, const int64_t* n, const int64_t* r, tt_dtype x_dtype, tt_dtype work_dtype,
+                              const void* X, const void* const* cores, void* hip_stream, double* rel_residual);
+
 #ifdef __cplusplus
 }
 #endif

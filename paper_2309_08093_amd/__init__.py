@@ -413,6 +413,36 @@ class Batch:
         return list(out)
 
 
+def residual_noalloc(X, cores, n, ranks, x_dtype="f32", work_dtype="f32", stream=None):
+    """tt_residual_noalloc: ||X - [[G]]|| / ||X|| with the library's static
+    device scratch (no plan, no workspace, nothing allocated)."""
+    n = [int(x) for x in n]
+    ranks = [int(x) for x in ranks]
+    d = len(n)
+    if len(ranks) != d + 1 or len(cores) != d:
+        raise ValueError("need d + 1 ranks and d cores")
+    if x_dtype not in _DT or work_dtype not in ("f64", "f32"):
+        raise ValueError("bad dtype")
+    if not (isinstance(X, torch.Tensor) and X.device.type == "cuda" and X.is_contiguous()
+            and X.dtype == _TORCH[x_dtype] and X.numel() == int(np.prod(n))):
+        raise ValueError("X must be a contiguous %s device tensor with %d entries" % (x_dtype, int(np.prod(n))))
+    ptrs = []
+    for k, G in enumerate(cores):
+        numel = ranks[k] * n[k] * ranks[k + 1]
+        if not (isinstance(G, torch.Tensor) and G.device.type == "cuda" and G.is_contiguous()
+                and G.dtype == torch.float64 and G.numel() == numel):
+            raise ValueError("core %d must be a contiguous float64 device tensor with %d entries" % (k, numel))
+        ptrs.append(G.data_ptr())
+    arr, keep = _abi.ptr_array(ptrs)
+    if stream is None:
+        stream = torch.cuda.current_stream(X.device)
+    out = ctypes.c_double()
+    check(_lib.tt_residual_noalloc(d, (ctypes.c_int64 * d)(*n), (ctypes.c_int64 * (d + 1))(*ranks), _DT[x_dtype],
+                                   _DT[work_dtype], _ptr(X), arr, ctypes.c_void_p(stream.cuda_stream),
+                                   ctypes.byref(out)), "tt_residual_noalloc")
+    return out.value
+
+
 def sketch_size_bound(s, q, eps=0.5, delta=0.1):
     """Corollary 3 sketch size m for s unknowns per column and q sketched modes."""
     m = ctypes.c_double()

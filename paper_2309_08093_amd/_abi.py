@@ -13,6 +13,7 @@ TT_GRAM_WORK, TT_GRAM_BF16 = 0, 1
 TT_FLAG_SERIAL = 1
 
 MAX_ORDER, MAX_J, MAX_RANK, MAX_S, MAX_N0 = 16, 8192, 16, 180, 4096
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 class PlanDesc(ctypes.Structure):
@@ -77,6 +78,8 @@ SIGNATURES = {
     "tt_batch_sweep": [_vp, _vpp, _vp, ctypes.POINTER(ctypes.c_double)],
     "tt_batch_autotune": [_vp, _vpp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)],
     "tt_batch_sketch_path": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "tt_residual_noalloc": [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                            ctypes.c_int32, ctypes.c_int32, _vp, _vpp, _vp, ctypes.POINTER(ctypes.c_double)],
     "tt_als_run": [_vp, _vp, _vpp, _vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), ctypes.c_void_p],
 }

@@ -251,10 +251,7 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   }
   p->gram_chunks = tt_gram_chunks(p->J);
   // residual work units: (outer tuple, block of 64 i_1), four waves per block
-  int64_t rb = (p->O0 * ((p->n[1] + 63) / 64) + 3) / 4;
-  if (rb > 2048) rb = 2048;
-  if (rb < 1) rb = 1;
-  p->res_waves = 4 * rb;
+  p->res_waves = tt_residual_waves(p->O0, p->n[1]);
 
   const size_t ws = p->wsize();
   const size_t gs = (p->gram_mode == TT_GRAM_BF16) ? 4 : 8;   // Gram partials: FP64 unless BF16 MFMA

@@ -276,6 +276,15 @@ hipError_t dispatch(const tt_plan_s* p, const void* Xv, const CoreDesc& cd) {
 
 }  // namespace
 
+// Waves of the residual pass: one work unit per (outer tuple, block of 64
+// i_1), four waves per unit, at most 2048 units.
+int64_t tt_residual_waves(int64_t O0, int64_t n1) {
+  int64_t rb = (O0 * ((n1 + 63) / 64) + 3) / 4;
+  if (rb > 2048) rb = 2048;
+  if (rb < 1) rb = 1;
+  return 4 * rb;
+}
+
 hipError_t launch_residual(const tt_plan_s* p, const void* X, const CoreDesc& cd) {
   if (p->wdt == TT_F64) {
     if (p->xdt == TT_F64) return dispatch<double, double>(p, X, cd);

@@ -143,6 +143,7 @@ hipError_t launch_qr_core(const tt_plan_s* p, double* G, int64_t m, int64_t rcol
 hipError_t launch_absorb_left(const tt_plan_s* p, double* Gnext, int64_t r, int64_t cols);   // G^R <- R G^R
 hipError_t launch_absorb_right(const tt_plan_s* p, double* Gprev, int64_t rows, int64_t r);  // G^L <- G^L R^T
 hipError_t launch_residual(const tt_plan_s* p, const void* X, const CoreDesc& cd);
+int64_t tt_residual_waves(int64_t O0, int64_t n1);   // waves (and partials) of the residual pass
 hipError_t launch_copy_f64(const tt_plan_s* p, double* dst, const double* src, int64_t count);
 
 #define TT_SKETCH_MAX_WG 4096
