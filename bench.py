@@ -429,21 +429,28 @@ def main():
     entries_per_s = d * N / (ms_per_step * 1e-3)
     xbytes = XBYTES[cfg["xd"]]
 
-    # the data sketches dominate: k >= 1 (d - 1 launches per sweep) and k = 0
-    def roof(cls, kernel):
+    # the data sketches dominate: the k = 0 pass (which also writes the
+    # J x n_0 x n_1 outer sketch when Y_1 is derived from it) and the k >= 2
+    # (or k >= 1) passes, one launch each per sweep
+    src = plan.sketch_sources()
+    fused = src[1] == 0
+    wbytes = 8 if cfg["wd"] == "f64" else 4
+    outer_bytes = J * n[0] * n[1] * wbytes if fused else 0
+
+    def roof(cls, kernel, nbytes):
         ms, cnt = prof[cls]
         if cnt == 0:
             return None
         avg_s = ms / cnt * 1e-3
-        gbps = N * xbytes / avg_s / 1e9
+        gbps = nbytes / avg_s / 1e9
         return {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": stored_traffic(kernel, args.config),
                 "kernel": kernel, "avg_launch_ms": round(ms / cnt, 4), "launches": cnt,
-                "bytes_per_launch": N * xbytes}
+                "bytes_per_launch": nbytes}
 
-    kern_k = sorted(set(plan.sketch_kernel(k) for k in range(1, d)))
-    rfk = roof("sketch_k", "+".join(kern_k))
-    rf0 = roof("sketch_k0", plan.sketch_kernel(0))
+    kern_k = sorted(set(plan.sketch_kernel(k) for k in range(1, d) if src[k] == k))
+    rfk = roof("sketch_k", "+".join(kern_k), N * xbytes)
+    rf0 = roof("sketch_k0", plan.sketch_kernel(0) + ("+outer" if fused else ""), N * xbytes + outer_bytes)
     rf, rf_other = (rfk, rf0) if prof["sketch_k"][0] >= prof["sketch_k0"][0] else (rf0, rfk)
     # per-class times from separate sweeps with every class timed
     n_cls = min(args.steps, 5)
@@ -469,10 +476,14 @@ def main():
         "dtype": cfg["xd"],
         "data": "synthetic",
         "config": {"workload": cfg["desc"], "n": n, "ranks": R, "J": J, "lambda": lam,
-                   "step": "one sweep of Algorithm 1 (%d data-sketch passes over X)" % d,
+                   "step": "one sweep of Algorithm 1 (%d data sketches from %d passes over X)"
+                           % (d, sum(1 for k in range(d) if src[k] == k)),
+                   "sketch_sources": src,
                    "schedule": "serial" if args.serial else "data sketches overlapped on a second stream",
                    "reserved_cus": None if args.serial else args.reserve_cus},
-        "hbm_gbps_sweep": d * N * xbytes / (ms_per_step * 1e-3) / 1e9,
+        "hbm_gbps_sweep": (sum(1 for k in range(d) if src[k] == k) * N * xbytes + 2 * outer_bytes)
+                          / (ms_per_step * 1e-3) / 1e9,
+        "hbm_gbps_sweep_note": "passes over X plus the outer sketch written and read once, per sweep time",
         "wall_s_timed": wall,
         "roofline": rf,
         "roofline_other_sketch": rf_other,
@@ -521,6 +532,24 @@ def main():
                   "frac": round(gbps / HBM_PEAK_GBPS, 4)}
     out["sketch_isolated"] = iso
     del Ytmp
+    if not args.no_isolated:
+        # all d sketches of a sweep alone (tt_sketch_tensor_all): the fused
+        # k = 0 pass, the k >= 2 passes, and the rest (sorts, Y_1 stage, sums)
+        plan.sketch_tensor_all(X)
+        torch.cuda.synchronize()
+        plan.profile(True, ["sketch_k0", "sketch_k", "sketch_aux"])
+        plan.profile_read()
+        for _ in range(5):
+            plan.sketch_tensor_all(X)
+        pr = plan.profile_read()
+        plan.profile(False)
+        k0ms = pr["sketch_k0"][0] / 5
+        out["sketch_all_isolated"] = {
+            "ms_per_call": {c: round(pr[c][0] / 5, 4) for c in ("sketch_k0", "sketch_k", "sketch_aux")},
+            "k0_pass": {"kernel": plan.sketch_kernel(0) + ("+outer" if fused else ""),
+                        "bytes": N * xbytes + outer_bytes,
+                        "GB/s": round((N * xbytes + outer_bytes) / (k0ms * 1e-3) / 1e9, 1),
+                        "frac": round((N * xbytes + outer_bytes) / (k0ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}}
 
     if not args.no_time_to_target:
         print("[bench] time to relative residual 1e-2", file=sys.stderr, flush=True)

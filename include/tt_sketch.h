@@ -90,6 +90,17 @@ typedef struct {
  * plan's stream instead. */
 #define TT_FLAG_SERIAL 1u
 
+/* Data sketches of a sweep (Algorithm 1 draws S once per outer iteration, so
+ * all d sketches share the tables).  When d >= 3 the k = 0 pass over X can
+ * also write the TensorSketch of X over modes 2..d-1 (J x n_0 x n_1 values
+ * of the work type in the workspace), from which Y_1 follows without its own
+ * pass over X.  By default this is done when that intermediate is small,
+ * 2 J n_0 n_1 sizeof(work) <= N sizeof(X) / 2.  TT_FLAG_FUSE asks for it
+ * whenever d >= 3, TT_FLAG_NO_FUSE never (not both).  tt_sketch_tensor(k)
+ * is not affected: it always makes its own pass. */
+#define TT_FLAG_FUSE 2u
+#define TT_FLAG_NO_FUSE 4u
+
 /* Create a plan (Algorithm 1, REQUIRE line: tensor shape, TT ranks, m, sigma).
  * Validates the descriptor, computes the workspace size the caller must
  * provide (*workspace_bytes), and stores the stream (a hipStream_t, may be
@@ -139,6 +150,20 @@ tt_status tt_plan_set_tables(tt_plan plan, int32_t s, const int32_t* h, const in
  * Y[(sum_{s!=k} h_s(i_s)) mod J, i_k].  X: device, x_dtype, N entries.
  * Y: device, work type, J x n_k column-major, fully overwritten. */
 tt_status tt_sketch_tensor(tt_plan plan, const void* X, int32_t k, void* Y);
+
+/* All d data sketches of the current sweep's tables, Y_k = S_{-k} A_(k)^T
+ * for k = 0..d-1 ((lrtt_sub4), Algorithm 1's sketches of one outer
+ * iteration), with as few passes over X as the plan allows (TT_FLAG_FUSE).
+ * Yall: device, work type; Y_k is J x n_k column-major at element offset
+ * J (n_0 + ... + n_{k-1}); fully overwritten.  Same errors as
+ * tt_sketch_tensor. */
+tt_status tt_sketch_tensor_all(tt_plan plan, const void* X, void* Yall);
+
+/* How tt_sketch_tensor_all and tt_als_sweep obtain each Y_k (host query, no
+ * device work): src[k] = k when Y_k takes its own pass over X, src[k] = j != k
+ * when it is derived from an intermediate written by the pass of mode j.
+ * src: host array of d entries. */
+tt_status tt_plan_sketch_sources(tt_plan plan, int32_t* src);
 
 /* Interface sketch SH_k = S_{-k} (G_{>k}^T (x) G_{<k}) (Theorem 1 and 2,
  * Sec. 3): per-core CountSketch along mode 2, length-J FFT, slice-wise
@@ -197,7 +222,7 @@ tt_status tt_plan_set_overlap(tt_plan plan, int32_t reserved_cus);
  * classes you need.  Classes: */
 #define TT_PROF_SKETCH0 0    /* data sketch main kernel, k = 0 (bucket gather) */
 #define TT_PROF_SKETCHK 1    /* data sketch main kernel, k >= 1 (LDS buckets) */
-#define TT_PROF_SKETCH_AUX 2 /* data sketch key tables, bucket lists, partial sums */
+#define TT_PROF_SKETCH_AUX 2 /* data sketch key tables, bucket lists, partial sums, Y_1 from the outer sketch */
 #define TT_PROF_INTERFACE 3  /* core CountSketch + FFT, chains, face-split + inverse FFT */
 #define TT_PROF_GRAM 4       /* MFMA Gram / right-hand side */
 #define TT_PROF_SOLVE 5      /* FP64 partial sums, Cholesky, substitution */

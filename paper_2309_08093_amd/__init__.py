@@ -50,7 +50,7 @@ class Plan:
     tensor) and runs on a HIP stream (torch's current stream by default)."""
 
     def __init__(self, n, ranks, J, lam, seed=0, x_dtype="f32", work_dtype="f32", gram="work",
-                 device="cuda", stream=None, serial=False):
+                 device="cuda", stream=None, serial=False, fuse=None):
         self.n = [int(x) for x in n]
         self.ranks = [int(x) for x in ranks]
         self.d = len(self.n)
@@ -64,8 +64,10 @@ class Plan:
             raise ValueError("ranks must have d+1 entries")
         self._n_arr = (ctypes.c_int64 * self.d)(*self.n)
         self._r_arr = (ctypes.c_int64 * (self.d + 1))(*self.ranks)
+        flags = (_abi.TT_FLAG_SERIAL if serial else 0) | \
+            {None: 0, True: _abi.TT_FLAG_FUSE, False: _abi.TT_FLAG_NO_FUSE}[fuse]
         desc = _abi.PlanDesc(self.d, self._n_arr, self._r_arr, self.J, self.lam, int(seed) & (2 ** 64 - 1),
-                             _DT[x_dtype], _DT[work_dtype], _GRAM[gram], _abi.TT_FLAG_SERIAL if serial else 0)
+                             _DT[x_dtype], _DT[work_dtype], _GRAM[gram], flags)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
@@ -164,6 +166,28 @@ class Plan:
         self._check_work(Y, self.J * self.n[k], "Y")
         check(_lib.tt_sketch_tensor(self._h, _ptr(X), int(k), _ptr(Y)), "tt_sketch_tensor")
         return Y
+
+    def sketch_tensor_all(self, X, Yall=None):
+        """All d data sketches of the current sweep; returns [Y_0, ..., Y_{d-1}]
+        as views of one buffer (Y_k flat J x n_k, column-major)."""
+        self._check_X(X)
+        total = self.J * sum(self.n)
+        if Yall is None:
+            Yall = torch.empty(total, dtype=self.wdtype, device=self.device)
+        self._check_work(Yall, total, "Yall")
+        check(_lib.tt_sketch_tensor_all(self._h, _ptr(X), _ptr(Yall)), "tt_sketch_tensor_all")
+        out, off = [], 0
+        for nk in self.n:
+            out.append(Yall[off:off + self.J * nk])
+            off += self.J * nk
+        return out
+
+    def sketch_sources(self):
+        """src[k] = k if Y_k takes its own pass over X, else the mode whose
+        pass writes the intermediate it comes from."""
+        arr = (ctypes.c_int32 * self.d)()
+        check(_lib.tt_plan_sketch_sources(self._h, arr), "tt_plan_sketch_sources")
+        return list(arr)
 
     def sketch_interface(self, cores, k, SH=None):
         arr, keep = self._cores(cores, skip=k)

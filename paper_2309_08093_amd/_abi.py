@@ -11,6 +11,8 @@ STATUS_NAMES = {0: "TT_OK", 1: "TT_ERR_ARG", 2: "TT_ERR_SHAPE", 3: "TT_ERR_WORKS
 TT_F64, TT_F32, TT_BF16 = 0, 1, 2
 TT_GRAM_WORK, TT_GRAM_BF16 = 0, 1
 TT_FLAG_SERIAL = 1
+TT_FLAG_FUSE = 2
+TT_FLAG_NO_FUSE = 4
 
 MAX_ORDER, MAX_J, MAX_RANK, MAX_S, MAX_N0 = 16, 8192, 16, 180, 4096
 NOALLOC_SCRATCH_BYTES = 32 << 20
@@ -46,6 +48,8 @@ SIGNATURES = {
     "tt_plan_get_tables": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int8)],
     "tt_plan_set_tables": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int8)],
     "tt_sketch_tensor": [_vp, _vp, ctypes.c_int32, _vp],
+    "tt_sketch_tensor_all": [_vp, _vp, _vp],
+    "tt_plan_sketch_sources": [_vp, ctypes.POINTER(ctypes.c_int32)],
     "tt_sketch_interface": [_vp, _vpp, ctypes.c_int32, _vp],
     "tt_prox_solve": [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp],
     "tt_left_orth_absorb": [_vp, _vpp, ctypes.c_int32],

@@ -154,7 +154,9 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   const int d = desc->d;
   if (d < 2 || d > TT_MAX_ORDER) return tt_fail(TT_ERR_SHAPE, "order d=%d outside [2, %d]", d, TT_MAX_ORDER);
   if (!desc->n || !desc->r) return tt_fail(TT_ERR_ARG, "null n or r");
-  if (desc->flags & ~TT_FLAG_SERIAL) return tt_fail(TT_ERR_ARG, "unknown flags");
+  if (desc->flags & ~(TT_FLAG_SERIAL | TT_FLAG_FUSE | TT_FLAG_NO_FUSE)) return tt_fail(TT_ERR_ARG, "unknown flags");
+  if ((desc->flags & TT_FLAG_FUSE) && (desc->flags & TT_FLAG_NO_FUSE))
+    return tt_fail(TT_ERR_ARG, "TT_FLAG_FUSE and TT_FLAG_NO_FUSE together");
   if (desc->x_dtype != TT_F64 && desc->x_dtype != TT_F32 && desc->x_dtype != TT_BF16)
     return tt_fail(TT_ERR_ARG, "bad x_dtype");
   if (desc->work_dtype != TT_F64 && desc->work_dtype != TT_F32) return tt_fail(TT_ERR_ARG, "work_dtype must be F64 or F32");
@@ -249,6 +251,17 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
     const int64_t e = p->n[k] * tt_sketch_slots(p, k, W) * p->J;
     if (e > p->part_entries) p->part_entries = e;
   }
+  // fused k = 0 pass writing the outer sketch (TT_FLAG_FUSE); its Y_1 stage
+  // keeps n_1 x slices partials of J entries
+  bool fuse = false;
+  if (d >= 3 && !(p->flags & TT_FLAG_NO_FUSE)) {
+    const double zo_bytes = (double)p->wsize() * (double)p->J_cap * (double)p->n[0] * (double)p->n[1];
+    fuse = (p->flags & TT_FLAG_FUSE) || 2.0 * zo_bytes <= 0.5 * (double)N * (double)p->xsize();
+  }
+  if (fuse) {
+    const int64_t e = p->n[1] * tt_outer_slices(p) * p->J_cap;
+    if (e > p->part_entries) p->part_entries = e;
+  }
   p->gram_chunks = tt_gram_chunks(p->J);
   // residual work units: (outer tuple, block of 64 i_1), four waves per block
   p->res_waves = tt_residual_waves(p->O0, p->n[1]);
@@ -308,6 +321,8 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
     p->o_foff = take(sizeof(uint32_t) * d * (p->J + 1));
   }
   p->o_pol = take(sizeof(float) * TT_MAX_ORDER * (TT_JPOLICY_FEATURES + TT_JPOLICY_OUTPUTS));
+  // outer sketch of the fused k = 0 pass (J_cap x n_0 x n_1)
+  p->o_zo = fuse ? take(ws * (size_t)p->J_cap * (size_t)p->n[0] * (size_t)p->n[1]) : 0;
   p->ws_need = o;
   p->ws = nullptr;
   p->ws_bytes = 0;
@@ -495,6 +510,41 @@ tt_status tt_sketch_tensor(tt_plan p, const void* X, int32_t k, void* Y) {
   return TT_OK;
 }
 
+tt_status tt_sketch_tensor_all(tt_plan p, const void* X, void* Yall) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (!X || !Yall) return tt_fail(TT_ERR_ARG, "null argument");
+  struct ListsReady {
+    tt_plan p;
+    ~ListsReady() { p->lists_ready = false; }
+  } lists_guard{p};
+  {
+    TTProfScope ps(p, TT_PROF_SKETCH_AUX);
+    TT_HIP_TRY(launch_sweep_sorts(p));
+  }
+  p->lists_ready = true;
+  const bool fused = tt_sketch_fused01(p);
+  char* Yb = static_cast<char*>(Yall);
+  for (int k = 0; k < p->d; ++k) {
+    void* Yk = Yb + p->wsize() * p->J * p->tab_off[k];
+    if (fused && k == 0) {
+      TT_HIP_TRY(launch_sketch_mode0_outer(p, X, Yk));
+    } else if (fused && k == 1) {
+      TT_HIP_TRY(launch_sketch_y1_outer(p, Yk));
+    } else {
+      TT_HIP_TRY(launch_sketch_tensor(p, X, k, Yk));
+    }
+  }
+  return TT_OK;
+}
+
+tt_status tt_plan_sketch_sources(tt_plan p, int32_t* src) {
+  if (!p || !src) return tt_fail(TT_ERR_ARG, "null argument");
+  for (int k = 0; k < p->d; ++k) src[k] = k;
+  if (tt_sketch_fused01(p)) src[1] = 0;
+  return TT_OK;
+}
+
 tt_status tt_sketch_interface(tt_plan p, const void* const* cores, int32_t k, void* SH) {
   tt_status st = check_plan(p);
   if (st) return st;
@@ -572,6 +622,8 @@ tt_status tt_plan_sync_status(tt_plan p) {
   TT_HIP_TRY(hipStreamSynchronize(p->stream));
   TT_HIP_TRY(hipMemsetAsync(p->ws + p->o_status, 0, 64, p->stream));
   if (flags[0] & 1) return tt_fail(TT_ERR_NOT_SPD, "Cholesky of SH^T SH + lambda I failed (not positive definite)");
+  if (flags[0] & 2)
+    return tt_fail(TT_ERR_HIP, "fused data sketch: a wave waited too long for its LDS hand-off (results invalid)");
   return TT_OK;
 }
 
@@ -589,6 +641,7 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
   // ahead on the side stream while the chain of core updates proceeds on the
   // chain stream; both fork from and join back into the plan's stream.
   const bool overlap = !(p->flags & TT_FLAG_SERIAL);
+  const bool fused = tt_sketch_fused01(p);
   char* Yall = p->ws + p->o_Yall;
   StreamRestore restore{p};
   // the bucket and fibre lists of every data sketch of the sweep are built
@@ -614,7 +667,10 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
     p->sketch_cus = (p->reserved_cus > 0 && ncu > p->reserved_cus) ? ncu - p->reserved_cus : 0;
     if ((st = sort_lists())) return st;
     for (int k = 0; k < d; ++k) {
-      const hipError_t e = launch_sketch_tensor(p, X, k, Yall + p->wsize() * p->J * p->tab_off[k]);
+      void* Yk = Yall + p->wsize() * p->J * p->tab_off[k];
+      const hipError_t e = fused && k == 0 ? launch_sketch_mode0_outer(p, X, Yk)
+                           : fused && k == 1 ? launch_sketch_y1_outer(p, Yk)
+                                             : launch_sketch_tensor(p, X, k, Yk);
       if (e != hipSuccess) return tt_fail(TT_ERR_HIP, "data sketch launch failed: %s", hipGetErrorString(e));
       TT_HIP_TRY(hipEventRecord(p->ev_y[k], p->side));
     }
@@ -631,6 +687,13 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
     if (overlap) {
       Y = Yall + p->wsize() * p->J * p->tab_off[k];
       TT_HIP_TRY(hipStreamWaitEvent(p->stream, p->ev_y[k], 0));
+    } else if (fused && k <= 1) {
+      // Y_0 and Y_1 from the one pass, into their slots of the all-mode buffer
+      Y = Yall + p->wsize() * p->J * p->tab_off[k];
+      if (k == 0) {
+        TT_HIP_TRY(launch_sketch_mode0_outer(p, X, Y));
+        TT_HIP_TRY(launch_sketch_y1_outer(p, Yall + p->wsize() * p->J * p->tab_off[1]));
+      }
     } else {
       TT_HIP_TRY(launch_sketch_tensor(p, X, k, Y));
     }

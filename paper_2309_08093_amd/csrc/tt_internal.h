@@ -56,7 +56,7 @@ struct tt_plan_s {
 
   size_t o_tab, o_KI, o_KO, o_cnt, o_hist, o_sortO, o_part, o_chat, o_pre, o_suf, o_SH, o_Y,
       o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_pol, o_gsum, o_resU, o_resH,
-      o_tw;
+      o_tw, o_zo;                  // o_zo: outer sketch of the fused k = 0 pass (0: not fused)
   int64_t tw_J;                // J whose roots of unity the o_tw table holds (0: none)
   // key sorts, slot 0 = outer tuples of the k = 0 sketch, slot k >= 1 =
   // fibres of mode k: keys (o_skeys), per-chunk counts (o_hist), fibre lists
@@ -135,6 +135,12 @@ hipError_t tt_sort_args_outer(const tt_plan_s* p, void* out, int32_t* nb);   // 
 hipError_t launch_outer_sorts_batched(const void* args, const void* src, int32_t nsets, int32_t nblocks, int32_t J,
                                       hipStream_t st);
 hipError_t launch_sketch_tensor(const tt_plan_s* p, const void* X, int k, void* Y);
+// Y_0 and Y_1 from one pass over X: the fused k = 0 pass (Y_0 and the outer
+// sketch in o_zo), then Y_1 from the outer sketch
+hipError_t launch_sketch_mode0_outer(const tt_plan_s* p, const void* X, void* Y0);
+hipError_t launch_sketch_y1_outer(const tt_plan_s* p, void* Y1);
+bool tt_sketch_fused01(const tt_plan_s* p);
+int64_t tt_outer_slices(const tt_plan_s* p);   // workgroups per column of the Y_1 stage
 hipError_t launch_core_fft(const tt_plan_s* p, const CoreDesc& cd, int core_lo, int core_hi, int skip);
 hipError_t launch_interface_from_chat(const tt_plan_s* p, const CoreDesc& cd, int k, void* SH);
 hipError_t launch_gram(const tt_plan_s* p, int k, const void* SH, const void* Y);

@@ -72,6 +72,10 @@ def test_full_size_sketch_sampled_columns(tts, name):
         hs.append(h)
         vs.append(v)
     Xv = X.view(*n[::-1])   # torch dims (i_{d-1}, ..., i_0): i_0 fastest
+    # the sweep's sketches: Y_1 from the outer sketch of the k = 0 pass
+    assert plan.sketch_sources()[:2] == [0, 0]
+    Yall = [y.cpu().numpy().astype(np.float64).reshape(J, n[k], order="F")
+            for k, y in enumerate(plan.sketch_tensor_all(X))]
     for k in range(d):
         assert plan.sketch_kernel(k) == (kernels[0] if k == 0 else kernels[1]), k
         say("mode", k, plan.sketch_kernel(k))
@@ -82,6 +86,9 @@ def test_full_size_sketch_sampled_columns(tts, name):
             nsub[k] = 1
             Yo = sketch.data_sketch(sub, nsub, k, hs, vs, J)[:, 0]
             assert rel(Y[:, c], Yo) < 1e-5, (k, c, rel(Y[:, c], Yo))
+            assert rel(Yall[k][:, c], Yo) < 1e-5, (k, c, rel(Yall[k][:, c], Yo))
+        # every column of the fused result against the per-mode pass
+        assert rel(Yall[k], Y) < 1e-5, (k, rel(Yall[k], Y))
     del X, Xv, plan
     torch.cuda.empty_cache()
 

@@ -160,6 +160,60 @@ def test_data_sketch_float(tts, n, J, xd, wd):
         assert colmax(Y, Yo) < tol, (k, colmax(Y, Yo))
 
 
+# all d sketches of a sweep with the outer sketch of the k = 0 pass forced on
+# (Y_1 derived from it): f64, bf16 with short fibres (lane groups folded),
+# n_0 above the k = 0 chunk, n_0 = 1, n_1 = 1, scalar loads, two vectors per
+# lane, J = 1
+FUSED_CASES = [
+    ([16, 16, 16, 16], 256, "f64", "f64"),
+    ([37, 5, 9, 4], 60, "f32", "f32"),
+    ([64, 8, 8, 8, 8], 3000, "bf16", "f32"),
+    ([7, 300, 5], 1000, "f32", "f32"),
+    ([1030, 3, 2], 50, "f32", "f32"),
+    ([1, 5, 4], 8, "f32", "f32"),
+    ([5, 1, 4], 8, "f64", "f64"),
+    ([37, 12, 11, 13], 40, "f32", "f32"),
+    ([300, 12, 10, 7], 30, "f32", "f32"),
+    ([20, 30, 40, 10], 60, "f32", "f32"),
+    ([12, 9, 7], 1, "f32", "f32"),
+]
+
+
+@pytest.mark.parametrize("n,J,xd,wd", FUSED_CASES)
+def test_sketch_all_fused(tts, n, J, xd, wd):
+    say("sketch all fused", n, J, xd, wd)
+    N = int(np.prod(n))
+    plan = tts.Plan(n, [1] * (len(n) + 1), J, 1e-3, seed=5, x_dtype=xd, work_dtype=wd, fuse=True)
+    assert plan.sketch_sources()[:2] == [0, 0]
+    hs, vs = host_tables(plan)
+    # integer-valued: bit-exact
+    Xi = synth.rng(6).integers(-4, 5, size=N).astype(np.float64)
+    Ys = plan.sketch_tensor_all(to_dev_x(Xi, xd))
+    for k in range(len(n)):
+        Y = Ys[k].cpu().numpy().astype(np.float64).reshape(J, n[k], order="F")
+        Yo = sketch.data_sketch(Xi, n, k, hs, vs, J)
+        assert np.array_equal(Y, Yo), (k, np.abs(Y - Yo).max())
+    # Gaussian: 1e-5 (FP32 work) or 1e-12 (FP64 work), norm-wise and element-wise
+    Xh = synth.rng(7).standard_normal(N)
+    Xo = synth.upcast_host(synth.to_dtype_host(Xh, xd))
+    Ys = plan.sketch_tensor_all(to_dev_x(Xh, xd))
+    tol = 1e-12 if wd == "f64" else 1e-5
+    for k in range(len(n)):
+        Y = Ys[k].cpu().numpy().astype(np.float64).reshape(J, n[k], order="F")
+        Yo = sketch.data_sketch(Xo, n, k, hs, vs, J)
+        assert rel(Y, Yo) < tol and colmax(Y, Yo) < tol, (k, rel(Y, Yo), colmax(Y, Yo))
+
+
+def test_sketch_fusion_rule(tts):
+    say("sketch fusion rule")
+    # O_0 = n_2 ... n_{d-1} = 3600 outer tuples >= 4 J: fused by default
+    assert tts.Plan([100, 10, 60, 60], [1, 1, 1, 1, 1], 500, 1e-3).sketch_sources() == [0, 0, 2, 3]
+    # few outer tuples per bucket: every mode takes its own pass
+    assert tts.Plan([16, 16, 16, 16], [1, 1, 1, 1, 1], 256, 1e-3).sketch_sources() == [0, 1, 2, 3]
+    assert tts.Plan([100, 10, 60, 60], [1, 1, 1, 1, 1], 500, 1e-3, fuse=False).sketch_sources() == [0, 1, 2, 3]
+    assert tts.Plan([30, 40], [1, 3, 1], 64, 1e-3, fuse=True).sketch_sources() == [0, 1]   # d = 2: no outer modes
+
+
 def test_paper_example_via_gpu_sketch(tts):
     # Sec. 2.2 worked example: m = 2, two modes of size 2; a third mode of
     # size 1 plays the unsketched index, one-hot inputs read off S's columns.
@@ -340,10 +394,10 @@ def test_residual_nonfinite_reported(tts, bad):
 
 
 # ------------------------------------------------------------------ full sweeps
-def _run_sweeps(tts, n, R, J, lam, seed, sweeps, xd, wd, noise, init_seed=2, gram="work"):
+def _run_sweeps(tts, n, R, J, lam, seed, sweeps, xd, wd, noise, init_seed=2, gram="work", fuse=None, serial=False):
     Xh, _ = synth.tt_tensor_host(n, R, noise, 1)
     init = synth.random_cores(n, R, init_seed)
-    plan = tts.Plan(n, R, J, lam, seed=seed, x_dtype=xd, work_dtype=wd, gram=gram)
+    plan = tts.Plan(n, R, J, lam, seed=seed, x_dtype=xd, work_dtype=wd, gram=gram, fuse=fuse, serial=serial)
     X = to_dev_x(Xh, xd)
     Xo = synth.upcast_host(synth.to_dtype_host(Xh, xd))
     dc = [tts.core_to_device(c) for c in init]
@@ -507,3 +561,19 @@ def test_video_shaped_steps(tts):
     want = solve.prox_update(SHh, Yh, cores[k], lam)
     print("video prox rel %.3e colmax %.3e" % (rel(out, want), colmax(solve.core_unfold2(out), solve.core_unfold2(want))))
     assert rel(out, want) < 1e-5
+
+
+@pytest.mark.parametrize("serial", [False, True])
+def test_sweeps_fused_sketches(tts, serial):
+    # sweeps whose Y_1 comes from the outer sketch of the k = 0 pass, in the
+    # overlapped and the serial schedule, against the oracle's passes
+    say("sweeps fused serial=%s" % serial)
+    plan, dc, ref, res, res_o, Xo = _run_sweeps(tts, [16] * 4, [1, 3, 3, 3, 1], 256, 1e-3, 17, 4, "f64", "f64", 1e-3,
+                                                fuse=True, serial=serial)
+    assert plan.sketch_sources()[1] == 0
+    assert max(abs(a - b) for a, b in zip(res, res_o)) < 1e-10
+    got = [tts.core_to_host(c, r.shape) for c, r in zip(dc, ref)]
+    assert rel(als.tt_full(got), als.tt_full(ref)) < 1e-9
+    plan, dc, ref, res, res_o, Xo = _run_sweeps(tts, [30, 20, 25, 10], [1, 4, 5, 3, 1], 500, 1e-3, 5, 3, "f32", "f32",
+                                                1e-2, fuse=True, serial=serial)
+    assert max(abs(a - b) for a, b in zip(res, res_o)) < 1e-4
