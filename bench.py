@@ -142,6 +142,63 @@ def warm(plan, X, init, dev, params=None):
     plan.set_sweep(0)
 
 
+def exact_section(cfg, X, init, args, dev):
+    """The exact (unsketched) proximal ALS on the same tensor: ms per sweep,
+    time to relative residual 1e-2, and the two contraction passes over X
+    (the right chain of core 0 and the left interface of core d-1), each
+    timed alone with its algorithmic bytes (X read once plus the first
+    intermediate written)."""
+    import numpy as np
+    import torch
+    import paper_2309_08093_amd as tts
+    n, R = cfg["n"], cfg["r"]
+    d = len(n)
+    N = int(np.prod(n))
+    xb = XBYTES[cfg["xd"]]
+    wb = 8 if cfg["wd"] == "f64" else 4
+    plan = tts.Plan(n, R, cfg["J"], cfg["lam"], seed=args.seed, x_dtype=cfg["xd"], work_dtype=cfg["wd"],
+                    gram=cfg["gram"], device=dev, serial=True, exact=True)
+    cores = [tts.core_to_device(c, dev) for c in init]
+    plan.als_sweep_exact(X, cores)
+    torch.cuda.synchronize()
+    stream = plan.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record(stream)
+    for _ in range(reps):
+        plan.als_sweep_exact(X, cores)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_sweep = e0.elapsed_time(e1) / reps
+    passes = {}
+    for k, name, inter in ((0, "right_chain_k0", N // n[-1] * R[d - 1]), (d - 1, "left_interfaces_k%d" % (d - 1),
+                                                                           N // n[0] * R[1])):
+        plan.exact_rhs(X, cores, k)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            plan.exact_rhs(X, cores, k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        nbytes = N * xb + inter * wb
+        passes[name] = {"ms": round(ms, 4), "bytes": nbytes, "GB/s": round(nbytes / ms / 1e6, 1),
+                        "frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBPS, 4)}
+    cores2 = [tts.core_to_device(c, dev) for c in init]
+    plan.set_sweep(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = []
+    for _ in range(30):
+        hist.append(plan.als_sweep_exact(X, cores2, residual=True))
+        if hist[-1] <= 1e-2:
+            break
+    wall = time.perf_counter() - t0
+    return {"ms_per_sweep": ms_sweep, "passes_over_x": passes,
+            "time_to_rel_residual_1e-2": {"seconds": wall, "sweeps": len(hist), "residuals": hist,
+                                          "reached": bool(hist[-1] <= 1e-2)}}
+
+
 def compare_forms(seed, dev, log):
     """Time to a target relative residual: plain FP32 at fixed J vs mixed
     precision (BF16 X, BF16 MFMA Gram) with the learned sketch-size policy."""
@@ -357,6 +414,7 @@ def main():
                     help="skip the isolated per-mode sketch timings (profile runs of the timed sweeps alone)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the mixed + learned-J vs plain FP32 time-to-target comparison")
+    ap.add_argument("--no-exact", action="store_true", help="skip the exact (unsketched) sweeps")
     ap.add_argument("--cpu-entries", type=int, default=128_000_000)
     ap.add_argument("--overlap", action="store_true",
                     help="time the overlapped schedule (data sketches on a second stream beside the core "
@@ -558,6 +616,10 @@ def main():
         tt = timed_plain(plan, X, cores2, 1e-2, 30)
         tt["form"] = "plain " + cfg["xd"]
         out["time_to_rel_residual_1e-2"] = tt
+
+    if not args.no_exact:
+        print("[bench] exact sweeps", file=sys.stderr, flush=True)
+        out["exact"] = exact_section(cfg, X, init, args, dev)
 
     if not args.no_compare:
         out["mixed_learned_vs_plain"] = compare_forms(args.seed, dev,

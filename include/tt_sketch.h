@@ -101,6 +101,12 @@ typedef struct {
 #define TT_FLAG_FUSE 2u
 #define TT_FLAG_NO_FUSE 4u
 
+/* Workspace for the exact (unsketched) update: tt_exact_rhs, tt_prox_exact,
+ * tt_als_sweep_exact, and the exact fallback sweep of tt_als_run.  Adds two
+ * buffers of max_k R_k n_k ... n_{d-1} and two of the largest right-chain
+ * intermediate (about R N / n_{d-1}) work-type values. */
+#define TT_FLAG_EXACT 8u
+
 /* Create a plan (Algorithm 1, REQUIRE line: tensor shape, TT ranks, m, sigma).
  * Validates the descriptor, computes the workspace size the caller must
  * provide (*workspace_bytes), and stores the stream (a hipStream_t, may be
@@ -181,6 +187,32 @@ tt_status tt_sketch_interface(tt_plan plan, const void* const* cores, int32_t k,
 tt_status tt_prox_solve(tt_plan plan, int32_t k, const void* SH, const void* Y,
                         const void* G_old, void* G_new);
 
+/* Exact proximal update (Sec. 3, (lrtt_sub_prox), whose closed form is (ite)
+ * with S = I): the plan needs TT_FLAG_EXACT (TT_ERR_STATE otherwise).
+ *
+ * tt_exact_rhs: B = A_(k) H_k with H_k = G_{>k}^T (x) G_{<k} (defined under
+ * (lrtt_sub4)), n_k x R_k R_{k+1}, column-major, work type:
+ * B[i + n_k (alpha + R_k beta)].  X is contracted with the cores one mode at
+ * a time (left interface over modes 0..k-1, then modes d-1..k+1): one pass
+ * over X and intermediates of at most about R N / n_i values; H_k is never
+ * formed.  cores: host array of d device pointers (core k unused).
+ *
+ * tt_prox_exact: G_k(2)^new = (A_(k) H_k + lambda G_k(2)^old)
+ * (H_k^T H_k + lambda I)^{-1} with H_k^T H_k = (G_{>k} G_{>k}^T) (x)
+ * (G_{<k}^T G_{<k}) from the cores, FP64 Cholesky and substitution.  G_old =
+ * cores[k]; G_new may alias it.
+ *
+ * tt_als_sweep_exact: one outer iteration of Algorithm 1 with every sketched
+ * subproblem replaced by the exact one (S^T S = I): right-to-left
+ * orthogonalisation, then for k = 0..d-1 the exact update and (k < d-1) QR +
+ * absorb.  In this gauge H_k has orthonormal columns, so H_k^T H_k = I.  The
+ * left interface is carried from one core to the next, so a sweep reads X
+ * twice.  Advances the sweep index like tt_als_sweep; rel_residual as
+ * there. */
+tt_status tt_exact_rhs(tt_plan plan, const void* X, const void* const* cores, int32_t k, void* B);
+tt_status tt_prox_exact(tt_plan plan, const void* X, void* const* cores, int32_t k, void* G_new);
+tt_status tt_als_sweep_exact(tt_plan plan, const void* X, void* const* cores, double* rel_residual);
+
 /* QR step of Algorithm 1's inner loop for k < d-1: [Q,R] = qr(G_k^L) by FP64
  * Householder with diag(R) >= 0; G_k <- Q; G_{k+1} <- R G_{k+1}^R.  In place
  * on the device cores (host array of d device pointers). */
@@ -229,8 +261,9 @@ tt_status tt_plan_set_overlap(tt_plan plan, int32_t reserved_cus);
 #define TT_PROF_QR 6         /* FP64 Householder QR and absorb */
 #define TT_PROF_RESIDUAL 7   /* residual pass */
 #define TT_PROF_TABLES 8     /* hash/sign table generation */
-#define TT_PROF_NCLASS 9
-#define TT_PROF_ALL 0x1ff    /* every class */
+#define TT_PROF_EXACT 9      /* exact update: contractions of X with the cores, assembly */
+#define TT_PROF_NCLASS 10
+#define TT_PROF_ALL 0x3ff    /* every class */
 /* enable: bit mask of the classes to time (bit c for class c, TT_PROF_ALL for
  * all of them); 0 stops measurement and releases its events (after
  * synchronising the plan's stream).  Counts already taken are kept until the
@@ -335,8 +368,12 @@ tt_status tt_plan_fallback_J(tt_plan plan, double eps, double delta, int64_t* J)
  * sweeps are done.  With params == NULL every sweep uses the plan's current
  * J and lambda.  Otherwise the policy chooses (J, lambda) before each sweep
  * from the features above; when a sweep (from the second on) does not lower
- * the previous sweep's residual, the next sweep uses tt_plan_fallback_J
- * (eps = 0.5, delta = 0.1) and the descriptor's lambda.  The residual of every sweep is computed exactly and
+ * the previous sweep's residual, the next sweep is the fallback: an exact
+ * sweep (tt_als_sweep_exact, recorded with J = 0) when the plan has
+ * TT_FLAG_EXACT and the Corollary 3 size (eps = 0.5, delta = 0.1) of some
+ * core update is at least its N / n_k (a sketch no smaller than the
+ * problem), else a sketched sweep at tt_plan_fallback_J; both with the
+ * descriptor's lambda.  The residual of every sweep is computed exactly and
  * read back (synchronising).  residuals, Js, lambdas: host arrays of
  * max_sweeps entries or NULL. */
 typedef struct {

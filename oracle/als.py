@@ -67,6 +67,32 @@ def sweep(X, n, cores, J, lam, seed=0, t=0, tabs=None, interface="cyclic", recor
     return cores
 
 
+def exact_rhs(X, n, cores, k):
+    """A_(k) H_k (n_k x R_k R_{k+1}) with H_k = G_{>k}^T (x) G_{<k} formed
+    explicitly (Sec. 3, under (lrtt_sub4)); tiny sizes only."""
+    return sketch.unfold(X, n, k) @ sketch.interface_matrix(cores, k)
+
+
+def prox_exact(X, n, cores, k, lam):
+    """Minimiser of the unsketched proximal subproblem (lrtt_sub_prox):
+    (ite) with S^T S = I, i.e. the proximal update with SH = H_k and
+    Y = A_(k)^T."""
+    return solve.prox_update(sketch.interface_matrix(cores, k), sketch.unfold(X, n, k).T, cores[k], lam)
+
+
+def sweep_exact(X, n, cores, lam):
+    """One while-pass of Algorithm 1 with every sketched subproblem replaced
+    by the exact one (lrtt_sub_prox): right-to-left orthogonalisation, then for
+    k = 0..d-1 the exact proximal update and, for k < d-1, QR + absorb."""
+    d = len(n)
+    cores = solve.right_orthogonalize(cores)
+    for k in range(d):
+        cores[k] = prox_exact(X, n, cores, k, lam)
+        if k < d - 1:
+            cores[k], cores[k + 1] = solve.left_orth_absorb(cores[k], cores[k + 1])
+    return cores
+
+
 def run(X, n, cores, J, lam, seed, sweeps, interface="cyclic"):
     """``sweeps`` passes; returns (cores, residual history, core-change history)."""
     res, chg = [], []

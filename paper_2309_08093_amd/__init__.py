@@ -50,7 +50,7 @@ class Plan:
     tensor) and runs on a HIP stream (torch's current stream by default)."""
 
     def __init__(self, n, ranks, J, lam, seed=0, x_dtype="f32", work_dtype="f32", gram="work",
-                 device="cuda", stream=None, serial=False, fuse=None):
+                 device="cuda", stream=None, serial=False, fuse=None, exact=False):
         self.n = [int(x) for x in n]
         self.ranks = [int(x) for x in ranks]
         self.d = len(self.n)
@@ -64,7 +64,7 @@ class Plan:
             raise ValueError("ranks must have d+1 entries")
         self._n_arr = (ctypes.c_int64 * self.d)(*self.n)
         self._r_arr = (ctypes.c_int64 * (self.d + 1))(*self.ranks)
-        flags = (_abi.TT_FLAG_SERIAL if serial else 0) | \
+        flags = (_abi.TT_FLAG_SERIAL if serial else 0) | (_abi.TT_FLAG_EXACT if exact else 0) | \
             {None: 0, True: _abi.TT_FLAG_FUSE, False: _abi.TT_FLAG_NO_FUSE}[fuse]
         desc = _abi.PlanDesc(self.d, self._n_arr, self._r_arr, self.J, self.lam, int(seed) & (2 ** 64 - 1),
                              _DT[x_dtype], _DT[work_dtype], _GRAM[gram], flags)
@@ -181,6 +181,37 @@ class Plan:
             out.append(Yall[off:off + self.J * nk])
             off += self.J * nk
         return out
+
+    def exact_rhs(self, X, cores, k, B=None):
+        """A_(k) H_k (n_k x R_k R_{k+1}, column-major, work type) by the exact
+        contraction of X with the cores (plan made with exact=True)."""
+        self._check_X(X)
+        arr, keep = self._cores(cores, skip=k)
+        numel = self.n[k] * self.s(k)
+        if B is None:
+            B = torch.empty(numel, dtype=self.wdtype, device=self.device)
+        self._check_work(B, numel, "B")
+        check(_lib.tt_exact_rhs(self._h, _ptr(X), arr, int(k), _ptr(B)), "tt_exact_rhs")
+        return B
+
+    def prox_exact(self, X, cores, k, G_new=None):
+        """Exact proximal update of core k (G_old = cores[k])."""
+        self._check_X(X)
+        arr, keep = self._cores(cores)
+        if G_new is None:
+            G_new = torch.empty_like(cores[k])
+        self._check_core(G_new, k)
+        check(_lib.tt_prox_exact(self._h, _ptr(X), arr, int(k), _ptr(G_new)), "tt_prox_exact")
+        return G_new
+
+    def als_sweep_exact(self, X, cores, residual=False):
+        """One sweep of exact proximal ALS (every sketch replaced by S = I)."""
+        self._check_X(X)
+        arr, keep = self._cores(cores)
+        out = ctypes.c_double()
+        check(_lib.tt_als_sweep_exact(self._h, _ptr(X), arr, ctypes.byref(out) if residual else None),
+              "tt_als_sweep_exact")
+        return out.value if residual else None
 
     def sketch_sources(self):
         """src[k] = k if Y_k takes its own pass over X, else the mode whose

@@ -13,6 +13,7 @@ TT_GRAM_WORK, TT_GRAM_BF16 = 0, 1
 TT_FLAG_SERIAL = 1
 TT_FLAG_FUSE = 2
 TT_FLAG_NO_FUSE = 4
+TT_FLAG_EXACT = 8
 
 MAX_ORDER, MAX_J, MAX_RANK, MAX_S, MAX_N0 = 16, 8192, 16, 180, 4096
 NOALLOC_SCRATCH_BYTES = 32 << 20
@@ -49,6 +50,9 @@ SIGNATURES = {
     "tt_plan_set_tables": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int8)],
     "tt_sketch_tensor": [_vp, _vp, ctypes.c_int32, _vp],
     "tt_sketch_tensor_all": [_vp, _vp, _vp],
+    "tt_exact_rhs": [_vp, _vp, _vpp, ctypes.c_int32, _vp],
+    "tt_prox_exact": [_vp, _vp, _vpp, ctypes.c_int32, _vp],
+    "tt_als_sweep_exact": [_vp, _vp, _vpp, ctypes.POINTER(ctypes.c_double)],
     "tt_plan_sketch_sources": [_vp, ctypes.POINTER(ctypes.c_int32)],
     "tt_sketch_interface": [_vp, _vpp, ctypes.c_int32, _vp],
     "tt_prox_solve": [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp],
@@ -100,7 +104,8 @@ class RunStats(ctypes.Structure):
 
 SKETCH_PATHS = {0: "k_sketch_mode0", 1: "k_sketch_modek", 2: "k_sketch_gs"}
 BSKETCH_PATHS = {0: "k_bsketch_0", 1: "k_bsketch_k", 2: "k_bsketch_slab"}
-PROF_CLASSES = ["sketch_k0", "sketch_k", "sketch_aux", "interface", "gram", "solve", "qr", "residual", "tables"]
+PROF_CLASSES = ["sketch_k0", "sketch_k", "sketch_aux", "interface", "gram", "solve", "qr", "residual", "tables",
+                "exact"]
 STRING_FUNCS = ["tt_last_error", "tt_version"]
 
 _lib = None

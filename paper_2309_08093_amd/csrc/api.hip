@@ -154,7 +154,8 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   const int d = desc->d;
   if (d < 2 || d > TT_MAX_ORDER) return tt_fail(TT_ERR_SHAPE, "order d=%d outside [2, %d]", d, TT_MAX_ORDER);
   if (!desc->n || !desc->r) return tt_fail(TT_ERR_ARG, "null n or r");
-  if (desc->flags & ~(TT_FLAG_SERIAL | TT_FLAG_FUSE | TT_FLAG_NO_FUSE)) return tt_fail(TT_ERR_ARG, "unknown flags");
+  if (desc->flags & ~(TT_FLAG_SERIAL | TT_FLAG_FUSE | TT_FLAG_NO_FUSE | TT_FLAG_EXACT))
+    return tt_fail(TT_ERR_ARG, "unknown flags");
   if ((desc->flags & TT_FLAG_FUSE) && (desc->flags & TT_FLAG_NO_FUSE))
     return tt_fail(TT_ERR_ARG, "TT_FLAG_FUSE and TT_FLAG_NO_FUSE together");
   if (desc->x_dtype != TT_F64 && desc->x_dtype != TT_F32 && desc->x_dtype != TT_BF16)
@@ -323,6 +324,18 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_pol = take(sizeof(float) * TT_MAX_ORDER * (TT_JPOLICY_FEATURES + TT_JPOLICY_OUTPUTS));
   // outer sketch of the fused k = 0 pass (J_cap x n_0 x n_1)
   p->o_zo = fuse ? take(ws * (size_t)p->J_cap * (size_t)p->n[0] * (size_t)p->n[1]) : 0;
+  // exact update
+  p->o_exphi = p->o_exch = p->o_expart = p->o_exgram = 0;
+  p->ex_phi = p->ex_chain = p->ex_part = 0;
+  if (p->flags & TT_FLAG_EXACT) {
+    tt_exact_sizes(p, &p->ex_phi, &p->ex_chain);
+    const int64_t big = p->ex_phi > p->ex_chain ? p->ex_phi : p->ex_chain;
+    p->ex_part = 8 * big < ((int64_t)1 << 22) ? (8 * big > 4096 ? 8 * big : 4096) : ((int64_t)1 << 22);
+    p->o_exphi = take(ws * 2 * (size_t)p->ex_phi);
+    p->o_exch = take(ws * 2 * (size_t)p->ex_chain);
+    p->o_expart = take(sizeof(double) * (size_t)p->ex_part);
+    p->o_exgram = take(sizeof(double) * 512);
+  }
   p->ws_need = o;
   p->ws = nullptr;
   p->ws_bytes = 0;
@@ -614,6 +627,104 @@ tt_status tt_residual(tt_plan p, const void* X, const void* const* cores, double
   return residual_impl(p, X, cores, rel_residual);
 }
 
+// Phi_k: X contracted over modes 0..k-1 with the cores (ping-pong buffers);
+// *is_x when k = 0 (Phi_0 = X).
+static tt_status exact_phi(tt_plan p, const void* X, const double* const* G, int k, const void** phi, bool* is_x) {
+  const void* cur = X;
+  bool cur_x = true;
+  char* bufs[2] = {p->ws + p->o_exphi, p->ws + p->o_exphi + p->wsize() * p->ex_phi};
+  for (int i = 0; i < k; ++i) {
+    TT_HIP_TRY(launch_exact_left(p, cur, cur_x, i, G[i], bufs[i & 1]));
+    cur = bufs[i & 1];
+    cur_x = false;
+  }
+  *phi = cur;
+  *is_x = cur_x;
+  return TT_OK;
+}
+
+static tt_status check_exact(tt_plan p, const void* X, const void* const* cores, int32_t k) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (!p->o_exphi) return tt_fail(TT_ERR_STATE, "the plan was created without TT_FLAG_EXACT");
+  if (!X) return tt_fail(TT_ERR_ARG, "null X");
+  if (k < 0 || k >= p->d) return tt_fail(TT_ERR_ARG, "k=%d out of range", k);
+  return check_cores(p, cores);
+}
+
+tt_status tt_exact_rhs(tt_plan p, const void* X, const void* const* cores, int32_t k, void* B) {
+  tt_status st = check_exact(p, X, cores, k);
+  if (st) return st;
+  if (!B) return tt_fail(TT_ERR_ARG, "null B");
+  const double* const* G = reinterpret_cast<const double* const*>(cores);
+  const void* phi;
+  bool is_x;
+  if ((st = exact_phi(p, X, G, k, &phi, &is_x))) return st;
+  const void* Bc = nullptr;
+  TT_HIP_TRY(launch_exact_right(p, phi, is_x, k, G, &Bc));
+  TT_HIP_TRY(launch_exact_rhs_out(p, k, Bc, B));
+  return TT_OK;
+}
+
+tt_status tt_prox_exact(tt_plan p, const void* X, void* const* cores, int32_t k, void* G_new) {
+  tt_status st = check_exact(p, X, cores, k);
+  if (st) return st;
+  if (!G_new) return tt_fail(TT_ERR_ARG, "null G_new");
+  const double* const* G = reinterpret_cast<const double* const*>(cores);
+  const CoreDesc cd = make_desc(p, cores);
+  const void* phi;
+  bool is_x;
+  const void* Bc = nullptr;
+  {
+    TTProfScope ps(p, TT_PROF_EXACT);
+    if ((st = exact_phi(p, X, G, k, &phi, &is_x))) return st;
+    TT_HIP_TRY(launch_exact_right(p, phi, is_x, k, G, &Bc));
+    TT_HIP_TRY(launch_exact_grams(p, cd, k));
+    TT_HIP_TRY(launch_exact_assemble(p, k, Bc, true));
+  }
+  TTProfScope ps(p, TT_PROF_SOLVE);
+  TT_HIP_TRY(launch_prox_from_gsum(p, k, G[k], static_cast<double*>(G_new)));
+  return TT_OK;
+}
+
+tt_status tt_als_sweep_exact(tt_plan p, const void* X, void* const* cores, double* rel_residual) {
+  tt_status st = check_exact(p, X, cores, 0);
+  if (st) return st;
+  double* const* G = reinterpret_cast<double* const*>(cores);
+  const int d = p->d;
+  for (int k = d - 1; k >= 1; --k)
+    if ((st = right_orth(p, G, k))) return st;
+  const void* phi = X;
+  bool is_x = true;
+  char* bufs[2] = {p->ws + p->o_exphi, p->ws + p->o_exphi + p->wsize() * p->ex_phi};
+  for (int k = 0; k < d; ++k) {
+    {
+      const void* Bc = nullptr;
+      {
+        TTProfScope ps(p, TT_PROF_EXACT);
+        TT_HIP_TRY(launch_exact_right(p, phi, is_x, k, G, &Bc));
+        // cores left of k left-orthonormal, right of k right-orthonormal: H_k^T H_k = I
+        TT_HIP_TRY(launch_exact_assemble(p, k, Bc, false));
+      }
+      TTProfScope ps(p, TT_PROF_SOLVE);
+      TT_HIP_TRY(launch_prox_from_gsum(p, k, G[k], G[k]));
+    }
+    if (k < d - 1) {
+      if ((st = left_orth(p, G, k))) return st;
+      TTProfScope ps(p, TT_PROF_EXACT);
+      TT_HIP_TRY(launch_exact_left(p, phi, is_x, k, G[k], bufs[k & 1]));
+      phi = bufs[k & 1];
+      is_x = false;
+    }
+  }
+  if ((st = tt_sweep_end(p))) return st;
+  if (rel_residual) {
+    if ((st = residual_impl(p, X, cores, rel_residual))) return st;
+    return tt_plan_sync_status(p);
+  }
+  return TT_OK;
+}
+
 tt_status tt_plan_sync_status(tt_plan p) {
   tt_status st = check_plan(p);
   if (st) return st;
@@ -795,7 +906,19 @@ tt_status tt_als_run(tt_plan p, const void* X, void* const* cores, const float* 
   stats->residual = 1.0;
   double prev = 1.0, drop = 0.0;
   bool fallback = false;
+  // the exact sweep replaces the sketched fallback when the plan can run it
+  // and the Corollary 3 size of some core update is no smaller than that
+  // update's unsketched problem (N / n_k rows)
+  bool exact_fb = false;
+  if (p->o_exphi) {
+    for (int k = 0; k < p->d; ++k) {
+      double m = 0.0;
+      if ((st = tt_sketch_size_bound(p->r[k] * p->r[k + 1], p->d - 1, 0.5, 0.1, &m))) return st;
+      if (m >= (double)(p->N / p->n[k])) exact_fb = true;
+    }
+  }
   for (int32_t t = 0; t < max_sweeps; ++t) {
+    bool exact = false;
     if (params) {
       int64_t J = p->J;
       double lam = p->lambda;
@@ -803,16 +926,17 @@ tt_status tt_als_run(tt_plan p, const void* X, void* const* cores, const float* 
         if ((st = tt_plan_fallback_J(p, 0.5, 0.1, &J))) return st;
         lam = p->lambda0;
         stats->fallbacks += 1;
+        exact = exact_fb;
       } else if ((st = tt_jpolicy_choose(p, params, t, t == 0 ? 0.0 : drop, J_min, &J, &lam))) {
         return st;
       }
       if (J != p->J || lam != p->lambda)
         if ((st = tt_plan_set_sketch(p, J, lam))) return st;
     }
-    if (Js) Js[t] = p->J;
+    if (Js) Js[t] = exact ? 0 : p->J;
     if (lambdas) lambdas[t] = p->lambda;
     double res = 0.0;
-    if ((st = tt_als_sweep(p, X, cores, &res))) return st;
+    if ((st = exact ? tt_als_sweep_exact(p, X, cores, &res) : tt_als_sweep(p, X, cores, &res))) return st;
     if (residuals) residuals[t] = res;
     stats->sweeps = t + 1;
     stats->residual = res;

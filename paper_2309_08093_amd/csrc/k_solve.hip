@@ -411,22 +411,17 @@ __global__ void k_copy_f64(double* dst, const double* src, int64_t count) {
 
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-template <typename AT>
-hipError_t prox_t(const tt_plan_s* p, int k, const double* G_old, double* G_new) {
+// Cholesky of gsum's s x s block plus lambda I and the blocked substitution
+// of its n_k right-hand-side columns plus lambda G_(2)^T; gsum is row-major
+// s x (s + n_k) in the plan's o_gsum buffer.
+hipError_t solve_from_gsum(const tt_plan_s* p, int k, const double* G_old, double* G_new) {
   const int s = (int)(p->r[k] * p->r[k + 1]);
   const int nk = (int)p->n[k];
   const int ldg = s + nk;
-  const int chunks = (int)tt_gram_chunks(p->J);
   double* Lg = p->at<double>(p->o_minv);
   int32_t* status = p->at<int32_t>(p->o_status);
-  // the split-K partials summed once, every entry in parallel; the solve
-  // kernels then read one FP64 copy
-  double* gsum = p->at<double>(p->o_gsum);
-  const int64_t count = (int64_t)s * ldg;
-  hipLaunchKernelGGL(k_gram_sum<AT>, dim3(nblk(count, 256)), dim3(256), 0, p->stream, p->at<AT>(p->o_gram), chunks,
-                     count, gsum);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  const double* gsum = p->at<double>(p->o_gsum);
+  hipError_t e;
   const size_t np = (size_t)s * (s + 1) / 2;
   const size_t lds1 = tt_chol_lds_bytes(s);
   if ((e = tt_allow_lds(k_chol_blk, lds1)) != hipSuccess) return e;
@@ -446,10 +441,31 @@ hipError_t prox_t(const tt_plan_s* p, int k, const double* G_old, double* G_new)
   return hipGetLastError();
 }
 
+template <typename AT>
+hipError_t prox_t(const tt_plan_s* p, int k, const double* G_old, double* G_new) {
+  const int s = (int)(p->r[k] * p->r[k + 1]);
+  const int nk = (int)p->n[k];
+  const int ldg = s + nk;
+  const int chunks = (int)tt_gram_chunks(p->J);
+  // the split-K partials summed once, every entry in parallel; the solve
+  // kernels then read one FP64 copy
+  double* gsum = p->at<double>(p->o_gsum);
+  const int64_t count = (int64_t)s * ldg;
+  hipLaunchKernelGGL(k_gram_sum<AT>, dim3(nblk(count, 256)), dim3(256), 0, p->stream, p->at<AT>(p->o_gram), chunks,
+                     count, gsum);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return solve_from_gsum(p, k, G_old, G_new);
+}
+
 }  // namespace
 
 size_t tt_chol_lds_bytes(int64_t s) { return (size_t)(s * (s + 1) / 2 + kCholExtra) * sizeof(double); }
 int64_t tt_chol_out_doubles(int64_t s) { return s * (s + 1) / 2 + ((s + kBS - 1) / kBS) * kBS * kBS; }
+
+hipError_t launch_prox_from_gsum(const tt_plan_s* p, int k, const double* G_old, double* G_new) {
+  return solve_from_gsum(p, k, G_old, G_new);
+}
 
 hipError_t launch_prox_from_gram(const tt_plan_s* p, int k, const double* G_old, double* G_new) {
   // FP32 partials only under TT_GRAM_BF16 (FP32 MFMA accumulation)

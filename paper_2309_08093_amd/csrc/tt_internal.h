@@ -57,6 +57,11 @@ struct tt_plan_s {
   size_t o_tab, o_KI, o_KO, o_cnt, o_hist, o_sortO, o_part, o_chat, o_pre, o_suf, o_SH, o_Y,
       o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_pol, o_gsum, o_resU, o_resH,
       o_tw, o_zo;                  // o_zo: outer sketch of the fused k = 0 pass (0: not fused)
+  // exact update (TT_FLAG_EXACT; 0 otherwise): two left-interface buffers of
+  // ex_phi work-type values, two right-chain buffers of ex_chain, ex_part FP64
+  // slice partials, the two Gram factors (2 x 256 doubles)
+  size_t o_exphi, o_exch, o_expart, o_exgram;
+  int64_t ex_phi, ex_chain, ex_part;
   int64_t tw_J;                // J whose roots of unity the o_tw table holds (0: none)
   // key sorts, slot 0 = outer tuples of the k = 0 sketch, slot k >= 1 =
   // fibres of mode k: keys (o_skeys), per-chunk counts (o_hist), fibre lists
@@ -135,6 +140,14 @@ hipError_t tt_sort_args_outer(const tt_plan_s* p, void* out, int32_t* nb);   // 
 hipError_t launch_outer_sorts_batched(const void* args, const void* src, int32_t nsets, int32_t nblocks, int32_t J,
                                       hipStream_t st);
 hipError_t launch_sketch_tensor(const tt_plan_s* p, const void* X, int k, void* Y);
+// exact update (k_exact.hip)
+void tt_exact_sizes(const tt_plan_s* p, int64_t* phi, int64_t* chain);
+hipError_t launch_exact_left(const tt_plan_s* p, const void* phi_k, bool is_x, int k, const double* Gk, void* phi_next);
+hipError_t launch_exact_right(const tt_plan_s* p, const void* phi_k, bool is_x, int k, const double* const* G,
+                              const void** result);
+hipError_t launch_exact_grams(const tt_plan_s* p, const CoreDesc& cd, int k);
+hipError_t launch_exact_assemble(const tt_plan_s* p, int k, const void* Bc, bool use_grams);
+hipError_t launch_exact_rhs_out(const tt_plan_s* p, int k, const void* Bc, void* B);
 // Y_0 and Y_1 from one pass over X: the fused k = 0 pass (Y_0 and the outer
 // sketch in o_zo), then Y_1 from the outer sketch
 hipError_t launch_sketch_mode0_outer(const tt_plan_s* p, const void* X, void* Y0);
@@ -145,6 +158,8 @@ hipError_t launch_core_fft(const tt_plan_s* p, const CoreDesc& cd, int core_lo, 
 hipError_t launch_interface_from_chat(const tt_plan_s* p, const CoreDesc& cd, int k, void* SH);
 hipError_t launch_gram(const tt_plan_s* p, int k, const void* SH, const void* Y);
 hipError_t launch_prox_from_gram(const tt_plan_s* p, int k, const double* G_old, double* G_new);
+// the solve alone, from [M | B] already in o_gsum (row-major s x (s + n_k))
+hipError_t launch_prox_from_gsum(const tt_plan_s* p, int k, const double* G_old, double* G_new);
 hipError_t launch_qr_core(const tt_plan_s* p, double* G, int64_t m, int64_t rcols, int64_t rs, int64_t cs);
 hipError_t launch_absorb_left(const tt_plan_s* p, double* Gnext, int64_t r, int64_t cols);   // G^R <- R G^R
 hipError_t launch_absorb_right(const tt_plan_s* p, double* Gprev, int64_t rows, int64_t r);  // G^L <- G^L R^T

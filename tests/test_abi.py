@@ -78,7 +78,7 @@ def test_valid_plan_reports_workspace(abi):
     (dict(n=[4, 4, 4], r=[1, 2, 2, 1], lam=-1.0), "TT_ERR_ARG"),
     (dict(n=[4, 4, 4], r=[1, 2, 2, 1], lam=float("nan")), "TT_ERR_ARG"),
     (dict(n=[4, 4, 4], r=[1, 2, 2, 1], gram=1, w=0), "TT_ERR_ARG"),              # BF16 Gram needs F32 work
-    (dict(n=[4, 4, 4], r=[1, 2, 2, 1], flags=8), "TT_ERR_ARG"),                  # unknown flag bit
+    (dict(n=[4, 4, 4], r=[1, 2, 2, 1], flags=16), "TT_ERR_ARG"),                 # unknown flag bit
     (dict(n=[4, 4, 4], r=[1, 2, 2, 1], flags=6), "TT_ERR_ARG"),                  # FUSE with NO_FUSE
     (dict(n=[5000, 4], r=[1, 4, 1]), "TT_ERR_SHAPE"),                            # n_0 > TT_MAX_N0
 ])

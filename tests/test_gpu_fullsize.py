@@ -164,3 +164,22 @@ def test_full_size_batched_form_matches_single_plans(tts):
         assert abs(res_b[i] - r) <= 1e-4 * r + 1e-9, (i, res_b[i], r)
     del Xs, batch, cores
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_full_size_exact_sweeps(tts, name):
+    """Exact (unsketched) proximal sweeps at full size: from the generating
+    cores on the noise-free tensor the residual stays at the storage
+    rounding; from random cores on the noisy tensor three sweeps reach the
+    noise floor (the residual of the generating cores), within 5 %."""
+    n, R, J, noise, xd, gram, _ = CASES[name]
+    say("full-size exact sweeps", name)
+    X, gen = synth.tt_tensor_device(n, R, noise, SEED, dtype=xd, device="cuda")
+    plan = tts.Plan(n, R, J, 1e-3, seed=SEED, x_dtype=xd, work_dtype="f32", gram=gram, device="cuda", exact=True)
+    floor = plan.residual(X, [tts.core_to_device(c, "cuda") for c in gen])
+    cores = [tts.core_to_device(c, "cuda") for c in synth.random_cores(n, R, SEED + 1)]
+    res = [plan.als_sweep_exact(X, cores, residual=True) for _ in range(3)]
+    print(name, "floor %.6e" % floor, "exact sweeps", res)
+    assert res[-1] <= 1.05 * floor, (res, floor)
+    del X, plan, cores
+    torch.cuda.empty_cache()

@@ -160,3 +160,47 @@ def test_run_histories_match_single_sweeps():
     # the first pass starts from unorthogonalised random cores, so every core
     # moves; the residual history is that of a converging run
     assert chg[0] > 0.1 and res[-1] < res[0]
+
+
+def test_exact_sweep_equals_injective_sketch_and_stacked_lstsq():
+    # (lrtt_sub_prox) three ways: explicit H_k (sweep_exact), an injective
+    # sketch (S^T S = I, als.sweep), and the stacked least squares of the
+    # proof of Theorem 5 per core
+    n, R, lam = [4, 5, 3, 2], [1, 2, 3, 2, 1], 0.05
+    X = synth.rng(44).standard_normal(120)
+    cores0 = synth.random_cores(n, R, 45)
+    got = als.sweep_exact(X, n, cores0, lam)
+    hs, vs, J = injective_tables(n)
+    inj = als.sweep(X, n, cores0, J, lam, tabs=(hs, vs))
+    cores = solve.right_orthogonalize(cores0)
+    for k in range(4):
+        H = sketch.interface_matrix(cores, k)
+        cores[k] = solve.prox_update_stacked(H, sketch.unfold(X, n, k).T, cores[k], lam)
+        if k < 3:
+            cores[k], cores[k + 1] = solve.left_orth_absorb(cores[k], cores[k + 1])
+    for a, b, c in zip(got, inj, cores):
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-11)
+        np.testing.assert_allclose(a, c, rtol=1e-9, atol=1e-11)
+
+
+def test_exact_rhs_by_brute_force():
+    # (A_(k) H_k)(i_k, alpha + R_k beta) = sum over the other indices of
+    # X(i) G_<k(i_<k, alpha) G_>k(beta, i_>k), entry by entry
+    n, R = [3, 4, 2], [1, 2, 3, 1]
+    X = synth.rng(46).standard_normal(24)
+    cores = synth.random_cores(n, R, 47)
+    T = X.reshape(n, order="F")
+    for k in range(3):
+        B = als.exact_rhs(X, n, cores, k)
+        want = np.zeros_like(B)
+        for idx in np.ndindex(*n):
+            left = np.ones((1,))
+            for i in range(k):
+                left = left @ cores[i][:, idx[i], :]
+            right = np.ones((1,))
+            for i in range(2, k, -1):
+                right = cores[i][:, idx[i], :] @ right
+            for a in range(R[k]):
+                for b in range(R[k + 1]):
+                    want[idx[k], a + R[k] * b] += T[idx] * left[a] * right[b]
+        np.testing.assert_allclose(B, want, rtol=1e-12, atol=1e-12)

@@ -134,3 +134,12 @@ def test_round_bf16_truncation_mutant(monkeypatch):
         return b.view(np.float32).astype(np.float64).reshape(np.shape(A))
     monkeypatch.setattr(solve, "round_bf16", bad)
     _fails(T_so.test_round_bf16_pins)
+
+
+def test_exact_rhs_kron_order_mutant(monkeypatch):
+    # the exact right-hand side pinned by brute force catches swapped
+    # Kronecker operands in H_k
+    def bad(cores, k):
+        return np.kron(sketch.left_product(cores, k), sketch.right_product(cores, k).T)
+    monkeypatch.setattr(sketch, "interface_matrix", bad)
+    _fails(T_als.test_exact_rhs_by_brute_force)
