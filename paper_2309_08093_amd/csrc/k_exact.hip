@@ -32,20 +32,21 @@ __device__ __forceinline__ double to_f64(T v) { return (double)v; }
 template <>
 __device__ __forceinline__ double to_f64<uint16_t>(uint16_t v) { return (double)__uint_as_float((uint32_t)v << 16); }
 
-// 4 consecutive values of T (k .. k+3 of one column), as doubles
+// 4 consecutive values of T (k .. k+3 of one column) in their storage type;
+// zero beyond K
 template <typename TT, bool VEC>
-__device__ __forceinline__ void load4(const TT* __restrict__ col, int64_t k, int64_t K, double (&v)[4]) {
+__device__ __forceinline__ void load4(const TT* __restrict__ col, int64_t k, int64_t K, TT (&v)[4]) {
   if constexpr (VEC) {
     typedef TT raw_t __attribute__((ext_vector_type(4)));
     if (k + 3 < K) {
       const raw_t r = *reinterpret_cast<const raw_t*>(col + k);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] = to_f64<TT>(r[e]);
+      for (int e = 0; e < 4; ++e) v[e] = r[e];
       return;
     }
   }
 #pragma unroll
-  for (int e = 0; e < 4; ++e) v[e] = k + e < K ? to_f64<TT>(col[k + e]) : 0.0;
+  for (int e = 0; e < 4; ++e) v[e] = k + e < K ? col[k + e] : (TT)0;
 }
 
 // Out(b, q) = sum_{k < K} G[k + K b] T[k + K q] for b < Rout, q < Q, with the
@@ -54,9 +55,12 @@ __device__ __forceinline__ void load4(const TT* __restrict__ col, int64_t k, int
 // NT tiles of 16 columns; v_mfma_f64_16x16x4f64 with A(row b, k) = G and
 // B(k, column q) = T.  Lane l loads 4 consecutive k of column l % 16 at
 // offset 4 (l / 16) of each 16-value step and feeds them to 4 MFMAs, so a
-// column is read in 64-byte pieces (FP32).  Results: lane l, register r hold
-// row 4 r + l / 16, column l % 16.  S == 1 writes OT directly, else FP64
-// partials part[(s Q + q) R_out + b].
+// column is read in 64-byte pieces (FP32).  The loads of the next step are
+// issued before the MFMAs of the current one, and values stay in their
+// storage type until the MFMA (registers: two load buffers and the
+// accumulators).  Results: lane l, register r hold row 4 r + l / 16, column
+// l % 16.  S == 1 writes OT directly, else FP64 partials
+// part[(s Q + q) R_out + b].
 template <typename TT, typename OT, int NT, bool VEC>
 __global__ __launch_bounds__(256) void k_contract_fast(const TT* __restrict__ T, const double* __restrict__ G,
                                                        OT* __restrict__ out, double* __restrict__ part, int64_t Q,
@@ -72,35 +76,53 @@ __global__ __launch_bounds__(256) void k_contract_fast(const TT* __restrict__ T,
   const int kq = lane >> 4, nl = lane & 15;
   const bool brow = nl < Rout;
   const double* Gcol = G + K * (brow ? nl : 0);
-  doublex4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t kb = kb0; kb < kb1; kb += 16) {
-    const int64_t k = kb + 4 * kq;
-    const int64_t kend = kb1;   // slice end: values beyond it belong to the next slice
-    double a[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) a[e] = (brow && k + e < kend) ? Gcol[k + e] : 0.0;
-    double x[NT][4];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int64_t q = q0 + 16 * t + nl;
-      if (q < Q) {
-        load4<TT, VEC>(T + K * q, k, kend, x[t]);
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) x[t][e] = 0.0;
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], x[t][e], acc[t], 0, 0, 0);
-  }
+  const TT* cols[NT];
+  bool qok[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int64_t q = q0 + 16 * t + nl;
-    if (q >= Q) continue;
+    qok[t] = q < Q;
+    cols[t] = T + K * (qok[t] ? q : 0);
+  }
+  doublex4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+  auto issue = [&](TT (&x)[NT][4], int64_t kb) {
+    const int64_t k = kb + 4 * kq;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if (qok[t]) {
+        load4<TT, VEC>(cols[t], k, kb1, x[t]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[t][e] = (TT)0;
+      }
+    }
+  };
+  auto consume = [&](const TT (&x)[NT][4], int64_t kb) {
+    const int64_t k = kb + 4 * kq;
+    double a[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] = (brow && k + e < kb1) ? Gcol[k + e] : 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], to_f64<TT>(x[t][e]), acc[t], 0, 0, 0);
+  };
+  TT xa[NT][4], xb[NT][4];
+  if (kb0 < kb1) issue(xa, kb0);
+  for (int64_t kb = kb0; kb < kb1; kb += 32) {
+    if (kb + 16 < kb1) issue(xb, kb + 16);
+    consume(xa, kb);
+    if (kb + 16 >= kb1) break;
+    if (kb + 32 < kb1) issue(xa, kb + 32);
+    consume(xb, kb + 16);
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (!qok[t]) continue;
+    const int64_t q = q0 + 16 * t + nl;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int b = 4 * r + kq;
@@ -115,13 +137,14 @@ __global__ __launch_bounds__(256) void k_contract_fast(const TT* __restrict__ T,
 
 // Out(m, a) = sum_{kk < n R_in} T[m + M kk] G[a + R_out kk] for a < R_out
 // (contraction of the slowest mode and the trailing rank), with the kk range
-// of slice blockIdx.y.  Lanes run along m (coalesced); the core values are
-// the same for the whole wave.  RB bounds R_out.  S == 1 writes OT directly,
-// else FP64 partials part[(s R_out + a) M + m].
+// of slice blockIdx.y.  Lanes run along m (coalesced), U loads in flight per
+// lane; the core values are the same for the whole wave.  RB bounds R_out.
+// S == 1 writes OT directly, else FP64 partials part[(s R_out + a) M + m].
 template <typename TT, typename OT, int RB>
 __global__ __launch_bounds__(256) void k_contract_slow(const TT* __restrict__ T, const double* __restrict__ G,
                                                        OT* __restrict__ out, double* __restrict__ part, int64_t M,
                                                        int64_t KK, int32_t Rout, int32_t S) {
+  constexpr int U = 16;
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
   const int64_t k0 = (int64_t)s * KK / S, k1 = (int64_t)(s + 1) * KK / S;
@@ -131,17 +154,17 @@ __global__ __launch_bounds__(256) void k_contract_slow(const TT* __restrict__ T,
   if (m < M) {
     const TT* col = T + m;
     int64_t kk = k0;
-    // four loads in flight
-    for (; kk + 4 <= k1; kk += 4) {
-      double x[4];
+    for (; kk + U <= k1; kk += U) {
+      TT x[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = to_f64<TT>(col[M * (kk + u)]);
+      for (int u = 0; u < U; ++u) x[u] = col[M * (kk + u)];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < U; ++u) {
+        const double xv = to_f64<TT>(x[u]);
         const double* g = G + (int64_t)Rout * (kk + u);
 #pragma unroll
         for (int a = 0; a < RB; ++a)
-          if (a < Rout) acc[a] += x[u] * g[a];
+          if (a < Rout) acc[a] += xv * g[a];
       }
     }
     for (; kk < k1; ++kk) {
@@ -275,7 +298,7 @@ template <typename TT, typename WT>
 hipError_t fast_t(const tt_plan_s* p, const void* Tv, const double* G, void* outv, int64_t Q, int64_t K, int32_t Rout) {
   const TT* T = static_cast<const TT*>(Tv);
   WT* out = static_cast<WT*>(outv);
-  constexpr int NT = 4;
+  constexpr int NT = 2;
   const int64_t waves = (Q + 16 * NT - 1) / (16 * NT);
   const int64_t blocks = (waves + 3) / 4;
   const int32_t S = pick_slices(blocks, K, Q * Rout, p->ex_part);
