@@ -199,6 +199,41 @@ def exact_section(cfg, X, init, args, dev):
                                           "reached": bool(hist[-1] <= 1e-2)}}
 
 
+def sparse_section(cfg, args, dev, density=0.01):
+    """O(nnz) sketches of a random sparse tensor of the workload's shape: all d
+    sketches from one pass over the nonzeros (tt_sketch_sparse_all)."""
+    import numpy as np
+    import torch
+    import paper_2309_08093_amd as tts
+    n = cfg["n"]
+    d = len(n)
+    N = int(np.prod(n))
+    nnz = int(N * density)
+    g = torch.Generator(device=dev)
+    g.manual_seed(args.seed + 101)
+    coords = torch.stack([torch.randint(0, ns, (nnz,), generator=g, device=dev, dtype=torch.int32) for ns in n],
+                         dim=1).contiguous()
+    vals = torch.randn(nnz, generator=g, device=dev).to(getattr(torch, {"f64": "float64", "f32": "float32",
+                                                                         "bf16": "bfloat16"}[cfg["xd"]]))
+    plan = tts.Plan(n, [1] * (d + 1), cfg["J"], cfg["lam"], seed=args.seed, x_dtype=cfg["xd"], work_dtype=cfg["wd"],
+                    device=dev)
+    plan.sketch_sparse_all(coords, vals)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record(plan.stream)
+    for _ in range(reps):
+        plan.sketch_sparse_all(coords, vals)
+    e1.record(plan.stream)
+    torch.cuda.synchronize()
+    plan.sync_status()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = nnz * (4 * d + XBYTES[cfg["xd"]])
+    return {"nnz": nnz, "density": density, "ms_all_modes": round(ms, 4), "nonzeros_per_s": nnz / (ms * 1e-3),
+            "sketched_entries_per_s": d * nnz / (ms * 1e-3), "input_GB/s": round(nbytes / ms / 1e6, 1),
+            "note": "one pass over COO coordinates and values; FP64 atomics into the %d sketches" % d}
+
+
 def compare_forms(seed, dev, log):
     """Time to a target relative residual: plain FP32 at fixed J vs mixed
     precision (BF16 X, BF16 MFMA Gram) with the learned sketch-size policy."""
@@ -415,6 +450,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the mixed + learned-J vs plain FP32 time-to-target comparison")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact (unsketched) sweeps")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the sparse-input sketch timing")
     ap.add_argument("--cpu-entries", type=int, default=128_000_000)
     ap.add_argument("--overlap", action="store_true",
                     help="time the overlapped schedule (data sketches on a second stream beside the core "
@@ -616,6 +652,10 @@ def main():
         tt = timed_plain(plan, X, cores2, 1e-2, 30)
         tt["form"] = "plain " + cfg["xd"]
         out["time_to_rel_residual_1e-2"] = tt
+
+    if not args.no_sparse:
+        print("[bench] sparse sketches", file=sys.stderr, flush=True)
+        out["sparse"] = sparse_section(cfg, args, dev)
 
     if not args.no_exact:
         print("[bench] exact sweeps", file=sys.stderr, flush=True)

@@ -165,6 +165,18 @@ tt_status tt_sketch_tensor(tt_plan plan, const void* X, int32_t k, void* Y);
  * tt_sketch_tensor. */
 tt_status tt_sketch_tensor_all(tt_plan plan, const void* X, void* Yall);
 
+/* Data sketch of a sparse tensor in O(nnz) (Sec. 3, complexity remark after
+ * Theorem 3): the same Y_k = S_{-k} A_(k)^T as tt_sketch_tensor, from the
+ * nonzeros only.  COO input: coords device int32, nnz x d row-major
+ * (coords[e d + s] = i_s of nonzero e), vals device x_dtype (nnz values);
+ * repeated coordinates add.  Y: device work type, J x n_k column-major, fully
+ * overwritten (zero for nnz = 0).  tt_sketch_sparse_all reads each nonzero
+ * once and writes every Y_k, at element offset J (n_0 + ... + n_{k-1}) of
+ * Yall.  Sums are FP64.  A coordinate outside [0, n_s) makes its entry be
+ * skipped and the next synchronising call return TT_ERR_ARG. */
+tt_status tt_sketch_sparse(tt_plan plan, int64_t nnz, const int32_t* coords, const void* vals, int32_t k, void* Y);
+tt_status tt_sketch_sparse_all(tt_plan plan, int64_t nnz, const int32_t* coords, const void* vals, void* Yall);
+
 /* How tt_sketch_tensor_all and tt_als_sweep obtain each Y_k (host query, no
  * device work): src[k] = k when Y_k takes its own pass over X, src[k] = j != k
  * when it is derived from an intermediate written by the pass of mode j.

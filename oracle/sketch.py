@@ -177,3 +177,21 @@ def interface_cyclic(cores, k, hs, vs, J):
         # out[b, alpha + beta*rk] += P[bp, alpha] * Q[(b - bp) mod J, beta]
         out += np.einsum("bq,p->bpq", Qs, P[bp]).reshape(J, rk * rk1, order="F")
     return out
+
+
+def data_sketch_sparse(coords, vals, n, k, hs, vs, J):
+    """Y_k from the nonzeros of a COO tensor: nonzero e with indices
+    coords[e] adds prod_{s!=k} v_s(i_s) vals[e] to Y_k[(sum_{s!=k} h_s(i_s)) mod
+    J, i_k] (the definition of the data sketch restricted to stored entries;
+    repeated coordinates add)."""
+    coords = np.asarray(coords, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64)
+    Y = np.zeros((J, int(n[k])))
+    bucket = np.zeros(len(vals), dtype=np.int64)
+    sign = np.ones(len(vals))
+    for s in range(len(n)):
+        if s != k:
+            bucket += np.asarray(hs[s], dtype=np.int64)[coords[:, s]]
+            sign *= np.asarray(vs[s], dtype=np.float64)[coords[:, s]]
+    np.add.at(Y, (bucket % J, coords[:, k]), sign * vals)
+    return Y

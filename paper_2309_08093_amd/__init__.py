@@ -182,6 +182,37 @@ class Plan:
             off += self.J * nk
         return out
 
+    def _check_sparse(self, coords, vals):
+        if not (isinstance(coords, torch.Tensor) and coords.device.type == "cuda" and coords.is_contiguous()
+                and coords.dtype == torch.int32 and coords.dim() == 2 and coords.shape[1] == self.d):
+            raise ValueError("coords must be a contiguous int32 device tensor of shape (nnz, d)")
+        nnz = coords.shape[0]
+        if not (isinstance(vals, torch.Tensor) and vals.device.type == "cuda" and vals.is_contiguous()
+                and vals.dtype == _TORCH[self.x_dtype] and vals.numel() == nnz):
+            raise ValueError("vals must be a contiguous %s device tensor of nnz values" % self.x_dtype)
+        return nnz
+
+    def sketch_sparse(self, coords, vals, k, Y=None):
+        """Y_k of the sparse tensor given by COO coords (nnz x d int32) and vals."""
+        nnz = self._check_sparse(coords, vals)
+        if Y is None:
+            Y = torch.empty(self.J * self.n[k], dtype=self.wdtype, device=self.device)
+        self._check_work(Y, self.J * self.n[k], "Y")
+        check(_lib.tt_sketch_sparse(self._h, nnz, _ptr(coords), _ptr(vals), int(k), _ptr(Y)), "tt_sketch_sparse")
+        return Y
+
+    def sketch_sparse_all(self, coords, vals):
+        """[Y_0, ..., Y_{d-1}] of the sparse tensor, one pass over the nonzeros."""
+        nnz = self._check_sparse(coords, vals)
+        total = self.J * sum(self.n)
+        Yall = torch.empty(total, dtype=self.wdtype, device=self.device)
+        check(_lib.tt_sketch_sparse_all(self._h, nnz, _ptr(coords), _ptr(vals), _ptr(Yall)), "tt_sketch_sparse_all")
+        out, off = [], 0
+        for nk in self.n:
+            out.append(Yall[off:off + self.J * nk])
+            off += self.J * nk
+        return out
+
     def exact_rhs(self, X, cores, k, B=None):
         """A_(k) H_k (n_k x R_k R_{k+1}, column-major, work type) by the exact
         contraction of X with the cores (plan made with exact=True)."""

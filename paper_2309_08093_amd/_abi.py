@@ -50,6 +50,8 @@ SIGNATURES = {
     "tt_plan_set_tables": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int8)],
     "tt_sketch_tensor": [_vp, _vp, ctypes.c_int32, _vp],
     "tt_sketch_tensor_all": [_vp, _vp, _vp],
+    "tt_sketch_sparse": [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int32, _vp],
+    "tt_sketch_sparse_all": [_vp, ctypes.c_int64, _vp, _vp, _vp],
     "tt_exact_rhs": [_vp, _vp, _vpp, ctypes.c_int32, _vp],
     "tt_prox_exact": [_vp, _vp, _vpp, ctypes.c_int32, _vp],
     "tt_als_sweep_exact": [_vp, _vp, _vpp, ctypes.POINTER(ctypes.c_double)],

@@ -324,6 +324,7 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_pol = take(sizeof(float) * TT_MAX_ORDER * (TT_JPOLICY_FEATURES + TT_JPOLICY_OUTPUTS));
   // outer sketch of the fused k = 0 pass (J_cap x n_0 x n_1)
   p->o_zo = fuse ? take(ws * (size_t)p->J_cap * (size_t)p->n[0] * (size_t)p->n[1]) : 0;
+  p->o_spacc = take(sizeof(double) * (size_t)p->J_cap * (size_t)p->tab_off[d]);
   // exact update
   p->o_exphi = p->o_exch = p->o_expart = p->o_exgram = 0;
   p->ex_phi = p->ex_chain = p->ex_part = 0;
@@ -551,6 +552,25 @@ tt_status tt_sketch_tensor_all(tt_plan p, const void* X, void* Yall) {
   return TT_OK;
 }
 
+tt_status tt_sketch_sparse(tt_plan p, int64_t nnz, const int32_t* coords, const void* vals, int32_t k, void* Y) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (nnz < 0 || (nnz > 0 && (!coords || !vals)) || !Y) return tt_fail(TT_ERR_ARG, "null argument or nnz < 0");
+  if (k < 0 || k >= p->d) return tt_fail(TT_ERR_ARG, "k=%d out of range", k);
+  TTProfScope ps(p, TT_PROF_SKETCHK);
+  TT_HIP_TRY(launch_sketch_sparse(p, nnz, coords, vals, k, Y));
+  return TT_OK;
+}
+
+tt_status tt_sketch_sparse_all(tt_plan p, int64_t nnz, const int32_t* coords, const void* vals, void* Yall) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (nnz < 0 || (nnz > 0 && (!coords || !vals)) || !Yall) return tt_fail(TT_ERR_ARG, "null argument or nnz < 0");
+  TTProfScope ps(p, TT_PROF_SKETCHK);
+  TT_HIP_TRY(launch_sketch_sparse(p, nnz, coords, vals, -1, Yall));
+  return TT_OK;
+}
+
 tt_status tt_plan_sketch_sources(tt_plan p, int32_t* src) {
   if (!p || !src) return tt_fail(TT_ERR_ARG, "null argument");
   for (int k = 0; k < p->d; ++k) src[k] = k;
@@ -735,6 +755,7 @@ tt_status tt_plan_sync_status(tt_plan p) {
   if (flags[0] & 1) return tt_fail(TT_ERR_NOT_SPD, "Cholesky of SH^T SH + lambda I failed (not positive definite)");
   if (flags[0] & 2)
     return tt_fail(TT_ERR_HIP, "fused data sketch: a wave waited too long for its LDS hand-off (results invalid)");
+  if (flags[0] & 4) return tt_fail(TT_ERR_ARG, "sparse sketch: a coordinate was outside [0, n_s) (entry skipped)");
   return TT_OK;
 }
 

@@ -61,6 +61,7 @@ struct tt_plan_s {
   // ex_phi work-type values, two right-chain buffers of ex_chain, ex_part FP64
   // slice partials, the two Gram factors (2 x 256 doubles)
   size_t o_exphi, o_exch, o_expart, o_exgram;
+  size_t o_spacc;              // FP64 accumulators of the sparse sketches (J_cap x sum n)
   int64_t ex_phi, ex_chain, ex_part;
   int64_t tw_J;                // J whose roots of unity the o_tw table holds (0: none)
   // key sorts, slot 0 = outer tuples of the k = 0 sketch, slot k >= 1 =
@@ -140,6 +141,9 @@ hipError_t tt_sort_args_outer(const tt_plan_s* p, void* out, int32_t* nb);   // 
 hipError_t launch_outer_sorts_batched(const void* args, const void* src, int32_t nsets, int32_t nblocks, int32_t J,
                                       hipStream_t st);
 hipError_t launch_sketch_tensor(const tt_plan_s* p, const void* X, int k, void* Y);
+// sparse sketch (k_sparse.hip): k >= 0 one mode, k < 0 every mode
+hipError_t launch_sketch_sparse(const tt_plan_s* p, int64_t nnz, const int32_t* coords, const void* vals, int k,
+                                void* Y);
 // exact update (k_exact.hip)
 void tt_exact_sizes(const tt_plan_s* p, int64_t* phi, int64_t* chain);
 hipError_t launch_exact_left(const tt_plan_s* p, const void* phi_k, bool is_x, int k, const double* Gk, void* phi_next);

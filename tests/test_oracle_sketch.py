@@ -237,3 +237,22 @@ def test_lemma2_tail_bound():
         err = np.linalg.norm((S @ A).T @ (S @ B) - A.T @ B) ** 2
         ok += err <= eps0 ** 2 * np.linalg.norm(A) ** 2 * np.linalg.norm(B) ** 2
     assert ok / T >= 1 - delta0
+
+
+def test_sparse_sketch_equals_dense_sketch_of_densified_tensor():
+    # the O(nnz) definition (sum over stored entries, repeated ones adding)
+    # against the dense sketch of the tensor they describe
+    n, J = [7, 5, 6, 4], 23
+    g = synth.rng(61)
+    nnz = 300
+    coords = np.stack([g.integers(0, ns, size=nnz) for ns in n], axis=1)
+    coords[10] = coords[3]                       # a repeated coordinate
+    vals = g.standard_normal(nnz)
+    X = np.zeros(n, order="F")
+    np.add.at(X, tuple(coords.T), vals)
+    hs = [g.integers(0, J, size=ns) for ns in n]
+    vs = [g.choice([-1, 1], size=ns) for ns in n]
+    for k in range(4):
+        got = sketch.data_sketch_sparse(coords, vals, n, k, hs, vs, J)
+        want = sketch.data_sketch(X.reshape(-1, order="F"), n, k, hs, vs, J)
+        np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
