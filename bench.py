@@ -234,6 +234,102 @@ def sparse_section(cfg, args, dev, density=0.01):
             "note": "one pass over COO coordinates and values; FP64 atomics into the %d sketches" % d}
 
 
+# the synthetic workloads of Sec. 5: order 6, n_k = 10 (10^6 entries), FP32,
+# from zero cores, 100 sweeps; name: (tensor, rank, sketch size, sigma)
+PAPER_WORKLOADS = [
+    ("tt6_r5_noise0.1_m150_sigma0.5", ("tt6", 0.1), 5, 150, 0.5),
+    ("tt6_r5_noise0.01_m200_sigma0.5", ("tt6", 0.01), 5, 200, 0.5),
+    ("sinc_r5_m45_sigma0", ("fn", "sinc"), 5, 45, 0.0),
+    ("sinc_r5_m45_sigma0.5", ("fn", "sinc"), 5, 45, 0.5),
+    ("osc_r13_m1000_sigma0.5", ("fn", "osc"), 13, 1000, 0.5),
+]
+
+
+def paper_workloads_section(args, dev, sweeps=100, exact_sweeps=10, runs=10):
+    """Sec. 5 synthetic workloads: per workload, `sweeps` sketched sweeps
+    (TT-TS) from zero cores with per-sweep HIP-event times (median), the final
+    exact residual and core change (the paper's accuracy measure), and
+    `exact_sweeps` unsketched sweeps (TT-ALS) for the same tensor; for the
+    random-TT workloads also `runs` independent runs advanced as one batch
+    with the sweep captured in a hipGraph (the paper averages ten runs)."""
+    import numpy as np
+    import torch
+    import paper_2309_08093_amd as tts
+    import synth
+    n = synth.PAPER_N
+
+    def start(R, lam):
+        # zero cores as in the paper; sigma = 0 starts from Gaussian cores, since
+        # the zero start's first subproblems are singular without the proximal term
+        return synth.random_cores(n, R, 5) if lam == 0.0 else synth.zero_cores(n, R)
+
+    def tensor(src, seed):
+        if src[0] == "tt6":
+            return synth.paper_tt6(seed, src[1])[0]
+        return synth.function_tensor(src[1])
+
+    out = {}
+    for name, src, r, J, lam in PAPER_WORKLOADS:
+        R = synth.function_ranks(r)
+        Xh = tensor(src, args.seed)
+        X = torch.from_numpy(Xh.astype(np.float32)).to(dev)
+        ent = {"ranks": R, "J": J, "sigma": lam}
+        try:
+            plan = tts.Plan(n, R, J, lam, seed=args.seed, device=dev, exact=True)
+            cores = [tts.core_to_device(c, dev) for c in start(R, lam)]
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(sweeps + 1)]
+            torch.cuda.synchronize()
+            ev[0].record(plan.stream)
+            prev = None
+            for t in range(sweeps):
+                if t == sweeps - 1:
+                    prev = [c.clone() for c in cores]
+                    ev[t].record(plan.stream)   # the copy stays out of the last interval
+                plan.als_sweep(X, cores)
+                ev[t + 1].record(plan.stream)
+            torch.cuda.synchronize()
+            per = [ev[t].elapsed_time(ev[t + 1]) for t in range(sweeps)]
+            ent["tt_ts"] = {"sweeps": sweeps, "ms_per_sweep_median": round(float(np.median(per)), 4),
+                            "ms_total": round(float(sum(per)), 3), "rel_residual": plan.residual(X, cores),
+                            "core_change_last_sweep": plan.core_change(prev, cores)}
+            ex = [tts.core_to_device(c, dev) for c in start(R, lam)]
+            exr, exms = [], []
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            for t in range(exact_sweeps):
+                e0.record(plan.stream)
+                plan.als_sweep_exact(X, ex)
+                e1.record(plan.stream)
+                torch.cuda.synchronize()
+                exms.append(e0.elapsed_time(e1))
+            ent["tt_als_exact"] = {"sweeps": exact_sweeps, "ms_per_sweep_median": round(float(np.median(exms)), 4),
+                                   "rel_residual": plan.residual(X, ex)}
+            plan.sync_status()
+        except tts.TTError as e:
+            ent["error"] = str(e)
+        if src[0] == "tt6":
+            probs = [dict(n=n, ranks=R, J=J, lam=lam, seed=args.seed + i) for i in range(runs)]
+            Xs = [torch.from_numpy(tensor(src, args.seed + 100 + i).astype(np.float32)).to(dev) for i in range(runs)]
+            b = tts.Batch(probs, device=dev)
+            b.set_graph(True)
+            cb = [[tts.core_to_device(c, dev) for c in synth.zero_cores(n, R)] for _ in range(runs)]
+            b.sweep(Xs, cb)                      # capture
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(b.stream)
+            for _ in range(sweeps - 2):
+                b.sweep(Xs, cb)
+            e1.record(b.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / (sweeps - 2)
+            res = b.sweep(Xs, cb, residuals=True)
+            ent["batched_runs"] = {"runs": runs, "sweeps": sweeps, "ms_per_sweep_all_runs": round(ms, 4),
+                                   "rel_residual_mean": float(np.mean(res)), "rel_residual_max": float(np.max(res))}
+            del b, Xs, cb
+        out[name] = ent
+        print("[bench] %s %s" % (name, json.dumps(ent)), file=sys.stderr, flush=True)
+    return out
+
+
 def compare_forms(seed, dev, log):
     """Time to a target relative residual: plain FP32 at fixed J vs mixed
     precision (BF16 X, BF16 MFMA Gram) with the learned sketch-size policy."""
@@ -451,6 +547,8 @@ def main():
                     help="skip the mixed + learned-J vs plain FP32 time-to-target comparison")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact (unsketched) sweeps")
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse-input sketch timing")
+    ap.add_argument("--no-paper-workloads", action="store_true",
+                    help="skip the order-6 synthetic workloads of the paper's experiments")
     ap.add_argument("--cpu-entries", type=int, default=128_000_000)
     ap.add_argument("--overlap", action="store_true",
                     help="time the overlapped schedule (data sketches on a second stream beside the core "
@@ -656,6 +754,10 @@ def main():
     if not args.no_sparse:
         print("[bench] sparse sketches", file=sys.stderr, flush=True)
         out["sparse"] = sparse_section(cfg, args, dev)
+
+    if not args.no_paper_workloads:
+        print("[bench] paper's synthetic workloads", file=sys.stderr, flush=True)
+        out["paper_workloads"] = paper_workloads_section(args, dev)
 
     if not args.no_exact:
         print("[bench] exact sweeps", file=sys.stderr, flush=True)

@@ -59,7 +59,7 @@ typedef enum {
   TT_ERR_WORKSPACE = 3,  /* no workspace bound, or smaller than required */
   TT_ERR_HIP = 4,        /* a HIP runtime call or kernel launch failed */
   TT_ERR_NOT_SPD = 5,    /* Cholesky of SH^T SH + lambda I failed */
-  TT_ERR_NONFINITE = 6,  /* NaN/Inf in the residual */
+  TT_ERR_NONFINITE = 6,  /* NaN/Inf in a residual, a core change or a solve */
   TT_ERR_STATE = 7       /* call order violated (e.g. tables never set) */
 } tt_status;
 
@@ -239,6 +239,15 @@ tt_status tt_right_orthogonalize(tt_plan plan, void* const* cores);
  * reconstructing the TT on the fly and accumulating in FP64.  Synchronises;
  * *rel_residual receives the value.  Returns TT_ERR_NONFINITE on NaN/Inf. */
 tt_status tt_residual(tt_plan plan, const void* X, const void* const* cores, double* rel_residual);
+
+/* Relative change of the cores between two iterates, the accuracy measure
+ * the experiments of Sec. 5 stop on: max over k of
+ * ||cur_k - prev_k||_F / ||cur_k||_F, summed in FP64.  prev, cur: d device
+ * pointers each to FP64 cores of the plan's shapes (the layout of
+ * tt_als_sweep); the caller keeps the previous iterate.  Synchronises;
+ * *change receives the value.  TT_ERR_NONFINITE (value still written) when
+ * some cur_k is zero or a core holds NaN/Inf. */
+tt_status tt_core_change(tt_plan plan, const void* const* prev, const void* const* cur, double* change);
 
 /* One outer iteration of Algorithm 1 with the plan's current tables:
  * right-to-left orthogonalisation; then for k = 0..d-1 the interface sketch,

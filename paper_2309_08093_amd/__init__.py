@@ -284,6 +284,14 @@ class Plan:
         check(_lib.tt_residual(self._h, _ptr(X), arr, ctypes.byref(out)), "tt_residual")
         return out.value
 
+    def core_change(self, prev, cur):
+        """max_k ||cur_k - prev_k|| / ||cur_k|| (tt_core_change)."""
+        a, ka = self._cores(prev)
+        b, kb = self._cores(cur)
+        out = ctypes.c_double()
+        check(_lib.tt_core_change(self._h, a, b, ctypes.byref(out)), "tt_core_change")
+        return out.value
+
     def als_sweep(self, X, cores, residual=False):
         self._check_X(X)
         arr, keep = self._cores(cores)

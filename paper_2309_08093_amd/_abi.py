@@ -61,6 +61,7 @@ SIGNATURES = {
     "tt_left_orth_absorb": [_vp, _vpp, ctypes.c_int32],
     "tt_right_orthogonalize": [_vp, _vpp],
     "tt_residual": [_vp, _vp, _vpp, ctypes.POINTER(ctypes.c_double)],
+    "tt_core_change": [_vp, _vpp, _vpp, ctypes.POINTER(ctypes.c_double)],
     "tt_als_sweep": [_vp, _vp, _vpp, ctypes.POINTER(ctypes.c_double)],
     "tt_plan_sync_status": [_vp],
     "tt_plan_profile": [_vp, ctypes.c_int32],

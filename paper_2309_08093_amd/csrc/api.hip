@@ -297,6 +297,7 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_qrR = take(sizeof(double) * p->r_max * p->r_max);
   p->o_status = take(64);
   p->o_res = take(sizeof(double) * (2 * p->res_waves + 8));
+  p->o_chg = take(sizeof(double) * (2 * TT_MAX_ORDER + 8));
   p->o_resU = take(ws * p->O0 * p->r[2]);   // u(o) of the residual, O0 x R_2
   // G_0 x G_1 of the residual (n_0 n_1 x R_2), when it is at most 2^26 entries
   const int64_t nH = p->n[0] * p->n[1] * p->r[2];
@@ -647,6 +648,22 @@ tt_status tt_residual(tt_plan p, const void* X, const void* const* cores, double
   return residual_impl(p, X, cores, rel_residual);
 }
 
+tt_status tt_core_change(tt_plan p, const void* const* prev, const void* const* cur, double* change) {
+  tt_status st = check_plan(p);
+  if (st) return st;
+  if (!change) return tt_fail(TT_ERR_ARG, "null argument");
+  if ((st = check_cores(p, prev)) || (st = check_cores(p, cur))) return st;
+  double* sums = p->at<double>(p->o_chg);
+  double* dout = sums + 2 * TT_MAX_ORDER;
+  TT_HIP_TRY(launch_core_change(p, make_desc(p, prev), make_desc(p, cur), sums, dout));
+  double host = 0.0;
+  TT_HIP_TRY(hipMemcpyAsync(&host, dout, sizeof host, hipMemcpyDeviceToHost, p->stream));
+  TT_HIP_TRY(hipStreamSynchronize(p->stream));
+  *change = host;
+  if (!isfinite(host)) return tt_fail(TT_ERR_NONFINITE, "core change is not finite (a zero or non-finite core)");
+  return TT_OK;
+}
+
 // Phi_k: X contracted over modes 0..k-1 with the cores (ping-pong buffers);
 // *is_x when k = 0 (Phi_0 = X).
 static tt_status exact_phi(tt_plan p, const void* X, const double* const* G, int k, const void** phi, bool* is_x) {
@@ -739,8 +756,11 @@ tt_status tt_als_sweep_exact(tt_plan p, const void* X, void* const* cores, doubl
   }
   if ((st = tt_sweep_end(p))) return st;
   if (rel_residual) {
-    if ((st = residual_impl(p, X, cores, rel_residual))) return st;
-    return tt_plan_sync_status(p);
+    // a failed solve (the status word) explains a non-finite residual, so it
+    // is reported first
+    st = residual_impl(p, X, cores, rel_residual);
+    const tt_status ss = tt_plan_sync_status(p);
+    return ss ? ss : st;
   }
   return TT_OK;
 }
@@ -840,8 +860,11 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
   }
   if ((st = tt_sweep_end(p))) return st;
   if (rel_residual) {
-    if ((st = residual_impl(p, X, cores, rel_residual))) return st;
-    return tt_plan_sync_status(p);
+    // a failed solve (the status word) explains a non-finite residual, so it
+    // is reported first
+    st = residual_impl(p, X, cores, rel_residual);
+    const tt_status ss = tt_plan_sync_status(p);
+    return ss ? ss : st;
   }
   return TT_OK;
 }

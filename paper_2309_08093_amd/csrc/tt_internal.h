@@ -62,6 +62,7 @@ struct tt_plan_s {
   // slice partials, the two Gram factors (2 x 256 doubles)
   size_t o_exphi, o_exch, o_expart, o_exgram;
   size_t o_spacc;              // FP64 accumulators of the sparse sketches (J_cap x sum n)
+  size_t o_chg;                // core change: 2 d partial sums and the result (FP64)
   int64_t ex_phi, ex_chain, ex_part;
   int64_t tw_J;                // J whose roots of unity the o_tw table holds (0: none)
   // key sorts, slot 0 = outer tuples of the k = 0 sketch, slot k >= 1 =
@@ -168,6 +169,8 @@ hipError_t launch_qr_core(const tt_plan_s* p, double* G, int64_t m, int64_t rcol
 hipError_t launch_absorb_left(const tt_plan_s* p, double* Gnext, int64_t r, int64_t cols);   // G^R <- R G^R
 hipError_t launch_absorb_right(const tt_plan_s* p, double* Gprev, int64_t rows, int64_t r);  // G^L <- G^L R^T
 hipError_t launch_residual(const tt_plan_s* p, const void* X, const CoreDesc& cd);
+hipError_t launch_core_change(const tt_plan_s* p, const CoreDesc& prev, const CoreDesc& cur, double* sums,
+                              double* out);
 int64_t tt_residual_waves(int64_t O0, int64_t n1);   // waves (and partials) of the residual pass
 hipError_t launch_copy_f64(const tt_plan_s* p, double* dst, const double* src, int64_t count);
 

@@ -154,6 +154,47 @@ def sinusoid_tensor_host(n, terms=20, noise=1e-2, seed=0):
     return X
 
 
+# ---- the synthetic workloads of Sec. 5 (Experimental Results for Synthetic
+# Data): order 6, n_k = 10, 10^6 entries -------------------------------------
+
+PAPER_N = [10] * 6
+
+
+def paper_tt6(seed, noise, r=5):
+    """First synthetic experiment: a random TT of equal inner ranks r whose
+    core entries are iid N(0, 1), plus iid N(0, noise^2) noise on every entry
+    (noise is an absolute standard deviation: 0.1 or 0.01 in the paper).
+    Returns (X fp64 flat, true cores)."""
+    return tt_tensor_host(PAPER_N, clip_ranks(PAPER_N, tt_ranks(6, r)), noise, seed)
+
+
+def function_points(name, points=10 ** 6):
+    """Sample points of the second synthetic experiment: 'sinc' on [-5, 5]
+    (both ends included) and 'osc' on (0, 1] (x = j / points, j = 1..points:
+    the function has no value at 0)."""
+    if name == "sinc":
+        return np.linspace(-5.0, 5.0, points)
+    if name == "osc":
+        return np.arange(1, points + 1, dtype=np.float64) / points
+    raise ValueError("unknown function %r" % name)
+
+
+def function_tensor(name, points=10 ** 6):
+    """f at the points of ``function_points``, in order, as a flat tensor with
+    i_0 fastest, i.e. folded column-major into 10 x ... x 10:
+    'sinc': sin(pi x) / (pi x) (1 at x = 0); 'osc': sin(4 / x) cos(x^2)."""
+    x = function_points(name, points)
+    if name == "sinc":
+        return np.sinc(x)
+    return np.sin(4.0 / x) * np.cos(x * x)
+
+
+def function_ranks(r, n=PAPER_N):
+    """TT ranks (1, r, ..., r, 1) clipped to what a tensor of shape n admits
+    (R_1 <= n_0, R_{d-1} <= n_{d-1}, ...)."""
+    return clip_ranks(n, tt_ranks(len(n), r))
+
+
 def batched_shapes(count, seed, order=(3, 5), nrange=(20, 60), rrange=(2, 8)):
     """Shapes and ranks of ``count`` independent problems: order uniform in
     [order[0], order[1]], each n_i uniform in nrange, each inner rank uniform
