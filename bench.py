@@ -44,9 +44,64 @@ PROFILE_TAG = {"c1": "16x4_f64", "c2": "200x4_f32", "c3": "64x5_bf16", "c3f32": 
 BATCH = dict(count=256, J=1024, lam=1e-3, noise=1e-3)
 
 
-def cpu_baseline(X, cfg, plan, budget_entries):
-    """FP64 oracle data sketch (numpy, single thread) on a slab of X: the
-    first few indices of the last mode, all modes sketched once."""
+def cpu_info():
+    """Host CPU description from /proc/cpuinfo (first processor) and the
+    affinity mask."""
+    info, first, procs, packages = {}, True, 0, set()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if ":" not in line:
+                    if procs:
+                        first = False
+                    continue
+                key, val = (x.strip() for x in line.split(":", 1))
+                if key == "processor":
+                    procs += 1
+                elif key == "physical id":
+                    packages.add(val)
+                elif first and key in ("vendor_id", "cpu family", "model", "model name", "stepping", "cpu MHz",
+                                       "cache size", "siblings", "cpu cores"):
+                    info[key.replace(" ", "_")] = val
+    except OSError:
+        pass
+    info["logical_cpus"] = procs
+    info["packages"] = len(packages) or None
+    info["cpus_visible"] = len(os.sched_getaffinity(0))
+    return info
+
+
+def cpu_workers():
+    """Oracle workers for the all-core CPU baseline, forked before anything
+    touches the GPU: one per visible CPU, at most 16 (one GPU's share of
+    the host)."""
+    import multiprocessing
+    w = max(1, min(16, len(os.sched_getaffinity(0))))
+    return multiprocessing.get_context("fork").Pool(w), w
+
+
+def _oracle_slab(job):
+    """Worker: the oracle's data sketch of every mode over the slab
+    a <= i_{d-1} < b of the FP64 sample in the file `path`; returns its own
+    seconds."""
+    import numpy as np
+    from oracle import sketch
+    path, n, a, b, hs, vs, J = job
+    inner = int(np.prod(n[:-1]))
+    part = np.array(np.memmap(path, dtype=np.float64, mode="r", offset=8 * a * inner, shape=((b - a) * inner,)))
+    nsl = list(n[:-1]) + [b - a]
+    hs2 = list(hs[:-1]) + [hs[-1][a:b]]
+    vs2 = list(vs[:-1]) + [vs[-1][a:b]]
+    t0 = time.perf_counter()
+    for k in range(len(n)):
+        sketch.data_sketch(part, nsl, k, hs2, vs2, J)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(X, cfg, plan, budget_entries, pool=None, workers=1):
+    """FP64 oracle data sketch (numpy) on a slab of X, the first few indices
+    of the last mode, all modes sketched once: on one core in this process,
+    and split by last-mode index over the worker pool (all cores)."""
     import numpy as np
     import torch
     from oracle import sketch
@@ -56,6 +111,7 @@ def cpu_baseline(X, cfg, plan, budget_entries):
     ns = max(1, min(n[-1], budget_entries // inner))
     slab = X.view(n[-1], inner)[:ns].contiguous()
     Xs = slab.to("cpu", torch.float64).numpy().reshape(-1)
+    del slab
     nsl = list(n[:-1]) + [ns]
     hs, vs = [], []
     for s in range(len(n)):
@@ -65,21 +121,42 @@ def cpu_baseline(X, cfg, plan, budget_entries):
     t0 = time.perf_counter()
     for k in range(len(n)):
         sketch.data_sketch(Xs, nsl, k, hs, vs, plan.J)
-    dt = time.perf_counter() - t0
+    dt1 = time.perf_counter() - t0
     entries = len(n) * Xs.size
-    model = None
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
-    return {"value": entries / dt, "unit": "entries/s", "cores": 1, "kind": "oracle",
-            "sample": "numpy FP64 data sketch of all %d modes over the slab i_%d < %d (%d entries, %.1f s)"
-                      % (len(n), len(n) - 1, ns, Xs.size, dt),
-            "host": {"cpu_model": model, "cpus_visible": len(os.sched_getaffinity(0))}}
+    out = {"value": entries / dt1, "unit": "entries/s", "cores": 1, "kind": "oracle",
+           "sample": "numpy FP64 data sketch of all %d modes over the slab i_%d < %d (%d entries; one core %.1f s)"
+                     % (len(n), len(n) - 1, ns, Xs.size, dt1),
+           "single_core": {"value": entries / dt1, "seconds": dt1},
+           "host": cpu_info()}
+    if pool is not None:
+        # the sample goes to the workers through a memory-backed file; each
+        # worker copies its slab in before its clock starts
+        import tempfile
+        shm_dir = None
+        try:
+            st = os.statvfs("/dev/shm")
+            if st.f_bavail * st.f_frsize >= 2 * Xs.nbytes:
+                shm_dir = "/dev/shm"
+        except OSError:
+            pass
+        fd, path = tempfile.mkstemp(suffix=".f64", dir=shm_dir)
+        try:
+            with os.fdopen(fd, "wb") as f:
+                Xs.tofile(f)
+            jobs = [(path, nsl, a, a + 1, hs, vs, plan.J) for a in range(ns)]
+            t0 = time.perf_counter()
+            per = pool.map(_oracle_slab, jobs, chunksize=1)
+            dtw = time.perf_counter() - t0
+        finally:
+            os.unlink(path)
+        used = min(workers, ns)
+        out.update({"value": entries / dtw, "cores": used,
+                    "sample": out["sample"] + "; the same slab split by i_%d over %d worker processes: %.2f s wall"
+                                              % (len(n) - 1, used, dtw),
+                    "all_cores": {"value": entries / dtw, "seconds": dtw, "workers": used,
+                                  "worker_seconds": round(float(sum(per)), 3),
+                                  "note": "wall time includes each worker's copy of its slab from the shared file"}})
+    return out
 
 
 POLICY_WEIGHTS = os.path.join(ROOT, "paper_2309_08093_amd", "jpolicy_weights.npy")
@@ -566,6 +643,11 @@ def main():
               "per core update); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    # the CPU baseline's workers are forked before torch or HIP is loaded
+    pool, workers = (None, 1)
+    if not args.no_cpu_baseline and args.config != "c4" and not args.probe_traffic:
+        pool, workers = cpu_workers()
+
     import numpy as np
     import torch
     import paper_2309_08093_amd as tts
@@ -606,18 +688,20 @@ def main():
     stream = torch.cuda.current_stream(dev)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs[0].record(stream)
+    for t in range(args.steps):
         plan.als_sweep(X, cores)
-    ev1.record(stream)
+        evs[t + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = plan.profile_read()
     plan.profile(False)
-    ms_total = ev0.elapsed_time(ev1)
-    ms_per_step = ms_total / args.steps
+    ms_total = evs[0].elapsed_time(evs[-1])
+    per_step = [evs[t].elapsed_time(evs[t + 1]) for t in range(args.steps)]
+    ms_per_step = float(np.median(per_step))
     entries_per_s = d * N / (ms_per_step * 1e-3)
     xbytes = XBYTES[cfg["xd"]]
 
@@ -662,6 +746,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "ms_per_step_note": "median of the timed sweeps (HIP events between sweeps); mean %.4f, min %.4f, max %.4f"
+                            % (ms_total / args.steps, min(per_step), max(per_step)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -769,7 +855,10 @@ def main():
 
     if not args.no_cpu_baseline:
         print("[bench] CPU baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(X, cfg, plan, args.cpu_entries)
+        out["cpu_baseline"] = cpu_baseline(X, cfg, plan, args.cpu_entries, pool, workers)
+    if pool is not None:
+        pool.close()
+        pool.join()
     print(json.dumps(out), flush=True)
 
 
