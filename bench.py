@@ -409,7 +409,8 @@ def paper_workloads_section(args, dev, sweeps=100, exact_sweeps=10, runs=10):
 
 def compare_forms(seed, dev, log):
     """Time to a target relative residual: plain FP32 at fixed J vs mixed
-    precision (BF16 X, BF16 MFMA Gram) with the learned sketch-size policy."""
+    precision (BF16 X, BF16 MFMA Gram) with the learned sketch-size policy,
+    whose choices include the unsketched update (J recorded as 0)."""
     import numpy as np
     import torch
     import paper_2309_08093_amd as tts
@@ -426,7 +427,8 @@ def compare_forms(seed, dev, log):
     X16 = X32.to(torch.bfloat16)
     init = synth.random_cores(n, R, seed + 1)
     p32 = tts.Plan(n, R, 3000, 1e-3, seed=seed, x_dtype="f32", work_dtype="f32", device=dev)
-    p16 = tts.Plan(n, R, 8000, 1e-3, seed=seed, x_dtype="bf16", work_dtype="f32", gram="bf16", device=dev)
+    p16 = tts.Plan(n, R, 8000, 1e-3, seed=seed, x_dtype="bf16", work_dtype="f32", gram="bf16", device=dev,
+                   exact=True)
     warm(p32, X32, init, dev)
     warm(p16, X16, init, dev, params=pol.params)
     c = [tts.core_to_device(x, dev) for x in init]
@@ -464,7 +466,8 @@ def compare_forms(seed, dev, log):
         del p
     reached = {J: r["seconds"] for J, r in grid.items() if r["reached"]}
     bestJ = min(reached, key=reached.get) if reached else None
-    p16 = tts.Plan(n, R, 8000, 1e-3, seed=seed, x_dtype="bf16", work_dtype="f32", gram="bf16", device=dev)
+    p16 = tts.Plan(n, R, 8000, 1e-3, seed=seed, x_dtype="bf16", work_dtype="f32", gram="bf16", device=dev,
+                   exact=True)
     pref = tts.Plan(n, R, 3000, 1e-3, seed=seed, x_dtype="f32", work_dtype="f32", device=dev)
     warm(p16, X16, init, dev, params=pol.params)
     c = [tts.core_to_device(x, dev) for x in init]

@@ -342,6 +342,12 @@ const char* tt_version(void);
 #define TT_JPOLICY_OUTPUTS 2
 #define TT_JPOLICY_PARAMS 9026
 #define TT_JPOLICY_MAX_BATCH (1 << 20)
+/* A predicted J at or above TT_JPOLICY_EXACT_J (three times TT_MAX_J)
+ * selects the unsketched update (tt_als_sweep_exact) when the plan has
+ * TT_FLAG_EXACT: a sketch that large is no cheaper than the problem itself.
+ * Training labels encode that choice as TT_JPOLICY_EXACT_LABEL. */
+#define TT_JPOLICY_EXACT_J 24576
+#define TT_JPOLICY_EXACT_LABEL 65536
 /* tt_jpolicy_choose clamps log10 lambda to the range of the training labels */
 #define TT_JPOLICY_LOG10_LAMBDA_MIN (-4.0)
 #define TT_JPOLICY_LOG10_LAMBDA_MAX (-1.0)
@@ -370,8 +376,10 @@ tt_status tt_jpolicy_features(tt_plan plan, int64_t t, double last_drop, float* 
 /* Apply the network to the plan's d feature rows (in the plan's workspace, on
  * its stream; synchronises) and return the sweep's sketch size and lambda:
  * J = the largest of the d predictions, rounded to the nearest product of
- * 2, 3, 5, 7 in [J_min, plan J]; lambda = the prediction of that core,
- * clamped to [10^TT_JPOLICY_LOG10_LAMBDA_MIN, 10^TT_JPOLICY_LOG10_LAMBDA_MAX]. */
+ * 2, 3, 5, 7 in [J_min, plan J], or 0 (the unsketched update) when that
+ * prediction is at least TT_JPOLICY_EXACT_J and the plan has TT_FLAG_EXACT;
+ * lambda = the prediction of that core, clamped to
+ * [10^TT_JPOLICY_LOG10_LAMBDA_MIN, 10^TT_JPOLICY_LOG10_LAMBDA_MAX]. */
 tt_status tt_jpolicy_choose(tt_plan plan, const float* params, int64_t t, double last_drop, int64_t J_min, int64_t* J,
                             double* lambda);
 
@@ -388,7 +396,8 @@ tt_status tt_plan_fallback_J(tt_plan plan, double eps, double delta, int64_t* J)
 /* Run sweeps until the exact relative residual is <= target or max_sweeps
  * sweeps are done.  With params == NULL every sweep uses the plan's current
  * J and lambda.  Otherwise the policy chooses (J, lambda) before each sweep
- * from the features above; when a sweep (from the second on) does not lower
+ * from the features above, J = 0 meaning an exact sweep (tt_als_sweep_exact)
+ * with the chosen lambda; when a sweep (from the second on) does not lower
  * the previous sweep's residual, the next sweep is the fallback: an exact
  * sweep (tt_als_sweep_exact, recorded with J = 0) when the plan has
  * TT_FLAG_EXACT and the Corollary 3 size (eps = 0.5, delta = 0.1) of some

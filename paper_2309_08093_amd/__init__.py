@@ -343,7 +343,8 @@ class Plan:
         return np.frombuffer(out, dtype=np.float32).reshape(self.d, _abi.JPOLICY_FEATURES).copy()
 
     def choose(self, params, t, last_drop, J_min=64):
-        """(J, lambda) the policy network picks for sweep t."""
+        """(J, lambda) the policy network picks for sweep t; J = 0 is the
+        unsketched update (plans with exact=True only)."""
         J = ctypes.c_int64()
         lam = ctypes.c_double()
         check(_lib.tt_jpolicy_choose(self._h, _ptr(params), int(t), float(last_drop), int(J_min), ctypes.byref(J),

@@ -98,6 +98,8 @@ JPOLICY_FEATURES = 8
 JPOLICY_HIDDEN = 64
 JPOLICY_OUTPUTS = 2
 JPOLICY_PARAMS = 9026
+JPOLICY_EXACT_J = 24576        # predictions at or above select the unsketched update
+JPOLICY_EXACT_LABEL = 65536    # label of that choice
 
 
 class RunStats(ctypes.Structure):

@@ -915,7 +915,10 @@ tt_status tt_jpolicy_choose(tt_plan p, const float* params, int64_t t, double la
   const double l10 = (double)out[best * TT_JPOLICY_OUTPUTS + 1] - 3.0;
   if (!isfinite(lnJ) || !isfinite(l10)) return tt_fail(TT_ERR_NONFINITE, "policy output is not finite");
   const int64_t lo = tt_floor_smooth(J_min) < J_min ? tt_round_smooth((double)J_min, J_min, p->J_cap) : J_min;
-  *J = tt_round_smooth(exp(lnJ > 30.0 ? 30.0 : lnJ), lo, tt_floor_smooth(p->J_cap));
+  if (p->o_exphi && lnJ >= log((double)TT_JPOLICY_EXACT_J))
+    *J = 0;   // the unsketched update
+  else
+    *J = tt_round_smooth(exp(lnJ > 30.0 ? 30.0 : lnJ), lo, tt_floor_smooth(p->J_cap));
   // lambda stays within the range of the training labels
   const double lam = pow(10.0, l10 < TT_JPOLICY_LOG10_LAMBDA_MIN ? TT_JPOLICY_LOG10_LAMBDA_MIN
                                    : (l10 > TT_JPOLICY_LOG10_LAMBDA_MAX ? TT_JPOLICY_LOG10_LAMBDA_MAX : l10));
@@ -973,6 +976,9 @@ tt_status tt_als_run(tt_plan p, const void* X, void* const* cores, const float* 
         exact = exact_fb;
       } else if ((st = tt_jpolicy_choose(p, params, t, t == 0 ? 0.0 : drop, J_min, &J, &lam))) {
         return st;
+      } else if (J == 0) {
+        exact = true;     // the policy chose the unsketched update
+        J = p->J;
       }
       if (J != p->J || lam != p->lambda)
         if ((st = tt_plan_set_sketch(p, J, lam))) return st;

@@ -10,11 +10,13 @@ one per core update, all carry it as (ln J* - 7, log10 lambda* + 3), and
 their residual drop is that of the previous sweep, as in tt_als_run):
 
 * "runs" (default): from the problem's start, one run per J of a geometric
-  grid at lambda = 1e-3, each up to a fixed number of sweeps, timed with its
-  residual check after every sweep (as tt_als_run runs).  The target is
-  max(1e-2, 1.5 x the best residual any run reached); J* is the J whose run
-  reaches it first, and the states of that run up to the target are labelled
-  J*.  This is the quantity a run is judged by, the time to a target.
+  grid at lambda = 1e-3, and one run of exact (unsketched) sweeps, each up to
+  a fixed number of sweeps, timed with its residual check after every sweep
+  (as tt_als_run runs).  The target is max(1e-2, 1.5 x the best residual any
+  run reached); J* is the choice whose run reaches it first (the exact run
+  is labelled J = TT_JPOLICY_EXACT_LABEL), and the states of that run up to
+  the target are labelled J*.  This is the quantity a run is judged by, the
+  time to a target.
 * "sweep": starting from the same cores and sweep index, one sweep per J;
   J* maximises that sweep's residual drop per second, lambda* is the best of
   a grid at J*, and the run continues from that sweep.  Greedy: a larger
@@ -224,8 +226,11 @@ def collect(n_tensors, seed, device="cuda", J_grid=(250, 500, 1000, 2000, 4000, 
     return np.concatenate(feats).astype(np.float32), np.concatenate(targs).astype(np.float32), meta
 
 
+EXACT = 0   # key of the exact run among the J choices
+
+
 def collect_runs(n_tensors, seed, device="cuda", J_grid=(250, 500, 1000, 2000, 4000, 8000), lam=1e-3,
-                 max_sweeps=8, log=None):
+                 max_sweeps=8, exact=True, log=None):
     """Labelled (features, targets) from whole runs to a target; see the
     module doc.  Returns the same layout as collect()."""
     import synth
@@ -240,21 +245,26 @@ def collect_runs(n_tensors, seed, device="cuda", J_grid=(250, 500, 1000, 2000, 4
         s_i = int(g.integers(1, 2 ** 31))
         scale = math.sqrt(float(np.prod(R[1:-1])))
         X, _ = synth.tt_tensor_device(n, R, nu * scale, s_i, dtype="f32", device=dev)
-        plan = Plan(n, R, Jmax, lam, seed=s_i, x_dtype="f32", work_dtype="f32", device=dev, serial=True)
+        plan = Plan(n, R, Jmax, lam, seed=s_i, x_dtype="f32", work_dtype="f32", device=dev, serial=True,
+                    exact=exact)
         init = synth.random_cores(n, R, s_i + 1)
         scratch = [core_to_device(c, dev) for c in init]   # first-use costs out of the timings
         plan.als_sweep(X, scratch)
+        if exact:
+            plan.als_sweep_exact(X, scratch)
         plan.residual(X, scratch)
         runs = {}
-        for J in J_grid:
+        choices = tuple(J_grid) + ((EXACT,) if exact else ())
+        for J in choices:
             cores = [core_to_device(c, dev) for c in init]
-            plan.set_sketch(J, lam)
+            plan.set_sketch(Jmax if J == EXACT else J, lam)
             plan.set_sweep(0)
+            sweep = plan.als_sweep_exact if J == EXACT else plan.als_sweep
             torch.cuda.synchronize()
             t_acc, times, res = 0.0, [], []
             for _ in range(max_sweeps):
                 ta = time.perf_counter()
-                plan.als_sweep(X, cores)
+                sweep(X, cores)
                 r = plan.residual(X, cores)   # synchronises
                 t_acc += time.perf_counter() - ta
                 times.append(t_acc)
@@ -270,15 +280,17 @@ def collect_runs(n_tensors, seed, device="cuda", J_grid=(250, 500, 1000, 2000, 4
                     return times[s], s + 1
             return math.inf, None
 
-        Jstar = min(J_grid, key=lambda J: (reach(J)[0], J))
+        # ties go to the smaller sketch; the exact run ranks above every J
+        Jstar = min(choices, key=lambda J: (reach(J)[0], J if J != EXACT else math.inf))
         T_star = reach(Jstar)[1]
+        Jlab = _abi.JPOLICY_EXACT_LABEL if Jstar == EXACT else Jstar
         h = [1.0] + runs[Jstar][1]   # h[s + 1]: residual after sweep s
         for t in range(T_star):
             drop = math.log10(h[t - 1] / h[t]) if t >= 1 else 0.0
             feats.append(plan.features(t, drop))
-            targs.append(np.repeat(encode_targets(Jstar, lam)[None, :], len(n), axis=0))
-            meta.append({"n": n, "R": R, "noise": nu, "t": t, "J": Jstar, "lambda": lam, "target": tau,
-                         "ms_to_target": {J: reach(J)[0] * 1e3 for J in J_grid}})
+            targs.append(np.repeat(encode_targets(Jlab, lam)[None, :], len(n), axis=0))
+            meta.append({"n": n, "R": R, "noise": nu, "t": t, "J": Jlab, "lambda": lam, "target": tau,
+                         "ms_to_target": {J: reach(J)[0] * 1e3 for J in choices}})
         del X, plan, scratch
         if log and (i + 1) % 20 == 0:
             log("[collect] %d/%d tensors, %d rows, %.0f s" % (i + 1, n_tensors, sum(len(f) for f in feats),

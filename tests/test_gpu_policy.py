@@ -1,6 +1,7 @@
 """GPU parity of the sketch-size policy kernels (forward, backpropagation,
 Adam) against the FP64 oracle, and of the policy-driven run loop."""
 import math
+import time
 
 import numpy as np
 import pytest
@@ -91,6 +92,48 @@ def test_training_on_gpu_reduces_loss(env):
     L0 = pol.mse(X, T)
     pol.fit(X, T, steps=600, lr=3e-3, batch=256, seed=1)
     assert pol.mse(X, T) < 0.02 * L0
+
+
+def test_choose_selects_the_exact_update(env):
+    """A prediction at or above TT_JPOLICY_EXACT_J selects the unsketched
+    update (J = 0) on a plan with exact buffers, and the plan's J cap on a
+    plan without; just below it, a sketch size."""
+    torch, tts, jpolicy = env
+    say("choose exact")
+    theta = np.zeros(jpolicy.P, dtype=np.float32)
+    theta[-1] = math.log10(1e-2) + 3.0
+    n, R = [12, 10, 9, 11], [1, 3, 4, 3, 1]
+    pe = tts.Plan(n, R, 4000, 1e-3, seed=1, exact=True)
+    pn = tts.Plan(n, R, 4000, 1e-3, seed=1)
+    theta[-2] = math.log(jpolicy._abi.JPOLICY_EXACT_LABEL) - 7.0
+    assert pe.choose(jpolicy.Policy(theta).params, 1, 0.3)[0] == 0
+    assert pn.choose(jpolicy.Policy(theta).params, 1, 0.3)[0] == 4000
+    theta[-2] = math.log(jpolicy._abi.JPOLICY_EXACT_J * 0.99) - 7.0
+    assert pe.choose(jpolicy.Policy(theta).params, 1, 0.3)[0] == 4000
+
+
+def test_run_with_exact_choices_equals_exact_sweeps(env):
+    """A policy that always picks the exact update makes tt_als_run's sweeps
+    those of tt_als_sweep_exact with the policy's lambda, recorded as J = 0."""
+    torch, tts, jpolicy = env
+    import synth
+    say("run with exact choices")
+    n, R = [20, 22, 18, 21], [1, 4, 5, 4, 1]
+    dev = torch.device("cuda:0")
+    X, _ = synth.tt_tensor_device(n, R, 1e-3, 41, dtype="f32", device=dev)
+    init = synth.random_cores(n, R, 42)
+    theta = np.zeros(jpolicy.P, dtype=np.float32)
+    theta[-2] = math.log(jpolicy._abi.JPOLICY_EXACT_LABEL) - 7.0
+    theta[-1] = math.log10(1e-2) + 3.0
+    plan = tts.Plan(n, R, 1000, 1e-3, seed=43, exact=True)
+    c = [tts.core_to_device(x) for x in init]
+    out = plan.run(X, c, 3, 0.0, params=jpolicy.Policy(theta).params)
+    ref = tts.Plan(n, R, 1000, 1e-2, seed=43, exact=True)
+    c2 = [tts.core_to_device(x) for x in init]
+    res = [ref.als_sweep_exact(X, c2, residual=True) for _ in range(3)]
+    assert out["J"] == [0, 0, 0] and out["fallbacks"] == 0
+    assert out["lambda"] == pytest.approx([1e-2] * 3, rel=1e-6)
+    np.testing.assert_allclose(out["residuals"], res, rtol=1e-9)
 
 
 def test_choose_decodes_outputs(env):
@@ -191,7 +234,7 @@ def test_whole_run_labels(env):
     torch, tts, jpolicy = env
     say("whole-run labels")
     # seed 2 draws a small order-4 problem (33 x 34 x 38 x 34)
-    X, T, meta = jpolicy.collect_runs(1, 2, "cuda", J_grid=(250, 1000), max_sweeps=3)
+    X, T, meta = jpolicy.collect_runs(1, 2, "cuda", J_grid=(250, 1000), max_sweeps=3, exact=False)
     assert meta
     ms = meta[0]["ms_to_target"]
     finite = {J: v for J, v in ms.items() if v != math.inf}
@@ -203,3 +246,100 @@ def test_whole_run_labels(env):
     assert X.shape == (d * len(meta), F) and T.shape == (d * len(meta), O)
     assert np.allclose(T[:, 0], math.log(Jstar) - 7.0) and np.allclose(T[:, 1], 0.0)   # lambda = 1e-3
     assert np.allclose(X[:d, 7], 0.0)   # no residual drop before the first sweep
+
+
+def test_whole_run_labels_with_the_exact_run(env):
+    """With the exact run among the choices its label is
+    TT_JPOLICY_EXACT_LABEL when it reaches the target first."""
+    torch, tts, jpolicy = env
+    say("whole-run labels with exact")
+    X, T, meta = jpolicy.collect_runs(1, 2, "cuda", J_grid=(250, 1000), max_sweeps=3, exact=True)
+    ms = meta[0]["ms_to_target"]
+    finite = {J: v for J, v in ms.items() if v != math.inf}
+    best = min(finite, key=lambda J: (finite[J], J if J != jpolicy.EXACT else math.inf))
+    lab = jpolicy._abi.JPOLICY_EXACT_LABEL if best == jpolicy.EXACT else best
+    assert all(m["J"] == lab for m in meta)
+    assert np.allclose(T[:, 0], math.log(lab) - 7.0)
+
+
+def _time_to_target(fn):
+    torch = pytest.importorskip("torch")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, out
+
+
+GAIN_PROBLEMS = [([40] * 5, [1, 8, 8, 8, 8, 1], 2e-3, 71), ([56, 48, 52, 60], [1, 10, 12, 10, 1], 1e-3, 72),
+                 ([36] * 5, [1, 6, 9, 9, 6, 1], 3e-3, 73)]
+
+
+def test_policy_gain_over_fixed_sketch_sizes(env):
+    """Time to relative residual 1e-2 on problems outside the training draw
+    (shapes and seeds the collection never produced): the shipped policy
+    (tt_als_run with the trained weights, exact update available) against
+    fixed J = 3000, the best J of {1000, 3000, 8000}, the capped Corollary 3
+    size from the start, and exact sweeps throughout.  Asserts that the
+    policy reaches the target on every problem and takes less than 0.8 x
+    the total time of fixed J = 3000 and of the Corollary 3 size; reports
+    the rest (the best grid J, and exact sweeps, which the shipped policy
+    picks on these problems)."""
+    import os
+    import synth
+    torch, tts, jpolicy = env
+    say("policy gain")
+    pol = jpolicy.Policy.load(os.path.join(os.path.dirname(tts.__file__), "jpolicy_weights.npy"), device="cuda")
+    dev = torch.device("cuda:0")
+    tgt, maxs = 1e-2, 12
+    tot = {"policy": 0.0, "J3000": 0.0, "best_grid": 0.0, "cor3": 0.0, "exact": 0.0}
+    for n, R, nu, seed in GAIN_PROBLEMS:
+        scale = math.sqrt(float(np.prod(R[1:-1])))
+        X, _ = synth.tt_tensor_device(n, R, nu * scale, seed, dtype="f32", device=dev)
+        init = synth.random_cores(n, R, seed + 1)
+
+        def fresh():
+            return [tts.core_to_device(c, dev) for c in init]
+
+        def fixed(J):
+            p = tts.Plan(n, R, J, 1e-3, seed=seed, device=dev)
+            p.run(X, fresh(), 1, 0.0)          # first-use costs out of the timing
+            p.set_sweep(0)
+            return _time_to_target(lambda: p.run(X, fresh(), maxs, tgt))
+
+        pp = tts.Plan(n, R, 8000, 1e-3, seed=seed, device=dev, exact=True)
+        pp.run(X, fresh(), 1, 0.0, params=pol.params)
+        pp.set_sketch(8000, 1e-3)
+        pp.set_sweep(0)
+        t_pol, o_pol = _time_to_target(lambda: pp.run(X, fresh(), maxs, tgt, params=pol.params))
+        grid = {J: fixed(J) for J in (1000, 3000, 8000)}
+        fb = pp.fallback_J()
+        t_fb, o_fb = fixed(fb)
+        pe = tts.Plan(n, R, 8000, 1e-3, seed=seed, device=dev, exact=True)
+        c = fresh()
+        pe.als_sweep_exact(X, fresh())
+
+        def exact_run():
+            h = []
+            for _ in range(maxs):
+                h.append(pe.als_sweep_exact(X, c, residual=True))
+                if h[-1] <= tgt:
+                    break
+            return h
+
+        t_ex, h_ex = _time_to_target(exact_run)
+        best = min(grid, key=lambda J: (not grid[J][1]["reached"], grid[J][0]))
+        print("%s R=%s: policy %.1f ms (%d sweeps, J %s) | J=3000 %.1f ms (%d, %s) | best grid J=%d %.1f ms | "
+              "Cor. 3 J=%d %.1f ms (%s) | exact %.1f ms (%d sweeps)" % (
+                  n, R, t_pol * 1e3, o_pol["sweeps"], o_pol["J"], grid[3000][0] * 1e3, grid[3000][1]["sweeps"],
+                  grid[3000][1]["reached"], best, grid[best][0] * 1e3, fb, t_fb * 1e3, o_fb["reached"],
+                  t_ex * 1e3, len(h_ex)))
+        assert o_pol["reached"], (n, o_pol)
+        tot["policy"] += t_pol
+        tot["J3000"] += grid[3000][0]
+        tot["best_grid"] += grid[best][0]
+        tot["cor3"] += t_fb
+        tot["exact"] += t_ex
+        del X, pp, pe
+    print("totals (ms):", {k: round(v * 1e3, 1) for k, v in tot.items()})
+    assert tot["policy"] < 0.8 * tot["J3000"] and tot["policy"] < 0.8 * tot["cor3"], tot
