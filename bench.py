@@ -481,9 +481,10 @@ def compare_forms(seed, dev, log):
     return out
 
 
-def run_batched(args):
+def batched_section(args, dev, steps, warmup, cache=None):
     """Batched workload: one step = one batched sweep (captured in a hipGraph)
-    of every problem; value = sketched entries (sum of d_i N_i) per second."""
+    of every problem; returns the timing, the per-step sketch launches and
+    the dominant launch's roofline."""
     import numpy as np
     import torch
     import paper_2309_08093_amd as tts
@@ -492,8 +493,6 @@ def run_batched(args):
     def log(m):
         print(m, file=sys.stderr, flush=True)
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     shapes = synth.batched_shapes(BATCH["count"], args.seed)
     probs = [dict(n=n, ranks=R, J=BATCH["J"], lam=BATCH["lam"], seed=args.seed + 17 * i)
              for i, (n, R) in enumerate(shapes)]
@@ -506,28 +505,31 @@ def run_batched(args):
     cores = [[tts.core_to_device(c, dev) for c in synth.random_cores(p["n"], p["ranks"], args.seed + 7 * i + 1)]
              for i, p in enumerate(probs)]
     log("[bench] autotune")
-    chosen = batch.autotune(Xs, reps=2)
+    t_tune = time.perf_counter()
+    batch.autotune(Xs, reps=2, cache=cache)
+    t_tune = time.perf_counter() - t_tune
+    tuning = batch.get_tuning()
     batch.set_graph(True)
-    log("[bench] warmup %d sweeps (the first captures the graph)" % max(1, args.warmup))
-    for _ in range(max(1, args.warmup)):
+    log("[bench] warmup %d sweeps (the first captures the graph)" % max(1, warmup))
+    for _ in range(max(1, warmup)):
         batch.sweep(Xs, cores)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream(dev)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    log("[bench] timing %d sweeps" % args.steps)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    log("[bench] timing %d batched sweeps" % steps)
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs[0].record(stream)
+    for t in range(steps):
         batch.sweep(Xs, cores)
-    ev1.record(stream)
+        evs[t + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    per = [evs[t].elapsed_time(evs[t + 1]) for t in range(steps)]
+    ms_per_step = float(np.median(per))
     entries = sum(d * N for d, N in zip(ds, Ns))
     # the batched data-sketch launches, one step at a time, timed with events on
     # the stream they run on
-    steps = {}
+    sk = {}
     for k in range(max(ds)):
         nbytes = 4 * sum(N for d, N in zip(ds, Ns) if d > k)
         batch.sketch_launch(Xs, k)
@@ -540,27 +542,46 @@ def run_batched(args):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 5
         kern = batch.sketch_kernel(k)
-        steps[k] = {"kernel": kern if k == 0 else kern + "+k_breduce", "avg_launch_ms": round(ms, 4),
-                    "bytes": nbytes, "GB/s": round(nbytes / ms / 1e6, 1),
-                    "frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBPS, 4)}
-    dom = max((k for k in steps if k >= 1), key=lambda k: steps[k]["avg_launch_ms"] * 1.0)
-    rf = {"bound": "hbm", "achieved": steps[dom]["GB/s"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-          "frac": steps[dom]["frac"], "traffic": stored_traffic("k_bsketch", "c4", "batch.hip", step=dom),
+        sk[k] = {"kernel": kern if k == 0 else kern + "+k_breduce", "avg_launch_ms": round(ms, 4),
+                 "bytes": nbytes, "GB/s": round(nbytes / ms / 1e6, 1),
+                 "frac": round(nbytes / ms / 1e6 / HBM_PEAK_GBPS, 4)}
+    dom = max((k for k in sk if k >= 1), key=lambda k: sk[k]["avg_launch_ms"] * 1.0)
+    rf = {"bound": "hbm", "achieved": sk[dom]["GB/s"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+          "frac": sk[dom]["frac"], "traffic": stored_traffic("k_bsketch", "c4", "batch.hip", step=dom),
           "kernel": "%s (step %d)" % (batch.sketch_kernel(dom), dom),
-          "avg_launch_ms": steps[dom]["avg_launch_ms"], "bytes_per_launch": steps[dom]["bytes"]}
+          "avg_launch_ms": sk[dom]["avg_launch_ms"], "bytes_per_launch": sk[dom]["bytes"]}
     res = batch.sweep(Xs, cores, residuals=True)
+    out = {"value": entries / (ms_per_step * 1e-3), "unit": "entries/s", "ms_per_step": ms_per_step,
+           "ms_per_step_note": "median of %d graph-replayed sweeps; mean %.3f" % (steps, sum(per) / steps),
+           "workload": "%d independent random TTs, order U{3,4,5}, n_i U[20,60], ranks U[2,8], FP32, noise 1e-3, "
+                       "J=%d, lambda=%g; one batched sweep per step, captured in a hipGraph"
+                       % (BATCH["count"], BATCH["J"], BATCH["lam"]),
+           "problems": len(probs), "total_entries": sum(Ns),
+           "tuning": {"steps": tuning, "seconds": round(t_tune, 3),
+                      "from_cache": bool(getattr(batch, "tuned_from_cache", False))},
+           "hbm_gbps_sweep": 4 * entries / (ms_per_step * 1e-3) / 1e9, "wall_s_timed": wall, "roofline": rf,
+           "batched_sketch_steps": sk,
+           "residuals_after": {"median": float(np.median(res)), "max": float(np.max(res))}}
+    del Xs, cores, batch
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_batched(args):
+    """The batched workload as the bench line itself (--config c4)."""
+    import torch
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    b = batched_section(args, dev, args.steps, args.warmup, cache=args.tune_cache)
     out = {
         "metric": "sketched X entries/s (HBM GB/s) + time-to-rel-residual 1e-2, mixed vs plain FP32",
-        "value": entries / (ms_per_step * 1e-3), "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "value": b["value"], "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": b["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "%d independent random TTs, order U{3,4,5}, n_i U[20,60], ranks U[2,8], FP32, "
-                               "noise 1e-3, J=%d, lambda=%g; one batched sweep per step, captured in a hipGraph"
-                               % (BATCH["count"], BATCH["J"], BATCH["lam"]),
-                   "problems": len(probs), "total_entries": sum(Ns), "autotuned_workgroups": chosen},
-        "hbm_gbps_sweep": 4 * entries / (ms_per_step * 1e-3) / 1e9,
-        "wall_s_timed": wall, "roofline": rf, "batched_sketch_steps": steps,
-        "residuals_after": {"median": float(np.median(res)), "max": float(np.max(res))},
+        "config": {"workload": b["workload"], "problems": b["problems"], "total_entries": b["total_entries"],
+                   "tuning": b["tuning"]},
+        "hbm_gbps_sweep": b["hbm_gbps_sweep"], "wall_s_timed": b["wall_s_timed"], "roofline": b["roofline"],
+        "batched_sketch_steps": b["batched_sketch_steps"], "residuals_after": b["residuals_after"],
     }
     print(json.dumps(out), flush=True)
 
@@ -629,6 +650,10 @@ def main():
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse-input sketch timing")
     ap.add_argument("--no-paper-workloads", action="store_true",
                     help="skip the order-6 synthetic workloads of the paper's experiments")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched workload (256 uneven TTs) in the default line")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file the batched autotuner reads its choices from and writes them to")
     ap.add_argument("--cpu-entries", type=int, default=128_000_000)
     ap.add_argument("--overlap", action="store_true",
                     help="time the overlapped schedule (data sketches on a second stream beside the core "
@@ -851,6 +876,10 @@ def main():
     if not args.no_exact:
         print("[bench] exact sweeps", file=sys.stderr, flush=True)
         out["exact"] = exact_section(cfg, X, init, args, dev)
+
+    if not args.no_batched:
+        print("[bench] batched workload", file=sys.stderr, flush=True)
+        out["batched_256_uneven_tt"] = batched_section(args, dev, 5, 1, cache=args.tune_cache)
 
     if not args.no_compare:
         out["mixed_learned_vs_plain"] = compare_forms(args.seed, dev,

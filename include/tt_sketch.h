@@ -467,11 +467,31 @@ tt_status tt_batch_sketch_path(tt_batch batch, int32_t k, int32_t* path);
  * receiving each problem's exact relative residual (synchronises). */
 tt_status tt_batch_sweep(tt_batch batch, const void* const* X, void* const* const* cores, double* residuals);
 
-/* Autotuner: time the k >= 1 data-sketch launch of every step with workgroup
- * counts of 1/2, 1, 2, 4 and 8 times the device occupancy (at most 16384) (reps launches each)
- * and keep the fastest.  chosen: NULL or host int64 array of max order
- * entries receiving the choice per step (0 for k = 0). */
+/* Autotuner: for every step, time (reps launches each, after one warm-up)
+ * and keep the fastest of
+ *  - the data-sketch launch over its shapes: entries of a fibre per lane
+ *    (2 when every n_0 <= 128, or 4), fibres per lane group in flight (4 or 8
+ *    at k = 0, 8 or 16 at k >= 1), and for k >= 1 workgroup counts of 1/2,
+ *    1, 2, 4 and 8 times the device occupancy of that shape (at most 16384);
+ *    slab steps (k >= 2 when the slabs fit in LDS) have the count only;
+ *  - the Gram K-chunk of the step's core updates (256, 512 or 1024 rows of SH
+ *    per partial product), timed with the partial sums.
+ * The choices stay with the batch (tt_batch_get_tuning exports them for a
+ * caller to keep, tt_batch_set_tuning restores them).  chosen: NULL or host
+ * int64 array of max order entries receiving the workgroup count per step
+ * (0 for k = 0).  Drops a captured graph. */
 tt_status tt_batch_autotune(tt_batch batch, const void* const* X, int32_t reps, int64_t* chosen);
+
+/* The batch's tuning, TT_MAX_ORDER steps of TT_BATCH_TUNE_FIELDS int64:
+ * [0] workgroups of the data-sketch launch (0: device occupancy; 0 at k = 0),
+ * [1] entries per lane, [2] fibres per lane group in flight, [3] Gram
+ * K-chunk.  set validates every used step (values as listed under
+ * tt_batch_autotune; the K-chunk may be any multiple of 256 up to 8192) and
+ * returns TT_ERR_ARG, changing nothing, on the first bad one; it drops a
+ * captured graph.  Steps at or beyond the largest order are ignored. */
+#define TT_BATCH_TUNE_FIELDS 4
+tt_status tt_batch_get_tuning(tt_batch batch, int64_t* tuning);
+tt_status tt_batch_set_tuning(tt_batch batch, const int64_t* tuning);
 
 /* ------------------------------------------------------------------------
  * For callers that cannot allocate device memory (code under stream capture,

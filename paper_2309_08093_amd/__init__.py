@@ -500,11 +500,69 @@ class Batch:
         check(_lib.tt_batch_sweep(self._h, xs, cs, None), "tt_batch_sweep")
         return None
 
-    def autotune(self, Xs, reps=3):
+    def get_tuning(self):
+        """Per step: dict(workgroups, entries_per_lane, fibres_in_flight,
+        gram_kchunk) (tt_batch_get_tuning)."""
+        F = _abi.BATCH_TUNE_FIELDS
+        buf = (ctypes.c_int64 * (_abi.MAX_ORDER * F))()
+        check(_lib.tt_batch_get_tuning(self._h, buf), "tt_batch_get_tuning")
+        dmax = max(len(p["n"]) for p in self.problems)
+        names = ("workgroups", "entries_per_lane", "fibres_in_flight", "gram_kchunk")
+        return [dict(zip(names, buf[k * F:(k + 1) * F])) for k in range(dmax)]
+
+    def set_tuning(self, steps):
+        """Restore get_tuning()'s list (tt_batch_set_tuning)."""
+        F = _abi.BATCH_TUNE_FIELDS
+        buf = (ctypes.c_int64 * (_abi.MAX_ORDER * F))()
+        check(_lib.tt_batch_get_tuning(self._h, buf), "tt_batch_get_tuning")
+        for k, st in enumerate(steps):
+            buf[k * F:(k + 1) * F] = [int(st["workgroups"]), int(st["entries_per_lane"]),
+                                      int(st["fibres_in_flight"]), int(st["gram_kchunk"])]
+        check(_lib.tt_batch_set_tuning(self._h, buf), "tt_batch_set_tuning")
+
+    def step_keys(self):
+        """Cache key of each step's tuning: the step, the number of problems
+        taking part, their total mode-0 fibres (the data sketch's units), the
+        largest n_0, their total n_k (columns), the largest J, the data type
+        and the device."""
+        dmax = max(len(p["n"]) for p in self.problems)
+        dev = torch.cuda.get_device_name(self.device) if torch.cuda.is_available() else "none"
+        keys = []
+        for k in range(dmax):
+            ps = [p for p in self.problems if len(p["n"]) > k]
+            units = sum(int(np.prod(p["n"])) // int(p["n"][0]) for p in ps)
+            keys.append("k=%d|problems=%d|fibres=%d|n0max=%d|columns=%d|J=%d|dtype=f32|device=%s|%s" % (
+                k, len(ps), units, max(p["n"][0] for p in ps), sum(p["n"][k] for p in ps),
+                max(int(p["J"]) for p in ps), dev, version()))
+        return keys
+
+    def autotune(self, Xs, reps=3, cache=None):
+        """Tune every step (tt_batch_autotune) and return the workgroup count
+        per step.  With cache (a JSON file path), steps whose key
+        (step_keys) is in the file take the stored tuning instead, and a
+        fresh tuning is written back."""
+        import json
+        import os
+        keys = self.step_keys()
+        db = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                db = json.load(f)
+        if cache and all(k in db for k in keys):
+            self.set_tuning([db[k] for k in keys])
+            self.tuned_from_cache = True
+            return [st["workgroups"] for st in self.get_tuning()]
         xs, keep = self._xs(Xs)
         dmax = max(len(p["n"]) for p in self.problems)
         out = (ctypes.c_int64 * dmax)()
         check(_lib.tt_batch_autotune(self._h, xs, int(reps), out), "tt_batch_autotune")
+        self.tuned_from_cache = False
+        if cache:
+            db.update(dict(zip(keys, self.get_tuning())))
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(db, f, indent=1)
+            os.replace(tmp, cache)
         return list(out)
 
 

@@ -88,6 +88,8 @@ SIGNATURES = {
     "tt_batch_sketch_tensor": [_vp, _vpp, ctypes.c_int32, _vpp],
     "tt_batch_sweep": [_vp, _vpp, _vp, ctypes.POINTER(ctypes.c_double)],
     "tt_batch_autotune": [_vp, _vpp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)],
+    "tt_batch_get_tuning": [_vp, ctypes.POINTER(ctypes.c_int64)],
+    "tt_batch_set_tuning": [_vp, ctypes.POINTER(ctypes.c_int64)],
     "tt_batch_sketch_path": [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "tt_residual_noalloc": [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                             ctypes.c_int32, ctypes.c_int32, _vp, _vpp, _vp, ctypes.POINTER(ctypes.c_double)],
@@ -100,6 +102,7 @@ JPOLICY_OUTPUTS = 2
 JPOLICY_PARAMS = 9026
 JPOLICY_EXACT_J = 24576        # predictions at or above select the unsketched update
 JPOLICY_EXACT_LABEL = 65536    # label of that choice
+BATCH_TUNE_FIELDS = 4
 
 
 class RunStats(ctypes.Structure):

@@ -89,10 +89,9 @@ __device__ __forceinline__ int lpf_log2_of(int n0) {
 }
 
 // ---------------------------------------------------------------- k >= 1
-constexpr int kBFib = 16;   // k >= 1: fibres per lane group per load batch
-constexpr int kB0Fib = 8;   // k = 0: fibres per lane group per load batch
-
-template <int NJ>
+// NJ: entries of a fibre per lane; FIB: fibres per lane group per load batch
+// (both chosen per step by the autotuner)
+template <int NJ, int FIB>
 __global__ __launch_bounds__(256) void k_bsketch_k(const BTensor* __restrict__ T, const int32_t* __restrict__ tids,
                                                    const int64_t* __restrict__ fpre, const int64_t* __restrict__ cpre,
                                                    const int64_t* __restrict__ spre, int32_t nt, int32_t k,
@@ -162,14 +161,14 @@ __global__ __launch_bounds__(256) void k_bsketch_k(const BTensor* __restrict__ T
         }
       }
       const int nb = (we - fb) < 64 ? (int)(we - fb) : 64;
-      // kBFib fibres per lane group in flight: short fibres need many loads
+      // FIB fibres per lane group in flight: short fibres need many loads
       // outstanding per wave to cover the memory latency
-      for (int u0 = 0; u0 < nb; u0 += kBFib * G) {
-        float x[kBFib][NJ];
-        uint32_t kb[kBFib], ks[kBFib];
-        bool ok[kBFib];
+      for (int u0 = 0; u0 < nb; u0 += FIB * G) {
+        float x[FIB][NJ];
+        uint32_t kb[FIB], ks[FIB];
+        bool ok[FIB];
 #pragma unroll
-        for (int u = 0; u < kBFib; ++u) {
+        for (int u = 0; u < FIB; ++u) {
           const int idx = u0 + u * G + gi;
           ok[u] = idx < nb;
           const uint32_t key = (uint32_t)__shfl((int)keyl, idx & 63, 64);
@@ -185,7 +184,7 @@ __global__ __launch_bounds__(256) void k_bsketch_k(const BTensor* __restrict__ T
           }
         }
 #pragma unroll
-        for (int u = 0; u < kBFib; ++u)
+        for (int u = 0; u < FIB; ++u)
 #pragma unroll
           for (int q = 0; q < NJ; ++q) {
             const int i0 = v + LPF * q;
@@ -359,7 +358,7 @@ __global__ void k_breduce(const BTensor* __restrict__ T, const int32_t* __restri
 }
 
 // ---------------------------------------------------------------- k = 0
-template <int NJ>
+template <int NJ, int FIB>
 __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T, const int32_t* __restrict__ tids,
                                                    int32_t Jmax) {
   __shared__ double red[4][64 * NJ];
@@ -387,11 +386,11 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
     for (uint32_t e0 = beg; e0 < end; e0 += 64) {
       const uint32_t itl = (e0 + lane < end) ? sortg[e0 + lane] : 0u;
       const int nb = (end - e0) < 64u ? (int)(end - e0) : 64;
-      for (int u0 = 0; u0 < nb; u0 += kB0Fib * G) {
-        float x[kB0Fib][NJ];
-        uint32_t sg[kB0Fib];
+      for (int u0 = 0; u0 < nb; u0 += FIB * G) {
+        float x[FIB][NJ];
+        uint32_t sg[FIB];
 #pragma unroll
-        for (int u = 0; u < kB0Fib; ++u) {   // all loads first, then the sums
+        for (int u = 0; u < FIB; ++u) {   // all loads first, then the sums
           const int idx = u0 + u * G + gi;
           const uint32_t item = (uint32_t)__shfl((int)itl, idx & 63, 64);
           sg[u] = (item ^ t1) & TT_KEY_SIGN;
@@ -403,7 +402,7 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
           }
         }
 #pragma unroll
-        for (int u = 0; u < kB0Fib; ++u)   // in list order, as before
+        for (int u = 0; u < FIB; ++u)   // in list order, as before
 #pragma unroll
           for (int q = 0; q < NJ; ++q) acc[q] += signed_f64(x[u][q], sg[u]);
       }
@@ -432,6 +431,20 @@ __global__ void k_inc_i64(int64_t* p) {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+typedef void (*BKFn)(const BTensor*, const int32_t*, const int64_t*, const int64_t*, const int64_t*, int32_t, int32_t,
+                     double*, int32_t);
+typedef void (*B0Fn)(const BTensor*, const int32_t*, int32_t);
+
+// the compiled (entries per lane, fibres in flight) shapes
+BKFn bk_kernel(int nj, int fib) {
+  if (nj == 2) return fib == 8 ? k_bsketch_k<2, 8> : k_bsketch_k<2, 16>;
+  return fib == 8 ? k_bsketch_k<4, 8> : k_bsketch_k<4, 16>;
+}
+B0Fn b0_kernel(int nj, int fib) {
+  if (nj == 2) return fib == 4 ? k_bsketch_0<2, 4> : k_bsketch_0<2, 8>;
+  return fib == 4 ? k_bsketch_0<4, 4> : k_bsketch_0<4, 8>;
+}
+
 }  // namespace
 
 struct tt_batch_s {
@@ -443,7 +456,11 @@ struct tt_batch_s {
   size_t ws_need = 0;
   int max_d = 0;
   int32_t Jmax = 0;
-  int nj = 1;
+  int max_n0 = 1;
+  // tuning per step k: entries per lane and fibres in flight of the data
+  // sketch, Gram K-chunk of the core updates (the workgroup count is W below)
+  int nj[TT_MAX_ORDER] = {}, fib[TT_MAX_ORDER] = {};
+  int32_t kchunk[TT_MAX_ORDER] = {};
   // per step k
   std::vector<std::vector<int32_t>> tids;
   std::vector<std::vector<int64_t>> fpre, cpre, spre;
@@ -497,15 +514,14 @@ size_t step_lds(tt_batch b, int k) {
 }
 
 // resident workgroups of the step-k launch on the whole device
-int occupancy_grid(tt_batch b, int k) {
+int occupancy_grid(tt_batch b, int k, int nj, int fib) {
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     ncu = 256;
   const size_t lds = step_lds(b, k);
   hipError_t e = hipErrorInvalidValue;
   if (b->slab[k]) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_slab, 256, lds);
-  else if (b->nj == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_k<2>, 256, lds);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_k<4>, 256, lds);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bk_kernel(nj, fib), 256, lds);
   if (e != hipSuccess || per < 1) per = 1;
   return per * ncu;
 }
@@ -567,8 +583,7 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
                                         b->stream)) != hipSuccess)
       return e;
     const dim3 grid((unsigned)(nt * b->Jmax));
-    if (b->nj == 2) hipLaunchKernelGGL(k_bsketch_0<2>, grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
-    else hipLaunchKernelGGL(k_bsketch_0<4>, grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
+    hipLaunchKernelGGL(b0_kernel(b->nj[0], b->fib[0]), grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
     return hipGetLastError();
   }
   const int64_t* fpre = reinterpret_cast<const int64_t*>(b->ws + b->o_fpre[k]);
@@ -576,7 +591,7 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
   const int64_t* spre = reinterpret_cast<const int64_t*>(b->ws + b->o_spre[k]);
   double* part = reinterpret_cast<double*>(b->ws + b->o_part);
   const int64_t Ttot = b->fpre[k].back();
-  int64_t W = Wk > 0 ? Wk : occupancy_grid(b, k);
+  int64_t W = Wk > 0 ? Wk : occupancy_grid(b, k, b->nj[k], b->fib[k]);
   if (W > b->Wmax) W = b->Wmax;
   if (W > Ttot) W = Ttot;
   if (W < 1) W = 1;
@@ -584,12 +599,9 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
   if (b->slab[k])
     hipLaunchKernelGGL(k_bsketch_slab, dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre, cpre, spre, nt, k,
                        part, b->Jmax, b->slab_S[k]);
-  else if (b->nj == 2)
-    hipLaunchKernelGGL(k_bsketch_k<2>, dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre, cpre, spre, nt, k,
-                       part, b->Jmax);
   else
-    hipLaunchKernelGGL(k_bsketch_k<4>, dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre, cpre, spre, nt, k,
-                       part, b->Jmax);
+    hipLaunchKernelGGL(bk_kernel(b->nj[k], b->fib[k]), dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre,
+                       cpre, spre, nt, k, part, b->Jmax);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int64_t total = b->cpre[k].back() * b->Jmax;
   hipLaunchKernelGGL(k_breduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, b->stream, T, tids, fpre, cpre,
@@ -616,6 +628,38 @@ tt_status make_lanes(tt_batch b) {
 // Fill and upload the core-update descriptors (core pointers may change
 // between calls; the descriptors live in device memory, so a captured graph
 // stays valid when only their contents change).
+// the plan-buffer pointers of the core-update descriptors (fixed once the
+// workspace is bound)
+void fill_upd_buffers(tt_batch b) {
+  for (int k = 0; k < b->max_d; ++k)
+    for (size_t j = 0; j < b->upd[k].size(); ++j) {
+      tt_plan p = b->plans[b->tids[k][j]];
+      BUpd& u = b->upd[k][j];
+      u.SH = p->at<float>(p->o_SH);
+      u.Y = p->at<float>(p->o_Yall) + p->J * p->tab_off[k];
+      u.gpart = p->at<double>(p->o_gram);
+      u.gsum = p->at<double>(p->o_gsum);
+      u.Lg = p->at<double>(p->o_minv);
+      u.status = p->at<int32_t>(p->o_status);
+      u.R = p->at<double>(p->o_qrR);
+    }
+}
+
+// Gram K-chunk of step k; the descriptors and the launch width follow, and
+// the next sweep uploads them again
+void set_kchunk(tt_batch b, int k, int32_t kc) {
+  b->kchunk[k] = kc;
+  int32_t gx = 0;
+  for (BUpd& u : b->upd[k]) {
+    u.kchunk = kc;
+    u.chunks = (u.J + kc - 1) / kc;
+    const int tiles = ((u.s + 15) / 16) * ((u.s + u.nk + 15) / 16);
+    gx = std::max(gx, ((tiles + 3) / 4) * u.chunks);
+  }
+  b->g_gx[k] = gx;
+  b->upd_key.clear();
+}
+
 tt_status upload_upd(tt_batch b, void* const* const* cores) {
   std::vector<const void*> key;
   for (int i = 0; i < b->count; ++i)
@@ -626,16 +670,9 @@ tt_status upload_upd(tt_batch b, void* const* const* cores) {
       const int i = b->tids[k][j];
       tt_plan p = b->plans[i];
       BUpd& u = b->upd[k][j];
-      u.SH = p->at<float>(p->o_SH);
-      u.Y = p->at<float>(p->o_Yall) + p->J * p->tab_off[k];
-      u.gpart = p->at<double>(p->o_gram);
-      u.gsum = p->at<double>(p->o_gsum);
-      u.Lg = p->at<double>(p->o_minv);
-      u.status = p->at<int32_t>(p->o_status);
       u.G = static_cast<double*>(cores[i][k]);
       const bool fall = std::find(b->qfall[k].begin(), b->qfall[k].end(), i) != b->qfall[k].end();
       u.Gnext = (k + 1 < p->d && !fall) ? static_cast<double*>(cores[i][k + 1]) : nullptr;
-      u.R = p->at<double>(p->o_qrR);
     }
     if (!b->upd[k].empty())
       TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_upd[k], b->upd[k].data(), sizeof(BUpd) * b->upd[k].size(),
@@ -786,6 +823,85 @@ void drop_graph(tt_batch b) {
 
 }  // namespace
 
+namespace {
+
+// average milliseconds of `reps` calls of f after one warm call
+template <typename F>
+tt_status time_ms(tt_batch b, hipEvent_t e0, hipEvent_t e1, int reps, F f, float* ms) {
+  TT_HIP_TRY(f());
+  TT_HIP_TRY(hipEventRecord(e0, b->stream));
+  for (int r = 0; r < reps; ++r) TT_HIP_TRY(f());
+  TT_HIP_TRY(hipEventRecord(e1, b->stream));
+  TT_HIP_TRY(hipEventSynchronize(e1));
+  TT_HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+  *ms /= (float)reps;
+  return TT_OK;
+}
+
+bool nj_ok(tt_batch b, int nj) { return nj == 4 || (nj == 2 && b->max_n0 <= 128); }
+
+tt_status autotune_body(tt_batch b, int reps, hipEvent_t e0, hipEvent_t e1) {
+  tt_status st;
+  float ms = 0.0f;
+  for (int k = 0; k < b->max_d; ++k) {
+    if (b->tids[k].empty()) continue;
+    // data sketch of step k
+    float best = 1e30f;
+    int bnj = b->nj[k], bfib = b->fib[k];
+    int64_t bW = b->W[k];
+    for (int nj : {2, 4}) {
+      if (!nj_ok(b, nj)) continue;
+      for (int fib : k == 0 ? std::vector<int>{4, 8} : std::vector<int>{8, 16}) {
+        if (b->slab[k] && (nj != b->nj[k] || fib != b->fib[k])) continue;   // the slab kernel has neither knob
+        b->nj[k] = nj;
+        b->fib[k] = fib;
+        std::vector<int64_t> cand{0};
+        if (k >= 1) {
+          const int64_t res = occupancy_grid(b, k, nj, fib);
+          cand = {res / 2, res, 2 * res, 4 * res, 8 * res};
+        }
+        for (int64_t W : cand) {
+          if (k >= 1 && (W < 1 || W > b->Wmax)) continue;
+          if ((st = time_ms(b, e0, e1, reps, [&]() { return launch_step_sketch(b, k, W); }, &ms))) return st;
+          if (ms < best) {
+            best = ms;
+            bnj = nj;
+            bfib = fib;
+            bW = W;
+          }
+        }
+      }
+    }
+    b->nj[k] = bnj;
+    b->fib[k] = bfib;
+    b->W[k] = bW;
+    // Gram K-chunk of step k's core updates (contents of SH and Y do not
+    // matter for the timing; the Cholesky is not run)
+    const int32_t nt = (int32_t)b->upd[k].size();
+    float gbest = 1e30f;
+    int32_t bkc = b->kchunk[k];
+    for (int32_t kc : {256, 512, 1024}) {
+      set_kchunk(b, k, kc);
+      TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_upd[k], b->upd[k].data(), sizeof(BUpd) * nt, hipMemcpyHostToDevice,
+                                b->stream));
+      const BUpd* du = reinterpret_cast<const BUpd*>(b->ws + b->o_upd[k]);
+      auto gram = [&]() -> hipError_t {
+        const hipError_t e = launch_gram_batched(du, nt, b->g_gx[k], b->stream);
+        return e != hipSuccess ? e : launch_gram_sum_batched(du, nt, b->g_count[k], b->stream);
+      };
+      if ((st = time_ms(b, e0, e1, reps, gram, &ms))) return st;
+      if (ms < gbest) {
+        gbest = ms;
+        bkc = kc;
+      }
+    }
+    set_kchunk(b, k, bkc);
+  }
+  return TT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stream, size_t* workspace_bytes,
@@ -833,7 +949,12 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
   // offset shuffles, bucket arithmetic) is shared by more entries (measured
   // on 256 uneven TTs with n_0 in [20, 60]: 1 / 2 / 4 entries per lane gave
   // 81.7 / 73.0 / 81.1 ms per sweep)
-  b->nj = max_n0 <= 128 ? 2 : 4;
+  b->max_n0 = max_n0;
+  for (int k = 0; k < TT_MAX_ORDER; ++k) {
+    b->nj[k] = max_n0 <= 128 ? 2 : 4;
+    b->fib[k] = k == 0 ? 8 : 16;
+    b->kchunk[k] = 256;
+  }
   // per-step work lists: problems of order > k, their fibre and column prefixes,
   // and partial slots per column for the largest grid
   b->tids.resize(b->max_d);
@@ -896,7 +1017,8 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
       u.nk = (int32_t)p->n[k];
       u.rk = (int32_t)p->r[k];
       u.rk1 = (int32_t)p->r[k + 1];
-      u.chunks = (int32_t)tt_gram_chunks(p->J);
+      u.kchunk = b->kchunk[k];
+      u.chunks = (int32_t)((p->J + u.kchunk - 1) / u.kchunk);
       u.lambda = p->lambda;
       const size_t np = (size_t)u.s * (u.s + 1) / 2;
       int CB = 64;
@@ -1031,6 +1153,7 @@ tt_status tt_batch_bind_workspace(tt_batch b, void* dev_ws, size_t bytes) {
                               b->stream));
   }
   TT_HIP_TRY(hipStreamSynchronize(b->stream));
+  fill_upd_buffers(b);
   b->desc_valid = false;
   b->upd_key.clear();
   drop_graph(b);
@@ -1147,32 +1270,52 @@ tt_status tt_batch_autotune(tt_batch b, const void* const* X, int32_t reps, int6
   hipEvent_t e0, e1;
   TT_HIP_TRY(hipEventCreate(&e0));
   TT_HIP_TRY(hipEventCreate(&e1));
-  for (int k = 1; k < b->max_d; ++k) {
-    if (b->tids[k].empty()) continue;
-    const int64_t res = occupancy_grid(b, k);
-    const int64_t cand[5] = {res / 2, res, 2 * res, 4 * res, 8 * res};
-    float best = 1e30f;
-    int64_t bestW = res;
-    for (int64_t W : cand) {
-      if (W < 1 || W > b->Wmax) continue;
-      TT_HIP_TRY(launch_step_sketch(b, k, W));   // warm
-      TT_HIP_TRY(hipEventRecord(e0, b->stream));
-      for (int r = 0; r < reps; ++r) TT_HIP_TRY(launch_step_sketch(b, k, W));
-      TT_HIP_TRY(hipEventRecord(e1, b->stream));
-      TT_HIP_TRY(hipEventSynchronize(e1));
-      float ms = 0.0f;
-      TT_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best) {
-        best = ms;
-        bestW = W;
-      }
-    }
-    b->W[k] = bestW;
-  }
+  st = autotune_body(b, reps, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  b->upd_key.clear();   // the timing uploads carried no core pointers
+  drop_graph(b);
+  if (st) return st;
   if (chosen)
     for (int k = 0; k < b->max_d; ++k) chosen[k] = b->W[k];
+  return TT_OK;
+}
+
+tt_status tt_batch_get_tuning(tt_batch b, int64_t* out) {
+  if (!b || !out) return tt_fail(TT_ERR_ARG, "null argument");
+  for (int k = 0; k < TT_MAX_ORDER; ++k) {
+    int64_t* o = out + (size_t)k * TT_BATCH_TUNE_FIELDS;
+    o[0] = b->W[k];
+    o[1] = b->nj[k];
+    o[2] = b->fib[k];
+    o[3] = b->kchunk[k];
+  }
+  return TT_OK;
+}
+
+tt_status tt_batch_set_tuning(tt_batch b, const int64_t* in) {
+  if (!b || !in) return tt_fail(TT_ERR_ARG, "null argument");
+  for (int k = 0; k < b->max_d; ++k) {
+    const int64_t* v = in + (size_t)k * TT_BATCH_TUNE_FIELDS;
+    if (v[0] < 0 || v[0] > b->Wmax || (k == 0 && v[0] != 0))
+      return tt_fail(TT_ERR_ARG, "step %d: workgroups %lld outside [0, %lld] (0 for step 0)", k, (long long)v[0],
+                     (long long)b->Wmax);
+    if ((v[1] != 2 && v[1] != 4) || !nj_ok(b, (int)v[1]))
+      return tt_fail(TT_ERR_ARG, "step %d: entries per lane %lld (2 needs n_0 <= 128, else 4)", k, (long long)v[1]);
+    if (k == 0 ? (v[2] != 4 && v[2] != 8) : (v[2] != 8 && v[2] != 16))
+      return tt_fail(TT_ERR_ARG, "step %d: fibres in flight %lld not in {%s}", k, (long long)v[2],
+                     k == 0 ? "4, 8" : "8, 16");
+    if (v[3] < tt_gram_chunk_min() || v[3] > 8192 || v[3] % tt_gram_chunk_min() != 0)
+      return tt_fail(TT_ERR_ARG, "step %d: Gram K-chunk %lld not a multiple of %d in [%d, 8192]", k, (long long)v[3],
+                     tt_gram_chunk_min(), tt_gram_chunk_min());
+  }
+  for (int k = 0; k < b->max_d; ++k) {
+    const int64_t* v = in + (size_t)k * TT_BATCH_TUNE_FIELDS;
+    b->W[k] = v[0];
+    b->nj[k] = (int)v[1];
+    b->fib[k] = (int)v[2];
+    set_kchunk(b, k, (int32_t)v[3]);
+  }
   drop_graph(b);
   return TT_OK;
 }

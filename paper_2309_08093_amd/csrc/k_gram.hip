@@ -34,13 +34,13 @@ __device__ __forceinline__ short to_bf16(float x) {
 template <typename T>
 __device__ __forceinline__ void gram_body(const T* __restrict__ SH, const T* __restrict__ Y, double* __restrict__ gpart,
                                           int32_t J, int32_t s, int32_t nk, int32_t tiles_c, int32_t ntiles, int blk,
-                                          int chunk) {
+                                          int chunk, int klen) {
   const int lane = threadIdx.x & 63;
   const int tile = blk * 4 + (threadIdx.x >> 6);
   if (tile >= ntiles) return;
   const int tr = tile / tiles_c, tc = tile - tr * tiles_c;
-  const int k0 = chunk * kChunk;
-  const int k1 = min(J, k0 + kChunk);
+  const int k0 = chunk * klen;
+  const int k1 = min(J, k0 + klen);
   const int ncol = s + nk;
   const int arow = tr * 16 + (lane & 15);   // row of SH^T = column of SH
   const int bcol = tc * 16 + (lane & 15);
@@ -64,7 +64,7 @@ __device__ __forceinline__ void gram_body(const T* __restrict__ SH, const T* __r
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram(const T* __restrict__ SH, const T* __restrict__ Y, double* __restrict__ gpart,
                                              int32_t J, int32_t s, int32_t nk, int32_t tiles_c, int32_t ntiles) {
-  gram_body<T>(SH, Y, gpart, J, s, nk, tiles_c, ntiles, blockIdx.x, blockIdx.y);
+  gram_body<T>(SH, Y, gpart, J, s, nk, tiles_c, ntiles, blockIdx.x, blockIdx.y, kChunk);
 }
 
 // Batched: problem blockIdx.y; blockIdx.x runs over (tile block, chunk).
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void kb_gram(const BUpd* __restrict__ d) {
   const int tb = (ntiles + 3) / 4;
   const int chunk = blockIdx.x / tb;
   if (chunk >= u.chunks) return;
-  gram_body<float>(u.SH, u.Y, u.gpart, u.J, u.s, u.nk, tiles_c, ntiles, blockIdx.x - chunk * tb, chunk);
+  gram_body<float>(u.SH, u.Y, u.gpart, u.J, u.s, u.nk, tiles_c, ntiles, blockIdx.x - chunk * tb, chunk, u.kchunk);
 }
 
 // BF16 operands, FP32 accumulation; K step 16 (4 per lane).
@@ -115,6 +115,7 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const float* __restrict__ SH,
 }  // namespace
 
 int64_t tt_gram_chunks(int64_t J) { return (J + kChunk - 1) / kChunk; }
+int32_t tt_gram_chunk_min() { return kChunk; }
 
 hipError_t launch_gram(const tt_plan_s* p, int k, const void* SH, const void* Y) {
   const int s = (int)(p->r[k] * p->r[k + 1]);

@@ -478,12 +478,17 @@ hipError_t launch_copy_f64(const tt_plan_s* p, double* dst, const double* src, i
   return hipGetLastError();
 }
 
+hipError_t launch_gram_sum_batched(const BUpd* d, int32_t nprob, int32_t max_count, hipStream_t st) {
+  if (nprob <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_gram_sum, dim3(nblk(max_count, 256), (unsigned)nprob), dim3(256), 0, st, d);
+  return hipGetLastError();
+}
+
 hipError_t launch_solve_batched(const BUpd* d, int32_t nprob, int32_t max_s, int32_t max_count, int32_t max_cb_blocks,
                                 size_t lds_chol, size_t lds_trsm, hipStream_t st) {
   if (nprob <= 0) return hipSuccess;
   (void)max_s;
-  hipLaunchKernelGGL(kb_gram_sum, dim3(nblk(max_count, 256), (unsigned)nprob), dim3(256), 0, st, d);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_gram_sum_batched(d, nprob, max_count, st);
   if (e != hipSuccess) return e;
   if ((e = tt_allow_lds(kb_chol, lds_chol)) != hipSuccess) return e;
   hipLaunchKernelGGL(kb_chol, dim3((unsigned)nprob), dim3(256), lds_chol, st, d);

@@ -217,8 +217,11 @@ struct BUpd {
   double* R;            // QR factor R
   double lambda;
   int32_t J, s, nk, rk, rk1, chunks, CB, ncols_next;   // ncols_next = n_{k+1} R_{k+2}
+  int32_t kchunk;       // Gram K-chunk (rows of SH per partial); chunks = ceil(J / kchunk)
 };
 hipError_t launch_gram_batched(const BUpd* d, int32_t nprob, int32_t gx, hipStream_t st);
+hipError_t launch_gram_sum_batched(const BUpd* d, int32_t nprob, int32_t max_count, hipStream_t st);
+int32_t tt_gram_chunk_min();   // the K-chunk the single-plan Gram uses (partial buffers are sized for it)
 size_t tt_chol_lds_bytes(int64_t s);   // dynamic LDS of the Cholesky kernel for an s x s system
 int64_t tt_chol_out_doubles(int64_t s);  // packed L plus the inverses of its 16 x 16 diagonal blocks
 hipError_t launch_solve_batched(const BUpd* d, int32_t nprob, int32_t max_s, int32_t max_count, int32_t max_cb_blocks,

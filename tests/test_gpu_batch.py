@@ -244,3 +244,101 @@ def test_autotune_keeps_results(env):
         for y0, y1 in zip(before[k], after[k]):
             if y0 is not None:
                 assert torch.equal(y0, y1)
+
+
+def _tuning_with(b, **kw):
+    steps = b.get_tuning()
+    for st in steps:
+        st.update(kw)
+    steps[0]["workgroups"] = 0
+    if "fibres_in_flight" in kw:
+        steps[0]["fibres_in_flight"] = kw["fibres_in_flight"] // 2   # k = 0 takes 4 or 8
+    return steps
+
+
+@pytest.mark.parametrize("which", ["default", "n0<=256"])
+def test_every_tuned_shape_gives_the_oracle_sketch(env, which):
+    """Every (entries per lane, fibres in flight) shape the autotuner can pick
+    computes the same sketches, integer-exact against the oracle."""
+    torch, tts = env
+    probs = PROBLEMS if which == "default" else WIDE[which]
+    say("tuned shapes %s" % which)
+    b = tts.Batch(probs)
+    Xs, Xh = make_inputs(torch, probs, integer=True)
+    njs = (2, 4) if max(p["n"][0] for p in probs) <= 128 else (4,)
+    dmax = max(len(p["n"]) for p in probs)
+    for nj in njs:
+        for fib in (8, 16):
+            b.set_tuning(_tuning_with(b, entries_per_lane=nj, fibres_in_flight=fib))
+            for k in range(dmax):
+                Ys = b.sketch_tensor(Xs, k)
+                torch.cuda.synchronize()
+                for i, p in enumerate(probs):
+                    if len(p["n"]) <= k:
+                        continue
+                    hs, vs = zip(*[b.plan_tables(i, s) for s in range(len(p["n"]))])
+                    want = sketch.data_sketch(Xh[i], p["n"], k, hs, vs, p["J"])
+                    got = Ys[i].cpu().numpy().astype(np.float64).reshape(want.shape, order="F")
+                    np.testing.assert_array_equal(got, want, err_msg="nj=%d fib=%d k=%d" % (nj, fib, k))
+
+
+def test_set_tuning_rejects_bad_values(env):
+    torch, tts = env
+    say("set_tuning arguments")
+    b = tts.Batch(WIDE["n0<=256"])          # n_0 = 200: two entries per lane cannot cover a fibre
+    before = b.get_tuning()
+    for bad in (dict(entries_per_lane=2), dict(entries_per_lane=3), dict(fibres_in_flight=12),
+                dict(gram_kchunk=300), dict(gram_kchunk=16384), dict(workgroups=1 << 20)):
+        steps = _tuning_with(b, **bad)
+        with pytest.raises(tts.TTError) as ei:
+            b.set_tuning(steps)
+        assert ei.value.status == 1, bad          # TT_ERR_ARG
+        assert b.get_tuning() == before, bad      # unchanged
+
+
+def test_gram_kchunk_and_tuning_keep_sweeps(env):
+    """Sweeps under another tuning (Gram K-chunk 1024, 4 entries per lane, 8
+    fibres in flight, twice the workgroups) match the default tuning's: only
+    the order of FP64 partial sums changes."""
+    import synth
+    torch, tts = env
+    say("tuning keeps sweeps")
+    Xs, _ = make_inputs(torch, PROBLEMS)
+    ba, bb = tts.Batch(PROBLEMS), tts.Batch(PROBLEMS)
+    steps = _tuning_with(bb, gram_kchunk=1024, entries_per_lane=4, fibres_in_flight=8)
+    for k in range(1, len(steps)):
+        steps[k]["workgroups"] = 2 * 256
+    bb.set_tuning(steps)
+    assert [st["gram_kchunk"] for st in bb.get_tuning()] == [1024] * len(steps)
+    init = [synth.random_cores(p["n"], p["ranks"], 40 + i) for i, p in enumerate(PROBLEMS)]
+    ca = [[tts.core_to_device(c) for c in cs] for cs in init]
+    cb = [[tts.core_to_device(c) for c in cs] for cs in init]
+    for t in range(3):
+        ra = ba.sweep(Xs, ca, residuals=True)
+        rb = bb.sweep(Xs, cb, residuals=True)
+        np.testing.assert_allclose(rb, ra, rtol=1e-5)
+    for i, p in enumerate(PROBLEMS):
+        Ta = als.tt_full([tts.core_to_host(c, g.shape) for c, g in zip(ca[i], init[i])])
+        Tb = als.tt_full([tts.core_to_host(c, g.shape) for c, g in zip(cb[i], init[i])])
+        assert np.linalg.norm(Ta - Tb) <= 1e-5 * np.linalg.norm(Ta), i
+
+
+def test_autotune_persists_its_choices(env, tmp_path):
+    """A tuning written to the cache file is taken back by a new batch of
+    the same problems, which then skips the timing."""
+    torch, tts = env
+    say("autotune cache")
+    Xs, _ = make_inputs(torch, PROBLEMS, integer=True)
+    cache = str(tmp_path / "tune.json")
+    b1 = tts.Batch(PROBLEMS)
+    w1 = b1.autotune(Xs, reps=1, cache=cache)
+    assert not b1.tuned_from_cache
+    b2 = tts.Batch(PROBLEMS)
+    w2 = b2.autotune(Xs, reps=1, cache=cache)
+    assert b2.tuned_from_cache and w2 == w1 and b2.get_tuning() == b1.get_tuning()
+    for st in b1.get_tuning()[1:]:
+        assert st["gram_kchunk"] in (256, 512, 1024) and st["fibres_in_flight"] in (8, 16)
+    # another batch (other problems) does not match the stored keys
+    b3 = tts.Batch(PROBLEMS[:3])
+    b3.autotune(Xs[:3], reps=1, cache=cache)
+    assert not b3.tuned_from_cache
