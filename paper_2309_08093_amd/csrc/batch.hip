@@ -216,9 +216,10 @@ __global__ __launch_bounds__(256) void k_bsketch_k(const BTensor* __restrict__ T
 // coalesced row and no per-fibre key or offset is exchanged between lanes.
 // A lane recomputes K (from the mode tables, copied to LDS) only when it
 // steps into another slab.
-constexpr int kSlabU = 8;           // 64-entry rows per lane in flight
 constexpr size_t kSlabLds = 48 << 10;   // bytes for the slab table and the mode tables
 
+// U: 64-entry rows per lane in flight (chosen per step by the autotuner)
+template <int U>
 __global__ __launch_bounds__(256) void k_bsketch_slab(const BTensor* __restrict__ T, const int32_t* __restrict__ tids,
                                                       const int64_t* __restrict__ fpre, const int64_t* __restrict__ cpre,
                                                       const int64_t* __restrict__ spre, int32_t nt, int32_t k,
@@ -292,12 +293,12 @@ __global__ __launch_bounds__(256) void k_bsketch_slab(const BTensor* __restrict_
       ++sl;
     }
     if (sl < we) locate(sl, base, K);
-    for (int64_t m0 = 0; m0 < tot; m0 += 64 * kSlabU) {
-      float x[kSlabU];
-      uint32_t pe[kSlabU], kk[kSlabU];
-      bool ok[kSlabU];
+    for (int64_t m0 = 0; m0 < tot; m0 += 64 * U) {
+      float x[U];
+      uint32_t pe[U], kk[U];
+      bool ok[U];
 #pragma unroll
-      for (int u = 0; u < kSlabU; ++u) {
+      for (int u = 0; u < U; ++u) {
         ok[u] = sl < we;
         x[u] = ok[u] ? __builtin_nontemporal_load(Xg + base + e) : 0.0f;
         pe[u] = e;
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(256) void k_bsketch_slab(const BTensor* __restrict_
         }
       }
 #pragma unroll
-      for (int u = 0; u < kSlabU; ++u)
+      for (int u = 0; u < U; ++u)
         if (ok[u]) {
           const uint32_t pk = P[pe[u]];
           uint32_t bk = (pk & TT_KEY_MASK) + (kk[u] & TT_KEY_MASK);
@@ -440,6 +441,10 @@ BKFn bk_kernel(int nj, int fib) {
   if (nj == 2) return fib == 8 ? k_bsketch_k<2, 8> : k_bsketch_k<2, 16>;
   return fib == 8 ? k_bsketch_k<4, 8> : k_bsketch_k<4, 16>;
 }
+typedef void (*BSFn)(const BTensor*, const int32_t*, const int64_t*, const int64_t*, const int64_t*, int32_t, int32_t,
+                     double*, int32_t, int32_t);
+BSFn bs_kernel(int rows) { return rows == 4 ? k_bsketch_slab<4> : k_bsketch_slab<8>; }
+
 B0Fn b0_kernel(int nj, int fib) {
   if (nj == 2) return fib == 4 ? k_bsketch_0<2, 4> : k_bsketch_0<2, 8>;
   return fib == 4 ? k_bsketch_0<4, 4> : k_bsketch_0<4, 8>;
@@ -520,7 +525,7 @@ int occupancy_grid(tt_batch b, int k, int nj, int fib) {
     ncu = 256;
   const size_t lds = step_lds(b, k);
   hipError_t e = hipErrorInvalidValue;
-  if (b->slab[k]) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_bsketch_slab, 256, lds);
+  if (b->slab[k]) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bs_kernel(fib), 256, lds);
   else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, bk_kernel(nj, fib), 256, lds);
   if (e != hipSuccess || per < 1) per = 1;
   return per * ncu;
@@ -597,8 +602,8 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
   if (W < 1) W = 1;
   const size_t lds = step_lds(b, k);
   if (b->slab[k])
-    hipLaunchKernelGGL(k_bsketch_slab, dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre, cpre, spre, nt, k,
-                       part, b->Jmax, b->slab_S[k]);
+    hipLaunchKernelGGL(bs_kernel(b->fib[k]), dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre, cpre, spre, nt,
+                       k, part, b->Jmax, b->slab_S[k]);
   else
     hipLaunchKernelGGL(bk_kernel(b->nj[k], b->fib[k]), dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre,
                        cpre, spre, nt, k, part, b->Jmax);
@@ -840,6 +845,12 @@ tt_status time_ms(tt_batch b, hipEvent_t e0, hipEvent_t e1, int reps, F f, float
 
 bool nj_ok(tt_batch b, int nj) { return nj == 4 || (nj == 2 && b->max_n0 <= 128); }
 
+// fibres (or, on slab steps, 64-entry rows) per lane group in flight
+std::vector<int> fib_choices(tt_batch b, int k) {
+  if (k == 0 || b->slab[k]) return {4, 8};
+  return {8, 16};
+}
+
 tt_status autotune_body(tt_batch b, int reps, hipEvent_t e0, hipEvent_t e1) {
   tt_status st;
   float ms = 0.0f;
@@ -851,8 +862,8 @@ tt_status autotune_body(tt_batch b, int reps, hipEvent_t e0, hipEvent_t e1) {
     int64_t bW = b->W[k];
     for (int nj : {2, 4}) {
       if (!nj_ok(b, nj)) continue;
-      for (int fib : k == 0 ? std::vector<int>{4, 8} : std::vector<int>{8, 16}) {
-        if (b->slab[k] && (nj != b->nj[k] || fib != b->fib[k])) continue;   // the slab kernel has neither knob
+      for (int fib : fib_choices(b, k)) {
+        if (b->slab[k] && nj != b->nj[k]) continue;   // the slab kernel reads whole rows
         b->nj[k] = nj;
         b->fib[k] = fib;
         std::vector<int64_t> cand{0};
@@ -952,7 +963,7 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
   b->max_n0 = max_n0;
   for (int k = 0; k < TT_MAX_ORDER; ++k) {
     b->nj[k] = max_n0 <= 128 ? 2 : 4;
-    b->fib[k] = k == 0 ? 8 : 16;
+    b->fib[k] = k == 0 ? 8 : 16;   // slab steps: rows in flight, set below
     b->kchunk[k] = 256;
   }
   // per-step work lists: problems of order > k, their fibre and column prefixes,
@@ -979,6 +990,7 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
       b->slab_tab[k] = std::max(b->slab_tab[k], (int32_t)tab);
     }
     if (sizeof(uint32_t) * ((size_t)b->slab_S[k] + b->slab_tab[k]) > kSlabLds) b->slab[k] = false;
+    if (b->slab[k]) b->fib[k] = 8;
     for (int i = 0; i < count; ++i) {
       tt_plan p = b->plans[i];
       if (p->d <= k) continue;
@@ -1302,9 +1314,10 @@ tt_status tt_batch_set_tuning(tt_batch b, const int64_t* in) {
                      (long long)b->Wmax);
     if ((v[1] != 2 && v[1] != 4) || !nj_ok(b, (int)v[1]))
       return tt_fail(TT_ERR_ARG, "step %d: entries per lane %lld (2 needs n_0 <= 128, else 4)", k, (long long)v[1]);
-    if (k == 0 ? (v[2] != 4 && v[2] != 8) : (v[2] != 8 && v[2] != 16))
-      return tt_fail(TT_ERR_ARG, "step %d: fibres in flight %lld not in {%s}", k, (long long)v[2],
-                     k == 0 ? "4, 8" : "8, 16");
+    const std::vector<int> fc = fib_choices(b, k);
+    if (v[2] != fc[0] && v[2] != fc[1])
+      return tt_fail(TT_ERR_ARG, "step %d: fibres (rows) in flight %lld not in {%d, %d}", k, (long long)v[2], fc[0],
+                     fc[1]);
     if (v[3] < tt_gram_chunk_min() || v[3] > 8192 || v[3] % tt_gram_chunk_min() != 0)
       return tt_fail(TT_ERR_ARG, "step %d: Gram K-chunk %lld not a multiple of %d in [%d, 8192]", k, (long long)v[3],
                      tt_gram_chunk_min(), tt_gram_chunk_min());

@@ -247,12 +247,14 @@ def test_autotune_keeps_results(env):
 
 
 def _tuning_with(b, **kw):
+    """The batch's tuning with kw applied; fibres_in_flight (8 or 16) maps to
+    4 or 8 at k = 0 and on slab steps, whose kernels take those."""
     steps = b.get_tuning()
-    for st in steps:
+    for k, st in enumerate(steps):
         st.update(kw)
+        if "fibres_in_flight" in kw and (k == 0 or b.sketch_kernel(k) == "k_bsketch_slab"):
+            st["fibres_in_flight"] = kw["fibres_in_flight"] // 2
     steps[0]["workgroups"] = 0
-    if "fibres_in_flight" in kw:
-        steps[0]["fibres_in_flight"] = kw["fibres_in_flight"] // 2   # k = 0 takes 4 or 8
     return steps
 
 
@@ -336,8 +338,9 @@ def test_autotune_persists_its_choices(env, tmp_path):
     b2 = tts.Batch(PROBLEMS)
     w2 = b2.autotune(Xs, reps=1, cache=cache)
     assert b2.tuned_from_cache and w2 == w1 and b2.get_tuning() == b1.get_tuning()
-    for st in b1.get_tuning()[1:]:
-        assert st["gram_kchunk"] in (256, 512, 1024) and st["fibres_in_flight"] in (8, 16)
+    for k, st in enumerate(b1.get_tuning()):
+        slabs = k == 0 or b1.sketch_kernel(k) == "k_bsketch_slab"
+        assert st["gram_kchunk"] in (256, 512, 1024) and st["fibres_in_flight"] in ((4, 8) if slabs else (8, 16))
     # another batch (other problems) does not match the stored keys
     b3 = tts.Batch(PROBLEMS[:3])
     b3.autotune(Xs[:3], reps=1, cache=cache)
