@@ -248,8 +248,12 @@ def exact_section(cfg, X, init, args, dev):
     torch.cuda.synchronize()
     ms_sweep = e0.elapsed_time(e1) / reps
     passes = {}
-    for k, name, inter in ((0, "right_chain_k0", N // n[-1] * R[d - 1]), (d - 1, "left_interfaces_k%d" % (d - 1),
-                                                                           N // n[0] * R[1])):
+    # the right chain of core 0 contracts the two slowest modes in one pass
+    # (merged cores) when d >= 3, so its first write is N / (n_{d-2} n_{d-1})
+    # R_{d-2} values
+    right_inter = N // (n[-1] * n[-2]) * R[d - 2] if d >= 3 else N // n[-1] * R[d - 1]
+    for k, name, inter in ((0, "right_chain_k0", right_inter), (d - 1, "left_interfaces_k%d" % (d - 1),
+                                                                N // n[0] * R[1])):
         plan.exact_rhs(X, cores, k)
         torch.cuda.synchronize()
         e0.record(stream)

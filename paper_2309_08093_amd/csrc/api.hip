@@ -327,7 +327,7 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_zo = fuse ? take(ws * (size_t)p->J_cap * (size_t)p->n[0] * (size_t)p->n[1]) : 0;
   p->o_spacc = take(sizeof(double) * (size_t)p->J_cap * (size_t)p->tab_off[d]);
   // exact update
-  p->o_exphi = p->o_exch = p->o_expart = p->o_exgram = 0;
+  p->o_exphi = p->o_exch = p->o_expart = p->o_exgram = p->o_exmerge = 0;
   p->ex_phi = p->ex_chain = p->ex_part = 0;
   if (p->flags & TT_FLAG_EXACT) {
     tt_exact_sizes(p, &p->ex_phi, &p->ex_chain);
@@ -337,6 +337,8 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
     p->o_exch = take(ws * 2 * (size_t)p->ex_chain);
     p->o_expart = take(sizeof(double) * (size_t)p->ex_part);
     p->o_exgram = take(sizeof(double) * 512);
+    const int64_t nmerge = tt_exact_merge_doubles(p);
+    p->o_exmerge = nmerge > 0 ? take(sizeof(double) * (size_t)nmerge) : 0;
   }
   p->ws_need = o;
   p->ws = nullptr;

@@ -185,6 +185,65 @@ __global__ __launch_bounds__(256) void k_contract_slow(const TT* __restrict__ T,
   }
 }
 
+// The contraction of k_contract_slow for a long kk range (the two slow modes
+// merged, KK = n_a n_b): the core rows of the slice are staged through LDS,
+// CH at a time, so that the waves of a workgroup read them from LDS instead
+// of each streaming the whole slice of the core from L2.
+template <typename TT, typename OT, int RB>
+__global__ __launch_bounds__(256) void k_contract_merged(const TT* __restrict__ T, const double* __restrict__ G,
+                                                         OT* __restrict__ out, double* __restrict__ part, int64_t M,
+                                                         int64_t KK, int32_t Rout, int32_t S) {
+  constexpr int U = 16, CH = 256;
+  __shared__ double cs[CH * RB];
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  const int64_t k0 = (int64_t)s * KK / S, k1 = (int64_t)(s + 1) * KK / S;
+  double acc[RB];
+#pragma unroll
+  for (int a = 0; a < RB; ++a) acc[a] = 0.0;
+  const TT* col = T + (m < M ? m : 0);
+  for (int64_t c0 = k0; c0 < k1; c0 += CH) {
+    const int ch = (int)(k1 - c0 < CH ? k1 - c0 : CH);
+    __syncthreads();   // the previous chunk has been read
+    for (int i = threadIdx.x; i < ch * RB; i += blockDim.x) {
+      const int u = i / RB, a = i - u * RB;
+      cs[i] = a < Rout ? G[(int64_t)Rout * (c0 + u) + a] : 0.0;
+    }
+    __syncthreads();
+    if (m < M) {
+      int u0 = 0;
+      for (; u0 + U <= ch; u0 += U) {
+        TT x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = col[M * (c0 + u0 + u)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double xv = to_f64<TT>(x[u]);
+          const double* g = cs + (u0 + u) * RB;
+#pragma unroll
+          for (int a = 0; a < RB; ++a) acc[a] = fma(xv, g[a], acc[a]);
+        }
+      }
+      for (; u0 < ch; ++u0) {
+        const double xv = to_f64<TT>(col[M * (c0 + u0)]);
+        const double* g = cs + u0 * RB;
+#pragma unroll
+        for (int a = 0; a < RB; ++a) acc[a] = fma(xv, g[a], acc[a]);
+      }
+    }
+  }
+  if (m < M) {
+#pragma unroll
+    for (int a = 0; a < RB; ++a) {
+      if (a >= Rout) break;
+      if (S == 1)
+        out[m + M * a] = (OT)acc[a];
+      else
+        part[((int64_t)s * Rout + a) * M + m] = acc[a];
+    }
+  }
+}
+
 // out[e] = sum over the S slices of part[s count + e], FP64, in slice order
 template <typename OT>
 __global__ void k_sum_slices(const double* __restrict__ part, OT* __restrict__ out, int64_t count, int32_t S) {
@@ -340,6 +399,44 @@ hipError_t slow_t(const tt_plan_s* p, const void* Tv, const double* G, void* out
 }
 
 // one contraction step on input of storage type xdt (X itself) or the work type
+template <typename TT, typename WT>
+hipError_t merged_t(const tt_plan_s* p, const void* Tv, const double* G, void* outv, int64_t M, int64_t KK,
+                    int32_t Rout) {
+  const TT* T = static_cast<const TT*>(Tv);
+  WT* out = static_cast<WT*>(outv);
+  const int64_t blocks = (M + 255) / 256;
+  const int32_t S = pick_slices(blocks, KK, M * Rout, p->ex_part);
+  double* part = p->at<double>(p->o_expart);
+  const dim3 grid((unsigned)blocks, (unsigned)S);
+  if (Rout <= 4)
+    hipLaunchKernelGGL((k_contract_merged<TT, WT, 4>), grid, dim3(256), 0, p->stream, T, G, out, part, M, KK, Rout, S);
+  else if (Rout <= 8)
+    hipLaunchKernelGGL((k_contract_merged<TT, WT, 8>), grid, dim3(256), 0, p->stream, T, G, out, part, M, KK, Rout, S);
+  else if (Rout <= 12)
+    hipLaunchKernelGGL((k_contract_merged<TT, WT, 12>), grid, dim3(256), 0, p->stream, T, G, out, part, M, KK, Rout,
+                       S);
+  else
+    hipLaunchKernelGGL((k_contract_merged<TT, WT, 16>), grid, dim3(256), 0, p->stream, T, G, out, part, M, KK, Rout,
+                       S);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || S == 1) return e;
+  hipLaunchKernelGGL(k_sum_slices<WT>, dim3(nblk(M * Rout, 256)), dim3(256), 0, p->stream, part, out, M * Rout, S);
+  return hipGetLastError();
+}
+
+hipError_t contract_merged(const tt_plan_s* p, bool input_is_x, const void* T, const double* C, void* out, int64_t M,
+                           int64_t KK, int32_t Rout) {
+  const tt_dtype it = input_is_x ? p->xdt : p->wdt;
+  if (p->wdt == TT_F64) {
+    if (it == TT_F64) return merged_t<double, double>(p, T, C, out, M, KK, Rout);
+    if (it == TT_F32) return merged_t<float, double>(p, T, C, out, M, KK, Rout);
+    return merged_t<uint16_t, double>(p, T, C, out, M, KK, Rout);
+  }
+  if (it == TT_F64) return merged_t<double, float>(p, T, C, out, M, KK, Rout);
+  if (it == TT_F32) return merged_t<float, float>(p, T, C, out, M, KK, Rout);
+  return merged_t<uint16_t, float>(p, T, C, out, M, KK, Rout);
+}
+
 hipError_t contract(const tt_plan_s* p, bool fast, bool input_is_x, const void* T, const double* G, void* out,
                     int64_t a, int64_t b, int32_t Rout) {
   const tt_dtype it = input_is_x ? p->xdt : p->wdt;
@@ -353,7 +450,35 @@ hipError_t contract(const tt_plan_s* p, bool fast, bool input_is_x, const void* 
   return fast ? fast_t<uint16_t, float>(p, T, G, out, a, b, Rout) : slow_t<uint16_t, float>(p, T, G, out, a, b, Rout);
 }
 
+// C(a, i + n_a j) = sum_b Ga(a, i, b) Gb(b, j, 0): the last two cores merged
+// into one core of shape (R_a, n_a n_b, 1), so that the first step of a right
+// chain contracts both slow modes in one pass over its input and writes
+// R_a N' / (n_a n_b) values instead of R_b N' / n_b (N' the input's size):
+// on an X-sized input the large intermediate write, which costs HBM time in
+// a read stream, disappears.  FP64, one thread per entry.
+__global__ void k_merge_cores(const double* __restrict__ Ga, const double* __restrict__ Gb, double* __restrict__ C,
+                              int32_t Ra, int32_t na, int32_t Rb, int32_t nb) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)Ra * na * nb;
+  if (e >= total) return;
+  const int32_t a = (int32_t)(e % Ra);
+  const int64_t ij = e / Ra;
+  const int32_t i = (int32_t)(ij % na), j = (int32_t)(ij / na);
+  double s = 0.0;
+  for (int b = 0; b < Rb; ++b) s = fma(Ga[a + (int64_t)Ra * (i + (int64_t)na * b)], Gb[b + (int64_t)Rb * j], s);
+  C[e] = s;
+}
+
 }  // namespace
+
+// Doubles of the merged last two cores (0 when the plan has fewer than 3
+// modes or the merged core would exceed 2^23 doubles)
+int64_t tt_exact_merge_doubles(const tt_plan_s* p) {
+  const int d = p->d;
+  if (d < 3) return 0;
+  const int64_t c = p->r[d - 2] * p->n[d - 2] * p->n[d - 1];
+  return c <= ((int64_t)1 << 23) ? c : 0;
+}
 
 // Sizes of the exact path's buffers (work-type values): the left interfaces
 // Phi_1 .. Phi_{d-1} and the right chains of every Phi_k.
@@ -394,7 +519,24 @@ hipError_t launch_exact_right(const tt_plan_s* p, const void* phi_k, bool is_x, 
   bool cur_x = is_x;
   char* bufs[2] = {p->ws + p->o_exch, p->ws + p->o_exch + p->wsize() * p->ex_chain};
   int which = 0;
-  for (int s = d - 1; s > k; --s) {
+  int s = d - 1;
+  if (p->o_exmerge && d - 2 > k) {
+    // modes d-1 and d-2 in one pass, through the merged core (R_d = 1)
+    double* C = p->at<double>(p->o_exmerge);
+    const int32_t Ra = (int32_t)p->r[d - 2], na = (int32_t)p->n[d - 2], Rb = (int32_t)p->r[d - 1],
+                  nb = (int32_t)p->n[d - 1];
+    hipLaunchKernelGGL(k_merge_cores, dim3(nblk((int64_t)Ra * na * nb, 256)), dim3(256), 0, p->stream, G[d - 2],
+                       G[d - 1], C, Ra, na, Rb, nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    M /= (int64_t)na * nb;
+    if ((e = contract_merged(p, cur_x, cur, C, bufs[which], M, (int64_t)na * nb, Ra)) != hipSuccess) return e;
+    cur = bufs[which];
+    cur_x = false;
+    which ^= 1;
+    s = d - 3;
+  }
+  for (; s > k; --s) {
     M /= p->n[s];
     const int64_t KK = p->n[s] * p->r[s + 1];
     hipError_t e = contract(p, false, cur_x, cur, G[s], bufs[which], M, KK, (int32_t)p->r[s]);

@@ -61,6 +61,7 @@ struct tt_plan_s {
   // ex_phi work-type values, two right-chain buffers of ex_chain, ex_part FP64
   // slice partials, the two Gram factors (2 x 256 doubles)
   size_t o_exphi, o_exch, o_expart, o_exgram;
+  size_t o_exmerge;            // the last two cores merged (FP64), 0: not used
   size_t o_spacc;              // FP64 accumulators of the sparse sketches (J_cap x sum n)
   size_t o_chg;                // core change: 2 d partial sums and the result (FP64)
   int64_t ex_phi, ex_chain, ex_part;
@@ -147,6 +148,7 @@ hipError_t launch_sketch_sparse(const tt_plan_s* p, int64_t nnz, const int32_t* 
                                 void* Y);
 // exact update (k_exact.hip)
 void tt_exact_sizes(const tt_plan_s* p, int64_t* phi, int64_t* chain);
+int64_t tt_exact_merge_doubles(const tt_plan_s* p);
 hipError_t launch_exact_left(const tt_plan_s* p, const void* phi_k, bool is_x, int k, const double* Gk, void* phi_next);
 hipError_t launch_exact_right(const tt_plan_s* p, const void* phi_k, bool is_x, int k, const double* const* G,
                               const void** result);
