@@ -620,13 +620,19 @@ def stored_traffic(kernel, config, source="k_sketch.hip", step=None):
 
 
 def probe_traffic(plan, X, d, J, n, dev):
-    """One launch of every data sketch and one device-to-device copy of X,
-    bracketed by prints: the workload of the FETCH_SIZE / WRITE_SIZE runs."""
+    """The data sketches of a sweep as the sweep runs them (tt_sketch_tensor_all:
+    the fused k = 0 pass when the plan fuses, then the other passes), one
+    launch of every single-mode data sketch, and one device-to-device copy of
+    X, bracketed by prints: the workload of the FETCH_SIZE / WRITE_SIZE runs."""
     import torch
     Ys = [torch.empty(J * n[k], dtype=plan.wdtype, device=dev) for k in range(d)]
     for k in range(d):                      # warm (fibre lists, caches of tables)
         plan.sketch_tensor(X, k, Ys[k])
+    plan.sketch_tensor_all(X)
     torch.cuda.synchronize()
+    plan.sketch_tensor_all(X)
+    torch.cuda.synchronize()
+    print("[probe] all sketches of a sweep, sources %s" % (plan.sketch_sources(),), flush=True)
     for k in range(d):
         plan.sketch_tensor(X, k, Ys[k])
         torch.cuda.synchronize()
@@ -745,20 +751,22 @@ def main():
     wbytes = 8 if cfg["wd"] == "f64" else 4
     outer_bytes = J * n[0] * n[1] * wbytes if fused else 0
 
-    def roof(cls, kernel, nbytes):
+    def roof(cls, kernel, nbytes, traffic_kernel):
         ms, cnt = prof[cls]
         if cnt == 0:
             return None
         avg_s = ms / cnt * 1e-3
         gbps = nbytes / avg_s / 1e9
         return {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": stored_traffic(kernel, args.config),
+                "frac": round(gbps / HBM_PEAK_GBPS, 4), "traffic": stored_traffic(traffic_kernel, args.config),
                 "kernel": kernel, "avg_launch_ms": round(ms / cnt, 4), "launches": cnt,
                 "bytes_per_launch": nbytes}
 
     kern_k = sorted(set(plan.sketch_kernel(k) for k in range(1, d) if src[k] == k))
-    rfk = roof("sketch_k", "+".join(kern_k), N * xbytes)
-    rf0 = roof("sketch_k0", plan.sketch_kernel(0) + ("+outer" if fused else ""), N * xbytes + outer_bytes)
+    rfk = roof("sketch_k", "+".join(kern_k), N * xbytes, "+".join(kern_k))
+    # the fused k = 0 pass is k_sketch_mode0_outer (X read, outer sketch written)
+    rf0 = roof("sketch_k0", plan.sketch_kernel(0) + ("+outer" if fused else ""), N * xbytes + outer_bytes,
+               "k_sketch_mode0_outer" if fused else plan.sketch_kernel(0))
     rf, rf_other = (rfk, rf0) if prof["sketch_k"][0] >= prof["sketch_k0"][0] else (rf0, rfk)
     # per-class times from separate sweeps with every class timed
     n_cls = min(args.steps, 5)
