@@ -816,16 +816,20 @@ def main():
         plan2 = tts.Plan(n, R, J, lam, seed=args.seed, x_dtype=cfg["xd"], work_dtype=cfg["wd"], gram=cfg["gram"],
                          device=dev, serial=False)
         cores3 = [tts.core_to_device(c, dev) for c in init]
-        for _ in range(args.warmup):
+        for _ in range(max(3, args.warmup)):
             plan2.als_sweep(X, cores3)
         torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(args.steps):
+        evs2 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        evs2[0].record(stream)
+        for t in range(args.steps):
             plan2.als_sweep(X, cores3)
-        ev1.record(stream)
+            evs2[t + 1].record(stream)
         torch.cuda.synchronize()
-        ms2 = ev0.elapsed_time(ev1) / args.steps
-        out["overlapped_schedule"] = {"ms_per_step": ms2, "value": d * N / (ms2 * 1e-3), "unit": "entries/s"}
+        ms2 = float(np.median([evs2[t].elapsed_time(evs2[t + 1]) for t in range(args.steps)]))
+        out["overlapped_schedule"] = {"ms_per_step": ms2, "value": d * N / (ms2 * 1e-3), "unit": "entries/s",
+                                      "reserved_cus": "the library default: the CUs of one XCD kept from the sketches",
+                                      "note": "data sketches on a CU-masked side stream beside the core updates; "
+                                              "median over the timed sweeps"}
         del plan2, cores3
 
     # each data sketch alone on the plan's stream (no concurrent core updates)

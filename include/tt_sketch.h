@@ -264,8 +264,10 @@ tt_status tt_als_sweep(tt_plan plan, const void* X, void* const* cores, double* 
  * stream; both fork from and join back into the plan's stream, so the call
  * stays asynchronous and ordered with respect to it.  reserved_cus CUs are
  * left out of the side stream's CU mask (hipExtStreamCreateWithCUMask) for
- * the short kernels of the core updates; 0 (the default) gives the side
- * stream every CU.  TT_ERR_ARG if reserved_cus is negative or not below the
+ * the short kernels of the core updates; 0 gives the side stream every CU.
+ * The default (before any call) reserves the CUs of one XCD (CU count / 8;
+ * the runtime numbers CUs XCD by XCD), which keeps the two streams on
+ * separate L2s.  TT_ERR_ARG if reserved_cus is negative or not below the
  * device's CU count.  Synchronises and recreates the plan's streams. */
 tt_status tt_plan_set_overlap(tt_plan plan, int32_t reserved_cus);
 

@@ -389,16 +389,27 @@ int device_cus() {
   return n;
 }
 
+// CUs kept from the side stream: the plan's setting, or by default those of
+// one XCD.  The runtime numbers CUs XCD by XCD (ncu / 8 per XCD), and a
+// reservation of exactly one XCD keeps the two streams on separate L2s:
+// measured on the 200^4 sweep, 32 CUs gave 4.56 ms, 0 gave 4.94 ms, and 24,
+// 40 or 48 (an XCD split between the streams) 5.46-5.63 ms.
+int reserved_of(const tt_plan_s* p, int ncu) {
+  if (p->reserved_cus >= 0) return p->reserved_cus;
+  return (ncu >= 64 && ncu % 8 == 0) ? ncu / 8 : 0;
+}
+
 // The side stream carries the data sketches; its CU mask leaves the first
-// reserved_cus CUs (in the runtime's CU numbering) to the chain stream, so
+// reserved CUs (in the runtime's CU numbering) to the chain stream, so
 // the short latency-bound kernels of the core updates are not queued behind
 // the persistent sketch grids.
 tt_status make_streams(tt_plan p) {
   if (p->side) return TT_OK;
   const int ncu = device_cus();
-  if (p->reserved_cus > 0 && ncu > p->reserved_cus) {
+  const int reserved = reserved_of(p, ncu);
+  if (reserved > 0 && ncu > reserved) {
     std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
-    for (int i = p->reserved_cus; i < ncu; ++i) mask[i / 32] |= 1u << (i % 32);
+    for (int i = reserved; i < ncu; ++i) mask[i / 32] |= 1u << (i % 32);
     TT_HIP_TRY(hipExtStreamCreateWithCUMask(&p->side, (uint32_t)mask.size(), mask.data()));
   } else {
     TT_HIP_TRY(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
@@ -818,7 +829,8 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
     TT_HIP_TRY(hipStreamWaitEvent(p->chain, p->ev_fork, 0));
     p->stream = p->side;
     const int ncu = device_cus();
-    p->sketch_cus = (p->reserved_cus > 0 && ncu > p->reserved_cus) ? ncu - p->reserved_cus : 0;
+    const int reserved = reserved_of(p, ncu);
+    p->sketch_cus = (reserved > 0 && ncu > reserved) ? ncu - reserved : 0;
     if ((st = sort_lists())) return st;
     for (int k = 0; k < d; ++k) {
       void* Yk = Yall + p->wsize() * p->J * p->tab_off[k];

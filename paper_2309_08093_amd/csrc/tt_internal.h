@@ -179,7 +179,7 @@ hipError_t launch_copy_f64(const tt_plan_s* p, double* dst, const double* src, i
 #define TT_SKETCH_MAX_WG 4096
 // CUs an overlapped sweep keeps free of the data sketches by default
 #ifndef TT_DEFAULT_RESERVED_CUS
-#define TT_DEFAULT_RESERVED_CUS 0
+#define TT_DEFAULT_RESERVED_CUS (-1)   // -1: the CUs of one XCD (CU count / 8), else 0
 #endif
 int64_t tt_sketch_workgroups(const tt_plan_s* p, int k, int64_t resident);   // k >= 1 sketch grid
 int64_t tt_sketch_slots(const tt_plan_s* p, int k, int64_t W);              // partials per column
