@@ -163,3 +163,57 @@ def test_set_sketch_validates(abi):
     assert lib.tt_plan_get_sketch(h, ctypes.byref(J), ctypes.byref(lam)) == abi.TT_OK
     assert (J.value, lam.value) == (500, 1e-2)
     lib.tt_plan_destroy(h)
+
+
+def test_core_change_and_sparse_validate_before_device_work(abi):
+    lib = abi.load()
+    st, h, _ = _plan(abi, [9, 12, 7], [1, 3, 4, 1], J=96)
+    out = ctypes.c_double()
+    assert lib.tt_core_change(None, None, None, ctypes.byref(out)) == abi.TT_ERR_ARG
+    assert lib.tt_core_change(h, None, None, ctypes.byref(out)) == abi.TT_ERR_WORKSPACE   # nothing bound yet
+    assert lib.tt_sketch_sparse(None, 0, None, None, 0, None) == abi.TT_ERR_ARG
+    assert lib.tt_sketch_sparse_all(h, 0, None, None, None) == abi.TT_ERR_WORKSPACE
+    lib.tt_plan_destroy(h)
+
+
+def test_batch_tuning_round_trip_and_validation(abi):
+    """A batch plan (no workspace, no device work) exports its default tuning
+    (TT_BATCH_TUNE_FIELDS per step: workgroups, entries per lane, fibres or
+    rows in flight, Gram K-chunk) and rejects bad values without changing it."""
+    lib = abi.load()
+    probs = [([9, 12, 7], [1, 3, 4, 1]), ([20, 8, 11, 6], [1, 4, 5, 3, 1])]
+    keep = []
+    descs = (abi.PlanDesc * len(probs))()
+    for i, (n, r) in enumerate(probs):
+        na = (ctypes.c_int64 * len(n))(*n)
+        ra = (ctypes.c_int64 * len(r))(*r)
+        keep += [na, ra]
+        descs[i] = abi.PlanDesc(len(n), na, ra, 96, 1e-3, i, abi.TT_F32, abi.TT_F32, abi.TT_GRAM_WORK, 0)
+    ws = ctypes.c_size_t(0)
+    h = ctypes.c_void_p()
+    assert lib.tt_batch_plan(len(probs), ctypes.cast(descs, ctypes.c_void_p), None, ctypes.byref(ws),
+                             ctypes.byref(h)) == abi.TT_OK
+    F = abi.BATCH_TUNE_FIELDS
+    buf = (ctypes.c_int64 * (abi.MAX_ORDER * F))()
+    assert lib.tt_batch_get_tuning(h, buf) == abi.TT_OK
+    before = list(buf)
+    # defaults: occupancy-sized grids, 2 entries per lane (n_0 <= 128), 8 fibres at k = 0,
+    # 16 at k = 1, 8 rows on the slab steps, K-chunk 256
+    assert [before[k * F:(k + 1) * F] for k in range(4)] == [[0, 2, 8, 256], [0, 2, 16, 256], [0, 2, 8, 256],
+                                                             [0, 2, 8, 256]]
+    assert lib.tt_batch_set_tuning(h, buf) == abi.TT_OK
+    for field, bad in ((1, 3), (2, 12), (3, 300), (3, 16384), (0, -1)):
+        b2 = (ctypes.c_int64 * (abi.MAX_ORDER * F))(*before)
+        b2[F * 1 + field] = bad
+        assert lib.tt_batch_set_tuning(h, b2) == abi.TT_ERR_ARG, (field, bad)
+        assert lib.tt_batch_get_tuning(h, buf) == abi.TT_OK and list(buf) == before
+    b2 = (ctypes.c_int64 * (abi.MAX_ORDER * F))(*before)
+    b2[0] = 512                       # step 0 has no workgroup count
+    assert lib.tt_batch_set_tuning(h, b2) == abi.TT_ERR_ARG
+    b2 = (ctypes.c_int64 * (abi.MAX_ORDER * F))(*before)
+    b2[F * 2 + 2], b2[F * 2 + 3] = 4, 1024   # slab step: 4 rows; any K-chunk multiple of 256
+    assert lib.tt_batch_set_tuning(h, b2) == abi.TT_OK
+    assert lib.tt_batch_get_tuning(h, buf) == abi.TT_OK and buf[F * 2 + 2] == 4 and buf[F * 2 + 3] == 1024
+    assert lib.tt_batch_get_tuning(None, buf) == abi.TT_ERR_ARG
+    assert lib.tt_batch_set_tuning(h, None) == abi.TT_ERR_ARG
+    lib.tt_batch_destroy(h)
