@@ -448,8 +448,13 @@ tt_status tt_batch_set_graph(tt_batch batch, int32_t enable);
 
 /* The batched data sketch of step k alone: Y[i] (J_i x n_k, column-major,
  * FP32, device) for every problem of order > k; Y[i] of the others is not
- * touched.  X: count device pointers.  Y == NULL runs the launch only (the
- * results stay in the problems' plans), e.g. to time it. */
+ * touched.  X: count device pointers.  Problems whose plans take Y_1 from
+ * the outer sketch of the k = 0 pass (tt_plan_sketch_sources) get it the
+ * same way here: their step-0 launch writes that sketch beside Y_0, and
+ * step 1 reads it back instead of X, so asking for k = 1 runs step 0 first.
+ * Y == NULL runs the launches of step k only (the results stay in the
+ * problems' plans; at k = 1 the outer sketch is read as step 0 left it),
+ * e.g. to time them. */
 tt_status tt_batch_sketch_tensor(tt_batch batch, const void* const* X, int32_t k, void* const* Y);
 
 /* Which data-sketch kernel the batched launch of step k runs (host query, no

@@ -459,6 +459,16 @@ class Batch:
         check(_lib.tt_plan_get_tables(ph, int(s), h, v), "tt_plan_get_tables")
         return np.array(h, dtype=np.int64), np.array(v, dtype=np.int8)
 
+    def sketch_sources(self, i):
+        """tt_plan_sketch_sources of problem i's plan: entry k is the mode
+        whose pass produces Y_k (0 at k = 1: Y_1 from the outer sketch)."""
+        ph = ctypes.c_void_p()
+        check(_lib.tt_batch_get_plan(self._h, int(i), ctypes.byref(ph)), "tt_batch_get_plan")
+        d = len(self.problems[i]["n"])
+        src = (ctypes.c_int32 * d)()
+        check(_lib.tt_plan_sketch_sources(ph, src), "tt_plan_sketch_sources")
+        return list(src)
+
     def set_graph(self, enable=True):
         check(_lib.tt_batch_set_graph(self._h, 1 if enable else 0), "tt_batch_set_graph")
 

@@ -44,6 +44,7 @@ struct BTensor {
   const uint32_t* tab;       // packed tables of all modes
   const uint32_t* off;       // k = 0: bucket offsets of the outer tuples (J + 1)
   const uint32_t* sorted;    // k = 0: outer tuples sorted by bucket
+  float* zo;                 // problems whose Y_1 comes from the k = 0 pass: its outer sketch, else null
   int32_t n[TT_MAX_ORDER];
   int32_t toff[TT_MAX_ORDER];
   int32_t d;
@@ -384,6 +385,10 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
     const uint32_t h1 = t1 & TT_KEY_MASK;
     const uint32_t c = b >= h1 ? b - h1 : b + J - h1;
     const uint32_t beg = offg[c], end = offg[c + 1];
+    // row (i_1, b): the outer tuples of key b - h_1(i_1), outer signs only
+    double row[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) row[q] = 0.0;
     for (uint32_t e0 = beg; e0 < end; e0 += 64) {
       const uint32_t itl = (e0 + lane < end) ? sortg[e0 + lane] : 0u;
       const int nb = (end - e0) < 64u ? (int)(end - e0) : 64;
@@ -394,7 +399,7 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
         for (int u = 0; u < FIB; ++u) {   // all loads first, then the sums
           const int idx = u0 + u * G + gi;
           const uint32_t item = (uint32_t)__shfl((int)itl, idx & 63, 64);
-          sg[u] = (item ^ t1) & TT_KEY_SIGN;
+          sg[u] = item & TT_KEY_SIGN;
           const gfloat base = Xg + ((int64_t)(item & TT_KEY_MASK) * n1 + i1) * (int64_t)n0;
 #pragma unroll
           for (int q = 0; q < NJ; ++q) {
@@ -403,11 +408,31 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
           }
         }
 #pragma unroll
-        for (int u = 0; u < FIB; ++u)   // in list order, as before
+        for (int u = 0; u < FIB; ++u)   // in list order
 #pragma unroll
-          for (int q = 0; q < NJ; ++q) acc[q] += signed_f64(x[u][q], sg[u]);
+          for (int q = 0; q < NJ; ++q) row[q] += signed_f64(x[u][q], sg[u]);
       }
     }
+    if (t.zo) {
+      // the row summed over the lane groups is the outer sketch of (i_1, b):
+      // zo[(b n_1 + i_1) n_0 + i_0] (the rows of one workgroup contiguous),
+      // every (i_1, b) written once
+      double rr[NJ];
+#pragma unroll
+      for (int q = 0; q < NJ; ++q) rr[q] = row[q];
+      for (int m = LPF; m < 64; m <<= 1)
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) rr[q] += __shfl_xor(rr[q], m, 64);
+      if (gi == 0)
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) {
+          const int i0 = v + LPF * q;
+          if (i0 < n0) t.zo[((int64_t)b * n1 + i1) * n0 + i0] = (float)rr[q];
+        }
+    }
+    const bool neg1 = (t1 & TT_KEY_SIGN) != 0;
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) acc[q] += neg1 ? -row[q] : row[q];
   }
   for (int m = LPF; m < 64; m <<= 1)
 #pragma unroll
@@ -421,6 +446,37 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
     for (int ww = 0; ww < NW; ++ww) s += red[ww][i];
     t.Y[b + (int64_t)J * i] = (float)s;
   }
+}
+
+// Y_1 of a problem whose k = 0 step wrote its outer sketch: workgroup
+// (i_1, f) adds row (r, i_1) of the sketch at bucket r - h_1(i_1) + h_0(i_0)
+// with the sign of i_0, in a J-entry FP64 LDS array, and writes column i_1
+// of Y_1.
+__global__ __launch_bounds__(256) void kb_y1_outer(const BTensor* __restrict__ T, const int32_t* __restrict__ fids) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const BTensor& t = T[fids[blockIdx.y]];
+  const int i1 = blockIdx.x;
+  const int n0 = t.n[0];
+  if (i1 >= t.n[1]) return;
+  const uint32_t J = t.J;
+  double* acc = reinterpret_cast<double*>(smem_raw);
+  uint32_t* t0 = reinterpret_cast<uint32_t*>(acc + J);
+  for (uint32_t q = threadIdx.x; q < J; q += blockDim.x) acc[q] = 0.0;
+  for (int q = threadIdx.x; q < n0; q += blockDim.x) t0[q] = t.tab[t.toff[0] + q];
+  __syncthreads();
+  const uint32_t h1 = t.tab[t.toff[1] + i1] & TT_KEY_MASK;
+  const int64_t n1 = t.n[1];
+  const uint32_t tot = J * (uint32_t)n0;
+  for (uint32_t q = threadIdx.x; q < tot; q += blockDim.x) {
+    const uint32_t r = q / (uint32_t)n0, i0 = q - r * (uint32_t)n0;
+    const uint32_t tv = t0[i0];
+    uint32_t bk = (r >= h1 ? r - h1 : r + J - h1) + (tv & TT_KEY_MASK);
+    bk = bk >= J ? bk - J : bk;
+    atomicAdd(&acc[bk], signed_f64(t.zo[((int64_t)r * n1 + i1) * n0 + i0], tv & TT_KEY_SIGN));
+  }
+  __syncthreads();
+  float* y = t.Y + (int64_t)J * t.toff[1] + (int64_t)J * i1;
+  for (uint32_t q = threadIdx.x; q < J; q += blockDim.x) y[q] = (float)acc[q];
 }
 
 __global__ void k_set_i64(int64_t* p, int64_t v) {
@@ -466,9 +522,15 @@ struct tt_batch_s {
   // sketch, Gram K-chunk of the core updates (the workgroup count is W below)
   int nj[TT_MAX_ORDER] = {}, fib[TT_MAX_ORDER] = {};
   int32_t kchunk[TT_MAX_ORDER] = {};
-  // per step k
-  std::vector<std::vector<int32_t>> tids;
+  // per step k: problems of order > k (core updates), and the problems whose
+  // data sketch the step's launch covers with their unit prefixes (at k = 1
+  // the problems in fids are left out: their Y_1 comes from the outer sketch
+  // of the k = 0 step)
+  std::vector<std::vector<int32_t>> tids, stids;
   std::vector<std::vector<int64_t>> fpre, cpre, spre;
+  std::vector<int32_t> fids;
+  size_t o_fids = 0;
+  int32_t fid_n1 = 0;          // largest n_1 among fids
   size_t o_desc = 0, o_part = 0, o_counter = 0;
   // the outer-tuple sorts of the k = 0 step, one launch set for all problems:
   // argument sets and (set, chunk) per workgroup
@@ -492,7 +554,8 @@ struct tt_batch_s {
   size_t g_lchol[TT_MAX_ORDER] = {}, g_ltrsm[TT_MAX_ORDER] = {};
   std::vector<const void*> upd_key;
   hipEvent_t ev_main = nullptr;
-  size_t o_tids[TT_MAX_ORDER], o_fpre[TT_MAX_ORDER], o_cpre[TT_MAX_ORDER], o_spre[TT_MAX_ORDER];
+  size_t o_tids[TT_MAX_ORDER], o_stids[TT_MAX_ORDER], o_fpre[TT_MAX_ORDER], o_cpre[TT_MAX_ORDER],
+      o_spre[TT_MAX_ORDER];
   int64_t Wmax = 16384;
   int64_t W[TT_MAX_ORDER];   // workgroups of the k >= 1 launch (0: device occupancy)
   // k >= 2 steps run in slab units when every slab and table set fits in LDS
@@ -563,6 +626,7 @@ tt_status upload_desc(tt_batch b, const void* const* X) {
     t.tab = p->at<uint32_t>(p->o_tab);
     t.off = p->at<uint32_t>(p->o_cnt);
     t.sorted = p->at<uint32_t>(p->o_sortO);
+    t.zo = tt_sketch_fused01(p) ? p->at<float>(p->o_zo) : nullptr;
     for (int s = 0; s < TT_MAX_ORDER; ++s) {
       t.n[s] = s < p->d ? (int32_t)p->n[s] : 1;
       t.toff[s] = s < p->d ? (int32_t)p->tab_off[s] : 0;
@@ -579,10 +643,19 @@ tt_status upload_desc(tt_batch b, const void* const* X) {
 
 hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
   const BTensor* T = reinterpret_cast<const BTensor*>(b->ws + b->o_desc);
-  const int32_t* tids = reinterpret_cast<const int32_t*>(b->ws + b->o_tids[k]);
-  const int32_t nt = (int32_t)b->tids[k].size();
-  if (nt == 0) return hipSuccess;
+  const int32_t* tids = reinterpret_cast<const int32_t*>(b->ws + b->o_stids[k]);
+  const int32_t nt = (int32_t)b->stids[k].size();
   hipError_t e;
+  if (k == 1 && !b->fids.empty()) {
+    // Y_1 of the problems whose step-0 launch wrote the outer sketch (the
+    // launch of step 0 precedes this one on the stream)
+    const size_t lds = sizeof(double) * b->Jmax + sizeof(uint32_t) * b->max_n0;
+    if ((e = tt_allow_lds(kb_y1_outer, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL(kb_y1_outer, dim3((unsigned)b->fid_n1, (unsigned)b->fids.size()), dim3(256), lds, b->stream, T,
+                       reinterpret_cast<const int32_t*>(b->ws + b->o_fids));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (nt == 0) return hipSuccess;
   if (k == 0) {
     if ((e = launch_outer_sorts_batched(b->ws + b->o_sargs, b->ws + b->o_ssrc, b->sort_sets, b->sort_blocks, b->Jmax,
                                         b->stream)) != hipSuccess)
@@ -969,6 +1042,7 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
   // per-step work lists: problems of order > k, their fibre and column prefixes,
   // and partial slots per column for the largest grid
   b->tids.resize(b->max_d);
+  b->stids.resize(b->max_d);
   b->fpre.resize(b->max_d);
   b->cpre.resize(b->max_d);
   b->spre.resize(b->max_d);
@@ -995,13 +1069,19 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
       tt_plan p = b->plans[i];
       if (p->d <= k) continue;
       b->tids[k].push_back(i);
+      if (k == 1 && tt_sketch_fused01(p)) {   // Y_1 from the outer sketch of step 0
+        b->fids.push_back(i);
+        b->fid_n1 = std::max(b->fid_n1, (int32_t)p->n[1]);
+        continue;
+      }
+      b->stids[k].push_back(i);
       b->fpre[k].push_back(b->fpre[k].back() + p->N / p->n[0] / (b->slab[k] ? p->n[1] : 1));
       b->cpre[k].push_back(b->cpre[k].back() + p->n[k]);
     }
     const int64_t Ttot = b->fpre[k].back();
     b->spre[k].push_back(0);
-    for (size_t j = 0; j < b->tids[k].size(); ++j) {
-      tt_plan p = b->plans[b->tids[k][j]];
+    for (size_t j = 0; j < b->stids[k].size(); ++j) {
+      tt_plan p = b->plans[b->stids[k][j]];
       const int64_t F = (p->N / p->n[0] / (b->slab[k] ? p->n[1] : 1)) / (k == 0 ? 1 : p->n[k]);
       // a column of F consecutive fibres meets at most floor((F - 1) W / T) + 2 ranges
       const int64_t slots = (int64_t)(((__int128)(F - 1) * b->Wmax) / (Ttot > 0 ? Ttot : 1)) + 2;
@@ -1092,9 +1172,13 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
     b->o_qidx[k] = o;
     o = align256(o + sizeof(int32_t) * (b->qidx[k].size() + 1));
   }
+  b->o_fids = o;
+  o = align256(o + sizeof(int32_t) * (b->fids.size() + 1));
   for (int k = 0; k < b->max_d; ++k) {
     b->o_tids[k] = o;
     o = align256(o + sizeof(int32_t) * (b->tids[k].size() + 1));
+    b->o_stids[k] = o;
+    o = align256(o + sizeof(int32_t) * (b->stids[k].size() + 1));
     b->o_fpre[k] = o;
     o = align256(o + sizeof(int64_t) * b->fpre[k].size());
     b->o_cpre[k] = o;
@@ -1135,6 +1219,9 @@ tt_status tt_batch_bind_workspace(tt_batch b, void* dev_ws, size_t bytes) {
     if (st) return st;
   }
   for (int k = 0; k < b->max_d; ++k) {
+    if (!b->stids[k].empty())
+      TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_stids[k], b->stids[k].data(), sizeof(int32_t) * b->stids[k].size(),
+                                hipMemcpyHostToDevice, b->stream));
     TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_tids[k], b->tids[k].data(), sizeof(int32_t) * b->tids[k].size(),
                               hipMemcpyHostToDevice, b->stream));
     TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_fpre[k], b->fpre[k].data(), sizeof(int64_t) * b->fpre[k].size(),
@@ -1144,6 +1231,9 @@ tt_status tt_batch_bind_workspace(tt_batch b, void* dev_ws, size_t bytes) {
     TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_spre[k], b->spre[k].data(), sizeof(int64_t) * b->spre[k].size(),
                               hipMemcpyHostToDevice, b->stream));
   }
+  if (!b->fids.empty())
+    TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_fids, b->fids.data(), sizeof(int32_t) * b->fids.size(),
+                              hipMemcpyHostToDevice, b->stream));
   for (int k = 0; k < b->max_d; ++k)
     if (!b->qidx[k].empty())
       TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_qidx[k], b->qidx[k].data(), sizeof(int32_t) * b->qidx[k].size(),
@@ -1194,6 +1284,9 @@ tt_status tt_batch_sketch_tensor(tt_batch b, const void* const* X, int32_t k, vo
     if (!X[i]) return tt_fail(TT_ERR_ARG, "problem %d: null X", i);
   tt_status st;
   if ((st = upload_desc(b, X))) return st;
+  // Y_1 of the problems that take it from the outer sketch needs step 0 first;
+  // without Y (timing) only the launches of step k run
+  if (Y && k == 1 && !b->fids.empty()) TT_HIP_TRY(launch_step_sketch(b, 0, b->W[0]));
   TT_HIP_TRY(launch_step_sketch(b, k, b->W[k]));
   if (!Y) return TT_OK;
   for (int32_t i : b->tids[k]) {

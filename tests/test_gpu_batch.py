@@ -345,3 +345,72 @@ def test_autotune_persists_its_choices(env, tmp_path):
     b3 = tts.Batch(PROBLEMS[:3])
     b3.autotune(Xs[:3], reps=1, cache=cache)
     assert not b3.tuned_from_cache
+
+
+# problems whose plans take Y_1 from the outer sketch of the k = 0 step
+# (J n_0 n_1 <= N / 4: the outer sketch is small beside X), mixed with one
+# that does not
+FUSED = [dict(n=[8, 6, 10, 10, 12], ranks=[1, 3, 4, 4, 3, 1], J=64, seed=131),
+         dict(n=[20, 10, 30, 40], ranks=[1, 4, 5, 4, 1], J=128, seed=132),
+         dict(n=[10, 8, 600], ranks=[1, 4, 3, 1], J=96, seed=133),
+         dict(n=[9, 12, 7], ranks=[1, 3, 4, 1], J=96, seed=134)]
+
+
+def test_batched_outer_sketch_gives_the_oracle_sketches(env):
+    """Step 0 writes the outer sketch of the large problems and step 1 takes
+    their Y_1 from it (the other problems keep the fibre launch): every Y_k
+    integer-exact against the oracle, step 1 also asked for alone."""
+    torch, tts = env
+    say("batched outer sketch")
+    # the first three take Y_1 from the outer sketch (source of Y_1 = mode 0), the last does not
+    srcs = [tts.Plan(p["n"], p["ranks"], p["J"], 1e-3).sketch_sources()[1] for p in FUSED]
+    assert srcs == [0, 0, 0, 1], srcs
+    b = tts.Batch(FUSED)
+    Xs, Xh = make_inputs(torch, FUSED, integer=True)
+    for order in ([1, 0, 2, 3, 4], [0, 1, 2, 3, 4]):
+        for k in order:
+            Ys = b.sketch_tensor(Xs, k)
+            torch.cuda.synchronize()
+            for i, p in enumerate(FUSED):
+                if len(p["n"]) <= k:
+                    continue
+                hs, vs = zip(*[b.plan_tables(i, s) for s in range(len(p["n"]))])
+                want = sketch.data_sketch(Xh[i], p["n"], k, hs, vs, p["J"])
+                got = Ys[i].cpu().numpy().astype(np.float64).reshape(want.shape, order="F")
+                np.testing.assert_array_equal(got, want, err_msg="k=%d problem %d" % (k, i))
+
+
+def test_batched_sweeps_with_outer_sketch_match_oracle(env):
+    import synth
+    torch, tts = env
+    say("batched sweeps with outer sketch vs oracle")
+    Xs, Xh = make_inputs(torch, FUSED)
+    b = tts.Batch(FUSED)
+    init = [synth.random_cores(p["n"], p["ranks"], 140 + i) for i, p in enumerate(FUSED)]
+    cb = [[tts.core_to_device(c) for c in cs] for cs in init]
+    ref = [[c.copy() for c in cs] for cs in init]
+    for t in range(3):
+        res = b.sweep(Xs, cb, residuals=True)
+        for i, p in enumerate(FUSED):
+            ref[i] = als.sweep(Xh[i], p["n"], ref[i], p["J"], 1e-3, seed=p["seed"], t=t)
+            ro = als.rel_residual(Xh[i], ref[i])
+            Tb, To = _tt(tts, cb[i], p), als.tt_full(ref[i])
+            d_tt = np.linalg.norm(Tb - To) / np.linalg.norm(To)
+            print("sweep %d problem %d: residual %.6e oracle %.6e, TT rel diff %.2e" % (t, i, res[i], ro, d_tt))
+            assert abs(res[i] - ro) < 1e-4 and d_tt < 1e-4, (t, i)
+
+
+def test_graph_replays_with_outer_sketch(env):
+    torch, tts = env
+    say("graph replays with outer sketch")
+    Xs, _ = make_inputs(torch, FUSED)
+    be, bg = tts.Batch(FUSED), tts.Batch(FUSED)
+    bg.set_graph(True)
+    ce, cg = _cores(torch, tts, FUSED, 150), _cores(torch, tts, FUSED, 150)
+    for t in range(3):
+        be.sweep(Xs, ce)
+        bg.sweep(Xs, cg)
+        torch.cuda.synchronize()
+        for i, p in enumerate(FUSED):
+            Te, Tg = _tt(tts, ce[i], p), _tt(tts, cg[i], p)
+            assert np.linalg.norm(Te - Tg) <= 1e-6 * np.linalg.norm(Te), (t, i)
