@@ -533,15 +533,15 @@ def batched_section(args, dev, steps, warmup, cache=None):
     entries = sum(d * N for d, N in zip(ds, Ns))
     # the batched data-sketch launches, one step at a time, timed with events on
     # the stream they run on.  Problems whose plans take Y_1 from the outer
-    # sketch of the k = 0 pass: step 0 also writes that sketch (J n_0 n_1
-    # FP32 values) and step 1 reads it instead of X.
+    # sketch of the k = 0 pass: step 0 writes that sketch (J n_0 n_1 FP32
+    # values) and reads it back for Y_0, and step 1 reads it instead of X.
     fused = [batch.sketch_sources(i)[1] == 0 if len(p["n"]) > 1 else False for i, p in enumerate(probs)]
     zo = [4 * p["J"] * p["n"][0] * p["n"][1] if f else 0 for p, f in zip(probs, fused)]
     sk = {}
     for k in range(max(ds)):
         nbytes = 4 * sum(N for d, N in zip(ds, Ns) if d > k)
         if k == 0:
-            nbytes += sum(zo)
+            nbytes += 2 * sum(zo)
         elif k == 1:
             nbytes = 4 * sum(N for d, N, f in zip(ds, Ns, fused) if d > 1 and not f) + sum(zo)
         batch.sketch_launch(Xs, k)
@@ -554,6 +554,8 @@ def batched_section(args, dev, steps, warmup, cache=None):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / 5
         kern = batch.sketch_kernel(k)
+        if k == 0 and any(fused):
+            kern = "kb_zo+kb_y0_outer+" + kern
         if k == 1 and any(fused):
             kern = "kb_y1_outer+" + kern
         sk[k] = {"kernel": kern if k == 0 else kern + "+k_breduce", "avg_launch_ms": round(ms, 4),
@@ -562,7 +564,7 @@ def batched_section(args, dev, steps, warmup, cache=None):
     dom = max(sk, key=lambda k: sk[k]["avg_launch_ms"])   # the step with the longest sketch launch
     rf = {"bound": "hbm", "achieved": sk[dom]["GB/s"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
           "frac": sk[dom]["frac"], "traffic": stored_traffic("k_bsketch", "c4", "batch.hip", step=dom),
-          "kernel": "%s (step %d)" % (batch.sketch_kernel(dom), dom),
+          "kernel": "%s (step %d)" % (sk[dom]["kernel"], dom),
           "avg_launch_ms": sk[dom]["avg_launch_ms"], "bytes_per_launch": sk[dom]["bytes"]}
     res = batch.sweep(Xs, cores, residuals=True)
     out = {"value": entries / (ms_per_step * 1e-3), "unit": "entries/s", "ms_per_step": ms_per_step,

@@ -22,7 +22,11 @@
 //      fly from the tables) and writes it as one partial of that column; a
 //      second launch adds the partials of each column in a fixed order;
 //    - k = 0: one workgroup per (problem, bucket) gathers the fibres hashed to
-//      the bucket from the problem's bucket-sorted list of outer tuples.
+//      the bucket from the problem's bucket-sorted list of outer tuples.  For
+//      the problems whose plans take Y_1 from the outer sketch (J n_0 n_1
+//      small beside X) a workgroup per (problem, bucket) instead sums the
+//      whole n_0 x n_1 slabs of its outer tuples into that sketch, and Y_0
+//      and Y_1 are both formed from it, so X is read once for the two steps.
 // The data sketches of every step need only X and the sweep's tables, so they
 // all run first, on a side stream, and step k's core updates wait for step
 // k's sketch.  A whole sweep can be captured once into a hipGraph and
@@ -413,23 +417,6 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
           for (int q = 0; q < NJ; ++q) row[q] += signed_f64(x[u][q], sg[u]);
       }
     }
-    if (t.zo) {
-      // the row summed over the lane groups is the outer sketch of (i_1, b):
-      // zo[(b n_1 + i_1) n_0 + i_0] (the rows of one workgroup contiguous),
-      // every (i_1, b) written once
-      double rr[NJ];
-#pragma unroll
-      for (int q = 0; q < NJ; ++q) rr[q] = row[q];
-      for (int m = LPF; m < 64; m <<= 1)
-#pragma unroll
-        for (int q = 0; q < NJ; ++q) rr[q] += __shfl_xor(rr[q], m, 64);
-      if (gi == 0)
-#pragma unroll
-        for (int q = 0; q < NJ; ++q) {
-          const int i0 = v + LPF * q;
-          if (i0 < n0) t.zo[((int64_t)b * n1 + i1) * n0 + i0] = (float)rr[q];
-        }
-    }
     const bool neg1 = (t1 & TT_KEY_SIGN) != 0;
 #pragma unroll
     for (int q = 0; q < NJ; ++q) acc[q] += neg1 ? -row[q] : row[q];
@@ -448,10 +435,106 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
   }
 }
 
+// k = 0 of a problem whose Y_1 comes from the outer sketch: workgroup
+// (f, c) adds the contiguous n_0 x n_1 slabs of the outer tuples hashed to
+// bucket c, each with its outer sign, into zo[c n_0 n_1 + i_1 n_0 + i_0].
+// Each slab is read by one workgroup, so no 128-byte line is fetched twice
+// except where two slabs meet.  A slab is taken in pieces of at most
+// 256 MS entries; a group of TPI lanes (64, 128 or 256, the fewest that
+// cover a piece with MS entries per lane) sums one slab of the bucket at a
+// time in FP64 registers, U slabs per load batch, the 256 / TPI groups
+// splitting the bucket's list; the groups are then added in a fixed order.
+constexpr int kZoMS = 16, kZoU = 2;   // entries per lane of a slab piece, slabs per load batch
+
+template <int MS, int U>
+__global__ __launch_bounds__(256) void kb_zo(const BTensor* __restrict__ T, const int32_t* __restrict__ fids,
+                                             int32_t Jmax) {
+  __shared__ double red[3 * 64 * MS];   // groups 1..3 (TPI = 64) or group 1 (TPI = 128)
+  const int f = blockIdx.x / Jmax;
+  const uint32_t c = blockIdx.x - (uint32_t)f * Jmax;
+  const BTensor& t = T[fids[f]];
+  if (c >= t.J) return;
+  const int64_t S = (int64_t)t.n[0] * t.n[1];
+  const int tpi = S <= 64 * MS ? 64 : S <= 128 * MS ? 128 : 256;
+  const int ipw = 256 / tpi;
+  const int grp = threadIdx.x / tpi, li = threadIdx.x - grp * tpi;
+  const guint offg = (guint)t.off, sortg = (guint)t.sorted;
+  const uint32_t beg = offg[c], end = offg[c + 1];
+  const gfloat Xg = (gfloat)t.X;
+  float* zo = t.zo + (int64_t)c * S;
+  for (int64_t p0 = 0; p0 < S; p0 += (int64_t)tpi * MS) {
+    const int plen = (int)(S - p0 < (int64_t)tpi * MS ? S - p0 : (int64_t)tpi * MS);
+    const int ms = (plen + tpi - 1) / tpi;
+    double acc[MS];
+#pragma unroll
+    for (int m = 0; m < MS; ++m) acc[m] = 0.0;
+    for (uint32_t e0 = beg + grp; e0 < end; e0 += ipw * U) {
+      float x[U][MS];
+      uint32_t sg[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {   // all loads first, then the sums
+        const uint32_t e = e0 + ipw * u;
+        const bool ok = e < end;
+        const uint32_t item = ok ? sortg[e] : 0u;
+        sg[u] = item & TT_KEY_SIGN;
+        const gfloat base = Xg + (int64_t)(item & TT_KEY_MASK) * S + p0 + li;
+#pragma unroll
+        for (int m = 0; m < MS; ++m)
+          x[u][m] = (ok && m < ms && li + tpi * m < plen) ? __builtin_nontemporal_load(base + tpi * m) : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)   // in list order
+#pragma unroll
+        for (int m = 0; m < MS; ++m) acc[m] += signed_f64(x[u][m], sg[u]);
+    }
+    if (ipw > 1) {
+      __syncthreads();   // the previous piece's reads of red are done
+      if (grp > 0)
+#pragma unroll
+        for (int m = 0; m < MS; ++m)
+          if (m < ms) red[(grp - 1) * tpi * MS + li + tpi * m] = acc[m];
+      __syncthreads();
+      if (grp == 0)
+        for (int g = 1; g < ipw; ++g)
+#pragma unroll
+          for (int m = 0; m < MS; ++m)
+            if (m < ms) acc[m] += red[(g - 1) * tpi * MS + li + tpi * m];
+    }
+    if (grp == 0)
+#pragma unroll
+      for (int m = 0; m < MS; ++m)
+        if (m < ms && li + tpi * m < plen) zo[p0 + li + tpi * m] = (float)acc[m];
+  }
+}
+
+// Y_0 of a problem whose k = 0 step wrote its outer sketch: workgroup
+// (b, f) adds row (b - h_1(i_1), i_1) of the sketch with the sign of i_1 for
+// every i_1 (a wave per i_1, n_0 <= 256 entries in an FP64 LDS array) and
+// writes row b of Y_0.
+__global__ __launch_bounds__(256) void kb_y0_outer(const BTensor* __restrict__ T, const int32_t* __restrict__ fids) {
+  __shared__ double acc[256];
+  const BTensor& t = T[fids[blockIdx.y]];
+  const uint32_t b = blockIdx.x, J = t.J;
+  if (b >= J) return;
+  const int n0 = t.n[0], n1 = t.n[1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int q = threadIdx.x; q < n0; q += blockDim.x) acc[q] = 0.0;
+  __syncthreads();
+  const uint32_t* tab1 = t.tab + t.toff[1];
+  for (int i1 = wv; i1 < n1; i1 += 4) {
+    const uint32_t t1 = tab1[i1], h1 = t1 & TT_KEY_MASK;
+    const uint32_t r = b >= h1 ? b - h1 : b + J - h1;
+    const float* row = t.zo + ((int64_t)r * n1 + i1) * n0;
+    for (int i0 = lane; i0 < n0; i0 += 64) atomicAdd(&acc[i0], signed_f64(row[i0], t1 & TT_KEY_SIGN));
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < n0; q += blockDim.x) t.Y[b + (int64_t)J * q] = (float)acc[q];
+}
+
 // Y_1 of a problem whose k = 0 step wrote its outer sketch: workgroup
-// (i_1, f) adds row (r, i_1) of the sketch at bucket r - h_1(i_1) + h_0(i_0)
-// with the sign of i_0, in a J-entry FP64 LDS array, and writes column i_1
-// of Y_1.
+// (i_1, f) adds row (r, i_1) of the sketch (outer key r) at bucket
+// r + h_0(i_0) with the sign of i_0, in a J-entry FP64 LDS array, and writes
+// column i_1 of Y_1.
 __global__ __launch_bounds__(256) void kb_y1_outer(const BTensor* __restrict__ T, const int32_t* __restrict__ fids) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const BTensor& t = T[fids[blockIdx.y]];
@@ -464,13 +547,12 @@ __global__ __launch_bounds__(256) void kb_y1_outer(const BTensor* __restrict__ T
   for (uint32_t q = threadIdx.x; q < J; q += blockDim.x) acc[q] = 0.0;
   for (int q = threadIdx.x; q < n0; q += blockDim.x) t0[q] = t.tab[t.toff[0] + q];
   __syncthreads();
-  const uint32_t h1 = t.tab[t.toff[1] + i1] & TT_KEY_MASK;
   const int64_t n1 = t.n[1];
   const uint32_t tot = J * (uint32_t)n0;
   for (uint32_t q = threadIdx.x; q < tot; q += blockDim.x) {
     const uint32_t r = q / (uint32_t)n0, i0 = q - r * (uint32_t)n0;
     const uint32_t tv = t0[i0];
-    uint32_t bk = (r >= h1 ? r - h1 : r + J - h1) + (tv & TT_KEY_MASK);
+    uint32_t bk = r + (tv & TT_KEY_MASK);
     bk = bk >= J ? bk - J : bk;
     atomicAdd(&acc[bk], signed_f64(t.zo[((int64_t)r * n1 + i1) * n0 + i0], tv & TT_KEY_SIGN));
   }
@@ -655,15 +737,25 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
                        reinterpret_cast<const int32_t*>(b->ws + b->o_fids));
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (nt == 0) return hipSuccess;
   if (k == 0) {
-    if ((e = launch_outer_sorts_batched(b->ws + b->o_sargs, b->ws + b->o_ssrc, b->sort_sets, b->sort_blocks, b->Jmax,
+    if (b->sort_sets > 0 &&
+        (e = launch_outer_sorts_batched(b->ws + b->o_sargs, b->ws + b->o_ssrc, b->sort_sets, b->sort_blocks, b->Jmax,
                                         b->stream)) != hipSuccess)
       return e;
+    if (!b->fids.empty()) {   // outer sketch, then Y_0 from it
+      const int32_t* fids = reinterpret_cast<const int32_t*>(b->ws + b->o_fids);
+      const unsigned nf = (unsigned)b->fids.size();
+      hipLaunchKernelGGL((kb_zo<kZoMS, kZoU>), dim3(nf * (unsigned)b->Jmax), dim3(256), 0, b->stream, T, fids, b->Jmax);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(kb_y0_outer, dim3((unsigned)b->Jmax, nf), dim3(256), 0, b->stream, T, fids);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (nt == 0) return hipSuccess;
     const dim3 grid((unsigned)(nt * b->Jmax));
     hipLaunchKernelGGL(b0_kernel(b->nj[0], b->fib[0]), grid, dim3(256), 0, b->stream, T, tids, b->Jmax);
     return hipGetLastError();
   }
+  if (nt == 0) return hipSuccess;
   const int64_t* fpre = reinterpret_cast<const int64_t*>(b->ws + b->o_fpre[k]);
   const int64_t* cpre = reinterpret_cast<const int64_t*>(b->ws + b->o_cpre[k]);
   const int64_t* spre = reinterpret_cast<const int64_t*>(b->ws + b->o_spre[k]);
@@ -1069,9 +1161,11 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
       tt_plan p = b->plans[i];
       if (p->d <= k) continue;
       b->tids[k].push_back(i);
-      if (k == 1 && tt_sketch_fused01(p)) {   // Y_1 from the outer sketch of step 0
-        b->fids.push_back(i);
-        b->fid_n1 = std::max(b->fid_n1, (int32_t)p->n[1]);
+      if (k <= 1 && tt_sketch_fused01(p)) {   // outer sketch at k = 0, Y_0 and Y_1 from it
+        if (k == 1) {
+          b->fids.push_back(i);
+          b->fid_n1 = std::max(b->fid_n1, (int32_t)p->n[1]);
+        }
         continue;
       }
       b->stids[k].push_back(i);
@@ -1089,6 +1183,10 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
     }
     if (k >= 1 && (size_t)b->spre[k].back() > part_max) part_max = (size_t)b->spre[k].back();
   }
+  // the largest buckets first, so that the last workgroups of the outer-sketch launch are short ones
+  std::stable_sort(b->fids.begin(), b->fids.end(), [&](int32_t a, int32_t c) {
+    return b->plans[a]->N / b->plans[a]->J > b->plans[c]->N / b->plans[c]->J;
+  });
   b->o_desc = o;
   o = align256(o + sizeof(BTensor) * count);
   // batched core updates: shapes known now, pointers filled per call
