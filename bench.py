@@ -534,7 +534,8 @@ def batched_section(args, dev, steps, warmup, cache=None):
     # the batched data-sketch launches, one step at a time, timed with events on
     # the stream they run on.  Problems whose plans take Y_1 from the outer
     # sketch of the k = 0 pass: step 0 writes that sketch (J n_0 n_1 FP32
-    # values) and reads it back for Y_0, and step 1 reads it instead of X.
+    # values) and reads it back for Y_0 (k_bsketch_0), and step 1 reads it
+    # instead of X.
     fused = [batch.sketch_sources(i)[1] == 0 if len(p["n"]) > 1 else False for i, p in enumerate(probs)]
     zo = [4 * p["J"] * p["n"][0] * p["n"][1] if f else 0 for p, f in zip(probs, fused)]
     sk = {}
@@ -555,7 +556,7 @@ def batched_section(args, dev, steps, warmup, cache=None):
         ms = e0.elapsed_time(e1) / 5
         kern = batch.sketch_kernel(k)
         if k == 0 and any(fused):
-            kern = "kb_zo+kb_y0_outer+" + kern
+            kern = "kb_zo+" + kern
         if k == 1 and any(fused):
             kern = "kb_y1_outer+" + kern
         sk[k] = {"kernel": kern if k == 0 else kern + "+k_breduce", "avg_launch_ms": round(ms, 4),

@@ -364,62 +364,101 @@ __global__ void k_breduce(const BTensor* __restrict__ T, const int32_t* __restri
 }
 
 // ---------------------------------------------------------------- k = 0
+// Row b of Y_0: every fibre (i_1, o) whose key h_1(i_1) + h(o) is b adds its
+// n_0 values with the signs of i_1 and o.  The outer tuples o of a key are a
+// contiguous range of the problem's bucket-sorted list, so the fibres of row
+// i_1 are those of key b - h_1(i_1).  The workgroup finds the ranges of 256
+// rows at once (a thread per row, then a prefix sum of their lengths in LDS);
+// the fibres of those rows then form one sequence split over all lane
+// groups, FIB fibres per group per load batch.  A problem whose k = 0 step
+// wrote the outer sketch (zo set) reads that sketch in place of X, with one
+// "tuple" per key: its row r of the sketch, outer signs already applied.
 template <int NJ, int FIB>
 __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T, const int32_t* __restrict__ tids,
                                                    int32_t Jmax) {
   __shared__ double red[4][64 * NJ];
+  __shared__ int64_t rpre[257];   // fibres of the chunk's rows before row q
+  __shared__ uint32_t rbeg[256];  // list position of row q's first fibre
+  __shared__ uint32_t rsg[256];   // sign of i_1 of row q
+  __shared__ int64_t wsum[4];
   const int j = blockIdx.x / Jmax;
   const uint32_t b = blockIdx.x - (uint32_t)j * Jmax;
   const BTensor& t = T[tids[j]];
   if (b >= t.J) return;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, NW = blockDim.x >> 6;
+  const bool oz = t.zo != nullptr;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int n0 = t.n[0], n1 = t.n[1];
   const uint32_t J = t.J;
   const int lpf_log2 = lpf_log2_of<NJ>(n0);
   const int LPF = 1 << lpf_log2, G = 64 >> lpf_log2;
   const int gi = lane >> lpf_log2, v = lane & (LPF - 1);
+  const int ng = 4 * G, gid = wv * G + gi;   // lane groups of the workgroup
   const uint32_t* tab1 = t.tab + t.toff[1];
-  const gfloat Xg = (gfloat)t.X;
+  const gfloat Xg = (gfloat)(oz ? t.zo : t.X);
   const guint offg = (guint)t.off, sortg = (guint)t.sorted;
-  double acc[NJ];   // FP64: the result does not depend on the order of the list
+  double acc[NJ];   // FP64: the result does not depend on the order of the fibres
 #pragma unroll
   for (int q = 0; q < NJ; ++q) acc[q] = 0.0;
-  for (int i1 = wv; i1 < n1; i1 += NW) {
-    const uint32_t t1 = tab1[i1];
-    const uint32_t h1 = t1 & TT_KEY_MASK;
-    const uint32_t c = b >= h1 ? b - h1 : b + J - h1;
-    const uint32_t beg = offg[c], end = offg[c + 1];
-    // row (i_1, b): the outer tuples of key b - h_1(i_1), outer signs only
-    double row[NJ];
-#pragma unroll
-    for (int q = 0; q < NJ; ++q) row[q] = 0.0;
-    for (uint32_t e0 = beg; e0 < end; e0 += 64) {
-      const uint32_t itl = (e0 + lane < end) ? sortg[e0 + lane] : 0u;
-      const int nb = (end - e0) < 64u ? (int)(end - e0) : 64;
-      for (int u0 = 0; u0 < nb; u0 += FIB * G) {
-        float x[FIB][NJ];
-        uint32_t sg[FIB];
-#pragma unroll
-        for (int u = 0; u < FIB; ++u) {   // all loads first, then the sums
-          const int idx = u0 + u * G + gi;
-          const uint32_t item = (uint32_t)__shfl((int)itl, idx & 63, 64);
-          sg[u] = item & TT_KEY_SIGN;
-          const gfloat base = Xg + ((int64_t)(item & TT_KEY_MASK) * n1 + i1) * (int64_t)n0;
-#pragma unroll
-          for (int q = 0; q < NJ; ++q) {
-            const int i0 = v + LPF * q;
-            x[u][q] = (idx < nb && i0 < n0) ? __builtin_nontemporal_load(base + i0) : 0.0f;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < FIB; ++u)   // in list order
-#pragma unroll
-          for (int q = 0; q < NJ; ++q) row[q] += signed_f64(x[u][q], sg[u]);
+  for (int r0 = 0; r0 < n1; r0 += 256) {
+    const int nr = n1 - r0 < 256 ? n1 - r0 : 256;
+    const int i1 = r0 + (int)threadIdx.x;
+    int64_t cnt = 0;
+    uint32_t bg = 0, sg = 0;
+    if (i1 < n1) {
+      const uint32_t t1 = tab1[i1], h1 = t1 & TT_KEY_MASK;
+      const uint32_t c = b >= h1 ? b - h1 : b + J - h1;
+      sg = t1 & TT_KEY_SIGN;
+      if (oz) {
+        bg = c;
+        cnt = 1;
+      } else {
+        bg = offg[c];
+        cnt = offg[c + 1] - bg;
       }
     }
-    const bool neg1 = (t1 & TT_KEY_SIGN) != 0;
+    int64_t inc = cnt;   // inclusive prefix over the wave, then over the waves
+    for (int m = 1; m < 64; m <<= 1) {
+      const int64_t o = __shfl_up(inc, m, 64);
+      if (lane >= m) inc += o;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    for (int w = 0; w < wv; ++w) inc += wsum[w];
+    rpre[threadIdx.x + 1] = inc;
+    if (threadIdx.x == 0) rpre[0] = 0;
+    rbeg[threadIdx.x] = bg;
+    rsg[threadIdx.x] = sg;
+    __syncthreads();
+    const int64_t tot = rpre[nr];
+    for (int64_t f0 = 0; f0 < tot; f0 += (int64_t)ng * FIB) {
+      float x[FIB][NJ];
+      uint32_t sgn[FIB];
 #pragma unroll
-    for (int q = 0; q < NJ; ++q) acc[q] += neg1 ? -row[q] : row[q];
+      for (int u = 0; u < FIB; ++u) {   // all loads first, then the sums
+        const int64_t f = f0 + (int64_t)u * ng + gid;
+        const bool ok = f < tot;
+        int lo = 0, hi = nr - 1;   // the row of fibre f: the last q with rpre[q] <= f
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (rpre[mid] <= f) lo = mid;
+          else hi = mid - 1;
+        }
+        const uint32_t pos = rbeg[lo] + (uint32_t)(f - rpre[lo]);
+        const uint32_t item = !ok ? 0u : oz ? pos : sortg[pos];
+        sgn[u] = (item ^ rsg[lo]) & TT_KEY_SIGN;
+        const gfloat base = Xg + ((int64_t)(item & TT_KEY_MASK) * n1 + r0 + lo) * (int64_t)n0;
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) {
+          const int i0 = v + LPF * q;
+          x[u][q] = (ok && i0 < n0) ? __builtin_nontemporal_load(base + i0) : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < FIB; ++u)
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) acc[q] += signed_f64(x[u][q], sgn[u]);
+    }
+    __syncthreads();   // the next chunk rewrites the row arrays
   }
   for (int m = LPF; m < 64; m <<= 1)
 #pragma unroll
@@ -430,20 +469,11 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
   __syncthreads();
   for (int i = threadIdx.x; i < n0; i += blockDim.x) {
     double s = 0.0;
-    for (int ww = 0; ww < NW; ++ww) s += red[ww][i];
+    for (int ww = 0; ww < 4; ++ww) s += red[ww][i];
     t.Y[b + (int64_t)J * i] = (float)s;
   }
 }
 
-// k = 0 of a problem whose Y_1 comes from the outer sketch: workgroup
-// (f, c) adds the contiguous n_0 x n_1 slabs of the outer tuples hashed to
-// bucket c, each with its outer sign, into zo[c n_0 n_1 + i_1 n_0 + i_0].
-// Each slab is read by one workgroup, so no 128-byte line is fetched twice
-// except where two slabs meet.  A slab is taken in pieces of at most
-// 256 MS entries; a group of TPI lanes (64, 128 or 256, the fewest that
-// cover a piece with MS entries per lane) sums one slab of the bucket at a
-// time in FP64 registers, U slabs per load batch, the 256 / TPI groups
-// splitting the bucket's list; the groups are then added in a fixed order.
 constexpr int kZoMS = 16, kZoU = 2;   // entries per lane of a slab piece, slabs per load batch
 
 template <int MS, int U>
@@ -505,30 +535,6 @@ __global__ __launch_bounds__(256) void kb_zo(const BTensor* __restrict__ T, cons
       for (int m = 0; m < MS; ++m)
         if (m < ms && li + tpi * m < plen) zo[p0 + li + tpi * m] = (float)acc[m];
   }
-}
-
-// Y_0 of a problem whose k = 0 step wrote its outer sketch: workgroup
-// (b, f) adds row (b - h_1(i_1), i_1) of the sketch with the sign of i_1 for
-// every i_1 (a wave per i_1, n_0 <= 256 entries in an FP64 LDS array) and
-// writes row b of Y_0.
-__global__ __launch_bounds__(256) void kb_y0_outer(const BTensor* __restrict__ T, const int32_t* __restrict__ fids) {
-  __shared__ double acc[256];
-  const BTensor& t = T[fids[blockIdx.y]];
-  const uint32_t b = blockIdx.x, J = t.J;
-  if (b >= J) return;
-  const int n0 = t.n[0], n1 = t.n[1];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int q = threadIdx.x; q < n0; q += blockDim.x) acc[q] = 0.0;
-  __syncthreads();
-  const uint32_t* tab1 = t.tab + t.toff[1];
-  for (int i1 = wv; i1 < n1; i1 += 4) {
-    const uint32_t t1 = tab1[i1], h1 = t1 & TT_KEY_MASK;
-    const uint32_t r = b >= h1 ? b - h1 : b + J - h1;
-    const float* row = t.zo + ((int64_t)r * n1 + i1) * n0;
-    for (int i0 = lane; i0 < n0; i0 += 64) atomicAdd(&acc[i0], signed_f64(row[i0], t1 & TT_KEY_SIGN));
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < n0; q += blockDim.x) t.Y[b + (int64_t)J * q] = (float)acc[q];
 }
 
 // Y_1 of a problem whose k = 0 step wrote its outer sketch: workgroup
@@ -742,12 +748,10 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
         (e = launch_outer_sorts_batched(b->ws + b->o_sargs, b->ws + b->o_ssrc, b->sort_sets, b->sort_blocks, b->Jmax,
                                         b->stream)) != hipSuccess)
       return e;
-    if (!b->fids.empty()) {   // outer sketch, then Y_0 from it
+    if (!b->fids.empty()) {   // the outer sketch, which Y_0 of those problems then reads
       const int32_t* fids = reinterpret_cast<const int32_t*>(b->ws + b->o_fids);
       const unsigned nf = (unsigned)b->fids.size();
       hipLaunchKernelGGL((kb_zo<kZoMS, kZoU>), dim3(nf * (unsigned)b->Jmax), dim3(256), 0, b->stream, T, fids, b->Jmax);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL(kb_y0_outer, dim3((unsigned)b->Jmax, nf), dim3(256), 0, b->stream, T, fids);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (nt == 0) return hipSuccess;
@@ -1161,11 +1165,9 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
       tt_plan p = b->plans[i];
       if (p->d <= k) continue;
       b->tids[k].push_back(i);
-      if (k <= 1 && tt_sketch_fused01(p)) {   // outer sketch at k = 0, Y_0 and Y_1 from it
-        if (k == 1) {
-          b->fids.push_back(i);
-          b->fid_n1 = std::max(b->fid_n1, (int32_t)p->n[1]);
-        }
+      if (k == 1 && tt_sketch_fused01(p)) {   // Y_1 from the outer sketch of step 0
+        b->fids.push_back(i);
+        b->fid_n1 = std::max(b->fid_n1, (int32_t)p->n[1]);
         continue;
       }
       b->stids[k].push_back(i);
