@@ -474,32 +474,56 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
   }
 }
 
-constexpr int kZoMS = 16, kZoU = 2;   // entries per lane of a slab piece, slabs per load batch
+// V-wide loads of FP32 values (V = 1, 2, 4)
+template <int V> struct FVec;
+template <> struct FVec<1> { typedef float T; };
+template <> struct FVec<2> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct FVec<4> { typedef float T __attribute__((ext_vector_type(4))); };
+template <int V> __device__ __forceinline__ float lane_of(const typename FVec<V>::T& a, int i) { return a[i]; }
+template <> __device__ __forceinline__ float lane_of<1>(const float& a, int) { return a; }
 
-template <int MS, int U>
+constexpr int kZoMS = 16, kZoU = 2;   // FP32 entries per lane of a slab piece, slabs per load batch
+
+// k = 0 of the problems whose Y_1 comes from the outer sketch: workgroup
+// (f, c) adds the contiguous n_0 x n_1 slabs of the outer tuples hashed to
+// bucket c, each with its outer sign, into zo[c n_0 n_1 + i_1 n_0 + i_0].
+// Each slab is read by one workgroup, so no 128-byte line is fetched twice
+// except where two slabs meet.  A slab is read in V-entry vectors (V = 4 or
+// 2 when n_0 n_1 and the address of X allow it: every slab then starts on a
+// V-entry boundary) and taken in pieces of at most 256 MS entries; a group
+// of TPI lanes (64, 128 or 256, the fewest that cover a piece with MS
+// entries per lane) sums one slab of the bucket at a time in FP64 registers,
+// U slabs per load batch, the 256 / TPI groups splitting the bucket's list;
+// the groups are then added in a fixed order.  fids lists the problems of
+// this V.
+template <int V, int MS, int U>
 __global__ __launch_bounds__(256) void kb_zo(const BTensor* __restrict__ T, const int32_t* __restrict__ fids,
                                              int32_t Jmax) {
-  __shared__ double red[3 * 64 * MS];   // groups 1..3 (TPI = 64) or group 1 (TPI = 128)
+  typedef typename FVec<V>::T vt;
+  constexpr int MV = MS / V;              // vectors per lane of a piece
+  __shared__ double red[3 * 64 * MS];     // groups 1..3 (TPI = 64) or group 1 (TPI = 128)
   const int f = blockIdx.x / Jmax;
   const uint32_t c = blockIdx.x - (uint32_t)f * Jmax;
   const BTensor& t = T[fids[f]];
   if (c >= t.J) return;
-  const int64_t S = (int64_t)t.n[0] * t.n[1];
-  const int tpi = S <= 64 * MS ? 64 : S <= 128 * MS ? 128 : 256;
+  const int64_t Sv = (int64_t)t.n[0] * t.n[1] / V;   // vectors per slab
+  const int tpi = Sv <= 64 * MV ? 64 : Sv <= 128 * MV ? 128 : 256;
   const int ipw = 256 / tpi;
   const int grp = threadIdx.x / tpi, li = threadIdx.x - grp * tpi;
   const guint offg = (guint)t.off, sortg = (guint)t.sorted;
   const uint32_t beg = offg[c], end = offg[c + 1];
-  const gfloat Xg = (gfloat)t.X;
-  float* zo = t.zo + (int64_t)c * S;
-  for (int64_t p0 = 0; p0 < S; p0 += (int64_t)tpi * MS) {
-    const int plen = (int)(S - p0 < (int64_t)tpi * MS ? S - p0 : (int64_t)tpi * MS);
+  const vt* Xv = reinterpret_cast<const vt*>(t.X);
+  vt* zo = reinterpret_cast<vt*>(t.zo) + (int64_t)c * Sv;
+  for (int64_t p0 = 0; p0 < Sv; p0 += (int64_t)tpi * MV) {
+    const int plen = (int)(Sv - p0 < (int64_t)tpi * MV ? Sv - p0 : (int64_t)tpi * MV);
     const int ms = (plen + tpi - 1) / tpi;
-    double acc[MS];
+    double acc[MV][V];
 #pragma unroll
-    for (int m = 0; m < MS; ++m) acc[m] = 0.0;
+    for (int m = 0; m < MV; ++m)
+#pragma unroll
+      for (int i = 0; i < V; ++i) acc[m][i] = 0.0;
     for (uint32_t e0 = beg + grp; e0 < end; e0 += ipw * U) {
-      float x[U][MS];
+      vt x[U][MV];
       uint32_t sg[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {   // all loads first, then the sums
@@ -507,33 +531,48 @@ __global__ __launch_bounds__(256) void kb_zo(const BTensor* __restrict__ T, cons
         const bool ok = e < end;
         const uint32_t item = ok ? sortg[e] : 0u;
         sg[u] = item & TT_KEY_SIGN;
-        const gfloat base = Xg + (int64_t)(item & TT_KEY_MASK) * S + p0 + li;
+        const vt* base = Xv + (int64_t)(item & TT_KEY_MASK) * Sv + p0 + li;
 #pragma unroll
-        for (int m = 0; m < MS; ++m)
-          x[u][m] = (ok && m < ms && li + tpi * m < plen) ? __builtin_nontemporal_load(base + tpi * m) : 0.0f;
+        for (int m = 0; m < MV; ++m)
+          x[u][m] = (ok && m < ms && li + tpi * m < plen) ? __builtin_nontemporal_load(base + tpi * m) : (vt)(0.0f);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)   // in list order
 #pragma unroll
-        for (int m = 0; m < MS; ++m) acc[m] += signed_f64(x[u][m], sg[u]);
+        for (int m = 0; m < MV; ++m)
+#pragma unroll
+          for (int i = 0; i < V; ++i) acc[m][i] += signed_f64(lane_of<V>(x[u][m], i), sg[u]);
     }
     if (ipw > 1) {
       __syncthreads();   // the previous piece's reads of red are done
       if (grp > 0)
 #pragma unroll
-        for (int m = 0; m < MS; ++m)
-          if (m < ms) red[(grp - 1) * tpi * MS + li + tpi * m] = acc[m];
+        for (int m = 0; m < MV; ++m)
+          if (m < ms)
+#pragma unroll
+            for (int i = 0; i < V; ++i) red[((grp - 1) * tpi * MV + li + tpi * m) * V + i] = acc[m][i];
       __syncthreads();
       if (grp == 0)
         for (int g = 1; g < ipw; ++g)
 #pragma unroll
-          for (int m = 0; m < MS; ++m)
-            if (m < ms) acc[m] += red[(g - 1) * tpi * MS + li + tpi * m];
+          for (int m = 0; m < MV; ++m)
+            if (m < ms)
+#pragma unroll
+              for (int i = 0; i < V; ++i) acc[m][i] += red[((g - 1) * tpi * MV + li + tpi * m) * V + i];
     }
     if (grp == 0)
 #pragma unroll
-      for (int m = 0; m < MS; ++m)
-        if (m < ms && li + tpi * m < plen) zo[p0 + li + tpi * m] = (float)acc[m];
+      for (int m = 0; m < MV; ++m)
+        if (m < ms && li + tpi * m < plen) {
+          vt o;
+          if constexpr (V == 1) {
+            o = (float)acc[m][0];
+          } else {
+#pragma unroll
+            for (int i = 0; i < V; ++i) o[i] = (float)acc[m][i];
+          }
+          zo[p0 + li + tpi * m] = o;
+        }
   }
 }
 
@@ -618,6 +657,10 @@ struct tt_batch_s {
   std::vector<std::vector<int64_t>> fpre, cpre, spre;
   std::vector<int32_t> fids;
   size_t o_fids = 0;
+  // the problems of fids by the load width of their outer-sketch pass (4, 2,
+  // 1 FP32 values), set with the X pointers: counts and the device list
+  int32_t zcnt[3] = {};
+  size_t o_zids = 0;
   int32_t fid_n1 = 0;          // largest n_1 among fids
   size_t o_desc = 0, o_part = 0, o_counter = 0;
   // the outer-tuple sorts of the k = 0 step, one launch set for all problems:
@@ -724,6 +767,24 @@ tt_status upload_desc(tt_batch b, const void* const* X) {
   }
   TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_desc, b->host_desc.data(), sizeof(BTensor) * b->count, hipMemcpyHostToDevice,
                             b->stream));
+  // outer-sketch problems by load width: V-entry vectors need n_0 n_1 and the
+  // address of X divisible by V (largest slabs first within each width)
+  std::vector<int32_t> zids;
+  for (int vc = 0; vc < 3; ++vc) {
+    const int V = 4 >> vc;
+    b->zcnt[vc] = 0;
+    for (int32_t i : b->fids) {
+      const int64_t S = b->plans[i]->n[0] * b->plans[i]->n[1];
+      const uintptr_t a = (uintptr_t)X[i];
+      const int w = (S % 4 == 0 && a % 16 == 0) ? 4 : (S % 2 == 0 && a % 8 == 0) ? 2 : 1;
+      if (w != V) continue;
+      zids.push_back(i);
+      b->zcnt[vc] += 1;
+    }
+  }
+  if (!zids.empty())
+    TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_zids, zids.data(), sizeof(int32_t) * zids.size(), hipMemcpyHostToDevice,
+                              b->stream));
   TT_HIP_TRY(hipStreamSynchronize(b->stream));
   b->desc_valid = true;
   return TT_OK;
@@ -748,10 +809,14 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
         (e = launch_outer_sorts_batched(b->ws + b->o_sargs, b->ws + b->o_ssrc, b->sort_sets, b->sort_blocks, b->Jmax,
                                         b->stream)) != hipSuccess)
       return e;
-    if (!b->fids.empty()) {   // the outer sketch, which Y_0 of those problems then reads
-      const int32_t* fids = reinterpret_cast<const int32_t*>(b->ws + b->o_fids);
-      const unsigned nf = (unsigned)b->fids.size();
-      hipLaunchKernelGGL((kb_zo<kZoMS, kZoU>), dim3(nf * (unsigned)b->Jmax), dim3(256), 0, b->stream, T, fids, b->Jmax);
+    // the outer sketch, which Y_0 of those problems then reads: one launch per load width
+    const int32_t* zids = reinterpret_cast<const int32_t*>(b->ws + b->o_zids);
+    for (int vc = 0, at = 0; vc < 3; at += b->zcnt[vc], ++vc) {
+      if (b->zcnt[vc] == 0) continue;
+      const dim3 gz((unsigned)b->zcnt[vc] * (unsigned)b->Jmax);
+      if (vc == 0) hipLaunchKernelGGL((kb_zo<4, kZoMS, kZoU>), gz, dim3(256), 0, b->stream, T, zids + at, b->Jmax);
+      else if (vc == 1) hipLaunchKernelGGL((kb_zo<2, kZoMS, kZoU>), gz, dim3(256), 0, b->stream, T, zids + at, b->Jmax);
+      else hipLaunchKernelGGL((kb_zo<1, kZoMS, kZoU>), gz, dim3(256), 0, b->stream, T, zids + at, b->Jmax);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (nt == 0) return hipSuccess;
@@ -1273,6 +1338,8 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
     o = align256(o + sizeof(int32_t) * (b->qidx[k].size() + 1));
   }
   b->o_fids = o;
+  o = align256(o + sizeof(int32_t) * (b->fids.size() + 1));
+  b->o_zids = o;
   o = align256(o + sizeof(int32_t) * (b->fids.size() + 1));
   for (int k = 0; k < b->max_d; ++k) {
     b->o_tids[k] = o;

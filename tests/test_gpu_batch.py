@@ -414,3 +414,36 @@ def test_graph_replays_with_outer_sketch(env):
         for i, p in enumerate(FUSED):
             Te, Tg = _tt(tts, ce[i], p), _tt(tts, cg[i], p)
             assert np.linalg.norm(Te - Tg) <= 1e-6 * np.linalg.norm(Te), (t, i)
+
+
+# outer-sketch problems whose slabs take each load width of the k = 0 pass:
+# n_0 n_1 = 63 (odd: single values), 42 (even: pairs), 48 (four-value vectors)
+WIDTHS = [dict(n=[7, 9, 10, 10, 12], ranks=[1, 3, 4, 4, 3, 1], J=64, seed=161),
+          dict(n=[6, 7, 12, 10, 9], ranks=[1, 3, 4, 4, 3, 1], J=64, seed=162),
+          dict(n=[8, 6, 10, 10, 12], ranks=[1, 3, 4, 4, 3, 1], J=64, seed=163)]
+
+
+@pytest.mark.parametrize("shift", [0, 1, 2])
+def test_outer_sketch_every_load_width(env, shift):
+    """Every Y_k integer-exact against the oracle for slabs of odd, even and
+    multiple-of-four size, with X at an aligned address and at 1 and 2
+    values past one (narrower loads for the same problems)."""
+    torch, tts = env
+    say("outer sketch load widths, X shifted by %d values" % shift)
+    srcs = [tts.Plan(p["n"], p["ranks"], p["J"], 1e-3).sketch_sources()[1] for p in WIDTHS]
+    assert srcs == [0, 0, 0], srcs
+    b = tts.Batch(WIDTHS)
+    Xs0, Xh = make_inputs(torch, WIDTHS, integer=True)
+    Xs = []
+    for x in Xs0:   # the same values at an address shift * 4 bytes past a 256-byte boundary
+        buf = torch.empty(x.numel() + shift, dtype=x.dtype, device=x.device)
+        buf[shift:] = x
+        Xs.append(buf[shift:])
+    for k in (0, 1, 2, 3, 4):
+        Ys = b.sketch_tensor(Xs, k)
+        torch.cuda.synchronize()
+        for i, p in enumerate(WIDTHS):
+            hs, vs = zip(*[b.plan_tables(i, s) for s in range(len(p["n"]))])
+            want = sketch.data_sketch(Xh[i], p["n"], k, hs, vs, p["J"])
+            got = Ys[i].cpu().numpy().astype(np.float64).reshape(want.shape, order="F")
+            np.testing.assert_array_equal(got, want, err_msg="k=%d problem %d shift %d" % (k, i, shift))
