@@ -597,7 +597,7 @@ def run_batched(args):
         "warmup": args.warmup, "ms_per_step": b["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": b["workload"], "problems": b["problems"], "total_entries": b["total_entries"],
-                   "tuning": b["tuning"]},
+                   "problems_with_outer_sketch": b["problems_with_outer_sketch"], "tuning": b["tuning"]},
         "hbm_gbps_sweep": b["hbm_gbps_sweep"], "wall_s_timed": b["wall_s_timed"], "roofline": b["roofline"],
         "batched_sketch_steps": b["batched_sketch_steps"], "residuals_after": b["residuals_after"],
     }
