@@ -35,6 +35,7 @@
 // advances.  The workgroup count of each k >= 1 launch is chosen by
 // tt_batch_autotune from timed candidates.
 #include <algorithm>
+#include <type_traits>
 #include <new>
 #include <vector>
 
@@ -49,6 +50,7 @@ struct BTensor {
   const uint32_t* off;       // k = 0: bucket offsets of the outer tuples (J + 1)
   const uint32_t* sorted;    // k = 0: outer tuples sorted by bucket
   float* zo;                 // problems whose Y_1 comes from the k = 0 pass: its outer sketch, else null
+  const uint2* sl[TT_MAX_ORDER];   // k >= 2: the slabs of a mode-k column sorted by key
   int32_t n[TT_MAX_ORDER];
   int32_t toff[TT_MAX_ORDER];
   int32_t d;
@@ -92,6 +94,14 @@ __device__ __forceinline__ int lpf_log2_of(int n0) {
   while ((NJ << l) < n0 && l < 6) ++l;
   return l;
 }
+
+// V-wide loads of FP32 values (V = 1, 2, 4)
+template <int V> struct FVec;
+template <> struct FVec<1> { typedef float T; };
+template <> struct FVec<2> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct FVec<4> { typedef float T __attribute__((ext_vector_type(4))); };
+template <int V> __device__ __forceinline__ float lane_of(const typename FVec<V>::T& a, int i) { return a[i]; }
+template <> __device__ __forceinline__ float lane_of<1>(const float& a, int) { return a; }
 
 // ---------------------------------------------------------------- k >= 1
 // NJ: entries of a fibre per lane; FIB: fibres per lane group per load batch
@@ -336,6 +346,143 @@ __global__ __launch_bounds__(256) void k_bsketch_slab(const BTensor* __restrict_
   }
 }
 
+// k >= 2, key-sorted slabs: the units, partials and LDS tables of
+// k_bsketch_slab, but slab q of a column is entry q of the problem's mode-k
+// slab list, sorted by the key K over the modes other than 0, 1 and k.  A
+// slab is read whole (V-value vectors when n_0 n_1 and the address of X
+// allow it) by a group of TPI lanes (64, 128 or 256, the fewest that cover a
+// piece of 256 MS values with MS per lane), U slabs per load batch; the 256 /
+// TPI groups split the workgroup's share of the list.  A group keeps FP64
+// running sums of its slabs' entries while K stays the same and adds them
+// to the accumulator at bucket P[e] + K when it changes: one LDS atomic per
+// entry of a run of equal keys instead of one per entry of X.
+template <int MS, int U>
+__global__ __launch_bounds__(256) void k_bsketch_ks(const BTensor* __restrict__ T, const int32_t* __restrict__ tids,
+                                                    const int64_t* __restrict__ fpre, const int64_t* __restrict__ cpre,
+                                                    const int64_t* __restrict__ spre, int32_t nt, int32_t k,
+                                                    double* __restrict__ part, int32_t Jmax, int32_t Smax) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* acc = reinterpret_cast<double*>(smem_raw);
+  uint32_t* P = reinterpret_cast<uint32_t*>(acc + Jmax);   // Smax entries
+  uint32_t* tl = P + Smax;                                  // the problem's packed tables
+  const int64_t W = gridDim.x, w = blockIdx.x;
+  const int64_t Ttot = fpre[nt];
+  const int64_t gs = w * Ttot / W, ge = (w + 1) * Ttot / W;
+  if (gs >= ge) return;
+  int j = seg_of(fpre, nt, gs), jp = -1;
+  int64_t g = gs;
+  while (g < ge) {
+    while (fpre[j + 1] <= g) ++j;
+    const BTensor& t = T[tids[j]];
+    const int d = t.d;
+    const uint32_t n0 = (uint32_t)t.n[0], n1 = (uint32_t)t.n[1];
+    const uint32_t S = n0 * n1;
+    const uint32_t J = t.J;
+    int64_t Mp = 1, R = 1;
+    for (int s = 2; s < k; ++s) Mp *= t.n[s];
+    for (int s = k + 1; s < d; ++s) R *= t.n[s];
+    const int64_t F = Mp * R;   // slabs per column
+    const int64_t q0 = g - fpre[j];
+    const int64_t c = q0 / F;
+    const int64_t qa = q0 - c * F;
+    const int64_t lim = ge - fpre[j] - c * F;
+    const int64_t qe = lim < F ? lim : F;
+    for (uint32_t b = threadIdx.x; b < J; b += blockDim.x) acc[b] = 0.0;
+    if (j != jp) {   // P of a new problem (no thread reads it here)
+      const int ntab = t.toff[1] + t.n[1];
+      for (int i = threadIdx.x; i < ntab; i += blockDim.x) tl[i] = t.tab[i];
+      __syncthreads();
+      for (uint32_t e = threadIdx.x; e < S; e += blockDim.x) {
+        const uint32_t i1 = e / n0;
+        P[e] = key_add(tl[t.toff[0] + (e - i1 * n0)], tl[t.toff[1] + i1], J);
+      }
+      jp = j;
+    }
+    __syncthreads();
+    const uint2* lst = t.sl[k];
+    const int64_t cM = c * Mp;
+    const uintptr_t xa = (uintptr_t)t.X;
+    const int vw = (S % 4 == 0 && xa % 16 == 0) ? 4 : (S % 2 == 0 && xa % 8 == 0) ? 2 : 1;
+    auto run_v = [&](auto Vc) {
+      constexpr int V = decltype(Vc)::value;
+      constexpr int MV = MS / V;
+      typedef typename FVec<V>::T vt;
+      const vt* Xv = reinterpret_cast<const vt*>(t.X);
+      const uint32_t Sv = S / V;
+      const int tpi = Sv <= 64u * MV ? 64 : Sv <= 128u * MV ? 128 : 256;
+      const int ipw = 256 / tpi;
+      const int grp = threadIdx.x / tpi, li = threadIdx.x - grp * tpi;
+      for (uint32_t p0 = 0; p0 < Sv; p0 += (uint32_t)tpi * MV) {
+        const int plen = (int)(Sv - p0 < (uint32_t)tpi * MV ? Sv - p0 : (uint32_t)tpi * MV);
+        const int ms = (plen + tpi - 1) / tpi;
+        double run[MV][V];
+#pragma unroll
+        for (int m = 0; m < MV; ++m)
+#pragma unroll
+          for (int i = 0; i < V; ++i) run[m][i] = 0.0;
+        uint32_t cur = 0xffffffffu;   // key of the running sums (none yet)
+        auto flush = [&]() {
+#pragma unroll
+          for (int m = 0; m < MV; ++m)
+            if (m < ms && li + tpi * m < plen)
+#pragma unroll
+              for (int i = 0; i < V; ++i) {
+                const uint32_t pk = P[(p0 + li + tpi * m) * V + i];
+                uint32_t bk = (pk & TT_KEY_MASK) + cur;
+                bk = bk >= J ? bk - J : bk;
+                atomicAdd(&acc[bk], (pk & TT_KEY_SIGN) ? -run[m][i] : run[m][i]);
+              }
+#pragma unroll
+          for (int m = 0; m < MV; ++m)
+#pragma unroll
+            for (int i = 0; i < V; ++i) run[m][i] = 0.0;
+        };
+        for (int64_t e0 = qa + grp; e0 < qe; e0 += (int64_t)ipw * U) {
+          vt x[U][MV];
+          uint32_t ky[U], sg[U];
+          bool ok[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {   // all loads first, then the sums
+            const int64_t e = e0 + (int64_t)ipw * u;
+            ok[u] = e < qe;
+            const uint2 it = ok[u] ? lst[e] : make_uint2(0u, 0u);
+            ky[u] = it.y;
+            sg[u] = it.x & TT_KEY_SIGN;
+            const vt* base = Xv + ((int64_t)(it.x & TT_KEY_MASK) + cM) * Sv + p0 + li;
+#pragma unroll
+            for (int m = 0; m < MV; ++m)
+              x[u][m] = (ok[u] && m < ms && li + tpi * m < plen) ? __builtin_nontemporal_load(base + tpi * m)
+                                                                 : (vt)(0.0f);
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u)   // in list order
+            if (ok[u]) {
+              if (ky[u] != cur) {
+                if (cur != 0xffffffffu) flush();
+                cur = ky[u];
+              }
+#pragma unroll
+              for (int m = 0; m < MV; ++m)
+#pragma unroll
+                for (int i = 0; i < V; ++i) run[m][i] += signed_f64(lane_of<V>(x[u][m], i), sg[u]);
+            }
+        }
+        if (cur != 0xffffffffu) flush();
+      }
+    };
+    if (vw == 4) run_v(std::integral_constant<int, 4>());
+    else if (vw == 2) run_v(std::integral_constant<int, 2>());
+    else run_v(std::integral_constant<int, 1>());
+    __syncthreads();
+    const int64_t gc = cpre[j] + c;
+    const int64_t slot = w - owner(fpre[j] + c * F, W, Ttot);
+    double* out = part + (spre[gc] + slot) * (int64_t)Jmax;
+    for (uint32_t b = threadIdx.x; b < J; b += blockDim.x) out[b] = acc[b];
+    __syncthreads();
+    g = fpre[j] + c * F + qe;
+  }
+}
+
 // Y_j[b + J c] = sum over the partials of column (j, c), in slot order
 // (units: slabs for the slab launch, else fibres).
 __global__ void k_breduce(const BTensor* __restrict__ T, const int32_t* __restrict__ tids,
@@ -473,14 +620,6 @@ __global__ __launch_bounds__(256) void k_bsketch_0(const BTensor* __restrict__ T
     t.Y[b + (int64_t)J * i] = (float)s;
   }
 }
-
-// V-wide loads of FP32 values (V = 1, 2, 4)
-template <int V> struct FVec;
-template <> struct FVec<1> { typedef float T; };
-template <> struct FVec<2> { typedef float T __attribute__((ext_vector_type(2))); };
-template <> struct FVec<4> { typedef float T __attribute__((ext_vector_type(4))); };
-template <int V> __device__ __forceinline__ float lane_of(const typename FVec<V>::T& a, int i) { return a[i]; }
-template <> __device__ __forceinline__ float lane_of<1>(const float& a, int) { return a; }
 
 constexpr int kZoMS = 16, kZoU = 2;   // FP32 entries per lane of a slab piece, slabs per load batch
 
@@ -626,7 +765,13 @@ BKFn bk_kernel(int nj, int fib) {
 }
 typedef void (*BSFn)(const BTensor*, const int32_t*, const int64_t*, const int64_t*, const int64_t*, int32_t, int32_t,
                      double*, int32_t, int32_t);
-BSFn bs_kernel(int rows) { return rows == 4 ? k_bsketch_slab<4> : k_bsketch_slab<8>; }
+// slab steps: 4 or 8 rows in flight of the stream in memory order, or 1 or 2
+// slabs per group in flight of the key-sorted stream
+BSFn bs_kernel(int rows) {
+  return rows == 1 ? k_bsketch_ks<16, 1> : rows == 2 ? k_bsketch_ks<16, 2> : rows == 4 ? k_bsketch_slab<4>
+                                                                                      : k_bsketch_slab<8>;
+}
+bool slab_sorted(int rows) { return rows <= 2; }
 
 B0Fn b0_kernel(int nj, int fib) {
   if (nj == 2) return fib == 4 ? k_bsketch_0<2, 4> : k_bsketch_0<2, 8>;
@@ -663,10 +808,14 @@ struct tt_batch_s {
   size_t o_zids = 0;
   int32_t fid_n1 = 0;          // largest n_1 among fids
   size_t o_desc = 0, o_part = 0, o_counter = 0;
-  // the outer-tuple sorts of the k = 0 step, one launch set for all problems:
-  // argument sets and (set, chunk) per workgroup
-  size_t o_sargs = 0, o_ssrc = 0;
-  int32_t sort_sets = 0, sort_blocks = 0;
+  // the key sorts of step k, one launch set for all its problems (k = 0: the
+  // outer tuples; k >= 2 on the slab path: the slabs of a mode-k column, for
+  // the key-sorted slab kernel): argument sets and (set, chunk) per workgroup
+  size_t o_sargs[TT_MAX_ORDER] = {}, o_ssrc[TT_MAX_ORDER] = {};
+  int32_t sort_sets[TT_MAX_ORDER] = {}, sort_blocks[TT_MAX_ORDER] = {};
+  // slab steps whose slab offsets fit the key sort (the key-sorted kernel is
+  // then among the tuner's choices)
+  bool ssort[TT_MAX_ORDER] = {};
   // batched core updates per step k: descriptors, QR classes, launch bounds
   struct QrClass {
     int32_t rmax, rpt, off, cnt;
@@ -758,6 +907,7 @@ tt_status upload_desc(tt_batch b, const void* const* X) {
     t.off = p->at<uint32_t>(p->o_cnt);
     t.sorted = p->at<uint32_t>(p->o_sortO);
     t.zo = tt_sketch_fused01(p) ? p->at<float>(p->o_zo) : nullptr;
+    for (int s = 0; s < TT_MAX_ORDER; ++s) t.sl[s] = s >= 2 && s < p->d ? tt_fibre_list(p, s) : nullptr;
     for (int s = 0; s < TT_MAX_ORDER; ++s) {
       t.n[s] = s < p->d ? (int32_t)p->n[s] : 1;
       t.toff[s] = s < p->d ? (int32_t)p->tab_off[s] : 0;
@@ -805,9 +955,9 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (k == 0) {
-    if (b->sort_sets > 0 &&
-        (e = launch_outer_sorts_batched(b->ws + b->o_sargs, b->ws + b->o_ssrc, b->sort_sets, b->sort_blocks, b->Jmax,
-                                        b->stream)) != hipSuccess)
+    if (b->sort_sets[0] > 0 &&
+        (e = launch_outer_sorts_batched(b->ws + b->o_sargs[0], b->ws + b->o_ssrc[0], b->sort_sets[0],
+                                        b->sort_blocks[0], b->Jmax, b->stream)) != hipSuccess)
       return e;
     // the outer sketch, which Y_0 of those problems then reads: one launch per load width
     const int32_t* zids = reinterpret_cast<const int32_t*>(b->ws + b->o_zids);
@@ -835,6 +985,10 @@ hipError_t launch_step_sketch(tt_batch b, int k, int64_t Wk) {
   if (W > Ttot) W = Ttot;
   if (W < 1) W = 1;
   const size_t lds = step_lds(b, k);
+  if (b->slab[k] && slab_sorted(b->fib[k]) &&
+      (e = launch_outer_sorts_batched(b->ws + b->o_sargs[k], b->ws + b->o_ssrc[k], b->sort_sets[k], b->sort_blocks[k],
+                                      b->Jmax, b->stream)) != hipSuccess)
+    return e;
   if (b->slab[k])
     hipLaunchKernelGGL(bs_kernel(b->fib[k]), dim3((unsigned)W), dim3(256), lds, b->stream, T, tids, fpre, cpre, spre, nt,
                        k, part, b->Jmax, b->slab_S[k]);
@@ -1081,7 +1235,8 @@ bool nj_ok(tt_batch b, int nj) { return nj == 4 || (nj == 2 && b->max_n0 <= 128)
 
 // fibres (or, on slab steps, 64-entry rows) per lane group in flight
 std::vector<int> fib_choices(tt_batch b, int k) {
-  if (k == 0 || b->slab[k]) return {4, 8};
+  if (k == 0) return {4, 8};
+  if (b->slab[k]) return b->ssort[k] ? std::vector<int>{1, 2, 4, 8} : std::vector<int>{4, 8};
   return {8, 16};
 }
 
@@ -1215,9 +1370,11 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
     // slab units for k >= 2 when the largest slab table and table set fit in
     // kSlabLds bytes of LDS beside the accumulator
     b->slab[k] = k >= 2;
+    b->ssort[k] = k >= 2;
     for (int i = 0; i < count; ++i) {
       tt_plan p = b->plans[i];
       if (p->d <= k) continue;
+      if (p->N / (p->n[0] * p->n[1]) >= ((int64_t)1 << 31)) b->ssort[k] = false;   // slab offsets carry a sign bit
       // (clamped: any value past the LDS limit only turns the slab path off)
       const int64_t S = std::min<int64_t>((int64_t)p->n[0] * p->n[1], INT32_MAX);
       const int64_t tab = std::min<int64_t>((int64_t)p->tab_off[p->d], INT32_MAX);
@@ -1225,6 +1382,7 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
       b->slab_tab[k] = std::max(b->slab_tab[k], (int32_t)tab);
     }
     if (sizeof(uint32_t) * ((size_t)b->slab_S[k] + b->slab_tab[k]) > kSlabLds) b->slab[k] = false;
+    if (!b->slab[k]) b->ssort[k] = false;
     if (b->slab[k]) b->fib[k] = 8;
     for (int i = 0; i < count; ++i) {
       tt_plan p = b->plans[i];
@@ -1353,13 +1511,19 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
     b->o_spre[k] = o;
     o = align256(o + sizeof(int64_t) * b->spre[k].size());
   }
-  b->sort_sets = (int32_t)b->tids[0].size();
-  b->sort_blocks = 0;
-  for (int32_t j : b->tids[0]) b->sort_blocks += (int32_t)tt_sort_chunks(b->plans[j]->O0);
-  b->o_sargs = o;
-  o = align256(o + tt_sort_args_bytes() * (b->sort_sets + 1));
-  b->o_ssrc = o;
-  o = align256(o + sizeof(int2) * (b->sort_blocks + 1));
+  for (int k = 0; k < b->max_d; ++k) {
+    const std::vector<int32_t>& ids = k == 0 ? b->tids[0] : b->stids[k];
+    b->sort_sets[k] = k == 0 || b->ssort[k] ? (int32_t)ids.size() : 0;
+    b->sort_blocks[k] = 0;
+    for (int32_t i = 0; i < b->sort_sets[k]; ++i) {
+      tt_plan p = b->plans[ids[i]];
+      b->sort_blocks[k] += (int32_t)tt_sort_chunks(k == 0 ? p->O0 : p->N / (p->n[0] * p->n[1] * p->n[k]));
+    }
+    b->o_sargs[k] = o;
+    o = align256(o + tt_sort_args_bytes() * (b->sort_sets[k] + 1));
+    b->o_ssrc[k] = o;
+    o = align256(o + sizeof(int2) * (b->sort_blocks[k] + 1));
+  }
   b->o_part = o;
   o = align256(o + sizeof(double) * part_max * b->Jmax);
   b->o_counter = o;
@@ -1405,23 +1569,27 @@ tt_status tt_batch_bind_workspace(tt_batch b, void* dev_ws, size_t bytes) {
     if (!b->qidx[k].empty())
       TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_qidx[k], b->qidx[k].data(), sizeof(int32_t) * b->qidx[k].size(),
                                 hipMemcpyHostToDevice, b->stream));
-  // argument sets of the outer sorts (pointers into the plans' workspaces)
-  std::vector<char> sargs(tt_sort_args_bytes() * (b->sort_sets + 1));
-  std::vector<int2> ssrc;
-  for (int32_t i = 0; i < b->sort_sets; ++i) {
-    int32_t nb = 0;
-    const hipError_t e = tt_sort_args_outer(b->plans[b->tids[0][i]], sargs.data() + tt_sort_args_bytes() * i, &nb);
-    if (e != hipSuccess) return tt_fail(TT_ERR_SHAPE, "problem %d: outer tuples do not fit the sort", b->tids[0][i]);
-    for (int32_t w = 0; w < nb; ++w) ssrc.push_back(make_int2(i, w));
-  }
-  if ((int32_t)ssrc.size() != b->sort_blocks) return tt_fail(TT_ERR_STATE, "outer sort chunks changed");
-  if (b->sort_sets > 0) {
-    TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_sargs, sargs.data(), tt_sort_args_bytes() * b->sort_sets,
+  // argument sets of each step's key sorts (pointers into the plans' workspaces)
+  for (int k = 0; k < b->max_d; ++k) {
+    if (b->sort_sets[k] == 0) continue;
+    const std::vector<int32_t>& ids = k == 0 ? b->tids[0] : b->stids[k];
+    std::vector<char> sargs(tt_sort_args_bytes() * (b->sort_sets[k] + 1));
+    std::vector<int2> ssrc;
+    for (int32_t i = 0; i < b->sort_sets[k]; ++i) {
+      int32_t nb = 0;
+      char* at = sargs.data() + tt_sort_args_bytes() * i;
+      const hipError_t e = k == 0 ? tt_sort_args_outer(b->plans[ids[i]], at, &nb)
+                                  : tt_sort_args_slabs(b->plans[ids[i]], k, at, &nb);
+      if (e != hipSuccess) return tt_fail(TT_ERR_SHAPE, "problem %d: step-%d tuples do not fit the sort", ids[i], k);
+      for (int32_t w = 0; w < nb; ++w) ssrc.push_back(make_int2(i, w));
+    }
+    if ((int32_t)ssrc.size() != b->sort_blocks[k]) return tt_fail(TT_ERR_STATE, "sort chunks changed");
+    TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_sargs[k], sargs.data(), tt_sort_args_bytes() * b->sort_sets[k],
                               hipMemcpyHostToDevice, b->stream));
-    TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_ssrc, ssrc.data(), sizeof(int2) * ssrc.size(), hipMemcpyHostToDevice,
+    TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_ssrc[k], ssrc.data(), sizeof(int2) * ssrc.size(), hipMemcpyHostToDevice,
                               b->stream));
+    TT_HIP_TRY(hipStreamSynchronize(b->stream));   // before the host arrays go out of scope
   }
-  TT_HIP_TRY(hipStreamSynchronize(b->stream));
   fill_upd_buffers(b);
   b->desc_valid = false;
   b->upd_key.clear();
@@ -1575,9 +1743,9 @@ tt_status tt_batch_set_tuning(tt_batch b, const int64_t* in) {
     if ((v[1] != 2 && v[1] != 4) || !nj_ok(b, (int)v[1]))
       return tt_fail(TT_ERR_ARG, "step %d: entries per lane %lld (2 needs n_0 <= 128, else 4)", k, (long long)v[1]);
     const std::vector<int> fc = fib_choices(b, k);
-    if (v[2] != fc[0] && v[2] != fc[1])
-      return tt_fail(TT_ERR_ARG, "step %d: fibres (rows) in flight %lld not in {%d, %d}", k, (long long)v[2], fc[0],
-                     fc[1]);
+    if (std::find(fc.begin(), fc.end(), (int)v[2]) == fc.end() || v[2] != (int)v[2])
+      return tt_fail(TT_ERR_ARG, "step %d: fibres (rows, slabs) in flight %lld not among the step's choices", k,
+                     (long long)v[2]);
     if (v[3] < tt_gram_chunk_min() || v[3] > 8192 || v[3] % tt_gram_chunk_min() != 0)
       return tt_fail(TT_ERR_ARG, "step %d: Gram K-chunk %lld not a multiple of %d in [%d, 8192]", k, (long long)v[3],
                      tt_gram_chunk_min(), tt_gram_chunk_min());

@@ -444,8 +444,49 @@ hipError_t tt_sort_args_outer(const tt_plan_s* p, void* out, int32_t* nb) {
   return hipSuccess;
 }
 
-// The outer sorts of several plans in one launch set: args = nsets argument
-// sets (device memory), src = (set, chunk) per workgroup, nblocks workgroups.
+// The argument set of the sort of plan p's mode-k slabs (k >= 2): the
+// n_0 x n_1 slabs of a mode-k column (modes 2..d-1 except k; t = mu + M rho,
+// modes 2..k-1 giving mu) by their key over those modes, as {column-
+// independent slab offset rho n_k M + mu with the key's sign bit; bucket} in
+// the plan's mode-k list (which holds the larger mode-k fibre list of the
+// single-plan path).  Host memory, for the batched launches; *nb = chunks.
+hipError_t tt_sort_args_slabs(const tt_plan_s* p, int k, void* out, int32_t* nb) {
+  if (k < 2 || k >= p->d) return hipErrorInvalidValue;
+  SortArgs a{};
+  a.tab = p->at<uint32_t>(p->o_tab);
+  for (int s = 0; s < p->d; ++s) {
+    a.tab_off[s] = (int32_t)p->tab_off[s];
+    a.n[s] = (int32_t)p->n[s];
+  }
+  a.d = p->d;
+  a.J = (uint32_t)p->J;
+  SortJob& jb = a.job[0];
+  int64_t M = 1, Rk = 1;
+  for (int s = 2; s < k; ++s) M *= p->n[s];
+  for (int s = k + 1; s < p->d; ++s) Rk *= p->n[s];
+  const int64_t count = M * Rk;
+  if (count < 1 || p->n[k] * count >= ((int64_t)1 << 31)) return hipErrorInvalidValue;   // offsets carry a sign bit
+  jb.lo = 2;
+  jb.ex = k;
+  jb.fibre = 1;
+  jb.M = (uint32_t)M;
+  jb.nkM = (uint32_t)(p->n[k] * M);
+  jb.list = p->at<uint2>(p->o_flist) + p->flist_off[k];
+  jb.off = p->at<uint32_t>(p->o_foff) + (int64_t)k * (p->J_cap + 1);
+  jb.count = count;
+  jb.nb = (int32_t)tt_sort_chunks(count);
+  jb.chunk = (count + jb.nb - 1) / jb.nb;
+  jb.blk0 = 0;
+  jb.keys = p->at<uint32_t>(p->o_skeys) + p->skeys_off[k];
+  jb.hist = p->at<uint32_t>(p->o_hist) + p->hist_off[k];
+  a.njobs = 1;
+  std::memcpy(out, &a, sizeof a);
+  *nb = jb.nb;
+  return hipSuccess;
+}
+
+// The sorts of several plans in one launch set: args = nsets argument sets
+// (device memory), src = (set, chunk) per workgroup, nblocks workgroups.
 hipError_t launch_outer_sorts_batched(const void* args, const void* src, int32_t nsets, int32_t nblocks, int32_t J,
                                       hipStream_t st) {
   if (nsets <= 0) return hipSuccess;

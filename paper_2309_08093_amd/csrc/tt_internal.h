@@ -140,6 +140,7 @@ hipError_t launch_sweep_sorts(const tt_plan_s* p);         // every list of one 
 const uint2* tt_fibre_list(const tt_plan_s* p, int k);     // the k >= 1 fibre list of mode k
 size_t tt_sort_args_bytes();                               // one argument set of the key sorts
 hipError_t tt_sort_args_outer(const tt_plan_s* p, void* out, int32_t* nb);   // plan p's outer sort, host memory
+hipError_t tt_sort_args_slabs(const tt_plan_s* p, int k, void* out, int32_t* nb);   // mode-k slab sort (k >= 2)
 hipError_t launch_outer_sorts_batched(const void* args, const void* src, int32_t nsets, int32_t nblocks, int32_t J,
                                       hipStream_t st);
 hipError_t launch_sketch_tensor(const tt_plan_s* p, const void* X, int k, void* Y);

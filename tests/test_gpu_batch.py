@@ -339,8 +339,9 @@ def test_autotune_persists_its_choices(env, tmp_path):
     w2 = b2.autotune(Xs, reps=1, cache=cache)
     assert b2.tuned_from_cache and w2 == w1 and b2.get_tuning() == b1.get_tuning()
     for k, st in enumerate(b1.get_tuning()):
-        slabs = k == 0 or b1.sketch_kernel(k) == "k_bsketch_slab"
-        assert st["gram_kchunk"] in (256, 512, 1024) and st["fibres_in_flight"] in ((4, 8) if slabs else (8, 16))
+        slab = b1.sketch_kernel(k) == "k_bsketch_slab"
+        allowed = (4, 8) if k == 0 else (1, 2, 4, 8) if slab else (8, 16)
+        assert st["gram_kchunk"] in (256, 512, 1024) and st["fibres_in_flight"] in allowed
     # another batch (other problems) does not match the stored keys
     b3 = tts.Batch(PROBLEMS[:3])
     b3.autotune(Xs[:3], reps=1, cache=cache)
@@ -447,3 +448,47 @@ def test_outer_sketch_every_load_width(env, shift):
             want = sketch.data_sketch(Xh[i], p["n"], k, hs, vs, p["J"])
             got = Ys[i].cpu().numpy().astype(np.float64).reshape(want.shape, order="F")
             np.testing.assert_array_equal(got, want, err_msg="k=%d problem %d shift %d" % (k, i, shift))
+
+
+# slab steps with slabs longer than one piece of the key-sorted kernel
+# (n_0 n_1 = 5000 > 4096 values) beside short ones
+LONG_SLABS = [dict(n=[100, 50, 6, 5], ranks=[1, 3, 4, 3, 1], J=64, seed=171),
+              dict(n=[9, 7, 8, 6, 5], ranks=[1, 2, 3, 3, 2, 1], J=96, seed=172)]
+
+
+@pytest.mark.parametrize("which", ["default", "widths", "long slabs"])
+@pytest.mark.parametrize("slabs", [1, 2])
+def test_key_sorted_slab_steps_give_the_oracle_sketch(env, which, slabs):
+    """The key-sorted slab kernel (slab steps with 1 or 2 slabs per group in
+    flight) integer-exact against the oracle, for slabs of odd, even and
+    multiple-of-four size with X shifted off 16-byte alignment, and for slabs
+    longer than one piece."""
+    torch, tts = env
+    probs = {"default": PROBLEMS, "widths": WIDTHS, "long slabs": LONG_SLABS}[which]
+    say("key-sorted slabs %s, %d per group" % (which, slabs))
+    b = tts.Batch(probs)
+    Xs0, Xh = make_inputs(torch, probs, integer=True)
+    Xs = []
+    for x in Xs0:   # one value past a 256-byte boundary for half of the problems
+        shift = len(Xs) % 2
+        buf = torch.empty(x.numel() + shift, dtype=x.dtype, device=x.device)
+        buf[shift:] = x
+        Xs.append(buf[shift:])
+    steps = b.get_tuning()
+    dmax = max(len(p["n"]) for p in probs)
+    for k in range(2, dmax):
+        assert b.sketch_kernel(k) == "k_bsketch_slab", k
+        steps[k]["fibres_in_flight"] = slabs
+    steps[0]["workgroups"] = 0
+    b.set_tuning(steps)
+    assert all(b.get_tuning()[k]["fibres_in_flight"] == slabs for k in range(2, dmax))
+    for k in range(dmax):
+        Ys = b.sketch_tensor(Xs, k)
+        torch.cuda.synchronize()
+        for i, p in enumerate(probs):
+            if len(p["n"]) <= k:
+                continue
+            hs, vs = zip(*[b.plan_tables(i, s) for s in range(len(p["n"]))])
+            want = sketch.data_sketch(Xh[i], p["n"], k, hs, vs, p["J"])
+            got = Ys[i].cpu().numpy().astype(np.float64).reshape(want.shape, order="F")
+            np.testing.assert_array_equal(got, want, err_msg="k=%d problem %d" % (k, i))
