@@ -480,8 +480,12 @@ tt_status tt_batch_sweep(tt_batch batch, const void* const* X, void* const* cons
  *    (2 when every n_0 <= 128, or 4), fibres per lane group in flight (4 or 8
  *    at k = 0, 8 or 16 at k >= 1), and for k >= 1 workgroup counts of 1/2,
  *    1, 2, 4 and 8 times the device occupancy of that shape (at most 16384);
- *    slab steps (k >= 2 when the slabs fit in LDS) read whole 64-entry rows:
- *    rows per lane in flight (4 or 8) replace the fibres, and the entries
+ *    slab steps (k >= 2 when the slabs fit in LDS) take 4 or 8 in that
+ *    field for the stream of 64-entry rows in memory order (rows per lane in
+ *    flight), or 1 or 2 for the key-sorted slab stream (each column's slabs
+ *    sorted by their key over the modes other than 0, 1 and k, read whole,
+ *    slabs of one key summed in registers; slabs per lane group in flight;
+ *    offered when every problem's N / (n_0 n_1) is below 2^31); the entries
  *    per lane stay as set;
  *  - the Gram K-chunk of the step's core updates (256, 512 or 1024 rows of SH
  *    per partial product), timed with the partial sums.
@@ -493,8 +497,8 @@ tt_status tt_batch_autotune(tt_batch batch, const void* const* X, int32_t reps, 
 
 /* The batch's tuning, TT_MAX_ORDER steps of TT_BATCH_TUNE_FIELDS int64:
  * [0] workgroups of the data-sketch launch (0: device occupancy; 0 at k = 0),
- * [1] entries per lane, [2] fibres (slab steps: rows) per lane group in
- * flight, [3] Gram K-chunk.  set validates every used step (values as listed under
+ * [1] entries per lane, [2] fibres (slab steps: rows, or for the key-sorted
+ * slab stream slabs) per lane group in flight, [3] Gram K-chunk.  set validates every used step (values as listed under
  * tt_batch_autotune; the K-chunk may be any multiple of 256 up to 8192) and
  * returns TT_ERR_ARG, changing nothing, on the first bad one; it drops a
  * captured graph.  Steps at or beyond the largest order are ignored. */

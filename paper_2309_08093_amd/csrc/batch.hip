@@ -351,8 +351,8 @@ __global__ __launch_bounds__(256) void k_bsketch_slab(const BTensor* __restrict_
 // slab list, sorted by the key K over the modes other than 0, 1 and k.  A
 // slab is read whole (V-value vectors when n_0 n_1 and the address of X
 // allow it) by a group of TPI lanes (64, 128 or 256, the fewest that cover a
-// piece of 256 MS values with MS per lane), U slabs per load batch; the 256 /
-// TPI groups split the workgroup's share of the list.  A group keeps FP64
+// piece of 256 MV vectors with MV = min(MS / V, 8) per lane), U slabs per
+// load batch; the 256 / TPI groups split the workgroup's share of the list.  A group keeps FP64
 // running sums of its slabs' entries while K stays the same and adds them
 // to the accumulator at bucket P[e] + K when it changes: one LDS atomic per
 // entry of a run of equal keys instead of one per entry of X.
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(256) void k_bsketch_ks(const BTensor* __restrict__ 
     const int vw = (S % 4 == 0 && xa % 16 == 0) ? 4 : (S % 2 == 0 && xa % 8 == 0) ? 2 : 1;
     auto run_v = [&](auto Vc) {
       constexpr int V = decltype(Vc)::value;
-      constexpr int MV = MS / V;
+      constexpr int MV = MS / V < 8 ? MS / V : 8;   // at most 8 vectors per lane: registers
       typedef typename FVec<V>::T vt;
       const vt* Xv = reinterpret_cast<const vt*>(t.X);
       const uint32_t Sv = S / V;
@@ -1383,7 +1383,7 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
     }
     if (sizeof(uint32_t) * ((size_t)b->slab_S[k] + b->slab_tab[k]) > kSlabLds) b->slab[k] = false;
     if (!b->slab[k]) b->ssort[k] = false;
-    if (b->slab[k]) b->fib[k] = 8;
+    if (b->slab[k]) b->fib[k] = b->ssort[k] ? 1 : 8;   // the key-sorted slab stream by default
     for (int i = 0; i < count; ++i) {
       tt_plan p = b->plans[i];
       if (p->d <= k) continue;

@@ -198,9 +198,9 @@ def test_batch_tuning_round_trip_and_validation(abi):
     assert lib.tt_batch_get_tuning(h, buf) == abi.TT_OK
     before = list(buf)
     # defaults: occupancy-sized grids, 2 entries per lane (n_0 <= 128), 8 fibres at k = 0,
-    # 16 at k = 1, 8 rows on the slab steps, K-chunk 256
-    assert [before[k * F:(k + 1) * F] for k in range(4)] == [[0, 2, 8, 256], [0, 2, 16, 256], [0, 2, 8, 256],
-                                                             [0, 2, 8, 256]]
+    # 16 at k = 1, the key-sorted stream (1 slab per group) on the slab steps, K-chunk 256
+    assert [before[k * F:(k + 1) * F] for k in range(4)] == [[0, 2, 8, 256], [0, 2, 16, 256], [0, 2, 1, 256],
+                                                             [0, 2, 1, 256]]
     assert lib.tt_batch_set_tuning(h, buf) == abi.TT_OK
     for field, bad in ((1, 3), (2, 12), (3, 300), (3, 16384), (0, -1)):
         b2 = (ctypes.c_int64 * (abi.MAX_ORDER * F))(*before)
@@ -211,9 +211,13 @@ def test_batch_tuning_round_trip_and_validation(abi):
     b2[0] = 512                       # step 0 has no workgroup count
     assert lib.tt_batch_set_tuning(h, b2) == abi.TT_ERR_ARG
     b2 = (ctypes.c_int64 * (abi.MAX_ORDER * F))(*before)
-    b2[F * 2 + 2], b2[F * 2 + 3] = 4, 1024   # slab step: 4 rows; any K-chunk multiple of 256
+    b2[F * 2 + 2], b2[F * 2 + 3] = 4, 1024   # slab step: 4 rows in memory order; any K-chunk multiple of 256
     assert lib.tt_batch_set_tuning(h, b2) == abi.TT_OK
     assert lib.tt_batch_get_tuning(h, buf) == abi.TT_OK and buf[F * 2 + 2] == 4 and buf[F * 2 + 3] == 1024
+    for v, ok in ((2, True), (3, False), (16, False)):   # slab step: 1 or 2 key-sorted slabs, 4 or 8 rows
+        b2 = (ctypes.c_int64 * (abi.MAX_ORDER * F))(*before)
+        b2[F * 2 + 2] = v
+        assert lib.tt_batch_set_tuning(h, b2) == (abi.TT_OK if ok else abi.TT_ERR_ARG), v
     assert lib.tt_batch_get_tuning(None, buf) == abi.TT_ERR_ARG
     assert lib.tt_batch_set_tuning(h, None) == abi.TT_ERR_ARG
     lib.tt_batch_destroy(h)
