@@ -461,12 +461,16 @@ tt_status tt_batch_sketch_tensor(tt_batch batch, const void* const* X, int32_t k
  * device work): TT_BSKETCH_PATH_BUCKET for k = 0 (one workgroup per (problem,
  * bucket) gathers the fibres hashed to it), TT_BSKETCH_PATH_FIBRES (mode-0
  * fibres streamed into LDS bucket arrays; k = 1, and k >= 2 when slabs do not
- * fit in LDS) or TT_BSKETCH_PATH_SLABS (for k >= 2, the contiguous n_0 x n_1
- * slabs streamed 64 entries at a time with a per-problem LDS key table).
- * TT_ERR_ARG for k outside [0, max order) or null output. */
+ * fit in LDS), TT_BSKETCH_PATH_SLABS (for k >= 2, the contiguous n_0 x n_1
+ * slabs streamed 64 entries at a time with a per-problem LDS key table) or
+ * TT_BSKETCH_PATH_SLABS_SORTED (the same slabs read whole in the order of a
+ * per-step key sort, slabs of one key summed in registers), as the step's
+ * current tuning selects.  TT_ERR_ARG for k outside [0, max order) or null
+ * output. */
 #define TT_BSKETCH_PATH_BUCKET 0
 #define TT_BSKETCH_PATH_FIBRES 1
 #define TT_BSKETCH_PATH_SLABS 2
+#define TT_BSKETCH_PATH_SLABS_SORTED 3
 tt_status tt_batch_sketch_path(tt_batch batch, int32_t k, int32_t* path);
 
 /* One sweep of every problem.  X: count device pointers; cores: count host

@@ -111,7 +111,7 @@ class RunStats(ctypes.Structure):
 
 
 SKETCH_PATHS = {0: "k_sketch_mode0", 1: "k_sketch_modek", 2: "k_sketch_gs"}
-BSKETCH_PATHS = {0: "k_bsketch_0", 1: "k_bsketch_k", 2: "k_bsketch_slab"}
+BSKETCH_PATHS = {0: "k_bsketch_0", 1: "k_bsketch_k", 2: "k_bsketch_slab", 3: "k_bsketch_ks"}
 PROF_CLASSES = ["sketch_k0", "sketch_k", "sketch_aux", "interface", "gram", "solve", "qr", "residual", "tables",
                 "exact"]
 STRING_FUNCS = ["tt_last_error", "tt_version"]

@@ -1697,7 +1697,10 @@ tt_status tt_batch_sweep(tt_batch b, const void* const* X, void* const* const* c
 tt_status tt_batch_sketch_path(tt_batch b, int32_t k, int32_t* path) {
   if (!b || !path) return tt_fail(TT_ERR_ARG, "null argument");
   if (k < 0 || k >= b->max_d) return tt_fail(TT_ERR_ARG, "step %d outside [0, %d)", k, b->max_d);
-  *path = k == 0 ? TT_BSKETCH_PATH_BUCKET : b->slab[k] ? TT_BSKETCH_PATH_SLABS : TT_BSKETCH_PATH_FIBRES;
+  *path = k == 0                                    ? TT_BSKETCH_PATH_BUCKET
+          : b->slab[k] && slab_sorted(b->fib[k])    ? TT_BSKETCH_PATH_SLABS_SORTED
+          : b->slab[k]                              ? TT_BSKETCH_PATH_SLABS
+                                                    : TT_BSKETCH_PATH_FIBRES;
   return TT_OK;
 }
 

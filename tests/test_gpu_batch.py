@@ -18,6 +18,10 @@ PROBLEMS = [
 ]
 
 
+# the slab-step kernels: rows in memory order, or slabs in key order
+SLAB_KERNELS = ("k_bsketch_slab", "k_bsketch_ks")
+
+
 def say(msg):
     print("[case] " + msg, flush=True)
 
@@ -93,10 +97,10 @@ def test_batched_sketch_wide_fibres(env, which):
     b = tts.Batch(probs)
     Xs, Xh = make_inputs(torch, probs, integer=True)
     for k in range(max(len(p["n"]) for p in probs)):
-        # slabs for k >= 2 unless a participating problem's slab table does
-        # not fit in LDS (n = [130, 100, 3] at k = 2)
+        # slabs (key-sorted by default) for k >= 2 unless a participating
+        # problem's slab table does not fit in LDS (n = [130, 100, 3] at k = 2)
         want_kernel = "k_bsketch_0" if k == 0 else \
-            "k_bsketch_slab" if k >= 2 and (which, k) != ("large slabs", 2) else "k_bsketch_k"
+            "k_bsketch_ks" if k >= 2 and (which, k) != ("large slabs", 2) else "k_bsketch_k"
         assert b.sketch_kernel(k) == want_kernel, (k, b.sketch_kernel(k))
         Ys = b.sketch_tensor(Xs, k)
         torch.cuda.synchronize()
@@ -252,7 +256,7 @@ def _tuning_with(b, **kw):
     steps = b.get_tuning()
     for k, st in enumerate(steps):
         st.update(kw)
-        if "fibres_in_flight" in kw and (k == 0 or b.sketch_kernel(k) == "k_bsketch_slab"):
+        if "fibres_in_flight" in kw and (k == 0 or b.sketch_kernel(k) in SLAB_KERNELS):
             st["fibres_in_flight"] = kw["fibres_in_flight"] // 2
     steps[0]["workgroups"] = 0
     return steps
@@ -339,7 +343,7 @@ def test_autotune_persists_its_choices(env, tmp_path):
     w2 = b2.autotune(Xs, reps=1, cache=cache)
     assert b2.tuned_from_cache and w2 == w1 and b2.get_tuning() == b1.get_tuning()
     for k, st in enumerate(b1.get_tuning()):
-        slab = b1.sketch_kernel(k) == "k_bsketch_slab"
+        slab = b1.sketch_kernel(k) in SLAB_KERNELS
         allowed = (4, 8) if k == 0 else (1, 2, 4, 8) if slab else (8, 16)
         assert st["gram_kchunk"] in (256, 512, 1024) and st["fibres_in_flight"] in allowed
     # another batch (other problems) does not match the stored keys
@@ -477,11 +481,12 @@ def test_key_sorted_slab_steps_give_the_oracle_sketch(env, which, slabs):
     steps = b.get_tuning()
     dmax = max(len(p["n"]) for p in probs)
     for k in range(2, dmax):
-        assert b.sketch_kernel(k) == "k_bsketch_slab", k
+        assert b.sketch_kernel(k) in SLAB_KERNELS, k
         steps[k]["fibres_in_flight"] = slabs
     steps[0]["workgroups"] = 0
     b.set_tuning(steps)
     assert all(b.get_tuning()[k]["fibres_in_flight"] == slabs for k in range(2, dmax))
+    assert all(b.sketch_kernel(k) == "k_bsketch_ks" for k in range(2, dmax))
     for k in range(dmax):
         Ys = b.sketch_tensor(Xs, k)
         torch.cuda.synchronize()
