@@ -399,7 +399,9 @@ __global__ __launch_bounds__(256) void k_bsketch_ks(const BTensor* __restrict__ 
       jp = j;
     }
     __syncthreads();
-    const uint2* lst = t.sl[k];
+    // list entries {offset | sign, key} read as one 64-bit global load (x in the low half)
+    typedef const uint64_t __attribute__((address_space(1)))* gu64;
+    const gu64 lst = (gu64)t.sl[k];
     const int64_t cM = c * Mp;
     const uintptr_t xa = (uintptr_t)t.X;
     const int vw = (S % 4 == 0 && xa % 16 == 0) ? 4 : (S % 2 == 0 && xa % 8 == 0) ? 2 : 1;
@@ -407,7 +409,8 @@ __global__ __launch_bounds__(256) void k_bsketch_ks(const BTensor* __restrict__ 
       constexpr int V = decltype(Vc)::value;
       constexpr int MV = MS / V < 8 ? MS / V : 8;   // at most 8 vectors per lane: registers
       typedef typename FVec<V>::T vt;
-      const vt* Xv = reinterpret_cast<const vt*>(t.X);
+      typedef const vt __attribute__((address_space(1)))* gvt;   // global loads: off the LDS wait counter
+      const gvt Xv = (gvt)t.X;
       const uint32_t Sv = S / V;
       const int tpi = Sv <= 64u * MV ? 64 : Sv <= 128u * MV ? 128 : 256;
       const int ipw = 256 / tpi;
@@ -445,13 +448,14 @@ __global__ __launch_bounds__(256) void k_bsketch_ks(const BTensor* __restrict__ 
           for (int u = 0; u < U; ++u) {   // all loads first, then the sums
             const int64_t e = e0 + (int64_t)ipw * u;
             ok[u] = e < qe;
-            const uint2 it = ok[u] ? lst[e] : make_uint2(0u, 0u);
-            ky[u] = it.y;
-            sg[u] = it.x & TT_KEY_SIGN;
-            const vt* base = Xv + ((int64_t)(it.x & TT_KEY_MASK) + cM) * Sv + p0 + li;
+            const uint64_t it = ok[u] ? lst[e] : 0ull;
+            const uint32_t ix = (uint32_t)it;
+            ky[u] = (uint32_t)(it >> 32);
+            sg[u] = ix & TT_KEY_SIGN;
+            const gvt base = Xv + ((int64_t)(ix & TT_KEY_MASK) + cM) * Sv + p0 + li;
 #pragma unroll
             for (int m = 0; m < MV; ++m)
-              x[u][m] = (ok[u] && m < ms && li + tpi * m < plen) ? __builtin_nontemporal_load(base + tpi * m)
+              x[u][m] = (ok[u] && m < ms && li + tpi * m < plen) ? base[tpi * m]
                                                                  : (vt)(0.0f);
           }
 #pragma unroll
@@ -634,7 +638,9 @@ constexpr int kZoMS = 16, kZoU = 2;   // FP32 entries per lane of a slab piece, 
 // entries per lane) sums one slab of the bucket at a time in FP64 registers,
 // U slabs per load batch, the 256 / TPI groups splitting the bucket's list;
 // the groups are then added in a fixed order.  fids lists the problems of
-// this V.
+// this V.  Plain (L2-allocating) loads: the lines that two consecutive load
+// instructions of a group share are then fetched once (non-temporal loads
+// fetched them twice for 1- and 2-value vectors).
 template <int V, int MS, int U>
 __global__ __launch_bounds__(256) void kb_zo(const BTensor* __restrict__ T, const int32_t* __restrict__ fids,
                                              int32_t Jmax) {
@@ -651,7 +657,8 @@ __global__ __launch_bounds__(256) void kb_zo(const BTensor* __restrict__ T, cons
   const int grp = threadIdx.x / tpi, li = threadIdx.x - grp * tpi;
   const guint offg = (guint)t.off, sortg = (guint)t.sorted;
   const uint32_t beg = offg[c], end = offg[c + 1];
-  const vt* Xv = reinterpret_cast<const vt*>(t.X);
+  typedef const vt __attribute__((address_space(1)))* gvt;
+  const gvt Xv = (gvt)t.X;
   vt* zo = reinterpret_cast<vt*>(t.zo) + (int64_t)c * Sv;
   for (int64_t p0 = 0; p0 < Sv; p0 += (int64_t)tpi * MV) {
     const int plen = (int)(Sv - p0 < (int64_t)tpi * MV ? Sv - p0 : (int64_t)tpi * MV);
@@ -670,10 +677,10 @@ __global__ __launch_bounds__(256) void kb_zo(const BTensor* __restrict__ T, cons
         const bool ok = e < end;
         const uint32_t item = ok ? sortg[e] : 0u;
         sg[u] = item & TT_KEY_SIGN;
-        const vt* base = Xv + (int64_t)(item & TT_KEY_MASK) * Sv + p0 + li;
+        const gvt base = Xv + (int64_t)(item & TT_KEY_MASK) * Sv + p0 + li;
 #pragma unroll
         for (int m = 0; m < MV; ++m)
-          x[u][m] = (ok && m < ms && li + tpi * m < plen) ? __builtin_nontemporal_load(base + tpi * m) : (vt)(0.0f);
+          x[u][m] = (ok && m < ms && li + tpi * m < plen) ? base[tpi * m] : (vt)(0.0f);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)   // in list order
