@@ -831,6 +831,15 @@ struct tt_batch_s {
   std::vector<std::vector<QrClass>> qcls;
   std::vector<std::vector<int32_t>> qidx, qfall;   // QR class members (index into upd[k]); per-problem QRs
   size_t o_upd[TT_MAX_ORDER] = {}, o_qidx[TT_MAX_ORDER] = {};
+  // batched right-to-left orthogonalisation, per step s >= 1 (problems of
+  // order > s): descriptors, QR classes, per-problem QRs, largest G_{s-1}
+  // row count; columns of the sweep-start core transforms
+  std::vector<std::vector<BRo>> ro;
+  std::vector<std::vector<QrClass>> rcls;
+  std::vector<std::vector<int32_t>> ridx, rids, rfall;
+  size_t o_ro[TT_MAX_ORDER] = {}, o_ridx[TT_MAX_ORDER] = {};
+  int32_t ro_rows[TT_MAX_ORDER] = {};
+  int32_t fft0_cols = 0;
   // batched interface of each step: descriptors, largest core-transform and
   // output column counts, waves of a chain workgroup
   std::vector<std::vector<BIface>> bif;
@@ -1102,6 +1111,20 @@ tt_status upload_upd(tt_batch b, void* const* const* cores) {
       TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_bif[k], b->bif[k].data(), sizeof(BIface) * b->bif[k].size(),
                                 hipMemcpyHostToDevice, b->stream));
   }
+  for (int k = 1; k < b->max_d; ++k) {
+    for (size_t j = 0; j < b->ro[k].size(); ++j) {
+      const int i = b->rids[k][j];
+      tt_plan p = b->plans[i];
+      BRo& u = b->ro[k][j];
+      u.G = static_cast<double*>(cores[i][k]);
+      u.R = p->at<double>(p->o_qrR);
+      const bool fall = std::find(b->rfall[k].begin(), b->rfall[k].end(), (int32_t)j) != b->rfall[k].end();
+      u.Gprev = fall ? nullptr : static_cast<double*>(cores[i][k - 1]);
+    }
+    if (!b->ro[k].empty())
+      TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_ro[k], b->ro[k].data(), sizeof(BRo) * b->ro[k].size(),
+                                hipMemcpyHostToDevice, b->stream));
+  }
   TT_HIP_TRY(hipStreamSynchronize(b->stream));
   b->upd_key = key;
   return TT_OK;
@@ -1150,18 +1173,26 @@ tt_status enqueue_sweep(tt_batch b, void* const* const* cores) {
   auto restore = [&]() {
     for (int i = 0; i < b->count; ++i) b->plans[i]->stream = keep[i];
   };
-  // right-to-left orthogonalisation and core transforms, per problem
-  for (int i = 0; i < b->count; ++i) {
-    b->plans[i]->stream = lane_of(i);
-    if ((st = tt_sweep_begin(b->plans[i], reinterpret_cast<double* const*>(cores[i]), cd[i]))) {
-      restore();
-      return st;
+  // right-to-left orthogonalisation, one step s at a time for every problem
+  // of order > s (register QRs by class, taller ones per problem, then the
+  // absorb of R into core s - 1), and the transforms of cores 1..d-1
+  for (int k = b->max_d - 1; k >= 1; --k) {
+    const BRo* dr = reinterpret_cast<const BRo*>(b->ws + b->o_ro[k]);
+    const int32_t* ix = reinterpret_cast<const int32_t*>(b->ws + b->o_ridx[k]);
+    for (const auto& c : b->rcls[k]) TT_HIP_TRY(launch_qr_right_batched(dr, ix + c.off, c.cnt, c.rmax, c.rpt, main));
+    for (int32_t j : b->rfall[k]) {
+      const int i = b->rids[k][j];
+      tt_plan p = b->plans[i];
+      const BRo& u = b->ro[k][j];
+      p->stream = main;
+      double* const* G = reinterpret_cast<double* const*>(cores[i]);
+      TT_HIP_TRY(launch_qr_core(p, G[k], u.m, u.r, u.r, 1));
+      TT_HIP_TRY(launch_absorb_right(p, G[k - 1], u.rows, u.r));
+      p->stream = keep[i];
     }
+    TT_HIP_TRY(launch_absorb_right_batched(dr, (int32_t)b->ro[k].size(), b->ro_rows[k], main));
   }
-  for (int l = 0; l < kLanes; ++l) {
-    TT_HIP_TRY(hipEventRecord(b->ev_lane[l], b->lane[l]));
-    TT_HIP_TRY(hipStreamWaitEvent(main, b->ev_lane[l], 0));
-  }
+  TT_HIP_TRY(launch_core_fft_batched(b->ws + b->o_bif[0], (int32_t)b->tids[0].size(), b->Jmax, b->fft0_cols, main));
   for (int k = 0; k < b->max_d; ++k) {
     const int32_t nt = (int32_t)b->tids[k].size();
     // the transform of core k - 1 (changed in step k - 1) and the interface
@@ -1502,6 +1533,66 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
     b->o_qidx[k] = o;
     o = align256(o + sizeof(int32_t) * (b->qidx[k].size() + 1));
   }
+  // right-to-left orthogonalisation: QR of G_s^R transposed (n_s R_{s+1} x
+  // R_s) in register classes, per-problem QRs beyond them
+  b->ro.resize(b->max_d);
+  b->rcls.resize(b->max_d);
+  b->ridx.resize(b->max_d);
+  b->rids.resize(b->max_d);
+  b->rfall.resize(b->max_d);
+  for (int sidx = 1; sidx < b->max_d; ++sidx) {
+    for (int i = 0; i < count; ++i) {
+      tt_plan p = b->plans[i];
+      if (p->d <= sidx) continue;
+      BRo u{};
+      u.m = (int32_t)(p->n[sidx] * p->r[sidx + 1]);
+      u.r = (int32_t)p->r[sidx];
+      u.rows = (int32_t)(p->r[sidx - 1] * p->n[sidx - 1]);
+      b->ro[sidx].push_back(u);
+      b->rids[sidx].push_back(i);
+      b->ro_rows[sidx] = std::max(b->ro_rows[sidx], u.rows);
+    }
+    auto cls = [](const BRo& u, int32_t& rmax, int32_t& rpt) {
+      if (u.m > 4 * 512 || u.r > 16) return false;
+      rmax = u.r <= 4 ? 4 : (u.r <= 8 ? 8 : (u.r <= 12 ? 12 : 16));
+      rpt = u.m <= 512 ? 1 : (u.m <= 1024 ? 2 : 4);
+      return true;
+    };
+    for (size_t j = 0; j < b->ro[sidx].size(); ++j) {
+      int32_t rmax = 0, rpt = 0;
+      if (!cls(b->ro[sidx][j], rmax, rpt)) {
+        b->rfall[sidx].push_back((int32_t)j);
+        continue;
+      }
+      size_t c = 0;
+      while (c < b->rcls[sidx].size() && !(b->rcls[sidx][c].rmax == rmax && b->rcls[sidx][c].rpt == rpt)) ++c;
+      if (c == b->rcls[sidx].size()) b->rcls[sidx].push_back({rmax, rpt, 0, 0});
+      b->rcls[sidx][c].cnt += 1;
+    }
+    int32_t off = 0;
+    for (auto& c : b->rcls[sidx]) {
+      c.off = off;
+      off += c.cnt;
+      c.cnt = 0;
+    }
+    b->ridx[sidx].assign(off, 0);
+    for (size_t j = 0; j < b->ro[sidx].size(); ++j) {
+      int32_t rmax = 0, rpt = 0;
+      if (!cls(b->ro[sidx][j], rmax, rpt)) continue;
+      for (auto& c : b->rcls[sidx])
+        if (c.rmax == rmax && c.rpt == rpt) b->ridx[sidx][c.off + c.cnt++] = (int32_t)j;
+    }
+    b->o_ro[sidx] = o;
+    o = align256(o + sizeof(BRo) * (b->ro[sidx].size() + 1));
+    b->o_ridx[sidx] = o;
+    o = align256(o + sizeof(int32_t) * (b->ridx[sidx].size() + 1));
+  }
+  for (int i = 0; i < count; ++i) {
+    tt_plan p = b->plans[i];
+    int32_t cols = 0;
+    for (int c = 1; c < p->d; ++c) cols += (int32_t)(p->r[c] * p->r[c + 1]);
+    b->fft0_cols = std::max(b->fft0_cols, cols);
+  }
   b->o_fids = o;
   o = align256(o + sizeof(int32_t) * (b->fids.size() + 1));
   b->o_zids = o;
@@ -1575,6 +1666,10 @@ tt_status tt_batch_bind_workspace(tt_batch b, void* dev_ws, size_t bytes) {
   for (int k = 0; k < b->max_d; ++k)
     if (!b->qidx[k].empty())
       TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_qidx[k], b->qidx[k].data(), sizeof(int32_t) * b->qidx[k].size(),
+                                hipMemcpyHostToDevice, b->stream));
+  for (int k = 1; k < b->max_d; ++k)
+    if (!b->ridx[k].empty())
+      TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_ridx[k], b->ridx[k].data(), sizeof(int32_t) * b->ridx[k].size(),
                                 hipMemcpyHostToDevice, b->stream));
   // argument sets of each step's key sorts (pointers into the plans' workspaces)
   for (int k = 0; k < b->max_d; ++k) {

@@ -300,6 +300,18 @@ __global__ __launch_bounds__(kFftThreads) void kb_core_fft(const BIface* __restr
                        static_cast<const cplx<float>*>(u.tw), u.k - 1, u.k - 1, -1, blockIdx.x);
 }
 
+// Batched (FP32), at the start of a sweep: the transforms of cores 1..d-1
+// of problem blockIdx.y (the descriptors of step 0); columns past the
+// problem's count return at once.
+__global__ __launch_bounds__(kFftThreads) void kb_core_fft_all(const BIface* __restrict__ d) {
+  const BIface& u = d[blockIdx.y];
+  int64_t cols = 0;
+  for (int i = 1; i < u.cd.d; ++i) cols += (int64_t)u.cd.r0[i] * u.cd.r1[i];
+  if ((int64_t)blockIdx.x >= cols) return;
+  core_fft_body<float>(u.cd, u.tab, static_cast<cplx<float>*>(u.chat), u.J, FftPlan{u.fft_code, u.fft_nrad},
+                       static_cast<const cplx<float>*>(u.tw), 1, u.cd.d - 1, -1, blockIdx.x);
+}
+
 // grid.x covers the largest J; frequencies past a problem's J only take part
 // in the workgroup's barriers
 __global__ __launch_bounds__(64 * TT_MAX_RANK) void kb_chain(const BIface* __restrict__ d) {
@@ -414,5 +426,15 @@ hipError_t launch_fill_twiddles(const tt_plan_s* p) {
   else
     hipLaunchKernelGGL(k_fill_twiddles<float>, dim3(g), dim3(256), 0, p->stream, p->at<cplx<float>>(p->o_tw),
                        (int32_t)p->J);
+  return hipGetLastError();
+}
+
+hipError_t launch_core_fft_batched(const void* desc, int32_t nprob, int32_t Jmax, int32_t max_cols, hipStream_t st) {
+  if (nprob <= 0 || max_cols <= 0) return hipSuccess;
+  const size_t lds = 2 * (size_t)Jmax * sizeof(cplx<float>);
+  hipError_t e;
+  if ((e = tt_allow_lds(kb_core_fft_all, lds)) != hipSuccess) return e;
+  hipLaunchKernelGGL(kb_core_fft_all, dim3((unsigned)max_cols, (unsigned)nprob), dim3(kFftThreads), lds, st,
+                     static_cast<const BIface*>(desc));
   return hipGetLastError();
 }

@@ -360,6 +360,14 @@ __global__ __launch_bounds__(kQrRegThreads) __attribute__((amdgpu_waves_per_eu(1
   qr_reg_body<RMAX, RPT>((gdbl)u.G, m, u.rk1, 1, m, (gdbl)u.R);
 }
 
+// Batched: QR of G_s^R transposed (m x r, row stride r) of problem
+// idx[blockIdx.x], R into the problem's R buffer.
+template <int RMAX, int RPT>
+__global__ __launch_bounds__(kQrRegThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) void kb_qr_right(const BRo* __restrict__ d, const int32_t* __restrict__ idx) {
+  const BRo u = d[idx[blockIdx.x]];
+  qr_reg_body<RMAX, RPT>((gdbl)u.G, u.m, u.r, u.r, 1, (gdbl)u.R);
+}
+
 template <int RMAX>
 hipError_t qr_reg(const tt_plan_s* p, double* G, int64_t m, int64_t r, int64_t rs, int64_t cs) {
   double* R = p->at<double>(p->o_qrR);
@@ -435,6 +443,31 @@ __global__ void k_absorb_right(double* G, const double* __restrict__ R, int64_t 
   }
 }
 
+// Batched: G_{s-1}^L <- G_{s-1}^L R^T for problem blockIdx.y (thread per row).
+__global__ void kb_absorb_right(const BRo* __restrict__ d) {
+  const BRo u = d[blockIdx.y];
+  if (!u.Gprev) return;
+  const gdbl G = (gdbl)u.Gprev;
+  const cgdbl Rg = (cgdbl)u.R;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= u.rows) return;
+  const int r = u.r;
+  const int64_t rows = u.rows;
+  double x[TT_MAX_RANK];
+#pragma unroll
+  for (int q = 0; q < TT_MAX_RANK; ++q) x[q] = q < r ? G[p + rows * q] : 0.0;
+#pragma unroll
+  for (int b = 0; b < TT_MAX_RANK; ++b) {
+    if (b < r) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < TT_MAX_RANK; ++q)
+        if (q < r) acc += x[q] * Rg[b * r + q];
+      G[p + rows * b] = acc;
+    }
+  }
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -490,5 +523,36 @@ hipError_t launch_qr_batched(const BUpd* d, const int32_t* idx, int32_t nidx, in
 hipError_t launch_absorb_left_batched(const BUpd* d, int32_t nprob, int32_t max_cols, hipStream_t st) {
   if (nprob <= 0 || max_cols <= 0) return hipSuccess;   // last step: no problem has a next core
   hipLaunchKernelGGL(kb_absorb_left, dim3(nblk(max_cols, 256), (unsigned)nprob), dim3(256), 0, st, d);
+  return hipGetLastError();
+}
+
+template <int RMAX, int RPT>
+hipError_t qr_right_t(const BRo* d, const int32_t* idx, int32_t nidx, hipStream_t st) {
+  hipLaunchKernelGGL((kb_qr_right<RMAX, RPT>), dim3((unsigned)nidx), dim3(kQrRegThreads), 0, st, d, idx);
+  return hipGetLastError();
+}
+
+template <int RMAX>
+hipError_t qr_right_r(const BRo* d, const int32_t* idx, int32_t nidx, int32_t rpt, hipStream_t st) {
+  if (rpt <= 1) return qr_right_t<RMAX, 1>(d, idx, nidx, st);
+  if (rpt <= 2) return qr_right_t<RMAX, 2>(d, idx, nidx, st);
+  return qr_right_t<RMAX, 4>(d, idx, nidx, st);
+}
+
+// Problems of one class (RMAX >= R_s, RPT * 512 >= n_s R_{s+1}, at most 4
+// rows per thread) in one launch.
+hipError_t launch_qr_right_batched(const BRo* d, const int32_t* idx, int32_t nidx, int32_t rmax, int32_t rpt,
+                                   hipStream_t st) {
+  if (nidx <= 0) return hipSuccess;
+  if (rpt > 4) return hipErrorInvalidValue;
+  if (rmax <= 4) return qr_right_r<4>(d, idx, nidx, rpt, st);
+  if (rmax <= 8) return qr_right_r<8>(d, idx, nidx, rpt, st);
+  if (rmax <= 12) return qr_right_r<12>(d, idx, nidx, rpt, st);
+  return qr_right_r<16>(d, idx, nidx, rpt, st);
+}
+
+hipError_t launch_absorb_right_batched(const BRo* d, int32_t nprob, int32_t max_rows, hipStream_t st) {
+  if (nprob <= 0 || max_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_absorb_right, dim3(nblk(max_rows, 256), (unsigned)nprob), dim3(256), 0, st, d);
   return hipGetLastError();
 }

@@ -232,6 +232,22 @@ hipError_t launch_solve_batched(const BUpd* d, int32_t nprob, int32_t max_s, int
 hipError_t launch_qr_batched(const BUpd* d, const int32_t* idx, int32_t nidx, int32_t rmax, int32_t rpt, hipStream_t st);
 hipError_t launch_absorb_left_batched(const BUpd* d, int32_t nprob, int32_t max_cols, hipStream_t st);
 
+// One problem's step of the right-to-left orthogonalisation in the batched
+// form: QR of G_s^R transposed (m = n_s R_{s+1} rows, r = R_s columns, G_s
+// itself with row stride r), then G_{s-1} (rows = R_{s-1} n_{s-1} x r) <-
+// G_{s-1} R^T.  Gprev is null for a problem whose QR runs on its own.
+struct BRo {
+  double* G;
+  double* Gprev;
+  double* R;
+  int32_t m, r, rows;
+};
+hipError_t launch_qr_right_batched(const BRo* d, const int32_t* idx, int32_t nidx, int32_t rmax, int32_t rpt,
+                                   hipStream_t st);
+hipError_t launch_absorb_right_batched(const BRo* d, int32_t nprob, int32_t max_rows, hipStream_t st);
+// the transforms of cores 1..d-1 of every problem (the descriptors of step 0)
+hipError_t launch_core_fft_batched(const void* desc, int32_t nprob, int32_t Jmax, int32_t max_cols, hipStream_t st);
+
 // pieces of one sweep (api.hip), shared by tt_als_sweep and the batched driver
 CoreDesc tt_make_desc(const tt_plan_s* p, const void* const* cores);
 tt_status tt_sweep_begin(tt_plan p, double* const* G, const CoreDesc& cd);
