@@ -840,6 +840,9 @@ struct tt_batch_s {
   size_t o_ro[TT_MAX_ORDER] = {}, o_ridx[TT_MAX_ORDER] = {};
   int32_t ro_rows[TT_MAX_ORDER] = {};
   int32_t fft0_cols = 0;
+  // batched table generation: argument sets (device), largest table
+  size_t o_tabargs = 0;
+  int64_t tab_max = 0;
   // batched interface of each step: descriptors, largest core-transform and
   // output column counts, waves of a chain workgroup
   std::vector<std::vector<BIface>> bif;
@@ -1146,9 +1149,15 @@ tt_status enqueue_sweep(tt_batch b, void* const* const* cores) {
   tt_status st;
   if ((st = make_lanes(b))) return st;
   const hipStream_t main = b->stream;
+  // the next sweep's tables: one launch for every problem unless a plan's
+  // tables are overridden or its FFT roots still need filling (then per
+  // problem, on lanes)
+  bool tables_batched = b->o_tabargs != 0;
+  for (tt_plan p : b->plans) tables_batched = tables_batched && !p->override_tables && p->tw_J == p->J;
   TT_HIP_TRY(hipEventRecord(b->ev_fork, main));
   TT_HIP_TRY(hipStreamWaitEvent(b->side, b->ev_fork, 0));
-  for (int l = 0; l < kLanes; ++l) TT_HIP_TRY(hipStreamWaitEvent(b->lane[l], b->ev_fork, 0));
+  if (!tables_batched)
+    for (int l = 0; l < kLanes; ++l) TT_HIP_TRY(hipStreamWaitEvent(b->lane[l], b->ev_fork, 0));
   // data sketches
   b->stream = b->side;
   for (int k = 0; k < b->max_d; ++k) {
@@ -1226,6 +1235,12 @@ tt_status enqueue_sweep(tt_batch b, void* const* const* cores) {
   }
   // next sweep's tables, once the sketches (side stream) and the interface
   // sketches (batch stream) have read the current ones
+  if (tables_batched) {
+    TT_HIP_TRY(hipStreamWaitEvent(main, b->ev_done, 0));
+    for (tt_plan p : b->plans) p->sweep += 1;
+    TT_HIP_TRY(launch_gen_tables_batched(b->ws + b->o_tabargs, b->count, b->tab_max, main));
+    return TT_OK;
+  }
   TT_HIP_TRY(hipEventRecord(b->ev_main, main));
   for (int l = 0; l < kLanes; ++l) TT_HIP_TRY(hipStreamWaitEvent(b->lane[l], b->ev_main, 0));
   for (int i = 0; i < b->count; ++i) {
@@ -1626,6 +1641,9 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
   o = align256(o + sizeof(double) * part_max * b->Jmax);
   b->o_counter = o;
   o = align256(o + sizeof(int64_t));
+  b->o_tabargs = o;
+  o = align256(o + tt_tab_args_bytes() * (count + 1));
+  for (int i = 0; i < count; ++i) b->tab_max = std::max(b->tab_max, (int64_t)b->plans[i]->tab_off[b->plans[i]->d]);
   b->ws_need = o;
   b->host_desc.resize(count);
   *workspace_bytes = o;
@@ -1646,6 +1664,15 @@ tt_status tt_batch_bind_workspace(tt_batch b, void* dev_ws, size_t bytes) {
     p->dsweep = counter;
     const tt_status st = tt_plan_bind_workspace(p, b->ws + b->plan_off[i], p->ws_need);
     if (st) return st;
+  }
+  {
+    std::vector<char> targs(tt_tab_args_bytes() * (b->count + 1));
+    for (int i = 0; i < b->count; ++i)
+      if (tt_tab_args(b->plans[i], targs.data() + tt_tab_args_bytes() * i) != hipSuccess)
+        return tt_fail(TT_ERR_STATE, "problem %d: no device sweep counter", i);
+    TT_HIP_TRY(hipMemcpyAsync(b->ws + b->o_tabargs, targs.data(), tt_tab_args_bytes() * b->count,
+                              hipMemcpyHostToDevice, b->stream));
+    TT_HIP_TRY(hipStreamSynchronize(b->stream));
   }
   for (int k = 0; k < b->max_d; ++k) {
     if (!b->stids[k].empty())

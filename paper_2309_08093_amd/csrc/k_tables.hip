@@ -30,8 +30,7 @@ struct TabArgs {
 };
 
 // tab[off[s] + i] = h_s[i] | (v_s[i] < 0) << 31
-__global__ void k_gen_tables(uint32_t* tab, TabArgs a) {
-  const int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gen_tables_body(uint32_t* tab, const TabArgs& a, int32_t g) {
   if (g >= a.off[a.d]) return;
   int s = 0;
   while (g >= a.off[s + 1]) ++s;
@@ -44,6 +43,18 @@ __global__ void k_gen_tables(uint32_t* tab, TabArgs a) {
   const uint64_t xv = mix64(st + (ns + i + 1) * kGamma);
   const uint32_t h = (uint32_t)__umul64hi(xh, (uint64_t)a.J);   // floor(xh * J / 2^64)
   tab[g] = h | ((uint32_t)(xv >> 63) << 31);
+}
+
+__global__ void k_gen_tables(uint32_t* tab, TabArgs a) { gen_tables_body(tab, a, blockIdx.x * blockDim.x + threadIdx.x); }
+
+// Batched: the tables of problem blockIdx.y (its arguments in device memory).
+struct BTab {
+  uint32_t* tab;
+  TabArgs a;
+};
+__global__ void kb_gen_tables(const BTab* __restrict__ A) {
+  const BTab& t = A[blockIdx.y];
+  gen_tables_body(t.tab, t.a, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 struct KeyArgs {
@@ -309,6 +320,30 @@ hipError_t launch_gen_tables(const tt_plan_s* p, int64_t sweep) {
   const int64_t total = p->tab_off[p->d];
   hipLaunchKernelGGL(k_gen_tables, dim3(nblk(total, 256)), dim3(256), 0, p->stream,
                      p->at<uint32_t>(p->o_tab), a);
+  return hipGetLastError();
+}
+
+// The batched generator's argument set of plan p (host memory, the sweep
+// index read from the plan's device counter); launch over nprob sets with
+// max_entries the largest table size.
+size_t tt_tab_args_bytes() { return sizeof(BTab); }
+hipError_t tt_tab_args(const tt_plan_s* p, void* out) {
+  if (!p->dsweep) return hipErrorInvalidValue;
+  BTab t{};
+  t.tab = p->at<uint32_t>(p->o_tab);
+  for (int s = 0; s <= p->d; ++s) t.a.off[s] = (int32_t)p->tab_off[s];
+  t.a.d = p->d;
+  t.a.J = (uint32_t)p->J;
+  t.a.seed = p->seed;
+  t.a.sweep = 0;
+  t.a.dsweep = p->dsweep;
+  std::memcpy(out, &t, sizeof t);
+  return hipSuccess;
+}
+hipError_t launch_gen_tables_batched(const void* args, int32_t nprob, int64_t max_entries, hipStream_t st) {
+  if (nprob <= 0 || max_entries <= 0) return hipSuccess;
+  hipLaunchKernelGGL(kb_gen_tables, dim3(nblk(max_entries, 256), (unsigned)nprob), dim3(256), 0, st,
+                     static_cast<const BTab*>(args));
   return hipGetLastError();
 }
 

@@ -130,6 +130,10 @@ hipError_t launch_interface_batched(const void* desc, int32_t nprob, int32_t k, 
 
 // Launchers (each enqueues on p->stream; returns hipSuccess or the launch error)
 hipError_t launch_gen_tables(const tt_plan_s* p, int64_t sweep);
+// batched table generation (the sweep index from each plan's device counter)
+size_t tt_tab_args_bytes();
+hipError_t tt_tab_args(const tt_plan_s* p, void* out);
+hipError_t launch_gen_tables_batched(const void* args, int32_t nprob, int64_t max_entries, hipStream_t st);
 hipError_t launch_fill_twiddles(const tt_plan_s* p);   // o_tw <- exp(-2 pi i e / J), e < J
 hipError_t launch_build_keys(const tt_plan_s* p, uint32_t* out, int64_t count, int first, int last);
 hipError_t launch_build_keys_modes(const tt_plan_s* p, uint32_t* out, int64_t count, const int* modes, int nm);
