@@ -1135,16 +1135,16 @@ tt_status upload_upd(tt_batch b, void* const* const* cores) {
 
 // Enqueue one sweep of every problem.  The batched data sketches of all steps
 // need only X and the sweep's tables, so they go first, on the side stream,
-// one launch per step.  The right-to-left orthogonalisation of each problem
-// runs per problem on lanes (problem i on lane i mod kLanes), and the batch
-// stream joins the lanes before step 0.  Per step k, on the batch stream: one launch per
-// kernel computes the interface sketches (and the new transform of core
-// k - 1) of every problem of order > k; then one launch each covers the Gram,
-// the solve (summed partials, Cholesky, substitution) and the QR + absorb of
-// every problem of order > k (QR grouped by register shape; QRs too tall for
-// registers run per problem).  The next sweep's tables are drawn once every
-// sketch has read the current ones.  Everything forks from and joins back
-// into the batch stream.
+// one launch per step.  On the batch stream: the right-to-left
+// orthogonalisation, one step s at a time for every problem of order > s
+// (QRs grouped by register shape, taller ones per problem, one absorb launch),
+// and the transforms of cores 1..d-1 in one launch.  Then per step k: one
+// launch per kernel computes the interface sketches (and the new transform of
+// core k - 1) of every problem of order > k; then one launch each covers the
+// Gram, the solve (summed partials, Cholesky, substitution) and the QR +
+// absorb of every problem of order > k.  The next sweep's tables are drawn,
+// in one launch, once every sketch has read the current ones.  Everything
+// forks from and joins back into the batch stream.
 tt_status enqueue_sweep(tt_batch b, void* const* const* cores) {
   tt_status st;
   if ((st = make_lanes(b))) return st;
