@@ -92,11 +92,11 @@ typedef struct {
 
 /* Data sketches of a sweep (Algorithm 1 draws S once per outer iteration, so
  * all d sketches share the tables).  When d >= 3 the k = 0 pass over X can
- * also write the TensorSketch of X over modes 2..d-1 (J x n_0 x n_1 values
- * of the work type in the workspace), from which Y_1 follows without its own
- * pass over X.  By default this is done when that intermediate is small,
- * 2 J n_0 n_1 sizeof(work) <= N sizeof(X) / 2.  TT_FLAG_FUSE asks for it
- * whenever d >= 3, TT_FLAG_NO_FUSE never (not both).  tt_sketch_tensor(k)
+ * be the TensorSketch of X over modes 2..d-1 (J x n_0 x n_1 values of the
+ * work type in the workspace), from which Y_0 and Y_1 follow without their
+ * own passes over X.  By default this is done when that intermediate is
+ * small, 2 J n_0 n_1 sizeof(work) <= N sizeof(X) / 2.  TT_FLAG_FUSE asks for
+ * it whenever d >= 3, TT_FLAG_NO_FUSE never (not both).  tt_sketch_tensor(k)
  * is not affected: it always makes its own pass. */
 #define TT_FLAG_FUSE 2u
 #define TT_FLAG_NO_FUSE 4u

@@ -33,15 +33,15 @@
 //    fibres hashed to b: for each i_1 it visits the outer tuples (modes
 //    2..d-1) whose partial hash is (b - h_1(i_1)) mod J, found in a
 //    bucket-sorted list.  Accumulation is in registers; no atomics.
-//  * k = 0 and k = 1 from one pass (fused): the k = 0 gather already forms,
-//    for its bucket b and each i_1, the signed sum over the outer tuples
-//    hashed to (b - h_1(i_1)) mod J of the fibres X(:, i_1, o).  Those sums are
-//    the TensorSketch of X over modes 2..d-1, a J x n_0 x n_1 tensor.  The
-//    fused pass writes them out (i_1, then b, then i_0), and a second kernel
-//    scatters them into Y_1: entry (i_1, b, i_0) adds v_0(i_0) times the sum
-//    to bucket (b - h_1(i_1) + h_0(i_0)) mod J of column i_1.  This
-//    replaces the k = 1 pass over X by a write and a read of J n_0 n_1
-//    values, which pays when J n_0 n_1 is small against N.
+//  * k = 0 and k = 1 from one pass (fused): the TensorSketch of X over modes
+//    2..d-1 alone, the outer sketch (a J x n_0 x n_1 tensor: row (i_1, c)
+//    sums, with their signs, the fibres X(:, i_1, o) of the outer tuples o of
+//    key c), is formed from X once, slab by slab: the n_0 x n_1 slabs
+//    X(:, :, o) of one key are added whole.  Y_0 row b then sums rows
+//    (i_1, b - h_1(i_1)) of it with the signs of i_1, and Y_1 column i_1 adds
+//    row (i_1, c) value i_0 with the sign of i_0 to bucket (c + h_0(i_0)) mod
+//    J.  This replaces the k = 1 pass over X by a write and two reads of
+//    J n_0 n_1 values, which pays when J n_0 n_1 is small against N.
 #include "tt_internal.h"
 
 // threads per workgroup of the k >= 1 sketch kernels
@@ -223,13 +223,14 @@ __global__ void k_reduce_parts(const double* __restrict__ part, WT* __restrict__
 }
 
 // Y_1 from the outer sketch of the fused k = 0 pass.  Workgroup (s, i_1)
-// scatters rows b in [s J / S, (s + 1) J / S) of column i_1, one contiguous
-// range of the outer sketch, into a J-entry FP64 LDS array and writes it as
-// partial s of column i_1.  V: values per load (n_0 a multiple of V).
+// scatters rows (c, i_1) for c in [s J / S, (s + 1) J / S) (row c holds the
+// outer tuples of key c; its value i_0 goes to bucket (c + h_0(i_0)) mod J)
+// into a J-entry FP64 LDS array and writes it as partial s of column i_1.
+// V: values per load (n_0 a multiple of V).
 template <typename WT, int V>
 __global__ __launch_bounds__(256) void k_sketch_y1_outer(const WT* __restrict__ zo, const uint32_t* __restrict__ tab0,
-                                                         const uint32_t* __restrict__ tab1, double* __restrict__ part,
-                                                         int32_t n0, uint32_t J, int32_t S) {
+                                                         double* __restrict__ part, int32_t n0, int32_t n1, uint32_t J,
+                                                         int32_t S) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* acc = reinterpret_cast<double*>(smem_raw);
   uint32_t* t0 = reinterpret_cast<uint32_t*>(acc + J);
@@ -237,18 +238,16 @@ __global__ __launch_bounds__(256) void k_sketch_y1_outer(const WT* __restrict__ 
   for (uint32_t q = threadIdx.x; q < J; q += blockDim.x) acc[q] = 0.0;
   for (int q = threadIdx.x; q < n0; q += blockDim.x) t0[q] = tab0[q];
   __syncthreads();
-  const uint32_t h1 = tab1[i1] & TT_KEY_MASK;
   const uint32_t r0 = (uint32_t)((int64_t)s * J / S), r1 = (uint32_t)((int64_t)(s + 1) * J / S);
   const uint32_t nv = (r1 - r0) * (uint32_t)(n0 / V);   // vectors in the range (< 2^31)
   const uint32_t vpr = (uint32_t)(n0 / V);
-  const WT* base = zo + ((int64_t)i1 * J + r0) * (int64_t)n0;
+  const int64_t Sz = (int64_t)n0 * n1;                  // one outer key's rows
+  const WT* base = zo + (int64_t)r0 * Sz + (int64_t)i1 * n0;
   for (uint32_t q = threadIdx.x; q < nv; q += blockDim.x) {
     const uint32_t r = q / vpr;
     const uint32_t i0 = (q - r * vpr) * V;
-    const Vec<WT, V> x = load_vec<WT, V>(base + (int64_t)q * V);
-    // bucket of (r0 + r, i_0) before adding h_0: b - h_1 (mod J)
-    uint32_t c = r0 + r;
-    c = c >= h1 ? c - h1 : c + J - h1;
+    const Vec<WT, V> x = load_vec<WT, V>(base + (int64_t)r * Sz + i0);
+    const uint32_t c = r0 + r;   // the outer key of the row
 #pragma unroll
     for (int e = 0; e < V; ++e) {
       const uint32_t t = t0[i0 + e];
@@ -545,249 +544,152 @@ __global__ __launch_bounds__(256) void k_sketch_mode0(
   }
 }
 
-// V consecutive work-type values to dst (16-byte stores when aligned to that)
-template <typename WT, int V, typename ST>
-__device__ __forceinline__ void store_vec(WT* dst, const ST (&v)[V]) {
-  if constexpr (V * sizeof(WT) % 16 == 0) {
-    constexpr int C = 16 / sizeof(WT);
-    typedef WT raw_t __attribute__((ext_vector_type(C)));
-#pragma unroll
-    for (int q = 0; q < V / C; ++q) {
-      raw_t r;
-#pragma unroll
-      for (int e = 0; e < C; ++e) r[e] = (WT)v[q * C + e];
-      *reinterpret_cast<raw_t*>(dst + q * C) = r;
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < V; ++e) dst[e] = (WT)v[e];
-  }
-}
-
 // ---------------------------------------------------------------- k = 0 and the outer sketch
-// The fused k = 0 pass.  Waves 0 .. kReaders-1 (readers) gather the fibres
-// of bucket b as k_sketch_mode0 does, but keep, per lane group, the sum over
-// the list of the current i_1 only, without the sign of i_1.  When an i_1 is
-// done a reader copies its lane groups' partial sums into a ring of kRing
-// slots in LDS and goes on loading.  The last wave (writer) adds the lane
-// groups' partials of each slot, stores the row to the outer sketch at
-// zo[(i_1 J + b) n_0 + i_0] and accumulates Y_0 row b with the sign of i_1.
-// A wave's global loads and stores complete in order, so a store issued by a
-// reader would hold its next wait on loads for the store's latency (a full
-// memory round trip under load); the writer's stores hold only the writer.
-// Every wait is bounded: a wave that waits kSpinMax rounds without progress
-// sets bit 1 of the status word and leaves, and the others follow it (the
-// results are then invalid, and the next synchronising call says so).
-constexpr int kRing = 2;
-constexpr int kReaders = 4;
-constexpr uint32_t kSpinMax = 1u << 22;
-
-// LDS bytes of k_sketch_mode0_outer: the ring (FP64 partial sums: FP32 slots
-// cost the BF16 variant two waves of occupancy in conversions), its tags, the
-// counters
-constexpr size_t outer_lds_bytes(int V, int NJ) {
-  return (size_t)kReaders * kRing * 64 * NJ * V * sizeof(double) + (size_t)kReaders * kRing * 4 + (2 * kReaders + 2) * 4;
+// The fused k = 0 pass, slab by slab.  Workgroup (piece, c) adds its piece
+// of the n_0 x n_1 slabs X(:, :, o) of the outer tuples o hashed to bucket c
+// (modes 2..d-1), each with its sign, and writes the sum to the outer sketch
+// zo[c n_0 n_1 + i_1 n_0 + i_0] (one contiguous piece per workgroup).  Each
+// slab is contiguous and read by one
+// workgroup per piece, so a 128-byte line is fetched twice only where two
+// slabs or pieces meet.  Values are read as V-entry vectors (every slab
+// starts on a V-entry boundary when n_0 n_1 and the address of X allow it);
+// a group of TPI lanes (64, 128 or 256, the fewest that cover a piece of
+// 256 MV vectors with MV per lane) sums one slab at a time in FP64 registers,
+// U slabs per load batch, the 256 / TPI groups splitting the bucket's list
+// and adding up in a fixed order at the end.  Y_0 and Y_1 are then formed
+// from the outer sketch by the two kernels below.
+template <typename XT, int V>
+__device__ __forceinline__ Vec<XT, V> load_vec_plain(const XT* p) {
+  // plain (L2-allocating) loads: two load instructions that share a line
+  // fetch it once
+  typedef const XT __attribute__((address_space(1)))* gxt;
+  if constexpr (V == 1) {
+    return Vec<XT, 1>{{*(gxt)p}};
+  } else {
+    typedef XT raw_t __attribute__((ext_vector_type(V)));
+    typedef const raw_t __attribute__((address_space(1)))* graw;
+    const raw_t r = *(graw)p;
+    Vec<XT, V> out;
+#pragma unroll
+    for (int e = 0; e < V; ++e) out.e[e] = r[e];
+    return out;
+  }
 }
 
-template <typename XT, typename WT, int V, int NJ, int U>
-__global__ __launch_bounds__(64 * (kReaders + 1)) void k_sketch_mode0_outer(
-    const XT* __restrict__ X, const uint32_t* __restrict__ tab1, const uint32_t* __restrict__ off,
-    const uint32_t* __restrict__ sorted, WT* __restrict__ Y, WT* __restrict__ zo, int32_t* __restrict__ status,
-    int32_t n0, int32_t n1, uint32_t J, int32_t i0_lo, int32_t i0_cnt, int32_t lpf_log2) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int SW = 64 * NJ * V;                                   // values per slot, all lane groups
-  double* ring = reinterpret_cast<double*>(smem_raw);               // [reader][slot][lane group][position]
-  uint32_t* tag = reinterpret_cast<uint32_t*>(ring + kReaders * kRing * SW);   // sign of i_1 of each slot
-  int32_t* prod = reinterpret_cast<int32_t*>(tag + kReaders * kRing);         // rows handed over, per reader
-  int32_t* cons = prod + kReaders;                                              // rows taken, per reader
-  int32_t* fail = cons + kReaders;
-  const uint32_t b = blockIdx.x;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int LPF = 1 << lpf_log2;
-  const int G = 64 >> lpf_log2;
-  const int g = lane >> lpf_log2;
-  const int v = lane & (LPF - 1);
-  const int GS = LPF * NJ * V;                                      // slot values of one lane group
-  if (threadIdx.x < 2 * kReaders + 1) prod[threadIdx.x] = 0;        // prod, cons and fail
-  __syncthreads();
-
-  if (wv == kReaders) {
-    // ---- writer: positions p = (lane + 64 m) V + e of the row
-    double y0[NJ][V];
+template <typename XT, typename WT, int V, int MV, int U>
+__global__ __launch_bounds__(256) void k_sketch_zo(const XT* __restrict__ X, const uint32_t* __restrict__ off,
+                                                   const uint32_t* __restrict__ sorted, WT* __restrict__ zo,
+                                                   int64_t S) {
+  __shared__ double red[3 * 64 * MV * V];   // groups 1..3 (TPI = 64) or group 1 (TPI = 128)
+  const uint32_t c = blockIdx.y;
+  const int64_t Sv = S / V;
+  const int tpi = Sv <= 64 * MV ? 64 : Sv <= 128 * MV ? 128 : 256;
+  const int ipw = 256 / tpi;
+  const int grp = threadIdx.x / tpi, li = threadIdx.x - grp * tpi;
+  const int64_t p0 = (int64_t)blockIdx.x * tpi * MV;   // first vector of the piece
+  if (p0 >= Sv) return;
+  const int plen = (int)(Sv - p0 < (int64_t)tpi * MV ? Sv - p0 : (int64_t)tpi * MV);
+  const int ms = (plen + tpi - 1) / tpi;
+  const uint32_t beg = off[c], end = off[c + 1];
+  double acc[MV][V];
 #pragma unroll
-    for (int m = 0; m < NJ; ++m)
+  for (int m = 0; m < MV; ++m)
 #pragma unroll
-      for (int e = 0; e < V; ++e) y0[m][e] = 0.0;
-    int32_t done[kReaders], total[kReaders];
+    for (int i = 0; i < V; ++i) acc[m][i] = 0.0;
+  for (uint32_t e0 = beg + grp; e0 < end; e0 += ipw * U) {
+    Vec<XT, V> x[U][MV];
+    uint32_t sg[U];
 #pragma unroll
-    for (int w = 0; w < kReaders; ++w) {
-      done[w] = 0;
-      total[w] = w < n1 ? (n1 - 1 - w) / kReaders + 1 : 0;
-    }
-    uint32_t spins = 0;
-    while (true) {
-      bool all = true, progress = false;
+    for (int u = 0; u < U; ++u) {   // all loads first, then the sums
+      const uint32_t e = e0 + ipw * u;
+      const bool ok = e < end;
+      const uint32_t item = ok ? sorted[e] : 0u;
+      sg[u] = item & TT_KEY_SIGN;
+      const XT* base = X + (int64_t)(item & TT_KEY_MASK) * S + (p0 + li) * V;
 #pragma unroll
-      for (int w = 0; w < kReaders; ++w) {
-        if (done[w] >= total[w]) continue;
-        all = false;
-        const int32_t avail = __hip_atomic_load(&prod[w], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        while (done[w] < avail) {
-          const int sl = w * kRing + done[w] % kRing;
-          const double* slot = ring + sl * SW;
-          const uint32_t sg = tag[sl];
-          const int i1 = w + kReaders * done[w];
-          WT* row = zo + ((int64_t)i1 * J + b) * (int64_t)n0 + i0_lo;
+      for (int m = 0; m < MV; ++m) {
+        if (ok && m < ms && li + tpi * m < plen) {
+          x[u][m] = load_vec_plain<XT, V>(base + (int64_t)tpi * m * V);
+        } else {
 #pragma unroll
-          for (int m = 0; m < NJ; ++m) {
-            const int p0 = (lane + 64 * m) * V;
-            if (p0 < i0_cnt) {
-              // CW positions at a time (one 16-byte store when aligned)
-              constexpr int CW = V * sizeof(WT) % 16 == 0 ? 16 / (int)sizeof(WT) : V;
-#pragma unroll
-              for (int c = 0; c < V; c += CW) {
-                double sm[CW];
-#pragma unroll
-                for (int e = 0; e < CW; ++e) sm[e] = 0.0;
-#pragma unroll 1
-                for (int gg = 0; gg < G; ++gg)
-#pragma unroll
-                  for (int e = 0; e < CW; ++e) sm[e] += slot[gg * GS + p0 + c + e];
-                store_vec<WT, CW>(row + p0 + c, sm);
-#pragma unroll
-                for (int e = 0; e < CW; ++e) y0[m][c + e] += signed_f64(sm[e], sg);
-              }
-            }
-          }
-          ++done[w];
-          // the slot's values are in registers: hand it back
-          if (lane == 0) __hip_atomic_store(&cons[w], done[w], __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-          progress = true;
+          for (int i = 0; i < V; ++i) x[u][m].e[i] = XT(0);
         }
-      }
-      if (all) break;
-      if (progress) {
-        spins = 0;
-      } else {
-        if (++spins > kSpinMax || __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-          if (lane == 0) {
-            __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            atomicOr(status, 2);
-          }
-          return;
-        }
-        __builtin_amdgcn_s_sleep(1);
       }
     }
 #pragma unroll
-    for (int m = 0; m < NJ; ++m)
+    for (int u = 0; u < U; ++u)   // in list order
 #pragma unroll
-      for (int e = 0; e < V; ++e) {
-        const int p = (lane + 64 * m) * V + e;
-        if (p < i0_cnt) Y[(int64_t)b + (int64_t)J * (i0_lo + p)] = (WT)y0[m][e];
-      }
-    return;
+      for (int m = 0; m < MV; ++m)
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc[m][i] += signed_f64(x[u][m].e[i], sg[u]);
   }
+  if (ipw > 1) {
+    if (grp > 0)
+#pragma unroll
+      for (int m = 0; m < MV; ++m)
+        if (m < ms)
+#pragma unroll
+          for (int i = 0; i < V; ++i) red[((grp - 1) * tpi * MV + li + tpi * m) * V + i] = acc[m][i];
+    __syncthreads();
+    if (grp == 0)
+      for (int g = 1; g < ipw; ++g)
+#pragma unroll
+        for (int m = 0; m < MV; ++m)
+          if (m < ms)
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc[m][i] += red[((g - 1) * tpi * MV + li + tpi * m) * V + i];
+  }
+  WT* out = zo + (int64_t)c * S;
+  if (grp == 0)
+#pragma unroll
+    for (int m = 0; m < MV; ++m)
+      if (m < ms && li + tpi * m < plen) {
+        const int64_t e = (p0 + li + tpi * m) * V;   // slab position of the vector's first value
+#pragma unroll
+        for (int i = 0; i < V; ++i) out[e + i] = (WT)acc[m][i];
+      }
+}
 
-  // ---- readers: i_1 = wv + kReaders q, as in k_sketch_mode0
-  constexpr int NW = kReaders;
-  double fac[NJ][V];
-  int32_t cw = 0;   // rows handed over
-  for (int i1b = wv; i1b < n1; i1b += NW * 64) {
-    const int i1l = i1b + NW * lane;
-    uint32_t t1l = 0, begl = 0, endl = 0;
-    if (i1l < n1) {
-      t1l = tab1[i1l];
-      const uint32_t h1 = t1l & TT_KEY_MASK;
+// Y_0 from the outer sketch: row b of Y_0 adds, for every i_1, row
+// ((b - h_1(i_1)) mod J, i_1) of the sketch with the sign of i_1.  Thread t
+// keeps i_0 = t + 256 j (j < NJ0, n_0 <= 256 NJ0) in FP64 registers; R rows
+// are loaded before they are added.
+template <typename WT, int NJ0>
+__global__ __launch_bounds__(256) void k_sketch_y0_zo(const WT* __restrict__ zo, const uint32_t* __restrict__ tab1,
+                                                      WT* __restrict__ Y, int32_t n0, int32_t n1, uint32_t J) {
+  constexpr int R = 16 / NJ0;
+  typedef const WT __attribute__((address_space(1)))* gwt;
+  const uint32_t b = blockIdx.x;
+  double acc[NJ0];
+#pragma unroll
+  for (int j = 0; j < NJ0; ++j) acc[j] = 0.0;
+  for (int r0 = 0; r0 < n1; r0 += R) {
+    WT x[R][NJ0];
+    uint32_t sg[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int i1 = r0 + u;
+      const bool ok = i1 < n1;
+      const uint32_t t1 = ok ? tab1[i1] : 0u;
+      const uint32_t h1 = t1 & TT_KEY_MASK;
       const uint32_t c = b >= h1 ? b - h1 : b + J - h1;
-      begl = off[c];
-      endl = off[c + 1];
-    }
-    const int nq0 = (n1 - i1b + NW - 1) / NW;
-    const int nq = nq0 < 64 ? nq0 : 64;
-    uint32_t nxt;
-    {
-      const uint32_t nb0 = (uint32_t)__shfl((int)begl, 0, 64), ne0 = (uint32_t)__shfl((int)endl, 0, 64);
-      nxt = (nb0 + lane < ne0) ? sorted[nb0 + lane] : 0u;
-    }
-    auto issue = [&](uint32_t itl, int t, int nb, int i1, Vec<XT, V> (&x)[U][NJ], uint32_t (&sg)[U], bool (&ok)[U]) {
+      sg[u] = t1 & TT_KEY_SIGN;
+      const gwt row = (gwt)(zo + ((int64_t)c * n1 + i1) * n0);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int idx = t + u * G + g;
-        ok[u] = idx < nb;
-        const uint32_t item = (uint32_t)__shfl((int)itl, idx & 63, 64);
-        sg[u] = item & TT_KEY_SIGN;
-        const XT* base = X + ((int64_t)(item & TT_KEY_MASK) * n1 + i1) * (int64_t)n0 + i0_lo;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          const int p = (v + LPF * j) * V;
-          if (ok[u] && p < i0_cnt) x[u][j] = load_vec<XT, V>(base + p);
-        }
-      }
-    };
-    auto consume = [&](const Vec<XT, V> (&x)[U][NJ], const uint32_t (&sg)[U], const bool (&ok)[U]) {
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          const int p = (v + LPF * j) * V;
-          if (ok[u] && p < i0_cnt)
-#pragma unroll
-            for (int e = 0; e < V; ++e) fac[j][e] += signed_f64(x[u][j].e[e], sg[u]);
-        }
-    };
-    Vec<XT, V> xa[U][NJ];
-    uint32_t sga[U];
-    bool oka[U];
-    for (int q = 0; q < nq; ++q) {
-      const uint32_t t1 = (uint32_t)__shfl((int)t1l, q, 64);
-      const uint32_t beg = (uint32_t)__shfl((int)begl, q, 64), end = (uint32_t)__shfl((int)endl, q, 64);
-      const int i1 = i1b + NW * q;
-      const uint32_t first = nxt;
-      if (q + 1 < nq) {
-        const uint32_t nb1 = (uint32_t)__shfl((int)begl, q + 1, 64), ne1 = (uint32_t)__shfl((int)endl, q + 1, 64);
-        nxt = (nb1 + lane < ne1) ? sorted[nb1 + lane] : 0u;
-      }
-#pragma unroll
-      for (int j = 0; j < NJ; ++j)
-#pragma unroll
-        for (int e = 0; e < V; ++e) fac[j][e] = 0.0;
-      for (uint32_t e0 = beg; e0 < end; e0 += 64) {
-        const uint32_t itl = e0 == beg ? first : ((e0 + lane < end) ? sorted[e0 + lane] : 0u);
-        const int nb = (end - e0) < 64u ? (int)(end - e0) : 64;
-        for (int t = 0; t < nb; t += G * U) {
-          issue(itl, t, nb, i1, xa, sga, oka);
-          consume(xa, sga, oka);
-        }
-      }
-      // wait for a free slot, fill it, publish it
-      uint32_t spins = 0;
-      while (cw - __hip_atomic_load(&cons[wv], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= kRing) {
-        if (++spins > kSpinMax || __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-          if (lane == 0) {
-            __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            atomicOr(status, 2);
-          }
-          return;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-      const int sl = wv * kRing + cw % kRing;
-      double* slot = ring + sl * SW + g * GS;
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        const int p = (v + LPF * j) * V;
-        if (p < i0_cnt)
-#pragma unroll
-          for (int e = 0; e < V; ++e) slot[p + e] = fac[j][e];
-      }
-      ++cw;
-      if (lane == 0) {
-        tag[sl] = t1 & TT_KEY_SIGN;
-        __hip_atomic_store(&prod[wv], cw, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      for (int j = 0; j < NJ0; ++j) {
+        const int i0 = threadIdx.x + 256 * j;
+        x[u][j] = ok && i0 < n0 ? row[i0] : WT(0);
       }
     }
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int j = 0; j < NJ0; ++j) acc[j] += signed_f64(x[u][j], sg[u]);
+  }
+#pragma unroll
+  for (int j = 0; j < NJ0; ++j) {
+    const int i0 = threadIdx.x + 256 * j;
+    if (i0 < n0) Y[b + (int64_t)J * i0] = (WT)acc[j];
   }
 }
 
@@ -888,7 +790,7 @@ hipError_t run_gs(const tt_plan_s* p, const XT* X, int k, WT* Y, int lpf_log2) {
 }
 
 template <typename XT, typename WT, int V, int NJ>
-hipError_t run_mode0(const tt_plan_s* p, const XT* X, WT* Y, WT* zo, int lpf_log2, int64_t chunk) {
+hipError_t run_mode0(const tt_plan_s* p, const XT* X, WT* Y, int lpf_log2, int64_t chunk) {
   constexpr int U = NJ >= 4 ? 1 : 4 / NJ;
   hipError_t e;
   {
@@ -899,23 +801,54 @@ hipError_t run_mode0(const tt_plan_s* p, const XT* X, WT* Y, WT* zo, int lpf_log
   const uint32_t* tab1 = p->at<uint32_t>(p->o_tab) + p->tab_off[1];
   const uint32_t* off = p->at<uint32_t>(p->o_cnt);
   const uint32_t* sorted = p->at<uint32_t>(p->o_sortO);
-  const size_t lds = zo ? outer_lds_bytes(V, NJ) : (size_t)4 * 64 * NJ * V * sizeof(double);
-  int32_t* status = p->at<int32_t>(p->o_status);
-  if (zo && (e = tt_allow_lds(k_sketch_mode0_outer<XT, WT, V, NJ, U>, lds)) != hipSuccess) return e;
+  const size_t lds = (size_t)4 * 64 * NJ * V * sizeof(double);
   TTProfScope ps(p, TT_PROF_SKETCH0);
   for (int64_t lo = 0; lo < n0; lo += chunk) {
     const int64_t cnt = (n0 - lo) < chunk ? (n0 - lo) : chunk;
-    if (zo)
-      hipLaunchKernelGGL((k_sketch_mode0_outer<XT, WT, V, NJ, U>), dim3((unsigned)p->J), dim3(64 * (kReaders + 1)),
-                         lds, p->stream, X, tab1, off, sorted, Y, zo, status, (int32_t)n0, (int32_t)n1,
-                         (uint32_t)p->J, (int32_t)lo, (int32_t)cnt, lpf_log2);
-    else
-      hipLaunchKernelGGL((k_sketch_mode0<XT, WT, V, NJ, U>), dim3((unsigned)p->J), dim3(256), lds, p->stream, X,
-                         tab1, off, sorted, Y, (int32_t)n0, (int32_t)n1, (uint32_t)p->J, (int32_t)lo, (int32_t)cnt,
-                         lpf_log2);
+    hipLaunchKernelGGL((k_sketch_mode0<XT, WT, V, NJ, U>), dim3((unsigned)p->J), dim3(256), lds, p->stream, X, tab1, off,
+                       sorted, Y, (int32_t)n0, (int32_t)n1, (uint32_t)p->J, (int32_t)lo, (int32_t)cnt, lpf_log2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// The fused k = 0 pass: the outer sketch from the slabs (V-value loads when
+// n_0 n_1 and the address of X allow), then Y_0 from it.
+template <typename XT, typename WT, int V>
+hipError_t run_zo_v(const tt_plan_s* p, const XT* X, WT* Y, WT* zo) {
+  constexpr int MV = 16 / V;
+  const int64_t n0 = p->n[0], n1 = p->n[1], S = n0 * n1, Sv = S / V;
+  const int64_t pieces = Sv <= 128 * MV ? 1 : (Sv + 256 * MV - 1) / (256 * MV);
+  const uint32_t* off = p->at<uint32_t>(p->o_cnt);
+  const uint32_t* sorted = p->at<uint32_t>(p->o_sortO);
+  hipLaunchKernelGGL((k_sketch_zo<XT, WT, V, MV, 2>), dim3((unsigned)pieces, (unsigned)p->J), dim3(256), 0, p->stream,
+                     X, off, sorted, zo, S);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint32_t* tab1 = p->at<uint32_t>(p->o_tab) + p->tab_off[1];
+  const dim3 g((unsigned)p->J);
+  const int32_t a0 = (int32_t)n0, a1 = (int32_t)n1;
+  const uint32_t J = (uint32_t)p->J;
+  if (n0 <= 256) hipLaunchKernelGGL((k_sketch_y0_zo<WT, 1>), g, dim3(256), 0, p->stream, zo, tab1, Y, a0, a1, J);
+  else if (n0 <= 512) hipLaunchKernelGGL((k_sketch_y0_zo<WT, 2>), g, dim3(256), 0, p->stream, zo, tab1, Y, a0, a1, J);
+  else if (n0 <= 1024) hipLaunchKernelGGL((k_sketch_y0_zo<WT, 4>), g, dim3(256), 0, p->stream, zo, tab1, Y, a0, a1, J);
+  else if (n0 <= 2048) hipLaunchKernelGGL((k_sketch_y0_zo<WT, 8>), g, dim3(256), 0, p->stream, zo, tab1, Y, a0, a1, J);
+  else if (n0 <= 4096) hipLaunchKernelGGL((k_sketch_y0_zo<WT, 16>), g, dim3(256), 0, p->stream, zo, tab1, Y, a0, a1, J);
+  else return hipErrorInvalidValue;   // not reached: plans take n_0 <= TT_MAX_N0 = 4096
+  return hipGetLastError();
+}
+
+template <typename XT, typename WT>
+hipError_t run_zo(const tt_plan_s* p, const XT* X, WT* Y, WT* zo) {
+  hipError_t e;
+  {
+    TTProfScope ps(p, TT_PROF_SKETCH_AUX);
+    if (!p->lists_ready && (e = launch_outer_sort(p)) != hipSuccess) return e;
+  }
+  TTProfScope ps(p, TT_PROF_SKETCH0);
+  constexpr int VV = 16 / (int)sizeof(XT);
+  const bool vec = (p->n[0] * p->n[1]) % VV == 0 && ((uintptr_t)X % 16) == 0;
+  return vec ? run_zo_v<XT, WT, VV>(p, X, Y, zo) : run_zo_v<XT, WT, 1>(p, X, Y, zo);
 }
 
 // Lanes per fibre (power of two <= 64) and vector loads per lane for n0.
@@ -935,13 +868,14 @@ hipError_t dispatch_v(const tt_plan_s* p, const XT* X, int k, WT* Y, WT* zo) {
   const int64_t n0 = p->n[0];
   int lpf, nj;
   if (k == 0) {
+    if (zo) return run_zo<XT, WT>(p, X, Y, zo);
     // the k = 0 gather covers at most 64 * 4 * V positions of i_0 per launch
     const int64_t chunk = 64 * 4 * V;
     lane_shape(n0 < chunk ? n0 : chunk, V, &lpf, &nj);
     switch (nj) {
-      case 1: return run_mode0<XT, WT, V, 1>(p, X, Y, zo, lpf, chunk);
-      case 2: return run_mode0<XT, WT, V, 2>(p, X, Y, zo, lpf, chunk);
-      default: return run_mode0<XT, WT, V, 4>(p, X, Y, zo, lpf, chunk);
+      case 1: return run_mode0<XT, WT, V, 1>(p, X, Y, lpf, chunk);
+      case 2: return run_mode0<XT, WT, V, 2>(p, X, Y, lpf, chunk);
+      default: return run_mode0<XT, WT, V, 4>(p, X, Y, lpf, chunk);
     }
   }
   lane_shape(n0, V, &lpf, &nj);
@@ -994,7 +928,7 @@ hipError_t run_y1_outer(const tt_plan_s* p, void* Yv) {
   {
     TTProfScope ps(p, TT_PROF_SKETCH_AUX);
     hipLaunchKernelGGL(kern, dim3((unsigned)S, (unsigned)n1), dim3(256), lds, p->stream, p->at<WT>(p->o_zo),
-                       tab + p->tab_off[0], tab + p->tab_off[1], part, (int32_t)n0, (uint32_t)p->J, S);
+                       tab + p->tab_off[0], part, (int32_t)n0, (int32_t)n1, (uint32_t)p->J, S);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   TTProfScope ps(p, TT_PROF_SKETCH_AUX);
