@@ -204,6 +204,41 @@ def test_sketch_all_fused(tts, n, J, xd, wd):
         assert rel(Y, Yo) < tol and colmax(Y, Yo) < tol, (k, rel(Y, Yo), colmax(Y, Yo))
 
 
+# key-grouped sketches at k >= 2 with fibres that straddle 128-byte lines at
+# every phase: FP32 in 4-value loads (n_0 = 72, 96) and single values
+# (n_0 = 77, fibres on 4-byte boundaries), FP64 (n_0 = 40), BF16 (n_0 = 136);
+# X also shifted off its allocation's alignment (16 bytes keeps the vector
+# loads, 4 bytes makes them single values)
+LINE_CASES = [([72, 6, 9, 7], 16, "f32", 0), ([72, 6, 9, 7], 16, "f32", 4), ([72, 6, 9, 7], 16, "f32", 1),
+              ([96, 5, 6, 8], 12, "f32", 0), ([77, 5, 8, 6], 12, "f32", 0), ([40, 6, 8, 5], 12, "f64", 0),
+              ([40, 6, 8, 5], 12, "f64", 2), ([136, 4, 6, 5], 8, "bf16", 0), ([136, 4, 6, 5], 8, "bf16", 8)]
+
+
+@pytest.mark.parametrize("n,J,xd,shift", LINE_CASES)
+def test_sketch_straddling_lines(tts, n, J, xd, shift):
+    say("sketch straddling lines", n, J, xd, shift)
+    N = int(np.prod(n))
+    plan = tts.Plan(n, [1] * (len(n) + 1), J, 1e-3, seed=9, x_dtype=xd, work_dtype="f64" if xd == "f64" else "f32")
+    assert all(plan.sketch_kernel(k) == "k_sketch_gs" for k in range(2, len(n)))
+    hs, vs = host_tables(plan)
+    for kind in ("integer", "gaussian"):
+        Xh = (synth.rng(11).integers(-4, 5, size=N).astype(np.float64) if kind == "integer"
+              else synth.rng(12).standard_normal(N))
+        xt = to_dev_x(Xh, xd)
+        buf = torch.empty(N + shift, dtype=xt.dtype, device=DEV)
+        buf[shift:] = xt
+        X = buf[shift:]
+        Xo = synth.upcast_host(synth.to_dtype_host(Xh, xd))
+        for k in range(2, len(n)):
+            Y = plan.sketch_tensor(X, k).cpu().numpy().astype(np.float64).reshape(J, n[k], order="F")
+            Yo = sketch.data_sketch(Xo, n, k, hs, vs, J)
+            if kind == "integer":
+                assert np.array_equal(Y, Yo), (k, np.abs(Y - Yo).max())
+            else:
+                tol = 1e-12 if xd == "f64" else 1e-5
+                assert rel(Y, Yo) < tol and colmax(Y, Yo) < tol, (k, rel(Y, Yo), colmax(Y, Yo))
+
+
 def test_sketch_fusion_rule(tts):
     say("sketch fusion rule")
     # O_0 = n_2 ... n_{d-1} = 3600 outer tuples >= 4 J: fused by default
