@@ -428,17 +428,26 @@ WIDTHS = [dict(n=[7, 9, 10, 10, 12], ranks=[1, 3, 4, 4, 3, 1], J=64, seed=161),
           dict(n=[8, 6, 10, 10, 12], ranks=[1, 3, 4, 4, 3, 1], J=64, seed=163)]
 
 
+# outer-sketch problems whose slabs are longer than one piece of the k = 0
+# pass (n_0 n_1 = 4800 in 4-value loads, 4331 in single values)
+LONG_OUTER = [dict(n=[80, 60, 8, 8, 8], ranks=[1, 3, 4, 4, 3, 1], J=64, seed=181),
+              dict(n=[71, 61, 8, 8, 8], ranks=[1, 3, 4, 4, 3, 1], J=64, seed=182)]
+
+
+@pytest.mark.parametrize("which", ["widths", "long slabs"])
 @pytest.mark.parametrize("shift", [0, 1, 2])
-def test_outer_sketch_every_load_width(env, shift):
+def test_outer_sketch_every_load_width(env, which, shift):
     """Every Y_k integer-exact against the oracle for slabs of odd, even and
-    multiple-of-four size, with X at an aligned address and at 1 and 2
-    values past one (narrower loads for the same problems)."""
+    multiple-of-four size and slabs longer than one piece, with X at an
+    aligned address and at 1 and 2 values past one (narrower loads for the
+    same problems)."""
     torch, tts = env
-    say("outer sketch load widths, X shifted by %d values" % shift)
-    srcs = [tts.Plan(p["n"], p["ranks"], p["J"], 1e-3).sketch_sources()[1] for p in WIDTHS]
-    assert srcs == [0, 0, 0], srcs
-    b = tts.Batch(WIDTHS)
-    Xs0, Xh = make_inputs(torch, WIDTHS, integer=True)
+    probs = WIDTHS if which == "widths" else LONG_OUTER
+    say("outer sketch load widths %s, X shifted by %d values" % (which, shift))
+    srcs = [tts.Plan(p["n"], p["ranks"], p["J"], 1e-3).sketch_sources()[1] for p in probs]
+    assert srcs == [0] * len(probs), srcs
+    b = tts.Batch(probs)
+    Xs0, Xh = make_inputs(torch, probs, integer=True)
     Xs = []
     for x in Xs0:   # the same values at an address shift * 4 bytes past a 256-byte boundary
         buf = torch.empty(x.numel() + shift, dtype=x.dtype, device=x.device)
@@ -447,7 +456,7 @@ def test_outer_sketch_every_load_width(env, shift):
     for k in (0, 1, 2, 3, 4):
         Ys = b.sketch_tensor(Xs, k)
         torch.cuda.synchronize()
-        for i, p in enumerate(WIDTHS):
+        for i, p in enumerate(probs):
             hs, vs = zip(*[b.plan_tables(i, s) for s in range(len(p["n"]))])
             want = sketch.data_sketch(Xh[i], p["n"], k, hs, vs, p["J"])
             got = Ys[i].cpu().numpy().astype(np.float64).reshape(want.shape, order="F")

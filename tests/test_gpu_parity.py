@@ -161,9 +161,9 @@ def test_data_sketch_float(tts, n, J, xd, wd):
 
 
 # all d sketches of a sweep with the outer sketch of the k = 0 pass forced on
-# (Y_1 derived from it): f64, bf16 with short fibres (lane groups folded),
-# n_0 above the k = 0 chunk, n_0 = 1, n_1 = 1, scalar loads, two vectors per
-# lane, J = 1
+# (Y_0 and Y_1 derived from it): f64, bf16 with short fibres (lane groups
+# folded), n_0 above the k = 0 chunk, n_0 = 1, n_1 = 1, scalar loads, two
+# vectors per lane, J = 1, slabs longer than one piece
 FUSED_CASES = [
     ([16, 16, 16, 16], 256, "f64", "f64"),
     ([37, 5, 9, 4], 60, "f32", "f32"),
@@ -176,6 +176,8 @@ FUSED_CASES = [
     ([300, 12, 10, 7], 30, "f32", "f32"),
     ([20, 30, 40, 10], 60, "f32", "f32"),
     ([12, 9, 7], 1, "f32", "f32"),
+    ([90, 50, 4, 4, 4], 8, "f32", "f32"),     # slabs of 4500 values: two pieces per slab
+    ([77, 61, 4, 4, 3], 8, "f32", "f32"),     # 4697 (odd): single values, two pieces
 ]
 
 
