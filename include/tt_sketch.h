@@ -101,6 +101,21 @@ typedef struct {
 #define TT_FLAG_FUSE 2u
 #define TT_FLAG_NO_FUSE 4u
 
+/* Data sketches of modes k >= 2 (d >= 4, n_0 <= 1024): the pass of mode 2
+ * can instead write the TensorSketch of every slab X(:, :, o) over modes 0
+ * and 1 alone (Z: J x prod(n_2..n_{d-1}) values of the work type in the
+ * workspace; row o holds sum v_0(i_0) v_1(i_1) X(i_0, i_1, o) at bucket
+ * (h_0(i_0) + h_1(i_1)) mod J).  Y_k for every k >= 2 follows from Z by the
+ * TensorSketch over the remaining modes (a cyclic shift of each row by their
+ * bucket, times their sign), so one pass over X serves all of them.  By
+ * default this is done when it moves fewer bytes,
+ * N sizeof(X) + (d - 1) |Z| sizeof(work) <= 0.75 (d - 2) N sizeof(X).
+ * TT_FLAG_INNER asks for it whenever d >= 4 and n_0 <= 1024,
+ * TT_FLAG_NO_INNER never (not both).  Independent of TT_FLAG_FUSE;
+ * tt_sketch_tensor(k) is not affected. */
+#define TT_FLAG_INNER 16u
+#define TT_FLAG_NO_INNER 32u
+
 /* Workspace for the exact (unsketched) update: tt_exact_rhs, tt_prox_exact,
  * tt_als_sweep_exact, and the exact fallback sweep of tt_als_run.  Adds two
  * buffers of max_k R_k n_k ... n_{d-1} and two of the largest right-chain
@@ -179,8 +194,9 @@ tt_status tt_sketch_sparse_all(tt_plan plan, int64_t nnz, const int32_t* coords,
 
 /* How tt_sketch_tensor_all and tt_als_sweep obtain each Y_k (host query, no
  * device work): src[k] = k when Y_k takes its own pass over X, src[k] = j != k
- * when it is derived from an intermediate written by the pass of mode j.
- * src: host array of d entries. */
+ * when it is derived from an intermediate written by the pass of mode j
+ * (src[1] = 0 with the outer sketch of TT_FLAG_FUSE, src[k] = 2 for k > 2
+ * with the inner sketch of TT_FLAG_INNER).  src: host array of d entries. */
 tt_status tt_plan_sketch_sources(tt_plan plan, int32_t* src);
 
 /* Interface sketch SH_k = S_{-k} (G_{>k}^T (x) G_{<k}) (Theorem 1 and 2,

@@ -50,7 +50,7 @@ class Plan:
     tensor) and runs on a HIP stream (torch's current stream by default)."""
 
     def __init__(self, n, ranks, J, lam, seed=0, x_dtype="f32", work_dtype="f32", gram="work",
-                 device="cuda", stream=None, serial=False, fuse=None, exact=False):
+                 device="cuda", stream=None, serial=False, fuse=None, exact=False, inner=None):
         self.n = [int(x) for x in n]
         self.ranks = [int(x) for x in ranks]
         self.d = len(self.n)
@@ -65,7 +65,8 @@ class Plan:
         self._n_arr = (ctypes.c_int64 * self.d)(*self.n)
         self._r_arr = (ctypes.c_int64 * (self.d + 1))(*self.ranks)
         flags = (_abi.TT_FLAG_SERIAL if serial else 0) | (_abi.TT_FLAG_EXACT if exact else 0) | \
-            {None: 0, True: _abi.TT_FLAG_FUSE, False: _abi.TT_FLAG_NO_FUSE}[fuse]
+            {None: 0, True: _abi.TT_FLAG_FUSE, False: _abi.TT_FLAG_NO_FUSE}[fuse] | \
+            {None: 0, True: _abi.TT_FLAG_INNER, False: _abi.TT_FLAG_NO_INNER}[inner]
         desc = _abi.PlanDesc(self.d, self._n_arr, self._r_arr, self.J, self.lam, int(seed) & (2 ** 64 - 1),
                              _DT[x_dtype], _DT[work_dtype], _GRAM[gram], flags)
         if stream is None:

@@ -14,6 +14,8 @@ TT_FLAG_SERIAL = 1
 TT_FLAG_FUSE = 2
 TT_FLAG_NO_FUSE = 4
 TT_FLAG_EXACT = 8
+TT_FLAG_INNER = 16
+TT_FLAG_NO_INNER = 32
 
 MAX_ORDER, MAX_J, MAX_RANK, MAX_S, MAX_N0 = 16, 8192, 16, 180, 4096
 NOALLOC_SCRATCH_BYTES = 32 << 20

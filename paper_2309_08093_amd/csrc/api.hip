@@ -154,8 +154,11 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   const int d = desc->d;
   if (d < 2 || d > TT_MAX_ORDER) return tt_fail(TT_ERR_SHAPE, "order d=%d outside [2, %d]", d, TT_MAX_ORDER);
   if (!desc->n || !desc->r) return tt_fail(TT_ERR_ARG, "null n or r");
-  if (desc->flags & ~(TT_FLAG_SERIAL | TT_FLAG_FUSE | TT_FLAG_NO_FUSE | TT_FLAG_EXACT))
+  if (desc->flags & ~(TT_FLAG_SERIAL | TT_FLAG_FUSE | TT_FLAG_NO_FUSE | TT_FLAG_EXACT | TT_FLAG_INNER |
+                      TT_FLAG_NO_INNER))
     return tt_fail(TT_ERR_ARG, "unknown flags");
+  if ((desc->flags & TT_FLAG_INNER) && (desc->flags & TT_FLAG_NO_INNER))
+    return tt_fail(TT_ERR_ARG, "TT_FLAG_INNER and TT_FLAG_NO_INNER together");
   if ((desc->flags & TT_FLAG_FUSE) && (desc->flags & TT_FLAG_NO_FUSE))
     return tt_fail(TT_ERR_ARG, "TT_FLAG_FUSE and TT_FLAG_NO_FUSE together");
   if (desc->x_dtype != TT_F64 && desc->x_dtype != TT_F32 && desc->x_dtype != TT_BF16)
@@ -263,6 +266,21 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
     const int64_t e = p->n[1] * tt_outer_slices(p) * p->J_cap;
     if (e > p->part_entries) p->part_entries = e;
   }
+  // inner sketch Z of the k >= 2 pass (TT_FLAG_INNER); its Y_k stages keep
+  // n_k x slices partials of J entries
+  bool inner = false;
+  if (d >= 4 && p->n[0] <= 1024 && !(p->flags & TT_FLAG_NO_INNER)) {
+    const double zi_bytes = (double)p->wsize() * (double)p->J_cap * (double)p->O0;
+    const double x_bytes = (double)N * (double)p->xsize();
+    inner = (p->flags & TT_FLAG_INNER) || x_bytes + (d - 1) * zi_bytes <= 0.75 * (d - 2) * x_bytes;
+  }
+  p->o_zi = 0;
+  if (inner) {
+    for (int k = 2; k < d; ++k) {
+      const int64_t e = p->n[k] * tt_inner_slices(p, k) * p->J_cap;
+      if (e > p->part_entries) p->part_entries = e;
+    }
+  }
   p->gram_chunks = tt_gram_chunks(p->J);
   // residual work units: (outer tuple, block of 64 i_1), four waves per block
   p->res_waves = tt_residual_waves(p->O0, p->n[1]);
@@ -325,6 +343,8 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_pol = take(sizeof(float) * TT_MAX_ORDER * (TT_JPOLICY_FEATURES + TT_JPOLICY_OUTPUTS));
   // outer sketch of the fused k = 0 pass (J_cap x n_0 x n_1)
   p->o_zo = fuse ? take(ws * (size_t)p->J_cap * (size_t)p->n[0] * (size_t)p->n[1]) : 0;
+  // inner sketch of the k >= 2 pass (J_cap x O0)
+  p->o_zi = inner ? take(ws * (size_t)p->J_cap * (size_t)p->O0) : 0;
   p->o_spacc = take(sizeof(double) * (size_t)p->J_cap * (size_t)p->tab_off[d]);
   // exact update
   p->o_exphi = p->o_exch = p->o_expart = p->o_exgram = p->o_exmerge = 0;
@@ -552,6 +572,7 @@ tt_status tt_sketch_tensor_all(tt_plan p, const void* X, void* Yall) {
   }
   p->lists_ready = true;
   const bool fused = tt_sketch_fused01(p);
+  const bool inner = tt_sketch_inner(p);
   char* Yb = static_cast<char*>(Yall);
   for (int k = 0; k < p->d; ++k) {
     void* Yk = Yb + p->wsize() * p->J * p->tab_off[k];
@@ -559,6 +580,8 @@ tt_status tt_sketch_tensor_all(tt_plan p, const void* X, void* Yall) {
       TT_HIP_TRY(launch_sketch_mode0_outer(p, X, Yk));
     } else if (fused && k == 1) {
       TT_HIP_TRY(launch_sketch_y1_outer(p, Yk));
+    } else if (inner && k >= 2) {
+      if (k == 2) TT_HIP_TRY(launch_sketch_inner(p, X, Yall));
     } else {
       TT_HIP_TRY(launch_sketch_tensor(p, X, k, Yk));
     }
@@ -589,6 +612,8 @@ tt_status tt_plan_sketch_sources(tt_plan p, int32_t* src) {
   if (!p || !src) return tt_fail(TT_ERR_ARG, "null argument");
   for (int k = 0; k < p->d; ++k) src[k] = k;
   if (tt_sketch_fused01(p)) src[1] = 0;
+  if (tt_sketch_inner(p))
+    for (int k = 3; k < p->d; ++k) src[k] = 2;
   return TT_OK;
 }
 
@@ -807,6 +832,7 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
   // chain stream; both fork from and join back into the plan's stream.
   const bool overlap = !(p->flags & TT_FLAG_SERIAL);
   const bool fused = tt_sketch_fused01(p);
+  const bool inner = tt_sketch_inner(p);
   char* Yall = p->ws + p->o_Yall;
   StreamRestore restore{p};
   // the bucket and fibre lists of every data sketch of the sweep are built
@@ -834,8 +860,10 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
     if ((st = sort_lists())) return st;
     for (int k = 0; k < d; ++k) {
       void* Yk = Yall + p->wsize() * p->J * p->tab_off[k];
-      const hipError_t e = fused && k == 0 ? launch_sketch_mode0_outer(p, X, Yk)
+      const hipError_t e = fused && k == 0   ? launch_sketch_mode0_outer(p, X, Yk)
                            : fused && k == 1 ? launch_sketch_y1_outer(p, Yk)
+                           : inner && k > 2  ? hipSuccess   // written with Y_2
+                           : inner && k == 2 ? launch_sketch_inner(p, X, Yall)
                                              : launch_sketch_tensor(p, X, k, Yk);
       if (e != hipSuccess) return tt_fail(TT_ERR_HIP, "data sketch launch failed: %s", hipGetErrorString(e));
       TT_HIP_TRY(hipEventRecord(p->ev_y[k], p->side));
@@ -860,6 +888,10 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
         TT_HIP_TRY(launch_sketch_mode0_outer(p, X, Y));
         TT_HIP_TRY(launch_sketch_y1_outer(p, Yall + p->wsize() * p->J * p->tab_off[1]));
       }
+    } else if (inner && k >= 2) {
+      // Y_2 .. Y_{d-1} from the one pass, into their slots of the all-mode buffer
+      Y = Yall + p->wsize() * p->J * p->tab_off[k];
+      if (k == 2) TT_HIP_TRY(launch_sketch_inner(p, X, Yall));
     } else {
       TT_HIP_TRY(launch_sketch_tensor(p, X, k, Y));
     }

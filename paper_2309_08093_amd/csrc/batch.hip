@@ -1378,7 +1378,7 @@ tt_status tt_batch_plan(int32_t count, const tt_plan_desc* descs, void* hip_stre
       return tt_fail(TT_ERR_SHAPE, "problem %d: the batched form needs d >= 2 and n_0 <= 256", i);
     }
     tt_plan_desc sd = ds;
-    sd.flags |= TT_FLAG_SERIAL;
+    sd.flags |= TT_FLAG_SERIAL | TT_FLAG_NO_INNER;   // the batch forms every Y_k itself
     size_t ws = 0;
     tt_plan p = nullptr;
     const tt_status st = tt_sketch_plan(&sd, hip_stream, &ws, &p);

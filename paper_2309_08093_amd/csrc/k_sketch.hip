@@ -693,6 +693,125 @@ __global__ __launch_bounds__(256) void k_sketch_y0_zo(const WT* __restrict__ zo,
   }
 }
 
+// ---------------------------------------------------------------- inner sketch
+// The TensorSketch of every slab X(:, :, o) over modes 0 and 1 alone: row o
+// of Z holds, at bucket (h_0(i_0) + h_1(i_1)) mod J, the sum of
+// v_0(i_0) v_1(i_1) X(i_0, i_1, o).  Workgroup o reads its slab once, row by
+// row (the lane layout of the fibre kernels: LPF lanes per row of n_0
+// values, the lane's mode-0 table entries in registers, U rows per wave in
+// flight), adds every entry into J FP64 LDS buckets, and writes them as row
+// o of Z.  Y_k for k >= 2 then follows from Z (k_sketch_y_zi) without a
+// pass over X of its own.
+template <typename XT, typename WT, int V, int NJ, int U>
+__global__ __launch_bounds__(256) void k_sketch_zi(const XT* __restrict__ X, const uint32_t* __restrict__ tab0,
+                                                   const uint32_t* __restrict__ tab1, WT* __restrict__ Z, int32_t n0,
+                                                   int32_t n1, uint32_t J, int lpf_log2) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* acc = reinterpret_cast<double*>(smem_raw);
+  uint32_t* t1 = reinterpret_cast<uint32_t*>(acc + J);
+  const int64_t o = blockIdx.x;
+  for (uint32_t q = threadIdx.x; q < J; q += 256) acc[q] = 0.0;
+  for (int q = threadIdx.x; q < n1; q += 256) t1[q] = tab1[q];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lpf = 1 << lpf_log2, g = lane >> lpf_log2, v = lane & (lpf - 1);
+  const int rw = 64 >> lpf_log2;   // rows per wave and load
+  uint32_t k0[NJ][V];
+  bool in0[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int i0 = (v + lpf * j) * V;
+    in0[j] = i0 < n0;   // n_0 is a multiple of V: the whole vector is in range
+#pragma unroll
+    for (int e = 0; e < V; ++e) k0[j][e] = in0[j] ? tab0[i0 + e] : 0u;
+  }
+  __syncthreads();
+  const XT* slab = X + o * (int64_t)n0 * n1;
+  for (int r0 = wave * U * rw; r0 < n1; r0 += 4 * U * rw) {
+    Vec<XT, V> x[U][NJ];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {   // all loads first, then the sums
+      const int r = r0 + u * rw + g;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        if (r < n1 && in0[j]) {
+          x[u][j] = load_vec_plain<XT, V>(slab + (int64_t)r * n0 + (v + lpf * j) * V);
+        } else {
+#pragma unroll
+          for (int e = 0; e < V; ++e) x[u][j].e[e] = XT(0);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + u * rw + g;
+      if (r >= n1) continue;
+      const uint32_t K = t1[r];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        if (!in0[j]) continue;
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const uint32_t b = key_add(k0[j][e], K, J);
+          atomicAdd(&acc[b & TT_KEY_MASK], signed_f64(x[u][j].e[e], b & TT_KEY_SIGN));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  WT* out = Z + o * (int64_t)J;
+  for (uint32_t q = threadIdx.x; q < J; q += 256) out[q] = (WT)acc[q];
+}
+
+// Y_k (k >= 2) from Z.  The outer tuples with i_k = c are o = a + A (c + n_k
+// b): a over modes 2..k-1 (A tuples, keys KA), b over modes k+1..d-1 (B
+// tuples, keys KB).  Workgroup (s, c) adds, for the tuples m = a + A b of
+// slice s of the A B, row o of Z shifted cyclically by the bucket of
+// key_add(KA[a], KB[b]) and with its sign, into J FP64 LDS entries (thread t
+// owns entries t, t + 256, ...: no atomics), and writes them as partial s of
+// column c.  Two rows at a time, four entries per thread per load batch.
+template <typename WT>
+__global__ __launch_bounds__(256) void k_sketch_y_zi(const WT* __restrict__ Z, const uint32_t* __restrict__ KA,
+                                                     const uint32_t* __restrict__ KB, double* __restrict__ part,
+                                                     int64_t A, int32_t nk, int64_t B, uint32_t J, int32_t S) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* acc = reinterpret_cast<double*>(smem_raw);
+  typedef const WT __attribute__((address_space(1)))* gwt;
+  const int s = blockIdx.x, c = blockIdx.y;
+  for (uint32_t q = threadIdx.x; q < J; q += 256) acc[q] = 0.0;   // thread-owned entries
+  const int64_t M = A * B;
+  const int64_t m0 = (int64_t)s * M / S, m1 = (int64_t)(s + 1) * M / S;
+  for (int64_t m = m0; m < m1; m += 2) {
+    const bool two = m + 1 < m1;
+    const int64_t b0 = m / A, a0 = m - b0 * A;
+    const int64_t mm = two ? m + 1 : m;
+    const int64_t b1 = mm / A, a1 = mm - b1 * A;
+    const uint32_t key0 = key_add(KA[a0], KB[b0], J), key1 = key_add(KA[a1], KB[b1], J);
+    const uint32_t h0 = key0 & TT_KEY_MASK, h1 = key1 & TT_KEY_MASK;
+    const uint32_t sg0 = key0 & TT_KEY_SIGN, sg1 = two ? (key1 & TT_KEY_SIGN) : 0u;
+    const gwt row0 = (gwt)(Z + (a0 + A * (c + (int64_t)nk * b0)) * (int64_t)J);
+    const gwt row1 = (gwt)(Z + (a1 + A * (c + (int64_t)nk * b1)) * (int64_t)J);
+    for (uint32_t q0 = threadIdx.x; q0 < J; q0 += 256 * 4) {
+      WT x0[4], x1[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t q = q0 + 256 * u;
+        const bool ok = q < J;
+        const uint32_t s0 = q >= h0 ? q - h0 : q + J - h0;
+        const uint32_t s1 = q >= h1 ? q - h1 : q + J - h1;
+        x0[u] = ok ? row0[s0] : WT(0);
+        x1[u] = ok && two ? row1[s1] : WT(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t q = q0 + 256 * u;
+        if (q < J) acc[q] += signed_f64(x0[u], sg0) + signed_f64(x1[u], sg1);
+      }
+    }
+  }
+  double* out = part + ((int64_t)c * S + s) * (int64_t)J;
+  for (uint32_t q = threadIdx.x; q < J; q += 256) out[q] = acc[q];
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 int ilog2_ceil(int64_t x) {
@@ -937,6 +1056,70 @@ hipError_t run_y1_outer(const tt_plan_s* p, void* Yv) {
   return hipGetLastError();
 }
 
+// The inner-sketch pass: Z from X, one workgroup per outer tuple.
+template <typename XT, typename WT, int V, int NJ>
+hipError_t run_zi_v(const tt_plan_s* p, const XT* X, WT* Z, int lpf_log2) {
+  constexpr int U = NJ >= 4 ? 1 : 4 / NJ;
+  const size_t lds = (size_t)p->J * sizeof(double) + (size_t)p->n[1] * sizeof(uint32_t);
+  auto kern = k_sketch_zi<XT, WT, V, NJ, U>;
+  hipError_t e;
+  if ((e = tt_allow_lds(kern, lds)) != hipSuccess) return e;
+  const uint32_t* tab = p->at<uint32_t>(p->o_tab);
+  hipLaunchKernelGGL(kern, dim3((unsigned)p->O0), dim3(256), lds, p->stream, X, tab + p->tab_off[0],
+                     tab + p->tab_off[1], Z, (int32_t)p->n[0], (int32_t)p->n[1], (uint32_t)p->J, lpf_log2);
+  return hipGetLastError();
+}
+
+template <typename XT, typename WT, int V>
+hipError_t run_zi_shape(const tt_plan_s* p, const XT* X, WT* Z) {
+  int lpf, nj;
+  lane_shape(p->n[0], V, &lpf, &nj);
+  switch (nj) {
+    case 1: return run_zi_v<XT, WT, V, 1>(p, X, Z, lpf);
+    case 2: return run_zi_v<XT, WT, V, 2>(p, X, Z, lpf);
+    case 4: return run_zi_v<XT, WT, V, 4>(p, X, Z, lpf);
+    case 8: return run_zi_v<XT, WT, V, 8>(p, X, Z, lpf);
+    case 16: return run_zi_v<XT, WT, V, 16>(p, X, Z, lpf);
+    default: return hipErrorInvalidValue;   // not reached: the plan takes this path for n_0 <= 1024 only
+  }
+}
+
+template <typename XT, typename WT>
+hipError_t run_zi(const tt_plan_s* p, const void* Xv) {
+  const XT* X = static_cast<const XT*>(Xv);
+  WT* Z = p->at<WT>(p->o_zi);
+  constexpr int VV = 16 / (int)sizeof(XT);
+  const bool vec = (p->n[0] % VV) == 0 && ((uintptr_t)Xv % 16) == 0;
+  return vec ? run_zi_shape<XT, WT, VV>(p, X, Z) : run_zi_shape<XT, WT, 1>(p, X, Z);
+}
+
+// Y_k (k >= 2) from Z: keys of the modes 2..k-1 and k+1..d-1, the partials,
+// their sum.
+template <typename WT>
+hipError_t run_y_inner(const tt_plan_s* p, int k, void* Yv) {
+  int64_t A = 1, B = 1;
+  for (int s = 2; s < k; ++s) A *= p->n[s];
+  for (int s = k + 1; s < p->d; ++s) B *= p->n[s];
+  const int64_t nk = p->n[k];
+  const int S = (int)tt_inner_slices(p, k);
+  if (nk * S * p->J > p->part_entries) return hipErrorInvalidValue;   // sized at plan time
+  uint32_t* KA = p->at<uint32_t>(p->o_KI);
+  uint32_t* KB = p->at<uint32_t>(p->o_KO);
+  double* part = p->at<double>(p->o_part);
+  hipError_t e;
+  // an empty mode range yields the single key 0 (bucket 0, sign +)
+  if ((e = launch_build_keys(p, KA, A, 2, k - 1)) != hipSuccess) return e;
+  if ((e = launch_build_keys(p, KB, B, k + 1, p->d - 1)) != hipSuccess) return e;
+  const size_t lds = (size_t)p->J * sizeof(double);
+  if ((e = tt_allow_lds(k_sketch_y_zi<WT>, lds)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sketch_y_zi<WT>, dim3((unsigned)S, (unsigned)nk), dim3(256), lds, p->stream,
+                     p->at<WT>(p->o_zi), KA, KB, part, A, (int32_t)nk, B, (uint32_t)p->J, (int32_t)S);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_slots<WT>, dim3(nblk(p->J * nk, 256)), dim3(256), 0, p->stream, part,
+                     static_cast<WT*>(Yv), p->J, nk, S);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 // Workgroups of the k >= 1 sketch: the occupancy-limited resident count,
@@ -1009,4 +1192,44 @@ hipError_t launch_sketch_mode0_outer(const tt_plan_s* p, const void* X, void* Y0
 hipError_t launch_sketch_y1_outer(const tt_plan_s* p, void* Y1) {
   if (!tt_sketch_fused01(p)) return hipErrorInvalidValue;
   return p->wdt == TT_F64 ? run_y1_outer<double>(p, Y1) : run_y1_outer<float>(p, Y1);
+}
+
+// Workgroups per column of the Y_k-from-Z kernel (k >= 2): about 1024 in all,
+// each summing at least 2 rows of Z.
+int64_t tt_inner_slices(const tt_plan_s* p, int k) {
+  const int64_t M = p->O0 / p->n[k];
+  int64_t S = (1024 + p->n[k] - 1) / p->n[k];
+  const int64_t cap = M / 2 > 1 ? M / 2 : 1;
+  if (S > cap) S = cap;
+  return S < 1 ? 1 : S;
+}
+
+// Y_k for k >= 2 come from the inner sketch Z: the plan holds the J_cap x
+// O_0 buffer for it.
+bool tt_sketch_inner(const tt_plan_s* p) { return p->o_zi != 0; }
+
+// One pass over X writes Z (the TensorSketch of every slab over modes 0 and
+// 1), then Y_k for every k >= 2 is formed from Z into its slot of Yall.
+hipError_t launch_sketch_inner(const tt_plan_s* p, const void* X, void* Yall) {
+  if (!tt_sketch_inner(p)) return hipErrorInvalidValue;
+  hipError_t e;
+  {
+    TTProfScope ps(p, TT_PROF_SKETCHK);
+    if (p->wdt == TT_F64) {
+      e = p->xdt == TT_F64 ? run_zi<double, double>(p, X)
+          : p->xdt == TT_F32 ? run_zi<float, double>(p, X) : run_zi<uint16_t, double>(p, X);
+    } else {
+      e = p->xdt == TT_F64 ? run_zi<double, float>(p, X)
+          : p->xdt == TT_F32 ? run_zi<float, float>(p, X) : run_zi<uint16_t, float>(p, X);
+    }
+    if (e != hipSuccess) return e;
+  }
+  TTProfScope ps(p, TT_PROF_SKETCH_AUX);
+  char* Yb = static_cast<char*>(Yall);
+  for (int k = 2; k < p->d; ++k) {
+    void* Yk = Yb + p->wsize() * p->J * p->tab_off[k];
+    e = p->wdt == TT_F64 ? run_y_inner<double>(p, k, Yk) : run_y_inner<float>(p, k, Yk);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }

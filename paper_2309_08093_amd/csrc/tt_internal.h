@@ -56,7 +56,8 @@ struct tt_plan_s {
 
   size_t o_tab, o_KI, o_KO, o_cnt, o_hist, o_sortO, o_part, o_chat, o_pre, o_suf, o_SH, o_Y,
       o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_pol, o_gsum, o_resU, o_resH,
-      o_tw, o_zo;                  // o_zo: outer sketch of the fused k = 0 pass (0: not fused)
+      o_tw, o_zo,                  // o_zo: outer sketch of the fused k = 0 pass (0: not fused)
+      o_zi;                        // o_zi: inner sketch Z of the k >= 2 pass (0: not used)
   // exact update (TT_FLAG_EXACT; 0 otherwise): two left-interface buffers of
   // ex_phi work-type values, two right-chain buffers of ex_chain, ex_part FP64
   // slice partials, the two Gram factors (2 x 256 doubles)
@@ -165,6 +166,11 @@ hipError_t launch_exact_rhs_out(const tt_plan_s* p, int k, const void* Bc, void*
 hipError_t launch_sketch_mode0_outer(const tt_plan_s* p, const void* X, void* Y0);
 hipError_t launch_sketch_y1_outer(const tt_plan_s* p, void* Y1);
 bool tt_sketch_fused01(const tt_plan_s* p);
+// Y_k for all k >= 2 from one pass over X through the inner sketch Z (o_zi),
+// into their slots of the all-mode buffer Yall
+hipError_t launch_sketch_inner(const tt_plan_s* p, const void* X, void* Yall);
+bool tt_sketch_inner(const tt_plan_s* p);
+int64_t tt_inner_slices(const tt_plan_s* p, int k);   // workgroups per column of the Y_k-from-Z stage
 int64_t tt_outer_slices(const tt_plan_s* p);   // workgroups per column of the Y_1 stage
 hipError_t launch_core_fft(const tt_plan_s* p, const CoreDesc& cd, int core_lo, int core_hi, int skip);
 hipError_t launch_interface_from_chat(const tt_plan_s* p, const CoreDesc& cd, int k, void* SH);

@@ -78,7 +78,8 @@ def test_valid_plan_reports_workspace(abi):
     (dict(n=[4, 4, 4], r=[1, 2, 2, 1], lam=-1.0), "TT_ERR_ARG"),
     (dict(n=[4, 4, 4], r=[1, 2, 2, 1], lam=float("nan")), "TT_ERR_ARG"),
     (dict(n=[4, 4, 4], r=[1, 2, 2, 1], gram=1, w=0), "TT_ERR_ARG"),              # BF16 Gram needs F32 work
-    (dict(n=[4, 4, 4], r=[1, 2, 2, 1], flags=16), "TT_ERR_ARG"),                 # unknown flag bit
+    (dict(n=[4, 4, 4], r=[1, 2, 2, 1], flags=64), "TT_ERR_ARG"),                 # unknown flag bit
+    (dict(n=[4, 4, 4], r=[1, 2, 2, 1], flags=48), "TT_ERR_ARG"),                 # INNER with NO_INNER
     (dict(n=[4, 4, 4], r=[1, 2, 2, 1], flags=6), "TT_ERR_ARG"),                  # FUSE with NO_FUSE
     (dict(n=[5000, 4], r=[1, 4, 1]), "TT_ERR_SHAPE"),                            # n_0 > TT_MAX_N0
 ])
@@ -86,6 +87,20 @@ def test_invalid_descriptors(abi, kw, code):
     st, h, ws = _plan(abi, **kw)
     assert st == getattr(abi, code), (st, abi.load().tt_last_error())
     assert abi.load().tt_last_error() != b""
+
+
+def test_sketch_sources_of_the_200x4_plan(abi):
+    # the headline plan: Y_1 from the outer sketch of the k = 0 pass, Y_3 from
+    # the inner sketch of the k = 2 pass (two passes over X per sweep); host
+    # query, no workspace needed
+    lib = abi.load()
+    for flags, want in ((0, [0, 0, 2, 2]), (32, [0, 0, 2, 3]), (4 | 32, [0, 1, 2, 3]), (4 | 16, [0, 1, 2, 2])):
+        st, h, ws = _plan(abi, [200, 200, 200, 200], [1, 10, 10, 10, 1], J=4000, flags=flags)
+        assert st == abi.TT_OK
+        src = (ctypes.c_int32 * 4)()
+        assert lib.tt_plan_sketch_sources(h, src) == abi.TT_OK
+        assert list(src) == want, (flags, list(src))
+        assert lib.tt_plan_destroy(h) == abi.TT_OK
 
 
 def test_null_arguments(abi):

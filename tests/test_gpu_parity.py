@@ -241,6 +241,70 @@ def test_sketch_straddling_lines(tts, n, J, xd, shift):
                 assert rel(Y, Yo) < tol and colmax(Y, Yo) < tol, (k, rel(Y, Yo), colmax(Y, Yo))
 
 
+# every Y_k, k >= 2, from the inner sketch (one pass over X writes the sketch
+# of every slab over modes 0 and 1): 4-value, 2-value (FP64), 8-value (BF16)
+# and single-value loads; 1, 2, 4 and 16 vectors per lane; short rows several
+# to a wave; d = 5; a mode of size 1; J = 1; X shifted off its alignment
+INNER_CASES = [
+    ([20, 30, 40, 10], 60, "f32", "f32", None, 0),
+    ([20, 30, 40, 10], 60, "f32", "f32", True, 4),
+    ([37, 12, 11, 13], 40, "f32", "f32", None, 0),
+    ([300, 12, 10, 7], 30, "f32", "f32", False, 0),
+    ([64, 8, 8, 8, 8], 300, "bf16", "f32", None, 0),
+    ([40, 6, 8, 5], 12, "f64", "f64", None, 0),
+    ([40, 6, 8, 5], 12, "f64", "f64", None, 1),
+    ([1000, 3, 4, 5], 16, "f32", "f32", None, 0),
+    ([1000, 3, 4, 5], 16, "bf16", "f32", None, 0),
+    ([999, 2, 3, 4], 16, "f32", "f32", None, 0),
+    ([12, 9, 7, 1], 1, "f32", "f32", None, 0),
+    ([8, 7, 1, 5, 3], 4, "f64", "f64", True, 0),
+]
+
+
+@pytest.mark.parametrize("n,J,xd,wd,fuse,shift", INNER_CASES)
+def test_sketch_all_inner(tts, n, J, xd, wd, fuse, shift):
+    say("sketch all inner", n, J, xd, wd, fuse, shift)
+    N = int(np.prod(n))
+    plan = tts.Plan(n, [1] * (len(n) + 1), J, 1e-3, seed=5, x_dtype=xd, work_dtype=wd, fuse=fuse, inner=True)
+    assert plan.sketch_sources()[2:] == [2] * (len(n) - 2)
+    hs, vs = host_tables(plan)
+
+    def shifted(Xh):
+        xt = to_dev_x(Xh, xd)
+        buf = torch.empty(N + shift, dtype=xt.dtype, device=DEV)
+        buf[shift:] = xt
+        return buf[shift:]
+
+    # integer-valued: bit-exact
+    Xi = synth.rng(6).integers(-4, 5, size=N).astype(np.float64)
+    Ys = plan.sketch_tensor_all(shifted(Xi))
+    for k in range(len(n)):
+        Y = Ys[k].cpu().numpy().astype(np.float64).reshape(J, n[k], order="F")
+        Yo = sketch.data_sketch(Xi, n, k, hs, vs, J)
+        assert np.array_equal(Y, Yo), (k, np.abs(Y - Yo).max())
+    # Gaussian: 1e-5 (FP32 work) or 1e-12 (FP64 work), norm-wise and element-wise
+    Xh = synth.rng(7).standard_normal(N)
+    Xo = synth.upcast_host(synth.to_dtype_host(Xh, xd))
+    Ys = plan.sketch_tensor_all(shifted(Xh))
+    tol = 1e-12 if wd == "f64" else 1e-5
+    for k in range(len(n)):
+        Y = Ys[k].cpu().numpy().astype(np.float64).reshape(J, n[k], order="F")
+        Yo = sketch.data_sketch(Xo, n, k, hs, vs, J)
+        assert rel(Y, Yo) < tol and colmax(Y, Yo) < tol, (k, rel(Y, Yo), colmax(Y, Yo))
+
+
+def test_sketch_inner_rule(tts):
+    say("sketch inner rule")
+    # |Z| = J n_2 n_3 = 2e5 values against N = 4e6: one pass serves Y_2 and Y_3
+    assert tts.Plan([100, 100, 20, 20], [1, 1, 1, 1, 1], 500, 1e-3).sketch_sources()[2:] == [2, 2]
+    assert tts.Plan([100, 100, 20, 20], [1, 1, 1, 1, 1], 500, 1e-3, inner=False).sketch_sources()[2:] == [2, 3]
+    # |Z| as large as X: each mode keeps its own pass
+    assert tts.Plan([16, 16, 16, 16], [1, 1, 1, 1, 1], 256, 1e-3).sketch_sources() == [0, 1, 2, 3]
+    # d = 3 has no mode beyond 2; n_0 > 1024 is not taken
+    assert tts.Plan([30, 40, 50], [1, 3, 3, 1], 64, 1e-3, inner=True).sketch_sources() == [0, 1, 2]
+    assert tts.Plan([1030, 3, 2, 2], [1] * 5, 8, 1e-3, inner=True, fuse=False).sketch_sources() == [0, 1, 2, 3]
+
+
 def test_sketch_fusion_rule(tts):
     say("sketch fusion rule")
     # O_0 = n_2 ... n_{d-1} = 3600 outer tuples >= 4 J: fused by default
@@ -431,10 +495,12 @@ def test_residual_nonfinite_reported(tts, bad):
 
 
 # ------------------------------------------------------------------ full sweeps
-def _run_sweeps(tts, n, R, J, lam, seed, sweeps, xd, wd, noise, init_seed=2, gram="work", fuse=None, serial=False):
+def _run_sweeps(tts, n, R, J, lam, seed, sweeps, xd, wd, noise, init_seed=2, gram="work", fuse=None, serial=False,
+                inner=None):
     Xh, _ = synth.tt_tensor_host(n, R, noise, 1)
     init = synth.random_cores(n, R, init_seed)
-    plan = tts.Plan(n, R, J, lam, seed=seed, x_dtype=xd, work_dtype=wd, gram=gram, fuse=fuse, serial=serial)
+    plan = tts.Plan(n, R, J, lam, seed=seed, x_dtype=xd, work_dtype=wd, gram=gram, fuse=fuse, serial=serial,
+                    inner=inner)
     X = to_dev_x(Xh, xd)
     Xo = synth.upcast_host(synth.to_dtype_host(Xh, xd))
     dc = [tts.core_to_device(c) for c in init]
@@ -598,6 +664,27 @@ def test_video_shaped_steps(tts):
     want = solve.prox_update(SHh, Yh, cores[k], lam)
     print("video prox rel %.3e colmax %.3e" % (rel(out, want), colmax(solve.core_unfold2(out), solve.core_unfold2(want))))
     assert rel(out, want) < 1e-5
+
+
+@pytest.mark.parametrize("serial", [False, True])
+def test_sweeps_inner_sketch(tts, serial):
+    # sweeps whose Y_k, k >= 2, come from the inner sketch (with and without
+    # the outer sketch for Y_1), in both schedules, against the oracle's passes
+    say("sweeps inner serial=%s" % serial)
+    plan, dc, ref, res, res_o, Xo = _run_sweeps(tts, [16] * 4, [1, 3, 3, 3, 1], 256, 1e-3, 17, 4, "f64", "f64", 1e-3,
+                                                fuse=True, serial=serial, inner=True)
+    assert plan.sketch_sources() == [0, 0, 2, 2]
+    assert max(abs(a - b) for a, b in zip(res, res_o)) < 1e-10
+    got = [tts.core_to_host(c, r.shape) for c, r in zip(dc, ref)]
+    assert rel(als.tt_full(got), als.tt_full(ref)) < 1e-9
+    plan, dc, ref, res, res_o, Xo = _run_sweeps(tts, [30, 20, 25, 10], [1, 4, 5, 3, 1], 500, 1e-3, 5, 3, "f32", "f32",
+                                                1e-2, fuse=False, serial=serial, inner=True)
+    assert plan.sketch_sources() == [0, 1, 2, 2]
+    assert max(abs(a - b) for a, b in zip(res, res_o)) < 1e-4
+    plan, dc, ref, res, res_o, Xo = _run_sweeps(tts, [12, 10, 8, 9, 7], [1, 3, 4, 4, 3, 1], 300, 1e-3, 8, 3, "f32",
+                                                "f32", 1e-2, serial=serial, inner=True)
+    assert plan.sketch_sources()[2:] == [2, 2, 2]
+    assert max(abs(a - b) for a, b in zip(res, res_o)) < 1e-4
 
 
 @pytest.mark.parametrize("serial", [False, True])
