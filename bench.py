@@ -777,8 +777,12 @@ def main():
                 "kernel": kernel, "avg_launch_ms": round(ms / cnt, 4), "launches": cnt,
                 "bytes_per_launch": nbytes}
 
-    kern_k = sorted(set(plan.sketch_kernel(k) for k in range(1, d) if src[k] == k))
-    rfk = roof("sketch_k", "+".join(kern_k), N * xbytes, ["+".join(kern_k)])
+    # the inner-sketch pass of mode 2 (k_sketch_zi: X read, the J x n_2...n_{d-1}
+    # sketch of every slab over modes 0 and 1 written) when Y_3.. come from it
+    inner = d >= 4 and all(src[k] == 2 for k in range(3, d))
+    inner_bytes = J * (N // (n[0] * n[1])) * wbytes if inner else 0
+    kern_k = ["k_sketch_zi"] if inner else sorted(set(plan.sketch_kernel(k) for k in range(1, d) if src[k] == k))
+    rfk = roof("sketch_k", "+".join(kern_k), N * xbytes + inner_bytes, ["+".join(kern_k)])
     # the fused k = 0 pass: k_sketch_zo (X read, outer sketch written) and
     # k_sketch_y0_zo (Y_0 from the outer sketch, read once)
     k0_kernels = ["k_sketch_zo", "k_sketch_y0_zo"] if fused else [plan.sketch_kernel(0)]
@@ -816,10 +820,10 @@ def main():
                    "sketch_sources": src,
                    "schedule": "serial" if args.serial else "data sketches overlapped on a second stream",
                    "reserved_cus": None if args.serial else args.reserve_cus},
-        "hbm_gbps_sweep": (sum(1 for k in range(d) if src[k] == k) * N * xbytes + 3 * outer_bytes)
-                          / (ms_per_step * 1e-3) / 1e9,
-        "hbm_gbps_sweep_note": "passes over X plus the outer sketch written once and read twice (Y_0, Y_1), "
-                               "per sweep time",
+        "hbm_gbps_sweep": (sum(1 for k in range(d) if src[k] == k) * N * xbytes + 3 * outer_bytes
+                           + (d - 1) * inner_bytes) / (ms_per_step * 1e-3) / 1e9,
+        "hbm_gbps_sweep_note": "passes over X plus the outer sketch written once and read twice (Y_0, Y_1) and the "
+                               "inner sketch written once and read d - 2 times (Y_2 .. Y_{d-1}), per sweep time",
         "wall_s_timed": wall,
         "roofline": rf,
         "roofline_other_sketch": rf_other,
@@ -889,6 +893,12 @@ def main():
             "k0_pass": {"kernel": "+".join(k0_kernels), "bytes": k0_bytes,
                         "GB/s": round(k0_bytes / (k0ms * 1e-3) / 1e9, 1),
                         "frac": round(k0_bytes / (k0ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}}
+        if inner:
+            kms = pr["sketch_k"][0] / 5
+            kb = N * xbytes + inner_bytes
+            out["sketch_all_isolated"]["inner_pass"] = {
+                "kernel": "k_sketch_zi", "bytes": kb, "GB/s": round(kb / (kms * 1e-3) / 1e9, 1),
+                "frac": round(kb / (kms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
 
     if not args.no_time_to_target:
         print("[bench] time to relative residual 1e-2", file=sys.stderr, flush=True)

@@ -112,7 +112,10 @@ typedef struct {
  * N sizeof(X) + (d - 1) |Z| sizeof(work) <= 0.75 (d - 2) N sizeof(X).
  * TT_FLAG_INNER asks for it whenever d >= 4 and n_0 <= 1024,
  * TT_FLAG_NO_INNER never (not both).  Independent of TT_FLAG_FUSE;
- * tt_sketch_tensor(k) is not affected. */
+ * tt_sketch_tensor(k) is not affected.  With both intermediates, FP32 work,
+ * FP32 or BF16 X, n_0 a multiple of 16 bytes' worth of X values and slabs
+ * of at most 40960 values, the k = 0 pass writes Z as well (one pass over X
+ * per sweep) whenever X is 16-byte aligned. */
 #define TT_FLAG_INNER 16u
 #define TT_FLAG_NO_INNER 32u
 
@@ -196,7 +199,9 @@ tt_status tt_sketch_sparse_all(tt_plan plan, int64_t nnz, const int32_t* coords,
  * device work): src[k] = k when Y_k takes its own pass over X, src[k] = j != k
  * when it is derived from an intermediate written by the pass of mode j
  * (src[1] = 0 with the outer sketch of TT_FLAG_FUSE, src[k] = 2 for k > 2
- * with the inner sketch of TT_FLAG_INNER).  src: host array of d entries. */
+ * with the inner sketch of TT_FLAG_INNER, src[k] = 0 for every k >= 1 when
+ * the k = 0 pass writes both; a 16-byte aligned X is assumed for the last).
+ * src: host array of d entries. */
 tt_status tt_plan_sketch_sources(tt_plan plan, int32_t* src);
 
 /* Interface sketch SH_k = S_{-k} (G_{>k}^T (x) G_{<k}) (Theorem 1 and 2,

@@ -614,6 +614,8 @@ tt_status tt_plan_sketch_sources(tt_plan p, int32_t* src) {
   if (tt_sketch_fused01(p)) src[1] = 0;
   if (tt_sketch_inner(p))
     for (int k = 3; k < p->d; ++k) src[k] = 2;
+  if (tt_sketch_joint(p))
+    for (int k = 2; k < p->d; ++k) src[k] = 0;
   return TT_OK;
 }
 

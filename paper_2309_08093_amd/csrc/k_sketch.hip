@@ -42,6 +42,8 @@
 //    row (i_1, c) value i_0 with the sign of i_0 to bucket (c + h_0(i_0)) mod
 //    J.  This replaces the k = 1 pass over X by a write and two reads of
 //    J n_0 n_1 values, which pays when J n_0 n_1 is small against N.
+#include <type_traits>
+
 #include "tt_internal.h"
 
 // threads per workgroup of the k >= 1 sketch kernels
@@ -812,6 +814,116 @@ __global__ __launch_bounds__(256) void k_sketch_y_zi(const WT* __restrict__ Z, c
   for (uint32_t q = threadIdx.x; q < J; q += 256) out[q] = acc[q];
 }
 
+// ---------------------------------------------------------------- outer and inner sketch in one pass
+// For FP32 work: workgroup c (1024 threads) reads the whole slabs of the
+// outer tuples of key c (the bucket list of the k = 0 sketch), once each,
+// and forms from them both
+//  * row c of the outer sketch: the slabs summed with their signs, thread t
+//    keeping slab positions V (t + 1024 j) + e (j < NV) in FP32 registers;
+//  * row o of the inner sketch Z for every slab o of the list: each entry
+//    added, with sign v_0(i_0) v_1(i_1), to bucket (h_0(i_0) + h_1(i_1))
+//    mod J of a J-entry FP64 LDS array.  A vector's V values share i_1
+//    (n_0 is a multiple of V), found as the high word of position times
+//    mdiv = ceil(2^32 / n_0) (exact for positions below 2^17); the table
+//    entries are read from LDS.
+// A slab is read in four chunks of ceil(NV / 4) vectors per thread; the next
+// chunk (of this slab or the next) is loaded before the current one is
+// added.  Two LDS arrays alternate between slabs: after the barrier that
+// closes slab o, each thread writes its entries of o's array as row o of Z
+// and clears them while the next slab goes to the other array, so one
+// barrier per slab suffices.
+template <typename XT, int V, int NV>
+__global__ __launch_bounds__(1024) void k_sketch_zoi(const XT* __restrict__ X, const uint32_t* __restrict__ off,
+                                                    const uint32_t* __restrict__ sorted,
+                                                    const uint32_t* __restrict__ tab0, const uint32_t* __restrict__ tab1,
+                                                    float* __restrict__ zo, float* __restrict__ Z, int32_t n0,
+                                                    int32_t n1, uint32_t J, uint32_t mdiv) {
+  constexpr int CH = (NV + 3) / 4;   // vectors per thread and chunk
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* acc = reinterpret_cast<double*>(smem_raw);                  // 2 J entries
+  uint32_t* t0 = reinterpret_cast<uint32_t*>(acc + 2 * (size_t)J);    // n_0 entries
+  uint32_t* t1 = t0 + n0;                                              // n_1 entries
+  const int t = threadIdx.x;
+  const uint32_t c = blockIdx.x;
+  const int S = n0 * n1;
+  for (uint32_t q = t; q < 2 * J; q += 1024) acc[q] = 0.0;
+  for (int q = t; q < n0; q += 1024) t0[q] = tab0[q];
+  for (int q = t; q < n1; q += 1024) t1[q] = tab1[q];
+  float za[NV][V];
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+#pragma unroll
+    for (int e = 0; e < V; ++e) za[j][e] = 0.0f;
+  const uint32_t beg = off[c], end = off[c + 1];
+  __syncthreads();
+  Vec<XT, V> xc[CH], xn[CH];
+  auto load_chunk = [&](Vec<XT, V>* x, const XT* slab, int ch) {
+#pragma unroll
+    for (int h = 0; h < CH; ++h) {
+      const int pos = V * (t + 1024 * (ch * CH + h));
+      if (ch * CH + h < NV && pos < S) {
+        x[h] = load_vec_plain<XT, V>(slab + pos);
+      } else {
+#pragma unroll
+        for (int e = 0; e < V; ++e) x[h].e[e] = XT(0);
+      }
+    }
+  };
+  auto add_chunk = [&](const Vec<XT, V>* x, int ch, double* A, uint32_t so) {
+#pragma unroll
+    for (int h = 0; h < CH; ++h) {
+      const int j = ch * CH + h;
+      if (j >= NV) continue;
+      const uint32_t pos = V * (t + 1024 * j);
+      if (pos >= (uint32_t)S) continue;
+      const uint32_t i1 = __umulhi(pos, mdiv), i0 = pos - i1 * (uint32_t)n0;
+      const uint32_t K = t1[i1];
+#pragma unroll
+      for (int e = 0; e < V; ++e) {
+        za[j][e] += __uint_as_float(__float_as_uint(to_work<float>(x[h].e[e])) ^ so);
+        const uint32_t b = key_add(t0[i0 + e], K, J);
+        atomicAdd(&A[b & TT_KEY_MASK], signed_f64(x[h].e[e], b & TT_KEY_SIGN));
+      }
+    }
+  };
+  int buf = 0;
+  if (beg < end) load_chunk(xc, X + (int64_t)(sorted[beg] & TT_KEY_MASK) * S, 0);
+  for (uint32_t it = beg; it < end; ++it) {
+    const uint32_t item = sorted[it];
+    const int64_t o = item & TT_KEY_MASK;
+    const uint32_t so = item & TT_KEY_SIGN;
+    const XT* slab = X + o * S;
+    const XT* next = it + 1 < end ? X + (int64_t)(sorted[it + 1] & TT_KEY_MASK) * S : nullptr;
+    double* A = acc + (size_t)buf * J;
+    // chunks 0..3 alternate between the two buffers; chunk 0 of the next
+    // slab lands in xc again
+    load_chunk(xn, slab, 1);
+    add_chunk(xc, 0, A, so);
+    load_chunk(xc, slab, 2);
+    add_chunk(xn, 1, A, so);
+    load_chunk(xn, slab, 3);
+    add_chunk(xc, 2, A, so);
+    if (next) load_chunk(xc, next, 0);
+    add_chunk(xn, 3, A, so);
+    __syncthreads();
+    float* zr = Z + o * (int64_t)J;
+    for (uint32_t q = t; q < J; q += 1024) {
+      zr[q] = (float)A[q];
+      A[q] = 0.0;
+    }
+    buf ^= 1;
+  }
+  float* out = zo + (int64_t)c * S;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const int pos = V * (t + 1024 * j);
+    if (pos < S) {
+#pragma unroll
+      for (int e = 0; e < V; ++e) out[pos + e] = za[j][e];
+    }
+  }
+}
+
 inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 int ilog2_ceil(int64_t x) {
@@ -931,6 +1043,9 @@ hipError_t run_mode0(const tt_plan_s* p, const XT* X, WT* Y, int lpf_log2, int64
   return hipSuccess;
 }
 
+template <typename WT>
+hipError_t launch_y0_zo(const tt_plan_s* p, const WT* zo, WT* Y);
+
 // The fused k = 0 pass: the outer sketch from the slabs (V-value loads when
 // n_0 n_1 and the address of X allow), then Y_0 from it.
 template <typename XT, typename WT, int V>
@@ -944,6 +1059,13 @@ hipError_t run_zo_v(const tt_plan_s* p, const XT* X, WT* Y, WT* zo) {
                      X, off, sorted, zo, S);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  return launch_y0_zo<WT>(p, zo, Y);
+}
+
+// Y_0 from the outer sketch (k_sketch_y0_zo), one workgroup per bucket.
+template <typename WT>
+hipError_t launch_y0_zo(const tt_plan_s* p, const WT* zo, WT* Y) {
+  const int64_t n0 = p->n[0], n1 = p->n[1];
   const uint32_t* tab1 = p->at<uint32_t>(p->o_tab) + p->tab_off[1];
   const dim3 g((unsigned)p->J);
   const int32_t a0 = (int32_t)n0, a1 = (int32_t)n1;
@@ -957,6 +1079,33 @@ hipError_t run_zo_v(const tt_plan_s* p, const XT* X, WT* Y, WT* zo) {
   return hipGetLastError();
 }
 
+// The one pass for the outer and the inner sketch (FP32 work), then Y_0.
+template <typename XT, int NV>
+hipError_t run_zoi_v(const tt_plan_s* p, const XT* X, float* Y, float* zo) {
+  constexpr int V = 16 / (int)sizeof(XT);
+  const size_t lds = 2 * (size_t)p->J * sizeof(double) + (size_t)(p->n[0] + p->n[1]) * sizeof(uint32_t);
+  auto kern = k_sketch_zoi<XT, V, NV>;
+  hipError_t e;
+  if ((e = tt_allow_lds(kern, lds)) != hipSuccess) return e;
+  const uint32_t* tab = p->at<uint32_t>(p->o_tab);
+  hipLaunchKernelGGL(kern, dim3((unsigned)p->J), dim3(1024), lds, p->stream, X, p->at<uint32_t>(p->o_cnt),
+                     p->at<uint32_t>(p->o_sortO), tab + p->tab_off[0], tab + p->tab_off[1], zo, p->at<float>(p->o_zi),
+                     (int32_t)p->n[0], (int32_t)p->n[1], (uint32_t)p->J,
+                     (uint32_t)((((uint64_t)1 << 32) + (uint64_t)p->n[0] - 1) / (uint64_t)p->n[0]));
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return launch_y0_zo<float>(p, zo, Y);
+}
+
+template <typename XT>
+hipError_t run_zoi(const tt_plan_s* p, const XT* X, float* Y, float* zo) {
+  switch (tt_joint_vectors(p)) {
+    case 4: return run_zoi_v<XT, 4>(p, X, Y, zo);
+    case 8: return run_zoi_v<XT, 8>(p, X, Y, zo);
+    case 10: return run_zoi_v<XT, 10>(p, X, Y, zo);
+    default: return hipErrorInvalidValue;   // not reached: the plan takes the path for at most 10
+  }
+}
+
 template <typename XT, typename WT>
 hipError_t run_zo(const tt_plan_s* p, const XT* X, WT* Y, WT* zo) {
   hipError_t e;
@@ -965,6 +1114,9 @@ hipError_t run_zo(const tt_plan_s* p, const XT* X, WT* Y, WT* zo) {
     if (!p->lists_ready && (e = launch_outer_sort(p)) != hipSuccess) return e;
   }
   TTProfScope ps(p, TT_PROF_SKETCH0);
+  if constexpr (std::is_same<WT, float>::value && !std::is_same<XT, double>::value) {
+    if (tt_sketch_joint_ok(p, X)) return run_zoi<XT>(p, X, Y, zo);
+  }
   constexpr int VV = 16 / (int)sizeof(XT);
   const bool vec = (p->n[0] * p->n[1]) % VV == 0 && ((uintptr_t)X % 16) == 0;
   return vec ? run_zo_v<XT, WT, VV>(p, X, Y, zo) : run_zo_v<XT, WT, 1>(p, X, Y, zo);
@@ -1213,7 +1365,7 @@ bool tt_sketch_inner(const tt_plan_s* p) { return p->o_zi != 0; }
 hipError_t launch_sketch_inner(const tt_plan_s* p, const void* X, void* Yall) {
   if (!tt_sketch_inner(p)) return hipErrorInvalidValue;
   hipError_t e;
-  {
+  if (!tt_sketch_joint_ok(p, X)) {   // else Z was written by the k = 0 pass
     TTProfScope ps(p, TT_PROF_SKETCHK);
     if (p->wdt == TT_F64) {
       e = p->xdt == TT_F64 ? run_zi<double, double>(p, X)
@@ -1232,4 +1384,27 @@ hipError_t launch_sketch_inner(const tt_plan_s* p, const void* X, void* Yall) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// The k = 0 pass also writes the inner sketch (k_sketch_zoi): FP32 work, FP32
+// or BF16 X, both sketches in the plan, rows of whole V-value vectors, at
+// most 40 values of a slab per thread (4, 8 or 10 vectors of FP32, 4 of
+// BF16: the outer-sketch sums stay in registers), tables and both bucket
+// arrays within 160 KB of LDS.
+int tt_joint_vectors(const tt_plan_s* p) {
+  if (!(tt_sketch_fused01(p) && tt_sketch_inner(p)) || p->wdt != TT_F32 || p->xdt == TT_F64) return 0;
+  const int64_t V = 16 / (int64_t)p->xsize(), S = p->n[0] * p->n[1];
+  if (p->n[0] % V != 0 || p->n[0] > 4096) return 0;
+  if (16 * p->J_cap + 4 * (p->n[0] + p->n[1]) > 160 * 1024) return 0;
+  const int64_t nv = (S / V + 1023) / 1024;
+  if (nv * V > 40) return 0;
+  return (int)(nv <= 4 ? 4 : nv <= 8 ? 8 : 10);
+}
+
+bool tt_sketch_joint(const tt_plan_s* p) { return tt_joint_vectors(p) > 0; }
+
+// The joint pass runs when the plan takes it and X is 16-byte aligned (the
+// slabs are then read in whole vectors); otherwise the two passes run.
+bool tt_sketch_joint_ok(const tt_plan_s* p, const void* X) {
+  return tt_sketch_joint(p) && ((uintptr_t)X % 16) == 0;
 }

@@ -171,6 +171,12 @@ bool tt_sketch_fused01(const tt_plan_s* p);
 hipError_t launch_sketch_inner(const tt_plan_s* p, const void* X, void* Yall);
 bool tt_sketch_inner(const tt_plan_s* p);
 int64_t tt_inner_slices(const tt_plan_s* p, int k);   // workgroups per column of the Y_k-from-Z stage
+// the k = 0 pass writes the inner sketch too (FP32 work): vectors per thread
+// of its kernel (0: not taken), whether the plan takes it, and whether it runs
+// for this X (16-byte aligned)
+int tt_joint_vectors(const tt_plan_s* p);
+bool tt_sketch_joint(const tt_plan_s* p);
+bool tt_sketch_joint_ok(const tt_plan_s* p, const void* X);
 int64_t tt_outer_slices(const tt_plan_s* p);   // workgroups per column of the Y_1 stage
 hipError_t launch_core_fft(const tt_plan_s* p, const CoreDesc& cd, int core_lo, int core_hi, int skip);
 hipError_t launch_interface_from_chat(const tt_plan_s* p, const CoreDesc& cd, int k, void* SH);

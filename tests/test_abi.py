@@ -90,12 +90,14 @@ def test_invalid_descriptors(abi, kw, code):
 
 
 def test_sketch_sources_of_the_200x4_plan(abi):
-    # the headline plan: Y_1 from the outer sketch of the k = 0 pass, Y_3 from
-    # the inner sketch of the k = 2 pass (two passes over X per sweep); host
-    # query, no workspace needed
+    # the headline plan: Y_1 from the outer sketch, Y_2 and Y_3 from the inner
+    # sketch, both written by the k = 0 pass (one pass over X per sweep);
+    # without one of them, more passes; host query, no workspace needed
     lib = abi.load()
-    for flags, want in ((0, [0, 0, 2, 2]), (32, [0, 0, 2, 3]), (4 | 32, [0, 1, 2, 3]), (4 | 16, [0, 1, 2, 2])):
-        st, h, ws = _plan(abi, [200, 200, 200, 200], [1, 10, 10, 10, 1], J=4000, flags=flags)
+    for flags, w, want in ((0, None, [0, 0, 0, 0]), (16, None, [0, 0, 0, 0]), (32, None, [0, 0, 2, 3]),
+                           (4 | 32, None, [0, 1, 2, 3]), (4 | 16, None, [0, 1, 2, 2]),
+                           (0, abi.TT_F64, [0, 0, 2, 3]), (16, abi.TT_F64, [0, 0, 2, 2])):
+        st, h, ws = _plan(abi, [200, 200, 200, 200], [1, 10, 10, 10, 1], J=4000, flags=flags, w=w)
         assert st == abi.TT_OK
         src = (ctypes.c_int32 * 4)()
         assert lib.tt_plan_sketch_sources(h, src) == abi.TT_OK

@@ -181,11 +181,12 @@ FUSED_CASES = [
 ]
 
 
+@pytest.mark.parametrize("inner", [None, False])
 @pytest.mark.parametrize("n,J,xd,wd", FUSED_CASES)
-def test_sketch_all_fused(tts, n, J, xd, wd):
-    say("sketch all fused", n, J, xd, wd)
+def test_sketch_all_fused(tts, n, J, xd, wd, inner):
+    say("sketch all fused", n, J, xd, wd, inner)
     N = int(np.prod(n))
-    plan = tts.Plan(n, [1] * (len(n) + 1), J, 1e-3, seed=5, x_dtype=xd, work_dtype=wd, fuse=True)
+    plan = tts.Plan(n, [1] * (len(n) + 1), J, 1e-3, seed=5, x_dtype=xd, work_dtype=wd, fuse=True, inner=inner)
     assert plan.sketch_sources()[:2] == [0, 0]
     hs, vs = host_tables(plan)
     # integer-valued: bit-exact
@@ -258,6 +259,18 @@ INNER_CASES = [
     ([999, 2, 3, 4], 16, "f32", "f32", None, 0),
     ([12, 9, 7, 1], 1, "f32", "f32", None, 0),
     ([8, 7, 1, 5, 3], 4, "f64", "f64", True, 0),
+    # with the outer sketch and FP32 work the k = 0 pass writes both
+    # intermediates (aligned X): 4, 8 and 10 vectors of FP32 per thread, a
+    # slab of 40000 values (the 200^4 workload's), of 40960 (the largest),
+    # BF16, d = 5
+    ([20, 30, 40, 10], 60, "f32", "f32", True, 0),
+    ([200, 200, 3, 2], 64, "f32", "f32", True, 0),
+    ([128, 320, 2, 3], 32, "f32", "f32", True, 0),
+    ([128, 256, 2, 2], 16, "f32", "f32", True, 0),
+    ([1000, 3, 4, 5], 16, "f32", "f32", True, 0),
+    ([96, 40, 5, 3], 16, "bf16", "f32", True, 0),
+    ([64, 8, 8, 8, 8], 300, "bf16", "f32", True, 0),
+    ([12, 10, 3, 4, 5], 20, "f32", "f32", True, 0),
 ]
 
 
@@ -266,7 +279,12 @@ def test_sketch_all_inner(tts, n, J, xd, wd, fuse, shift):
     say("sketch all inner", n, J, xd, wd, fuse, shift)
     N = int(np.prod(n))
     plan = tts.Plan(n, [1] * (len(n) + 1), J, 1e-3, seed=5, x_dtype=xd, work_dtype=wd, fuse=fuse, inner=True)
-    assert plan.sketch_sources()[2:] == [2] * (len(n) - 2)
+    src = plan.sketch_sources()
+    # Y_2.. from the inner sketch, written by the pass of mode 2 or (FP32
+    # work with the outer sketch) by the k = 0 pass
+    assert src[2:] == [2] * (len(n) - 2) or src[1:] == [0] * (len(n) - 1), src
+    if fuse and wd == "f32" and n[0] % (8 if xd == "bf16" else 4) == 0:
+        assert src == [0] * len(n), src
     hs, vs = host_tables(plan)
 
     def shifted(Xh):
@@ -303,6 +321,13 @@ def test_sketch_inner_rule(tts):
     # d = 3 has no mode beyond 2; n_0 > 1024 is not taken
     assert tts.Plan([30, 40, 50], [1, 3, 3, 1], 64, 1e-3, inner=True).sketch_sources() == [0, 1, 2]
     assert tts.Plan([1030, 3, 2, 2], [1] * 5, 8, 1e-3, inner=True, fuse=False).sketch_sources() == [0, 1, 2, 3]
+    # both intermediates from the k = 0 pass: FP32 work, n_0 a multiple of
+    # 4 (FP32 X), slabs of at most 40960 values
+    assert tts.Plan([200, 200, 3, 2], [1] * 5, 64, 1e-3, inner=True, fuse=True).sketch_sources() == [0, 0, 0, 0]
+    assert tts.Plan([202, 200, 3, 2], [1] * 5, 64, 1e-3, inner=True, fuse=True).sketch_sources() == [0, 0, 2, 2]
+    assert tts.Plan([128, 324, 2, 3], [1] * 5, 32, 1e-3, inner=True, fuse=True).sketch_sources() == [0, 0, 2, 2]
+    assert tts.Plan([200, 200, 3, 2], [1] * 5, 64, 1e-3, inner=True, fuse=True, x_dtype="f64",
+                    work_dtype="f64").sketch_sources() == [0, 0, 2, 2]
 
 
 def test_sketch_fusion_rule(tts):
@@ -682,9 +707,17 @@ def test_sweeps_inner_sketch(tts, serial):
     assert plan.sketch_sources() == [0, 1, 2, 2]
     assert max(abs(a - b) for a, b in zip(res, res_o)) < 1e-4
     plan, dc, ref, res, res_o, Xo = _run_sweeps(tts, [12, 10, 8, 9, 7], [1, 3, 4, 4, 3, 1], 300, 1e-3, 8, 3, "f32",
-                                                "f32", 1e-2, serial=serial, inner=True)
+                                                "f32", 1e-2, serial=serial, inner=True, fuse=False)
     assert plan.sketch_sources()[2:] == [2, 2, 2]
     assert max(abs(a - b) for a, b in zip(res, res_o)) < 1e-4
+    # both intermediates from the k = 0 pass (one pass over X per sweep)
+    for n, R in (([40, 20, 6, 5], [1, 4, 5, 3, 1]), ([12, 10, 8, 9, 7], [1, 3, 4, 4, 3, 1])):
+        plan, dc, ref, res, res_o, Xo = _run_sweeps(tts, n, R, 200, 1e-3, 8, 3, "f32", "f32", 1e-2, serial=serial,
+                                                    inner=True, fuse=True)
+        assert plan.sketch_sources() == [0] * len(n)
+        assert max(abs(a - b) for a, b in zip(res, res_o)) < 1e-4
+        got = [tts.core_to_host(c, r.shape) for c, r in zip(dc, ref)]
+        assert rel(als.tt_full(got), als.tt_full(ref)) < 1e-3
 
 
 @pytest.mark.parametrize("serial", [False, True])
