@@ -828,11 +828,12 @@ __global__ __launch_bounds__(256) void k_sketch_y_zi(const WT* __restrict__ Z, c
 //    entries are read from LDS.
 // A slab is read in four chunks of ceil(NV / 4) vectors per thread; the next
 // chunk (of this slab or the next) is loaded before the current one is
-// added.  Two LDS arrays alternate between slabs: after the barrier that
-// closes slab o, each thread writes its entries of o's array as row o of Z
-// and clears them while the next slab goes to the other array, so one
-// barrier per slab suffices.
-template <typename XT, int V, int NV>
+// added.  Slabs go in groups of G to G LDS arrays each, two sets alternating
+// between groups: after the barrier that closes a group, each thread writes
+// its entries of the group's arrays as their rows of Z and clears them while
+// the next group goes to the other set, so one barrier per G slabs
+// suffices.
+template <typename XT, int V, int NV, int G>
 __global__ __launch_bounds__(1024) void k_sketch_zoi(const XT* __restrict__ X, const uint32_t* __restrict__ off,
                                                     const uint32_t* __restrict__ sorted,
                                                     const uint32_t* __restrict__ tab0, const uint32_t* __restrict__ tab1,
@@ -840,13 +841,13 @@ __global__ __launch_bounds__(1024) void k_sketch_zoi(const XT* __restrict__ X, c
                                                     int32_t n1, uint32_t J, uint32_t mdiv) {
   constexpr int CH = (NV + 3) / 4;   // vectors per thread and chunk
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* acc = reinterpret_cast<double*>(smem_raw);                  // 2 J entries
-  uint32_t* t0 = reinterpret_cast<uint32_t*>(acc + 2 * (size_t)J);    // n_0 entries
+  double* acc = reinterpret_cast<double*>(smem_raw);                  // 2 G J entries
+  uint32_t* t0 = reinterpret_cast<uint32_t*>(acc + 2 * G * (size_t)J);   // n_0 entries
   uint32_t* t1 = t0 + n0;                                              // n_1 entries
   const int t = threadIdx.x;
   const uint32_t c = blockIdx.x;
   const int S = n0 * n1;
-  for (uint32_t q = t; q < 2 * J; q += 1024) acc[q] = 0.0;
+  for (uint32_t q = t; q < 2 * G * J; q += 1024) acc[q] = 0.0;
   for (int q = t; q < n0; q += 1024) t0[q] = tab0[q];
   for (int q = t; q < n1; q += 1024) t1[q] = tab1[q];
   float za[NV][V];
@@ -886,7 +887,8 @@ __global__ __launch_bounds__(1024) void k_sketch_zoi(const XT* __restrict__ X, c
       }
     }
   };
-  int buf = 0;
+  int buf = 0, np = 0;
+  int64_t pend[G];   // Z rows of the group's slabs
   if (beg < end) load_chunk(xc, X + (int64_t)(sorted[beg] & TT_KEY_MASK) * S, 0);
   for (uint32_t it = beg; it < end; ++it) {
     const uint32_t item = sorted[it];
@@ -894,7 +896,7 @@ __global__ __launch_bounds__(1024) void k_sketch_zoi(const XT* __restrict__ X, c
     const uint32_t so = item & TT_KEY_SIGN;
     const XT* slab = X + o * S;
     const XT* next = it + 1 < end ? X + (int64_t)(sorted[it + 1] & TT_KEY_MASK) * S : nullptr;
-    double* A = acc + (size_t)buf * J;
+    double* A = acc + (size_t)(buf * G + np) * J;
     // chunks 0..3 alternate between the two buffers; chunk 0 of the next
     // slab lands in xc again
     load_chunk(xn, slab, 1);
@@ -905,13 +907,25 @@ __global__ __launch_bounds__(1024) void k_sketch_zoi(const XT* __restrict__ X, c
     add_chunk(xc, 2, A, so);
     if (next) load_chunk(xc, next, 0);
     add_chunk(xn, 3, A, so);
-    __syncthreads();
-    float* zr = Z + o * (int64_t)J;
-    for (uint32_t q = t; q < J; q += 1024) {
-      zr[q] = (float)A[q];
-      A[q] = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (g == np) pend[g] = o;
+    ++np;
+    if (np == G || it + 1 == end) {   // the same for every thread of the workgroup
+      __syncthreads();
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (g >= np) break;
+        double* Ag = acc + (size_t)(buf * G + g) * J;
+        float* zr = Z + pend[g] * (int64_t)J;
+        for (uint32_t q = t; q < J; q += 1024) {
+          zr[q] = (float)Ag[q];
+          Ag[q] = 0.0;
+        }
+      }
+      buf ^= 1;
+      np = 0;
     }
-    buf ^= 1;
   }
   float* out = zo + (int64_t)c * S;
 #pragma unroll
@@ -1083,8 +1097,11 @@ hipError_t launch_y0_zo(const tt_plan_s* p, const WT* zo, WT* Y) {
 template <typename XT, int NV>
 hipError_t run_zoi_v(const tt_plan_s* p, const XT* X, float* Y, float* zo) {
   constexpr int V = 16 / (int)sizeof(XT);
-  const size_t lds = 2 * (size_t)p->J * sizeof(double) + (size_t)(p->n[0] + p->n[1]) * sizeof(uint32_t);
-  auto kern = k_sketch_zoi<XT, V, NV>;
+  const size_t tabs = (size_t)(p->n[0] + p->n[1]) * sizeof(uint32_t);
+  // two slabs per barrier when four bucket arrays fit in LDS
+  const bool two = 4 * (size_t)p->J * sizeof(double) + tabs <= 160 * 1024;
+  const size_t lds = (two ? 4 : 2) * (size_t)p->J * sizeof(double) + tabs;
+  auto kern = two ? k_sketch_zoi<XT, V, NV, 2> : k_sketch_zoi<XT, V, NV, 1>;
   hipError_t e;
   if ((e = tt_allow_lds(kern, lds)) != hipSuccess) return e;
   const uint32_t* tab = p->at<uint32_t>(p->o_tab);
@@ -1098,12 +1115,15 @@ hipError_t run_zoi_v(const tt_plan_s* p, const XT* X, float* Y, float* zo) {
 
 template <typename XT>
 hipError_t run_zoi(const tt_plan_s* p, const XT* X, float* Y, float* zo) {
-  switch (tt_joint_vectors(p)) {
-    case 4: return run_zoi_v<XT, 4>(p, X, Y, zo);
-    case 8: return run_zoi_v<XT, 8>(p, X, Y, zo);
-    case 10: return run_zoi_v<XT, 10>(p, X, Y, zo);
-    default: return hipErrorInvalidValue;   // not reached: the plan takes the path for at most 10
+  const int nv = tt_joint_vectors(p);
+  if constexpr (sizeof(XT) == 2) {   // BF16: 4 vectors of 8 values
+    if (nv == 4) return run_zoi_v<XT, 4>(p, X, Y, zo);
+  } else {
+    if (nv == 4) return run_zoi_v<XT, 4>(p, X, Y, zo);
+    if (nv == 8) return run_zoi_v<XT, 8>(p, X, Y, zo);
+    if (nv == 10) return run_zoi_v<XT, 10>(p, X, Y, zo);
   }
+  return hipErrorInvalidValue;   // not reached: the plan takes the path for these counts only
 }
 
 template <typename XT, typename WT>
@@ -1397,8 +1417,8 @@ int tt_joint_vectors(const tt_plan_s* p) {
   if (p->n[0] % V != 0 || p->n[0] > 4096) return 0;
   if (16 * p->J_cap + 4 * (p->n[0] + p->n[1]) > 160 * 1024) return 0;
   const int64_t nv = (S / V + 1023) / 1024;
-  if (nv * V > 40) return 0;
-  return (int)(nv <= 4 ? 4 : nv <= 8 ? 8 : 10);
+  const int NV = nv <= 4 ? 4 : nv <= 8 ? 8 : 10;
+  return nv <= NV && NV * V <= 40 ? NV : 0;
 }
 
 bool tt_sketch_joint(const tt_plan_s* p) { return tt_joint_vectors(p) > 0; }

@@ -269,6 +269,7 @@ INNER_CASES = [
     ([128, 256, 2, 2], 16, "f32", "f32", True, 0),
     ([1000, 3, 4, 5], 16, "f32", "f32", True, 0),
     ([96, 40, 5, 3], 16, "bf16", "f32", True, 0),
+    ([128, 256, 2, 2], 16, "bf16", "f32", True, 0),
     ([64, 8, 8, 8, 8], 300, "bf16", "f32", True, 0),
     ([12, 10, 3, 4, 5], 20, "f32", "f32", True, 0),
 ]
@@ -283,7 +284,8 @@ def test_sketch_all_inner(tts, n, J, xd, wd, fuse, shift):
     # Y_2.. from the inner sketch, written by the pass of mode 2 or (FP32
     # work with the outer sketch) by the k = 0 pass
     assert src[2:] == [2] * (len(n) - 2) or src[1:] == [0] * (len(n) - 1), src
-    if fuse and wd == "f32" and n[0] % (8 if xd == "bf16" else 4) == 0:
+    vec = 8 if xd == "bf16" else 4
+    if fuse and wd == "f32" and n[0] % vec == 0 and n[0] * n[1] <= 1024 * (32 if xd == "bf16" else 40):
         assert src == [0] * len(n), src
     hs, vs = host_tables(plan)
 
@@ -328,6 +330,11 @@ def test_sketch_inner_rule(tts):
     assert tts.Plan([128, 324, 2, 3], [1] * 5, 32, 1e-3, inner=True, fuse=True).sketch_sources() == [0, 0, 2, 2]
     assert tts.Plan([200, 200, 3, 2], [1] * 5, 64, 1e-3, inner=True, fuse=True, x_dtype="f64",
                     work_dtype="f64").sketch_sources() == [0, 0, 2, 2]
+    # BF16 X: 4 vectors of 8 values per thread at most (32768-value slabs)
+    assert tts.Plan([128, 256, 2, 2], [1] * 5, 16, 1e-3, inner=True, fuse=True,
+                    x_dtype="bf16").sketch_sources() == [0, 0, 0, 0]
+    assert tts.Plan([200, 200, 3, 2], [1] * 5, 64, 1e-3, inner=True, fuse=True,
+                    x_dtype="bf16").sketch_sources() == [0, 0, 2, 2]
 
 
 def test_sketch_fusion_rule(tts):
