@@ -345,6 +345,7 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_zo = fuse ? take(ws * (size_t)p->J_cap * (size_t)p->n[0] * (size_t)p->n[1]) : 0;
   // inner sketch of the k >= 2 pass (J_cap x O0)
   p->o_zi = inner ? take(ws * (size_t)p->J_cap * (size_t)p->O0) : 0;
+  p->o_zperm = inner ? take(sizeof(uint32_t) * (size_t)p->J_cap) : 0;
   p->o_spacc = take(sizeof(double) * (size_t)p->J_cap * (size_t)p->tab_off[d]);
   // exact update
   p->o_exphi = p->o_exch = p->o_expart = p->o_exgram = p->o_exmerge = 0;

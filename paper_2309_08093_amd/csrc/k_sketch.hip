@@ -815,7 +815,9 @@ __global__ __launch_bounds__(256) void k_sketch_y_zi(const WT* __restrict__ Z, c
 }
 
 // ---------------------------------------------------------------- outer and inner sketch in one pass
-// For FP32 work: workgroup c (1024 threads) reads the whole slabs of the
+// For FP32 work: workgroup w (1024 threads) takes bucket c = order[w] (the
+// buckets by number of outer tuples, largest first, so that the last
+// workgroups of the launch are short) and reads the whole slabs of the
 // outer tuples of key c (the bucket list of the k = 0 sketch), once each,
 // and forms from them both
 //  * row c of the outer sketch: the slabs summed with their signs, thread t
@@ -836,6 +838,7 @@ __global__ __launch_bounds__(256) void k_sketch_y_zi(const WT* __restrict__ Z, c
 template <typename XT, int V, int NV, int G>
 __global__ __launch_bounds__(1024) void k_sketch_zoi(const XT* __restrict__ X, const uint32_t* __restrict__ off,
                                                     const uint32_t* __restrict__ sorted,
+                                                    const uint32_t* __restrict__ order,
                                                     const uint32_t* __restrict__ tab0, const uint32_t* __restrict__ tab1,
                                                     float* __restrict__ zo, float* __restrict__ Z, int32_t n0,
                                                     int32_t n1, uint32_t J, uint32_t mdiv) {
@@ -845,7 +848,7 @@ __global__ __launch_bounds__(1024) void k_sketch_zoi(const XT* __restrict__ X, c
   uint32_t* t0 = reinterpret_cast<uint32_t*>(acc + 2 * G * (size_t)J);   // n_0 entries
   uint32_t* t1 = t0 + n0;                                              // n_1 entries
   const int t = threadIdx.x;
-  const uint32_t c = blockIdx.x;
+  const uint32_t c = order[blockIdx.x];
   const int S = n0 * n1;
   for (uint32_t q = t; q < 2 * G * J; q += 1024) acc[q] = 0.0;
   for (int q = t; q < n0; q += 1024) t0[q] = tab0[q];
@@ -1094,6 +1097,35 @@ hipError_t launch_y0_zo(const tt_plan_s* p, const WT* zo, WT* Y) {
 }
 
 // The one pass for the outer and the inner sketch (FP32 work), then Y_0.
+// order[] = the J buckets by their number of outer tuples (off[c + 1] -
+// off[c], counted up to 255), largest first; one workgroup.  The order
+// within a count follows LDS atomics and does not affect any result.
+__global__ __launch_bounds__(1024) void k_bucket_order(const uint32_t* __restrict__ off, uint32_t* __restrict__ order,
+                                                       uint32_t J) {
+  __shared__ uint32_t hist[256];
+  const int t = threadIdx.x;
+  if (t < 256) hist[t] = 0;
+  __syncthreads();
+  for (uint32_t c = t; c < J; c += 1024) {
+    const uint32_t n = off[c + 1] - off[c];
+    atomicAdd(&hist[255 - (n < 255 ? n : 255)], 1u);
+  }
+  __syncthreads();
+  if (t == 0) {   // exclusive prefix sum: bin 0 holds the largest buckets
+    uint32_t run = 0;
+    for (int b = 0; b < 256; ++b) {
+      const uint32_t h = hist[b];
+      hist[b] = run;
+      run += h;
+    }
+  }
+  __syncthreads();
+  for (uint32_t c = t; c < J; c += 1024) {
+    const uint32_t n = off[c + 1] - off[c];
+    order[atomicAdd(&hist[255 - (n < 255 ? n : 255)], 1u)] = c;
+  }
+}
+
 template <typename XT, int NV>
 hipError_t run_zoi_v(const tt_plan_s* p, const XT* X, float* Y, float* zo) {
   constexpr int V = 16 / (int)sizeof(XT);
@@ -1105,8 +1137,13 @@ hipError_t run_zoi_v(const tt_plan_s* p, const XT* X, float* Y, float* zo) {
   hipError_t e;
   if ((e = tt_allow_lds(kern, lds)) != hipSuccess) return e;
   const uint32_t* tab = p->at<uint32_t>(p->o_tab);
+  uint32_t* order = p->at<uint32_t>(p->o_zperm);
+  hipLaunchKernelGGL(k_bucket_order, dim3(1), dim3(1024), 0, p->stream, p->at<uint32_t>(p->o_cnt), order,
+                     (uint32_t)p->J);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3((unsigned)p->J), dim3(1024), lds, p->stream, X, p->at<uint32_t>(p->o_cnt),
-                     p->at<uint32_t>(p->o_sortO), tab + p->tab_off[0], tab + p->tab_off[1], zo, p->at<float>(p->o_zi),
+                     p->at<uint32_t>(p->o_sortO), order, tab + p->tab_off[0], tab + p->tab_off[1], zo,
+                     p->at<float>(p->o_zi),
                      (int32_t)p->n[0], (int32_t)p->n[1], (uint32_t)p->J,
                      (uint32_t)((((uint64_t)1 << 32) + (uint64_t)p->n[0] - 1) / (uint64_t)p->n[0]));
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -57,7 +57,8 @@ struct tt_plan_s {
   size_t o_tab, o_KI, o_KO, o_cnt, o_hist, o_sortO, o_part, o_chat, o_pre, o_suf, o_SH, o_Y,
       o_gram, o_minv, o_W, o_qrA, o_qrQ, o_qrR, o_status, o_res, o_gold, o_Yall, o_pol, o_gsum, o_resU, o_resH,
       o_tw, o_zo,                  // o_zo: outer sketch of the fused k = 0 pass (0: not fused)
-      o_zi;                        // o_zi: inner sketch Z of the k >= 2 pass (0: not used)
+      o_zi,                        // o_zi: inner sketch Z of the k >= 2 pass (0: not used)
+      o_zperm;                     // buckets of the joint k = 0 pass, largest first (J_cap entries)
   // exact update (TT_FLAG_EXACT; 0 otherwise): two left-interface buffers of
   // ex_phi work-type values, two right-chain buffers of ex_chain, ex_part FP64
   // slice partials, the two Gram factors (2 x 256 doubles)
