@@ -779,14 +779,18 @@ def main():
 
     # the inner-sketch pass of mode 2 (k_sketch_zi: X read, the J x n_2...n_{d-1}
     # sketch of every slab over modes 0 and 1 written) when Y_3.. come from it
-    inner = d >= 4 and all(src[k] == 2 for k in range(3, d))
+    # joint: the k = 0 pass (k_sketch_zoi) writes both intermediates, and
+    # every Y_k comes from them (one pass over X)
+    joint = d >= 4 and all(src[k] == 0 for k in range(1, d))
+    inner = joint or (d >= 4 and all(src[k] == 2 for k in range(3, d)))
     inner_bytes = J * (N // (n[0] * n[1])) * wbytes if inner else 0
     kern_k = ["k_sketch_zi"] if inner else sorted(set(plan.sketch_kernel(k) for k in range(1, d) if src[k] == k))
     rfk = roof("sketch_k", "+".join(kern_k), N * xbytes + inner_bytes, ["+".join(kern_k)])
     # the fused k = 0 pass: k_sketch_zo (X read, outer sketch written) and
     # k_sketch_y0_zo (Y_0 from the outer sketch, read once)
-    k0_kernels = ["k_sketch_zo", "k_sketch_y0_zo"] if fused else [plan.sketch_kernel(0)]
-    k0_bytes = N * xbytes + 2 * outer_bytes
+    k0_kernels = (["k_sketch_zoi", "k_sketch_y0_zo"] if joint else ["k_sketch_zo", "k_sketch_y0_zo"] if fused
+                  else [plan.sketch_kernel(0)])
+    k0_bytes = N * xbytes + 2 * outer_bytes + (inner_bytes if joint else 0)
     rf0 = roof("sketch_k0", "+".join(k0_kernels), k0_bytes, k0_kernels)
     rf, rf_other = (rfk, rf0) if prof["sketch_k"][0] >= prof["sketch_k0"][0] else (rf0, rfk)
     # per-class times from separate sweeps with every class timed
