@@ -680,15 +680,16 @@ def main():
                     help="JSON file the batched autotuner reads its choices from and writes them to")
     ap.add_argument("--cpu-entries", type=int, default=128_000_000)
     ap.add_argument("--overlap", action="store_true",
-                    help="time the overlapped schedule (data sketches on a second stream beside the core "
-                         "updates) instead of the serial one")
-    ap.add_argument("--serial", action="store_true", help="the serial schedule (the default)")
+                    help="the overlapped schedule (data sketches on a second stream beside the core updates; "
+                         "the library's default and this script's)")
+    ap.add_argument("--serial", action="store_true", help="time the serial schedule instead of the overlapped one")
     ap.add_argument("--reserve-cus", type=int, default=None,
                     help="CUs kept free of the overlapped data sketches (library default if omitted)")
     ap.add_argument("--probe-traffic", action="store_true",
                     help="run each data sketch once and one device copy of X, then exit (for HBM counter runs)")
     args = ap.parse_args()
-    args.serial = not args.overlap
+    if args.serial and args.overlap:
+        ap.error("--serial and --overlap together")
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the data sketch would shard by slabs of the last mode plus one all-reduce of J x n_k "
@@ -823,7 +824,8 @@ def main():
                            % (d, sum(1 for k in range(d) if src[k] == k)),
                    "sketch_sources": src,
                    "schedule": "serial" if args.serial else "data sketches overlapped on a second stream",
-                   "reserved_cus": None if args.serial else args.reserve_cus},
+                   "reserved_cus": None if args.serial else ("library default" if args.reserve_cus is None
+                                                             else args.reserve_cus)},
         "hbm_gbps_sweep": (sum(1 for k in range(d) if src[k] == k) * N * xbytes + 3 * outer_bytes
                            + (d - 1) * inner_bytes) / (ms_per_step * 1e-3) / 1e9,
         "hbm_gbps_sweep_note": "passes over X plus the outer sketch written once and read twice (Y_0, Y_1) and the "
@@ -835,12 +837,12 @@ def main():
         "kernels_ms_per_step_note": "%d further sweeps with every kernel class timed by HIP events" % n_cls,
     }
 
-    # the other schedule, for comparison: the overlapped one runs the data
-    # sketches beside the core updates, so its sweep is a little shorter but
-    # every kernel's launch time includes the sharing of the GPU
-    if args.serial and not args.no_isolated:
+    # the other schedule, for comparison: the serial one runs every kernel on
+    # the plan's stream; the overlapped one runs the data sketches beside the
+    # core updates
+    if not args.no_isolated:
         plan2 = tts.Plan(n, R, J, lam, seed=args.seed, x_dtype=cfg["xd"], work_dtype=cfg["wd"], gram=cfg["gram"],
-                         device=dev, serial=False)
+                         device=dev, serial=not args.serial)
         cores3 = [tts.core_to_device(c, dev) for c in init]
         for _ in range(max(3, args.warmup)):
             plan2.als_sweep(X, cores3)
@@ -852,10 +854,15 @@ def main():
             evs2[t + 1].record(stream)
         torch.cuda.synchronize()
         ms2 = float(np.median([evs2[t].elapsed_time(evs2[t + 1]) for t in range(args.steps)]))
-        out["overlapped_schedule"] = {"ms_per_step": ms2, "value": d * N / (ms2 * 1e-3), "unit": "entries/s",
-                                      "reserved_cus": "the library default: the CUs of one XCD kept from the sketches",
-                                      "note": "data sketches on a CU-masked side stream beside the core updates; "
-                                              "median over the timed sweeps"}
+        if args.serial:
+            out["overlapped_schedule"] = {
+                "ms_per_step": ms2, "value": d * N / (ms2 * 1e-3), "unit": "entries/s",
+                "reserved_cus": "the library default (none when the k = 0 pass writes both intermediates, else the "
+                                "CUs of one XCD)",
+                "note": "data sketches on a side stream beside the core updates; median over the timed sweeps"}
+        else:
+            out["serial_schedule"] = {"ms_per_step": ms2, "value": d * N / (ms2 * 1e-3), "unit": "entries/s",
+                                      "note": "every kernel on the plan's stream; median over the timed sweeps"}
         del plan2, cores3
 
     # each data sketch alone on the plan's stream (no concurrent core updates)
@@ -897,7 +904,7 @@ def main():
             "k0_pass": {"kernel": "+".join(k0_kernels), "bytes": k0_bytes,
                         "GB/s": round(k0_bytes / (k0ms * 1e-3) / 1e9, 1),
                         "frac": round(k0_bytes / (k0ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}}
-        if inner:
+        if inner and not joint:
             kms = pr["sketch_k"][0] / 5
             kb = N * xbytes + inner_bytes
             out["sketch_all_isolated"]["inner_pass"] = {

@@ -288,7 +288,10 @@ tt_status tt_als_sweep(tt_plan plan, const void* X, void* const* cores, double* 
  * the short kernels of the core updates; 0 gives the side stream every CU.
  * The default (before any call) reserves the CUs of one XCD (CU count / 8;
  * the runtime numbers CUs XCD by XCD), which keeps the two streams on
- * separate L2s.  TT_ERR_ARG if reserved_cus is negative or not below the
+ * separate L2s, except when the k = 0 pass writes both intermediates
+ * (tt_plan_sketch_sources gives 0 for every mode): the core updates then
+ * wait for that pass anyway, and no CU is reserved.  TT_ERR_ARG if
+ * reserved_cus is negative or not below the
  * device's CU count.  Synchronises and recreates the plan's streams. */
 tt_status tt_plan_set_overlap(tt_plan plan, int32_t reserved_cus);
 

@@ -413,10 +413,15 @@ int device_cus() {
 // CUs kept from the side stream: the plan's setting, or by default those of
 // one XCD.  The runtime numbers CUs XCD by XCD (ncu / 8 per XCD), and a
 // reservation of exactly one XCD keeps the two streams on separate L2s:
-// measured on the 200^4 sweep, 32 CUs gave 4.56 ms, 0 gave 4.94 ms, and 24,
-// 40 or 48 (an XCD split between the streams) 5.46-5.63 ms.
+// measured on the 200^4 sweep with a pass over X per mode, 32 CUs gave
+// 4.56 ms, 0 gave 4.94 ms, and 24, 40 or 48 (an XCD split between the
+// streams) 5.46-5.63 ms.  When the k = 0 pass writes both intermediates
+// (one pass over X per sweep) the core updates cannot start before it ends,
+// and the short stages after it leave CUs free: there the default keeps no
+// CU back (200^4: 3.04 ms against 3.41 ms with 32 and 3.40 ms with 16).
 int reserved_of(const tt_plan_s* p, int ncu) {
   if (p->reserved_cus >= 0) return p->reserved_cus;
+  if (tt_sketch_joint(p)) return 0;
   return (ncu >= 64 && ncu % 8 == 0) ? ncu / 8 : 0;
 }
 
