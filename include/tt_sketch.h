@@ -101,18 +101,22 @@ typedef struct {
 #define TT_FLAG_FUSE 2u
 #define TT_FLAG_NO_FUSE 4u
 
-/* Data sketches of modes k >= 2 (d >= 4, n_0 <= 1024): the pass of mode 2
- * can instead write the TensorSketch of every slab X(:, :, o) over modes 0
- * and 1 alone (Z: J x prod(n_2..n_{d-1}) values of the work type in the
- * workspace; row o holds sum v_0(i_0) v_1(i_1) X(i_0, i_1, o) at bucket
- * (h_0(i_0) + h_1(i_1)) mod J).  Y_k for every k >= 2 follows from Z by the
- * TensorSketch over the remaining modes (a cyclic shift of each row by their
- * bucket, times their sign), so one pass over X serves all of them.  By
- * default this is done when it moves fewer bytes,
- * N sizeof(X) + (d - 1) |Z| sizeof(work) <= 0.75 (d - 2) N sizeof(X).
- * TT_FLAG_INNER asks for it whenever d >= 4 and n_0 <= 1024,
+/* Data sketches of modes k >= m (d >= 4, n_0 <= 1024, 2 <= m <= d-2): the
+ * pass of mode m can instead write the TensorSketch of every slab
+ * X(:, ..., :, o) over modes 0..m-1 alone (Z: J x prod(n_m..n_{d-1}) values
+ * of the work type in the workspace; row o holds
+ * sum v_0(i_0)...v_{m-1}(i_{m-1}) X(i_0, ..., i_{m-1}, o) at bucket
+ * (h_0(i_0) + ... + h_{m-1}(i_{m-1})) mod J).  Y_k for every k >= m follows
+ * from Z by the TensorSketch over the remaining modes (a cyclic shift of
+ * each row by their bucket, times their sign), so one pass over X serves all
+ * of them; the modes 2..m-1 keep their own passes.  The plan takes the m
+ * with the fewest bytes moved, (m - 2) N sizeof(X) + N max(sizeof(X), 4) +
+ * (d - m + 1) |Z| sizeof(work) (the pass that writes Z adds each entry by an
+ * LDS atomic, which costs about the time of 4 bytes of HBM), among those
+ * whose slab rows (n_1 ... n_{m-1}) number at most 16384, and by default
+ * uses it when that is at most 0.75 (d - 2) N sizeof(X).  TT_FLAG_INNER asks for it whenever d >= 4 and n_0 <= 1024,
  * TT_FLAG_NO_INNER never (not both).  Independent of TT_FLAG_FUSE;
- * tt_sketch_tensor(k) is not affected.  With both intermediates, FP32 work,
+ * tt_sketch_tensor(k) is not affected.  With both intermediates, m = 2, FP32 work,
  * FP32 or BF16 X, n_0 a multiple of 16 bytes' worth of X values and slabs
  * of at most 40960 values, the k = 0 pass writes Z as well (one pass over X
  * per sweep) whenever X is 16-byte aligned. */
@@ -198,7 +202,7 @@ tt_status tt_sketch_sparse_all(tt_plan plan, int64_t nnz, const int32_t* coords,
 /* How tt_sketch_tensor_all and tt_als_sweep obtain each Y_k (host query, no
  * device work): src[k] = k when Y_k takes its own pass over X, src[k] = j != k
  * when it is derived from an intermediate written by the pass of mode j
- * (src[1] = 0 with the outer sketch of TT_FLAG_FUSE, src[k] = 2 for k > 2
+ * (src[1] = 0 with the outer sketch of TT_FLAG_FUSE, src[k] = m for k > m
  * with the inner sketch of TT_FLAG_INNER, src[k] = 0 for every k >= 1 when
  * the k = 0 pass writes both; a 16-byte aligned X is assumed for the last).
  * src: host array of d entries. */

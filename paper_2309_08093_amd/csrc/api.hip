@@ -266,17 +266,41 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
     const int64_t e = p->n[1] * tt_outer_slices(p) * p->J_cap;
     if (e > p->part_entries) p->part_entries = e;
   }
-  // inner sketch Z of the k >= 2 pass (TT_FLAG_INNER); its Y_k stages keep
-  // n_k x slices partials of J entries
+  // inner sketch Z over modes 0..m-1 (TT_FLAG_INNER): the m with the fewest
+  // bytes moved, own passes for the modes 2..m-1; its Y_k stages keep n_k x
+  // slices partials of J entries.  The pass that writes Z adds every entry
+  // by an LDS atomic, about 1.6e12 per second on this device: an entry costs
+  // at least the time of 4 bytes of HBM (measured at 64^5 BF16: 0.68 ms for
+  // the pass against 0.35 ms for a key-grouped pass over X).
   bool inner = false;
+  p->inner_m = 0;
+  p->inner_rows = p->inner_O = 0;
   if (d >= 4 && p->n[0] <= 1024 && !(p->flags & TT_FLAG_NO_INNER)) {
-    const double zi_bytes = (double)p->wsize() * (double)p->J_cap * (double)p->O0;
     const double x_bytes = (double)N * (double)p->xsize();
-    inner = (p->flags & TT_FLAG_INNER) || x_bytes + (d - 1) * zi_bytes <= 0.75 * (d - 2) * x_bytes;
+    double best = 0.0;
+    int64_t rows = 1;
+    for (int m = 2; m <= d - 2; ++m) {
+      rows *= p->n[m - 1];
+      int64_t Om = 1;
+      for (int s2 = m; s2 < d; ++s2) Om *= p->n[s2];
+      // the slab's row keys and the J buckets fit in LDS
+      if (rows > 16384) break;
+      const double zi_bytes = (double)p->wsize() * (double)p->J_cap * (double)Om;
+      const double pass = x_bytes > 4.0 * (double)N ? x_bytes : 4.0 * (double)N;
+      const double bytes = (m - 2) * x_bytes + pass + (d - m + 1) * zi_bytes;
+      if (p->inner_m == 0 || bytes < best) {
+        best = bytes;
+        p->inner_m = m;
+        p->inner_rows = rows;
+        p->inner_O = Om;
+      }
+    }
+    inner = p->inner_m > 0 && ((p->flags & TT_FLAG_INNER) || best <= 0.75 * (d - 2) * x_bytes);
+    if (!inner) p->inner_m = 0;
   }
   p->o_zi = 0;
   if (inner) {
-    for (int k = 2; k < d; ++k) {
+    for (int k = p->inner_m; k < d; ++k) {
       const int64_t e = p->n[k] * tt_inner_slices(p, k) * p->J_cap;
       if (e > p->part_entries) p->part_entries = e;
     }
@@ -343,8 +367,8 @@ tt_status tt_sketch_plan(const tt_plan_desc* desc, void* hip_stream, size_t* wor
   p->o_pol = take(sizeof(float) * TT_MAX_ORDER * (TT_JPOLICY_FEATURES + TT_JPOLICY_OUTPUTS));
   // outer sketch of the fused k = 0 pass (J_cap x n_0 x n_1)
   p->o_zo = fuse ? take(ws * (size_t)p->J_cap * (size_t)p->n[0] * (size_t)p->n[1]) : 0;
-  // inner sketch of the k >= 2 pass (J_cap x O0)
-  p->o_zi = inner ? take(ws * (size_t)p->J_cap * (size_t)p->O0) : 0;
+  // inner sketch of the pass of mode inner_m (J_cap x inner_O)
+  p->o_zi = inner ? take(ws * (size_t)p->J_cap * (size_t)p->inner_O) : 0;
   p->o_zperm = inner ? take(sizeof(uint32_t) * (size_t)p->J_cap) : 0;
   p->o_spacc = take(sizeof(double) * (size_t)p->J_cap * (size_t)p->tab_off[d]);
   // exact update
@@ -586,8 +610,8 @@ tt_status tt_sketch_tensor_all(tt_plan p, const void* X, void* Yall) {
       TT_HIP_TRY(launch_sketch_mode0_outer(p, X, Yk));
     } else if (fused && k == 1) {
       TT_HIP_TRY(launch_sketch_y1_outer(p, Yk));
-    } else if (inner && k >= 2) {
-      if (k == 2) TT_HIP_TRY(launch_sketch_inner(p, X, Yall));
+    } else if (inner && k >= p->inner_m) {
+      if (k == p->inner_m) TT_HIP_TRY(launch_sketch_inner(p, X, Yall));
     } else {
       TT_HIP_TRY(launch_sketch_tensor(p, X, k, Yk));
     }
@@ -619,7 +643,7 @@ tt_status tt_plan_sketch_sources(tt_plan p, int32_t* src) {
   for (int k = 0; k < p->d; ++k) src[k] = k;
   if (tt_sketch_fused01(p)) src[1] = 0;
   if (tt_sketch_inner(p))
-    for (int k = 3; k < p->d; ++k) src[k] = 2;
+    for (int k = p->inner_m + 1; k < p->d; ++k) src[k] = p->inner_m;
   if (tt_sketch_joint(p))
     for (int k = 2; k < p->d; ++k) src[k] = 0;
   return TT_OK;
@@ -870,8 +894,8 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
       void* Yk = Yall + p->wsize() * p->J * p->tab_off[k];
       const hipError_t e = fused && k == 0   ? launch_sketch_mode0_outer(p, X, Yk)
                            : fused && k == 1 ? launch_sketch_y1_outer(p, Yk)
-                           : inner && k > 2  ? hipSuccess   // written with Y_2
-                           : inner && k == 2 ? launch_sketch_inner(p, X, Yall)
+                           : inner && k > p->inner_m  ? hipSuccess   // written with Y_m
+                           : inner && k == p->inner_m ? launch_sketch_inner(p, X, Yall)
                                              : launch_sketch_tensor(p, X, k, Yk);
       if (e != hipSuccess) return tt_fail(TT_ERR_HIP, "data sketch launch failed: %s", hipGetErrorString(e));
       TT_HIP_TRY(hipEventRecord(p->ev_y[k], p->side));
@@ -896,10 +920,10 @@ tt_status tt_als_sweep(tt_plan p, const void* X, void* const* cores, double* rel
         TT_HIP_TRY(launch_sketch_mode0_outer(p, X, Y));
         TT_HIP_TRY(launch_sketch_y1_outer(p, Yall + p->wsize() * p->J * p->tab_off[1]));
       }
-    } else if (inner && k >= 2) {
-      // Y_2 .. Y_{d-1} from the one pass, into their slots of the all-mode buffer
+    } else if (inner && k >= p->inner_m) {
+      // Y_m .. Y_{d-1} from the one pass, into their slots of the all-mode buffer
       Y = Yall + p->wsize() * p->J * p->tab_off[k];
-      if (k == 2) TT_HIP_TRY(launch_sketch_inner(p, X, Yall));
+      if (k == p->inner_m) TT_HIP_TRY(launch_sketch_inner(p, X, Yall));
     } else {
       TT_HIP_TRY(launch_sketch_tensor(p, X, k, Y));
     }

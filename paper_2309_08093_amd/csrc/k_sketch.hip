@@ -696,24 +696,26 @@ __global__ __launch_bounds__(256) void k_sketch_y0_zo(const WT* __restrict__ zo,
 }
 
 // ---------------------------------------------------------------- inner sketch
-// The TensorSketch of every slab X(:, :, o) over modes 0 and 1 alone: row o
-// of Z holds, at bucket (h_0(i_0) + h_1(i_1)) mod J, the sum of
-// v_0(i_0) v_1(i_1) X(i_0, i_1, o).  Workgroup o reads its slab once, row by
-// row (the lane layout of the fibre kernels: LPF lanes per row of n_0
-// values, the lane's mode-0 table entries in registers, U rows per wave in
-// flight), adds every entry into J FP64 LDS buckets, and writes them as row
-// o of Z.  Y_k for k >= 2 then follows from Z (k_sketch_y_zi) without a
-// pass over X of its own.
+// The TensorSketch of every slab X(:, ..., :, o) over modes 0..m-1 alone
+// (m = 2 unless the plan groups more modes): row o of Z holds, at bucket
+// (h_0(i_0) + ... + h_{m-1}(i_{m-1})) mod J, the sum of
+// v_0(i_0) ... v_{m-1}(i_{m-1}) X(i_0, ..., i_{m-1}, o).  Workgroup o reads
+// its slab once, row by row (a row: n_0 values at fixed i_1..i_{m-1}, whose
+// packed key over modes 1..m-1 is rkey[row]; the lane layout of the fibre
+// kernels: LPF lanes per row, the lane's mode-0 table entries in registers,
+// U rows per wave in flight), adds every entry into J FP64 LDS buckets, and
+// writes them as row o of Z.  Y_k for k >= m then follows from Z
+// (k_sketch_y_zi) without a pass over X of its own.
 template <typename XT, typename WT, int V, int NJ, int U>
 __global__ __launch_bounds__(256) void k_sketch_zi(const XT* __restrict__ X, const uint32_t* __restrict__ tab0,
-                                                   const uint32_t* __restrict__ tab1, WT* __restrict__ Z, int32_t n0,
+                                                   const uint32_t* __restrict__ rkey, WT* __restrict__ Z, int32_t n0,
                                                    int32_t n1, uint32_t J, int lpf_log2) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* acc = reinterpret_cast<double*>(smem_raw);
   uint32_t* t1 = reinterpret_cast<uint32_t*>(acc + J);
   const int64_t o = blockIdx.x;
   for (uint32_t q = threadIdx.x; q < J; q += 256) acc[q] = 0.0;
-  for (int q = threadIdx.x; q < n1; q += 256) t1[q] = tab1[q];
+  for (int q = threadIdx.x; q < n1; q += 256) t1[q] = rkey[q];   // n1: rows of a slab
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lpf = 1 << lpf_log2, g = lane >> lpf_log2, v = lane & (lpf - 1);
   const int rw = 64 >> lpf_log2;   // rows per wave and load
@@ -764,8 +766,8 @@ __global__ __launch_bounds__(256) void k_sketch_zi(const XT* __restrict__ X, con
   for (uint32_t q = threadIdx.x; q < J; q += 256) out[q] = (WT)acc[q];
 }
 
-// Y_k (k >= 2) from Z.  The outer tuples with i_k = c are o = a + A (c + n_k
-// b): a over modes 2..k-1 (A tuples, keys KA), b over modes k+1..d-1 (B
+// Y_k (k >= m) from Z.  The outer tuples with i_k = c are o = a + A (c + n_k
+// b): a over modes m..k-1 (A tuples, keys KA), b over modes k+1..d-1 (B
 // tuples, keys KB).  Workgroup (s, c) adds, for the tuples m = a + A b of
 // slice s of the A B, row o of Z shifted cyclically by the bucket of
 // key_add(KA[a], KB[b]) and with its sign, into J FP64 LDS entries (thread t
@@ -1269,13 +1271,20 @@ hipError_t run_y1_outer(const tt_plan_s* p, void* Yv) {
 template <typename XT, typename WT, int V, int NJ>
 hipError_t run_zi_v(const tt_plan_s* p, const XT* X, WT* Z, int lpf_log2) {
   constexpr int U = NJ >= 4 ? 1 : 4 / NJ;
-  const size_t lds = (size_t)p->J * sizeof(double) + (size_t)p->n[1] * sizeof(uint32_t);
+  const size_t lds = (size_t)p->J * sizeof(double) + (size_t)p->inner_rows * sizeof(uint32_t);
   auto kern = k_sketch_zi<XT, WT, V, NJ, U>;
   hipError_t e;
   if ((e = tt_allow_lds(kern, lds)) != hipSuccess) return e;
   const uint32_t* tab = p->at<uint32_t>(p->o_tab);
-  hipLaunchKernelGGL(kern, dim3((unsigned)p->O0), dim3(256), lds, p->stream, X, tab + p->tab_off[0],
-                     tab + p->tab_off[1], Z, (int32_t)p->n[0], (int32_t)p->n[1], (uint32_t)p->J, lpf_log2);
+  // row keys: the mode-1 table when m = 2, else the keys over modes 1..m-1
+  const uint32_t* rkey = tab + p->tab_off[1];
+  if (p->inner_m > 2) {
+    uint32_t* KR = p->at<uint32_t>(p->o_KI);
+    if ((e = launch_build_keys(p, KR, p->inner_rows, 1, p->inner_m - 1)) != hipSuccess) return e;
+    rkey = KR;
+  }
+  hipLaunchKernelGGL(kern, dim3((unsigned)p->inner_O), dim3(256), lds, p->stream, X, tab + p->tab_off[0], rkey, Z,
+                     (int32_t)p->n[0], (int32_t)p->inner_rows, (uint32_t)p->J, lpf_log2);
   return hipGetLastError();
 }
 
@@ -1307,7 +1316,7 @@ hipError_t run_zi(const tt_plan_s* p, const void* Xv) {
 template <typename WT>
 hipError_t run_y_inner(const tt_plan_s* p, int k, void* Yv) {
   int64_t A = 1, B = 1;
-  for (int s = 2; s < k; ++s) A *= p->n[s];
+  for (int s = p->inner_m; s < k; ++s) A *= p->n[s];
   for (int s = k + 1; s < p->d; ++s) B *= p->n[s];
   const int64_t nk = p->n[k];
   const int S = (int)tt_inner_slices(p, k);
@@ -1317,7 +1326,7 @@ hipError_t run_y_inner(const tt_plan_s* p, int k, void* Yv) {
   double* part = p->at<double>(p->o_part);
   hipError_t e;
   // an empty mode range yields the single key 0 (bucket 0, sign +)
-  if ((e = launch_build_keys(p, KA, A, 2, k - 1)) != hipSuccess) return e;
+  if ((e = launch_build_keys(p, KA, A, p->inner_m, k - 1)) != hipSuccess) return e;
   if ((e = launch_build_keys(p, KB, B, k + 1, p->d - 1)) != hipSuccess) return e;
   const size_t lds = (size_t)p->J * sizeof(double);
   if ((e = tt_allow_lds(k_sketch_y_zi<WT>, lds)) != hipSuccess) return e;
@@ -1406,19 +1415,20 @@ hipError_t launch_sketch_y1_outer(const tt_plan_s* p, void* Y1) {
 // Workgroups per column of the Y_k-from-Z kernel (k >= 2): about 1024 in all,
 // each summing at least 2 rows of Z.
 int64_t tt_inner_slices(const tt_plan_s* p, int k) {
-  const int64_t M = p->O0 / p->n[k];
+  const int64_t M = p->inner_O / p->n[k];
   int64_t S = (1024 + p->n[k] - 1) / p->n[k];
   const int64_t cap = M / 2 > 1 ? M / 2 : 1;
   if (S > cap) S = cap;
   return S < 1 ? 1 : S;
 }
 
-// Y_k for k >= 2 come from the inner sketch Z: the plan holds the J_cap x
-// O_0 buffer for it.
+// Y_k for k >= inner_m come from the inner sketch Z: the plan holds the
+// J_cap x inner_O buffer for it.
 bool tt_sketch_inner(const tt_plan_s* p) { return p->o_zi != 0; }
 
-// One pass over X writes Z (the TensorSketch of every slab over modes 0 and
-// 1), then Y_k for every k >= 2 is formed from Z into its slot of Yall.
+// One pass over X writes Z (the TensorSketch of every slab over modes
+// 0..m-1; by the k = 0 pass instead when it writes both intermediates), then
+// Y_k for every k >= m is formed from Z into its slot of Yall.
 hipError_t launch_sketch_inner(const tt_plan_s* p, const void* X, void* Yall) {
   if (!tt_sketch_inner(p)) return hipErrorInvalidValue;
   hipError_t e;
@@ -1435,7 +1445,7 @@ hipError_t launch_sketch_inner(const tt_plan_s* p, const void* X, void* Yall) {
   }
   TTProfScope ps(p, TT_PROF_SKETCH_AUX);
   char* Yb = static_cast<char*>(Yall);
-  for (int k = 2; k < p->d; ++k) {
+  for (int k = p->inner_m; k < p->d; ++k) {
     void* Yk = Yb + p->wsize() * p->J * p->tab_off[k];
     e = p->wdt == TT_F64 ? run_y_inner<double>(p, k, Yk) : run_y_inner<float>(p, k, Yk);
     if (e != hipSuccess) return e;
@@ -1449,7 +1459,8 @@ hipError_t launch_sketch_inner(const tt_plan_s* p, const void* X, void* Yall) {
 // BF16: the outer-sketch sums stay in registers), tables and both bucket
 // arrays within 160 KB of LDS.
 int tt_joint_vectors(const tt_plan_s* p) {
-  if (!(tt_sketch_fused01(p) && tt_sketch_inner(p)) || p->wdt != TT_F32 || p->xdt == TT_F64) return 0;
+  if (!(tt_sketch_fused01(p) && tt_sketch_inner(p)) || p->inner_m != 2 || p->wdt != TT_F32 || p->xdt == TT_F64)
+    return 0;
   const int64_t V = 16 / (int64_t)p->xsize(), S = p->n[0] * p->n[1];
   if (p->n[0] % V != 0 || p->n[0] > 4096) return 0;
   if (16 * p->J_cap + 4 * (p->n[0] + p->n[1]) > 160 * 1024) return 0;

@@ -40,6 +40,9 @@ struct tt_plan_s {
   int64_t max_n, s_max, r_max;
   int64_t max_M, max_R;        // largest inner / outer fibre-key table
   int64_t O0;                  // outer combos for k = 0 (modes 2..d-1)
+  int inner_m;                 // inner sketch over modes 0..inner_m-1 (Y_k, k >= inner_m, from it); 0: none
+  int64_t inner_rows;          // rows of one of its slabs: n_1 ... n_{inner_m - 1}
+  int64_t inner_O;             // its slabs: n_{inner_m} ... n_{d-1}
   int64_t part_entries;        // data-sketch partial accumulators (work type elements)
   int64_t gram_chunks;         // split-K chunks of the Gram
   int64_t chat_cols;           // sum_i R_i R_{i+1}

@@ -272,6 +272,12 @@ INNER_CASES = [
     ([128, 256, 2, 2], 16, "bf16", "f32", True, 0),
     ([64, 8, 8, 8, 8], 300, "bf16", "f32", True, 0),
     ([12, 10, 3, 4, 5], 20, "f32", "f32", True, 0),
+    # the inner sketch over modes 0..2 (mode 2 keeps its own pass): d = 5
+    # FP32, BF16 and FP64, and d = 6
+    ([12, 10, 8, 9, 7], 300, "f32", "f32", None, 0),
+    ([16, 8, 8, 6, 5], 64, "bf16", "f32", True, 0),
+    ([10, 6, 5, 7, 4], 24, "f64", "f64", None, 0),
+    ([10, 6, 5, 4, 6, 5], 32, "f32", "f32", None, 0),
 ]
 
 
@@ -281,12 +287,19 @@ def test_sketch_all_inner(tts, n, J, xd, wd, fuse, shift):
     N = int(np.prod(n))
     plan = tts.Plan(n, [1] * (len(n) + 1), J, 1e-3, seed=5, x_dtype=xd, work_dtype=wd, fuse=fuse, inner=True)
     src = plan.sketch_sources()
-    # Y_2.. from the inner sketch, written by the pass of mode 2 or (FP32
-    # work with the outer sketch) by the k = 0 pass
-    assert src[2:] == [2] * (len(n) - 2) or src[1:] == [0] * (len(n) - 1), src
+    d = len(n)
+    # Y_m.. from the inner sketch over modes 0..m-1, written by the pass of
+    # mode m (modes 2..m-1 keep their own passes) or, for m = 2 with FP32 work
+    # and the outer sketch, by the k = 0 pass
+    m = src[-1]
+    if m == 0:
+        assert src[1:] == [0] * (d - 1), src
+    else:
+        assert 2 <= m <= d - 2 and src[2:] == list(range(2, m + 1)) + [m] * (d - m - 1), src
     vec = 8 if xd == "bf16" else 4
-    if fuse and wd == "f32" and n[0] % vec == 0 and n[0] * n[1] <= 1024 * (32 if xd == "bf16" else 40):
-        assert src == [0] * len(n), src
+    if m == 0 or (m == 2 and fuse and wd == "f32" and n[0] % vec == 0 and
+                  n[0] * n[1] <= 1024 * (32 if xd == "bf16" else 40)):
+        assert src == [0] * d, src
     hs, vs = host_tables(plan)
 
     def shifted(Xh):
@@ -330,6 +343,17 @@ def test_sketch_inner_rule(tts):
     assert tts.Plan([128, 324, 2, 3], [1] * 5, 32, 1e-3, inner=True, fuse=True).sketch_sources() == [0, 0, 2, 2]
     assert tts.Plan([200, 200, 3, 2], [1] * 5, 64, 1e-3, inner=True, fuse=True, x_dtype="f64",
                     work_dtype="f64").sketch_sources() == [0, 0, 2, 2]
+    # d = 5: the grouping with the fewest bytes; over modes 0..2 when the
+    # sketch of modes 0, 1 would be larger (|Z| = J n_2 n_3 n_4 = 151200
+    # values against J n_3 n_4 = 18900 and one more pass over X)
+    assert tts.Plan([12, 10, 8, 9, 7], [1] * 6, 300, 1e-3, inner=True, fuse=False).sketch_sources() == [0, 1, 2, 3, 3]
+    assert tts.Plan([40, 30, 3, 3, 2], [1] * 6, 50, 1e-3, inner=True, fuse=False).sketch_sources() == [0, 1, 2, 2, 2]
+    # the 64^5 BF16 workload (J = 3000): a pass per mode k >= 2 by default
+    # (2-byte entries: the inner pass is bound by its LDS atomics), modes
+    # 0..2 on request
+    assert tts.Plan([64] * 5, [1, 8, 8, 8, 8, 1], 3000, 1e-3, x_dtype="bf16").sketch_sources() == [0, 0, 2, 3, 4]
+    assert tts.Plan([64] * 5, [1, 8, 8, 8, 8, 1], 3000, 1e-3, x_dtype="bf16",
+                    inner=True).sketch_sources() == [0, 0, 2, 3, 3]
     # BF16 X: 4 vectors of 8 values per thread at most (32768-value slabs)
     assert tts.Plan([128, 256, 2, 2], [1] * 5, 16, 1e-3, inner=True, fuse=True,
                     x_dtype="bf16").sketch_sources() == [0, 0, 0, 0]
@@ -713,12 +737,13 @@ def test_sweeps_inner_sketch(tts, serial):
                                                 1e-2, fuse=False, serial=serial, inner=True)
     assert plan.sketch_sources() == [0, 1, 2, 2]
     assert max(abs(a - b) for a, b in zip(res, res_o)) < 1e-4
+    # modes 0..2 in the inner sketch, mode 2 its own pass
     plan, dc, ref, res, res_o, Xo = _run_sweeps(tts, [12, 10, 8, 9, 7], [1, 3, 4, 4, 3, 1], 300, 1e-3, 8, 3, "f32",
                                                 "f32", 1e-2, serial=serial, inner=True, fuse=False)
-    assert plan.sketch_sources()[2:] == [2, 2, 2]
+    assert plan.sketch_sources()[2:] == [2, 3, 3]
     assert max(abs(a - b) for a, b in zip(res, res_o)) < 1e-4
     # both intermediates from the k = 0 pass (one pass over X per sweep)
-    for n, R in (([40, 20, 6, 5], [1, 4, 5, 3, 1]), ([12, 10, 8, 9, 7], [1, 3, 4, 4, 3, 1])):
+    for n, R in (([40, 20, 6, 5], [1, 4, 5, 3, 1]), ([40, 30, 3, 3, 2], [1, 3, 3, 3, 2, 1])):
         plan, dc, ref, res, res_o, Xo = _run_sweeps(tts, n, R, 200, 1e-3, 8, 3, "f32", "f32", 1e-2, serial=serial,
                                                     inner=True, fuse=True)
         assert plan.sketch_sources() == [0] * len(n)
