@@ -830,7 +830,8 @@ __global__ __launch_bounds__(256) void k_sketch_y_zi(const WT* __restrict__ Z, c
 //    (n_0 is a multiple of V), found as the high word of position times
 //    mdiv = ceil(2^32 / n_0) (exact for positions below 2^17); the table
 //    entries are read from LDS.
-// A slab is read in four chunks of ceil(NV / 4) vectors per thread; the next
+// A slab is read in four chunks of NV / 4 vectors per thread (rounded down or
+// up, balanced: 2, 3, 2, 3 for NV = 10); the next
 // chunk (of this slab or the next) is loaded before the current one is
 // added.  Slabs go in groups of G to G LDS arrays each, two sets alternating
 // between groups: after the barrier that closes a group, each thread writes
@@ -844,7 +845,7 @@ __global__ __launch_bounds__(1024) void k_sketch_zoi(const XT* __restrict__ X, c
                                                     const uint32_t* __restrict__ tab0, const uint32_t* __restrict__ tab1,
                                                     float* __restrict__ zo, float* __restrict__ Z, int32_t n0,
                                                     int32_t n1, uint32_t J, uint32_t mdiv) {
-  constexpr int CH = (NV + 3) / 4;   // vectors per thread and chunk
+  constexpr int CH = (NV + 3) / 4;   // most vectors per thread in a chunk (chunk c: j in [c NV / 4, (c + 1) NV / 4))
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* acc = reinterpret_cast<double*>(smem_raw);                  // 2 G J entries
   uint32_t* t0 = reinterpret_cast<uint32_t*>(acc + 2 * G * (size_t)J);   // n_0 entries
@@ -866,8 +867,9 @@ __global__ __launch_bounds__(1024) void k_sketch_zoi(const XT* __restrict__ X, c
   auto load_chunk = [&](Vec<XT, V>* x, const XT* slab, int ch) {
 #pragma unroll
     for (int h = 0; h < CH; ++h) {
-      const int pos = V * (t + 1024 * (ch * CH + h));
-      if (ch * CH + h < NV && pos < S) {
+      const int j = ch * NV / 4 + h;
+      const int pos = V * (t + 1024 * j);
+      if (h < (ch + 1) * NV / 4 - ch * NV / 4 && pos < S) {
         x[h] = load_vec_plain<XT, V>(slab + pos);
       } else {
 #pragma unroll
@@ -878,8 +880,8 @@ __global__ __launch_bounds__(1024) void k_sketch_zoi(const XT* __restrict__ X, c
   auto add_chunk = [&](const Vec<XT, V>* x, int ch, double* A, uint32_t so) {
 #pragma unroll
     for (int h = 0; h < CH; ++h) {
-      const int j = ch * CH + h;
-      if (j >= NV) continue;
+      const int j = ch * NV / 4 + h;
+      if (h >= (ch + 1) * NV / 4 - ch * NV / 4) continue;
       const uint32_t pos = V * (t + 1024 * j);
       if (pos >= (uint32_t)S) continue;
       const uint32_t i1 = __umulhi(pos, mdiv), i0 = pos - i1 * (uint32_t)n0;
