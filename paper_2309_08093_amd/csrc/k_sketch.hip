@@ -886,10 +886,21 @@ __global__ __launch_bounds__(1024) void k_sketch_zoi(const XT* __restrict__ X, c
       if (pos >= (uint32_t)S) continue;
       const uint32_t i1 = __umulhi(pos, mdiv), i0 = pos - i1 * (uint32_t)n0;
       const uint32_t K = t1[i1];
+      // the vector's V mode-0 entries in 16-byte LDS reads (t0 and i0 are
+      // 16-byte aligned: t0 follows 2 G J doubles, i0 is a multiple of V)
+      uint32_t k0v[V];
+#pragma unroll
+      for (int q = 0; q < V; q += 4) {
+        const uint4 w = *reinterpret_cast<const uint4*>(t0 + i0 + q);
+        k0v[q] = w.x;
+        k0v[q + 1] = w.y;
+        k0v[q + 2] = w.z;
+        k0v[q + 3] = w.w;
+      }
 #pragma unroll
       for (int e = 0; e < V; ++e) {
         za[j][e] += __uint_as_float(__float_as_uint(to_work<float>(x[h].e[e])) ^ so);
-        const uint32_t b = key_add(t0[i0 + e], K, J);
+        const uint32_t b = key_add(k0v[e], K, J);
         atomicAdd(&A[b & TT_KEY_MASK], signed_f64(x[h].e[e], b & TT_KEY_SIGN));
       }
     }
