@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void k_sketch_y1_outer(const WT* __restrict__ 
                                                          int32_t S) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* acc = reinterpret_cast<double*>(smem_raw);
-  uint32_t* t0 = reinterpret_cast<uint32_t*>(acc + J);
+  uint32_t* t0 = reinterpret_cast<uint32_t*>(acc + ((J + 1) & ~1u));   // 16-byte aligned
   const int s = blockIdx.x, i1 = blockIdx.y;
   for (uint32_t q = threadIdx.x; q < J; q += blockDim.x) acc[q] = 0.0;
   for (int q = threadIdx.x; q < n0; q += blockDim.x) t0[q] = tab0[q];
@@ -250,9 +250,23 @@ __global__ __launch_bounds__(256) void k_sketch_y1_outer(const WT* __restrict__ 
     const uint32_t i0 = (q - r * vpr) * V;
     const Vec<WT, V> x = load_vec<WT, V>(base + (int64_t)r * Sz + i0);
     const uint32_t c = r0 + r;   // the outer key of the row
+    uint32_t tv[V];   // the V mode-0 entries in one LDS read (i0 is a multiple of V)
+    if constexpr (V == 4) {
+      const uint4 w = *reinterpret_cast<const uint4*>(t0 + i0);
+      tv[0] = w.x;
+      tv[1] = w.y;
+      tv[2] = w.z;
+      tv[3] = w.w;
+    } else if constexpr (V == 2) {
+      const uint2 w = *reinterpret_cast<const uint2*>(t0 + i0);
+      tv[0] = w.x;
+      tv[1] = w.y;
+    } else {
+      tv[0] = t0[i0];
+    }
 #pragma unroll
     for (int e = 0; e < V; ++e) {
-      const uint32_t t = t0[i0 + e];
+      const uint32_t t = tv[e];
       uint32_t b = c + (t & TT_KEY_MASK);
       b = b >= J ? b - J : b;
       atomicAdd(&acc[b], signed_f64(x.e[e], t & TT_KEY_SIGN));
@@ -1261,7 +1275,7 @@ hipError_t run_y1_outer(const tt_plan_s* p, void* Yv) {
   const int S = (int)tt_outer_slices(p);
   double* part = p->at<double>(p->o_part);
   if (n1 * S * p->J > p->part_entries) return hipErrorInvalidValue;   // sized at plan time
-  const size_t lds = (size_t)p->J * sizeof(double) + (size_t)n0 * sizeof(uint32_t);
+  const size_t lds = (size_t)((p->J + 1) & ~(int64_t)1) * sizeof(double) + (size_t)n0 * sizeof(uint32_t);
   // 16-byte loads when every row of n_0 values starts on a 16-byte boundary
   constexpr int VW = 16 / (int)sizeof(WT);
   auto kern = (n0 % VW) == 0 ? k_sketch_y1_outer<WT, VW> : k_sketch_y1_outer<WT, 1>;
